@@ -1,0 +1,272 @@
+"""Seeded synthetic MPC QP batches.
+
+This module only draws inputs: per-stage dynamics (A_k, B_k, c_k), diagonal
+cost weights, torque limits, friction coefficients, contact schedules,
+initial states and references.  It contains none of the solver's arithmetic
+(no bounds, penalties, factorisations or iterations), so both the FP64 CPU
+oracle and the HIP path can consume the same problems.
+
+The problem class is the linearised whole-body MPC QP of the paper's MPC
+formulation (Sec. III-A, Eq. (mpc_formulation)) under real-time iteration
+(Sec. III-B): one QP per agent per control step, with a floating-base state
+of 48 entries, foot contact wrenches/forces, a torque box, unilateral contact
+and a friction pyramid.  The robot model itself is not available, so the
+stage matrices are random with the documented distributions.
+
+Random streams: every agent owns a PCG64 stream seeded with
+``SeedSequence([seed, config_id, agent_id])``; per-step disturbances use
+``SeedSequence([seed, config_id, agent_id, 1_000_000 + step])``.  Any agent
+subset therefore reproduces exactly.
+
+Layout (all arrays row-major, agents concatenated in agent order, so a
+uniform batch is the plain [B][N][...] tensor):
+  A      [sum_a N_a*nx_a*nx_a]     B  [sum_a N_a*nx_a*nu_a]
+  c      [sum_a N_a*nx_a]          q  [sum_a nx_a]    r [sum_a nu_a]
+  x_ref  [sum_a (N_a+1)*nx_a]      x0 [sum_a nx_a]
+  tau_max[sum_a n_tau_a]           mu [n_agents]
+  stance [sum_a N_a*n_feet_a] (uint8, 1 = foot in stance)
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+DT = 0.01
+
+
+@dataclasses.dataclass(frozen=True)
+class Shape:
+    """Per-agent problem shape.
+
+    ``u = [tau (n_tau); w_1; ...; w_{n_feet}]`` with ``w`` a 6D wrench
+    (f_x, f_y, f_z, m_x, m_y, m_z) when ``foot_dim == 6`` or a 3D force when
+    ``foot_dim == 3``.  ``nu == n_tau + n_feet * foot_dim``.
+    """
+
+    N: int
+    nx: int
+    nu: int
+    n_tau: int
+    n_feet: int
+    foot_dim: int
+
+    def __post_init__(self):
+        if self.nu != self.n_tau + self.n_feet * self.foot_dim:
+            raise ValueError("nu must equal n_tau + n_feet*foot_dim")
+        if self.foot_dim not in (3, 6):
+            raise ValueError("foot_dim must be 3 or 6")
+
+    @property
+    def m(self) -> int:
+        """Constraint rows per stage: identity rows on u plus 4 pyramid rows per foot."""
+        return self.nu + 4 * self.n_feet
+
+    def as_tuple(self):
+        return (self.N, self.nx, self.nu, self.n_tau, self.n_feet, self.foot_dim)
+
+
+def humanoid(N: int = 10) -> Shape:
+    """24-DoF floating-base humanoid: q, v (48), 18 torques + two 6D foot wrenches."""
+    return Shape(N=N, nx=48, nu=30, n_tau=18, n_feet=2, foot_dim=6)
+
+
+def quadruped(N: int = 10) -> Shape:
+    """Quadruped-shaped agent: 36 states, 12 torques + four 3D foot forces."""
+    return Shape(N=N, nx=36, nu=24, n_tau=12, n_feet=4, foot_dim=3)
+
+
+def agent_rng(seed: int, config_id: int, agent_id: int, *extra: int) -> np.random.Generator:
+    return np.random.Generator(
+        np.random.PCG64(np.random.SeedSequence([seed, config_id, agent_id, *extra])))
+
+
+@dataclasses.dataclass
+class Batch:
+    """A batch of agents' raw QP data (see module docstring for the layout)."""
+
+    shapes: List[Shape]
+    A: np.ndarray
+    B: np.ndarray
+    c: np.ndarray
+    q: np.ndarray
+    r: np.ndarray
+    x_ref: np.ndarray
+    x0: np.ndarray
+    tau_max: np.ndarray
+    mu: np.ndarray
+    stance: np.ndarray
+    seed: int = 0
+    config_id: int = 0
+    agent_ids: Optional[np.ndarray] = None
+
+    @property
+    def n_agents(self) -> int:
+        return len(self.shapes)
+
+    @property
+    def uniform(self) -> bool:
+        return len(set(self.shapes)) <= 1
+
+    def offsets(self) -> dict:
+        """Start offset of each agent in each flat array (int64, length n_agents+1)."""
+        return compute_offsets(self.shapes)
+
+    def astype(self, dtype) -> "Batch":
+        f = lambda a: np.ascontiguousarray(a, dtype=dtype)
+        return dataclasses.replace(self, A=f(self.A), B=f(self.B), c=f(self.c), q=f(self.q),
+                                   r=f(self.r), x_ref=f(self.x_ref), x0=f(self.x0),
+                                   tau_max=f(self.tau_max), mu=f(self.mu))
+
+    def subset(self, idx: Sequence[int]) -> "Batch":
+        """Agents ``idx`` (in that order) as a new batch."""
+        off = self.offsets()
+        parts = {k: [] for k in ("A", "B", "c", "q", "r", "x_ref", "x0", "tau_max", "stance")}
+        for a in idx:
+            for k in parts:
+                parts[k].append(getattr(self, k)[off[k][a]:off[k][a + 1]])
+        ids = self.agent_ids if self.agent_ids is not None else np.arange(self.n_agents)
+        return Batch(shapes=[self.shapes[a] for a in idx],
+                     mu=np.ascontiguousarray(self.mu[list(idx)]),
+                     seed=self.seed, config_id=self.config_id,
+                     agent_ids=np.asarray([ids[a] for a in idx], dtype=np.int64),
+                     **{k: np.ascontiguousarray(np.concatenate(v)) for k, v in parts.items()})
+
+
+_FIELDS = {
+    "A": lambda s: s.N * s.nx * s.nx,
+    "B": lambda s: s.N * s.nx * s.nu,
+    "c": lambda s: s.N * s.nx,
+    "q": lambda s: s.nx,
+    "r": lambda s: s.nu,
+    "x_ref": lambda s: (s.N + 1) * s.nx,
+    "x0": lambda s: s.nx,
+    "tau_max": lambda s: s.n_tau,
+    "stance": lambda s: s.N * s.n_feet,
+    # solution-side arrays (used by bindings and tests)
+    "x": lambda s: (s.N + 1) * s.nx,
+    "u": lambda s: s.N * s.nu,
+    "z": lambda s: s.N * s.m,
+    "u0": lambda s: s.nu,
+}
+
+
+def compute_offsets(shapes: Sequence[Shape]) -> dict:
+    out = {}
+    for k, f in _FIELDS.items():
+        sizes = np.fromiter((f(s) for s in shapes), dtype=np.int64, count=len(shapes))
+        o = np.zeros(len(shapes) + 1, dtype=np.int64)
+        np.cumsum(sizes, out=o[1:])
+        out[k] = o
+    return out
+
+
+def _draw_agent(rng, s: Shape, *, stance_p, q_log, r_log, r_scale, dt=DT):
+    """Draw one agent's data in a fixed order (documented in the design doc)."""
+    G = rng.standard_normal((s.N, s.nx, s.nx)) / np.sqrt(s.nx)
+    A = G * dt
+    A[:, np.arange(s.nx), np.arange(s.nx)] += 1.0
+    B = rng.standard_normal((s.N, s.nx, s.nu)) * (dt / np.sqrt(s.nu))
+    c = rng.standard_normal((s.N, s.nx)) * 1e-3
+    q = 10.0 ** rng.uniform(q_log[0], q_log[1], s.nx)
+    r = r_scale * 10.0 ** rng.uniform(r_log[0], r_log[1], s.nu)
+    tau_max = rng.uniform(20.0, 100.0, s.n_tau)
+    mu = rng.uniform(0.4, 1.0)
+    if stance_p is None:  # per-foot stance probability ~ U[0.3, 0.9]
+        p = rng.uniform(0.3, 0.9, s.n_feet)
+    else:
+        p = np.full(s.n_feet, stance_p)
+    stance = (rng.random((s.N, s.n_feet)) < p[None, :]).astype(np.uint8)
+    x0 = rng.standard_normal(s.nx)
+    x_ref = rng.standard_normal((s.N + 1, s.nx))
+    return A, B, c, q, r, x_ref, x0, tau_max, mu, stance
+
+
+def make_batch(shapes: Sequence[Shape], *, seed: int = 0, config_id: int = 0,
+               agent_ids: Optional[Sequence[int]] = None, stance_p: Optional[float] = 0.6,
+               q_log=(-2.0, 2.0), r_log=(-4.0, -1.0), r_scale: float = 1.0,
+               dtype=np.float64) -> Batch:
+    """Draw a batch; agent ``i`` uses stream (seed, config_id, agent_ids[i])."""
+    shapes = list(shapes)
+    if agent_ids is None:
+        agent_ids = range(len(shapes))
+    agent_ids = np.asarray(list(agent_ids), dtype=np.int64)
+    off = compute_offsets(shapes)
+    out = {k: np.empty(int(off[k][-1]), dtype=dtype)
+           for k in ("A", "B", "c", "q", "r", "x_ref", "x0", "tau_max")}
+    stance = np.empty(int(off["stance"][-1]), dtype=np.uint8)
+    mu = np.empty(len(shapes), dtype=dtype)
+    for i, (s, aid) in enumerate(zip(shapes, agent_ids)):
+        rng = agent_rng(seed, config_id, int(aid))
+        A, B, c, q, r, x_ref, x0, tau_max, m_, st = _draw_agent(
+            rng, s, stance_p=stance_p, q_log=q_log, r_log=r_log, r_scale=r_scale)
+        for k, v in (("A", A), ("B", B), ("c", c), ("q", q), ("r", r), ("x_ref", x_ref),
+                     ("x0", x0), ("tau_max", tau_max)):
+            out[k][off[k][i]:off[k][i + 1]] = v.ravel()
+        stance[off["stance"][i]:off["stance"][i + 1]] = st.ravel()
+        mu[i] = m_
+    return Batch(shapes=shapes, stance=stance, mu=mu, seed=seed, config_id=config_id,
+                 agent_ids=agent_ids, **out)
+
+
+# --- the five benchmark configurations -------------------------------------------------
+
+def config0(n_agents: int = 64, seed: int = 0, agent_ids=None, dtype=np.float64) -> Batch:
+    """64 humanoid agents, N=10, stance Bernoulli(0.6), solved in FP64 for 50 iterations."""
+    ids = range(n_agents) if agent_ids is None else agent_ids
+    return make_batch([humanoid(10)] * len(list(ids)), seed=seed, config_id=0,
+                      agent_ids=ids, dtype=dtype)
+
+
+def config1(n_agents: int = 4096, seed: int = 0, agent_ids=None, dtype=np.float64) -> Batch:
+    """RL-training shape: config-0 generator at 4096 humanoid agents, N=10."""
+    ids = range(n_agents) if agent_ids is None else agent_ids
+    return make_batch([humanoid(10)] * len(list(ids)), seed=seed, config_id=1,
+                      agent_ids=ids, dtype=dtype)
+
+
+def config2_shapes(n_agents: int = 8192, seed: int = 0, config_id: int = 2,
+                   agent_ids=None) -> List[Shape]:
+    """Uneven batch: N ~ U{5..20}, 50/50 humanoid / quadruped, from a per-agent stream."""
+    ids = range(n_agents) if agent_ids is None else agent_ids
+    shapes = []
+    for aid in ids:
+        rng = agent_rng(seed, config_id, int(aid), 7)
+        kind = rng.integers(0, 2)
+        N = int(rng.integers(5, 21))
+        shapes.append(humanoid(N) if kind == 0 else quadruped(N))
+    return shapes
+
+
+def config2(n_agents: int = 8192, seed: int = 0, agent_ids=None, dtype=np.float64,
+            config_id: int = 2) -> Batch:
+    ids = list(range(n_agents) if agent_ids is None else agent_ids)
+    shapes = config2_shapes(seed=seed, config_id=config_id, agent_ids=ids)
+    return make_batch(shapes, seed=seed, config_id=config_id, agent_ids=ids,
+                      stance_p=None, dtype=dtype)
+
+
+def config3(n_agents: int = 16384, kappa: float = 1e4, seed: int = 0, agent_ids=None,
+            dtype=np.float64) -> Batch:
+    """Mixed-precision sweep: humanoid N=16, Q and R with condition number ``kappa``.
+
+    Q = diag(10^U[-h, h]) and R = 3.16e-3 * diag(10^U[-h, h]) with h = log10(kappa)/2,
+    centred on the geometric means of the config-0 draws (1 and 10^-2.5).
+    """
+    ids = range(n_agents) if agent_ids is None else agent_ids
+    h = 0.5 * np.log10(kappa)
+    cid = 300 + int(round(np.log10(kappa)))
+    return make_batch([humanoid(16)] * len(list(ids)), seed=seed, config_id=cid,
+                      agent_ids=ids, q_log=(-h, h), r_log=(-h, h), r_scale=10 ** -2.5,
+                      dtype=dtype)
+
+
+def step_noise(batch: Batch, step: int, std: float = 1e-2) -> np.ndarray:
+    """Per-step state disturbance, N(0, std^2), laid out like ``x0``."""
+    ids = batch.agent_ids if batch.agent_ids is not None else np.arange(batch.n_agents)
+    parts = []
+    for s, aid in zip(batch.shapes, ids):
+        rng = agent_rng(batch.seed, batch.config_id, int(aid), 1_000_000 + step)
+        parts.append(rng.standard_normal(s.nx) * std)
+    return np.concatenate(parts)

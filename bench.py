@@ -1,0 +1,193 @@
+"""Benchmark: batched MPC QP solves per second on one MI355X.
+
+A "step" is one control step of the RL-training workload: every agent's QP is
+solved (stage setup, Riccati factor, 50 warm-started ADMM iterations, FP64 KKT
+residual check) and every agent's plant is advanced by its own first stage
+plus Gaussian noise, x0 <- A_0 x0 + B_0 u_0* + c_0 + w, w ~ N(0, 1e-2^2).
+Default workload: 4096 humanoid agents (nx=48, nu=30, N=10), FP32.
+All inputs are synthetic and resident in HBM before timing starts.
+
+Prints ONE JSON line (see the design doc for the roofline and baseline fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"alu_f32": 157.3e12, "alu_f64": 78.6e12, "hbm": 8.0e12}
+
+
+def flops_iter_stage(nx, nu):
+    """Matvec FLOPs of one ADMM iteration per stage: back chain A_cl' (nx^2),
+    K' rt (nx nu), B' p' (nx nu), H^-1 (nu^2), B d (nx nu), forward chain
+    A_cl (nx^2), K x (nx nu); 2 FLOP per multiply-add."""
+    return 2 * (2 * nx * nx + 4 * nx * nu + nu * nu)
+
+
+def flops_factor_stage(nx, nu):
+    """FLOPs of one Riccati factor stage: P B, P A, B'(PB), B'(PA), K = -H^-1 G,
+    H^-1, A'(PA), G'K, A_cl = A + B K, s = P c (2 FLOP per multiply-add; the
+    Cholesky itself, nu^3/3, included)."""
+    mac = (nx * nx * nu + nx ** 3 + nx * nu * nu + nu * nx * nx + nu * nu * nx + nu ** 3
+           + nx ** 3 + nu * nx * nx + nx * nx * nu + nx * nx + nu ** 3 / 6)
+    return 2 * mac
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--agents", type=int, default=4096)
+    ap.add_argument("--horizon", type=int, default=10)
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "fused"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate wall time budget of the CPU-oracle baseline (0 = skip)")
+    ap.add_argument("--check-agents", type=int, default=64,
+                    help="agents whose first-step solution is compared with the FP64 oracle")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(agents shard across GPUs with no exchange, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    import oracle
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    shape = synth.humanoid(args.horizon)
+    batch = synth.make_batch([shape] * args.agents, seed=0, config_id=1,
+                             dtype=np.float64 if args.precision == "fp64" else np.float32)
+    plan = mpc.Plan(batch.shapes, precision=args.precision, iters=args.iters, kernel=args.kernel)
+    prob = mpc.to_device(batch, args.precision)
+    td = prob["A"].dtype
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    noise = torch.empty((args.warmup + args.steps, args.agents * shape.nx), dtype=td,
+                        device="cuda")
+    noise.normal_(0.0, 1e-2, generator=gen)
+    x0_init = prob["x0"].clone()
+
+    stream = torch.cuda.current_stream()
+
+    def step(i, warm):
+        plan.solve(prob, warm_start=warm, stream=stream)
+        plan.advance_state(prob, noise[i], prob["x0"], stream=stream)
+
+    # correctness spot check of the first (cold) step against the FP64 oracle
+    plan.solve(prob, warm_start=False, stream=stream)
+    sol = plan.get_solution(stream=stream)
+    torch.cuda.synchronize()
+    nchk = min(args.check_agents, args.agents)
+    chk_ids = np.linspace(0, args.agents - 1, nchk).astype(int)
+    sub = synth.make_batch([shape] * nchk, seed=0, config_id=1, agent_ids=chk_ids)
+    ref = oracle.solve_batch(sub, iters=args.iters)
+    ug = sol["u"].cpu().numpy().reshape(args.agents, -1)[chk_ids].astype(np.float64)
+    uo = ref["u"].reshape(nchk, -1)
+    err_traj = float((np.abs(ug - uo).max(1) / np.abs(uo).max(1)).max())
+    err_u0 = float((np.abs(ug[:, :shape.nu] - uo[:, :shape.nu]).max(1)
+                    / np.abs(uo[:, :shape.nu]).max(1)).max())
+    status_ok = bool((sol["status"] == 0).all().item())
+
+    # warmup (closed loop from the initial state)
+    prob["x0"].copy_(x0_init)
+    for i in range(args.warmup):
+        step(i, warm=i > 0)
+    torch.cuda.synchronize()
+
+    plan.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step(args.warmup + i, warm=True)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timing = plan.get_timing()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    solves = args.agents * args.steps
+    value = solves / wall
+
+    # dominant kernel: the ADMM-iteration launch (fused with the factor when
+    # the fused kernel serves the plan)
+    cfg = plan.config()
+    admm_ms, admm_n = timing["admm"]
+    fac_ms, fac_n = timing["factor"]
+    avg_admm_s = admm_ms / max(admm_n, 1) * 1e-3
+    fl_iter = flops_iter_stage(shape.nx, shape.nu) * shape.N * args.iters * args.agents
+    fl_fac = flops_factor_stage(shape.nx, shape.nu) * shape.N * args.agents
+    dominant_flops = fl_iter + (fl_fac if cfg["kernel"] == "fused" else 0)
+    peak = PEAK["alu_f64"] if args.precision == "fp64" else PEAK["alu_f32"]
+    achieved = dominant_flops / avg_admm_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "kernel": "fused solve (factor + ADMM)" if cfg["kernel"] == "fused" else "ADMM iterations",
+                "avg_launch_ms": avg_admm_s * 1e3,
+                "flops_per_launch": dominant_flops}
+
+    # CPU baseline: the FP64 oracle, warm-started closed loop on a bounded sample
+    cpu = None
+    if args.cpu_seconds > 0:
+        n_s = min(args.agents, 512)
+        cb = synth.make_batch([shape] * n_s, seed=0, config_id=1)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        t1 = time.perf_counter()
+        steps_done, state, x0 = 0, None, cb.x0.copy()
+        while True:
+            o = oracle.solve_batch(cb, iters=args.iters, warm=state, x0=x0, n_threads=threads)
+            state = {k: o[k] for k in ("u", "z", "y")}
+            x0 = oracle.advance_batch(cb, x0, o["u"], synth.step_noise(cb, steps_done))
+            steps_done += 1
+            if time.perf_counter() - t1 >= args.cpu_seconds or steps_done >= 200:
+                break
+        cpu_wall = time.perf_counter() - t1
+        cpu = {"value": n_s * steps_done / cpu_wall, "unit": "solves/s", "cores": int(o["threads"]),
+               "kind": "oracle",
+               "sample": f"{n_s} agents x {steps_done} warm-started control steps of the same "
+                         f"workload (FP64 C oracle, OpenMP over agents)"}
+
+    out = {
+        "metric": "MPC QP solves/sec at 4096 agents N=10 + p99 latency; FP32/BF16 vs FP64 error",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"{args.agents} humanoid agents (nx=48, nu=30), N={shape.N}, "
+                               f"{args.iters} warm-started ADMM iterations per control step, "
+                               "closed loop with plant noise",
+                   "agents": args.agents, "N": shape.N, "nx": shape.nx, "nu": shape.nu,
+                   "admm_iters": args.iters, "precision": args.precision,
+                   "kernel": cfg["kernel"], "threads_per_agent": cfg["threads_per_agent"],
+                   "lds_bytes": cfg["lds_bytes"], "parallelism": "agents (1 GPU)"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "kernel_ms": {"factor": fac_ms / max(fac_n, 1), "admm": admm_ms / max(admm_n, 1),
+                      "residual": timing["residual"][0] / max(timing["residual"][1], 1)},
+        "err_vs_fp64": {"u0": err_u0, "trajectory": err_traj, "agents_checked": int(nchk),
+                        "status_ok": status_ok},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

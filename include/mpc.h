@@ -1,0 +1,172 @@
+/*
+ * mpc.h -- C ABI of the batched MPC QP solver for AMD Instinct MI355X (gfx950).
+ *
+ * One call solves, for every agent of a batch, the linearised whole-body MPC
+ * quadratic program that real-time iteration reduces the paper's MPC problem
+ * to (one QP per control step; Sec. II-A and Sec. III-B, Eq. (OCP) and
+ * Eq. (mpc_formulation)), re-posed as a linear time-varying QP:
+ *
+ *   min  sum_{k=1..N} 1/2 (x_k - r_k)' Q (x_k - r_k)
+ *      + sum_{k=0..N-1} 1/2 (u_k - ubar_k)' R (u_k - ubar_k)
+ *   s.t. x_0 = xbar0,   x_{k+1} = A_k x_k + B_k u_k + c_k,
+ *        l_k <= C_k u_k <= h_k,
+ *
+ * with u = [tau (n_tau); foot wrenches or forces], C_k = [I; friction
+ * pyramid], torque box +-tau_max, stance feet f_z >= 0 and pyramid facets
+ * <= 0, swing feet forced to a zero wrench (contact rows of
+ * Eq. (mpc_formulation), with the cone replaced by a 4-sided pyramid).
+ *
+ * Method: OSQP's ADMM (adopted in Sec. III-B; KKT system Eq. (kkt_system))
+ * with the dynamics rows kept exact.  The x-update's KKT system is then an
+ * equality-constrained LQR: a Riccati factor computed once per solve plays
+ * the role of Eq. (ldl), and a backward/forward sweep per iteration plays the
+ * role of Eqs. (backsolve_1)-(backsolve_2); projection and dual update follow
+ * (Alg. 1, QP-iteration loop).
+ *
+ * Conventions
+ *   - All array arguments of mpc_problem_batch / mpc_solution are DEVICE
+ *     pointers on the plan's device, caller-owned, row-major, agents
+ *     concatenated in agent order (a uniform batch is the plain
+ *     [n_agents][N][...] tensor).  Per-agent sizes:
+ *        A [N][nx][nx]   B [N][nx][nu]   c [N][nx]    q_diag [nx]  r_diag [nu]
+ *        x_ref [N+1][nx] (row 0 unused)  x0 [nx]     tau_max [n_tau]
+ *        mu [1]          stance [N][n_feet] (uint8, nonzero = stance)
+ *        u_ref [N][nu] (optional input reference, may be NULL = 0)
+ *     Floating-point arrays have the plan's "io type": double for
+ *     MPC_FP64, float for every other precision.
+ *   - Solution arrays: u0 [nu], x [N+1][nx], u [N][nu], z [N][m], y [N][m]
+ *     (m = nu + 4 n_feet), objective [1] in the io type; residuals [4]
+ *     double (primal, dual, dynamics, complementarity infinity norms);
+ *     status [1] int32 (see MPC_AGENT_*).
+ *   - Calls are asynchronous and stream-ordered on the given stream
+ *     (a hipStream_t passed as void*, NULL = the null stream).  Inputs must
+ *     stay valid until the stream has reached the solve.
+ *   - API errors are returned as mpc_status and never abort the process;
+ *     mpc_last_error() gives a thread-local message.  Numerical failure is
+ *     per agent in status[] and never affects other agents.
+ *   - A plan is not thread-safe; use one plan per stream.
+ */
+#ifndef MPC_H
+#define MPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPC_OK = 0,
+  MPC_ERR_INVALID_ARG = 1,
+  MPC_ERR_OUT_OF_MEMORY = 2,
+  MPC_ERR_HIP = 3,
+  MPC_ERR_UNSUPPORTED_SHAPE = 4,
+  MPC_ERR_BUSY = 5,
+  MPC_ERR_NOT_READY = 6
+} mpc_status;
+
+typedef enum {
+  MPC_FP64 = 0,        /* everything in double                                    */
+  MPC_FP32 = 1,        /* everything in float (Cholesky included)                 */
+  MPC_BF16_REFINE = 2, /* bf16 block products, fp64 stage Cholesky, refinement    */
+  MPC_FP16_REFINE = 3  /* fp16 block products, fp64 stage Cholesky, refinement    */
+} mpc_precision;
+
+/* per-agent numerical status */
+enum { MPC_AGENT_OK = 0, MPC_AGENT_CONVERGED = 1, MPC_AGENT_NOT_PD = 2, MPC_AGENT_NONFINITE = 3 };
+
+/* Shape of one agent's QP.  nu must equal n_tau + n_feet * foot_dim;
+ * foot_dim is 6 (wrench f_x,f_y,f_z,m_x,m_y,m_z) or 3 (force f_x,f_y,f_z).
+ * Limits: 1 <= N <= 64, 1 <= nx <= 64, 1 <= nu <= 32, n_feet <= 8. */
+typedef struct {
+  int32_t N, nx, nu, n_tau, n_feet, foot_dim;
+} mpc_shape;
+
+typedef struct {
+  int32_t n_agents;         /* > 0                                                   */
+  const mpc_shape* shapes;  /* HOST array [n_agents]; copied at plan creation          */
+  int32_t precision;        /* mpc_precision                                           */
+  int32_t admm_iters;       /* fixed iteration count K (> 0)                           */
+  double rho;               /* ADMM penalty of inequality rows        (default 0.1)    */
+  double sigma;             /* proximal weight on x and u             (default 1e-6)   */
+  double alpha;             /* over-relaxation in (0, 2)              (default 1.6)    */
+  double rho_eq_scale;      /* equality rows get rho_eq_scale * rho   (default 1e3)    */
+  double rho_min;           /* rows with both bounds infinite         (default 1e-6)   */
+  int32_t max_refine_sweeps;/* refinement sweeps per x-update, mixed precisions only   */
+  double refine_tol;        /* stop refining at |r|_inf <= refine_tol * |b|_inf        */
+  int32_t device;           /* HIP device ordinal                                      */
+  int32_t kernel;           /* 0 = auto, 1 = generic kernels, 2 = fused kernel         */
+} mpc_plan_desc;
+
+/* Fill *desc with the defaults above for n_agents agents of the given shapes. */
+void mpc_plan_desc_default(mpc_plan_desc* desc);
+
+typedef struct mpc_plan_s* mpc_plan_t;
+
+/* Validate the description, copy the shapes, and allocate device workspace:
+ * factors, resident warm-start state (u, z, y), solution and status buffers.
+ * Errors: INVALID_ARG (bad pointer, count or constant), UNSUPPORTED_SHAPE
+ * (shape outside the limits), OUT_OF_MEMORY, HIP. */
+mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out);
+
+/* Release every device buffer of the plan (waits for the device). */
+mpc_status mpc_plan_destroy(mpc_plan_t plan);
+
+typedef struct {
+  const void *A, *B, *c, *q_diag, *r_diag, *x_ref, *x0, *tau_max, *mu;
+  const uint8_t* stance;
+  const void* u_ref;   /* may be NULL */
+  int32_t warm_start;  /* 0: u = z = y = 0;  1: start from the plan's resident (u, z, y) */
+} mpc_problem_batch;
+
+/* Solve every agent: stage penalties and bounds, Riccati factor (once), then
+ * admm_iters iterations of back-sweep, rollout, relaxation, projection and
+ * dual update, then the FP64 KKT residual check.  The solution stays
+ * resident in the plan (it is the next warm start).  warm_start = 1 before
+ * any solve (or after mpc_plan_create) is INVALID_ARG. */
+mpc_status mpc_solve(mpc_plan_t plan, const mpc_problem_batch* batch, void* stream);
+
+typedef struct {
+  void *u0, *x, *u, *z, *y, *objective; /* io type; any may be NULL (not copied) */
+  double* residuals;                    /* [n][4], may be NULL                   */
+  int32_t* status;                      /* [n],    may be NULL                   */
+} mpc_solution;
+
+/* Copy the resident solution into caller device buffers (stream-ordered).
+ * NOT_READY if no solve has been issued. */
+mpc_status mpc_get_solution(mpc_plan_t plan, const mpc_solution* out, void* stream);
+
+/* Replace the resident warm-start state with caller device buffers u [N][nu],
+ * z [N][m], y [N][m] (io type), e.g. to resume a controller. */
+mpc_status mpc_set_warm_state(mpc_plan_t plan, const void* u, const void* z, const void* y,
+                              void* stream);
+
+/* Closed-loop plant step of every agent under its own first stage:
+ * x0_next = A_0 x0 + B_0 u_0 + c_0 + noise, with u_0 the resident solution's
+ * first input.  noise may be NULL.  x0_next may alias x0. */
+mpc_status mpc_advance_state(mpc_plan_t plan, const mpc_problem_batch* batch, const void* noise,
+                             void* x0_next, void* stream);
+
+/* Per-kernel timing: when enabled, every launch of a solve is bracketed by
+ * HIP events on the solve's stream.  mpc_plan_get_timing synchronises the
+ * stream of the last solve and returns the accumulated milliseconds and launch
+ * counts of {stage setup + factor, ADMM iterations, KKT residual} in
+ * ms[0..2] / launches[0..2].  Enabling resets the counters. */
+mpc_status mpc_plan_set_timing(mpc_plan_t plan, int32_t enable);
+mpc_status mpc_plan_get_timing(mpc_plan_t plan, double* ms, int64_t* launches);
+
+/* Which kernel family the plan runs (1 generic, 2 fused) and its launch shape. */
+mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* threads_per_agent,
+                               int32_t* lds_bytes);
+
+/* Thread-local description of the last error returned on this thread. */
+const char* mpc_last_error(void);
+
+/* Library version string. */
+const char* mpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPC_H */

@@ -1,0 +1,648 @@
+// Generic kernels of the batched MPC solve: one workgroup per agent, any shape
+// within the plan limits, templated on the arithmetic type (double or float).
+//
+//   k_setup_factor : stage bounds/penalties and the Riccati factor (role of
+//                    Eq. (ldl), once per solve), written to the workspace as
+//                    K_k, A_cl,k = A_k + B_k K_k, H_k^{-1} and s_k = P_{k+1} c_k.
+//   k_admm         : all ADMM iterations (role of Eqs. (backsolve_1)-(backsolve_2)
+//                    plus projection and dual update, Alg. 1's QP loop).
+//   k_residual     : FP64 KKT residuals and objective of the returned iterate.
+//   k_advance      : closed-loop plant step x0 <- A_0 x0 + B_0 u_0 + c_0 + noise.
+//
+// The back-sweep is run in closed-loop form: with g_k = qt_k + K_k' rt_k,
+//   p'_k = p_{k+1} + s_k,  p_k = g_k + A_cl,k' p'_k,  d_k = -H_k^{-1}(rt_k + B_k' p'_k)
+// and the rollout as x_{k+1} = A_cl,k x_k + (B_k d_k + c_k), u_k = K_k x_k + d_k,
+// which is the textbook sweep (p_k = qt_k + A_k' p' + K_k' h, u_k = K_k x_k + d_k,
+// x_{k+1} = A_k x_k + B_k u_k + c_k) with K_k' B_k' p' folded into A_cl,k'.  The
+// serial chains then carry one nx x nx product per stage; everything else is
+// independent across stages.
+#include <math.h>
+
+#include "mpc_internal.h"
+#include "stage_rows.h"
+
+namespace mpc {
+
+template <typename T>
+__device__ inline bool finite_all(const T* p, int64_t n, int tid, int nt) {
+  bool ok = true;
+  for (int64_t i = tid; i < n; i += nt) ok &= (bool)isfinite(p[i]);
+  return ok;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverConsts sc,
+               T* __restrict__ ws, int32_t* __restrict__ status) {
+  const int a = blockIdx.x;
+  if (a >= n_agents) return;
+  const AgentDesc d = desc[a];
+  const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* P = reinterpret_cast<T*>(smem_raw);  // P_{k+1}, then P_k       nx*nx
+  T* Ak = P + nx * nx;                    // A_k                     nx*nx
+  T* PA = Ak + nx * nx;                   // P_{k+1} A_k             nx*nx
+  T* Bk = PA + nx * nx;                   // B_k                     nx*nu
+  T* PB = Bk + nx * nu;                   // P_{k+1} B_k, then K_k   nx*nu
+  T* Kk = PB;
+  T* G = PB + nx * nu;                    // B_k' P A_k              nu*nx
+  T* H = G + nu * nx;                     // H_k -> L_k              nu*nu
+  T* rdg = H + nu * nu;                   // diag Rt_k               nu
+  __shared__ int s_flag;
+
+  const T* A = in.A + d.oA;
+  const T* B = in.B + d.oB;
+  const T* c = in.c + d.oc;
+  const T* q = in.q + d.oq;
+  const T* r = in.r + d.orr;
+  const T* tau = in.tau + d.otau;
+  const uint8_t* stance = in.st + d.ost;
+  const T mu = in.mu[a];
+  T* wK = ws + d.ows;
+  T* wAcl = wK + (int64_t)N * nu * nx;
+  T* wHi = wAcl + (int64_t)N * nx * nx;
+  T* wS = wHi + (int64_t)N * nu * nu;
+  T* wl = wS + (int64_t)N * nx;
+  T* wh = wl + (int64_t)N * m;
+  T* wrho = wh + (int64_t)N * m;
+
+  // Non-finite inputs mark the agent and stop it (no other agent is touched).
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  bool ok = finite_all(A, (int64_t)N * nx * nx, tid, nt) && finite_all(B, (int64_t)N * nx * nu, tid, nt) &&
+            finite_all(c, (int64_t)N * nx, tid, nt) && finite_all(q, nx, tid, nt) &&
+            finite_all(r, nu, tid, nt) && finite_all(in.xr + d.oxr, (int64_t)(N + 1) * nx, tid, nt) &&
+            finite_all(in.x0 + d.ox0, nx, tid, nt) && finite_all(tau, d.n_tau, tid, nt) &&
+            (bool)isfinite(mu) && (!in.uref || finite_all(in.uref + d.ou, (int64_t)N * nu, tid, nt));
+  if (!ok) atomicOr(&s_flag, 1);
+  __syncthreads();
+  if (s_flag) {
+    if (tid == 0) status[a] = AGENT_NONFINITE;
+    return;
+  }
+
+  // Stage bounds and penalties (a1).
+  for (int idx = tid; idx < N * m; idx += nt) {
+    const int k = idx / m, i = idx % m;
+    T lo, hi, rr;
+    row_bounds<T>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rr);
+    wl[idx] = lo;
+    wh[idx] = hi;
+    wrho[idx] = rr;
+  }
+  for (int idx = tid; idx < nx * nx; idx += nt) {
+    const int i = idx / nx, j = idx % nx;
+    P[idx] = (i == j) ? q[i] + (T)sc.sigma : (T)0;
+  }
+  __syncthreads();
+
+  for (int k = N - 1; k >= 0; --k) {
+    const T* Ag = A + (int64_t)k * nx * nx;
+    const T* Bg = B + (int64_t)k * nx * nu;
+    for (int idx = tid; idx < nx * nx; idx += nt) Ak[idx] = Ag[idx];
+    for (int idx = tid; idx < nx * nu; idx += nt) Bk[idx] = Bg[idx];
+    for (int j = tid; j < nu; j += nt) rdg[j] = rtilde_diag<T>(d, j, r[j], mu, wrho + (int64_t)k * m, sc);
+    __syncthreads();
+    for (int idx = tid; idx < nx * nu; idx += nt) {
+      const int i = idx / nu, j = idx % nu;
+      T acc = 0;
+      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Bk[t * nu + j];
+      PB[idx] = acc;
+    }
+    for (int idx = tid; idx < nx * nx; idx += nt) {
+      const int i = idx / nx, j = idx % nx;
+      T acc = 0;
+      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Ak[t * nx + j];
+      PA[idx] = acc;
+    }
+    for (int i = tid; i < nx; i += nt) {
+      T acc = 0;
+      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * c[(int64_t)k * nx + t];
+      wS[(int64_t)k * nx + i] = acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nu * nu; idx += nt) {
+      const int i = idx / nu, j = idx % nu;
+      T acc = (i == j) ? rdg[i] : (T)0;
+      for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PB[t * nu + j];
+      H[idx] = acc;
+    }
+    for (int idx = tid; idx < nu * nx; idx += nt) {
+      const int i = idx / nx, j = idx % nx;
+      T acc = 0;
+      for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PA[t * nx + j];
+      G[idx] = acc;
+    }
+    __syncthreads();
+    // Right-looking Cholesky of H_k in place (lower triangle).
+    for (int j = 0; j < nu; ++j) {
+      if (tid == 0) {
+        const T v = H[j * nu + j];
+        if (!(v > (T)0)) s_flag = 1;
+        H[j * nu + j] = sqrt(v);
+      }
+      __syncthreads();
+      if (s_flag) break;
+      for (int i = j + 1 + tid; i < nu; i += nt) H[i * nu + j] /= H[j * nu + j];
+      __syncthreads();
+      const int rem = nu - j - 1;
+      for (int idx = tid; idx < rem * rem; idx += nt) {
+        const int i = j + 1 + idx / rem, cc = j + 1 + idx % rem;
+        if (cc <= i) H[i * nu + cc] -= H[i * nu + j] * H[cc * nu + j];
+      }
+      __syncthreads();
+    }
+    if (s_flag) {
+      if (tid == 0) status[a] = AGENT_NOT_PD;
+      return;
+    }
+    // K_k = -H_k^{-1} G_k into LDS (over the dead P B_k) and H_k^{-1} straight
+    // into the workspace, one column per thread.
+    for (int col = tid; col < nx + nu; col += nt) {
+      const bool isK = col < nx;
+      const int cc = isK ? col : col - nx;
+      T* dst = isK ? Kk : wHi + (int64_t)k * nu * nu;
+      const int ld = isK ? nx : nu;
+      for (int i = 0; i < nu; ++i) {
+        T acc = isK ? -G[i * nx + cc] : (T)(i == cc ? 1 : 0);
+        for (int t = 0; t < i; ++t) acc -= H[i * nu + t] * dst[t * ld + cc];
+        dst[i * ld + cc] = acc / H[i * nu + i];
+      }
+      for (int i = nu - 1; i >= 0; --i) {
+        T acc = dst[i * ld + cc];
+        for (int t = i + 1; t < nu; ++t) acc -= H[t * nu + i] * dst[t * ld + cc];
+        dst[i * ld + cc] = acc / H[i * nu + i];
+      }
+    }
+    __syncthreads();
+    // P_k = Q + sigma I + A_k' P A_k + G_k' K_k, symmetrised as (P_k + P_k')/2:
+    // one thread owns the pair (i, j), (j, i) and overwrites P (P_{k+1} is dead).
+    for (int idx = tid; idx < nx * nx; idx += nt) {
+      const int i = idx / nx, j = idx % nx;
+      if (j >= i) {
+        T a1 = (i == j) ? q[i] + (T)sc.sigma : (T)0, a2 = a1;
+        for (int t = 0; t < nx; ++t) {
+          a1 += Ak[t * nx + i] * PA[t * nx + j];
+          a2 += Ak[t * nx + j] * PA[t * nx + i];
+        }
+        for (int t = 0; t < nu; ++t) {
+          a1 += G[t * nx + i] * Kk[t * nx + j];
+          a2 += G[t * nx + j] * Kk[t * nx + i];
+        }
+        const T v = (T)0.5 * (a1 + a2);
+        P[i * nx + j] = v;
+        P[j * nx + i] = v;
+      }
+      T acl = Ak[idx];
+      for (int t = 0; t < nu; ++t) acl += Bk[i * nu + t] * Kk[t * nx + j];
+      wAcl[(int64_t)k * nx * nx + idx] = acl;
+    }
+    for (int idx = tid; idx < nu * nx; idx += nt) wK[(int64_t)k * nu * nx + idx] = Kk[idx];
+    __syncthreads();
+  }
+  if (tid == 0) status[a] = AGENT_OK;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverConsts sc, int iters,
+       int warm, const T* __restrict__ ws, State<T> st) {
+  const int a = blockIdx.x;
+  if (a >= n_agents) return;
+  const AgentDesc d = desc[a];
+  const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  T* X = st.x + d.ox;
+  T* U = st.u + d.ou;
+  T* Z = st.z + d.oz;
+  T* Y = st.y + d.oz;
+  if (st.status[a] != AGENT_OK) {
+    const T nan = (T)NAN;
+    for (int i = tid; i < (N + 1) * nx; i += nt) X[i] = nan;
+    for (int i = tid; i < N * nu; i += nt) U[i] = nan;
+    for (int i = tid; i < N * m; i += nt) {
+      Z[i] = nan;
+      Y[i] = nan;
+    }
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* x = reinterpret_cast<T*>(smem_raw);  // (N+1)*nx
+  T* xt = x + (N + 1) * nx;               // (N+1)*nx
+  T* u = xt + (N + 1) * nx;               // N*nu
+  T* ut = u + N * nu;                     // N*nu
+  T* rt = ut + N * nu;                    // N*nu
+  T* dv = rt + N * nu;                    // N*nu
+  T* z = dv + N * nu;                     // N*m
+  T* y = z + N * m;                       // N*m
+  T* g = y + N * m;                       // N*nx
+  T* pp = g + N * nx;                     // N*nx
+  T* e = pp + N * nx;                     // N*nx
+  T* p = e + N * nx;                      // nx
+  T* hv = p + nx;                         // N*nu
+
+  const T* A = in.A + d.oA;
+  const T* B = in.B + d.oB;
+  const T* c = in.c + d.oc;
+  const T* q = in.q + d.oq;
+  const T* r = in.r + d.orr;
+  const T* xr = in.xr + d.oxr;
+  const T* x0 = in.x0 + d.ox0;
+  const T* uref = in.uref ? in.uref + d.ou : nullptr;
+  const T mu = in.mu[a];
+  const T* wK = ws + d.ows;
+  const T* wAcl = wK + (int64_t)N * nu * nx;
+  const T* wHi = wAcl + (int64_t)N * nx * nx;
+  const T* wS = wHi + (int64_t)N * nu * nu;
+  const T* wl = wS + (int64_t)N * nx;
+  const T* wh = wl + (int64_t)N * m;
+  const T* wrho = wh + (int64_t)N * m;
+  const T sigma = (T)sc.sigma, alpha = (T)sc.alpha, oma = (T)1 - (T)sc.alpha;
+
+  for (int i = tid; i < N * nu; i += nt) u[i] = warm ? U[i] : (T)0;
+  for (int i = tid; i < N * m; i += nt) {
+    z[i] = warm ? Z[i] : (T)0;
+    y[i] = warm ? Y[i] : (T)0;
+  }
+  for (int i = tid; i < nx; i += nt) {
+    x[i] = x0[i];
+    xt[i] = x0[i];
+  }
+  __syncthreads();
+  // x^0: rollout of the dynamics under u^0.
+  for (int k = 0; k < N; ++k) {
+    for (int i = tid; i < nx; i += nt) {
+      T acc = c[(int64_t)k * nx + i];
+      const T* Ar = A + (int64_t)k * nx * nx + i * nx;
+      const T* Br = B + (int64_t)k * nx * nu + i * nu;
+      for (int t = 0; t < nx; ++t) acc += Ar[t] * x[k * nx + t];
+      for (int t = 0; t < nu; ++t) acc += Br[t] * u[k * nu + t];
+      x[(k + 1) * nx + i] = acc;
+    }
+    __syncthreads();
+  }
+
+  for (int it = 0; it < iters; ++it) {
+    // rt_k = -sigma u_k - R ubar_k + C_k'(y_k - rho_k z_k)
+    for (int idx = tid; idx < N * nu; idx += nt) {
+      const int k = idx / nu, j = idx % nu;
+      // w = y - rho z for this stage, read through ct_row on a stage-local view
+      const T* yk = y + k * m;
+      const T* zk = z + k * m;
+      const T* rk = wrho + (int64_t)k * m;
+      auto w = [&](int i) { return yk[i] - rk[i] * zk[i]; };
+      T v = w(j);
+      if (j >= d.n_tau) {
+        const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
+        const int b0 = nu + 4 * f;
+        if (cc == 0) v += w(b0) - w(b0 + 1);
+        if (cc == 1) v += w(b0 + 2) - w(b0 + 3);
+        if (cc == 2) v -= mu * (w(b0) + w(b0 + 1) + w(b0 + 2) + w(b0 + 3));
+      }
+      T acc = -sigma * u[idx] + v;
+      if (uref) acc -= r[j] * uref[idx];
+      rt[idx] = acc;
+    }
+    __syncthreads();
+    // g_k = qt_k + K_k' rt_k, qt_k = -Q r_k - sigma x_k
+    for (int idx = tid; idx < N * nx; idx += nt) {
+      const int k = idx / nx, i = idx % nx;
+      T acc = -q[i] * xr[(int64_t)k * nx + i] - sigma * x[idx];
+      const T* Kc = wK + (int64_t)k * nu * nx + i;
+      for (int j = 0; j < nu; ++j) acc += Kc[j * nx] * rt[k * nu + j];
+      g[idx] = acc;
+    }
+    for (int i = tid; i < nx; i += nt) p[i] = -q[i] * xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
+    __syncthreads();
+    // backward chain: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
+    for (int k = N - 1; k >= 0; --k) {
+      for (int i = tid; i < nx; i += nt) pp[k * nx + i] = p[i] + wS[(int64_t)k * nx + i];
+      __syncthreads();
+      if (k > 0) {
+        for (int i = tid; i < nx; i += nt) {
+          T acc = g[k * nx + i];
+          const T* Ac = wAcl + (int64_t)k * nx * nx + i;
+          for (int t = 0; t < nx; ++t) acc += Ac[t * nx] * pp[k * nx + t];
+          p[i] = acc;
+        }
+        __syncthreads();
+      }
+    }
+    // d_k = -H_k^{-1}(rt_k + B_k' p'_k),  e_k = B_k d_k + c_k
+    for (int idx = tid; idx < N * nu; idx += nt) {
+      const int k = idx / nu, j = idx % nu;
+      T acc = rt[idx];
+      const T* Bc = B + (int64_t)k * nx * nu + j;
+      for (int t = 0; t < nx; ++t) acc += Bc[t * nu] * pp[k * nx + t];
+      hv[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < N * nu; idx += nt) {
+      const int k = idx / nu, j = idx % nu;
+      T acc = 0;
+      const T* Hr = wHi + (int64_t)k * nu * nu + j * nu;
+      for (int t = 0; t < nu; ++t) acc += Hr[t] * hv[k * nu + t];
+      dv[idx] = -acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < N * nx; idx += nt) {
+      const int k = idx / nx, i = idx % nx;
+      T acc = c[(int64_t)k * nx + i];
+      const T* Br = B + (int64_t)k * nx * nu + i * nu;
+      for (int t = 0; t < nu; ++t) acc += Br[t] * dv[k * nu + t];
+      e[idx] = acc;
+    }
+    __syncthreads();
+    // forward chain: xt_{k+1} = A_cl,k xt_k + e_k
+    for (int k = 0; k < N; ++k) {
+      for (int i = tid; i < nx; i += nt) {
+        T acc = e[k * nx + i];
+        const T* Ar = wAcl + (int64_t)k * nx * nx + i * nx;
+        for (int t = 0; t < nx; ++t) acc += Ar[t] * xt[k * nx + t];
+        xt[(k + 1) * nx + i] = acc;
+      }
+      __syncthreads();
+    }
+    // ut_k = K_k xt_k + d_k
+    for (int idx = tid; idx < N * nu; idx += nt) {
+      const int k = idx / nu, j = idx % nu;
+      T acc = dv[idx];
+      const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
+      for (int t = 0; t < nx; ++t) acc += Kr[t] * xt[k * nx + t];
+      ut[idx] = acc;
+    }
+    __syncthreads();
+    // relaxation, projection onto [l, h], dual update
+    for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) x[idx] = alpha * xt[idx] + oma * x[idx];
+    for (int idx = tid; idx < N * m; idx += nt) {
+      const int k = idx / m, i = idx % m;
+      const T zeta = c_row<T>(d, i, mu, ut + k * nu);
+      const T w = alpha * zeta + oma * z[idx];
+      const T rr = wrho[(int64_t)k * m + i];
+      const T zn = fmin(fmax(w + y[idx] / rr, wl[(int64_t)k * m + i]), wh[(int64_t)k * m + i]);
+      y[idx] = y[idx] + rr * (w - zn);
+      z[idx] = zn;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < N * nu; idx += nt) u[idx] = alpha * ut[idx] + oma * u[idx];
+    __syncthreads();
+  }
+
+  bool ok = true;
+  for (int i = tid; i < (N + 1) * nx; i += nt) {
+    X[i] = x[i];
+    ok &= (bool)isfinite(x[i]);
+  }
+  for (int i = tid; i < N * nu; i += nt) {
+    U[i] = u[i];
+    ok &= (bool)isfinite(u[i]);
+  }
+  for (int i = tid; i < N * m; i += nt) {
+    Z[i] = z[i];
+    Y[i] = y[i];
+    ok &= (bool)isfinite(z[i]) && (bool)isfinite(y[i]);
+  }
+  if (!ok) st.status[a] = AGENT_NONFINITE;
+}
+
+// Block-wide reductions through LDS (blockDim.x <= 256).
+__device__ inline double block_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// FP64 KKT residuals of the returned iterate (the role of the solution check
+// that follows the QP loop in Alg. 1).  Costates of the dynamics rows come from
+// the adjoint sweep lambda_N = Q(x_N - r_N), lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_residual(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverConsts sc,
+           State<T> st) {
+  const int a = blockIdx.x;
+  if (a >= n_agents) return;
+  const AgentDesc d = desc[a];
+  const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double red[256];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lam = reinterpret_cast<double*>(smem_raw);  // (N+1)*nx
+  if (st.status[a] != AGENT_OK && st.status[a] != AGENT_CONVERGED) {
+    if (tid < 4) st.res[(int64_t)a * 4 + tid] = NAN;
+    if (tid == 0) st.obj[a] = (T)NAN;
+    return;
+  }
+  const T* A = in.A + d.oA;
+  const T* B = in.B + d.oB;
+  const T* c = in.c + d.oc;
+  const T* q = in.q + d.oq;
+  const T* r = in.r + d.orr;
+  const T* xr = in.xr + d.oxr;
+  const T* x0 = in.x0 + d.ox0;
+  const T* tau = in.tau + d.otau;
+  const uint8_t* stance = in.st + d.ost;
+  const T* uref = in.uref ? in.uref + d.ou : nullptr;
+  const double mu = (double)in.mu[a];
+  const T* x = st.x + d.ox;
+  const T* u = st.u + d.ou;
+  const T* z = st.z + d.oz;
+  const T* y = st.y + d.oz;
+
+  double obj = 0.0;
+  for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) {
+    const double ee = (double)x[idx] - (double)xr[idx];
+    obj += 0.5 * (double)q[idx % nx] * ee * ee;
+  }
+  for (int idx = tid; idx < N * nu; idx += nt) {
+    const double ee = (double)u[idx] - (uref ? (double)uref[idx] : 0.0);
+    obj += 0.5 * (double)r[idx % nu] * ee * ee;
+  }
+  for (int i = tid; i < nx; i += nt)
+    lam[N * nx + i] = (double)q[i] * ((double)x[N * nx + i] - (double)xr[N * nx + i]);
+  __syncthreads();
+  for (int k = N - 1; k >= 1; --k) {
+    for (int i = tid; i < nx; i += nt) {
+      double acc = (double)q[i] * ((double)x[k * nx + i] - (double)xr[k * nx + i]);
+      const T* Ac = A + (int64_t)k * nx * nx + i;
+      for (int t = 0; t < nx; ++t) acc += (double)Ac[t * nx] * lam[(k + 1) * nx + t];
+      lam[k * nx + i] = acc;
+    }
+    __syncthreads();
+  }
+  double rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
+  for (int i = tid; i < nx; i += nt) ry = fmax(ry, fabs((double)x[i] - (double)x0[i]));
+  for (int idx = tid; idx < N * nu; idx += nt) {
+    const int k = idx / nu, j = idx % nu;
+    double acc = (double)r[j] * ((double)u[idx] - (uref ? (double)uref[idx] : 0.0));
+    const T* Bc = B + (int64_t)k * nx * nu + j;
+    for (int t = 0; t < nx; ++t) acc += (double)Bc[t * nu] * lam[(k + 1) * nx + t];
+    // (C' y)_j
+    const T* yk = y + k * m;
+    double v = (double)yk[j];
+    if (j >= d.n_tau) {
+      const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
+      const T* yp = yk + nu + 4 * f;
+      if (cc == 0) v += (double)yp[0] - (double)yp[1];
+      if (cc == 1) v += (double)yp[2] - (double)yp[3];
+      if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
+    }
+    rd = fmax(rd, fabs(acc + v));
+  }
+  for (int idx = tid; idx < N * nx; idx += nt) {
+    const int k = idx / nx, i = idx % nx;
+    double acc = (double)x[(k + 1) * nx + i] - (double)c[idx];
+    const T* Ar = A + (int64_t)k * nx * nx + i * nx;
+    const T* Br = B + (int64_t)k * nx * nu + i * nu;
+    for (int t = 0; t < nx; ++t) acc -= (double)Ar[t] * (double)x[k * nx + t];
+    for (int t = 0; t < nu; ++t) acc -= (double)Br[t] * (double)u[k * nu + t];
+    ry = fmax(ry, fabs(acc));
+  }
+  for (int idx = tid; idx < N * m; idx += nt) {
+    const int k = idx / m, i = idx % m;
+    double cu;
+    const T* uk = u + k * nu;
+    if (i < nu) {
+      cu = (double)uk[i];
+    } else {
+      const int f = (i - nu) >> 2, pp = (i - nu) & 3, b = d.n_tau + f * d.foot_dim;
+      const double t = (pp < 2) ? (double)uk[b] : (double)uk[b + 1];
+      cu = ((pp & 1) ? -t : t) - mu * (double)uk[b + 2];
+    }
+    rp = fmax(rp, fabs(cu - (double)z[idx]));
+    T lo_t, hi_t, rho_t;
+    row_bounds<T>(d, i, stance + k * d.n_feet, tau, sc, lo_t, hi_t, rho_t);
+    const double lo = (double)lo_t, hi = (double)hi_t, zz = (double)z[idx], yy = (double)y[idx];
+    const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
+    const double ca = isinf(hi) ? yp : fmin(yp, hi - zz);
+    const double cb = isinf(lo) ? ym : fmin(ym, zz - lo);
+    rc = fmax(rc, fmax(fabs(ca), fabs(cb)));
+    if (zz > hi) rc = fmax(rc, zz - hi);
+    if (zz < lo) rc = fmax(rc, lo - zz);
+  }
+  rp = block_max(rp, red);
+  rd = block_max(rd, red);
+  ry = block_max(ry, red);
+  rc = block_max(rc, red);
+  obj = block_sum(obj, red);
+  if (tid == 0) {
+    double* res = st.res + (int64_t)a * 4;
+    res[0] = rp;
+    res[1] = rd;
+    res[2] = ry;
+    res[3] = rc;
+    st.obj[a] = (T)obj;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_advance(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, const T* __restrict__ u,
+          const T* __restrict__ noise, T* __restrict__ x0n) {
+  const int a = blockIdx.x;
+  if (a >= n_agents) return;
+  const AgentDesc d = desc[a];
+  const int nx = d.nx, nu = d.nu;
+  const T* A0 = in.A + d.oA;
+  const T* B0 = in.B + d.oB;
+  const T* x0 = in.x0 + d.ox0;
+  const T* u0 = u + d.ou;
+  T acc[2] = {0, 0};
+  for (int r = 0; r < 2; ++r) {
+    const int i = threadIdx.x + r * 64;
+    if (i < nx) {
+      T v = in.c[d.oc + i] + (noise ? noise[d.ox0 + i] : (T)0);
+      for (int t = 0; t < nx; ++t) v += A0[i * nx + t] * x0[t];
+      for (int t = 0; t < nu; ++t) v += B0[i * nu + t] * u0[t];
+      acc[r] = v;
+    }
+  }
+  __syncthreads();  // x0n may alias x0: all reads finish before any write
+  for (int r = 0; r < 2; ++r) {
+    const int i = threadIdx.x + r * 64;
+    if (i < nx) x0n[d.ox0 + i] = acc[r];
+  }
+}
+
+template <typename T>
+hipError_t launch_generic_factor(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
+                                 SolverConsts sc, T* ws, int32_t* status, size_t lds,
+                                 hipStream_t stream) {
+  hipLaunchKernelGGL(k_setup_factor<T>, dim3(n_agents), dim3(256), lds, stream, d_desc, n_agents,
+                     in, sc, ws, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_generic_admm(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
+                               SolverConsts sc, int iters, int warm, const T* ws, State<T> st,
+                               size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(k_admm<T>, dim3(n_agents), dim3(256), lds, stream, d_desc, n_agents, in, sc,
+                     iters, warm, ws, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual(const AgentDesc* d_desc, int n_agents, Inputs<T> in, SolverConsts sc,
+                           State<T> st, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(k_residual<T>, dim3(n_agents), dim3(256), lds, stream, d_desc, n_agents, in,
+                     sc, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_advance(const AgentDesc* d_desc, int n_agents, Inputs<T> in, const T* u,
+                          const T* noise, T* x0_next, hipStream_t stream) {
+  hipLaunchKernelGGL(k_advance<T>, dim3(n_agents), dim3(64), 0, stream, d_desc, n_agents, in, u,
+                     noise, x0_next);
+  return hipGetLastError();
+}
+
+hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds_res) {
+  hipError_t e = hipSuccess;
+#define MPC_SET(kern, bytes)                                                                  \
+  if (e == hipSuccess)                                                                        \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes));
+  MPC_SET(k_setup_factor<float>, lds_factor)
+  MPC_SET(k_setup_factor<double>, lds_factor)
+  MPC_SET(k_admm<float>, lds_admm)
+  MPC_SET(k_admm<double>, lds_admm)
+  MPC_SET(k_residual<float>, lds_res)
+  MPC_SET(k_residual<double>, lds_res)
+#undef MPC_SET
+  return e;
+}
+
+#define MPC_INSTANTIATE(T)                                                                         \
+  template hipError_t launch_generic_factor<T>(const AgentDesc*, int, Inputs<T>, SolverConsts, T*, \
+                                               int32_t*, size_t, hipStream_t);                     \
+  template hipError_t launch_generic_admm<T>(const AgentDesc*, int, Inputs<T>, SolverConsts, int,  \
+                                             int, const T*, State<T>, size_t, hipStream_t);        \
+  template hipError_t launch_residual<T>(const AgentDesc*, int, Inputs<T>, SolverConsts, State<T>, \
+                                         size_t, hipStream_t);                                     \
+  template hipError_t launch_advance<T>(const AgentDesc*, int, Inputs<T>, const T*, const T*, T*,  \
+                                        hipStream_t);
+MPC_INSTANTIATE(float)
+MPC_INSTANTIATE(double)
+
+}  // namespace mpc

@@ -1,0 +1,72 @@
+// Internal declarations shared by the HIP translation units of the solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpc {
+
+// Per-agent shape and offsets.  Input offsets index the caller's concatenated
+// arrays (elements), solution offsets index the plan's resident x/u/z/y, and
+// ws is the element offset of the agent's factor workspace.
+struct AgentDesc {
+  int32_t N, nx, nu, n_tau, n_feet, foot_dim, m, pad;
+  int64_t oA, oB, oc, oq, orr, oxr, ox0, otau, ost;
+  int64_t ox, ou, oz;
+  int64_t ows;
+};
+
+struct SolverConsts {
+  double rho, sigma, alpha, rho_eq, rho_min;
+};
+
+template <typename T>
+struct Inputs {
+  const T *A, *B, *c, *q, *r, *xr, *x0, *tau, *mu;
+  const uint8_t* st;
+  const T* uref;  // may be null
+};
+
+template <typename T>
+struct State {
+  T *x, *u, *z, *y;
+  T* obj;
+  double* res;
+  int32_t* status;
+};
+
+enum : int32_t { AGENT_OK = 0, AGENT_CONVERGED = 1, AGENT_NOT_PD = 2, AGENT_NONFINITE = 3 };
+
+// Elements of factor workspace per agent for the generic kernels:
+// K [N][nu][nx], Acl [N][nx][nx], Hinv [N][nu][nu], s [N][nx], l/h/rho [N][m].
+inline int64_t generic_ws_elems(int N, int nx, int nu, int m) {
+  return (int64_t)N * ((int64_t)nu * nx + (int64_t)nx * nx + (int64_t)nu * nu + nx + 3 * m);
+}
+
+inline size_t generic_factor_lds(int nx, int nu, size_t esz) {
+  return esz * (size_t)(3 * nx * nx + 3 * nx * nu + nu * nu + nu);
+}
+inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz) {
+  return esz * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu);
+}
+
+// Raise the dynamic-LDS limit of the generic kernels to what a plan needs.
+hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds_res);
+
+// Launchers (generic kernels, one workgroup per agent).
+template <typename T>
+hipError_t launch_generic_factor(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
+                                 SolverConsts sc, T* ws, int32_t* status, size_t lds,
+                                 hipStream_t stream);
+template <typename T>
+hipError_t launch_generic_admm(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
+                               SolverConsts sc, int iters, int warm, const T* ws, State<T> st,
+                               size_t lds, hipStream_t stream);
+template <typename T>
+hipError_t launch_residual(const AgentDesc* d_desc, int n_agents, Inputs<T> in, SolverConsts sc,
+                           State<T> st, size_t lds, hipStream_t stream);
+template <typename T>
+hipError_t launch_advance(const AgentDesc* d_desc, int n_agents, Inputs<T> in, const T* u,
+                          const T* noise, T* x0_next, hipStream_t stream);
+
+}  // namespace mpc

@@ -1,0 +1,482 @@
+// Host side of the C ABI declared in include/mpc.h: plan creation and
+// validation, device workspace, kernel dispatch, solution export, timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpc.h"
+#include "fused.h"
+#include "mpc_internal.h"
+
+using namespace mpc;
+
+namespace {
+
+thread_local std::string g_err;
+
+mpc_status fail(mpc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(_e == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,          \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                      \
+  } while (0)
+
+constexpr int kPhases = 3;
+
+}  // namespace
+
+struct mpc_plan_s {
+  mpc_plan_desc desc{};
+  std::vector<mpc_shape> shapes;
+  std::vector<AgentDesc> hdesc;
+  int n = 0;
+  bool fp64 = false;
+  size_t esz = 4;
+  int kernel = 1;
+  int maxN = 0, maxnx = 0, maxnu = 0, maxm = 0;
+  int64_t nX = 0, nU = 0, nZ = 0, nWS = 0;
+  AgentDesc* d_desc = nullptr;
+  void* d_ws = nullptr;
+  void *d_x = nullptr, *d_u = nullptr, *d_z = nullptr, *d_y = nullptr, *d_obj = nullptr;
+  double* d_res = nullptr;
+  int32_t* d_status = nullptr;
+  bool solved = false;
+  size_t lds_factor = 0, lds_admm = 0, lds_res = 0;
+  int fused_threads = 0;
+  size_t fused_lds = 0;
+  // timing
+  bool timing = false;
+  hipStream_t last_stream = nullptr;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[kPhases] = {0, 0, 0};
+  int64_t launches[kPhases] = {0, 0, 0};
+};
+
+static mpc_status validate_shape(const mpc_shape& s, int idx) {
+  char buf[256];
+  if (s.N < 1 || s.N > 64 || s.nx < 1 || s.nx > 64 || s.nu < 1 || s.nu > 32 || s.n_feet < 0 ||
+      s.n_feet > 8 || s.n_tau < 0 || (s.foot_dim != 3 && s.foot_dim != 6) ||
+      s.nu != s.n_tau + s.n_feet * s.foot_dim) {
+    snprintf(buf, sizeof buf,
+             "agent %d: unsupported shape (N=%d nx=%d nu=%d n_tau=%d n_feet=%d foot_dim=%d)", idx,
+             s.N, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim);
+    return fail(MPC_ERR_UNSUPPORTED_SHAPE, buf);
+  }
+  return MPC_OK;
+}
+
+extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
+  if (!d) return;
+  memset(d, 0, sizeof(*d));
+  d->precision = MPC_FP32;
+  d->admm_iters = 50;
+  d->rho = 0.1;
+  d->sigma = 1e-6;
+  d->alpha = 1.6;
+  d->rho_eq_scale = 1e3;
+  d->rho_min = 1e-6;
+  d->max_refine_sweeps = 3;
+  d->refine_tol = 1e-6;
+  d->device = 0;
+  d->kernel = 0;
+}
+
+extern "C" const char* mpc_last_error(void) { return g_err.c_str(); }
+extern "C" const char* mpc_version(void) { return "mpc-mi355x 0.1.0 (gfx950)"; }
+
+static void free_plan(mpc_plan_s* p) {
+  if (!p) return;
+  hipFree(p->d_desc);
+  hipFree(p->d_ws);
+  hipFree(p->d_x);
+  hipFree(p->d_u);
+  hipFree(p->d_z);
+  hipFree(p->d_y);
+  hipFree(p->d_obj);
+  hipFree(p->d_res);
+  hipFree(p->d_status);
+  for (auto e : p->ev_pool) hipEventDestroy(e);
+  for (auto& pe : p->pending) {
+    hipEventDestroy(pe.second.first);
+    hipEventDestroy(pe.second.second);
+  }
+  delete p;
+}
+
+extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out) {
+  if (!desc || !out) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (desc->n_agents <= 0 || !desc->shapes) return fail(MPC_ERR_INVALID_ARG, "n_agents must be > 0 with a shapes array");
+  if (desc->precision < MPC_FP64 || desc->precision > MPC_FP16_REFINE)
+    return fail(MPC_ERR_INVALID_ARG, "unknown precision");
+  if (desc->admm_iters <= 0) return fail(MPC_ERR_INVALID_ARG, "admm_iters must be > 0");
+  if (!(desc->rho > 0) || !(desc->sigma >= 0) || !(desc->alpha > 0 && desc->alpha < 2) ||
+      !(desc->rho_eq_scale > 0) || !(desc->rho_min > 0) || !std::isfinite(desc->rho) ||
+      !std::isfinite(desc->sigma) || !std::isfinite(desc->rho_eq_scale) || !std::isfinite(desc->rho_min))
+    return fail(MPC_ERR_INVALID_ARG, "solver constants out of range (rho>0, sigma>=0, 0<alpha<2, rho_eq_scale>0, rho_min>0)");
+  if (desc->kernel < 0 || desc->kernel > 2) return fail(MPC_ERR_INVALID_ARG, "unknown kernel selector");
+  for (int a = 0; a < desc->n_agents; ++a) {
+    mpc_status vs = validate_shape(desc->shapes[a], a);
+    if (vs != MPC_OK) return vs;
+  }
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (desc->device < 0 || desc->device >= ndev) return fail(MPC_ERR_INVALID_ARG, "device ordinal out of range");
+
+  auto* p = new mpc_plan_s();
+  p->desc = *desc;
+  p->n = desc->n_agents;
+  p->shapes.assign(desc->shapes, desc->shapes + desc->n_agents);
+  p->desc.shapes = nullptr;
+  p->fp64 = desc->precision == MPC_FP64;
+  p->esz = p->fp64 ? 8 : 4;
+
+  p->hdesc.resize(p->n);
+  AgentDesc cur{};
+  int64_t oA = 0, oB = 0, oc = 0, oq = 0, orr = 0, oxr = 0, ox0 = 0, otau = 0, ost = 0, ox = 0,
+          ou = 0, oz = 0, ows = 0;
+  bool uniform = true;
+  for (int a = 0; a < p->n; ++a) {
+    const mpc_shape& s = p->shapes[a];
+    if (a > 0 && memcmp(&s, &p->shapes[0], sizeof(s)) != 0) uniform = false;
+    cur.N = s.N;
+    cur.nx = s.nx;
+    cur.nu = s.nu;
+    cur.n_tau = s.n_tau;
+    cur.n_feet = s.n_feet;
+    cur.foot_dim = s.foot_dim;
+    cur.m = s.nu + 4 * s.n_feet;
+    cur.oA = oA; cur.oB = oB; cur.oc = oc; cur.oq = oq; cur.orr = orr; cur.oxr = oxr;
+    cur.ox0 = ox0; cur.otau = otau; cur.ost = ost; cur.ox = ox; cur.ou = ou; cur.oz = oz;
+    cur.ows = ows;
+    p->hdesc[a] = cur;
+    oA += (int64_t)s.N * s.nx * s.nx;
+    oB += (int64_t)s.N * s.nx * s.nu;
+    oc += (int64_t)s.N * s.nx;
+    oq += s.nx;
+    orr += s.nu;
+    oxr += (int64_t)(s.N + 1) * s.nx;
+    ox0 += s.nx;
+    otau += s.n_tau;
+    ost += (int64_t)s.N * s.n_feet;
+    ox += (int64_t)(s.N + 1) * s.nx;
+    ou += (int64_t)s.N * s.nu;
+    oz += (int64_t)s.N * cur.m;
+    ows += generic_ws_elems(s.N, s.nx, s.nu, cur.m);
+    p->maxN = std::max(p->maxN, s.N);
+    p->maxnx = std::max(p->maxnx, s.nx);
+    p->maxnu = std::max(p->maxnu, s.nu);
+    p->maxm = std::max(p->maxm, cur.m);
+  }
+  p->nX = ox;
+  p->nU = ou;
+  p->nZ = oz;
+  p->nWS = ows;
+  p->lds_factor = generic_factor_lds(p->maxnx, p->maxnu, p->esz);
+  p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz);
+  p->lds_res = sizeof(double) * (size_t)(p->maxN + 1) * p->maxnx;
+
+  // Kernel family: the fused single-launch kernel serves uniform FP32 batches
+  // of shapes it was built for; everything else takes the generic kernels.
+  const bool fused_ok = desc->precision == MPC_FP32 && uniform &&
+                        fused_supported(p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu,
+                                        p->shapes[0].n_feet);
+  if (desc->kernel == 2 && !fused_ok) {
+    delete p;
+    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "fused kernel requested for a batch it does not support");
+  }
+  p->kernel = (desc->kernel == 1 || !fused_ok) ? 1 : 2;
+  if (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE) p->kernel = 1;
+
+  hipError_t e = hipSetDevice(desc->device);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(MPC_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  int lds_max = 0;
+  hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device);
+  if ((int64_t)p->lds_factor > lds_max || (int64_t)p->lds_admm > lds_max) {
+    delete p;
+    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "shapes need more LDS than the device offers");
+  }
+  e = generic_set_lds_limits(p->lds_factor, p->lds_admm, p->lds_res);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(MPC_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  }
+  if (p->kernel == 2) {
+    fused_launch_shape(p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu, p->shapes[0].n_feet,
+                       &p->fused_threads, &p->fused_lds);
+  }
+  auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
+    return hipMalloc(ptr, bytes ? bytes : 16);
+  };
+  hipError_t errs[9] = {
+      alloc((void**)&p->d_desc, sizeof(AgentDesc) * p->n),
+      alloc(&p->d_ws, p->esz * (size_t)p->nWS),
+      alloc(&p->d_x, p->esz * (size_t)p->nX),
+      alloc(&p->d_u, p->esz * (size_t)p->nU),
+      alloc(&p->d_z, p->esz * (size_t)p->nZ),
+      alloc(&p->d_y, p->esz * (size_t)p->nZ),
+      alloc(&p->d_obj, p->esz * (size_t)p->n),
+      alloc((void**)&p->d_res, sizeof(double) * 4 * (size_t)p->n),
+      alloc((void**)&p->d_status, sizeof(int32_t) * (size_t)p->n)};
+  for (hipError_t ee : errs) {
+    if (ee != hipSuccess) {
+      mpc_status st = fail(ee == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,
+                           std::string("hipMalloc: ") + hipGetErrorString(ee));
+      free_plan(p);
+      return st;
+    }
+  }
+  e = hipMemcpy(p->d_desc, p->hdesc.data(), sizeof(AgentDesc) * p->n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int32_t) * p->n);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return fail(MPC_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  *out = p;
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_destroy(mpc_plan_t p) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  hipSetDevice(p->desc.device);
+  hipDeviceSynchronize();
+  free_plan(p);
+  return MPC_OK;
+}
+
+static mpc_status check_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
+  if (!b) return fail(MPC_ERR_INVALID_ARG, "null batch");
+  if (!b->A || !b->B || !b->c || !b->q_diag || !b->r_diag || !b->x_ref || !b->x0 || !b->mu ||
+      !b->stance)
+    return fail(MPC_ERR_INVALID_ARG, "null input pointer in batch");
+  bool any_tau = false;
+  for (const auto& s : p->shapes) any_tau |= s.n_tau > 0;
+  if (any_tau && !b->tau_max) return fail(MPC_ERR_INVALID_ARG, "null tau_max");
+  if (b->warm_start != 0 && b->warm_start != 1) return fail(MPC_ERR_INVALID_ARG, "warm_start must be 0 or 1");
+  if (b->warm_start && !p->solved)
+    return fail(MPC_ERR_INVALID_ARG, "warm_start requested before any solve or warm state");
+  return MPC_OK;
+}
+
+template <typename T>
+static Inputs<T> make_inputs(const mpc_problem_batch* b) {
+  Inputs<T> in;
+  in.A = (const T*)b->A;
+  in.B = (const T*)b->B;
+  in.c = (const T*)b->c;
+  in.q = (const T*)b->q_diag;
+  in.r = (const T*)b->r_diag;
+  in.xr = (const T*)b->x_ref;
+  in.x0 = (const T*)b->x0;
+  in.tau = (const T*)b->tau_max;
+  in.mu = (const T*)b->mu;
+  in.st = b->stance;
+  in.uref = (const T*)b->u_ref;
+  return in;
+}
+
+template <typename T>
+static State<T> make_state(mpc_plan_s* p) {
+  State<T> s;
+  s.x = (T*)p->d_x;
+  s.u = (T*)p->d_u;
+  s.z = (T*)p->d_z;
+  s.y = (T*)p->d_y;
+  s.obj = (T*)p->d_obj;
+  s.res = p->d_res;
+  s.status = p->d_status;
+  return s;
+}
+
+static hipEvent_t get_event(mpc_plan_s* p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Brackets one launch with events when timing is on.
+struct PhaseTimer {
+  mpc_plan_s* p;
+  int phase;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PhaseTimer(mpc_plan_s* p_, int ph, hipStream_t s_) : p(p_), phase(ph), s(s_) {
+    if (p->timing) {
+      e0 = get_event(p);
+      e1 = get_event(p);
+      hipEventRecord(e0, s);
+    }
+  }
+  ~PhaseTimer() {
+    if (p->timing) {
+      hipEventRecord(e1, s);
+      p->pending.push_back({phase, {e0, e1}});
+    }
+  }
+};
+
+template <typename T>
+static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s) {
+  Inputs<T> in = make_inputs<T>(b);
+  State<T> st = make_state<T>(p);
+  SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale, p->desc.rho_min};
+  if (p->kernel == 2) {
+    PhaseTimer t(p, 1, s);
+    HIP_TRY(fused_solve_f32(p->d_desc, p->n, p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu,
+                            p->shapes[0].n_feet, make_inputs<float>(b), sc, p->desc.admm_iters,
+                            b->warm_start, make_state<float>(p), p->fused_threads, p->fused_lds,
+                            s));
+  } else {
+    {
+      PhaseTimer t(p, 0, s);
+      HIP_TRY(launch_generic_factor<T>(p->d_desc, p->n, in, sc, (T*)p->d_ws, p->d_status,
+                                       p->lds_factor, s));
+    }
+    {
+      PhaseTimer t(p, 1, s);
+      HIP_TRY(launch_generic_admm<T>(p->d_desc, p->n, in, sc, p->desc.admm_iters, b->warm_start,
+                                     (const T*)p->d_ws, st, p->lds_admm, s));
+    }
+  }
+  {
+    PhaseTimer t(p, 2, s);
+    HIP_TRY(launch_residual<T>(p->d_desc, p->n, in, sc, st, p->lds_res, s));
+  }
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_solve(mpc_plan_t p, const mpc_problem_batch* b, void* stream) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  mpc_status cs = check_batch(p, b);
+  if (cs != MPC_OK) return cs;
+  if (p->desc.precision != MPC_FP32 && p->desc.precision != MPC_FP64)
+    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "mixed-precision plans are not available in this build");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  p->last_stream = s;
+  mpc_status r = p->fp64 ? solve_impl<double>(p, b, s) : solve_impl<float>(p, b, s);
+  if (r == MPC_OK) p->solved = true;
+  return r;
+}
+
+extern "C" mpc_status mpc_get_solution(mpc_plan_t p, const mpc_solution* o, void* stream) {
+  if (!p || !o) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t e = p->esz;
+  if (o->x) HIP_TRY(hipMemcpyAsync(o->x, p->d_x, e * p->nX, hipMemcpyDeviceToDevice, s));
+  if (o->u) HIP_TRY(hipMemcpyAsync(o->u, p->d_u, e * p->nU, hipMemcpyDeviceToDevice, s));
+  if (o->z) HIP_TRY(hipMemcpyAsync(o->z, p->d_z, e * p->nZ, hipMemcpyDeviceToDevice, s));
+  if (o->y) HIP_TRY(hipMemcpyAsync(o->y, p->d_y, e * p->nZ, hipMemcpyDeviceToDevice, s));
+  if (o->objective) HIP_TRY(hipMemcpyAsync(o->objective, p->d_obj, e * p->n, hipMemcpyDeviceToDevice, s));
+  if (o->residuals) HIP_TRY(hipMemcpyAsync(o->residuals, p->d_res, sizeof(double) * 4 * p->n, hipMemcpyDeviceToDevice, s));
+  if (o->status) HIP_TRY(hipMemcpyAsync(o->status, p->d_status, sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, s));
+  if (o->u0) {
+    // u0 of agent a is the first nu entries of its u block: a strided gather.
+    if (p->n > 0) {
+      bool uniform = true;
+      for (int a = 1; a < p->n && uniform; ++a) uniform = p->hdesc[a].N == p->hdesc[0].N && p->hdesc[a].nu == p->hdesc[0].nu;
+      if (uniform) {
+        const size_t nu = p->hdesc[0].nu, N = p->hdesc[0].N;
+        HIP_TRY(hipMemcpy2DAsync(o->u0, nu * e, p->d_u, N * nu * e, nu * e, p->n, hipMemcpyDeviceToDevice, s));
+      } else {
+        size_t off = 0;
+        for (int a = 0; a < p->n; ++a) {
+          const size_t nu = p->hdesc[a].nu;
+          HIP_TRY(hipMemcpyAsync((char*)o->u0 + off * e, (char*)p->d_u + (size_t)p->hdesc[a].ou * e,
+                                 nu * e, hipMemcpyDeviceToDevice, s));
+          off += nu;
+        }
+      }
+    }
+  }
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_set_warm_state(mpc_plan_t p, const void* u, const void* z, const void* y,
+                                         void* stream) {
+  if (!p || !u || !z || !y) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(p->d_u, u, p->esz * p->nU, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_z, z, p->esz * p->nZ, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_y, y, p->esz * p->nZ, hipMemcpyDeviceToDevice, s));
+  p->solved = true;
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_advance_state(mpc_plan_t p, const mpc_problem_batch* b, const void* noise,
+                                        void* x0_next, void* stream) {
+  if (!p || !b || !x0_next) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!b->A || !b->B || !b->c || !b->x0) return fail(MPC_ERR_INVALID_ARG, "null input pointer in batch");
+  if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solution to apply");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  if (p->fp64) {
+    HIP_TRY(launch_advance<double>(p->d_desc, p->n, make_inputs<double>(b), (const double*)p->d_u,
+                                   (const double*)noise, (double*)x0_next, s));
+  } else {
+    HIP_TRY(launch_advance<float>(p->d_desc, p->n, make_inputs<float>(b), (const float*)p->d_u,
+                                  (const float*)noise, (float*)x0_next, s));
+  }
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_set_timing(mpc_plan_t p, int32_t enable) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  p->timing = enable != 0;
+  for (int i = 0; i < kPhases; ++i) {
+    p->ms[i] = 0;
+    p->launches[i] = 0;
+  }
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_get_timing(mpc_plan_t p, double* ms, int64_t* launches) {
+  if (!p || !ms || !launches) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  for (auto& pe : p->pending) {
+    HIP_TRY(hipEventSynchronize(pe.second.second));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+    p->ms[pe.first] += t;
+    p->launches[pe.first] += 1;
+    p->ev_pool.push_back(pe.second.first);
+    p->ev_pool.push_back(pe.second.second);
+  }
+  p->pending.clear();
+  for (int i = 0; i < kPhases; ++i) {
+    ms[i] = p->ms[i];
+    launches[i] = p->launches[i];
+  }
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_get_config(mpc_plan_t p, int32_t* kernel, int32_t* threads,
+                                          int32_t* lds) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  if (kernel) *kernel = p->kernel;
+  if (threads) *threads = p->kernel == 2 ? p->fused_threads : 256;
+  if (lds) *lds = (int32_t)(p->kernel == 2 ? p->fused_lds : std::max(p->lds_factor, p->lds_admm));
+  return MPC_OK;
+}

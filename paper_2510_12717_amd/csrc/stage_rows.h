@@ -1,0 +1,99 @@
+// Device helpers for the per-stage constraint rows C_k = [I_nu ; friction pyramid].
+//
+// Row layout (m = nu + 4 n_feet rows per stage):
+//   rows 0 .. n_tau-1              torque box            [-tau_max, tau_max]
+//   rows n_tau + f*fd + j          foot f, component j   stance: f_z >= 0, others free
+//                                                        swing : [0, 0]
+//   rows nu + 4f + {0,1,2,3}       pyramid facets of f   f_x - mu f_z, -f_x - mu f_z,
+//                                                        f_y - mu f_z, -f_y - mu f_z
+//                                                        stance: <= 0, swing: free
+// These are the contact and swing conditions of Eq. (mpc_formulation) with the
+// friction cone replaced by its 4-sided outer pyramid.  The penalty of a row is
+// rho, rho_eq_scale * rho for equality rows (l == h) and rho_min for rows with
+// both bounds infinite (OSQP's choice, adopted in Sec. III-B).  The four facets
+// of one foot always share a penalty, so C_k' diag(rho) C_k is diagonal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mpc_internal.h"
+
+namespace mpc {
+
+template <typename T>
+__device__ inline T pos_inf() {
+  return (T)INFINITY;
+}
+
+// Bounds and penalty of row i at a stage with stance flags st (n_feet bytes).
+template <typename T>
+__device__ inline void row_bounds(const AgentDesc& d, int i, const uint8_t* st, const T* tau,
+                                  const SolverConsts& sc, T& lo, T& hi, T& rho) {
+  const T inf = pos_inf<T>();
+  if (i < d.n_tau) {
+    lo = -tau[i];
+    hi = tau[i];
+  } else if (i < d.nu) {
+    const int f = (i - d.n_tau) / d.foot_dim, j = (i - d.n_tau) % d.foot_dim;
+    if (st[f]) {
+      lo = (j == 2) ? (T)0 : -inf;
+      hi = inf;
+    } else {
+      lo = (T)0;
+      hi = (T)0;
+    }
+  } else {
+    const int f = (i - d.nu) >> 2;
+    lo = -inf;
+    hi = st[f] ? (T)0 : inf;
+  }
+  if (lo == hi)
+    rho = (T)(sc.rho_eq * sc.rho);
+  else if (isinf(lo) && isinf(hi))
+    rho = (T)sc.rho_min;
+  else
+    rho = (T)sc.rho;
+}
+
+// Diagonal of R + sigma I + C' diag(rho) C for input j (rho = this stage's row penalties).
+template <typename T>
+__device__ inline T rtilde_diag(const AgentDesc& d, int j, T rj, T mu, const T* rho,
+                                const SolverConsts& sc) {
+  T v = rj + (T)sc.sigma + rho[j];
+  if (j >= d.n_tau) {
+    const int f = (j - d.n_tau) / d.foot_dim, c = (j - d.n_tau) % d.foot_dim;
+    const T* rp = rho + d.nu + 4 * f;
+    if (c == 0) v += rp[0] + rp[1];
+    if (c == 1) v += rp[2] + rp[3];
+    if (c == 2) v += mu * mu * (rp[0] + rp[1] + rp[2] + rp[3]);
+  }
+  return v;
+}
+
+// (C' w)_j for one stage (w has m entries).
+template <typename T>
+__device__ inline T ct_row(const AgentDesc& d, int j, T mu, const T* w) {
+  T v = w[j];
+  if (j >= d.n_tau) {
+    const int f = (j - d.n_tau) / d.foot_dim, c = (j - d.n_tau) % d.foot_dim;
+    const T* wp = w + d.nu + 4 * f;
+    if (c == 0) v += wp[0] - wp[1];
+    if (c == 1) v += wp[2] - wp[3];
+    if (c == 2) v -= mu * (wp[0] + wp[1] + wp[2] + wp[3]);
+  }
+  return v;
+}
+
+// (C u)_i for one stage.
+template <typename T>
+__device__ inline T c_row(const AgentDesc& d, int i, T mu, const T* u) {
+  if (i < d.nu) return u[i];
+  const int f = (i - d.nu) >> 2, p = (i - d.nu) & 3;
+  const int b = d.n_tau + f * d.foot_dim;
+  const T fz = u[b + 2];
+  const T t = (p < 2) ? u[b] : u[b + 1];
+  return ((p & 1) ? -t : t) - mu * fz;
+}
+
+}  // namespace mpc

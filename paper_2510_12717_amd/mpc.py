@@ -1,0 +1,222 @@
+"""ctypes binding of the C ABI in ``include/mpc.h`` (argument marshalling only).
+
+Every step of the solve runs in the HIP library ``libmpc_hip.so``; PyTorch is
+used here only to hold device memory and to name the stream.  If the library
+is missing the binding raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpc_hip.so")
+
+MPC_OK, MPC_ERR_INVALID_ARG, MPC_ERR_OUT_OF_MEMORY, MPC_ERR_HIP = 0, 1, 2, 3
+MPC_ERR_UNSUPPORTED_SHAPE, MPC_ERR_BUSY, MPC_ERR_NOT_READY = 4, 5, 6
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+AGENT_OK, AGENT_CONVERGED, AGENT_NOT_PD, AGENT_NONFINITE = 0, 1, 2, 3
+
+
+class MPCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mpc error {code}: {msg}")
+        self.code = code
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("N", "nx", "nu", "n_tau", "n_feet", "foot_dim")]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n_agents", ctypes.c_int32), ("shapes", ctypes.POINTER(Shape)),
+                ("precision", ctypes.c_int32), ("admm_iters", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("sigma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("rho_eq_scale", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("max_refine_sweeps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("device", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+
+
+class ProblemBatch(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("A", "B", "c", "q_diag", "r_diag", "x_ref", "x0",
+                                               "tau_max", "mu", "stance", "u_ref")] + \
+               [("warm_start", ctypes.c_int32)]
+
+
+class Solution(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "x", "u", "z", "y", "objective",
+                                               "residuals", "status")]
+
+
+# every symbol the header declares
+EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_solve",
+           "mpc_get_solution", "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
+           "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_last_error", "mpc_version")
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP solver library not built: {LIB_PATH} "
+                               "(run `python -m paper_2510_12717_amd.build`)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, V, I32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32
+        L.mpc_plan_desc_default.argtypes = [P(PlanDesc)]
+        L.mpc_plan_desc_default.restype = None
+        L.mpc_plan_create.argtypes = [P(PlanDesc), P(V)]
+        L.mpc_plan_destroy.argtypes = [V]
+        L.mpc_solve.argtypes = [V, P(ProblemBatch), V]
+        L.mpc_get_solution.argtypes = [V, P(Solution), V]
+        L.mpc_set_warm_state.argtypes = [V, V, V, V, V]
+        L.mpc_advance_state.argtypes = [V, P(ProblemBatch), V, V, V]
+        L.mpc_plan_set_timing.argtypes = [V, I32]
+        L.mpc_plan_get_timing.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
+        L.mpc_plan_get_config.argtypes = [V, P(I32), P(I32), P(I32)]
+        for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
+                  "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
+                  "mpc_plan_get_timing", "mpc_plan_get_config"):
+            getattr(L, f).restype = ctypes.c_int
+        L.mpc_last_error.restype = ctypes.c_char_p
+        L.mpc_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != MPC_OK:
+        raise MPCError(code, lib().mpc_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def to_device(batch, dtype: str = "fp32", device: str = "cuda") -> Dict[str, "object"]:
+    """Copy a ``synth.Batch`` to device tensors in the plan's io type."""
+    import torch
+    td = torch.float64 if dtype == "fp64" else torch.float32
+    out = {}
+    for k in ("A", "B", "c", "q", "r", "x_ref", "x0", "tau_max", "mu"):
+        out[k] = torch.from_numpy(np.ascontiguousarray(getattr(batch, k))).to(device=device,
+                                                                               dtype=td)
+    out["stance"] = torch.from_numpy(np.ascontiguousarray(batch.stance, dtype=np.uint8)).to(device)
+    return out
+
+
+class Plan:
+    """A solver plan for a fixed batch of agent shapes (see ``mpc_plan_create``)."""
+
+    def __init__(self, shapes: Sequence, precision: str = "fp32", iters: int = 50,
+                 device: int = 0, kernel: str = "auto", **consts):
+        L = lib()
+        self.shapes = list(shapes)
+        self.precision = precision
+        arr = (Shape * len(self.shapes))(*[Shape(*s.as_tuple()) for s in self.shapes])
+        self._shapes_arr = arr
+        d = PlanDesc()
+        L.mpc_plan_desc_default(ctypes.byref(d))
+        d.n_agents = len(self.shapes)
+        d.shapes = ctypes.cast(arr, ctypes.POINTER(Shape))
+        d.precision = PRECISIONS[precision]
+        d.admm_iters = int(iters)
+        d.device = int(device)
+        d.kernel = {"auto": 0, "generic": 1, "fused": 2}[kernel]
+        for k, v in consts.items():
+            setattr(d, k, v)
+        h = ctypes.c_void_p()
+        _check(L.mpc_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.n = len(self.shapes)
+        self.dtype = "fp64" if precision == "fp64" else "fp32"
+        m = [s.nu + 4 * s.n_feet for s in self.shapes]
+        self.sizes = dict(x=sum((s.N + 1) * s.nx for s in self.shapes),
+                          u=sum(s.N * s.nu for s in self.shapes),
+                          z=sum(s.N * mm for s, mm in zip(self.shapes, m)),
+                          u0=sum(s.nu for s in self.shapes))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().mpc_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, prob, warm_start: bool) -> ProblemBatch:
+        b = ProblemBatch()
+        b.A, b.B, b.c = _ptr(prob["A"]), _ptr(prob["B"]), _ptr(prob["c"])
+        b.q_diag, b.r_diag = _ptr(prob["q"]), _ptr(prob["r"])
+        b.x_ref, b.x0 = _ptr(prob["x_ref"]), _ptr(prob["x0"])
+        b.tau_max, b.mu, b.stance = _ptr(prob["tau_max"]), _ptr(prob["mu"]), _ptr(prob["stance"])
+        b.u_ref = _ptr(prob.get("u_ref"))
+        b.warm_start = 1 if warm_start else 0
+        self._keep = prob  # inputs must outlive the stream's use of them
+        return b
+
+    def solve(self, prob, warm_start: bool = False, stream=None):
+        b = self._batch(prob, warm_start)
+        _check(lib().mpc_solve(self._h, ctypes.byref(b), _stream_handle(stream)))
+
+    def get_solution(self, stream=None, out=None) -> Dict[str, "object"]:
+        import torch
+        td = torch.float64 if self.dtype == "fp64" else torch.float32
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if out is None:
+            out = dict(u0=torch.empty(self.sizes["u0"], dtype=td, device=dev),
+                       x=torch.empty(self.sizes["x"], dtype=td, device=dev),
+                       u=torch.empty(self.sizes["u"], dtype=td, device=dev),
+                       z=torch.empty(self.sizes["z"], dtype=td, device=dev),
+                       y=torch.empty(self.sizes["z"], dtype=td, device=dev),
+                       objective=torch.empty(self.n, dtype=td, device=dev),
+                       residuals=torch.empty((self.n, 4), dtype=torch.float64, device=dev),
+                       status=torch.empty(self.n, dtype=torch.int32, device=dev))
+        s = Solution()
+        for k in ("u0", "x", "u", "z", "y", "objective", "residuals", "status"):
+            setattr(s, k, _ptr(out.get(k)))
+        _check(lib().mpc_get_solution(self._h, ctypes.byref(s), _stream_handle(stream)))
+        return out
+
+    def set_warm_state(self, u, z, y, stream=None):
+        _check(lib().mpc_set_warm_state(self._h, _ptr(u), _ptr(z), _ptr(y),
+                                        _stream_handle(stream)))
+
+    def advance_state(self, prob, noise, x0_next, stream=None):
+        b = self._batch(prob, False)
+        _check(lib().mpc_advance_state(self._h, ctypes.byref(b), _ptr(noise), _ptr(x0_next),
+                                       _stream_handle(stream)))
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().mpc_plan_set_timing(self._h, 1 if enable else 0))
+
+    def get_timing(self):
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        _check(lib().mpc_plan_get_timing(self._h, ms, n))
+        names = ("factor", "admm", "residual")
+        return {k: (ms[i], n[i]) for i, k in enumerate(names)}
+
+    def config(self):
+        k, t, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mpc_plan_get_config(self._h, ctypes.byref(k), ctypes.byref(t),
+                                         ctypes.byref(l)))
+        return dict(kernel={1: "generic", 2: "fused"}.get(k.value, str(k.value)),
+                    threads_per_agent=t.value, lds_bytes=l.value)

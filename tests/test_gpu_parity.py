@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (norm-wise relative error per agent, max over the checked agents):
+  FP64 plans: 1e-10 on u_0 and on the trajectory (x_1..N, u_0..N-1), and on z, y;
+  FP32 plans: 1e-5 on u_0 and on the trajectory.
+The FP32 bound is the stated target; a CPU emulation of the same arithmetic in
+float32 lands at 1e-6 .. 3e-6 on these problems.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2510_12717_amd import mpc, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    mpc.lib()
+
+
+def run_gpu(batch, precision, iters=50, kernel="auto", warm=None, x0=None):
+    plan = mpc.Plan(batch.shapes, precision=precision, iters=iters, kernel=kernel)
+    prob = mpc.to_device(batch, precision)
+    if x0 is not None:
+        prob["x0"] = torch.from_numpy(np.asarray(x0)).to(prob["x0"].dtype).cuda()
+    if warm is not None:
+        td = prob["A"].dtype
+        plan.set_warm_state(*(torch.from_numpy(np.asarray(warm[k])).to(td).cuda()
+                              for k in ("u", "z", "y")))
+    plan.solve(prob, warm_start=warm is not None)
+    sol = plan.get_solution()
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in sol.items()}
+    return out, plan, prob
+
+
+def agent_errors(batch, g, o, agents=None, go=None):
+    """Per-agent errors (u0, trajectory, z, y); ``go`` maps GPU agent index -> oracle index."""
+    off = batch.offsets()
+    errs = []
+    agents = range(batch.n_agents) if agents is None else agents
+    for j, a in enumerate(agents):
+        s = batch.shapes[a]
+        b = a if go is None else go[j]
+        ob = o["_off"] if "_off" in o else off
+        xg = g["x"][off["x"][a] + s.nx:off["x"][a + 1]]
+        ug = g["u"][off["u"][a]:off["u"][a + 1]]
+        xo = o["x"][ob["x"][b] + s.nx:ob["x"][b + 1]]
+        uo = o["u"][ob["u"][b]:ob["u"][b + 1]]
+        zg, yg = g["z"][off["z"][a]:off["z"][a + 1]], g["y"][off["z"][a]:off["z"][a + 1]]
+        zo, yo = o["z"][ob["z"][b]:ob["z"][b + 1]], o["y"][ob["z"][b]:ob["z"][b + 1]]
+        rel = lambda p, q: np.abs(p - q).max() / max(np.abs(q).max(), 1e-300)
+        errs.append((rel(ug[: s.nu], uo[: s.nu]),
+                     rel(np.concatenate([xg, ug]), np.concatenate([xo, uo])),
+                     rel(zg, zo), rel(yg, yo)))
+    return np.array(errs)
+
+
+def test_config0_fp64_every_agent():
+    b = synth.config0(64)
+    g, plan, _ = run_gpu(b, "fp64")
+    o = oracle.solve_batch(b, iters=50)
+    assert np.all(g["status"] == 0)
+    e = agent_errors(b, g, o)
+    print("fp64 max errors u0/traj/z/y:", e.max(axis=0))
+    assert e.max() < TOL["fp64"]
+    # u0 export equals the first stage of u
+    off = b.offsets()
+    np.testing.assert_array_equal(g["u0"].reshape(64, 30), g["u"].reshape(64, 10 * 30)[:, :30])
+    # GPU FP64 KKT residuals of its iterate agree with the oracle's of its own
+    np.testing.assert_allclose(g["residuals"][:, :2], o["res"][:, :2], rtol=1e-7, atol=1e-12)
+    assert np.all(g["residuals"][:, 2] < 1e-12)
+    np.testing.assert_allclose(g["objective"], o["objective"], rtol=1e-10)
+
+
+def test_config0_fp32_every_agent():
+    b = synth.config0(64)
+    g, plan, _ = run_gpu(b, "fp32")
+    o = oracle.solve_batch(b, iters=50)
+    assert np.all(g["status"] == 0)
+    e = agent_errors(b, g, o)
+    print("fp32 max errors u0/traj:", e[:, :2].max(axis=0))
+    assert e[:, :2].max() < TOL["fp32"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven_batch(precision):
+    b = synth.config2(96)
+    g, plan, _ = run_gpu(b, precision)
+    o = oracle.solve_batch(b, iters=50)
+    assert np.all(g["status"] == 0)
+    e = agent_errors(b, g, o)
+    assert e[:, :2].max() < TOL[precision]
+
+
+@pytest.mark.parametrize("shape", [
+    synth.Shape(N=1, nx=48, nu=30, n_tau=18, n_feet=2, foot_dim=6),
+    synth.Shape(N=3, nx=1, nu=3, n_tau=3, n_feet=0, foot_dim=3),
+    synth.Shape(N=20, nx=64, nu=32, n_tau=8, n_feet=4, foot_dim=6),
+    synth.Shape(N=7, nx=17, nu=13, n_tau=1, n_feet=4, foot_dim=3),
+])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_edge_shapes(shape, precision):
+    b = synth.make_batch([shape] * 5, seed=1, config_id=50)
+    g, plan, _ = run_gpu(b, precision, iters=30)
+    o = oracle.solve_batch(b, iters=30)
+    assert np.all(g["status"] == 0)
+    assert agent_errors(b, g, o)[:, :2].max() < TOL[precision]
+
+
+@pytest.mark.parametrize("pattern", ["all_stance", "all_swing"])
+def test_contact_extremes(pattern):
+    b = synth.config0(8)
+    b.stance[:] = 1 if pattern == "all_stance" else 0
+    g, _, _ = run_gpu(b, "fp64")
+    o = oracle.solve_batch(b, iters=50)
+    assert agent_errors(b, g, o).max() < TOL["fp64"]
+
+
+def test_failures_stay_local():
+    b = synth.config0(6)
+    o_ = b.offsets()
+    b.A[o_["A"][2] + 17] = np.nan
+    b.r[o_["r"][4]:o_["r"][5]] = -5.0
+    for precision in ("fp64", "fp32"):
+        g, _, _ = run_gpu(b, precision)
+        o = oracle.solve_batch(b, iters=50)
+        assert g["status"].tolist() == o["status"].tolist() == [0, 0, 3, 0, 2, 0]
+        e = agent_errors(b, g, o, agents=[0, 1, 3, 5])
+        assert e[:, :2].max() < TOL[precision]
+        assert np.all(np.isnan(g["u"][o_["u"][2]:o_["u"][3]]))
+        assert np.all(np.isnan(g["residuals"][[2, 4]]))
+
+
+def test_batch_invariance():
+    """An agent's result does not depend on which agents share the launch."""
+    full = synth.config0(32)
+    sub = full.subset([3, 17, 30])
+    gf, _, _ = run_gpu(full, "fp32")
+    gs, _, _ = run_gpu(sub, "fp32")
+    of, os_ = full.offsets(), sub.offsets()
+    for j, a in enumerate([3, 17, 30]):
+        np.testing.assert_array_equal(gf["u"][of["u"][a]:of["u"][a + 1]],
+                                      gs["u"][os_["u"][j]:os_["u"][j + 1]])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_closed_loop_warm_start(precision):
+    """Config-1 shape: repeated warm-started solves with x0 advanced by the
+    agent's own dynamics plus noise; the x0 sequence comes from the oracle's
+    closed loop, both sides warm-start from their own previous solution."""
+    b = synth.config1(128)
+    plan = mpc.Plan(b.shapes, precision=precision, iters=50)
+    prob = mpc.to_device(b, precision)
+    x0 = b.x0.copy()
+    state = None
+    worst = 0.0
+    for step in range(6):
+        o = oracle.solve_batch(b, iters=50, warm=state, x0=x0)
+        prob["x0"] = torch.from_numpy(x0).to(prob["A"].dtype).cuda()
+        plan.solve(prob, warm_start=step > 0)
+        g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+        e = agent_errors(b, g, o)
+        worst = max(worst, e[:, :2].max())
+        assert np.all(g["status"] == 0)
+        # the plan's own plant step agrees with the oracle's
+        noise = synth.step_noise(b, step)
+        nxt = torch.empty_like(prob["x0"])
+        plan.advance_state(prob, torch.from_numpy(noise).to(prob["A"].dtype).cuda(), nxt)
+        x0_next = oracle.advance_batch(b, x0, o["u"], noise)
+        g_next = oracle.advance_batch(b, x0, g["u"], noise)
+        np.testing.assert_allclose(nxt.cpu().numpy(), g_next, rtol=1e-5 if precision == "fp32" else 1e-12,
+                                   atol=1e-6 if precision == "fp32" else 1e-13)
+        state = {k: o[k] for k in ("u", "z", "y")}
+        x0 = x0_next
+    print(precision, "closed-loop worst error:", worst)
+    assert worst < TOL[precision]
+
+
+def test_warm_state_import():
+    b = synth.config0(16)
+    o1 = oracle.solve_batch(b, iters=20)
+    o2 = oracle.solve_batch(b, iters=20, warm={k: o1[k] for k in ("u", "z", "y")})
+    g, _, _ = run_gpu(b, "fp64", iters=20, warm={k: o1[k] for k in ("u", "z", "y")})
+    assert agent_errors(b, g, o2).max() < TOL["fp64"]
+
+
+def test_timing_and_config():
+    b = synth.config0(16)
+    plan = mpc.Plan(b.shapes, precision="fp32")
+    prob = mpc.to_device(b, "fp32")
+    plan.set_timing(True)
+    for _ in range(3):
+        plan.solve(prob)
+    t = plan.get_timing()
+    assert t["admm"][1] == 3 and t["admm"][0] > 0
+    assert plan.config()["kernel"] in ("generic", "fused")
+
+
+def test_api_errors_on_device():
+    b = synth.config0(4)
+    plan = mpc.Plan(b.shapes, precision="fp32")
+    with pytest.raises(mpc.MPCError) as ei:
+        plan.get_solution()
+    assert ei.value.code == mpc.MPC_ERR_NOT_READY
+    prob = mpc.to_device(b, "fp32")
+    with pytest.raises(mpc.MPCError) as ei:
+        plan.solve(prob, warm_start=True)
+    assert ei.value.code == mpc.MPC_ERR_INVALID_ARG

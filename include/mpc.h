@@ -68,7 +68,9 @@ typedef enum {
 
 typedef enum {
   MPC_FP64 = 0,        /* everything in double                                    */
-  MPC_FP32 = 1,        /* everything in float (Cholesky included)                 */
+  MPC_FP32 = 1,        /* float io, operators and ADMM iterations; the Riccati    */
+                       /* factor runs in double and is rounded to float once, and */
+                       /* H_k^{-1} h accumulates in double                        */
   MPC_BF16_REFINE = 2, /* bf16 block products, fp64 stage Cholesky, refinement    */
   MPC_FP16_REFINE = 3  /* fp16 block products, fp64 stage Cholesky, refinement    */
 } mpc_precision;
@@ -159,6 +161,14 @@ mpc_status mpc_plan_get_timing(mpc_plan_t plan, double* ms, int64_t* launches);
 /* Which kernel family the plan runs (1 generic, 2 fused) and its launch shape. */
 mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* threads_per_agent,
                                int32_t* lds_bytes);
+
+/* Copy agent `agent`'s Riccati factor of the last solve into caller device
+ * buffers (io type): K [N][nu][nx], A_cl [N][nx][nx] (= A_k + B_k K_k),
+ * Hinv [N][nu][nu] (= H_k^{-1}), s [N][nx] (= P_{k+1} c_k); any may be NULL.
+ * Only plans running the generic kernels keep the factor in device memory
+ * (UNSUPPORTED_SHAPE otherwise).  For tests and diagnostics. */
+mpc_status mpc_plan_export_factor(mpc_plan_t plan, int32_t agent, void* K, void* A_cl, void* Hinv,
+                                  void* s, void* stream);
 
 /* Thread-local description of the last error returned on this thread. */
 const char* mpc_last_error(void);

@@ -40,15 +40,21 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* P = reinterpret_cast<T*>(smem_raw);  // P_{k+1}, then P_k       nx*nx
-  T* Ak = P + nx * nx;                    // A_k                     nx*nx
-  T* PA = Ak + nx * nx;                   // P_{k+1} A_k             nx*nx
-  T* Bk = PA + nx * nx;                   // B_k                     nx*nu
-  T* PB = Bk + nx * nu;                   // P_{k+1} B_k, then K_k   nx*nu
-  T* Kk = PB;
-  T* G = PB + nx * nu;                    // B_k' P A_k              nu*nx
-  T* H = G + nu * nx;                     // H_k -> L_k              nu*nu
-  T* rdg = H + nu * nu;                   // diag Rt_k               nu
+  // The Riccati recursion runs in double for every io type T: inputs are
+  // widened on load and the operators are rounded to T once when stored.
+  // (Rounding P_k to float at every stage perturbs the operators by ~1e-6
+  // relative, which 50 ADMM iterations amplify well past 1e-5.)
+  using D = double;
+  D* H = reinterpret_cast<D*>(smem_raw);   // H_k -> L_k               nu*nu
+  D* P = H + nu * nu;                      // P_{k+1}, then P_k        nx*nx
+  D* Ak = P + nx * nx;                     // A_k                      nx*nx
+  D* PA = Ak + nx * nx;                    // P_{k+1} A_k              nx*nx
+  D* Bk = PA + nx * nx;                    // B_k                      nx*nu
+  D* PB = Bk + nx * nu;                    // P_{k+1} B_k, then K_k    nx*nu
+  D* Kk = PB;
+  D* G = PB + nx * nu;                     // B_k' P A_k               nu*nx
+  D* rdg = G + nu * nx;                    // diag Rt_k                nu
+  D* rhok = rdg + nu;                      // row penalties of stage k m
   __shared__ int s_flag;
 
   const T* A = in.A + d.oA;
@@ -86,51 +92,56 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
   for (int idx = tid; idx < N * m; idx += nt) {
     const int k = idx / m, i = idx % m;
     T lo, hi, rr;
-    row_bounds<T>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rr);
+    row_bounds<T, T>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rr);
     wl[idx] = lo;
     wh[idx] = hi;
     wrho[idx] = rr;
   }
   for (int idx = tid; idx < nx * nx; idx += nt) {
     const int i = idx / nx, j = idx % nx;
-    P[idx] = (i == j) ? q[i] + (T)sc.sigma : (T)0;
+    P[idx] = (i == j) ? (D)q[i] + sc.sigma : 0.0;
   }
   __syncthreads();
 
   for (int k = N - 1; k >= 0; --k) {
     const T* Ag = A + (int64_t)k * nx * nx;
     const T* Bg = B + (int64_t)k * nx * nu;
-    for (int idx = tid; idx < nx * nx; idx += nt) Ak[idx] = Ag[idx];
-    for (int idx = tid; idx < nx * nu; idx += nt) Bk[idx] = Bg[idx];
-    for (int j = tid; j < nu; j += nt) rdg[j] = rtilde_diag<T>(d, j, r[j], mu, wrho + (int64_t)k * m, sc);
+    for (int idx = tid; idx < nx * nx; idx += nt) Ak[idx] = (D)Ag[idx];
+    for (int idx = tid; idx < nx * nu; idx += nt) Bk[idx] = (D)Bg[idx];
+    for (int i = tid; i < m; i += nt) {
+      D lo, hi;
+      row_bounds<D, T>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rhok[i]);
+    }
+    __syncthreads();
+    for (int j = tid; j < nu; j += nt) rdg[j] = rtilde_diag<D, D>(d, j, (D)r[j], (D)mu, rhok, sc);
     __syncthreads();
     for (int idx = tid; idx < nx * nu; idx += nt) {
       const int i = idx / nu, j = idx % nu;
-      T acc = 0;
+      D acc = 0;
       for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Bk[t * nu + j];
       PB[idx] = acc;
     }
     for (int idx = tid; idx < nx * nx; idx += nt) {
       const int i = idx / nx, j = idx % nx;
-      T acc = 0;
+      D acc = 0;
       for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Ak[t * nx + j];
       PA[idx] = acc;
     }
     for (int i = tid; i < nx; i += nt) {
-      T acc = 0;
-      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * c[(int64_t)k * nx + t];
-      wS[(int64_t)k * nx + i] = acc;
+      D acc = 0;
+      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * (D)c[(int64_t)k * nx + t];
+      wS[(int64_t)k * nx + i] = (T)acc;
     }
     __syncthreads();
     for (int idx = tid; idx < nu * nu; idx += nt) {
       const int i = idx / nu, j = idx % nu;
-      T acc = (i == j) ? rdg[i] : (T)0;
+      D acc = (i == j) ? rdg[i] : 0.0;
       for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PB[t * nu + j];
       H[idx] = acc;
     }
     for (int idx = tid; idx < nu * nx; idx += nt) {
       const int i = idx / nx, j = idx % nx;
-      T acc = 0;
+      D acc = 0;
       for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PA[t * nx + j];
       G[idx] = acc;
     }
@@ -138,8 +149,8 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
     // Right-looking Cholesky of H_k in place (lower triangle).
     for (int j = 0; j < nu; ++j) {
       if (tid == 0) {
-        const T v = H[j * nu + j];
-        if (!(v > (T)0)) s_flag = 1;
+        const double v = H[j * nu + j];
+        if (!(v > 0.0)) s_flag = 1;
         H[j * nu + j] = sqrt(v);
       }
       __syncthreads();
@@ -159,20 +170,41 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
     }
     // K_k = -H_k^{-1} G_k into LDS (over the dead P B_k) and H_k^{-1} straight
     // into the workspace, one column per thread.
+    // The column is carried in double registers (nu <= 32, loops unrolled so
+    // the array stays in VGPRs) and rounded to T once at the end.
     for (int col = tid; col < nx + nu; col += nt) {
       const bool isK = col < nx;
       const int cc = isK ? col : col - nx;
-      T* dst = isK ? Kk : wHi + (int64_t)k * nu * nu;
       const int ld = isK ? nx : nu;
-      for (int i = 0; i < nu; ++i) {
-        T acc = isK ? -G[i * nx + cc] : (T)(i == cc ? 1 : 0);
-        for (int t = 0; t < i; ++t) acc -= H[i * nu + t] * dst[t * ld + cc];
-        dst[i * ld + cc] = acc / H[i * nu + i];
+      double v[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        if (i < nu) {
+          double acc = isK ? -G[i * nx + cc] : (i == cc ? 1.0 : 0.0);
+#pragma unroll
+          for (int t = 0; t < i; ++t) acc -= H[i * nu + t] * v[t];
+          v[i] = acc / H[i * nu + i];
+        }
       }
-      for (int i = nu - 1; i >= 0; --i) {
-        T acc = dst[i * ld + cc];
-        for (int t = i + 1; t < nu; ++t) acc -= H[t * nu + i] * dst[t * ld + cc];
-        dst[i * ld + cc] = acc / H[i * nu + i];
+#pragma unroll
+      for (int i = 31; i >= 0; --i) {
+        if (i < nu) {
+          double acc = v[i];
+#pragma unroll
+          for (int t = i + 1; t < 32; ++t)
+            if (t < nu) acc -= H[t * nu + i] * v[t];
+          v[i] = acc / H[i * nu + i];
+        }
+      }
+      if (isK) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (i < nu) Kk[i * ld + cc] = v[i];
+      } else {
+        T* dst = wHi + (int64_t)k * nu * nu;
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (i < nu) dst[i * ld + cc] = (T)v[i];
       }
     }
     __syncthreads();
@@ -181,7 +213,7 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
     for (int idx = tid; idx < nx * nx; idx += nt) {
       const int i = idx / nx, j = idx % nx;
       if (j >= i) {
-        T a1 = (i == j) ? q[i] + (T)sc.sigma : (T)0, a2 = a1;
+        D a1 = (i == j) ? (D)q[i] + sc.sigma : 0.0, a2 = a1;
         for (int t = 0; t < nx; ++t) {
           a1 += Ak[t * nx + i] * PA[t * nx + j];
           a2 += Ak[t * nx + j] * PA[t * nx + i];
@@ -190,15 +222,15 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
           a1 += G[t * nx + i] * Kk[t * nx + j];
           a2 += G[t * nx + j] * Kk[t * nx + i];
         }
-        const T v = (T)0.5 * (a1 + a2);
+        const D v = 0.5 * (a1 + a2);
         P[i * nx + j] = v;
         P[j * nx + i] = v;
       }
-      T acl = Ak[idx];
+      D acl = Ak[idx];
       for (int t = 0; t < nu; ++t) acl += Bk[i * nu + t] * Kk[t * nx + j];
-      wAcl[(int64_t)k * nx * nx + idx] = acl;
+      wAcl[(int64_t)k * nx * nx + idx] = (T)acl;
     }
-    for (int idx = tid; idx < nu * nx; idx += nt) wK[(int64_t)k * nu * nx + idx] = Kk[idx];
+    for (int idx = tid; idx < nu * nx; idx += nt) wK[(int64_t)k * nu * nx + idx] = (T)Kk[idx];
     __syncthreads();
   }
   if (tid == 0) status[a] = AGENT_OK;
@@ -227,20 +259,26 @@ k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverCon
     }
     return;
   }
+  // Operators are read in the io type T; every vector, every accumulation and
+  // the relaxation / projection / dual update run in double (on this chip the
+  // FP64 VALU rate equals the non-packed FP32 rate).  Each product sum is
+  // formed first and its offset added last, because offset and sum nearly
+  // cancel (e.g. h = rt + B' p').
+  using V = double;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* x = reinterpret_cast<T*>(smem_raw);  // (N+1)*nx
-  T* xt = x + (N + 1) * nx;               // (N+1)*nx
-  T* u = xt + (N + 1) * nx;               // N*nu
-  T* ut = u + N * nu;                     // N*nu
-  T* rt = ut + N * nu;                    // N*nu
-  T* dv = rt + N * nu;                    // N*nu
-  T* z = dv + N * nu;                     // N*m
-  T* y = z + N * m;                       // N*m
-  T* g = y + N * m;                       // N*nx
-  T* pp = g + N * nx;                     // N*nx
-  T* e = pp + N * nx;                     // N*nx
-  T* p = e + N * nx;                      // nx
-  T* hv = p + nx;                         // N*nu
+  V* x = reinterpret_cast<V*>(smem_raw);  // (N+1)*nx
+  V* xt = x + (N + 1) * nx;               // (N+1)*nx
+  V* u = xt + (N + 1) * nx;               // N*nu
+  V* ut = u + N * nu;                     // N*nu
+  V* rt = ut + N * nu;                    // N*nu
+  V* dv = rt + N * nu;                    // N*nu
+  V* z = dv + N * nu;                     // N*m
+  V* y = z + N * m;                       // N*m
+  V* g = y + N * m;                       // N*nx
+  V* pp = g + N * nx;                     // N*nx
+  V* e = pp + N * nx;                     // N*nx
+  V* p = e + N * nx;                      // nx
+  V* hv = p + nx;                         // N*nu
 
   const T* A = in.A + d.oA;
   const T* B = in.B + d.oB;
@@ -249,36 +287,35 @@ k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverCon
   const T* r = in.r + d.orr;
   const T* xr = in.xr + d.oxr;
   const T* x0 = in.x0 + d.ox0;
+  const T* tau = in.tau + d.otau;
+  const uint8_t* stance = in.st + d.ost;
   const T* uref = in.uref ? in.uref + d.ou : nullptr;
-  const T mu = in.mu[a];
+  const V mu = (V)in.mu[a];
   const T* wK = ws + d.ows;
   const T* wAcl = wK + (int64_t)N * nu * nx;
   const T* wHi = wAcl + (int64_t)N * nx * nx;
   const T* wS = wHi + (int64_t)N * nu * nu;
-  const T* wl = wS + (int64_t)N * nx;
-  const T* wh = wl + (int64_t)N * m;
-  const T* wrho = wh + (int64_t)N * m;
-  const T sigma = (T)sc.sigma, alpha = (T)sc.alpha, oma = (T)1 - (T)sc.alpha;
+  const V sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
 
-  for (int i = tid; i < N * nu; i += nt) u[i] = warm ? U[i] : (T)0;
+  for (int i = tid; i < N * nu; i += nt) u[i] = warm ? (V)U[i] : 0.0;
   for (int i = tid; i < N * m; i += nt) {
-    z[i] = warm ? Z[i] : (T)0;
-    y[i] = warm ? Y[i] : (T)0;
+    z[i] = warm ? (V)Z[i] : 0.0;
+    y[i] = warm ? (V)Y[i] : 0.0;
   }
   for (int i = tid; i < nx; i += nt) {
-    x[i] = x0[i];
-    xt[i] = x0[i];
+    x[i] = (V)x0[i];
+    xt[i] = (V)x0[i];
   }
   __syncthreads();
   // x^0: rollout of the dynamics under u^0.
   for (int k = 0; k < N; ++k) {
     for (int i = tid; i < nx; i += nt) {
-      T acc = c[(int64_t)k * nx + i];
+      V acc = 0;
       const T* Ar = A + (int64_t)k * nx * nx + i * nx;
       const T* Br = B + (int64_t)k * nx * nu + i * nu;
-      for (int t = 0; t < nx; ++t) acc += Ar[t] * x[k * nx + t];
-      for (int t = 0; t < nu; ++t) acc += Br[t] * u[k * nu + t];
-      x[(k + 1) * nx + i] = acc;
+      for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * x[k * nx + t];
+      for (int t = 0; t < nu; ++t) acc += (V)Br[t] * u[k * nu + t];
+      x[(k + 1) * nx + i] = (V)c[(int64_t)k * nx + i] + acc;
     }
     __syncthreads();
   }
@@ -287,12 +324,15 @@ k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverCon
     // rt_k = -sigma u_k - R ubar_k + C_k'(y_k - rho_k z_k)
     for (int idx = tid; idx < N * nu; idx += nt) {
       const int k = idx / nu, j = idx % nu;
-      // w = y - rho z for this stage, read through ct_row on a stage-local view
-      const T* yk = y + k * m;
-      const T* zk = z + k * m;
-      const T* rk = wrho + (int64_t)k * m;
-      auto w = [&](int i) { return yk[i] - rk[i] * zk[i]; };
-      T v = w(j);
+      const V* yk = y + k * m;
+      const V* zk = z + k * m;
+      const uint8_t* stk = stance + k * d.n_feet;
+      auto w = [&](int i) {
+        V lo, hi, rr;
+        row_bounds<V, T>(d, i, stk, tau, sc, lo, hi, rr);
+        return yk[i] - rr * zk[i];
+      };
+      V v = w(j);
       if (j >= d.n_tau) {
         const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
         const int b0 = nu + 4 * f;
@@ -300,31 +340,32 @@ k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverCon
         if (cc == 1) v += w(b0 + 2) - w(b0 + 3);
         if (cc == 2) v -= mu * (w(b0) + w(b0 + 1) + w(b0 + 2) + w(b0 + 3));
       }
-      T acc = -sigma * u[idx] + v;
-      if (uref) acc -= r[j] * uref[idx];
+      V acc = -sigma * u[idx] + v;
+      if (uref) acc -= (V)r[j] * (V)uref[idx];
       rt[idx] = acc;
     }
     __syncthreads();
     // g_k = qt_k + K_k' rt_k, qt_k = -Q r_k - sigma x_k
     for (int idx = tid; idx < N * nx; idx += nt) {
       const int k = idx / nx, i = idx % nx;
-      T acc = -q[i] * xr[(int64_t)k * nx + i] - sigma * x[idx];
+      V acc = 0;
       const T* Kc = wK + (int64_t)k * nu * nx + i;
-      for (int j = 0; j < nu; ++j) acc += Kc[j * nx] * rt[k * nu + j];
-      g[idx] = acc;
+      for (int j = 0; j < nu; ++j) acc += (V)Kc[j * nx] * rt[k * nu + j];
+      g[idx] = (-(V)q[i] * (V)xr[(int64_t)k * nx + i] - sigma * x[idx]) + acc;
     }
-    for (int i = tid; i < nx; i += nt) p[i] = -q[i] * xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
+    for (int i = tid; i < nx; i += nt)
+      p[i] = -(V)q[i] * (V)xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
     __syncthreads();
     // backward chain: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
     for (int k = N - 1; k >= 0; --k) {
-      for (int i = tid; i < nx; i += nt) pp[k * nx + i] = p[i] + wS[(int64_t)k * nx + i];
+      for (int i = tid; i < nx; i += nt) pp[k * nx + i] = p[i] + (V)wS[(int64_t)k * nx + i];
       __syncthreads();
       if (k > 0) {
         for (int i = tid; i < nx; i += nt) {
-          T acc = g[k * nx + i];
+          V acc = 0;
           const T* Ac = wAcl + (int64_t)k * nx * nx + i;
-          for (int t = 0; t < nx; ++t) acc += Ac[t * nx] * pp[k * nx + t];
-          p[i] = acc;
+          for (int t = 0; t < nx; ++t) acc += (V)Ac[t * nx] * pp[k * nx + t];
+          p[i] = g[k * nx + i] + acc;
         }
         __syncthreads();
       }
@@ -332,55 +373,56 @@ k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverCon
     // d_k = -H_k^{-1}(rt_k + B_k' p'_k),  e_k = B_k d_k + c_k
     for (int idx = tid; idx < N * nu; idx += nt) {
       const int k = idx / nu, j = idx % nu;
-      T acc = rt[idx];
+      V acc = 0;
       const T* Bc = B + (int64_t)k * nx * nu + j;
-      for (int t = 0; t < nx; ++t) acc += Bc[t * nu] * pp[k * nx + t];
-      hv[idx] = acc;
+      for (int t = 0; t < nx; ++t) acc += (V)Bc[t * nu] * pp[k * nx + t];
+      hv[idx] = rt[idx] + acc;
     }
     __syncthreads();
     for (int idx = tid; idx < N * nu; idx += nt) {
       const int k = idx / nu, j = idx % nu;
-      T acc = 0;
+      V acc = 0;
       const T* Hr = wHi + (int64_t)k * nu * nu + j * nu;
-      for (int t = 0; t < nu; ++t) acc += Hr[t] * hv[k * nu + t];
+      for (int t = 0; t < nu; ++t) acc += (V)Hr[t] * hv[k * nu + t];
       dv[idx] = -acc;
     }
     __syncthreads();
     for (int idx = tid; idx < N * nx; idx += nt) {
       const int k = idx / nx, i = idx % nx;
-      T acc = c[(int64_t)k * nx + i];
+      V acc = 0;
       const T* Br = B + (int64_t)k * nx * nu + i * nu;
-      for (int t = 0; t < nu; ++t) acc += Br[t] * dv[k * nu + t];
-      e[idx] = acc;
+      for (int t = 0; t < nu; ++t) acc += (V)Br[t] * dv[k * nu + t];
+      e[idx] = (V)c[(int64_t)k * nx + i] + acc;
     }
     __syncthreads();
     // forward chain: xt_{k+1} = A_cl,k xt_k + e_k
     for (int k = 0; k < N; ++k) {
       for (int i = tid; i < nx; i += nt) {
-        T acc = e[k * nx + i];
+        V acc = 0;
         const T* Ar = wAcl + (int64_t)k * nx * nx + i * nx;
-        for (int t = 0; t < nx; ++t) acc += Ar[t] * xt[k * nx + t];
-        xt[(k + 1) * nx + i] = acc;
+        for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * xt[k * nx + t];
+        xt[(k + 1) * nx + i] = e[k * nx + i] + acc;
       }
       __syncthreads();
     }
     // ut_k = K_k xt_k + d_k
     for (int idx = tid; idx < N * nu; idx += nt) {
       const int k = idx / nu, j = idx % nu;
-      T acc = dv[idx];
+      V acc = 0;
       const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
-      for (int t = 0; t < nx; ++t) acc += Kr[t] * xt[k * nx + t];
-      ut[idx] = acc;
+      for (int t = 0; t < nx; ++t) acc += (V)Kr[t] * xt[k * nx + t];
+      ut[idx] = dv[idx] + acc;
     }
     __syncthreads();
     // relaxation, projection onto [l, h], dual update
     for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) x[idx] = alpha * xt[idx] + oma * x[idx];
     for (int idx = tid; idx < N * m; idx += nt) {
       const int k = idx / m, i = idx % m;
-      const T zeta = c_row<T>(d, i, mu, ut + k * nu);
-      const T w = alpha * zeta + oma * z[idx];
-      const T rr = wrho[(int64_t)k * m + i];
-      const T zn = fmin(fmax(w + y[idx] / rr, wl[(int64_t)k * m + i]), wh[(int64_t)k * m + i]);
+      V lo, hi, rr;
+      row_bounds<V, T>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rr);
+      const V zeta = c_row<V>(d, i, mu, ut + k * nu);
+      const V w = alpha * zeta + oma * z[idx];
+      const V zn = fmin(fmax(w + y[idx] / rr, lo), hi);
       y[idx] = y[idx] + rr * (w - zn);
       z[idx] = zn;
     }
@@ -391,17 +433,17 @@ k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverCon
 
   bool ok = true;
   for (int i = tid; i < (N + 1) * nx; i += nt) {
-    X[i] = x[i];
-    ok &= (bool)isfinite(x[i]);
+    X[i] = (T)x[i];
+    ok &= (bool)isfinite(X[i]);
   }
   for (int i = tid; i < N * nu; i += nt) {
-    U[i] = u[i];
-    ok &= (bool)isfinite(u[i]);
+    U[i] = (T)u[i];
+    ok &= (bool)isfinite(U[i]);
   }
   for (int i = tid; i < N * m; i += nt) {
-    Z[i] = z[i];
-    Y[i] = y[i];
-    ok &= (bool)isfinite(z[i]) && (bool)isfinite(y[i]);
+    Z[i] = (T)z[i];
+    Y[i] = (T)y[i];
+    ok &= (bool)isfinite(Z[i]) && (bool)isfinite(Y[i]);
   }
   if (!ok) st.status[a] = AGENT_NONFINITE;
 }
@@ -530,7 +572,7 @@ k_residual(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, Solve
     }
     rp = fmax(rp, fabs(cu - (double)z[idx]));
     T lo_t, hi_t, rho_t;
-    row_bounds<T>(d, i, stance + k * d.n_feet, tau, sc, lo_t, hi_t, rho_t);
+    row_bounds<T, T>(d, i, stance + k * d.n_feet, tau, sc, lo_t, hi_t, rho_t);
     const double lo = (double)lo_t, hi = (double)hi_t, zz = (double)z[idx], yy = (double)y[idx];
     const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
     const double ca = isinf(hi) ? yp : fmin(yp, hi - zz);

@@ -44,10 +44,12 @@ inline int64_t generic_ws_elems(int N, int nx, int nu, int m) {
 }
 
 inline size_t generic_factor_lds(int nx, int nu, size_t esz) {
-  return esz * (size_t)(3 * nx * nx + 3 * nx * nu + nu * nu + nu);
+  (void)esz;  // the recursion runs in double whatever the io type
+  return 8 * (size_t)(nu * nu + 3 * nx * nx + 3 * nx * nu + nu + 64);
 }
 inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz) {
-  return esz * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu);
+  (void)esz;  // vectors are held in double whatever the io type
+  return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu);
 }
 
 // Raise the dynamic-LDS limit of the generic kernels to what a plan needs.

@@ -260,12 +260,16 @@ extern "C" mpc_status mpc_plan_destroy(mpc_plan_t p) {
 
 static mpc_status check_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
   if (!b) return fail(MPC_ERR_INVALID_ARG, "null batch");
-  if (!b->A || !b->B || !b->c || !b->q_diag || !b->r_diag || !b->x_ref || !b->x0 || !b->mu ||
-      !b->stance)
+  if (!b->A || !b->B || !b->c || !b->q_diag || !b->r_diag || !b->x_ref || !b->x0 || !b->mu)
     return fail(MPC_ERR_INVALID_ARG, "null input pointer in batch");
-  bool any_tau = false;
-  for (const auto& s : p->shapes) any_tau |= s.n_tau > 0;
+  // tau_max and stance may be NULL only when no agent has torques / feet
+  bool any_tau = false, any_feet = false;
+  for (const auto& s : p->shapes) {
+    any_tau |= s.n_tau > 0;
+    any_feet |= s.n_feet > 0;
+  }
   if (any_tau && !b->tau_max) return fail(MPC_ERR_INVALID_ARG, "null tau_max");
+  if (any_feet && !b->stance) return fail(MPC_ERR_INVALID_ARG, "null stance");
   if (b->warm_start != 0 && b->warm_start != 1) return fail(MPC_ERR_INVALID_ARG, "warm_start must be 0 or 1");
   if (b->warm_start && !p->solved)
     return fail(MPC_ERR_INVALID_ARG, "warm_start requested before any solve or warm state");
@@ -478,5 +482,25 @@ extern "C" mpc_status mpc_plan_get_config(mpc_plan_t p, int32_t* kernel, int32_t
   if (kernel) *kernel = p->kernel;
   if (threads) *threads = p->kernel == 2 ? p->fused_threads : 256;
   if (lds) *lds = (int32_t)(p->kernel == 2 ? p->fused_lds : std::max(p->lds_factor, p->lds_admm));
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_export_factor(mpc_plan_t p, int32_t agent, void* K, void* Acl,
+                                             void* Hinv, void* sv, void* stream) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  if (agent < 0 || agent >= p->n) return fail(MPC_ERR_INVALID_ARG, "agent index out of range");
+  if (p->kernel != 1) return fail(MPC_ERR_UNSUPPORTED_SHAPE, "the fused kernel keeps its factor on chip");
+  if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  const AgentDesc& d = p->hdesc[agent];
+  const size_t e = p->esz;
+  const char* base = (const char*)p->d_ws + (size_t)d.ows * e;
+  const size_t nK = (size_t)d.N * d.nu * d.nx, nA = (size_t)d.N * d.nx * d.nx,
+               nH = (size_t)d.N * d.nu * d.nu, nS = (size_t)d.N * d.nx;
+  if (K) HIP_TRY(hipMemcpyAsync(K, base, nK * e, hipMemcpyDeviceToDevice, s));
+  if (Acl) HIP_TRY(hipMemcpyAsync(Acl, base + nK * e, nA * e, hipMemcpyDeviceToDevice, s));
+  if (Hinv) HIP_TRY(hipMemcpyAsync(Hinv, base + (nK + nA) * e, nH * e, hipMemcpyDeviceToDevice, s));
+  if (sv) HIP_TRY(hipMemcpyAsync(sv, base + (nK + nA + nH) * e, nS * e, hipMemcpyDeviceToDevice, s));
   return MPC_OK;
 }

@@ -27,13 +27,13 @@ __device__ inline T pos_inf() {
 }
 
 // Bounds and penalty of row i at a stage with stance flags st (n_feet bytes).
-template <typename T>
-__device__ inline void row_bounds(const AgentDesc& d, int i, const uint8_t* st, const T* tau,
+template <typename T, typename TT>
+__device__ inline void row_bounds(const AgentDesc& d, int i, const uint8_t* st, const TT* tau,
                                   const SolverConsts& sc, T& lo, T& hi, T& rho) {
   const T inf = pos_inf<T>();
   if (i < d.n_tau) {
-    lo = -tau[i];
-    hi = tau[i];
+    lo = -(T)tau[i];
+    hi = (T)tau[i];
   } else if (i < d.nu) {
     const int f = (i - d.n_tau) / d.foot_dim, j = (i - d.n_tau) % d.foot_dim;
     if (st[f]) {
@@ -57,16 +57,16 @@ __device__ inline void row_bounds(const AgentDesc& d, int i, const uint8_t* st, 
 }
 
 // Diagonal of R + sigma I + C' diag(rho) C for input j (rho = this stage's row penalties).
-template <typename T>
-__device__ inline T rtilde_diag(const AgentDesc& d, int j, T rj, T mu, const T* rho,
+template <typename T, typename R>
+__device__ inline T rtilde_diag(const AgentDesc& d, int j, T rj, T mu, const R* rho,
                                 const SolverConsts& sc) {
-  T v = rj + (T)sc.sigma + rho[j];
+  T v = rj + (T)sc.sigma + (T)rho[j];
   if (j >= d.n_tau) {
     const int f = (j - d.n_tau) / d.foot_dim, c = (j - d.n_tau) % d.foot_dim;
-    const T* rp = rho + d.nu + 4 * f;
-    if (c == 0) v += rp[0] + rp[1];
-    if (c == 1) v += rp[2] + rp[3];
-    if (c == 2) v += mu * mu * (rp[0] + rp[1] + rp[2] + rp[3]);
+    const R* rp = rho + d.nu + 4 * f;
+    if (c == 0) v += (T)rp[0] + (T)rp[1];
+    if (c == 1) v += (T)rp[2] + (T)rp[3];
+    if (c == 2) v += mu * mu * ((T)rp[0] + (T)rp[1] + (T)rp[2] + (T)rp[3]);
   }
   return v;
 }

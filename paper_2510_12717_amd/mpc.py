@@ -54,7 +54,8 @@ class Solution(ctypes.Structure):
 # every symbol the header declares
 EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_solve",
            "mpc_get_solution", "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
-           "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_last_error", "mpc_version")
+           "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
+           "mpc_last_error", "mpc_version")
 
 _lib = None
 
@@ -79,9 +80,10 @@ def lib():
         L.mpc_plan_set_timing.argtypes = [V, I32]
         L.mpc_plan_get_timing.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
         L.mpc_plan_get_config.argtypes = [V, P(I32), P(I32), P(I32)]
+        L.mpc_plan_export_factor.argtypes = [V, I32, V, V, V, V, V]
         for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
                   "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
-                  "mpc_plan_get_timing", "mpc_plan_get_config"):
+                  "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor"):
             getattr(L, f).restype = ctypes.c_int
         L.mpc_last_error.restype = ctypes.c_char_p
         L.mpc_version.restype = ctypes.c_char_p
@@ -220,3 +222,17 @@ class Plan:
                                          ctypes.byref(l)))
         return dict(kernel={1: "generic", 2: "fused"}.get(k.value, str(k.value)),
                     threads_per_agent=t.value, lds_bytes=l.value)
+
+    def export_factor(self, agent: int, stream=None):
+        """(K, A_cl, Hinv, s) of one agent from the last solve (generic kernels only)."""
+        import torch
+        td = torch.float64 if self.dtype == "fp64" else torch.float32
+        sh = self.shapes[agent]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        K = torch.empty((sh.N, sh.nu, sh.nx), dtype=td, device=dev)
+        Acl = torch.empty((sh.N, sh.nx, sh.nx), dtype=td, device=dev)
+        Hi = torch.empty((sh.N, sh.nu, sh.nu), dtype=td, device=dev)
+        sv = torch.empty((sh.N, sh.nx), dtype=td, device=dev)
+        _check(lib().mpc_plan_export_factor(self._h, int(agent), _ptr(K), _ptr(Acl), _ptr(Hi),
+                                            _ptr(sv), _stream_handle(stream)))
+        return K, Acl, Hi, sv

@@ -1,5 +1,6 @@
-// Fused single-launch FP32 solve (stage setup + Riccati factor + all ADMM
-// iterations in one workgroup per agent, operators resident on chip).
+// Register-resident FP32 solve: an FP64 MFMA Riccati-factor kernel followed
+// by an iteration kernel that keeps every stage's operators in the VGPRs of
+// one wavefront per stage.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,12 +9,15 @@
 
 namespace mpc {
 
-// True if the fused kernel has an instantiation for this uniform shape.
+// True if the register-resident kernels have an instantiation for this uniform shape.
 bool fused_supported(int N, int nx, int nu, int n_feet);
-// Threads per workgroup and dynamic LDS bytes of the fused kernel for the shape.
+// Threads per workgroup and dynamic LDS bytes of the iteration kernel for the shape.
 void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds);
+// Floats of operator workspace the two kernels exchange through HBM.
+size_t fused_workspace_floats(int nx, int nu, int n_agents);
+// phase_mask: 1 = factor kernel, 2 = iteration kernel (3 = both).
 hipError_t fused_solve_f32(const AgentDesc* d_desc, int n_agents, int N, int nx, int nu,
                            int n_feet, Inputs<float> in, SolverConsts sc, int iters, int warm,
-                           State<float> st, int threads, size_t lds, hipStream_t stream);
+                           State<float> st, float* ws, hipStream_t stream, int phase_mask);
 
 }  // namespace mpc

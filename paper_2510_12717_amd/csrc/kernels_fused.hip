@@ -1,15 +1,786 @@
+// Register-resident FP32 solve: two kernels, one workgroup per agent.
+//
+// k_riccati (once per solve) -- the Riccati factor that plays the role of
+// Eq. (ldl): stage by stage, k = N-1 .. 0, in FP64 in LDS.  The dense block
+// products (P B, P A, B'PB, B'PA, H^{-1} G, A'PA + G'K, A + B K) run on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64, 16x16 tiles spread over the
+// workgroup's wavefronts); the stage Hessian is inverted in FP64 by one
+// wavefront.  Stage k's operators A_cl,k, K_k, B_k, H_k^{-1} are rounded to
+// float once and written to HBM already in the per-lane order of the
+// register layout below, so the iteration kernel loads them with coalesced
+// loads: opws[agent][stage][slot][lane], SLOTS floats per lane.
+//
+// k_admm_resident -- one wavefront per stage; the QP iterations of Alg. 1
+// (the role of Eqs. (backsolve_1)-(backsolve_2), then projection and dual
+// update), with every operator read from registers.  The two serial chains
+// carry one nx x nx product per stage (p_k = g_k + A_cl,k' p'_k backwards,
+// x_{k+1} = A_cl,k x_k + e_k forwards), executed by the wavefront that owns
+// the stage, one hop per workgroup barrier.  Everything independent across
+// stages runs in all wavefronts at once.  Chain hops are FP32; the
+// stage-parallel products accumulate in FP64 from FP32 operators, and the
+// ADMM state (x, u, z, y) and its relaxation / projection / dual update are
+// FP64.
+//
+// Register layout of a stage's operators (lane = 8a + b, a, b in 0..7):
+//   Acl[i][j] = A_cl[a*RB + i][b*RB + j]      RB = ceil(nx/8)
+//   Km[i][j]  = K[b*CB + i][a*RB + j]         CB = ceil(nu/8)
+//   Bm[i][j]  = B[a*RB + i][b*CB + j]
+//   Hm[i][j]  = H^{-1}[a*CB + i][b*CB + j]
+// so every product is a small per-lane block followed by a butterfly over
+// either the b index (lanes xor 1, 2, 4) or the a index (lanes xor 8, 16, 32).
+#include <math.h>
+
 #include "fused.h"
+#include "stage_rows.h"
 
 namespace mpc {
+namespace {
 
-bool fused_supported(int, int, int, int) { return false; }
-void fused_launch_shape(int, int, int, int, int* threads, size_t* lds) {
-  *threads = 0;
-  *lds = 0;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxStages = 12;   // wavefronts per iteration workgroup
+constexpr int kFactorWaves = 8;  // wavefronts per factor workgroup
+
+template <int NX, int NU>
+struct FS {
+  static constexpr int RB = (NX + 7) / 8, CB = (NU + 7) / 8;
+  static constexpr int NXP = 8 * RB, NUP = 8 * CB;  // padded vector lengths
+  static constexpr int NXT = (NX + 15) / 16 * 16;   // MFMA-padded sizes
+  static constexpr int NUT = (NU + 15) / 16 * 16;
+  static constexpr int LX = NXT + 1, LU = NUT + 1;  // odd strides: no bank conflicts
+  static constexpr int SLOTS = RB * RB + CB * RB + RB * CB + CB * CB;
+  static constexpr int MMAX = 64;
+};
+
+// Marks a register value as redefined here, so loop-invariant code motion
+// cannot hoist its float->double conversions out of the iteration loop (which
+// would keep a double copy of every operator alive and spill).
+__device__ inline void opaque(float& v) { asm volatile("" : "+v"(v)); }
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
-hipError_t fused_solve_f32(const AgentDesc*, int, int, int, int, int, Inputs<float>, SolverConsts,
-                           int, int, State<float>, int, size_t, hipStream_t) {
-  return hipErrorInvalidConfiguration;
+
+template <typename T>
+__device__ inline T red_b(T v) {  // sum over lanes 8a .. 8a+7
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+template <typename T>
+__device__ inline T red_a(T v) {  // sum over lanes b, b+8, .., b+56
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// One 16x16 output tile of C = op(A) op(B) on the FP64 matrix cores.
+// a(i, k) and b(k, j) read the (padded, zero-filled) operands from LDS.
+// Output element v of this lane is C[ti*16 + lane/16 + 4*v][tj*16 + lane%16].
+template <class FA, class FB>
+__device__ inline d4 mfma_tile(int ti, int tj, int K, int lane, FA a, FB b) {
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int r = lane & 15, kk = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double av = a(ti * 16 + r, k0 + kk);
+    const double bv = b(k0 + kk, tj * 16 + r);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------------------------------
+// Riccati factor (FP64, MFMA)
+// ------------------------------------------------------------------------------------
+
+template <int NX, int NU>
+constexpr int riccati_lds_bytes() {
+  using S = FS<NX, NU>;
+  return 8 * (3 * S::NXT * S::LX + 2 * S::NXT * S::LU + S::NUT * S::LX + S::NUT * S::LU +
+              S::NUT + S::MMAX) + 16;
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(64 * kFactorWaves)
+k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, SolverConsts sc,
+          float* __restrict__ opws, float* __restrict__ sws, int32_t* __restrict__ status) {
+  using S = FS<NX, NU>;
+  constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NXT = S::NXT, NUT = S::NUT;
+  constexpr int LX = S::LX, LU = S::LU, SLOTS = S::SLOTS;
+  const int agent = blockIdx.x;
+  if (agent >= n_agents) return;
+  const AgentDesc d = desc[agent];
+  const int N = d.N, M = d.m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const int nw = nt >> 6;
+  extern __shared__ __align__(16) unsigned char sm[];
+  double* P = reinterpret_cast<double*>(sm);  // P_{k+1}, then P_k   NXT x LX
+  double* Ak = P + NXT * LX;                  // A_k                 NXT x LX
+  double* PA = Ak + NXT * LX;                 // P A_k, then A_cl,k  NXT x LX
+  double* Bk = PA + NXT * LX;                 // B_k                 NXT x LU
+  double* PB = Bk + NXT * LU;                 // P B_k, then K_k     NXT x LU | NUT x LX
+  double* Kd = PB;
+  double* G = PB + NXT * LU;                  // B_k' P A_k          NUT x LX
+  double* H = G + NUT * LX;                   // H_k, then H_k^{-1}  NUT x LU
+  double* rdg = H + NUT * LU;                 // diag Rt_k           NUT
+  double* rhok = rdg + NUT;                   // row penalties       MMAX
+  int* flag = reinterpret_cast<int*>(rhok + S::MMAX);
+
+  const float* A = in.A + d.oA;
+  const float* B = in.B + d.oB;
+  const float* c = in.c + d.oc;
+  const float* q = in.q + d.oq;
+  const float* r = in.r + d.orr;
+  const float* tau = in.tau + d.otau;
+  const uint8_t* stance = in.st + d.ost;
+  const float muf = in.mu[agent];
+  const double mu = (double)muf;
+  float* ops = opws + (int64_t)agent * kMaxStages * SLOTS * 64;
+  float* sk_out = sws + (int64_t)agent * kMaxStages * NXP;
+
+  for (int i = tid; i < riccati_lds_bytes<NX, NU>() / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
+  __syncthreads();
+  // non-finite inputs mark the agent and stop it
+  bool ok = isfinite(muf);
+  for (int i = tid; i < N * NX * NX; i += nt) ok &= (bool)isfinite(A[i]);
+  for (int i = tid; i < N * NX * NU; i += nt) ok &= (bool)isfinite(B[i]);
+  for (int i = tid; i < N * NX; i += nt) ok &= (bool)isfinite(c[i]);
+  for (int i = tid; i < (N + 1) * NX; i += nt) ok &= (bool)isfinite(in.xr[d.oxr + i]);
+  for (int i = tid; i < NX; i += nt) ok &= (bool)isfinite(q[i]) && (bool)isfinite(in.x0[d.ox0 + i]);
+  for (int i = tid; i < NU; i += nt) ok &= (bool)isfinite(r[i]);
+  for (int i = tid; i < d.n_tau; i += nt) ok &= (bool)isfinite(tau[i]);
+  if (in.uref)
+    for (int i = tid; i < N * NU; i += nt) ok &= (bool)isfinite(in.uref[d.ou + i]);
+  if (!ok) atomicOr(flag, 1);
+  for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma;
+  __syncthreads();
+  if (flag[0]) {
+    if (tid == 0) status[agent] = AGENT_NONFINITE;
+    return;
+  }
+
+  for (int k = N - 1; k >= 0; --k) {
+    const float* Ag = A + (int64_t)k * NX * NX;
+    const float* Bg = B + (int64_t)k * NX * NU;
+    for (int i = tid; i < NX * NX; i += nt) Ak[(i / NX) * LX + i % NX] = (double)Ag[i];
+    for (int i = tid; i < NX * NU; i += nt) Bk[(i / NU) * LU + i % NU] = (double)Bg[i];
+    for (int i = tid; i < M; i += nt) {
+      double lo, hi;
+      row_bounds<double, float>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rhok[i]);
+    }
+    __syncthreads();
+    for (int j = tid; j < NUT; j += nt)
+      rdg[j] = j < NU ? rtilde_diag<double, double>(d, j, (double)r[j], mu, rhok, sc) : 1.0;
+    // PB = P B_k (NXT x NUT) and PA = P A_k (NXT x NXT); s_k = P c_k
+    {
+      constexpr int TB = (NXT / 16) * (NUT / 16), TA = (NXT / 16) * (NXT / 16);
+      for (int t = w; t < TB + TA; t += nw) {
+        if (t < TB) {
+          const int ti = t / (NUT / 16), tj = t % (NUT / 16);
+          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
+                             [&](int kk, int j) { return Bk[kk * LU + j]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            PB[(ti * 16 + (lane >> 4) + 4 * v) * LU + tj * 16 + (lane & 15)] = acc[v];
+        } else {
+          const int tt = t - TB, ti = tt / (NXT / 16), tj = tt % (NXT / 16);
+          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
+                             [&](int kk, int j) { return Ak[kk * LX + j]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            PA[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = acc[v];
+        }
+      }
+      for (int i = tid; i < NXP; i += nt) {
+        double acc = 0.0;
+        if (i < NX)
+          for (int t = 0; t < NX; ++t) acc += P[i * LX + t] * (double)c[(int64_t)k * NX + t];
+        sk_out[k * NXP + i] = (float)acc;
+      }
+    }
+    __syncthreads();
+    // H = diag(Rt_k) + B_k' PB (NUT x NUT) and G = B_k' PA (NUT x NXT)
+    {
+      constexpr int TH = (NUT / 16) * (NUT / 16), TG = (NUT / 16) * (NXT / 16);
+      for (int t = w; t < TH + TG; t += nw) {
+        if (t < TH) {
+          const int ti = t / (NUT / 16), tj = t % (NUT / 16);
+          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
+                             [&](int kk, int j) { return PB[kk * LU + j]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = ti * 16 + (lane >> 4) + 4 * v, j = tj * 16 + (lane & 15);
+            H[i * LU + j] = acc[v] + (i == j ? rdg[i] : 0.0);
+          }
+        } else {
+          const int tt = t - TH, ti = tt / (NXT / 16), tj = tt % (NXT / 16);
+          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
+                             [&](int kk, int j) { return PA[kk * LX + j]; });
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            G[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = acc[v];
+        }
+      }
+    }
+    __syncthreads();
+    // H_k^{-1} in place by Gauss-Jordan sweeps without pivoting (H_k is SPD:
+    // every pivot is a squared Cholesky diagonal, so a pivot <= 0 means H_k is
+    // not positive definite).  One wavefront, lane-parallel.
+    if (w == 0) {
+      for (int j = 0; j < NU; ++j) {
+        const double piv = H[j * LU + j];
+        if (!(piv > 0.0)) {
+          if (lane == 0) flag[1] = 1;
+          break;
+        }
+        const double ip = 1.0 / piv;
+        // pass 1: entries outside row j and column j; they read row j and
+        // column j, which this pass does not write
+        for (int e = lane; e < NU * NU; e += 64) {
+          const int i = e / NU, t = e % NU;
+          if (i != j && t != j) H[i * LU + t] -= H[i * LU + j] * ip * H[j * LU + t];
+        }
+        wave_sync();
+        // pass 2: row j and column j, each from its own old value
+        for (int e = lane; e < 2 * NU; e += 64) {
+          const int t = e % NU;
+          if (t != j) {
+            if (e < NU)
+              H[j * LU + t] *= ip;
+            else
+              H[t * LU + j] *= -ip;
+          }
+        }
+        wave_sync();
+        if (lane == 0) H[j * LU + j] = ip;
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    if (flag[1]) {
+      if (tid == 0) status[agent] = AGENT_NOT_PD;
+      return;
+    }
+    // K_k = -H_k^{-1} G (NUT x NXT) into the dead PB storage
+    {
+      constexpr int TK = (NUT / 16) * (NXT / 16);
+      for (int t = w; t < TK; t += nw) {
+        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
+        d4 acc = mfma_tile(ti, tj, NUT, lane,
+                           [&](int i, int kk) { return (i < NU && kk < NU) ? H[i * LU + kk] : 0.0; },
+                           [&](int kk, int j) { return G[kk * LX + j]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          Kd[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = -acc[v];
+      }
+    }
+    __syncthreads();
+    // P_k = Q + sigma I + A_k' PA + G' K_k over the dead P_{k+1}
+    {
+      constexpr int TP = (NXT / 16) * (NXT / 16);
+      for (int t = w; t < TP; t += nw) {
+        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
+        d4 a1 = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return Ak[kk * LX + i]; },
+                          [&](int kk, int j) { return PA[kk * LX + j]; });
+        d4 a2 = mfma_tile(ti, tj, NUT, lane, [&](int i, int kk) { return G[kk * LX + i]; },
+                          [&](int kk, int j) { return Kd[kk * LX + j]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ti * 16 + (lane >> 4) + 4 * v, j = tj * 16 + (lane & 15);
+          const double qv = (i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0;
+          P[i * LX + j] = qv + a1[v] + a2[v];
+        }
+      }
+    }
+    __syncthreads();
+    // symmetrise P_k; A_cl,k = A_k + B_k K_k over the dead PA
+    for (int e = tid; e < NXT * NXT; e += nt) {
+      const int i = e / NXT, j = e % NXT;
+      if (j > i) {
+        const double v = 0.5 * (P[i * LX + j] + P[j * LX + i]);
+        P[i * LX + j] = v;
+        P[j * LX + i] = v;
+      }
+    }
+    {
+      constexpr int TA = (NXT / 16) * (NXT / 16);
+      for (int t = w; t < TA; t += nw) {
+        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
+        d4 acc = mfma_tile(ti, tj, NUT, lane, [&](int i, int kk) { return Bk[i * LU + kk]; },
+                           [&](int kk, int j) { return Kd[kk * LX + j]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ti * 16 + (lane >> 4) + 4 * v, j = tj * 16 + (lane & 15);
+          PA[i * LX + j] = Ak[i * LX + j] + acc[v];
+        }
+      }
+    }
+    __syncthreads();
+    // stage k's operators, rounded to float, in register-layout order
+    float* dst = ops + (int64_t)k * SLOTS * 64;
+    for (int e = tid; e < SLOTS * 64; e += nt) {
+      const int slot = e >> 6, ln = e & 63, a = ln >> 3, b = ln & 7;
+      double v = 0.0;
+      if (slot < RB * RB) {
+        const int ri = a * RB + slot / RB, cj = b * RB + slot % RB;
+        if (ri < NX && cj < NX) v = PA[ri * LX + cj];
+      } else if (slot < RB * RB + CB * RB) {
+        const int sl = slot - RB * RB, ri = b * CB + sl / RB, cj = a * RB + sl % RB;
+        if (ri < NU && cj < NX) v = Kd[ri * LX + cj];
+      } else if (slot < RB * RB + 2 * CB * RB) {
+        const int sl = slot - RB * RB - CB * RB, ri = a * RB + sl / CB, cj = b * CB + sl % CB;
+        if (ri < NX && cj < NU) v = Bk[ri * LU + cj];
+      } else {
+        const int sl = slot - RB * RB - 2 * CB * RB, ri = a * CB + sl / CB, cj = b * CB + sl % CB;
+        if (ri < NU && cj < NU) v = H[ri * LU + cj];
+      }
+      dst[e] = (float)v;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) status[agent] = AGENT_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// ADMM iterations with register-resident operators
+// ------------------------------------------------------------------------------------
+
+struct IterLds {
+  int xtf, pbuf, ppf, gf, ef, sf, cf;                         // float
+  int xd, ud, zd, yd, lod, hid, rhod, rtd, dd, utd, qd, xrd;  // double
+  int flag, total;
+};
+
+template <int NX, int NU>
+__host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
+  using S = FS<NX, NU>;
+  IterLds L{};
+  int o = 0;
+  auto take = [&](int bytes) {
+    const int r = o;
+    o += (bytes + 15) & ~15;
+    return r;
+  };
+  L.xtf = take(4 * (N + 1) * S::NXP);
+  L.pbuf = take(4 * (N + 1) * S::NXP);
+  L.ppf = take(4 * N * S::NXP);
+  L.gf = take(4 * N * S::NXP);
+  L.ef = take(4 * N * S::NXP);
+  L.sf = take(4 * N * S::NXP);
+  L.cf = take(4 * N * S::NXP);
+  L.xd = take(8 * (N + 1) * S::NXP);
+  L.ud = take(8 * N * S::NUP);
+  L.zd = take(8 * N * M);
+  L.yd = take(8 * N * M);
+  L.lod = take(8 * N * M);
+  L.hid = take(8 * N * M);
+  L.rhod = take(8 * N * M);
+  L.rtd = take(8 * N * S::NUP);
+  L.dd = take(8 * N * S::NUP);
+  L.utd = take(8 * N * S::NUP);
+  L.qd = take(8 * S::NXP);
+  L.xrd = take(8 * (N + 1) * S::NXP);
+  L.flag = take(16);
+  L.total = o;
+  return L;
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(64 * kMaxStages)
+k_admm_resident(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in,
+                SolverConsts sc, int iters, int warm, const float* __restrict__ opws,
+                const float* __restrict__ sws, State<float> st) {
+  using S = FS<NX, NU>;
+  constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS;
+  const int agent = blockIdx.x;
+  if (agent >= n_agents) return;
+  const AgentDesc d = desc[agent];
+  const int N = d.N, M = d.m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int w = tid >> 6, lane = tid & 63, la = lane >> 3, lb = lane & 7;
+  float* X = st.x + d.ox;
+  float* U = st.u + d.ou;
+  float* Z = st.z + d.oz;
+  float* Y = st.y + d.oz;
+  if (st.status[agent] != AGENT_OK) {
+    for (int i = tid; i < (N + 1) * d.nx; i += nt) X[i] = NAN;
+    for (int i = tid; i < N * d.nu; i += nt) U[i] = NAN;
+    for (int i = tid; i < N * M; i += nt) {
+      Z[i] = NAN;
+      Y[i] = NAN;
+    }
+    return;
+  }
+  const IterLds L = iter_lds_layout<NX, NU>(N, M);
+  extern __shared__ __align__(16) unsigned char sm[];
+  float* xtf = reinterpret_cast<float*>(sm + L.xtf);
+  float* pbuf = reinterpret_cast<float*>(sm + L.pbuf);
+  float* ppf = reinterpret_cast<float*>(sm + L.ppf);
+  float* gf = reinterpret_cast<float*>(sm + L.gf);
+  float* ef = reinterpret_cast<float*>(sm + L.ef);
+  float* sf = reinterpret_cast<float*>(sm + L.sf);
+  float* cf = reinterpret_cast<float*>(sm + L.cf);
+  double* xd = reinterpret_cast<double*>(sm + L.xd);
+  double* ud = reinterpret_cast<double*>(sm + L.ud);
+  double* zd = reinterpret_cast<double*>(sm + L.zd);
+  double* yd = reinterpret_cast<double*>(sm + L.yd);
+  double* lod = reinterpret_cast<double*>(sm + L.lod);
+  double* hid = reinterpret_cast<double*>(sm + L.hid);
+  double* rhod = reinterpret_cast<double*>(sm + L.rhod);
+  double* rtd = reinterpret_cast<double*>(sm + L.rtd);
+  double* dd = reinterpret_cast<double*>(sm + L.dd);
+  double* utd = reinterpret_cast<double*>(sm + L.utd);
+  double* qd = reinterpret_cast<double*>(sm + L.qd);
+  double* xrd = reinterpret_cast<double*>(sm + L.xrd);
+  int* flag = reinterpret_cast<int*>(sm + L.flag);
+
+  const float* c = in.c + d.oc;
+  const float* q = in.q + d.oq;
+  const float* r = in.r + d.orr;
+  const float* xr = in.xr + d.oxr;
+  const float* x0 = in.x0 + d.ox0;
+  const float* tau = in.tau + d.otau;
+  const uint8_t* stance = in.st + d.ost;
+  const float* uref = in.uref ? in.uref + d.ou : nullptr;
+  const double mu = (double)in.mu[agent];
+
+  // this wavefront's stage operators: coalesced loads into registers
+  float Acl[RB][RB], Km[CB][RB], Bm[RB][CB], Hm[CB][CB];
+  {
+    const float* src = opws + ((int64_t)agent * kMaxStages + w) * SLOTS * 64 + lane;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) Acl[i][j] = src[(i * RB + j) * 64];
+    src += RB * RB * 64;
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) Km[i][j] = src[(i * RB + j) * 64];
+    src += CB * RB * 64;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) Bm[i][j] = src[(i * CB + j) * 64];
+    src += RB * CB * 64;
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) Hm[i][j] = src[(i * CB + j) * 64];
+  }
+
+  // per-agent vectors into LDS (padding zero)
+  for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
+  __syncthreads();
+  const float* sk = sws + (int64_t)agent * kMaxStages * NXP;
+  for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
+  for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
+  for (int i = tid; i < NX; i += nt) {
+    qd[i] = (double)q[i];
+    xd[i] = (double)x0[i];
+    xtf[i] = x0[i];
+  }
+  for (int i = tid; i < (N + 1) * NX; i += nt) xrd[(i / NX) * NXP + i % NX] = (double)xr[i];
+  for (int i = tid; i < N * M; i += nt) {
+    const int k = i / M, j = i % M;
+    double lo, hi, rr;
+    row_bounds<double, float>(d, j, stance + k * d.n_feet, tau, sc, lo, hi, rr);
+    lod[i] = lo;
+    hid[i] = hi;
+    rhod[i] = rr;
+  }
+  for (int i = tid; i < N * NU; i += nt) ud[(i / NU) * NUP + i % NU] = warm ? (double)U[i] : 0.0;
+  for (int i = tid; i < N * M; i += nt) {
+    zd[i] = warm ? (double)Z[i] : 0.0;
+    yd[i] = warm ? (double)Y[i] : 0.0;
+  }
+  __syncthreads();
+
+  const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
+  const int k = w;  // this wavefront's stage (blockDim = 64 N)
+
+  // x^0: rollout of the dynamics under u^0, as x_{k+1} = A_cl x + B (u - K x) + c
+  for (int kk = 0; kk < N; ++kk) {
+    if (w == kk) {
+      float xa[RB], v[CB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + la * RB + j];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xa[j]);
+        v[i] = (float)(ud[kk * NUP + lb * CB + i] - red_a(s));
+      }
+#pragma unroll
+      for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + lb * RB + j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) s += (double)(Acl[i][j] * xa[j]);
+#pragma unroll
+        for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * v[j]);
+        s = red_b(s);
+        const int idx = la * RB + i;
+        if (lb == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = (double)cf[kk * NXP + idx] + s;
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        opaque(Km[i][j]);
+        opaque(Bm[j][i]);
+      }
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) opaque(Hm[i][j]);
+    // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k; wavefront N-1 also p_N
+    if (lane < NUP) {
+      double v = 0.0;
+      if (lane < NU) {
+        const double* yk = yd + k * M;
+        const double* zk = zd + k * M;
+        const double* rk = rhod + k * M;
+        auto wv = [&](int i) { return yk[i] - rk[i] * zk[i]; };
+        v = wv(lane);
+        if (lane >= d.n_tau) {
+          const int f = (lane - d.n_tau) / d.foot_dim, cc = (lane - d.n_tau) % d.foot_dim;
+          const int b0 = NU + 4 * f;
+          if (cc == 0) v += wv(b0) - wv(b0 + 1);
+          if (cc == 1) v += wv(b0 + 2) - wv(b0 + 3);
+          if (cc == 2) v -= mu * (wv(b0) + wv(b0 + 1) + wv(b0 + 2) + wv(b0 + 3));
+        }
+        v += -sigma * ud[k * NUP + lane];
+        if (uref) v -= (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
+      }
+      rtd[k * NUP + lane] = v;
+    }
+    if (k == N - 1)
+      for (int i = lane; i < NX; i += 64)
+        pbuf[N * NXP + i] = (float)(-qd[i] * xrd[N * NXP + i] - sigma * xd[N * NXP + i]);
+    wave_sync();
+    if (k >= 1) {
+      float rv[CB];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < CB; ++i) s += (double)(Km[i][j] * rv[i]);
+        s = red_b(s);
+        const int idx = la * RB + j;
+        if (lb == 0)
+          gf[k * NXP + idx] =
+              (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) + s);
+      }
+    }
+    // (B) backward chain, one hop per barrier: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
+    for (int kk = N - 1; kk >= 0; --kk) {
+      if (w == kk) {
+        float pin[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+          pin[i] = pbuf[(kk + 1) * NXP + la * RB + i] + sf[kk * NXP + la * RB + i];
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) ppf[kk * NXP + la * RB + i] = pin[i];
+        if (kk >= 1) {
+#pragma unroll
+          for (int j = 0; j < RB; ++j) {
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s += Acl[i][j] * pin[i];
+            s = red_a(s);
+            if (la == 0) pbuf[kk * NXP + lb * RB + j] = gf[kk * NXP + lb * RB + j] + s;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
+    {
+      float pv[RB], hv[CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) pv[i] = ppf[k * NXP + la * RB + i];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s += (double)(Bm[i][j] * pv[i]);
+        hv[j] = (float)(rtd[k * NUP + lb * CB + j] + red_a(s));
+      }
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) s += (double)(Hm[i][j] * hv[j]);
+        s = red_b(s);
+        if (lb == 0) dd[k * NUP + la * CB + i] = -s;
+      }
+      wave_sync();
+      float dv[CB];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) dv[j] = (float)dd[k * NUP + lb * CB + j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * dv[j]);
+        s = red_b(s);
+        const int idx = la * RB + i;
+        if (lb == 0) ef[k * NXP + idx] = (float)((double)cf[k * NXP + idx] + s);
+      }
+    }
+    __syncthreads();
+    // (D) forward chain: xt_{k+1} = A_cl,k xt_k + e_k
+    for (int kk = 0; kk < N; ++kk) {
+      if (w == kk) {
+        float xin[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) xin[j] = xtf[kk * NXP + lb * RB + j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          float s = 0.f;
+#pragma unroll
+          for (int j = 0; j < RB; ++j) s += Acl[i][j] * xin[j];
+          s = red_b(s);
+          if (lb == 0) xtf[(kk + 1) * NXP + la * RB + i] = ef[kk * NXP + la * RB + i] + s;
+        }
+      }
+      __syncthreads();
+    }
+    // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
+    {
+      float xv[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) xv[j] = xtf[k * NXP + la * RB + j];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xv[j]);
+        s = red_a(s);
+        if (la == 0) utd[k * NUP + lb * CB + i] = dd[k * NUP + lb * CB + i] + s;
+      }
+      wave_sync();
+      if (k >= 1)
+        for (int i = lane; i < NX; i += 64)
+          xd[k * NXP + i] = alpha * (double)xtf[k * NXP + i] + oma * xd[k * NXP + i];
+      if (k == N - 1)
+        for (int i = lane; i < NX; i += 64)
+          xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
+      if (lane < M) {
+        const int idx = k * M + lane;
+        const double zeta = c_row<double>(d, lane, mu, utd + k * NUP);
+        const double wv = alpha * zeta + oma * zd[idx];
+        const double zn = fmin(fmax(wv + yd[idx] / rhod[idx], lod[idx]), hid[idx]);
+        yd[idx] = yd[idx] + rhod[idx] * (wv - zn);
+        zd[idx] = zn;
+      }
+      if (lane < NU) ud[k * NUP + lane] = alpha * utd[k * NUP + lane] + oma * ud[k * NUP + lane];
+      wave_sync();
+    }
+  }
+  __syncthreads();
+
+  bool fin = true;
+  for (int i = tid; i < (N + 1) * NX; i += nt) {
+    const float v = (float)xd[(i / NX) * NXP + i % NX];
+    X[i] = v;
+    fin &= (bool)isfinite(v);
+  }
+  for (int i = tid; i < N * NU; i += nt) {
+    const float v = (float)ud[(i / NU) * NUP + i % NU];
+    U[i] = v;
+    fin &= (bool)isfinite(v);
+  }
+  for (int i = tid; i < N * M; i += nt) {
+    Z[i] = (float)zd[i];
+    Y[i] = (float)yd[i];
+    fin &= (bool)isfinite(Z[i]) && (bool)isfinite(Y[i]);
+  }
+  if (!fin) atomicOr(flag, 1);
+  __syncthreads();
+  if (tid == 0 && flag[0]) st.status[agent] = AGENT_NONFINITE;
+}
+
+template <int NX, int NU>
+hipError_t launch_pair(const AgentDesc* d_desc, int n_agents, int N, int M, Inputs<float> in,
+                       SolverConsts sc, int iters, int warm, State<float> st, float* opws,
+                       float* sws, hipStream_t stream, int phase_mask) {
+  const int lf = riccati_lds_bytes<NX, NU>();
+  const int li = iter_lds_layout<NX, NU>(N, M).total;
+  if (phase_mask & 1) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lf);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_riccati<NX, NU>), dim3(n_agents), dim3(64 * kFactorWaves), lf, stream,
+                       d_desc, n_agents, in, sc, opws, sws, st.status);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (phase_mask & 2) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, li);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_agents), dim3(64 * N), li, stream,
+                       d_desc, n_agents, in, sc, iters, warm, opws, sws, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+bool fused_supported(int N, int nx, int nu, int n_feet) {
+  const int m = nu + 4 * n_feet;
+  if (N < 1 || N > kMaxStages || m > 64) return false;
+  if (nx == 48 && nu == 30) return iter_lds_layout<48, 30>(N, m).total <= 160 * 1024;
+  if (nx == 36 && nu == 24) return iter_lds_layout<36, 24>(N, m).total <= 160 * 1024;
+  return false;
+}
+
+void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds) {
+  const int m = nu + 4 * n_feet;
+  *threads = 64 * N;
+  *lds = (nx == 48) ? iter_lds_layout<48, 30>(N, m).total : iter_lds_layout<36, 24>(N, m).total;
+  (void)nu;
+}
+
+size_t fused_workspace_floats(int nx, int nu, int n_agents) {
+  const int slots = (nx == 48) ? FS<48, 30>::SLOTS : FS<36, 24>::SLOTS;
+  const int nxp = (nx == 48) ? FS<48, 30>::NXP : FS<36, 24>::NXP;
+  (void)nu;
+  return (size_t)n_agents * kMaxStages * ((size_t)slots * 64 + nxp);
+}
+
+hipError_t fused_solve_f32(const AgentDesc* d_desc, int n_agents, int N, int nx, int nu,
+                           int n_feet, Inputs<float> in, SolverConsts sc, int iters, int warm,
+                           State<float> st, float* ws, hipStream_t stream, int phase_mask) {
+  const int m = nu + 4 * n_feet;
+  const int slots = (nx == 48) ? FS<48, 30>::SLOTS : FS<36, 24>::SLOTS;
+  float* opws = ws;
+  float* sws = ws + (size_t)n_agents * kMaxStages * slots * 64;
+  if (nx == 48 && nu == 30)
+    return launch_pair<48, 30>(d_desc, n_agents, N, m, in, sc, iters, warm, st, opws, sws, stream,
+                               phase_mask);
+  if (nx == 36 && nu == 24)
+    return launch_pair<36, 24>(d_desc, n_agents, N, m, in, sc, iters, warm, st, opws, sws, stream,
+                               phase_mask);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mpc

@@ -218,6 +218,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   if (p->kernel == 2) {
     fused_launch_shape(p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu, p->shapes[0].n_feet,
                        &p->fused_threads, &p->fused_lds);
+    // the register-resident kernels exchange operators through their own workspace
+    p->nWS = (int64_t)fused_workspace_floats(p->shapes[0].nx, p->shapes[0].nu, p->n);
   }
   auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
     return hipMalloc(ptr, bytes ? bytes : 16);
@@ -344,11 +346,19 @@ static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
   State<T> st = make_state<T>(p);
   SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale, p->desc.rho_min};
   if (p->kernel == 2) {
-    PhaseTimer t(p, 1, s);
-    HIP_TRY(fused_solve_f32(p->d_desc, p->n, p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu,
-                            p->shapes[0].n_feet, make_inputs<float>(b), sc, p->desc.admm_iters,
-                            b->warm_start, make_state<float>(p), p->fused_threads, p->fused_lds,
-                            s));
+    const mpc_shape& sh = p->shapes[0];
+    {
+      PhaseTimer t(p, 0, s);
+      HIP_TRY(fused_solve_f32(p->d_desc, p->n, sh.N, sh.nx, sh.nu, sh.n_feet, make_inputs<float>(b),
+                              sc, p->desc.admm_iters, b->warm_start, make_state<float>(p),
+                              (float*)p->d_ws, s, 1));
+    }
+    {
+      PhaseTimer t(p, 1, s);
+      HIP_TRY(fused_solve_f32(p->d_desc, p->n, sh.N, sh.nx, sh.nu, sh.n_feet, make_inputs<float>(b),
+                              sc, p->desc.admm_iters, b->warm_start, make_state<float>(p),
+                              (float*)p->d_ws, s, 2));
+    }
   } else {
     {
       PhaseTimer t(p, 0, s);

@@ -81,9 +81,11 @@ def test_config0_fp64_every_agent():
     np.testing.assert_allclose(g["objective"], o["objective"], rtol=1e-10)
 
 
-def test_config0_fp32_every_agent():
+@pytest.mark.parametrize("kernel", ["generic", "fused"])
+def test_config0_fp32_every_agent(kernel):
     b = synth.config0(64)
-    g, plan, _ = run_gpu(b, "fp32")
+    g, plan, _ = run_gpu(b, "fp32", kernel=kernel)
+    assert plan.config()["kernel"] == kernel
     o = oracle.solve_batch(b, iters=50)
     assert np.all(g["status"] == 0)
     e = agent_errors(b, g, o)
@@ -130,8 +132,8 @@ def test_failures_stay_local():
     o_ = b.offsets()
     b.A[o_["A"][2] + 17] = np.nan
     b.r[o_["r"][4]:o_["r"][5]] = -5.0
-    for precision in ("fp64", "fp32"):
-        g, _, _ = run_gpu(b, precision)
+    for precision, kernel in (("fp64", "auto"), ("fp32", "generic"), ("fp32", "fused")):
+        g, _, _ = run_gpu(b, precision, kernel=kernel)
         o = oracle.solve_batch(b, iters=50)
         assert g["status"].tolist() == o["status"].tolist() == [0, 0, 3, 0, 2, 0]
         e = agent_errors(b, g, o, agents=[0, 1, 3, 5])
@@ -140,28 +142,30 @@ def test_failures_stay_local():
         assert np.all(np.isnan(g["residuals"][[2, 4]]))
 
 
-def test_batch_invariance():
+@pytest.mark.parametrize("kernel", ["generic", "fused"])
+def test_batch_invariance(kernel):
     """An agent's result does not depend on which agents share the launch."""
     full = synth.config0(32)
     sub = full.subset([3, 17, 30])
-    gf, _, _ = run_gpu(full, "fp32")
-    gs, _, _ = run_gpu(sub, "fp32")
+    gf, _, _ = run_gpu(full, "fp32", kernel=kernel)
+    gs, _, _ = run_gpu(sub, "fp32", kernel=kernel)
     of, os_ = full.offsets(), sub.offsets()
     for j, a in enumerate([3, 17, 30]):
         np.testing.assert_array_equal(gf["u"][of["u"][a]:of["u"][a + 1]],
                                       gs["u"][os_["u"][j]:os_["u"][j + 1]])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_closed_loop_warm_start(precision):
+@pytest.mark.parametrize("precision,kernel", [("fp64", "auto"), ("fp32", "generic"),
+                                              ("fp32", "fused")])
+def test_closed_loop_warm_start(precision, kernel):
     """Config-1 shape: warm-started solves along a closed loop whose x0 advances
     by the agent's own dynamics plus noise.  Per-step parity: each GPU solve
     starts from the oracle's previous (u, z, y) and the oracle's x0, so both
     sides solve the same QP from the same point.  The drift of a GPU loop that
     warm-starts from its own iterates is reported alongside."""
     b = synth.config1(128)
-    plan = mpc.Plan(b.shapes, precision=precision, iters=50)
-    own = mpc.Plan(b.shapes, precision=precision, iters=50)
+    plan = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
+    own = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
     prob = mpc.to_device(b, precision)
     td = prob["A"].dtype
     x0 = b.x0.copy()
@@ -225,11 +229,12 @@ def test_api_errors_on_device():
     assert ei.value.code == mpc.MPC_ERR_INVALID_ARG
 
 
-def test_config1_full_size_sampled():
+@pytest.mark.parametrize("kernel", ["auto", "generic"])
+def test_config1_full_size_sampled(kernel):
     """4096 humanoid agents (the benchmark's batch and launch configuration),
     FP32, cold start; every 16th agent is checked against the oracle."""
     b = synth.config1(4096, dtype=np.float32)
-    g, plan, _ = run_gpu(b, "fp32")
+    g, plan, _ = run_gpu(b, "fp32", kernel=kernel)
     assert np.all(g["status"] == 0)
     ids = np.arange(0, 4096, 16)
     sub = synth.config1(agent_ids=ids)
@@ -240,3 +245,24 @@ def test_config1_full_size_sampled():
     print("config1 sampled: kernel", plan.config()["kernel"], "max u0/traj", e[:, :2].max(axis=0),
           "p99", np.percentile(e[:, :2], 99, axis=0))
     assert e[:, :2].max() < TOL["fp32"]
+
+
+@pytest.mark.parametrize("kernel", ["generic", "fused"])
+def test_quadruped_uniform_fp32(kernel):
+    b = synth.make_batch([synth.quadruped(8)] * 24, seed=3, config_id=51, stance_p=None)
+    g, plan, _ = run_gpu(b, "fp32", kernel=kernel)
+    assert plan.config()["kernel"] == kernel
+    o = oracle.solve_batch(b, iters=50)
+    assert np.all(g["status"] == 0)
+    assert agent_errors(b, g, o)[:, :2].max() < TOL["fp32"]
+
+
+def test_fused_horizon_limits():
+    """The register-resident kernels serve N <= 12; longer horizons fall back."""
+    for N, want in ((1, "fused"), (12, "fused"), (13, "generic")):
+        plan = mpc.Plan([synth.humanoid(N)] * 2, precision="fp32")
+        assert plan.config()["kernel"] == want, N
+    b = synth.make_batch([synth.humanoid(1)] * 4, seed=2, config_id=52)
+    g, plan, _ = run_gpu(b, "fp32", kernel="fused")
+    o = oracle.solve_batch(b, iters=50)
+    assert agent_errors(b, g, o)[:, :2].max() < TOL["fp32"]

@@ -26,15 +26,15 @@ _SRC = os.path.join(_HERE, "mpc_oracle.c")
 OK, CONVERGED, NOT_PD, NONFINITE = 0, 1, 2, 3
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, src: str = _SRC, out: str = _SO) -> str:
     """Compile the oracle with gcc (IEEE semantics: no fast-math, no FP contraction)."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp"
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
-                               "-fno-fast-math", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC,
-                               "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+                               "-fno-fast-math", "-shared", "-fPIC", "-Wall", "-I", _HERE, "-o",
+                               tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class Settings(ctypes.Structure):
@@ -54,17 +54,26 @@ class _Shape(ctypes.Structure):
 
 
 _lib = None
+_lib_path = None
 _D = ctypes.POINTER(ctypes.c_double)
 _U8 = ctypes.POINTER(ctypes.c_uint8)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 
 
+def use_library(path: Optional[str]) -> None:
+    """Point the wrapper at another build of the oracle (None = the default one).
+    Used by the mutation tests, which load deliberately broken copies."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        path = _lib_path or _SO
+        if path == _SO and not os.path.exists(_SO):
             build()
-        L = ctypes.CDLL(_SO)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         L.orc_rows.argtypes = [P(_Shape)]
         L.orc_rows.restype = ctypes.c_int32

@@ -62,18 +62,61 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes,
+// v_permlane16_swap / v_permlane32_swap across rows (gfx950).
+template <int C>
+__device__ inline float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, 0xF, 0xF, false));
+}
+template <int C>
+__device__ inline double dpp(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), C, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// v + (the same register of the lane 16 or 32 lanes away): permlane swaps hand
+// each lane its partner's value; both lanes of a pair add in the same order.
+__device__ inline float swap_sum16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float swap_sum32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline double join(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline double swap_sum16(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  return join(l[0], h[0]) + join(l[1], h[1]);
+}
+__device__ inline double swap_sum32(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  return join(l[0], h[0]) + join(l[1], h[1]);
+}
+
+// All-reduce over the 8 lanes 8a .. 8a+7 (the b index): quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror.  Every lane ends with the same sum.
 template <typename T>
-__device__ inline T red_b(T v) {  // sum over lanes 8a .. 8a+7
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
+__device__ inline T red_b(T v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
   return v;
 }
+// All-reduce over the 8 lanes b, b+8, .., b+56 (the a index): row_ror 8, then
+// the 16- and 32-lane swaps.
 template <typename T>
-__device__ inline T red_a(T v) {  // sum over lanes b, b+8, .., b+56
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
+__device__ inline T red_a(T v) {
+  v += dpp<0x128>(v);
+  v = swap_sum16(v);
+  v = swap_sum32(v);
   return v;
 }
 
@@ -100,7 +143,7 @@ template <int NX, int NU>
 constexpr int riccati_lds_bytes() {
   using S = FS<NX, NU>;
   return 8 * (3 * S::NXT * S::LX + 2 * S::NXT * S::LU + S::NUT * S::LX + S::NUT * S::LU +
-              S::NUT + S::MMAX) + 16;
+              S::NUT + S::MMAX + S::NXT + 2 * S::NUT) + 16;
 }
 
 template <int NX, int NU>
@@ -128,7 +171,10 @@ k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, So
   double* H = G + NUT * LX;                   // H_k, then H_k^{-1}  NUT x LU
   double* rdg = H + NUT * LU;                 // diag Rt_k           NUT
   double* rhok = rdg + NUT;                   // row penalties       MMAX
-  int* flag = reinterpret_cast<int*>(rhok + S::MMAX);
+  double* ck = rhok + S::MMAX;                // c_k                 NXT
+  double* xcol = ck + NXT;                    // Gauss-Jordan pivot column / row exchange
+  double* xrow = xcol + NUT;
+  int* flag = reinterpret_cast<int*>(xrow + NUT);
 
   const float* A = in.A + d.oA;
   const float* B = in.B + d.oB;
@@ -172,6 +218,7 @@ k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, So
       double lo, hi;
       row_bounds<double, float>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rhok[i]);
     }
+    for (int i = tid; i < NX; i += nt) ck[i] = (double)c[(int64_t)k * NX + i];
     __syncthreads();
     for (int j = tid; j < NUT; j += nt)
       rdg[j] = j < NU ? rtilde_diag<double, double>(d, j, (double)r[j], mu, rhok, sc) : 1.0;
@@ -198,7 +245,7 @@ k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, So
       for (int i = tid; i < NXP; i += nt) {
         double acc = 0.0;
         if (i < NX)
-          for (int t = 0; t < NX; ++t) acc += P[i * LX + t] * (double)c[(int64_t)k * NX + t];
+          for (int t = 0; t < NX; ++t) acc += P[i * LX + t] * ck[t];
         sk_out[k * NXP + i] = (float)acc;
       }
     }
@@ -227,37 +274,65 @@ k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, So
       }
     }
     __syncthreads();
-    // H_k^{-1} in place by Gauss-Jordan sweeps without pivoting (H_k is SPD:
-    // every pivot is a squared Cholesky diagonal, so a pivot <= 0 means H_k is
-    // not positive definite).  One wavefront, lane-parallel.
+    // H_k^{-1} in place by Gauss-Jordan sweeps without pivoting over the padded
+    // NUT x NUT matrix (padding is the identity).  H_k is SPD, so every pivot is
+    // a squared Cholesky diagonal and a pivot <= 0 means H_k is not positive
+    // definite.  One wavefront; lane (a, b) holds the 4x4 block rows 4a..,
+    // columns 4b.. in registers, and each sweep broadcasts the pivot row and
+    // column through LDS.
     if (w == 0) {
-      for (int j = 0; j < NU; ++j) {
-        const double piv = H[j * LU + j];
+      static_assert(NUT == 32, "the register-blocked inversion assumes 32 x 32");
+      const int ga = lane >> 3, gb = lane & 7;
+      double h[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) h[r][cc] = H[(4 * ga + r) * LU + 4 * gb + cc];
+      bool bad = false;
+      for (int j = 0; j < NUT; ++j) {
+        const int jb = j >> 2, jr = j & 3;
+        // owners publish column j (lanes with gb == jb) and row j (lanes with ga == jb)
+        if (gb == jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xcol[4 * ga + r] = h[r][jr];
+        if (ga == jb)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) xrow[4 * gb + cc] = h[jr][cc];
+        wave_sync();
+        double col[4], row[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[r] = xcol[4 * ga + r];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) row[cc] = xrow[4 * gb + cc];
+        const double piv = xrow[j];
+        wave_sync();
         if (!(piv > 0.0)) {
-          if (lane == 0) flag[1] = 1;
+          bad = true;
           break;
         }
         const double ip = 1.0 / piv;
-        // pass 1: entries outside row j and column j; they read row j and
-        // column j, which this pass does not write
-        for (int e = lane; e < NU * NU; e += 64) {
-          const int i = e / NU, t = e % NU;
-          if (i != j && t != j) H[i * LU + t] -= H[i * LU + j] * ip * H[j * LU + t];
-        }
-        wave_sync();
-        // pass 2: row j and column j, each from its own old value
-        for (int e = lane; e < 2 * NU; e += 64) {
-          const int t = e % NU;
-          if (t != j) {
-            if (e < NU)
-              H[j * LU + t] *= ip;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const bool ri = (4 * ga + r) == j, ct = (4 * gb + cc) == j;
+            if (ri && ct)
+              h[r][cc] = ip;
+            else if (ri)
+              h[r][cc] = row[cc] * ip;
+            else if (ct)
+              h[r][cc] = -col[r] * ip;
             else
-              H[t * LU + j] *= -ip;
+              h[r][cc] -= col[r] * ip * row[cc];
           }
-        }
-        wave_sync();
-        if (lane == 0) H[j * LU + j] = ip;
-        wave_sync();
+      }
+      if (bad) {
+        if (lane == 0) flag[1] = 1;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) H[(4 * ga + r) * LU + 4 * gb + cc] = h[r][cc];
       }
     }
     __syncthreads();

@@ -1,0 +1,80 @@
+"""The pins catch plausible mistakes: each case plants one error in a copy of
+the oracle's C source (a dropped term, a wrong sign or index, a transposed
+operand), builds it, and checks that at least one pin fails."""
+import os
+import shutil
+import tempfile
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "mpc_oracle.c")
+
+# (name, text in the source, replacement)
+MUTANTS = [
+    ("drop s_k in back-sweep", "pp[i] = p[i] + sv[(size_t)k * nx + i];", "pp[i] = p[i];"),
+    ("transposed A in back-sweep", "acc += Ak[t * nx + i] * pp[t];", "acc += Ak[i * nx + t] * pp[t];"),
+    ("wrong sign of d", "for (int j = 0; j < nu; ++j) dk[j] = -hv[j];",
+     "for (int j = 0; j < nu; ++j) dk[j] = hv[j];"),
+    ("K' h dropped from p", "for (int t = 0; t < nu; ++t) acc += Kk[t * nx + i] * hv[t];", ""),
+    ("sigma sign in qt", "- sigma * x[(size_t)k * nx + i];", "+ sigma * x[(size_t)k * nx + i];"),
+    ("dual update sign", "y[idx] = y[idx] + rho[idx] * (w - zn);", "y[idx] = y[idx] - rho[idx] * (w - zn);"),
+    ("no relaxation of z", "const double w = alpha * zeta + (1.0 - alpha) * z[idx];",
+     "const double w = zeta;"),
+    ("rho_eq not applied", "rr = st->rho_eq_scale * st->rho;", "rr = st->rho;"),
+    ("pyramid facet sign", "C[(p + 1) * nu + fx] = -1.0;", "C[(p + 1) * nu + fx] = 1.0;"),
+    ("G'K dropped from P", "for (int t = 0; t < nu; ++t) acc += G[t * nx + i] * Kk[t * nx + j];", ""),
+    ("P_{k+1} c instead of c in s", "acc += Pn[i * nx + t] * ck[t];", "acc += Pn[i * nx + t] * ck[i];"),
+    ("dual residual sign", "for (int row = 0; row < m; ++row) acc += C[row * nu + j] * yk[row];",
+     "for (int row = 0; row < m; ++row) acc -= C[row * nu + j] * yk[row];"),
+]
+
+CHECKS = [
+    lambda: pins.test_xupdate_equals_dense_kkt(pins.tiny_shape(5, 4), 1),
+    lambda: pins.test_xupdate_equals_dense_kkt(pins.synth.quadruped(4), 2),
+    lambda: pins.test_fixed_iterates_equal_dense_admm(pins.tiny_shape(3, 3), 4, 7),
+    lambda: pins.test_fixed_iterates_equal_dense_admm(pins.synth.quadruped(3), 5, 5),
+    lambda: pins.test_constraint_rows_and_bounds_match_statement(pins.synth.quadruped(3)),
+    lambda: pins.test_residuals_match_lagrangian_gradient(),
+    lambda: pins.test_converged_equals_brute_force_active_set(2, 2),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(name, old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"mutation site not unique/present: {name}"
+    tmp = tempfile.mkdtemp()
+    try:
+        src = os.path.join(tmp, "mpc_oracle.c")
+        open(src, "w").write(text.replace(old, new))
+        so = oracle.build(force=True, src=src, out=os.path.join(tmp, "libmutant.so"))
+        oracle.use_library(so)
+        caught = []
+        for chk in CHECKS:
+            try:
+                chk()
+            except (AssertionError, Exception):  # a failing pin (or a crash of the broken copy)
+                caught.append(chk)
+                break
+        assert caught, f"no pin failed for mutant: {name}"
+    finally:
+        oracle.use_library(None)
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
+def test_unmutated_copy_passes_every_check():
+    """Control: the same build-and-load path with the source unchanged passes."""
+    tmp = tempfile.mkdtemp()
+    try:
+        src = os.path.join(tmp, "mpc_oracle.c")
+        shutil.copy(SRC, src)
+        so = oracle.build(force=True, src=src, out=os.path.join(tmp, "libcopy.so"))
+        oracle.use_library(so)
+        for chk in CHECKS:
+            chk()
+    finally:
+        oracle.use_library(None)
+        shutil.rmtree(tmp, ignore_errors=True)

@@ -335,3 +335,32 @@ def test_subset_reproduces_agents():
     for j, a in enumerate((5, 2)):
         np.testing.assert_array_equal(full["u"][o["u"][a]:o["u"][a + 1]],
                                       part["u"][p["u"][j]:p["u"][j + 1]])
+
+
+def test_residuals_match_lagrangian_gradient():
+    """The oracle's residual report equals quantities built independently from
+    the stacked QP: primal |Cu - z|, dynamics |Gv - b|, the objective, and the
+    dual residual = gradient in u of the Lagrangian f + mu'(Gv - b) + y'Cu with
+    mu chosen so the gradient in x vanishes."""
+    s = synth.quadruped(4)
+    ag = one_agent(s, seed=31)
+    rng = np.random.default_rng(31)
+    C = D.C_dense(s, ag["mu"])
+    x = rng.standard_normal((s.N + 1, s.nx))
+    x[0] = ag["x0"]
+    u = rng.standard_normal((s.N, s.nu))
+    z = rng.standard_normal((s.N, C.shape[0]))
+    y = rng.standard_normal((s.N, C.shape[0]))
+    res, obj = oracle.residuals(s, ag["A"], ag["B"], ag["c"], ag["q"], ag["r"], ag["x_ref"],
+                                ag["x0"], ag["tau_max"], ag["mu"], ag["stance"], x, u, z, y)
+    G, b = D.dynamics_rows(s, ag["A"], ag["B"], ag["c"], ag["x0"])
+    v = np.concatenate([x[1:].ravel(), u.ravel()])
+    nxv = s.N * s.nx
+    grad = np.concatenate([(ag["q"] * (x[1:] - ag["x_ref"][1:])).ravel(), (ag["r"] * u).ravel()])
+    mu_ = np.linalg.solve(G[:, :nxv].T, -grad[:nxv])
+    dual = grad[nxv:] + G[:, nxv:].T @ mu_ + (y @ C).ravel()
+    f = 0.5 * np.sum(ag["q"] * (x[1:] - ag["x_ref"][1:]) ** 2) + 0.5 * np.sum(ag["r"] * u ** 2)
+    assert res[0] == pytest.approx(np.abs(u @ C.T - z).max(), rel=1e-12)
+    assert res[1] == pytest.approx(np.abs(dual).max(), rel=1e-9)
+    assert res[2] == pytest.approx(np.abs(G @ v - b).max(), rel=1e-9)
+    assert obj == pytest.approx(f, rel=1e-12)

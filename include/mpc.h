@@ -98,7 +98,9 @@ typedef struct {
   int32_t max_refine_sweeps;/* refinement sweeps per x-update, mixed precisions only   */
   double refine_tol;        /* stop refining at |r|_inf <= refine_tol * |b|_inf        */
   int32_t device;           /* HIP device ordinal                                      */
-  int32_t kernel;           /* 0 = auto, 1 = generic kernels, 2 = fused kernel         */
+  int32_t kernel;           /* 0 = auto, 1 = generic kernels only, 2 = register-      */
+                            /* resident kernels only (UNSUPPORTED_SHAPE if an agent has */
+                            /* no instantiation)                                        */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */
@@ -151,14 +153,17 @@ mpc_status mpc_advance_state(mpc_plan_t plan, const mpc_problem_batch* batch, co
                              void* x0_next, void* stream);
 
 /* Per-kernel timing: when enabled, every launch of a solve is bracketed by
- * HIP events on the solve's stream.  mpc_plan_get_timing synchronises the
- * stream of the last solve and returns the accumulated milliseconds and launch
- * counts of {stage setup + factor, ADMM iterations, KKT residual} in
- * ms[0..2] / launches[0..2].  Enabling resets the counters. */
+ * HIP events on the stream it runs on.  mpc_plan_get_timing waits for those
+ * events and returns the accumulated milliseconds and launch counts of
+ * {stage setup + factor, ADMM iterations, KKT residual} in ms[0..2] /
+ * launches[0..2], summed over launch groups (groups on different streams may
+ * overlap in time).  Enabling resets the counters.  Replays of a captured
+ * step are not timed. */
 mpc_status mpc_plan_set_timing(mpc_plan_t plan, int32_t enable);
 mpc_status mpc_plan_get_timing(mpc_plan_t plan, double* ms, int64_t* launches);
 
-/* Which kernel family the plan runs (1 generic, 2 fused) and its launch shape. */
+/* Which kernel families the plan runs (bit 0 generic, bit 1 register-resident:
+ * 1, 2 or 3) and the launch shape of its largest launch group. */
 mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* threads_per_agent,
                                int32_t* lds_bytes);
 
@@ -169,6 +174,46 @@ mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* thread
  * (UNSUPPORTED_SHAPE otherwise).  For tests and diagnostics. */
 mpc_status mpc_plan_export_factor(mpc_plan_t plan, int32_t agent, void* K, void* A_cl, void* Hinv,
                                   void* s, void* stream);
+
+/* Launch groups.  A plan splits its agents into groups: agents of one shape
+ * class (nx, nu, n_tau, n_feet, foot_dim) and, for the register-resident
+ * kernels, one horizon N.  Each group is one factor launch and one iteration
+ * launch; groups are spread over up to four streams that fork from and join
+ * back into the solve's stream. */
+typedef struct {
+  int32_t family;    /* 1 generic, 2 register-resident                        */
+  int32_t N;         /* horizon (longest in the group for generic groups)      */
+  int32_t nx, nu, n_feet;
+  int32_t n_agents;
+  int32_t threads;   /* workgroup size of the iteration kernel                 */
+  int32_t lds_bytes; /* dynamic LDS of the group's largest launch              */
+} mpc_group_info;
+
+/* Number of groups in *n_groups and the first min(cap, n) of them in out. */
+mpc_status mpc_plan_get_groups(mpc_plan_t plan, mpc_group_info* out, int32_t cap,
+                               int32_t* n_groups);
+
+/* Autotuner: for every group, time each candidate launch configuration (the
+ * register-resident kernels where the group has them; the generic kernels
+ * with 256, 128 and 64 threads per workgroup) over `reps` cold solves of
+ * that group's agents on `stream`, and keep the fastest.  Synchronous.
+ * The batch's warm_start is ignored.  Afterwards the resident state is
+ * undefined (the next solve must be cold) and a captured step is dropped. */
+mpc_status mpc_plan_autotune(mpc_plan_t plan, const mpc_problem_batch* batch, int32_t reps,
+                             void* stream);
+
+/* Capture one control step into a HIP graph held by the plan: mpc_solve on
+ * `batch` (with its warm_start flag) and, if x0_next is not NULL,
+ * mpc_advance_state with `noise` and x0_next.  The graph records the pointer
+ * values of batch, noise and x0_next: every replay reads the memory they
+ * point to at replay time.  Capture runs on a stream of the plan's own and
+ * launches nothing.  A new capture replaces the previous one. */
+mpc_status mpc_plan_capture(mpc_plan_t plan, const mpc_problem_batch* batch, const void* noise,
+                            void* x0_next);
+
+/* Launch the captured step on `stream` (stream-ordered).  NOT_READY if no
+ * step has been captured. */
+mpc_status mpc_plan_replay(mpc_plan_t plan, void* stream);
 
 /* Thread-local description of the last error returned on this thread. */
 const char* mpc_last_error(void);

@@ -9,15 +9,19 @@
 
 namespace mpc {
 
-// True if the register-resident kernels have an instantiation for this uniform shape.
+// True if the register-resident kernels have an instantiation for this shape.
 bool fused_supported(int N, int nx, int nu, int n_feet);
 // Threads per workgroup and dynamic LDS bytes of the iteration kernel for the shape.
 void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds);
-// Floats of operator workspace the two kernels exchange through HBM.
-size_t fused_workspace_floats(int nx, int nu, int n_agents);
-// phase_mask: 1 = factor kernel, 2 = iteration kernel (3 = both).
-hipError_t fused_solve_f32(const AgentDesc* d_desc, int n_agents, int N, int nx, int nu,
-                           int n_feet, Inputs<float> in, SolverConsts sc, int iters, int warm,
-                           State<float> st, float* ws, hipStream_t stream, int phase_mask);
+// Floats of operator workspace one agent of this shape class needs.
+size_t fused_agent_floats(int nx, int nu);
+// Raise the dynamic-LDS limits of every register-resident kernel (once per device).
+hipError_t fused_set_limits();
+// Launch for the n_launch agents list[0..n_launch) (all of one shape class and
+// horizon N).  phase_mask: 1 = factor kernel, 2 = iteration kernel.
+hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
+                           int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
+                           int warm, State<float> st, float* fws, hipStream_t stream,
+                           int phase_mask);
 
 }  // namespace mpc

@@ -148,13 +148,13 @@ constexpr int riccati_lds_bytes() {
 
 template <int NX, int NU>
 __global__ void __launch_bounds__(64 * kFactorWaves)
-k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, SolverConsts sc,
-          float* __restrict__ opws, float* __restrict__ sws, int32_t* __restrict__ status) {
+k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+          Inputs<float> in, SolverConsts sc, float* __restrict__ fws, int32_t* __restrict__ status) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NXT = S::NXT, NUT = S::NUT;
   constexpr int LX = S::LX, LU = S::LU, SLOTS = S::SLOTS;
-  const int agent = blockIdx.x;
-  if (agent >= n_agents) return;
+  if ((int)blockIdx.x >= n_launch) return;
+  const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -185,8 +185,8 @@ k_riccati(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in, So
   const uint8_t* stance = in.st + d.ost;
   const float muf = in.mu[agent];
   const double mu = (double)muf;
-  float* ops = opws + (int64_t)agent * kMaxStages * SLOTS * 64;
-  float* sk_out = sws + (int64_t)agent * kMaxStages * NXP;
+  float* ops = fws + d.ofw;                       // [stage][slot][lane]
+  float* sk_out = ops + (int64_t)kMaxStages * SLOTS * 64;  // [stage][NXP]
 
   for (int i = tid; i < riccati_lds_bytes<NX, NU>() / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
@@ -466,13 +466,13 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
 
 template <int NX, int NU>
 __global__ void __launch_bounds__(64 * kMaxStages)
-k_admm_resident(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> in,
-                SolverConsts sc, int iters, int warm, const float* __restrict__ opws,
-                const float* __restrict__ sws, State<float> st) {
+k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+                Inputs<float> in, SolverConsts sc, int iters, int warm,
+                const float* __restrict__ fws, State<float> st) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS;
-  const int agent = blockIdx.x;
-  if (agent >= n_agents) return;
+  if ((int)blockIdx.x >= n_launch) return;
+  const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -526,7 +526,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> 
   // this wavefront's stage operators: coalesced loads into registers
   float Acl[RB][RB], Km[CB][RB], Bm[RB][CB], Hm[CB][CB];
   {
-    const float* src = opws + ((int64_t)agent * kMaxStages + w) * SLOTS * 64 + lane;
+    const float* src = fws + d.ofw + (int64_t)w * SLOTS * 64 + lane;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -551,7 +551,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> 
   // per-agent vectors into LDS (padding zero)
   for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
-  const float* sk = sws + (int64_t)agent * kMaxStages * NXP;
+  const float* sk = fws + d.ofw + (int64_t)kMaxStages * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
   for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
   for (int i = tid; i < NX; i += nt) {
@@ -792,30 +792,35 @@ k_admm_resident(const AgentDesc* __restrict__ desc, int n_agents, Inputs<float> 
 }
 
 template <int NX, int NU>
-hipError_t launch_pair(const AgentDesc* d_desc, int n_agents, int N, int M, Inputs<float> in,
-                       SolverConsts sc, int iters, int warm, State<float> st, float* opws,
-                       float* sws, hipStream_t stream, int phase_mask) {
+hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int M,
+                       Inputs<float> in, SolverConsts sc, int iters, int warm, State<float> st,
+                       float* fws, hipStream_t stream, int phase_mask) {
+  if (n_launch <= 0) return hipSuccess;
   const int lf = riccati_lds_bytes<NX, NU>();
   const int li = iter_lds_layout<NX, NU>(N, M).total;
   if (phase_mask & 1) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lf);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_riccati<NX, NU>), dim3(n_agents), dim3(64 * kFactorWaves), lf, stream,
-                       d_desc, n_agents, in, sc, opws, sws, st.status);
-    e = hipGetLastError();
+    hipLaunchKernelGGL((k_riccati<NX, NU>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
+                       d_desc, list, n_launch, in, sc, fws, st.status);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (phase_mask & 2) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, li);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_agents), dim3(64 * N), li, stream,
-                       d_desc, n_agents, in, sc, iters, warm, opws, sws, st);
-    e = hipGetLastError();
+    hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_launch), dim3(64 * N), li, stream,
+                       d_desc, list, n_launch, in, sc, iters, warm, fws, st);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int NX, int NU>
+hipError_t set_limits() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     riccati_lds_bytes<NX, NU>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 }  // namespace
@@ -835,25 +840,28 @@ void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t*
   (void)nu;
 }
 
-size_t fused_workspace_floats(int nx, int nu, int n_agents) {
-  const int slots = (nx == 48) ? FS<48, 30>::SLOTS : FS<36, 24>::SLOTS;
-  const int nxp = (nx == 48) ? FS<48, 30>::NXP : FS<36, 24>::NXP;
+size_t fused_agent_floats(int nx, int nu) {
   (void)nu;
-  return (size_t)n_agents * kMaxStages * ((size_t)slots * 64 + nxp);
+  if (nx == 48) return (size_t)kMaxStages * (FS<48, 30>::SLOTS * 64 + FS<48, 30>::NXP);
+  return (size_t)kMaxStages * (FS<36, 24>::SLOTS * 64 + FS<36, 24>::NXP);
 }
 
-hipError_t fused_solve_f32(const AgentDesc* d_desc, int n_agents, int N, int nx, int nu,
-                           int n_feet, Inputs<float> in, SolverConsts sc, int iters, int warm,
-                           State<float> st, float* ws, hipStream_t stream, int phase_mask) {
+hipError_t fused_set_limits() {
+  hipError_t e = set_limits<48, 30>();
+  if (e != hipSuccess) return e;
+  return set_limits<36, 24>();
+}
+
+hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
+                           int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
+                           int warm, State<float> st, float* fws, hipStream_t stream,
+                           int phase_mask) {
   const int m = nu + 4 * n_feet;
-  const int slots = (nx == 48) ? FS<48, 30>::SLOTS : FS<36, 24>::SLOTS;
-  float* opws = ws;
-  float* sws = ws + (size_t)n_agents * kMaxStages * slots * 64;
   if (nx == 48 && nu == 30)
-    return launch_pair<48, 30>(d_desc, n_agents, N, m, in, sc, iters, warm, st, opws, sws, stream,
+    return launch_pair<48, 30>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
                                phase_mask);
   if (nx == 36 && nu == 24)
-    return launch_pair<36, 24>(d_desc, n_agents, N, m, in, sc, iters, warm, st, opws, sws, stream,
+    return launch_pair<36, 24>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
                                phase_mask);
   return hipErrorInvalidValue;
 }

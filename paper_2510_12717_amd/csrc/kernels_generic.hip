@@ -32,10 +32,10 @@ __device__ inline bool finite_all(const T* p, int64_t n, int tid, int nt) {
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverConsts sc,
-               T* __restrict__ ws, int32_t* __restrict__ status) {
-  const int a = blockIdx.x;
-  if (a >= n_agents) return;
+k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+               Inputs<T> in, SolverConsts sc, T* __restrict__ ws, int32_t* __restrict__ status) {
+  if ((int)blockIdx.x >= n_launch) return;
+  const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -238,10 +238,10 @@ k_setup_factor(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, S
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_admm(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverConsts sc, int iters,
-       int warm, const T* __restrict__ ws, State<T> st) {
-  const int a = blockIdx.x;
-  if (a >= n_agents) return;
+k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+       Inputs<T> in, SolverConsts sc, int iters, int warm, const T* __restrict__ ws, State<T> st) {
+  if ((int)blockIdx.x >= n_launch) return;
+  const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -479,10 +479,10 @@ __device__ inline double block_sum(double v, double* red) {
 // the adjoint sweep lambda_N = Q(x_N - r_N), lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_residual(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, SolverConsts sc,
-           State<T> st) {
-  const int a = blockIdx.x;
-  if (a >= n_agents) return;
+k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+           Inputs<T> in, SolverConsts sc, State<T> st) {
+  if ((int)blockIdx.x >= n_launch) return;
+  const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -598,10 +598,10 @@ k_residual(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, Solve
 
 template <typename T>
 __global__ void __launch_bounds__(64)
-k_advance(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, const T* __restrict__ u,
-          const T* __restrict__ noise, T* __restrict__ x0n) {
-  const int a = blockIdx.x;
-  if (a >= n_agents) return;
+k_advance(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+          Inputs<T> in, const T* __restrict__ u, const T* __restrict__ noise, T* __restrict__ x0n) {
+  if ((int)blockIdx.x >= n_launch) return;
+  const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[a];
   const int nx = d.nx, nu = d.nu;
   const T* A0 = in.A + d.oA;
@@ -626,36 +626,40 @@ k_advance(const AgentDesc* __restrict__ desc, int n_agents, Inputs<T> in, const 
 }
 
 template <typename T>
-hipError_t launch_generic_factor(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
-                                 SolverConsts sc, T* ws, int32_t* status, size_t lds,
-                                 hipStream_t stream) {
-  hipLaunchKernelGGL(k_setup_factor<T>, dim3(n_agents), dim3(256), lds, stream, d_desc, n_agents,
-                     in, sc, ws, status);
+hipError_t launch_generic_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch,
+                                 Inputs<T> in, SolverConsts sc, T* ws, int32_t* status, size_t lds,
+                                 int threads, hipStream_t stream) {
+  if (n_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_setup_factor<T>, dim3(n_launch), dim3(threads), lds, stream, d_desc, list,
+                     n_launch, in, sc, ws, status);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_generic_admm(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
-                               SolverConsts sc, int iters, int warm, const T* ws, State<T> st,
-                               size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL(k_admm<T>, dim3(n_agents), dim3(256), lds, stream, d_desc, n_agents, in, sc,
-                     iters, warm, ws, st);
+hipError_t launch_generic_admm(const AgentDesc* d_desc, const int32_t* list, int n_launch,
+                               Inputs<T> in, SolverConsts sc, int iters, int warm, const T* ws,
+                               State<T> st, size_t lds, int threads, hipStream_t stream) {
+  if (n_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_admm<T>, dim3(n_launch), dim3(threads), lds, stream, d_desc, list, n_launch,
+                     in, sc, iters, warm, ws, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_residual(const AgentDesc* d_desc, int n_agents, Inputs<T> in, SolverConsts sc,
-                           State<T> st, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL(k_residual<T>, dim3(n_agents), dim3(256), lds, stream, d_desc, n_agents, in,
-                     sc, st);
+hipError_t launch_residual(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
+                           SolverConsts sc, State<T> st, size_t lds, hipStream_t stream) {
+  if (n_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual<T>, dim3(n_launch), dim3(256), lds, stream, d_desc, list,
+                     n_launch, in, sc, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_advance(const AgentDesc* d_desc, int n_agents, Inputs<T> in, const T* u,
-                          const T* noise, T* x0_next, hipStream_t stream) {
-  hipLaunchKernelGGL(k_advance<T>, dim3(n_agents), dim3(64), 0, stream, d_desc, n_agents, in, u,
-                     noise, x0_next);
+hipError_t launch_advance(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
+                          const T* u, const T* noise, T* x0_next, hipStream_t stream) {
+  if (n_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_advance<T>, dim3(n_launch), dim3(64), 0, stream, d_desc, list, n_launch,
+                     in, u, noise, x0_next);
   return hipGetLastError();
 }
 
@@ -675,15 +679,17 @@ hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds
   return e;
 }
 
-#define MPC_INSTANTIATE(T)                                                                         \
-  template hipError_t launch_generic_factor<T>(const AgentDesc*, int, Inputs<T>, SolverConsts, T*, \
-                                               int32_t*, size_t, hipStream_t);                     \
-  template hipError_t launch_generic_admm<T>(const AgentDesc*, int, Inputs<T>, SolverConsts, int,  \
-                                             int, const T*, State<T>, size_t, hipStream_t);        \
-  template hipError_t launch_residual<T>(const AgentDesc*, int, Inputs<T>, SolverConsts, State<T>, \
-                                         size_t, hipStream_t);                                     \
-  template hipError_t launch_advance<T>(const AgentDesc*, int, Inputs<T>, const T*, const T*, T*,  \
-                                        hipStream_t);
+#define MPC_INSTANTIATE(T)                                                                        \
+  template hipError_t launch_generic_factor<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,  \
+                                               SolverConsts, T*, int32_t*, size_t, int,           \
+                                               hipStream_t);                                      \
+  template hipError_t launch_generic_admm<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,    \
+                                             SolverConsts, int, int, const T*, State<T>, size_t,  \
+                                             int, hipStream_t);                                   \
+  template hipError_t launch_residual<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,        \
+                                         SolverConsts, State<T>, size_t, hipStream_t);            \
+  template hipError_t launch_advance<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,         \
+                                        const T*, const T*, T*, hipStream_t);
 MPC_INSTANTIATE(float)
 MPC_INSTANTIATE(double)
 

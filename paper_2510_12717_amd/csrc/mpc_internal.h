@@ -13,7 +13,8 @@ struct AgentDesc {
   int32_t N, nx, nu, n_tau, n_feet, foot_dim, m, pad;
   int64_t oA, oB, oc, oq, orr, oxr, ox0, otau, ost;
   int64_t ox, ou, oz;
-  int64_t ows;
+  int64_t ows;  // generic-kernel factor workspace (elements of the io type)
+  int64_t ofw;  // register-resident workspace (floats), -1 if the agent has none
 };
 
 struct SolverConsts {
@@ -55,20 +56,21 @@ inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz) {
 // Raise the dynamic-LDS limit of the generic kernels to what a plan needs.
 hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds_res);
 
-// Launchers (generic kernels, one workgroup per agent).
+// Launchers (generic kernels, one workgroup per agent).  list (nullable) maps
+// workgroup i to agent list[i]; n_launch workgroups are launched.
 template <typename T>
-hipError_t launch_generic_factor(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
-                                 SolverConsts sc, T* ws, int32_t* status, size_t lds,
-                                 hipStream_t stream);
+hipError_t launch_generic_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch,
+                                 Inputs<T> in, SolverConsts sc, T* ws, int32_t* status, size_t lds,
+                                 int threads, hipStream_t stream);
 template <typename T>
-hipError_t launch_generic_admm(const AgentDesc* d_desc, int n_agents, Inputs<T> in,
-                               SolverConsts sc, int iters, int warm, const T* ws, State<T> st,
-                               size_t lds, hipStream_t stream);
+hipError_t launch_generic_admm(const AgentDesc* d_desc, const int32_t* list, int n_launch,
+                               Inputs<T> in, SolverConsts sc, int iters, int warm, const T* ws,
+                               State<T> st, size_t lds, int threads, hipStream_t stream);
 template <typename T>
-hipError_t launch_residual(const AgentDesc* d_desc, int n_agents, Inputs<T> in, SolverConsts sc,
-                           State<T> st, size_t lds, hipStream_t stream);
+hipError_t launch_residual(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
+                           SolverConsts sc, State<T> st, size_t lds, hipStream_t stream);
 template <typename T>
-hipError_t launch_advance(const AgentDesc* d_desc, int n_agents, Inputs<T> in, const T* u,
-                          const T* noise, T* x0_next, hipStream_t stream);
+hipError_t launch_advance(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
+                          const T* u, const T* noise, T* x0_next, hipStream_t stream);
 
 }  // namespace mpc

@@ -2,10 +2,13 @@
 // validation, device workspace, kernel dispatch, solution export, timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mpc.h"
@@ -32,6 +35,22 @@ mpc_status fail(mpc_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kPhases = 3;
+constexpr int kMaxAuxStreams = 3;  // plus the caller's stream: four hardware queues
+
+// A launch group: agents of one shape class (and, for the register-resident
+// kernels, one horizon) solved by one kernel family with one launch shape.
+struct Group {
+  int family = 1;          // 1 generic, 2 register-resident
+  bool fused_ok = false;   // register-resident kernels have an instantiation for it
+  int N = 0, nx = 0, nu = 0, n_feet = 0;  // N: largest horizon in the group
+  int count = 0;
+  int64_t list_off = 0;    // agents d_list[list_off .. list_off + count)
+  int gthreads = 256;      // generic workgroup size
+  size_t lds_factor = 0, lds_admm = 0;
+  int fthreads = 0;        // register-resident iteration-kernel workgroup size
+  size_t flds = 0;
+  double work = 0;         // relative cost used to order launches
+};
 
 }  // namespace
 
@@ -52,8 +71,20 @@ struct mpc_plan_s {
   int32_t* d_status = nullptr;
   bool solved = false;
   size_t lds_factor = 0, lds_admm = 0, lds_res = 0;
-  int fused_threads = 0;
-  size_t fused_lds = 0;
+  // launch groups
+  std::vector<Group> groups;
+  std::vector<int32_t> hlist;
+  int32_t* d_list = nullptr;
+  float* d_fws = nullptr;
+  int64_t nFWS = 0;
+  std::vector<hipStream_t> aux;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  // captured step
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool capturing = false;
   // timing
   bool timing = false;
   hipStream_t last_stream = nullptr;
@@ -97,7 +128,15 @@ extern "C" const char* mpc_version(void) { return "mpc-mi355x 0.1.0 (gfx950)"; }
 
 static void free_plan(mpc_plan_s* p) {
   if (!p) return;
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  for (auto st : p->aux) hipStreamDestroy(st);
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  for (auto e : p->ev_join) hipEventDestroy(e);
   hipFree(p->d_desc);
+  hipFree(p->d_list);
+  hipFree(p->d_fws);
   hipFree(p->d_ws);
   hipFree(p->d_x);
   hipFree(p->d_u);
@@ -146,10 +185,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   AgentDesc cur{};
   int64_t oA = 0, oB = 0, oc = 0, oq = 0, orr = 0, oxr = 0, ox0 = 0, otau = 0, ost = 0, ox = 0,
           ou = 0, oz = 0, ows = 0;
-  bool uniform = true;
   for (int a = 0; a < p->n; ++a) {
     const mpc_shape& s = p->shapes[a];
-    if (a > 0 && memcmp(&s, &p->shapes[0], sizeof(s)) != 0) uniform = false;
     cur.N = s.N;
     cur.nx = s.nx;
     cur.nu = s.nu;
@@ -160,6 +197,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     cur.oA = oA; cur.oB = oB; cur.oc = oc; cur.oq = oq; cur.orr = orr; cur.oxr = oxr;
     cur.ox0 = ox0; cur.otau = otau; cur.ost = ost; cur.ox = ox; cur.ou = ou; cur.oz = oz;
     cur.ows = ows;
+    cur.ofw = -1;
     p->hdesc[a] = cur;
     oA += (int64_t)s.N * s.nx * s.nx;
     oB += (int64_t)s.N * s.nx * s.nu;
@@ -187,17 +225,63 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz);
   p->lds_res = sizeof(double) * (size_t)(p->maxN + 1) * p->maxnx;
 
-  // Kernel family: the fused single-launch kernel serves uniform FP32 batches
-  // of shapes it was built for; everything else takes the generic kernels.
-  const bool fused_ok = desc->precision == MPC_FP32 && uniform &&
-                        fused_supported(p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu,
-                                        p->shapes[0].n_feet);
-  if (desc->kernel == 2 && !fused_ok) {
-    delete p;
-    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "fused kernel requested for a batch it does not support");
+  // Launch groups.  FP32 agents whose shape has a register-resident
+  // instantiation are grouped per (shape class, horizon) and take those
+  // kernels; every other agent is grouped per shape class and takes the
+  // generic kernels, sized for the group's longest horizon.
+  const bool mixed = desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE;
+  {
+    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
+    for (int a = 0; a < p->n; ++a) {
+      const mpc_shape& s = p->shapes[a];
+      const bool fok = desc->precision == MPC_FP32 && fused_supported(s.N, s.nx, s.nu, s.n_feet);
+      if (desc->kernel == 2 && !fok) {
+        delete p;
+        return fail(MPC_ERR_UNSUPPORTED_SHAPE,
+                    "register-resident kernels requested for an agent they do not support");
+      }
+      const bool use_fused = fok && desc->kernel != 1 && !mixed;
+      buckets[std::make_tuple(use_fused ? 2 : 1, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim,
+                              use_fused ? s.N : 0)]
+          .push_back(a);
+    }
+    for (auto& kv : buckets) {
+      Group g;
+      g.family = std::get<0>(kv.first);
+      g.fused_ok = g.family == 2;
+      std::vector<int32_t>& ag = kv.second;
+      // longest horizon first so the tail of a generic launch is short
+      std::stable_sort(ag.begin(), ag.end(),
+                       [&](int32_t x, int32_t y) { return p->shapes[x].N > p->shapes[y].N; });
+      const mpc_shape& s0 = p->shapes[ag[0]];
+      g.N = s0.N;
+      g.nx = s0.nx;
+      g.nu = s0.nu;
+      g.n_feet = s0.n_feet;
+      g.count = (int)ag.size();
+      g.list_off = (int64_t)p->hlist.size();
+      const int m = s0.nu + 4 * s0.n_feet;
+      g.lds_factor = generic_factor_lds(s0.nx, s0.nu, p->esz);
+      g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz);
+      if (g.fused_ok) fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
+      for (int32_t a : ag) g.work += (double)p->shapes[a].N * (s0.nx + s0.nu) * (s0.nx + s0.nu);
+      p->hlist.insert(p->hlist.end(), ag.begin(), ag.end());
+      p->groups.push_back(g);
+    }
+    std::stable_sort(p->groups.begin(), p->groups.end(),
+                     [](const Group& x, const Group& y) { return x.work > y.work; });
   }
-  p->kernel = (desc->kernel == 1 || !fused_ok) ? 1 : 2;
-  if (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE) p->kernel = 1;
+  // register-resident workspace for every agent of a group that may use it
+  for (const Group& g : p->groups) {
+    if (!g.fused_ok) continue;
+    const int64_t per = (int64_t)fused_agent_floats(g.nx, g.nu);
+    for (int i = 0; i < g.count; ++i) {
+      p->hdesc[p->hlist[g.list_off + i]].ofw = p->nFWS;
+      p->nFWS += per;
+    }
+  }
+  p->kernel = 0;
+  for (const Group& g : p->groups) p->kernel |= g.family;  // 1, 2 or 3 (both)
 
   hipError_t e = hipSetDevice(desc->device);
   if (e != hipSuccess) {
@@ -211,21 +295,18 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     return fail(MPC_ERR_UNSUPPORTED_SHAPE, "shapes need more LDS than the device offers");
   }
   e = generic_set_lds_limits(p->lds_factor, p->lds_admm, p->lds_res);
+  if (e == hipSuccess && p->nFWS > 0) e = fused_set_limits();
   if (e != hipSuccess) {
     delete p;
     return fail(MPC_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
-  if (p->kernel == 2) {
-    fused_launch_shape(p->shapes[0].N, p->shapes[0].nx, p->shapes[0].nu, p->shapes[0].n_feet,
-                       &p->fused_threads, &p->fused_lds);
-    // the register-resident kernels exchange operators through their own workspace
-    p->nWS = (int64_t)fused_workspace_floats(p->shapes[0].nx, p->shapes[0].nu, p->n);
-  }
   auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
     return hipMalloc(ptr, bytes ? bytes : 16);
   };
-  hipError_t errs[9] = {
+  hipError_t errs[11] = {
       alloc((void**)&p->d_desc, sizeof(AgentDesc) * p->n),
+      alloc((void**)&p->d_list, sizeof(int32_t) * p->hlist.size()),
+      alloc((void**)&p->d_fws, sizeof(float) * (size_t)p->nFWS),
       alloc(&p->d_ws, p->esz * (size_t)p->nWS),
       alloc(&p->d_x, p->esz * (size_t)p->nX),
       alloc(&p->d_u, p->esz * (size_t)p->nU),
@@ -243,7 +324,20 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     }
   }
   e = hipMemcpy(p->d_desc, p->hdesc.data(), sizeof(AgentDesc) * p->n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_list, p->hlist.data(), sizeof(int32_t) * p->hlist.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int32_t) * p->n);
+  // concurrent streams for the launch groups (default priority)
+  const int naux = std::min<int>((int)p->groups.size() - 1, kMaxAuxStreams);
+  if (e == hipSuccess && naux > 0) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+  for (int i = 0; i < naux && e == hipSuccess; ++i) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) p->aux.push_back(st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) p->ev_join.push_back(ev);
+  }
   if (e != hipSuccess) {
     free_plan(p);
     return fail(MPC_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
@@ -326,54 +420,85 @@ struct PhaseTimer {
   hipStream_t s;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   PhaseTimer(mpc_plan_s* p_, int ph, hipStream_t s_) : p(p_), phase(ph), s(s_) {
-    if (p->timing) {
+    if (p->timing && !p->capturing) {
       e0 = get_event(p);
       e1 = get_event(p);
       hipEventRecord(e0, s);
     }
   }
   ~PhaseTimer() {
-    if (p->timing) {
+    if (e0) {
       hipEventRecord(e1, s);
       p->pending.push_back({phase, {e0, e1}});
     }
   }
 };
 
+// Factor and iteration launches of one group on stream s.
 template <typename T>
-static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s) {
-  Inputs<T> in = make_inputs<T>(b);
-  State<T> st = make_state<T>(p);
-  SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale, p->desc.rho_min};
-  if (p->kernel == 2) {
-    const mpc_shape& sh = p->shapes[0];
+static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_batch* b,
+                            hipStream_t s, int warm) {
+  const SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
+                        p->desc.rho_min};
+  const int32_t* list = p->d_list + g.list_off;
+  if (g.family == 2) {
     {
       PhaseTimer t(p, 0, s);
-      HIP_TRY(fused_solve_f32(p->d_desc, p->n, sh.N, sh.nx, sh.nu, sh.n_feet, make_inputs<float>(b),
-                              sc, p->desc.admm_iters, b->warm_start, make_state<float>(p),
-                              (float*)p->d_ws, s, 1));
+      HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
+                              make_inputs<float>(b), sc, p->desc.admm_iters, warm,
+                              make_state<float>(p), p->d_fws, s, 1));
     }
     {
       PhaseTimer t(p, 1, s);
-      HIP_TRY(fused_solve_f32(p->d_desc, p->n, sh.N, sh.nx, sh.nu, sh.n_feet, make_inputs<float>(b),
-                              sc, p->desc.admm_iters, b->warm_start, make_state<float>(p),
-                              (float*)p->d_ws, s, 2));
+      HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
+                              make_inputs<float>(b), sc, p->desc.admm_iters, warm,
+                              make_state<float>(p), p->d_fws, s, 2));
     }
   } else {
+    const Inputs<T> in = make_inputs<T>(b);
     {
       PhaseTimer t(p, 0, s);
-      HIP_TRY(launch_generic_factor<T>(p->d_desc, p->n, in, sc, (T*)p->d_ws, p->d_status,
-                                       p->lds_factor, s));
+      HIP_TRY(launch_generic_factor<T>(p->d_desc, list, g.count, in, sc, (T*)p->d_ws, p->d_status,
+                                       g.lds_factor, g.gthreads, s));
     }
     {
       PhaseTimer t(p, 1, s);
-      HIP_TRY(launch_generic_admm<T>(p->d_desc, p->n, in, sc, p->desc.admm_iters, b->warm_start,
-                                     (const T*)p->d_ws, st, p->lds_admm, s));
+      HIP_TRY(launch_generic_admm<T>(p->d_desc, list, g.count, in, sc, p->desc.admm_iters, warm,
+                                     (const T*)p->d_ws, make_state<T>(p), g.lds_admm, g.gthreads,
+                                     s));
+    }
+  }
+  return MPC_OK;
+}
+
+// Groups run concurrently: group i goes to stream i mod (1 + aux streams),
+// the first of which is the caller's; the aux streams fork from and join
+// back into the caller's stream, so the solve stays stream-ordered (and
+// captures into one graph).
+template <typename T>
+static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s) {
+  const int ns = 1 + (int)p->aux.size();
+  if (ns > 1) {
+    HIP_TRY(hipEventRecord(p->ev_fork, s));
+    for (hipStream_t a : p->aux) HIP_TRY(hipStreamWaitEvent(a, p->ev_fork, 0));
+  }
+  for (size_t i = 0; i < p->groups.size(); ++i) {
+    const int k = (int)(i % ns);
+    mpc_status r = run_group<T>(p, p->groups[i], b, k == 0 ? s : p->aux[k - 1], b->warm_start);
+    if (r != MPC_OK) return r;
+  }
+  if (ns > 1) {
+    for (size_t k = 0; k < p->aux.size(); ++k) {
+      HIP_TRY(hipEventRecord(p->ev_join[k], p->aux[k]));
+      HIP_TRY(hipStreamWaitEvent(s, p->ev_join[k], 0));
     }
   }
   {
     PhaseTimer t(p, 2, s);
-    HIP_TRY(launch_residual<T>(p->d_desc, p->n, in, sc, st, p->lds_res, s));
+    const SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
+                          p->desc.rho_min};
+    HIP_TRY(launch_residual<T>(p->d_desc, nullptr, p->n, make_inputs<T>(b), sc, make_state<T>(p),
+                               p->lds_res, s));
   }
   return MPC_OK;
 }
@@ -447,10 +572,10 @@ extern "C" mpc_status mpc_advance_state(mpc_plan_t p, const mpc_problem_batch* b
   HIP_TRY(hipSetDevice(p->desc.device));
   hipStream_t s = (hipStream_t)stream;
   if (p->fp64) {
-    HIP_TRY(launch_advance<double>(p->d_desc, p->n, make_inputs<double>(b), (const double*)p->d_u,
+    HIP_TRY(launch_advance<double>(p->d_desc, nullptr, p->n, make_inputs<double>(b), (const double*)p->d_u,
                                    (const double*)noise, (double*)x0_next, s));
   } else {
-    HIP_TRY(launch_advance<float>(p->d_desc, p->n, make_inputs<float>(b), (const float*)p->d_u,
+    HIP_TRY(launch_advance<float>(p->d_desc, nullptr, p->n, make_inputs<float>(b), (const float*)p->d_u,
                                   (const float*)noise, (float*)x0_next, s));
   }
   return MPC_OK;
@@ -489,9 +614,10 @@ extern "C" mpc_status mpc_plan_get_timing(mpc_plan_t p, double* ms, int64_t* lau
 extern "C" mpc_status mpc_plan_get_config(mpc_plan_t p, int32_t* kernel, int32_t* threads,
                                           int32_t* lds) {
   if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  const Group& g = p->groups[0];
   if (kernel) *kernel = p->kernel;
-  if (threads) *threads = p->kernel == 2 ? p->fused_threads : 256;
-  if (lds) *lds = (int32_t)(p->kernel == 2 ? p->fused_lds : std::max(p->lds_factor, p->lds_admm));
+  if (threads) *threads = g.family == 2 ? g.fthreads : g.gthreads;
+  if (lds) *lds = (int32_t)(g.family == 2 ? g.flds : std::max(g.lds_factor, g.lds_admm));
   return MPC_OK;
 }
 
@@ -499,7 +625,12 @@ extern "C" mpc_status mpc_plan_export_factor(mpc_plan_t p, int32_t agent, void* 
                                              void* Hinv, void* sv, void* stream) {
   if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
   if (agent < 0 || agent >= p->n) return fail(MPC_ERR_INVALID_ARG, "agent index out of range");
-  if (p->kernel != 1) return fail(MPC_ERR_UNSUPPORTED_SHAPE, "the fused kernel keeps its factor on chip");
+  if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
+  for (const Group& g : p->groups)
+    for (int i = 0; i < g.count; ++i)
+      if (p->hlist[g.list_off + i] == agent && g.family != 1)
+        return fail(MPC_ERR_UNSUPPORTED_SHAPE,
+                    "this agent's operators are kept in the register-resident layout");
   if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
   HIP_TRY(hipSetDevice(p->desc.device));
   hipStream_t s = (hipStream_t)stream;
@@ -512,5 +643,149 @@ extern "C" mpc_status mpc_plan_export_factor(mpc_plan_t p, int32_t agent, void* 
   if (Acl) HIP_TRY(hipMemcpyAsync(Acl, base + nK * e, nA * e, hipMemcpyDeviceToDevice, s));
   if (Hinv) HIP_TRY(hipMemcpyAsync(Hinv, base + (nK + nA) * e, nH * e, hipMemcpyDeviceToDevice, s));
   if (sv) HIP_TRY(hipMemcpyAsync(sv, base + (nK + nA + nH) * e, nS * e, hipMemcpyDeviceToDevice, s));
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_get_groups(mpc_plan_t p, mpc_group_info* out, int32_t cap,
+                                          int32_t* n_groups) {
+  if (!p || !n_groups || (cap > 0 && !out)) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  *n_groups = (int32_t)p->groups.size();
+  for (int i = 0; i < (int)p->groups.size() && i < cap; ++i) {
+    const Group& g = p->groups[i];
+    mpc_group_info& o = out[i];
+    o.family = g.family;
+    o.N = g.N;
+    o.nx = g.nx;
+    o.nu = g.nu;
+    o.n_feet = g.n_feet;
+    o.n_agents = g.count;
+    o.threads = g.family == 2 ? g.fthreads : g.gthreads;
+    o.lds_bytes = (int32_t)(g.family == 2 ? g.flds : std::max(g.lds_factor, g.lds_admm));
+  }
+  return MPC_OK;
+}
+
+// Times every candidate launch configuration of every group on the caller's
+// stream (cold solves of that group only) and keeps the fastest.
+extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b, int32_t reps,
+                                        void* stream) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  if (reps < 1 || reps > 1000) return fail(MPC_ERR_INVALID_ARG, "reps must be in 1..1000");
+  mpc_problem_batch cold = b ? *b : mpc_problem_batch{};
+  cold.warm_start = 0;
+  mpc_status cs = check_batch(p, &cold);
+  if (cs != MPC_OK) return cs;
+  if (p->desc.precision != MPC_FP32 && p->desc.precision != MPC_FP64)
+    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "mixed-precision plans are not available in this build");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const bool timing = p->timing;
+  p->timing = false;
+  mpc_status r = MPC_OK;
+  for (Group& g : p->groups) {
+    struct Cand { int family, threads; };
+    std::vector<Cand> cands;
+    if (g.fused_ok) cands.push_back({2, g.fthreads});
+    for (int t : {256, 128, 64}) cands.push_back({1, t});
+    float best = INFINITY;
+    Cand pick = {g.family, g.family == 2 ? g.fthreads : g.gthreads};
+    for (const Cand& c : cands) {
+      Group trial = g;
+      trial.family = c.family;
+      if (c.family == 1) trial.gthreads = c.threads;
+      r = p->fp64 ? run_group<double>(p, trial, &cold, s, 0) : run_group<float>(p, trial, &cold, s, 0);
+      if (r != MPC_OK) break;
+      hipError_t he = hipEventRecord(e0, s);
+      for (int i = 0; i < reps && he == hipSuccess && r == MPC_OK; ++i)
+        r = p->fp64 ? run_group<double>(p, trial, &cold, s, 0) : run_group<float>(p, trial, &cold, s, 0);
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) r = fail(MPC_ERR_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
+      if (r != MPC_OK) break;
+      if (ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+    if (r != MPC_OK) break;
+    g.family = pick.family;
+    if (pick.family == 1) g.gthreads = pick.threads;
+  }
+  p->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  p->kernel = 0;
+  for (const Group& g : p->groups) p->kernel |= g.family;
+  // the resident iterates are those of partial cold solves now, and a
+  // captured step would launch the old configuration
+  p->solved = false;
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  return r;
+}
+
+extern "C" mpc_status mpc_plan_capture(mpc_plan_t p, const mpc_problem_batch* b, const void* noise,
+                                       void* x0_next) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  mpc_status cs = check_batch(p, b);
+  if (cs != MPC_OK) return cs;
+  if (p->desc.precision != MPC_FP32 && p->desc.precision != MPC_FP64)
+    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "mixed-precision plans are not available in this build");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  p->capturing = true;
+  const bool was_solved = p->solved;
+  mpc_status r = p->fp64 ? solve_impl<double>(p, b, p->cap_stream) : solve_impl<float>(p, b, p->cap_stream);
+  if (r == MPC_OK && x0_next) {
+    if (p->fp64)
+      r = [&]() -> mpc_status {
+        HIP_TRY(launch_advance<double>(p->d_desc, nullptr, p->n, make_inputs<double>(b),
+                                       (const double*)p->d_u, (const double*)noise,
+                                       (double*)x0_next, p->cap_stream));
+        return MPC_OK;
+      }();
+    else
+      r = [&]() -> mpc_status {
+        HIP_TRY(launch_advance<float>(p->d_desc, nullptr, p->n, make_inputs<float>(b),
+                                      (const float*)p->d_u, (const float*)noise, (float*)x0_next,
+                                      p->cap_stream));
+        return MPC_OK;
+      }();
+  }
+  p->capturing = false;
+  p->solved = was_solved;
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(p->cap_stream, &g);
+  if (r != MPC_OK) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
+  if (ee != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(MPC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+  }
+  p->graph = g;
+  HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_replay(mpc_plan_t p, void* stream) {
+  if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
+  if (!p->gexec) return fail(MPC_ERR_NOT_READY, "no captured step on this plan");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  HIP_TRY(hipGraphLaunch(p->gexec, (hipStream_t)stream));
+  p->solved = true;
   return MPC_OK;
 }

@@ -46,6 +46,11 @@ class ProblemBatch(ctypes.Structure):
                [("warm_start", ctypes.c_int32)]
 
 
+class GroupInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("family", "N", "nx", "nu", "n_feet", "n_agents",
+                                              "threads", "lds_bytes")]
+
+
 class Solution(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "x", "u", "z", "y", "objective",
                                                "residuals", "status")]
@@ -55,6 +60,7 @@ class Solution(ctypes.Structure):
 EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_solve",
            "mpc_get_solution", "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
            "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
+           "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture", "mpc_plan_replay",
            "mpc_last_error", "mpc_version")
 
 _lib = None
@@ -81,9 +87,15 @@ def lib():
         L.mpc_plan_get_timing.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
         L.mpc_plan_get_config.argtypes = [V, P(I32), P(I32), P(I32)]
         L.mpc_plan_export_factor.argtypes = [V, I32, V, V, V, V, V]
+        L.mpc_plan_get_groups.argtypes = [V, P(GroupInfo), I32, P(I32)]
+        L.mpc_plan_autotune.argtypes = [V, P(ProblemBatch), I32, V]
+        L.mpc_plan_capture.argtypes = [V, P(ProblemBatch), V, V]
+        L.mpc_plan_replay.argtypes = [V, V]
         for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
                   "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
-                  "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor"):
+                  "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
+                  "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture",
+                  "mpc_plan_replay"):
             getattr(L, f).restype = ctypes.c_int
         L.mpc_last_error.restype = ctypes.c_char_p
         L.mpc_version.restype = ctypes.c_char_p
@@ -220,8 +232,37 @@ class Plan:
         k, t, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().mpc_plan_get_config(self._h, ctypes.byref(k), ctypes.byref(t),
                                          ctypes.byref(l)))
-        return dict(kernel={1: "generic", 2: "fused"}.get(k.value, str(k.value)),
+        return dict(kernel={1: "generic", 2: "fused", 3: "mixed"}.get(k.value, str(k.value)),
                     threads_per_agent=t.value, lds_bytes=l.value)
+
+    def groups(self):
+        """Launch groups: list of dicts (family 'generic' | 'fused', N, nx, nu, n_feet,
+        n_agents, threads, lds_bytes)."""
+        n = ctypes.c_int32()
+        _check(lib().mpc_plan_get_groups(self._h, None, 0, ctypes.byref(n)))
+        arr = (GroupInfo * max(n.value, 1))()
+        _check(lib().mpc_plan_get_groups(self._h, arr, n.value, ctypes.byref(n)))
+        out = []
+        for g in arr[:n.value]:
+            d = {f: getattr(g, f) for f, _ in GroupInfo._fields_}
+            d["family"] = {1: "generic", 2: "fused"}[g.family]
+            out.append(d)
+        return out
+
+    def autotune(self, prob, reps: int = 3, stream=None):
+        b = self._batch(prob, False)
+        _check(lib().mpc_plan_autotune(self._h, ctypes.byref(b), int(reps),
+                                       _stream_handle(stream)))
+        return self.groups()
+
+    def capture(self, prob, warm_start: bool = True, noise=None, x0_next=None):
+        """Capture solve (+ plant step when x0_next is given) into the plan's graph."""
+        b = self._batch(prob, warm_start)
+        self._graph_keep = (prob, noise, x0_next)
+        _check(lib().mpc_plan_capture(self._h, ctypes.byref(b), _ptr(noise), _ptr(x0_next)))
+
+    def replay(self, stream=None):
+        _check(lib().mpc_plan_replay(self._h, _stream_handle(stream)))
 
     def export_factor(self, agent: int, stream=None):
         """(K, A_cl, Hinv, s) of one agent from the last solve (generic kernels only)."""

@@ -71,8 +71,12 @@ typedef enum {
   MPC_FP32 = 1,        /* float io, operators and ADMM iterations; the Riccati    */
                        /* factor runs in double and is rounded to float once, and */
                        /* H_k^{-1} h accumulates in double                        */
-  MPC_BF16_REFINE = 2, /* bf16 block products, fp64 stage Cholesky, refinement    */
-  MPC_FP16_REFINE = 3  /* fp16 block products, fp64 stage Cholesky, refinement    */
+  MPC_BF16_REFINE = 2, /* float io; Riccati block products with bf16 operands on   */
+                       /* the matrix cores (fp32 accumulation), fp64 stage-Hessian */
+                       /* inverse; iterations as MPC_FP32 but rolled out under the */
+                       /* exact dynamics, with up to max_refine_sweeps KKT-residual */
+                       /* refinement sweeps per x-update                            */
+  MPC_FP16_REFINE = 3  /* as MPC_BF16_REFINE with fp16 operands                     */
 } mpc_precision;
 
 /* per-agent numerical status */
@@ -162,8 +166,9 @@ mpc_status mpc_advance_state(mpc_plan_t plan, const mpc_problem_batch* batch, co
 mpc_status mpc_plan_set_timing(mpc_plan_t plan, int32_t enable);
 mpc_status mpc_plan_get_timing(mpc_plan_t plan, double* ms, int64_t* launches);
 
-/* Which kernel families the plan runs (bit 0 generic, bit 1 register-resident:
- * 1, 2 or 3) and the launch shape of its largest launch group. */
+/* Which kernel families the plan runs as a bit mask (1 generic, 2
+ * register-resident, 4 mixed precision) and the launch shape of its largest
+ * launch group. */
 mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* threads_per_agent,
                                int32_t* lds_bytes);
 
@@ -181,7 +186,7 @@ mpc_status mpc_plan_export_factor(mpc_plan_t plan, int32_t agent, void* K, void*
  * launch; groups are spread over up to four streams that fork from and join
  * back into the solve's stream. */
 typedef struct {
-  int32_t family;    /* 1 generic, 2 register-resident                        */
+  int32_t family;    /* 1 generic, 2 register-resident, 4 mixed precision     */
   int32_t N;         /* horizon (longest in the group for generic groups)      */
   int32_t nx, nu, n_feet;
   int32_t n_agents;

@@ -135,6 +135,56 @@ __device__ inline d4 mfma_tile(int ti, int tj, int K, int lane, FA a, FB b) {
   return acc;
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// Product precision of the factor's block products: FP64 (v_mfma_f64_16x16x4f64),
+// or BF16 / FP16 operands with FP32 accumulation (v_mfma_f32_16x16x32_{bf16,f16}).
+enum { kProdF64 = 0, kProdBF16 = 1, kProdF16 = 2 };
+
+// Output row of element v of this lane in a 16x16 tile (column is lane % 16).
+template <int PREC>
+__device__ inline int orow(int lane, int v) {
+  return PREC == kProdF64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+}
+
+// One 16x16 tile of C = op(A) op(B) over K (zero beyond K) in precision PREC.
+// Low precision: lane l feeds A[row l%16][k0 + 8(l/16) ..+7] and
+// B[k0 + 8(l/16) ..+7][col l%16]; operands are rounded to nearest from the
+// LDS doubles, products are exact and accumulate in FP32.
+template <int PREC, class FA, class FB>
+__device__ inline d4 prod_tile(int ti, int tj, int K, int lane, FA a, FB b) {
+  if constexpr (PREC == kProdF64) {
+    return mfma_tile(ti, tj, K, lane, a, b);
+  } else {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int r = lane & 15, g = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      if constexpr (PREC == kProdBF16) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int kk = k0 + 8 * g + i;
+          av[i] = (__bf16)(float)(kk < K ? a(ti * 16 + r, kk) : 0.0);
+          bv[i] = (__bf16)(float)(kk < K ? b(kk, tj * 16 + r) : 0.0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      } else {
+        f16x8 av, bv;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int kk = k0 + 8 * g + i;
+          av[i] = (_Float16)(float)(kk < K ? a(ti * 16 + r, kk) : 0.0);
+          bv[i] = (_Float16)(float)(kk < K ? b(kk, tj * 16 + r) : 0.0);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
+      }
+    }
+    return d4{(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Riccati factor (FP64, MFMA)
 // ------------------------------------------------------------------------------------
@@ -146,7 +196,11 @@ constexpr int riccati_lds_bytes() {
               S::NUT + S::MMAX + S::NXT + 2 * S::NUT) + 16;
 }
 
-template <int NX, int NU>
+// PREC == kProdF64: operators go to the register-resident layout at fws + ofw.
+// Otherwise (mixed precision) they go to the generic per-agent layout at
+// fws + ows: K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx],
+// then l, h, rho [N][m].
+template <int NX, int NU, int PREC>
 __global__ void __launch_bounds__(64 * kFactorWaves)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
           Inputs<float> in, SolverConsts sc, float* __restrict__ fws, int32_t* __restrict__ status) {
@@ -183,10 +237,18 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   const float* r = in.r + d.orr;
   const float* tau = in.tau + d.otau;
   const uint8_t* stance = in.st + d.ost;
-  const float muf = in.mu[agent];
+  const float muf = in.mu[d.omu];
   const double mu = (double)muf;
-  float* ops = fws + d.ofw;                       // [stage][slot][lane]
-  float* sk_out = ops + (int64_t)kMaxStages * SLOTS * 64;  // [stage][NXP]
+  constexpr bool kResident = PREC == kProdF64;
+  float* ops = fws + (kResident ? d.ofw : d.ows);
+  float* sk_out = kResident ? ops + (int64_t)kMaxStages * SLOTS * 64  // [stage][NXP]
+                            : ops + (int64_t)N * (NU * NX + NX * NX + NU * NU);
+  float* gK = ops;
+  float* gAcl = gK + (int64_t)N * NU * NX;
+  float* gHi = gAcl + (int64_t)N * NX * NX;
+  float* gl = sk_out + (int64_t)N * NX;
+  float* gh = gl + (int64_t)N * M;
+  float* grho = gh + (int64_t)N * M;
 
   for (int i = tid; i < riccati_lds_bytes<NX, NU>() / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
@@ -200,7 +262,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   for (int i = tid; i < NU; i += nt) ok &= (bool)isfinite(r[i]);
   for (int i = tid; i < d.n_tau; i += nt) ok &= (bool)isfinite(tau[i]);
   if (in.uref)
-    for (int i = tid; i < N * NU; i += nt) ok &= (bool)isfinite(in.uref[d.ou + i]);
+    for (int i = tid; i < N * NU; i += nt) ok &= (bool)isfinite(in.uref[d.our + i]);
   if (!ok) atomicOr(flag, 1);
   for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma;
   __syncthreads();
@@ -217,6 +279,11 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     for (int i = tid; i < M; i += nt) {
       double lo, hi;
       row_bounds<double, float>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rhok[i]);
+      if (!kResident) {
+        gl[k * M + i] = (float)lo;
+        gh[k * M + i] = (float)hi;
+        grho[k * M + i] = (float)rhok[i];
+      }
     }
     for (int i = tid; i < NX; i += nt) ck[i] = (double)c[(int64_t)k * NX + i];
     __syncthreads();
@@ -228,25 +295,26 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       for (int t = w; t < TB + TA; t += nw) {
         if (t < TB) {
           const int ti = t / (NUT / 16), tj = t % (NUT / 16);
-          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
+          d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
                              [&](int kk, int j) { return Bk[kk * LU + j]; });
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            PB[(ti * 16 + (lane >> 4) + 4 * v) * LU + tj * 16 + (lane & 15)] = acc[v];
+            PB[(ti * 16 + orow<PREC>(lane, v)) * LU + tj * 16 + (lane & 15)] = acc[v];
         } else {
           const int tt = t - TB, ti = tt / (NXT / 16), tj = tt % (NXT / 16);
-          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
+          d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
                              [&](int kk, int j) { return Ak[kk * LX + j]; });
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            PA[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = acc[v];
+            PA[(ti * 16 + orow<PREC>(lane, v)) * LX + tj * 16 + (lane & 15)] = acc[v];
         }
       }
-      for (int i = tid; i < NXP; i += nt) {
+      const int sstride = kResident ? NXP : NX;
+      for (int i = tid; i < sstride; i += nt) {
         double acc = 0.0;
         if (i < NX)
           for (int t = 0; t < NX; ++t) acc += P[i * LX + t] * ck[t];
-        sk_out[k * NXP + i] = (float)acc;
+        sk_out[k * sstride + i] = (float)acc;
       }
     }
     __syncthreads();
@@ -256,20 +324,20 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       for (int t = w; t < TH + TG; t += nw) {
         if (t < TH) {
           const int ti = t / (NUT / 16), tj = t % (NUT / 16);
-          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
+          d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
                              [&](int kk, int j) { return PB[kk * LU + j]; });
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int i = ti * 16 + (lane >> 4) + 4 * v, j = tj * 16 + (lane & 15);
+            const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
             H[i * LU + j] = acc[v] + (i == j ? rdg[i] : 0.0);
           }
         } else {
           const int tt = t - TH, ti = tt / (NXT / 16), tj = tt % (NXT / 16);
-          d4 acc = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
+          d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
                              [&](int kk, int j) { return PA[kk * LX + j]; });
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            G[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = acc[v];
+            G[(ti * 16 + orow<PREC>(lane, v)) * LX + tj * 16 + (lane & 15)] = acc[v];
         }
       }
     }
@@ -359,13 +427,13 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       constexpr int TP = (NXT / 16) * (NXT / 16);
       for (int t = w; t < TP; t += nw) {
         const int ti = t / (NXT / 16), tj = t % (NXT / 16);
-        d4 a1 = mfma_tile(ti, tj, NXT, lane, [&](int i, int kk) { return Ak[kk * LX + i]; },
+        d4 a1 = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return Ak[kk * LX + i]; },
                           [&](int kk, int j) { return PA[kk * LX + j]; });
-        d4 a2 = mfma_tile(ti, tj, NUT, lane, [&](int i, int kk) { return G[kk * LX + i]; },
+        d4 a2 = prod_tile<PREC>(ti, tj, NUT, lane, [&](int i, int kk) { return G[kk * LX + i]; },
                           [&](int kk, int j) { return Kd[kk * LX + j]; });
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = ti * 16 + (lane >> 4) + 4 * v, j = tj * 16 + (lane & 15);
+          const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
           const double qv = (i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0;
           P[i * LX + j] = qv + a1[v] + a2[v];
         }
@@ -385,19 +453,25 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       constexpr int TA = (NXT / 16) * (NXT / 16);
       for (int t = w; t < TA; t += nw) {
         const int ti = t / (NXT / 16), tj = t % (NXT / 16);
-        d4 acc = mfma_tile(ti, tj, NUT, lane, [&](int i, int kk) { return Bk[i * LU + kk]; },
+        d4 acc = prod_tile<PREC>(ti, tj, NUT, lane, [&](int i, int kk) { return Bk[i * LU + kk]; },
                            [&](int kk, int j) { return Kd[kk * LX + j]; });
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = ti * 16 + (lane >> 4) + 4 * v, j = tj * 16 + (lane & 15);
+          const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
           PA[i * LX + j] = Ak[i * LX + j] + acc[v];
         }
       }
     }
     __syncthreads();
-    // stage k's operators, rounded to float, in register-layout order
+    // stage k's operators, rounded to float, in register-layout order (or in
+    // the generic row-major layout for the mixed-precision iterations)
+    if (!kResident) {
+      for (int e = tid; e < NU * NX; e += nt) gK[(int64_t)k * NU * NX + e] = (float)Kd[(e / NX) * LX + e % NX];
+      for (int e = tid; e < NX * NX; e += nt) gAcl[(int64_t)k * NX * NX + e] = (float)PA[(e / NX) * LX + e % NX];
+      for (int e = tid; e < NU * NU; e += nt) gHi[(int64_t)k * NU * NU + e] = (float)H[(e / NU) * LU + e % NU];
+    }
     float* dst = ops + (int64_t)k * SLOTS * 64;
-    for (int e = tid; e < SLOTS * 64; e += nt) {
+    for (int e = tid; kResident && e < SLOTS * 64; e += nt) {
       const int slot = e >> 6, ln = e & 63, a = ln >> 3, b = ln & 7;
       double v = 0.0;
       if (slot < RB * RB) {
@@ -480,7 +554,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   float* X = st.x + d.ox;
   float* U = st.u + d.ou;
   float* Z = st.z + d.oz;
-  float* Y = st.y + d.oz;
+  float* Y = st.y + d.oy;
   if (st.status[agent] != AGENT_OK) {
     for (int i = tid; i < (N + 1) * d.nx; i += nt) X[i] = NAN;
     for (int i = tid; i < N * d.nu; i += nt) U[i] = NAN;
@@ -520,8 +594,8 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   const float* x0 = in.x0 + d.ox0;
   const float* tau = in.tau + d.otau;
   const uint8_t* stance = in.st + d.ost;
-  const float* uref = in.uref ? in.uref + d.ou : nullptr;
-  const double mu = (double)in.mu[agent];
+  const float* uref = in.uref ? in.uref + d.our : nullptr;
+  const double mu = (double)in.mu[d.omu];
 
   // this wavefront's stage operators: coalesced loads into registers
   float Acl[RB][RB], Km[CB][RB], Bm[RB][CB], Hm[CB][CB];
@@ -568,10 +642,11 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
     hid[i] = hi;
     rhod[i] = rr;
   }
-  for (int i = tid; i < N * NU; i += nt) ud[(i / NU) * NUP + i % NU] = warm ? (double)U[i] : 0.0;
+  const bool wm = agent_warm(warm, d);
+  for (int i = tid; i < N * NU; i += nt) ud[(i / NU) * NUP + i % NU] = wm ? (double)U[i] : 0.0;
   for (int i = tid; i < N * M; i += nt) {
-    zd[i] = warm ? (double)Z[i] : 0.0;
-    yd[i] = warm ? (double)Y[i] : 0.0;
+    zd[i] = wm ? (double)Z[i] : 0.0;
+    yd[i] = wm ? (double)Y[i] : 0.0;
   }
   __syncthreads();
 
@@ -799,7 +874,7 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
   const int lf = riccati_lds_bytes<NX, NU>();
   const int li = iter_lds_layout<NX, NU>(N, M).total;
   if (phase_mask & 1) {
-    hipLaunchKernelGGL((k_riccati<NX, NU>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
+    hipLaunchKernelGGL((k_riccati<NX, NU, kProdF64>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
                        d_desc, list, n_launch, in, sc, fws, st.status);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -815,9 +890,15 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
 
 template <int NX, int NU>
 hipError_t set_limits() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF64>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      riccati_lds_bytes<NX, NU>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdBF16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -850,6 +931,35 @@ hipError_t fused_set_limits() {
   hipError_t e = set_limits<48, 30>();
   if (e != hipSuccess) return e;
   return set_limits<36, 24>();
+}
+
+bool mixed_supported(int nx, int nu) { return (nx == 48 && nu == 30) || (nx == 36 && nu == 24); }
+
+hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch, int nx,
+                               int nu, int bf16, Inputs<float> in, SolverConsts sc, float* ws,
+                               int32_t* status, hipStream_t stream) {
+  if (n_launch <= 0) return hipSuccess;
+  const dim3 grid(n_launch), block(64 * kFactorWaves);
+  if (nx == 48 && nu == 30) {
+    const int lf = riccati_lds_bytes<48, 30>();
+    if (bf16)
+      hipLaunchKernelGGL((k_riccati<48, 30, kProdBF16>), grid, block, lf, stream, d_desc, list,
+                         n_launch, in, sc, ws, status);
+    else
+      hipLaunchKernelGGL((k_riccati<48, 30, kProdF16>), grid, block, lf, stream, d_desc, list,
+                         n_launch, in, sc, ws, status);
+  } else if (nx == 36 && nu == 24) {
+    const int lf = riccati_lds_bytes<36, 24>();
+    if (bf16)
+      hipLaunchKernelGGL((k_riccati<36, 24, kProdBF16>), grid, block, lf, stream, d_desc, list,
+                         n_launch, in, sc, ws, status);
+    else
+      hipLaunchKernelGGL((k_riccati<36, 24, kProdF16>), grid, block, lf, stream, d_desc, list,
+                         n_launch, in, sc, ws, status);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,

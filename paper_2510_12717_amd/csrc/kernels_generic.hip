@@ -64,7 +64,7 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
   const T* r = in.r + d.orr;
   const T* tau = in.tau + d.otau;
   const uint8_t* stance = in.st + d.ost;
-  const T mu = in.mu[a];
+  const T mu = in.mu[d.omu];
   T* wK = ws + d.ows;
   T* wAcl = wK + (int64_t)N * nu * nx;
   T* wHi = wAcl + (int64_t)N * nx * nx;
@@ -80,7 +80,7 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
             finite_all(c, (int64_t)N * nx, tid, nt) && finite_all(q, nx, tid, nt) &&
             finite_all(r, nu, tid, nt) && finite_all(in.xr + d.oxr, (int64_t)(N + 1) * nx, tid, nt) &&
             finite_all(in.x0 + d.ox0, nx, tid, nt) && finite_all(tau, d.n_tau, tid, nt) &&
-            (bool)isfinite(mu) && (!in.uref || finite_all(in.uref + d.ou, (int64_t)N * nu, tid, nt));
+            (bool)isfinite(mu) && (!in.uref || finite_all(in.uref + d.our, (int64_t)N * nu, tid, nt));
   if (!ok) atomicOr(&s_flag, 1);
   __syncthreads();
   if (s_flag) {
@@ -236,10 +236,69 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
   if (tid == 0) status[a] = AGENT_OK;
 }
 
+// Block-wide reductions through LDS (blockDim.x <= 256).
+__device__ inline double block_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Rollout under the exact dynamics with gains K:  u_k = K_k x_k + d_k,
+// x_{k+1} = A_k x_k + B_k u_k (+ c_k).  x_0 is x0p (zero if NULL); x_{k+1} is
+// written to Xn[k]; u may alias d (each entry reads only its own d).
+template <typename T, typename V>
+__device__ inline void forward_exact(int N, int nx, int nu, const T* A, const T* B, const T* c,
+                                     const T* wK, const V* d, const V* x0p, V* Xn, V* u, int tid,
+                                     int nt) {
+  for (int k = 0; k < N; ++k) {
+    const V* xk = k == 0 ? x0p : Xn + (k - 1) * nx;
+    for (int j = tid; j < nu; j += nt) {
+      V acc = 0;
+      if (xk) {
+        const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
+        for (int t = 0; t < nx; ++t) acc += (V)Kr[t] * xk[t];
+      }
+      u[k * nu + j] = d[k * nu + j] + acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < nx; i += nt) {
+      V acc = 0;
+      if (xk) {
+        const T* Ar = A + (int64_t)k * nx * nx + i * nx;
+        for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * xk[t];
+      }
+      const T* Br = B + (int64_t)k * nx * nu + i * nu;
+      for (int t = 0; t < nu; ++t) acc += (V)Br[t] * u[k * nu + t];
+      Xn[k * nx + i] = c ? (V)c[(int64_t)k * nx + i] + acc : acc;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-       Inputs<T> in, SolverConsts sc, int iters, int warm, const T* __restrict__ ws, State<T> st) {
+       Inputs<T> in, SolverConsts sc, int iters, int warm, const T* __restrict__ ws, State<T> st,
+       int sweeps, double rtol) {
   if ((int)blockIdx.x >= n_launch) return;
   const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[a];
@@ -248,7 +307,7 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   T* X = st.x + d.ox;
   T* U = st.u + d.ou;
   T* Z = st.z + d.oz;
-  T* Y = st.y + d.oz;
+  T* Y = st.y + d.oy;
   if (st.status[a] != AGENT_OK) {
     const T nan = (T)NAN;
     for (int i = tid; i < (N + 1) * nx; i += nt) X[i] = nan;
@@ -279,6 +338,7 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   V* e = pp + N * nx;                     // N*nx
   V* p = e + N * nx;                      // nx
   V* hv = p + nx;                         // N*nu
+  V* red = hv + N * nu;                   // 256 (refinement stopping test)
 
   const T* A = in.A + d.oA;
   const T* B = in.B + d.oB;
@@ -289,18 +349,21 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   const T* x0 = in.x0 + d.ox0;
   const T* tau = in.tau + d.otau;
   const uint8_t* stance = in.st + d.ost;
-  const T* uref = in.uref ? in.uref + d.ou : nullptr;
-  const V mu = (V)in.mu[a];
+  const T* uref = in.uref ? in.uref + d.our : nullptr;
+  const V mu = (V)in.mu[d.omu];
   const T* wK = ws + d.ows;
   const T* wAcl = wK + (int64_t)N * nu * nx;
   const T* wHi = wAcl + (int64_t)N * nx * nx;
   const T* wS = wHi + (int64_t)N * nu * nu;
+  const T* wrho = wS + (int64_t)N * nx + 2 * (int64_t)N * m;
   const V sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
+  const bool mixed = sweeps >= 0;
 
-  for (int i = tid; i < N * nu; i += nt) u[i] = warm ? (V)U[i] : 0.0;
+  const bool wm = agent_warm(warm, d);
+  for (int i = tid; i < N * nu; i += nt) u[i] = wm ? (V)U[i] : 0.0;
   for (int i = tid; i < N * m; i += nt) {
-    z[i] = warm ? (V)Z[i] : 0.0;
-    y[i] = warm ? (V)Y[i] : 0.0;
+    z[i] = wm ? (V)Z[i] : 0.0;
+    y[i] = wm ? (V)Y[i] : 0.0;
   }
   for (int i = tid; i < nx; i += nt) {
     x[i] = (V)x0[i];
@@ -387,33 +450,129 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       dv[idx] = -acc;
     }
     __syncthreads();
-    for (int idx = tid; idx < N * nx; idx += nt) {
-      const int k = idx / nx, i = idx % nx;
-      V acc = 0;
-      const T* Br = B + (int64_t)k * nx * nu + i * nu;
-      for (int t = 0; t < nu; ++t) acc += (V)Br[t] * dv[k * nu + t];
-      e[idx] = (V)c[(int64_t)k * nx + i] + acc;
-    }
-    __syncthreads();
-    // forward chain: xt_{k+1} = A_cl,k xt_k + e_k
-    for (int k = 0; k < N; ++k) {
-      for (int i = tid; i < nx; i += nt) {
+    if (!mixed) {
+      for (int idx = tid; idx < N * nx; idx += nt) {
+        const int k = idx / nx, i = idx % nx;
         V acc = 0;
-        const T* Ar = wAcl + (int64_t)k * nx * nx + i * nx;
-        for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * xt[k * nx + t];
-        xt[(k + 1) * nx + i] = e[k * nx + i] + acc;
+        const T* Br = B + (int64_t)k * nx * nu + i * nu;
+        for (int t = 0; t < nu; ++t) acc += (V)Br[t] * dv[k * nu + t];
+        e[idx] = (V)c[(int64_t)k * nx + i] + acc;
       }
       __syncthreads();
+      // forward chain: xt_{k+1} = A_cl,k xt_k + e_k
+      for (int k = 0; k < N; ++k) {
+        for (int i = tid; i < nx; i += nt) {
+          V acc = 0;
+          const T* Ar = wAcl + (int64_t)k * nx * nx + i * nx;
+          for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * xt[k * nx + t];
+          xt[(k + 1) * nx + i] = e[k * nx + i] + acc;
+        }
+        __syncthreads();
+      }
+      // ut_k = K_k xt_k + d_k
+      for (int idx = tid; idx < N * nu; idx += nt) {
+        const int k = idx / nu, j = idx % nu;
+        V acc = 0;
+        const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
+        for (int t = 0; t < nx; ++t) acc += (V)Kr[t] * xt[k * nx + t];
+        ut[idx] = dv[idx] + acc;
+      }
+      __syncthreads();
+    } else {
+      // Mixed precision: the gains come from low-precision products, so the
+      // rollout runs under the exact dynamics (ut_k = K_k xt_k + d_k,
+      // xt_{k+1} = A_k xt_k + B_k ut_k + c_k) and only the stationarity of
+      // the x-subproblem is left to refine.
+      forward_exact<T, V>(N, nx, nu, A, B, c, wK, dv, xt, xt + nx, ut, tid, nt);
+      // b = (qt, rt): scale of the stopping test
+      V bl = 0;
+      for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) {
+        const int i = idx % nx;
+        bl = fmax(bl, fabs(-(V)q[i] * (V)xr[idx] - sigma * x[idx]));
+      }
+      for (int idx = tid; idx < N * nu; idx += nt) bl = fmax(bl, fabs(rt[idx]));
+      const V bn = block_max(bl, red);
+      for (int sw = 0; sw < sweeps; ++sw) {
+        // costates of the x-subproblem at (xt, ut) from its x-stationarity:
+        // lam_N = Qt xt_N + qt_N, lam_k = Qt xt_k + qt_k + A_k' lam_{k+1};
+        // lam_{k+1} is kept in pp[k]
+        for (int i = tid; i < nx; i += nt) {
+          const int idx = N * nx + i;
+          pp[(N - 1) * nx + i] = ((V)q[i] + sigma) * xt[idx] + (-(V)q[i] * (V)xr[idx] - sigma * x[idx]);
+        }
+        __syncthreads();
+        for (int k = N - 1; k >= 1; --k) {
+          for (int i = tid; i < nx; i += nt) {
+            V acc = 0;
+            const T* Ac = A + (int64_t)k * nx * nx + i;
+            for (int t = 0; t < nx; ++t) acc += (V)Ac[t * nx] * pp[k * nx + t];
+            const int idx = k * nx + i;
+            pp[(k - 1) * nx + i] =
+                ((V)q[i] + sigma) * xt[idx] + (-(V)q[i] * (V)xr[idx] - sigma * x[idx]) + acc;
+          }
+          __syncthreads();
+        }
+        // u-stationarity residual ru_k = Rt_k ut_k + rt_k + B_k' lam_{k+1}
+        V rl = 0;
+        for (int idx = tid; idx < N * nu; idx += nt) {
+          const int k = idx / nu, j = idx % nu;
+          V acc = 0;
+          const T* Bc = B + (int64_t)k * nx * nu + j;
+          for (int t = 0; t < nx; ++t) acc += (V)Bc[t * nu] * pp[k * nx + t];
+          const V rtd = rtilde_diag<V, T>(d, j, (V)r[j], mu, wrho + (int64_t)k * m, sc);
+          hv[idx] = rtd * ut[idx] + rt[idx] + acc;
+          rl = fmax(rl, fabs(hv[idx]));
+        }
+        const V rn = block_max(rl, red);
+        if (!(rn > rtol * bn)) break;
+        // correction: the same LQR with linear term ru, no offsets, x_0 fixed,
+        // solved with the low-precision factor
+        for (int idx = tid; idx < N * nx; idx += nt) {
+          const int k = idx / nx, i = idx % nx;
+          V acc = 0;
+          const T* Kc = wK + (int64_t)k * nu * nx + i;
+          for (int j = 0; j < nu; ++j) acc += (V)Kc[j * nx] * hv[k * nu + j];
+          g[idx] = acc;
+        }
+        for (int i = tid; i < nx; i += nt) p[i] = 0;
+        __syncthreads();
+        for (int k = N - 1; k >= 0; --k) {
+          for (int i = tid; i < nx; i += nt) e[k * nx + i] = p[i];
+          __syncthreads();
+          if (k > 0) {
+            for (int i = tid; i < nx; i += nt) {
+              V acc = 0;
+              const T* Ac = wAcl + (int64_t)k * nx * nx + i;
+              for (int t = 0; t < nx; ++t) acc += (V)Ac[t * nx] * e[k * nx + t];
+              p[i] = g[k * nx + i] + acc;
+            }
+            __syncthreads();
+          }
+        }
+        for (int idx = tid; idx < N * nu; idx += nt) {
+          const int k = idx / nu, j = idx % nu;
+          V acc = 0;
+          const T* Bc = B + (int64_t)k * nx * nu + j;
+          for (int t = 0; t < nx; ++t) acc += (V)Bc[t * nu] * e[k * nx + t];
+          hv[idx] = hv[idx] + acc;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < N * nu; idx += nt) {
+          const int k = idx / nu, j = idx % nu;
+          V acc = 0;
+          const T* Hr = wHi + (int64_t)k * nu * nu + j * nu;
+          for (int t = 0; t < nu; ++t) acc += (V)Hr[t] * hv[k * nu + t];
+          dv[idx] = -acc;
+        }
+        __syncthreads();
+        // dx (in g, dx_{k+1} at g[k]) and du (in dv) under the exact dynamics
+        forward_exact<T, V>(N, nx, nu, A, B, (const T*)nullptr, wK, dv, (const V*)nullptr, g, dv,
+                            tid, nt);
+        for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) xt[idx] += g[idx - nx];
+        for (int idx = tid; idx < N * nu; idx += nt) ut[idx] += dv[idx];
+        __syncthreads();
+      }
     }
-    // ut_k = K_k xt_k + d_k
-    for (int idx = tid; idx < N * nu; idx += nt) {
-      const int k = idx / nu, j = idx % nu;
-      V acc = 0;
-      const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
-      for (int t = 0; t < nx; ++t) acc += (V)Kr[t] * xt[k * nx + t];
-      ut[idx] = dv[idx] + acc;
-    }
-    __syncthreads();
     // relaxation, projection onto [l, h], dual update
     for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) x[idx] = alpha * xt[idx] + oma * x[idx];
     for (int idx = tid; idx < N * m; idx += nt) {
@@ -448,32 +607,6 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   if (!ok) st.status[a] = AGENT_NONFINITE;
 }
 
-// Block-wide reductions through LDS (blockDim.x <= 256).
-__device__ inline double block_max(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  const double out = red[0];
-  __syncthreads();
-  return out;
-}
-__device__ inline double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double out = red[0];
-  __syncthreads();
-  return out;
-}
-
 // FP64 KKT residuals of the returned iterate (the role of the solution check
 // that follows the QP loop in Alg. 1).  Costates of the dynamics rows come from
 // the adjoint sweep lambda_N = Q(x_N - r_N), lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}.
@@ -503,12 +636,12 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
   const T* x0 = in.x0 + d.ox0;
   const T* tau = in.tau + d.otau;
   const uint8_t* stance = in.st + d.ost;
-  const T* uref = in.uref ? in.uref + d.ou : nullptr;
-  const double mu = (double)in.mu[a];
+  const T* uref = in.uref ? in.uref + d.our : nullptr;
+  const double mu = (double)in.mu[d.omu];
   const T* x = st.x + d.ox;
   const T* u = st.u + d.ou;
   const T* z = st.z + d.oz;
-  const T* y = st.y + d.oz;
+  const T* y = st.y + d.oy;
 
   double obj = 0.0;
   for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) {
@@ -638,10 +771,11 @@ hipError_t launch_generic_factor(const AgentDesc* d_desc, const int32_t* list, i
 template <typename T>
 hipError_t launch_generic_admm(const AgentDesc* d_desc, const int32_t* list, int n_launch,
                                Inputs<T> in, SolverConsts sc, int iters, int warm, const T* ws,
-                               State<T> st, size_t lds, int threads, hipStream_t stream) {
+                               State<T> st, size_t lds, int threads, hipStream_t stream,
+                               int sweeps, double rtol) {
   if (n_launch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_admm<T>, dim3(n_launch), dim3(threads), lds, stream, d_desc, list, n_launch,
-                     in, sc, iters, warm, ws, st);
+                     in, sc, iters, warm, ws, st, sweeps, rtol);
   return hipGetLastError();
 }
 
@@ -685,7 +819,7 @@ hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds
                                                hipStream_t);                                      \
   template hipError_t launch_generic_admm<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,    \
                                              SolverConsts, int, int, const T*, State<T>, size_t,  \
-                                             int, hipStream_t);                                   \
+                                             int, hipStream_t, int, double);                      \
   template hipError_t launch_residual<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,        \
                                          SolverConsts, State<T>, size_t, hipStream_t);            \
   template hipError_t launch_advance<T>(const AgentDesc*, const int32_t*, int, Inputs<T>,         \

@@ -6,13 +6,14 @@
 
 namespace mpc {
 
-// Per-agent shape and offsets.  Input offsets index the caller's concatenated
-// arrays (elements), solution offsets index the plan's resident x/u/z/y, and
-// ws is the element offset of the agent's factor workspace.
+// Per-agent shape and offsets.  Input offsets index the caller's arrays
+// (elements from each Inputs base pointer), solution offsets index the
+// resident x/u/z/y, and ws is the element offset of the agent's factor
+// workspace.  flags bit 0: warm start this agent when a launch passes warm < 0.
 struct AgentDesc {
-  int32_t N, nx, nu, n_tau, n_feet, foot_dim, m, pad;
-  int64_t oA, oB, oc, oq, orr, oxr, ox0, otau, ost;
-  int64_t ox, ou, oz;
+  int32_t N, nx, nu, n_tau, n_feet, foot_dim, m, flags;
+  int64_t oA, oB, oc, oq, orr, oxr, ox0, otau, ost, omu, our;
+  int64_t ox, ou, oz, oy;
   int64_t ows;  // generic-kernel factor workspace (elements of the io type)
   int64_t ofw;  // register-resident workspace (floats), -1 if the agent has none
 };
@@ -37,6 +38,12 @@ struct State {
 };
 
 enum : int32_t { AGENT_OK = 0, AGENT_CONVERGED = 1, AGENT_NOT_PD = 2, AGENT_NONFINITE = 3 };
+enum : int32_t { AGENT_FLAG_WARM = 1 };
+
+// Warm start of one agent: the launch's flag, or the agent's own when warm < 0.
+__host__ __device__ inline bool agent_warm(int warm, const AgentDesc& d) {
+  return warm < 0 ? (d.flags & AGENT_FLAG_WARM) != 0 : warm != 0;
+}
 
 // Elements of factor workspace per agent for the generic kernels:
 // K [N][nu][nx], Acl [N][nx][nx], Hinv [N][nu][nu], s [N][nx], l/h/rho [N][m].
@@ -50,7 +57,8 @@ inline size_t generic_factor_lds(int nx, int nu, size_t esz) {
 }
 inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz) {
   (void)esz;  // vectors are held in double whatever the io type
-  return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu);
+  // + 256 doubles of reduction scratch for the refinement's stopping test
+  return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu + 256);
 }
 
 // Raise the dynamic-LDS limit of the generic kernels to what a plan needs.
@@ -62,10 +70,14 @@ template <typename T>
 hipError_t launch_generic_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch,
                                  Inputs<T> in, SolverConsts sc, T* ws, int32_t* status, size_t lds,
                                  int threads, hipStream_t stream);
+// sweeps >= 0 selects the mixed-precision iteration: rollout under the exact
+// dynamics and up to `sweeps` KKT-residual refinement sweeps per x-update,
+// stopping once |r|_inf <= rtol * |b|_inf.  sweeps < 0: plain iteration.
 template <typename T>
 hipError_t launch_generic_admm(const AgentDesc* d_desc, const int32_t* list, int n_launch,
                                Inputs<T> in, SolverConsts sc, int iters, int warm, const T* ws,
-                               State<T> st, size_t lds, int threads, hipStream_t stream);
+                               State<T> st, size_t lds, int threads, hipStream_t stream,
+                               int sweeps = -1, double rtol = 0.0);
 template <typename T>
 hipError_t launch_residual(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
                            SolverConsts sc, State<T> st, size_t lds, hipStream_t stream);

@@ -13,26 +13,27 @@
 
 #include "../../include/mpc.h"
 #include "fused.h"
+#include "host_api.h"
 #include "mpc_internal.h"
 
 using namespace mpc;
 
+namespace mpc {
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-mpc_status fail(mpc_status s, const std::string& msg) {
+mpc_status api_fail(mpc_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+}  // namespace mpc
 
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t _e = (expr);                                                                 \
-    if (_e != hipSuccess)                                                                   \
-      return fail(_e == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,          \
-                  std::string(#expr) + ": " + hipGetErrorString(_e));                      \
-  } while (0)
+namespace {
+
+mpc_status fail(mpc_status s, const std::string& msg) { return api_fail(s, msg); }
+
+#define HIP_TRY(expr) MPC_HIP_TRY(expr)
 
 constexpr int kPhases = 3;
 constexpr int kMaxAuxStreams = 3;  // plus the caller's stream: four hardware queues
@@ -40,7 +41,7 @@ constexpr int kMaxAuxStreams = 3;  // plus the caller's stream: four hardware qu
 // A launch group: agents of one shape class (and, for the register-resident
 // kernels, one horizon) solved by one kernel family with one launch shape.
 struct Group {
-  int family = 1;          // 1 generic, 2 register-resident
+  int family = 1;          // 1 generic, 2 register-resident, 4 mixed precision
   bool fused_ok = false;   // register-resident kernels have an instantiation for it
   int N = 0, nx = 0, nu = 0, n_feet = 0;  // N: largest horizon in the group
   int count = 0;
@@ -123,7 +124,7 @@ extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
   d->kernel = 0;
 }
 
-extern "C" const char* mpc_last_error(void) { return g_err.c_str(); }
+extern "C" const char* mpc_last_error(void) { return mpc::g_err.c_str(); }
 extern "C" const char* mpc_version(void) { return "mpc-mi355x 0.1.0 (gfx950)"; }
 
 static void free_plan(mpc_plan_s* p) {
@@ -165,6 +166,9 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       !std::isfinite(desc->sigma) || !std::isfinite(desc->rho_eq_scale) || !std::isfinite(desc->rho_min))
     return fail(MPC_ERR_INVALID_ARG, "solver constants out of range (rho>0, sigma>=0, 0<alpha<2, rho_eq_scale>0, rho_min>0)");
   if (desc->kernel < 0 || desc->kernel > 2) return fail(MPC_ERR_INVALID_ARG, "unknown kernel selector");
+  if (desc->max_refine_sweeps < 0 || desc->max_refine_sweeps > 16 || !(desc->refine_tol >= 0) ||
+      !std::isfinite(desc->refine_tol))
+    return fail(MPC_ERR_INVALID_ARG, "max_refine_sweeps must be in 0..16 and refine_tol >= 0");
   for (int a = 0; a < desc->n_agents; ++a) {
     mpc_status vs = validate_shape(desc->shapes[a], a);
     if (vs != MPC_OK) return vs;
@@ -198,6 +202,10 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     cur.ox0 = ox0; cur.otau = otau; cur.ost = ost; cur.ox = ox; cur.ou = ou; cur.oz = oz;
     cur.ows = ows;
     cur.ofw = -1;
+    cur.oy = oz;
+    cur.omu = a;
+    cur.our = ou;
+    cur.flags = 0;
     p->hdesc[a] = cur;
     oA += (int64_t)s.N * s.nx * s.nx;
     oB += (int64_t)s.N * s.nx * s.nu;
@@ -240,9 +248,14 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
                     "register-resident kernels requested for an agent they do not support");
       }
+      if (mixed && !mixed_supported(s.nx, s.nu)) {
+        delete p;
+        return fail(MPC_ERR_UNSUPPORTED_SHAPE,
+                    "mixed precision is built for (nx, nu) = (48, 30) and (36, 24) only");
+      }
       const bool use_fused = fok && desc->kernel != 1 && !mixed;
-      buckets[std::make_tuple(use_fused ? 2 : 1, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim,
-                              use_fused ? s.N : 0)]
+      const int fam = mixed ? 4 : use_fused ? 2 : 1;
+      buckets[std::make_tuple(fam, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim, use_fused ? s.N : 0)]
           .push_back(a);
     }
     for (auto& kv : buckets) {
@@ -281,7 +294,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     }
   }
   p->kernel = 0;
-  for (const Group& g : p->groups) p->kernel |= g.family;  // 1, 2 or 3 (both)
+  for (const Group& g : p->groups) p->kernel |= g.family;
 
   hipError_t e = hipSetDevice(desc->device);
   if (e != hipSuccess) {
@@ -295,7 +308,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     return fail(MPC_ERR_UNSUPPORTED_SHAPE, "shapes need more LDS than the device offers");
   }
   e = generic_set_lds_limits(p->lds_factor, p->lds_admm, p->lds_res);
-  if (e == hipSuccess && p->nFWS > 0) e = fused_set_limits();
+  if (e == hipSuccess && (p->nFWS > 0 || mixed)) e = fused_set_limits();
   if (e != hipSuccess) {
     delete p;
     return fail(MPC_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
@@ -454,6 +467,20 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
                               make_inputs<float>(b), sc, p->desc.admm_iters, warm,
                               make_state<float>(p), p->d_fws, s, 2));
     }
+  } else if (g.family == 4) {
+    {
+      PhaseTimer t(p, 0, s);
+      HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu,
+                                  p->desc.precision == MPC_BF16_REFINE, make_inputs<float>(b), sc,
+                                  (float*)p->d_ws, p->d_status, s));
+    }
+    {
+      PhaseTimer t(p, 1, s);
+      HIP_TRY(launch_generic_admm<float>(p->d_desc, list, g.count, make_inputs<float>(b), sc,
+                                         p->desc.admm_iters, warm, (const float*)p->d_ws,
+                                         make_state<float>(p), g.lds_admm, g.gthreads, s,
+                                         p->desc.max_refine_sweeps, p->desc.refine_tol));
+    }
   } else {
     const Inputs<T> in = make_inputs<T>(b);
     {
@@ -507,8 +534,6 @@ extern "C" mpc_status mpc_solve(mpc_plan_t p, const mpc_problem_batch* b, void* 
   if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
   mpc_status cs = check_batch(p, b);
   if (cs != MPC_OK) return cs;
-  if (p->desc.precision != MPC_FP32 && p->desc.precision != MPC_FP64)
-    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "mixed-precision plans are not available in this build");
   HIP_TRY(hipSetDevice(p->desc.device));
   hipStream_t s = (hipStream_t)stream;
   p->last_stream = s;
@@ -628,7 +653,7 @@ extern "C" mpc_status mpc_plan_export_factor(mpc_plan_t p, int32_t agent, void* 
   if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
   for (const Group& g : p->groups)
     for (int i = 0; i < g.count; ++i)
-      if (p->hlist[g.list_off + i] == agent && g.family != 1)
+      if (p->hlist[g.list_off + i] == agent && g.family == 2)
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
                     "this agent's operators are kept in the register-resident layout");
   if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
@@ -675,8 +700,6 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
   cold.warm_start = 0;
   mpc_status cs = check_batch(p, &cold);
   if (cs != MPC_OK) return cs;
-  if (p->desc.precision != MPC_FP32 && p->desc.precision != MPC_FP64)
-    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "mixed-precision plans are not available in this build");
   HIP_TRY(hipSetDevice(p->desc.device));
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -689,13 +712,13 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
     struct Cand { int family, threads; };
     std::vector<Cand> cands;
     if (g.fused_ok) cands.push_back({2, g.fthreads});
-    for (int t : {256, 128, 64}) cands.push_back({1, t});
+    for (int t : {256, 128, 64}) cands.push_back({g.family == 4 ? 4 : 1, t});
     float best = INFINITY;
     Cand pick = {g.family, g.family == 2 ? g.fthreads : g.gthreads};
     for (const Cand& c : cands) {
       Group trial = g;
       trial.family = c.family;
-      if (c.family == 1) trial.gthreads = c.threads;
+      if (c.family != 2) trial.gthreads = c.threads;
       r = p->fp64 ? run_group<double>(p, trial, &cold, s, 0) : run_group<float>(p, trial, &cold, s, 0);
       if (r != MPC_OK) break;
       hipError_t he = hipEventRecord(e0, s);
@@ -714,7 +737,7 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
     }
     if (r != MPC_OK) break;
     g.family = pick.family;
-    if (pick.family == 1) g.gthreads = pick.threads;
+    if (pick.family != 2) g.gthreads = pick.threads;
   }
   p->timing = timing;
   hipEventDestroy(e0);
@@ -736,8 +759,6 @@ extern "C" mpc_status mpc_plan_capture(mpc_plan_t p, const mpc_problem_batch* b,
   if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
   mpc_status cs = check_batch(p, b);
   if (cs != MPC_OK) return cs;
-  if (p->desc.precision != MPC_FP32 && p->desc.precision != MPC_FP64)
-    return fail(MPC_ERR_UNSUPPORTED_SHAPE, "mixed-precision plans are not available in this build");
   HIP_TRY(hipSetDevice(p->desc.device));
   if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   if (p->gexec) hipGraphExecDestroy(p->gexec);

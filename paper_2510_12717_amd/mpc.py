@@ -157,7 +157,7 @@ class Plan:
         _check(L.mpc_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
         self.n = len(self.shapes)
-        self.dtype = "fp64" if precision == "fp64" else "fp32"
+        self.dtype = "fp64" if precision == "fp64" else "fp32"  # io type
         m = [s.nu + 4 * s.n_feet for s in self.shapes]
         self.sizes = dict(x=sum((s.N + 1) * s.nx for s in self.shapes),
                           u=sum(s.N * s.nu for s in self.shapes),
@@ -232,7 +232,8 @@ class Plan:
         k, t, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().mpc_plan_get_config(self._h, ctypes.byref(k), ctypes.byref(t),
                                          ctypes.byref(l)))
-        return dict(kernel={1: "generic", 2: "fused", 3: "mixed"}.get(k.value, str(k.value)),
+        return dict(kernel={1: "generic", 2: "fused", 3: "generic+fused",
+                            4: "mixed_precision"}.get(k.value, str(k.value)),
                     threads_per_agent=t.value, lds_bytes=l.value)
 
     def groups(self):
@@ -245,7 +246,7 @@ class Plan:
         out = []
         for g in arr[:n.value]:
             d = {f: getattr(g, f) for f, _ in GroupInfo._fields_}
-            d["family"] = {1: "generic", 2: "fused"}[g.family]
+            d["family"] = {1: "generic", 2: "fused", 4: "mixed_precision"}[g.family]
             out.append(d)
         return out
 

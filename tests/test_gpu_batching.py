@@ -38,7 +38,7 @@ def test_groups_of_uneven_batch():
     n_fused = sum(x["n_agents"] for x in groups if x["family"] == "fused")
     n_short = sum(1 for s in b.shapes if s.N <= 12)
     assert n_fused == n_short
-    assert plan.config()["kernel"] == "mixed"
+    assert plan.config()["kernel"] == "generic+fused"
     o = oracle.solve_batch(b, iters=50)
     assert np.all(g["status"] == 0)
     e = agent_errors(b, g, o)

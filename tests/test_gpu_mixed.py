@@ -1,0 +1,104 @@
+"""GPU: mixed-precision plans (BF16 / FP16 Riccati block products on the
+matrix cores, FP64 stage-Hessian inverse, KKT-residual refinement) against
+the FP64 oracle on the mixed-precision sweep: humanoid agents, N = 16, Q and R
+with condition number kappa in {1e2, 1e4, 1e6}.
+
+Bounds (norm-wise relative error per agent on u_0 and on the trajectory,
+max over the checked agents):
+  after 3 refinement sweeps: FP16 1e-5, BF16 1e-3;
+  before refinement (0 sweeps): 5e-2 -- a BF16 operand alone carries a
+  relative rounding error of 2^-9, and the 16-stage recursion amplifies it to
+  about 1e-2 on these problems; refinement must gain at least 10x.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2510_12717_amd import mpc, synth
+
+from test_gpu_parity import agent_errors
+
+pytestmark = pytest.mark.gpu
+
+AFTER = {"bf16": 1e-3, "fp16": 1e-5}
+BEFORE = 5e-2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    mpc.lib()
+
+
+def _solve(b, precision, sweeps):
+    plan = mpc.Plan(b.shapes, precision=precision, iters=50, max_refine_sweeps=sweeps,
+                    refine_tol=1e-6)
+    prob = mpc.to_device(b, "fp32")
+    plan.solve(prob)
+    sol = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    return sol, plan
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+def test_mixed_precision_error_table(kappa):
+    ids = np.arange(0, 16384, 256)  # 64 agents of the 16384-agent sweep
+    b = synth.config3(agent_ids=ids, kappa=kappa, dtype=np.float32)
+    o = oracle.solve_batch(synth.config3(agent_ids=ids, kappa=kappa), iters=50)
+    rows = []
+    for precision in ("bf16", "fp16"):
+        errs = {}
+        for sweeps in (0, 3):
+            g, plan = _solve(b, precision, sweeps)
+            assert plan.config()["kernel"] == "mixed_precision"
+            assert np.all(g["status"] == 0)
+            e = agent_errors(b, g, o)[:, :2]
+            errs[sweeps] = e.max()
+            rows.append("kappa %.0e %s sweeps %d: u0 %.2e traj %.2e (p50 %.2e)"
+                        % (kappa, precision, sweeps, e[:, 0].max(), e[:, 1].max(),
+                           np.median(e[:, 1])))
+        assert errs[0] < BEFORE
+        assert errs[3] < AFTER[precision]
+        assert errs[3] * 10 < errs[0]
+    g, _ = _solve(b, "fp32", 0)
+    e = agent_errors(b, g, o)[:, :2]
+    rows.append("kappa %.0e fp32: u0 %.2e traj %.2e" % (kappa, e[:, 0].max(), e[:, 1].max()))
+    assert e.max() < 1e-5
+    print("\n" + "\n".join(rows))
+
+
+def test_mixed_precision_warm_closed_loop():
+    """Warm-started steps of the mixed plan track the FP64 oracle from the same warm state."""
+    b = synth.config3(agent_ids=np.arange(0, 16384, 512), kappa=1e4, dtype=np.float32)
+    b64 = synth.config3(agent_ids=np.arange(0, 16384, 512), kappa=1e4)
+    plan = mpc.Plan(b.shapes, precision="fp16", iters=50)
+    prob = mpc.to_device(b, "fp32")
+    o = oracle.solve_batch(b64, iters=50)
+    x0 = b64.x0.copy()
+    for step in range(3):
+        noise = synth.step_noise(b64, step)
+        x0 = oracle.advance_batch(b64, x0, o["u"], noise)
+        o2 = oracle.solve_batch(b64, iters=50, warm={k: o[k] for k in ("u", "z", "y")}, x0=x0)
+        plan.set_warm_state(*(torch.from_numpy(o[k]).float().cuda() for k in ("u", "z", "y")))
+        prob["x0"] = torch.from_numpy(x0).float().cuda()
+        plan.solve(prob, warm_start=True)
+        g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+        assert agent_errors(b, g, o2)[:, :2].max() < AFTER["fp16"]
+        o = o2
+
+
+def test_mixed_precision_failures_stay_local():
+    b = synth.config3(agent_ids=np.arange(6), kappa=1e2, dtype=np.float32)
+    off = b.offsets()
+    b.A[off["A"][2] + 5] = np.nan
+    b.r[off["r"][4]:off["r"][5]] = -5.0
+    g, _ = _solve(b, "bf16", 3)
+    assert g["status"].tolist() == [0, 0, 3, 0, 2, 0]
+
+
+def test_mixed_precision_unsupported_shape():
+    with pytest.raises(mpc.MPCError) as ei:
+        mpc.Plan([synth.Shape(N=4, nx=20, nu=6, n_tau=6, n_feet=0, foot_dim=3)], precision="bf16")
+    assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE

@@ -55,7 +55,92 @@ def parse():
                     help="approximate wall time budget of the CPU-oracle baseline (0 = skip)")
     ap.add_argument("--check-agents", type=int, default=64,
                     help="agents whose first-step solution is compared with the FP64 oracle")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the served request loop instead: Poisson arrivals from independent "
+                         "controllers of uneven shapes (prints its own JSON line)")
+    ap.add_argument("--controllers", type=int, default=8192)
+    ap.add_argument("--rate-hz", type=float, default=100.0, help="request rate per controller")
+    ap.add_argument("--sim-seconds", type=float, default=2.0)
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
     return ap.parse_args()
+
+
+def serve(args):
+    """Served loop: every controller (shapes as the uneven batch: N ~ U{5..20},
+    half humanoid, half quadruped) sends Poisson requests at rate-hz for
+    sim-seconds of wall time; its problem data sit in a device-resident pool.
+    Latency = completion event time - arrival time, on the server's clock."""
+    import ctypes
+    import torch
+
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    nc = args.controllers
+    b = synth.config2(nc)
+    prob = mpc.to_device(b, "fp32")
+    reqs = mpc.agent_problems(prob, b)
+    for r in reqs:
+        r.warm_start = 1
+    rec_p = np.frombuffer(reqs, dtype=np.dtype((np.void, ctypes.sizeof(mpc.ProblemBatch))))
+    shapes = (mpc.Shape * nc)(*[mpc.Shape(*s.as_tuple()) for s in b.shapes])
+    rec_s = np.frombuffer(shapes, dtype=np.dtype((np.void, ctypes.sizeof(mpc.Shape))))
+    nu = np.array([s.nu for s in b.shapes])
+    u0 = torch.zeros(int(nu.sum()), device="cuda")
+    u0_ptr = (u0.data_ptr() + 4 * np.concatenate([[0], np.cumsum(nu)[:-1]])).astype(np.uint64)
+    rng = np.random.default_rng(11)
+    arr_t, arr_c = [], []
+    for c in range(nc):
+        t = np.cumsum(rng.exponential(1.0 / args.rate_hz, size=int(args.sim_seconds * args.rate_hz * 2) + 8))
+        t = t[t < args.sim_seconds]
+        arr_t.append(t)
+        arr_c.append(np.full(len(t), c))
+    at = np.concatenate(arr_t)
+    ac = np.concatenate(arr_c)
+    order = np.argsort(at, kind="stable")
+    at, ac = at[order], ac[order]
+    srv = mpc.Server(precision="fp32", iters=args.iters,
+                     hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), max_batch=8192,
+                     max_inflight=3)
+    # warm every controller once (cold first solves), outside the measurement
+    srv.submit_many(np.arange(nc), rec_s, rec_p, u0_ptr, np.zeros(nc))
+    srv.drain()
+    srv.poll(cap=nc + 16)
+    arrival = {}
+    lat = []
+    t0 = srv.clock()
+    i, n = 0, len(at)
+    while i < n or len(arrival):
+        now = srv.clock() - t0
+        j = np.searchsorted(at, now, side="right")
+        if j > i:
+            idx = ac[i:j]
+            tk = srv.submit_many(idx, rec_s[idx], rec_p[idx], u0_ptr[idx], t0 + at[i:j])
+            for k, t in zip(tk.tolist(), (t0 + at[i:j]).tolist()):
+                arrival[k] = t
+            i = j
+        tk, tm = srv.poll()
+        for k, t in zip(tk.tolist(), tm.tolist()):
+            lat.append(t - arrival.pop(k))
+        if i >= n and arrival:
+            srv.drain()
+    t_end = srv.clock() - t0
+    st = srv.stats()
+    lat = np.array(lat) * 1e3
+    out = {"metric": "served MPC QP solves/sec with p50/p95/p99 arrival-to-result latency",
+           "value": n / t_end, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{nc} controllers, Poisson {args.rate_hz:g} Hz each, "
+                                  f"{args.sim_seconds:g} s, N ~ U{{5..20}}, half humanoid (48, 30), "
+                                  "half quadruped (36, 24), warm-started", "controllers": nc,
+                      "offered_rate": nc * args.rate_hz, "requests": int(n),
+                      "admm_iters": args.iters, "hbm_budget_gb": args.hbm_budget_gb},
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p95": float(np.percentile(lat, 95)),
+                          "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
+           "server": {k: st[k] for k in ("batches", "evictions", "resident_controllers",
+                                         "resident_bytes")},
+           "wall_s": t_end}
+    print(json.dumps(out))
 
 
 def main():
@@ -64,6 +149,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(agents shard across GPUs with no exchange, see DESIGN.md)"}))
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
     import torch
 
     import oracle

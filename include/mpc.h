@@ -220,6 +220,90 @@ mpc_status mpc_plan_capture(mpc_plan_t plan, const mpc_problem_batch* batch, con
  * step has been captured. */
 mpc_status mpc_plan_replay(mpc_plan_t plan, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Served request loop (continuous batching).  Controllers submit single-QP
+ * requests as they arrive, each controller with its own shape.  The server
+ * keeps every solved controller's iterate (x, u, z, y) resident on the device
+ * as the warm start of its next request, launches pending requests in batches
+ * whenever one of max_inflight batch slots is free (requests arriving while
+ * others run join the next batch), and admits work by an HBM budget: one
+ * device arena of hbm_budget_bytes holds resident states and the factor
+ * workspace of in-flight requests; when it is full the least recently used
+ * idle controllers lose their resident state (their next solve is cold) and
+ * requests that still do not fit wait.  A controller's requests run in
+ * arrival order, one at a time.  Each request is solved exactly as the same
+ * agent in a plan of the same precision: its result does not depend on the
+ * other requests of its batch.
+ * ------------------------------------------------------------------------- */
+typedef struct mpc_server_s* mpc_server_t;
+
+typedef struct {
+  mpc_plan_desc solver;      /* precision, admm_iters, constants, refinement, device;   */
+                             /* n_agents, shapes and kernel are ignored                  */
+  int64_t hbm_budget_bytes;  /* device memory of the server (default 1 GiB)             */
+  int32_t max_batch;         /* requests per batch (default 4096)                       */
+  int32_t max_inflight;      /* batches on the device at once, 1..8 (default 3)        */
+} mpc_server_desc;
+
+typedef struct {
+  int64_t submitted, completed, batches, evictions;
+  int64_t pending, inflight;             /* requests waiting / on the device now       */
+  int64_t resident_controllers, resident_bytes;
+  int64_t arena_bytes, arena_free_bytes;
+} mpc_server_stats;
+
+void mpc_server_desc_default(mpc_server_desc* desc);
+
+/* Allocates the arena and the batch slots (each with its own stream).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP. */
+mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_t* out);
+
+/* Waits for the device and releases everything. */
+mpc_status mpc_server_destroy(mpc_server_t server);
+
+/* Seconds on the server's steady clock (zero at creation); arrival and
+ * completion times use it. */
+double mpc_server_clock(mpc_server_t server);
+
+/* Queue one request of controller controller_id (any int64 key).  problem
+ * holds DEVICE pointers to this controller's data for ONE agent in the
+ * layouts of mpc_problem_batch, in the io type of the server's precision;
+ * u_ref must be NULL; they must stay valid until the request completes.
+ * problem->warm_start = 1 starts from the controller's resident iterate when
+ * it has one (cold otherwise).  On completion u_0 [nu] is written to u0_out
+ * and, if status_out is not NULL, the agent status to *status_out (device
+ * pointers).  A controller keeps the shape of its first request.  Launches
+ * work if a batch slot is free.  Errors: INVALID_ARG, UNSUPPORTED_SHAPE,
+ * OUT_OF_MEMORY (one request of this shape exceeds the budget), HIP. */
+mpc_status mpc_server_submit(mpc_server_t server, int64_t controller_id, const mpc_shape* shape,
+                             const mpc_problem_batch* problem, void* u0_out, int32_t* status_out,
+                             double t_arrival, int64_t* ticket);
+
+/* n requests at once (arrays of n; status_out and tickets may be NULL). */
+mpc_status mpc_server_submit_many(mpc_server_t server, int32_t n, const int64_t* controller_ids,
+                                  const mpc_shape* shapes, const mpc_problem_batch* problems,
+                                  void* const* u0_out, int32_t* const* status_out,
+                                  const double* t_arrival, int64_t* tickets);
+
+/* Non-blocking: retire finished batches, launch pending work into free
+ * slots, and report up to cap completed tickets with their completion times
+ * (server clock, taken from the batch's completion event). */
+mpc_status mpc_server_poll(mpc_server_t server, int64_t* done_tickets, double* done_time,
+                           int32_t cap, int32_t* n_done);
+
+/* Blocks until every submitted request has completed (completions stay
+ * reportable by mpc_server_poll).  OUT_OF_MEMORY if pending requests can
+ * never fit the budget. */
+mpc_status mpc_server_drain(mpc_server_t server);
+
+/* Copy a controller's resident iterate (x [N+1][nx], u [N][nu], z, y [N][m],
+ * io type) to caller device buffers; any may be NULL.  BUSY while it has a
+ * request on the device, NOT_READY if it has no resident state. */
+mpc_status mpc_server_get_state(mpc_server_t server, int64_t controller_id, void* x, void* u,
+                                void* z, void* y, void* stream);
+
+mpc_status mpc_server_get_stats(mpc_server_t server, mpc_server_stats* out);
+
 /* Thread-local description of the last error returned on this thread. */
 const char* mpc_last_error(void);
 

@@ -193,7 +193,7 @@ template <int NX, int NU>
 constexpr int riccati_lds_bytes() {
   using S = FS<NX, NU>;
   return 8 * (3 * S::NXT * S::LX + 2 * S::NXT * S::LU + S::NUT * S::LX + S::NUT * S::LU +
-              S::NUT + S::MMAX + S::NXT + 2 * S::NUT) + 16;
+              S::NUT + S::MMAX + S::NXT + 4 * S::NUT) + 16;
 }
 
 // PREC == kProdF64: operators go to the register-resident layout at fws + ofw.
@@ -227,8 +227,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   double* rhok = rdg + NUT;                   // row penalties       MMAX
   double* ck = rhok + S::MMAX;                // c_k                 NXT
   double* xcol = ck + NXT;                    // Gauss-Jordan pivot column / row exchange
-  double* xrow = xcol + NUT;
-  int* flag = reinterpret_cast<int*>(xrow + NUT);
+  double* xrow = xcol + 2 * NUT;              //   (two buffers each)
+  int* flag = reinterpret_cast<int*>(xrow + 2 * NUT);
 
   const float* A = in.A + d.oA;
   const float* B = in.B + d.oB;
@@ -345,62 +345,48 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     // H_k^{-1} in place by Gauss-Jordan sweeps without pivoting over the padded
     // NUT x NUT matrix (padding is the identity).  H_k is SPD, so every pivot is
     // a squared Cholesky diagonal and a pivot <= 0 means H_k is not positive
-    // definite.  One wavefront; lane (a, b) holds the 4x4 block rows 4a..,
-    // columns 4b.. in registers, and each sweep broadcasts the pivot row and
-    // column through LDS.
-    if (w == 0) {
-      static_assert(NUT == 32, "the register-blocked inversion assumes 32 x 32");
-      const int ga = lane >> 3, gb = lane & 7;
-      double h[4][4];
+    // definite.  Every thread of the workgroup keeps EPT consecutive entries of
+    // one row in registers; each sweep publishes the pivot row and column
+    // through a double-buffered LDS exchange, so one barrier per sweep orders
+    // a buffer's writes after its previous readers.
+    {
+      static_assert(NUT * NUT == 2 * 64 * kFactorWaves, "two entries per thread");
+      constexpr int EPT = 2, TPR = NUT / EPT;  // entries per thread, threads per row
+      const int row = tid / TPR, c0 = (tid % TPR) * EPT;
+      double h[EPT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) h[r][cc] = H[(4 * ga + r) * LU + 4 * gb + cc];
+      for (int e = 0; e < EPT; ++e) h[e] = H[row * LU + c0 + e];
       bool bad = false;
       for (int j = 0; j < NUT; ++j) {
-        const int jb = j >> 2, jr = j & 3;
-        // owners publish column j (lanes with gb == jb) and row j (lanes with ga == jb)
-        if (gb == jb)
+        double* xc = xcol + (j & 1) * NUT;
+        double* xr = xrow + (j & 1) * NUT;
+        if (j >= c0 && j < c0 + EPT) xc[row] = h[j - c0];
+        if (row == j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) xcol[4 * ga + r] = h[r][jr];
-        if (ga == jb)
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) xrow[4 * gb + cc] = h[jr][cc];
-        wave_sync();
-        double col[4], row[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) col[r] = xcol[4 * ga + r];
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) row[cc] = xrow[4 * gb + cc];
-        const double piv = xrow[j];
-        wave_sync();
-        if (!(piv > 0.0)) {
+          for (int e = 0; e < EPT; ++e) xr[c0 + e] = h[e];
+        __syncthreads();
+        const double piv = xr[j];
+        if (!(piv > 0.0)) {  // the same value in every thread: a uniform exit
           bad = true;
           break;
         }
         const double ip = 1.0 / piv;
+        const double cr = xc[row] * ip;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
-            const bool ri = (4 * ga + r) == j, ct = (4 * gb + cc) == j;
-            if (ri && ct)
-              h[r][cc] = ip;
-            else if (ri)
-              h[r][cc] = row[cc] * ip;
-            else if (ct)
-              h[r][cc] = -col[r] * ip;
-            else
-              h[r][cc] -= col[r] * ip * row[cc];
-          }
+        for (int e = 0; e < EPT; ++e) {
+          const int cc = c0 + e;
+          const double rv = xr[cc];
+          if (row == j)
+            h[e] = cc == j ? ip : rv * ip;
+          else
+            h[e] = cc == j ? -cr : h[e] - cr * rv;
+        }
       }
       if (bad) {
-        if (lane == 0) flag[1] = 1;
+        if (tid == 0) flag[1] = 1;
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) H[(4 * ga + r) * LU + 4 * gb + cc] = h[r][cc];
+        for (int e = 0; e < EPT; ++e) H[row * LU + c0 + e] = h[e];
       }
     }
     __syncthreads();
@@ -499,7 +485,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
 // ------------------------------------------------------------------------------------
 
 struct IterLds {
-  int xtf, pbuf, ppf, gf, ef, sf, cf;                         // float
+  int xtf, pbuf, ppf, gf, ef, sf, cf, hml;                    // float
   int xd, ud, zd, yd, lod, hid, rhod, rtd, dd, utd, qd, xrd;  // double
   int flag, total;
 };
@@ -521,6 +507,7 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
   L.ef = take(4 * N * S::NXP);
   L.sf = take(4 * N * S::NXP);
   L.cf = take(4 * N * S::NXP);
+  L.hml = take(4 * N * S::CB * S::CB * 64);
   L.xd = take(8 * (N + 1) * S::NXP);
   L.ud = take(8 * N * S::NUP);
   L.zd = take(8 * N * M);
@@ -573,6 +560,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   float* ef = reinterpret_cast<float*>(sm + L.ef);
   float* sf = reinterpret_cast<float*>(sm + L.sf);
   float* cf = reinterpret_cast<float*>(sm + L.cf);
+  float* hml = reinterpret_cast<float*>(sm + L.hml);
   double* xd = reinterpret_cast<double*>(sm + L.xd);
   double* ud = reinterpret_cast<double*>(sm + L.ud);
   double* zd = reinterpret_cast<double*>(sm + L.zd);
@@ -598,7 +586,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   const double mu = (double)in.mu[d.omu];
 
   // this wavefront's stage operators: coalesced loads into registers
-  float Acl[RB][RB], Km[CB][RB], Bm[RB][CB], Hm[CB][CB];
+  float Acl[RB][RB], Km[CB][RB], Bm[RB][CB];
   {
     const float* src = fws + d.ofw + (int64_t)w * SLOTS * 64 + lane;
 #pragma unroll
@@ -615,16 +603,17 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
     for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < CB; ++j) Bm[i][j] = src[(i * CB + j) * 64];
-    src += RB * CB * 64;
-#pragma unroll
-    for (int i = 0; i < CB; ++i)
-#pragma unroll
-      for (int j = 0; j < CB; ++j) Hm[i][j] = src[(i * CB + j) * 64];
   }
 
   // per-agent vectors into LDS (padding zero)
   for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
+  // H_k^{-1} is used once per iteration: it stays in LDS, in register order
+  {
+    const float* src = fws + d.ofw + ((int64_t)w * SLOTS + RB * RB + 2 * CB * RB) * 64 + lane;
+#pragma unroll
+    for (int e = 0; e < CB * CB; ++e) hml[(w * CB * CB + e) * 64 + lane] = src[e * 64];
+  }
   const float* sk = fws + d.ofw + (int64_t)kMaxStages * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
   for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
@@ -691,10 +680,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         opaque(Km[i][j]);
         opaque(Bm[j][i]);
       }
-#pragma unroll
-    for (int i = 0; i < CB; ++i)
-#pragma unroll
-      for (int j = 0; j < CB; ++j) opaque(Hm[i][j]);
     // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k; wavefront N-1 also p_N
     if (lane < NUP) {
       double v = 0.0;
@@ -720,41 +705,58 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       for (int i = lane; i < NX; i += 64)
         pbuf[N * NXP + i] = (float)(-qd[i] * xrd[N * NXP + i] - sigma * xd[N * NXP + i]);
     wave_sync();
+    // Every product below forms all its partial sums first, then all its
+    // butterflies, then one guarded store, so the independent chains
+    // interleave instead of serialising behind the store's branch.
     if (k >= 1) {
       float rv[CB];
+      double sg[RB];
 #pragma unroll
       for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        double s = 0.0;
+      for (int j = 0; j < RB; ++j) sg[j] = 0.0;
 #pragma unroll
-        for (int i = 0; i < CB; ++i) s += (double)(Km[i][j] * rv[i]);
-        s = red_b(s);
-        const int idx = la * RB + j;
-        if (lb == 0)
+      for (int i = 0; i < CB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) sg[j] += (double)(Km[i][j] * rv[i]);
+#pragma unroll
+      for (int j = 0; j < RB; ++j) sg[j] = red_b(sg[j]);
+      if (lb == 0)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          const int idx = la * RB + j;
           gf[k * NXP + idx] =
-              (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) + s);
-      }
+              (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) + sg[j]);
+        }
     }
     // (B) backward chain, one hop per barrier: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
+    wave_sync();
     for (int kk = N - 1; kk >= 0; --kk) {
       if (w == kk) {
-        float pin[RB];
+        // s_k and g_k are this wavefront's own: their loads issue with p_{k+1}'s
+        float pin[RB], sp[RB], sreg[RB], greg[RB];
 #pragma unroll
-        for (int i = 0; i < RB; ++i)
-          pin[i] = pbuf[(kk + 1) * NXP + la * RB + i] + sf[kk * NXP + la * RB + i];
+        for (int i = 0; i < RB; ++i) {
+          sreg[i] = sf[kk * NXP + la * RB + i];
+          greg[i] = gf[kk * NXP + lb * RB + i];
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) pin[i] = pbuf[(kk + 1) * NXP + la * RB + i] + sreg[i];
         if (lb == 0)
 #pragma unroll
           for (int i = 0; i < RB; ++i) ppf[kk * NXP + la * RB + i] = pin[i];
         if (kk >= 1) {
 #pragma unroll
-          for (int j = 0; j < RB; ++j) {
-            float s = 0.f;
+          for (int j = 0; j < RB; ++j) sp[j] = 0.f;
 #pragma unroll
-            for (int i = 0; i < RB; ++i) s += Acl[i][j] * pin[i];
-            s = red_a(s);
-            if (la == 0) pbuf[kk * NXP + lb * RB + j] = gf[kk * NXP + lb * RB + j] + s;
-          }
+          for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) sp[j] += Acl[i][j] * pin[i];
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sp[j] = red_a(sp[j]);
+          if (la == 0)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) pbuf[kk * NXP + lb * RB + j] = greg[j] + sp[j];
         }
       }
       __syncthreads();
@@ -762,68 +764,96 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
     // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
     {
       float pv[RB], hv[CB];
+      double sh[CB], sd[CB], rtv[CB];
 #pragma unroll
       for (int i = 0; i < RB; ++i) pv[i] = ppf[k * NXP + la * RB + i];
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < RB; ++i) s += (double)(Bm[i][j] * pv[i]);
-        hv[j] = (float)(rtd[k * NUP + lb * CB + j] + red_a(s));
+        rtv[j] = rtd[k * NUP + lb * CB + j];
+        sh[j] = 0.0;
       }
 #pragma unroll
-      for (int i = 0; i < CB; ++i) {
-        double s = 0.0;
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < CB; ++j) s += (double)(Hm[i][j] * hv[j]);
-        s = red_b(s);
-        if (lb == 0) dd[k * NUP + la * CB + i] = -s;
-      }
+        for (int j = 0; j < CB; ++j) sh[j] += (double)(Bm[i][j] * pv[i]);
+#pragma unroll
+      for (int j = 0; j < CB; ++j) hv[j] = (float)(rtv[j] + red_a(sh[j]));
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sd[i] = 0.0;
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int i = 0; i < CB; ++i)
+          sd[i] += (double)(hml[(k * CB * CB + i * CB + j) * 64 + lane] * hv[j]);
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sd[i] = red_b(sd[i]);
+      if (lb == 0)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) dd[k * NUP + la * CB + i] = -sd[i];
       wave_sync();
-      float dv[CB];
+      float dv[CB], cv[RB];
+      double se[RB];
 #pragma unroll
       for (int j = 0; j < CB; ++j) dv[j] = (float)dd[k * NUP + lb * CB + j];
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * dv[j]);
-        s = red_b(s);
-        const int idx = la * RB + i;
-        if (lb == 0) ef[k * NXP + idx] = (float)((double)cf[k * NXP + idx] + s);
+        cv[i] = cf[k * NXP + la * RB + i];
+        se[i] = 0.0;
       }
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) se[i] += (double)(Bm[i][j] * dv[j]);
+#pragma unroll
+      for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
+      if (lb == 0)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = (float)((double)cv[i] + se[i]);
     }
     __syncthreads();
     // (D) forward chain: xt_{k+1} = A_cl,k xt_k + e_k
+    wave_sync();
     for (int kk = 0; kk < N; ++kk) {
       if (w == kk) {
-        float xin[RB];
+        float xin[RB], sx[RB], ereg[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) ereg[i] = ef[kk * NXP + la * RB + i];
 #pragma unroll
         for (int j = 0; j < RB; ++j) xin[j] = xtf[kk * NXP + lb * RB + j];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          float s = 0.f;
+        for (int i = 0; i < RB; ++i) sx[i] = 0.f;
 #pragma unroll
-          for (int j = 0; j < RB; ++j) s += Acl[i][j] * xin[j];
-          s = red_b(s);
-          if (lb == 0) xtf[(kk + 1) * NXP + la * RB + i] = ef[kk * NXP + la * RB + i] + s;
-        }
+        for (int j = 0; j < RB; ++j)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] += Acl[i][j] * xin[j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) sx[i] = red_b(sx[i]);
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xtf[(kk + 1) * NXP + la * RB + i] = ereg[i] + sx[i];
       }
       __syncthreads();
     }
     // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
     {
       float xv[RB];
+      double su[CB], dvv[CB];
 #pragma unroll
       for (int j = 0; j < RB; ++j) xv[j] = xtf[k * NXP + la * RB + j];
 #pragma unroll
       for (int i = 0; i < CB; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xv[j]);
-        s = red_a(s);
-        if (la == 0) utd[k * NUP + lb * CB + i] = dd[k * NUP + lb * CB + i] + s;
+        dvv[i] = dd[k * NUP + lb * CB + i];
+        su[i] = 0.0;
       }
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) su[i] += (double)(Km[i][j] * xv[j]);
+#pragma unroll
+      for (int i = 0; i < CB; ++i) su[i] = red_a(su[i]);
+      if (la == 0)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) utd[k * NUP + lb * CB + i] = dvv[i] + su[i];
       wave_sync();
       if (k >= 1)
         for (int i = lane; i < NX; i += 64)

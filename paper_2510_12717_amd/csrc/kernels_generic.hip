@@ -21,6 +21,8 @@
 #include "mpc_internal.h"
 #include "stage_rows.h"
 
+#include <mutex>
+
 namespace mpc {
 
 template <typename T>
@@ -797,18 +799,33 @@ hipError_t launch_advance(const AgentDesc* d_desc, const int32_t* list, int n_la
   return hipGetLastError();
 }
 
+// The limits are per kernel and process-wide (every plan and server shares
+// them), so they only ever grow: a limit has no effect on occupancy, and
+// lowering it would break launches of an earlier plan.
 hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds_res) {
+  static std::mutex mu;
+  static size_t cur[3] = {0, 0, 0};
+  std::lock_guard<std::mutex> lock(mu);
   hipError_t e = hipSuccess;
 #define MPC_SET(kern, bytes)                                                                  \
   if (e == hipSuccess)                                                                        \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),                              \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(bytes));
-  MPC_SET(k_setup_factor<float>, lds_factor)
-  MPC_SET(k_setup_factor<double>, lds_factor)
-  MPC_SET(k_admm<float>, lds_admm)
-  MPC_SET(k_admm<double>, lds_admm)
-  MPC_SET(k_residual<float>, lds_res)
-  MPC_SET(k_residual<double>, lds_res)
+  if (lds_factor > cur[0]) {
+    MPC_SET(k_setup_factor<float>, lds_factor)
+    MPC_SET(k_setup_factor<double>, lds_factor)
+    if (e == hipSuccess) cur[0] = lds_factor;
+  }
+  if (lds_admm > cur[1]) {
+    MPC_SET(k_admm<float>, lds_admm)
+    MPC_SET(k_admm<double>, lds_admm)
+    if (e == hipSuccess) cur[1] = lds_admm;
+  }
+  if (lds_res > cur[2]) {
+    MPC_SET(k_residual<float>, lds_res)
+    MPC_SET(k_residual<double>, lds_res)
+    if (e == hipSuccess) cur[2] = lds_res;
+  }
 #undef MPC_SET
   return e;
 }

@@ -27,6 +27,7 @@
 #include <set>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -161,6 +162,7 @@ struct mpc_server_s {
   hipEvent_t ev_ref = nullptr;
   std::chrono::steady_clock::time_point t0;
   double t_ref = 0;  // server clock at ev_ref
+  int lds_max = 0;
   mpc_server_stats stats{};
 };
 
@@ -280,9 +282,10 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_st_out, sizeof(int32_t*) * B, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_status, sizeof(int32_t) * B, hipHostMallocDefault);
   }
-  if (e == hipSuccess) e = generic_set_lds_limits(generic_factor_lds(64, 32, s->esz),
-                                                  generic_admm_lds(64, 64, 32, 64, s->esz),
-                                                  sizeof(double) * 65 * 64);
+  int lds_max = 0;
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, sd.device);
+  s->lds_max = lds_max;
   if (e == hipSuccess && !s->fp64) e = fused_set_limits();
   if (e == hipSuccess) e = hipEventCreate(&s->ev_ref);
   if (e == hipSuccess) e = hipEventRecord(s->ev_ref, s->slots[0].stream);
@@ -333,6 +336,14 @@ static mpc_status submit_one(mpc_server_s* s, int64_t ctrl, const mpc_shape* sha
       !prob->x0 || !prob->mu || (sh.n_tau > 0 && !prob->tau_max) || (sh.n_feet > 0 && !prob->stance))
     return api_fail(MPC_ERR_INVALID_ARG, "null input pointer in request");
   if (prob->u_ref) return api_fail(MPC_ERR_INVALID_ARG, "requests take no input reference (u_ref must be NULL)");
+  const int m = ctrl_m(sh);
+  if ((int64_t)generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz) > s->lds_max ||
+      (int64_t)generic_factor_lds(sh.nx, sh.nu, s->esz) > s->lds_max)
+    return api_fail(MPC_ERR_UNSUPPORTED_SHAPE, "controller shape needs more LDS than the device offers");
+  // the generic kernels' LDS limits grow to what this shape needs
+  MPC_HIP_TRY(generic_set_lds_limits(generic_factor_lds(sh.nx, sh.nu, s->esz),
+                                     generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz),
+                                     sizeof(double) * (size_t)(sh.N + 1) * sh.nx));
   const int64_t need = to_units(state_elems(sh) * (int64_t)s->esz) + to_units(ws_bytes(s, sh));
   if (need > s->arena_bytes / kUnit)
     return api_fail(MPC_ERR_OUT_OF_MEMORY, "one request of this shape exceeds the HBM budget");
@@ -496,28 +507,27 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
   const int iters = s->desc.solver.admm_iters;
   for (const G& g : gl) {
     const int32_t* list = sl.d_list + g.off;
-    if (g.fam == 2) {
-      MPC_HIP_TRY(fused_solve_f32(sl.d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
-                                  *reinterpret_cast<Inputs<float>*>(&in), sc, iters, -1,
-                                  *reinterpret_cast<State<float>*>(&state),
-                                  (float*)s->arena_base, st, 3));
-    } else if (g.fam == 4) {
-      MPC_HIP_TRY(launch_mixed_factor(sl.d_desc, list, g.count, g.nx, g.nu,
-                                      s->desc.solver.precision == MPC_BF16_REFINE,
-                                      *reinterpret_cast<Inputs<float>*>(&in), sc,
-                                      (float*)s->arena_base, sl.d_status, st));
-      MPC_HIP_TRY(launch_generic_admm<float>(sl.d_desc, list, g.count,
-                                             *reinterpret_cast<Inputs<float>*>(&in), sc, iters, -1,
-                                             (const float*)s->arena_base,
-                                             *reinterpret_cast<State<float>*>(&state), g.lds_a,
-                                             256, st, s->desc.solver.max_refine_sweeps,
-                                             s->desc.solver.refine_tol));
-    } else {
-      MPC_HIP_TRY(launch_generic_factor<T>(sl.d_desc, list, g.count, in, sc, (T*)s->arena_base,
-                                           sl.d_status, g.lds_f, 256, st));
-      MPC_HIP_TRY(launch_generic_admm<T>(sl.d_desc, list, g.count, in, sc, iters, -1,
-                                         (const T*)s->arena_base, state, g.lds_a, 256, st));
+    if constexpr (std::is_same<T, float>::value) {
+      if (g.fam == 2) {
+        MPC_HIP_TRY(fused_solve_f32(sl.d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet, in, sc,
+                                    iters, -1, state, (float*)s->arena_base, st, 3));
+        continue;
+      }
+      if (g.fam == 4) {
+        MPC_HIP_TRY(launch_mixed_factor(sl.d_desc, list, g.count, g.nx, g.nu,
+                                        s->desc.solver.precision == MPC_BF16_REFINE, in, sc,
+                                        (float*)s->arena_base, sl.d_status, st));
+        MPC_HIP_TRY(launch_generic_admm<float>(sl.d_desc, list, g.count, in, sc, iters, -1,
+                                               (const float*)s->arena_base, state, g.lds_a, 256,
+                                               st, s->desc.solver.max_refine_sweeps,
+                                               s->desc.solver.refine_tol));
+        continue;
+      }
     }
+    MPC_HIP_TRY(launch_generic_factor<T>(sl.d_desc, list, g.count, in, sc, (T*)s->arena_base,
+                                         sl.d_status, g.lds_f, 256, st));
+    MPC_HIP_TRY(launch_generic_admm<T>(sl.d_desc, list, g.count, in, sc, iters, -1,
+                                       (const T*)s->arena_base, state, g.lds_a, 256, st));
   }
   int maxN = 1, maxnx = 1;
   for (const G& g : gl) {

@@ -51,6 +51,17 @@ class GroupInfo(ctypes.Structure):
                                               "threads", "lds_bytes")]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("solver", PlanDesc), ("hbm_budget_bytes", ctypes.c_int64),
+                ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "completed", "batches", "evictions", "pending", "inflight",
+        "resident_controllers", "resident_bytes", "arena_bytes", "arena_free_bytes")]
+
+
 class Solution(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "x", "u", "z", "y", "objective",
                                                "residuals", "status")]
@@ -61,6 +72,9 @@ EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_
            "mpc_get_solution", "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
            "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
            "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture", "mpc_plan_replay",
+           "mpc_server_desc_default", "mpc_server_create", "mpc_server_destroy",
+           "mpc_server_clock", "mpc_server_submit", "mpc_server_submit_many", "mpc_server_poll",
+           "mpc_server_drain", "mpc_server_get_state", "mpc_server_get_stats",
            "mpc_last_error", "mpc_version")
 
 _lib = None
@@ -91,6 +105,24 @@ def lib():
         L.mpc_plan_autotune.argtypes = [V, P(ProblemBatch), I32, V]
         L.mpc_plan_capture.argtypes = [V, P(ProblemBatch), V, V]
         L.mpc_plan_replay.argtypes = [V, V]
+        D = ctypes.c_double
+        L.mpc_server_desc_default.argtypes = [P(ServerDesc)]
+        L.mpc_server_desc_default.restype = None
+        L.mpc_server_create.argtypes = [P(ServerDesc), P(V)]
+        L.mpc_server_destroy.argtypes = [V]
+        L.mpc_server_clock.argtypes = [V]
+        L.mpc_server_clock.restype = D
+        L.mpc_server_submit.argtypes = [V, ctypes.c_int64, P(Shape), P(ProblemBatch), V, V, D,
+                                        P(ctypes.c_int64)]
+        L.mpc_server_submit_many.argtypes = [V, I32, V, V, V, V, V, V, V]
+        L.mpc_server_poll.argtypes = [V, V, V, I32, P(I32)]
+        L.mpc_server_drain.argtypes = [V]
+        L.mpc_server_get_state.argtypes = [V, ctypes.c_int64, V, V, V, V, V]
+        L.mpc_server_get_stats.argtypes = [V, P(ServerStats)]
+        for f in ("mpc_server_create", "mpc_server_destroy", "mpc_server_submit",
+                  "mpc_server_submit_many", "mpc_server_poll", "mpc_server_drain",
+                  "mpc_server_get_state", "mpc_server_get_stats"):
+            getattr(L, f).restype = ctypes.c_int
         for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
                   "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
                   "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
@@ -278,3 +310,117 @@ class Plan:
         _check(lib().mpc_plan_export_factor(self._h, int(agent), _ptr(K), _ptr(Acl), _ptr(Hi),
                                             _ptr(sv), _stream_handle(stream)))
         return K, Acl, Hi, sv
+
+
+def agent_problems(prob, batch, agents=None):
+    """Per-agent ``ProblemBatch`` records pointing into a device-resident batch
+    (``to_device`` output) -- the request data of a served controller."""
+    import torch
+    off = batch.offsets()
+    esz = prob["A"].element_size()
+    agents = range(batch.n_agents) if agents is None else agents
+    arr = (ProblemBatch * len(list(agents)))()
+    base = {k: prob[k].data_ptr() for k in ("A", "B", "c", "q", "r", "x_ref", "x0", "tau_max",
+                                            "mu", "stance")}
+    for j, a in enumerate(agents):
+        b = arr[j]
+        at = lambda k, key=None: int(base[k] + int(off[key or k][a]) * esz)
+        b.A, b.B, b.c = at("A"), at("B"), at("c")
+        b.q_diag, b.r_diag = at("q"), at("r")
+        b.x_ref, b.x0, b.tau_max = at("x_ref"), at("x0"), at("tau_max")
+        b.mu = int(base["mu"] + int(a) * esz)
+        b.stance = int(base["stance"] + int(off["stance"][a]))
+        b.u_ref = None
+        b.warm_start = 1
+    return arr
+
+
+class Server:
+    """Served request loop (see ``mpc_server_create``)."""
+
+    def __init__(self, precision: str = "fp32", iters: int = 50, hbm_budget_bytes: int = 1 << 30,
+                 max_batch: int = 4096, max_inflight: int = 3, device: int = 0, **consts):
+        L = lib()
+        d = ServerDesc()
+        L.mpc_server_desc_default(ctypes.byref(d))
+        d.solver.precision = PRECISIONS[precision]
+        d.solver.admm_iters = int(iters)
+        d.solver.device = int(device)
+        for k, v in consts.items():
+            setattr(d.solver, k, v)
+        d.hbm_budget_bytes = int(hbm_budget_bytes)
+        d.max_batch = int(max_batch)
+        d.max_inflight = int(max_inflight)
+        h = ctypes.c_void_p()
+        _check(L.mpc_server_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.dtype = "fp64" if precision == "fp64" else "fp32"
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().mpc_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self) -> float:
+        return lib().mpc_server_clock(self._h)
+
+    def submit(self, ctrl: int, shape, problem: "ProblemBatch", u0_out, warm: bool = True,
+               status_out=None, t_arrival: Optional[float] = None) -> int:
+        problem.warm_start = 1 if warm else 0
+        sh = Shape(*shape.as_tuple())
+        t = ctypes.c_int64()
+        ta = self.clock() if t_arrival is None else float(t_arrival)
+        _check(lib().mpc_server_submit(self._h, int(ctrl), ctypes.byref(sh), ctypes.byref(problem),
+                                       _ptr(u0_out), _ptr(status_out), ta, ctypes.byref(t)))
+        return t.value
+
+    def submit_many(self, ctrls: np.ndarray, shapes, problems, u0_ptrs: np.ndarray,
+                    t_arrival: np.ndarray) -> np.ndarray:
+        """Bulk submission: ``shapes``/``problems`` hold one Shape / ProblemBatch
+        record per request (ctypes arrays, or numpy arrays of the raw records),
+        ``u0_ptrs`` device addresses (uint64)."""
+        n = len(ctrls)
+        ctrls = np.ascontiguousarray(ctrls, dtype=np.int64)
+        u0 = np.ascontiguousarray(u0_ptrs, dtype=np.uint64)
+        ta = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        tk = np.empty(n, dtype=np.int64)
+        addr = lambda a: a.ctypes.data if isinstance(a, np.ndarray) else ctypes.addressof(a)
+        _check(lib().mpc_server_submit_many(self._h, n, ctrls.ctypes.data, addr(shapes),
+                                            addr(problems), u0.ctypes.data, None,
+                                            ta.ctypes.data, tk.ctypes.data))
+        return tk
+
+    def poll(self, cap: int = 1 << 16):
+        tk = np.empty(cap, dtype=np.int64)
+        tm = np.empty(cap, dtype=np.float64)
+        n = ctypes.c_int32()
+        _check(lib().mpc_server_poll(self._h, tk.ctypes.data, tm.ctypes.data, cap, ctypes.byref(n)))
+        return tk[:n.value], tm[:n.value]
+
+    def drain(self):
+        _check(lib().mpc_server_drain(self._h))
+
+    def get_state(self, ctrl: int, shape, stream=None):
+        import torch
+        td = torch.float64 if self.dtype == "fp64" else torch.float32
+        m = shape.nu + 4 * shape.n_feet
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = dict(x=torch.empty((shape.N + 1) * shape.nx, dtype=td, device=dev),
+                   u=torch.empty(shape.N * shape.nu, dtype=td, device=dev),
+                   z=torch.empty(shape.N * m, dtype=td, device=dev),
+                   y=torch.empty(shape.N * m, dtype=td, device=dev))
+        _check(lib().mpc_server_get_state(self._h, int(ctrl), _ptr(out["x"]), _ptr(out["u"]),
+                                          _ptr(out["z"]), _ptr(out["y"]), _stream_handle(stream)))
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().mpc_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2510_12717_amd import mpc
@@ -83,3 +85,37 @@ def test_null_arguments():
     assert L.mpc_solve(None, None, None) == mpc.MPC_ERR_INVALID_ARG
     assert L.mpc_get_solution(None, None, None) == mpc.MPC_ERR_INVALID_ARG
     assert L.mpc_plan_destroy(None) == mpc.MPC_ERR_INVALID_ARG
+
+
+def test_agent_problem_records_point_into_the_pool():
+    """Per-request records of a served controller address its slice of a pool
+    batch (checked on host tensors: only pointer arithmetic is involved)."""
+    torch = pytest.importorskip("torch")
+    b = synth.config2(7)
+    prob = {k: torch.from_numpy(v.astype(np.float32) if v.dtype != np.uint8 else v)
+            for k, v in (("A", b.A), ("B", b.B), ("c", b.c), ("q", b.q), ("r", b.r),
+                         ("x_ref", b.x_ref), ("x0", b.x0), ("tau_max", b.tau_max),
+                         ("mu", b.mu), ("stance", b.stance.astype(np.uint8)))}
+    recs = mpc.agent_problems(prob, b)
+    off = b.offsets()
+    for a in range(b.n_agents):
+        r = recs[a]
+        assert r.A == prob["A"].data_ptr() + 4 * int(off["A"][a])
+        assert r.x_ref == prob["x_ref"].data_ptr() + 4 * int(off["x_ref"][a])
+        assert r.mu == prob["mu"].data_ptr() + 4 * a
+        assert r.stance == prob["stance"].data_ptr() + int(off["stance"][a])
+        assert r.u_ref is None and r.warm_start == 1
+
+
+def test_server_rejects_bad_descriptions():
+    L = mpc.lib()
+    d = mpc.ServerDesc()
+    L.mpc_server_desc_default(ctypes.byref(d))
+    assert (d.max_batch, d.max_inflight, d.hbm_budget_bytes) == (4096, 3, 1 << 30)
+    for field, bad in (("max_batch", 0), ("max_inflight", 9), ("hbm_budget_bytes", 0)):
+        dd = mpc.ServerDesc()
+        L.mpc_server_desc_default(ctypes.byref(dd))
+        setattr(dd, field, bad)
+        h = ctypes.c_void_p()
+        assert L.mpc_server_create(ctypes.byref(dd), ctypes.byref(h)) == mpc.MPC_ERR_INVALID_ARG
+        assert not h.value

@@ -55,6 +55,10 @@ def parse():
                     help="approximate wall time budget of the CPU-oracle baseline (0 = skip)")
     ap.add_argument("--check-agents", type=int, default=64,
                     help="agents whose first-step solution is compared with the FP64 oracle")
+    ap.add_argument("--uneven", action="store_true",
+                    help="time the uneven batch instead (8192 agents, N ~ U{5..20}, half humanoid, "
+                         "half quadruped): autotuned launch groups, captured-graph steps "
+                         "(prints its own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="run the served request loop instead: Poisson arrivals from independent "
                          "controllers of uneven shapes (prints its own JSON line)")
@@ -62,7 +66,158 @@ def parse():
     ap.add_argument("--rate-hz", type=float, default=100.0, help="request rate per controller")
     ap.add_argument("--sim-seconds", type=float, default=2.0)
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 1 GiB (x5), the reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_BENCH", "WRITE_BENCH",
+                                                         "FETCH_COPY", "WRITE_COPY"),
+                    help="turn four rocprofv3 --pmc counter_collection.csv files into the "
+                         "traffic summary under profiles/ (no GPU needed)")
     return ap.parse_args()
+
+
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "traffic_k_admm_resident_humanoid4096.md")
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_digest():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2510_12717_amd", "csrc", "kernels_fused.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def _pmc_per_dispatch(path, name_part):
+    """Mean counter value (summed over the counter's instances) per dispatch of the
+    kernels whose name contains name_part."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    kcol = next(c for c in rows[0] if c.lower() in ("kernel_name", "kernel-name"))
+    vcol = next(c for c in rows[0] if c.lower() in ("counter_value", "counter-value"))
+    dcol = next(c for c in rows[0] if c.lower() in ("dispatch_id", "dispatch-id"))
+    per = {}
+    for r in rows:
+        if name_part in r[kcol]:
+            per[r[dcol]] = per.get(r[dcol], 0.0) + float(r[vcol])
+    if not per:
+        raise SystemExit(f"no dispatch of a kernel matching {name_part!r} in {path}")
+    return sum(per.values()) / len(per), len(per)
+
+
+def summarize_pmc(paths):
+    """Traffic of the iteration kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for a 1 GiB device copy."""
+    fb, wb, fc, wc = paths
+    kname = "k_admm_resident<48, 30>"
+    f_k, n_f = _pmc_per_dispatch(fb, "k_admm_resident")
+    w_k, n_w = _pmc_per_dispatch(wb, "k_admm_resident")
+    f_c, _ = _pmc_per_dispatch(fc, "copy")
+    w_c, _ = _pmc_per_dispatch(wc, "copy")
+    scale_r = f_c * 1024.0 / COPY_BYTES
+    scale_w = w_c * 1024.0 / COPY_BYTES
+    traffic = f_k * 1024.0 / scale_r + w_k * 1024.0 / scale_w
+    rec = {"kernel": kname, "source_digest": kernel_source_digest(),
+           "fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k,
+           "dispatches": [n_f, n_w], "copy_fetch_kib": f_c, "copy_write_kib": w_c,
+           "copy_bytes": COPY_BYTES, "read_scale": scale_r, "write_scale": scale_w,
+           "traffic_bytes_per_launch": traffic}
+    cmd = ("cd /tmp && timeout -s KILL 60 rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
+           "-o run -- python3 <repo>/bench.py {a}")
+    lines = ["# HBM traffic of the iteration kernel: config-1 workload (4096 humanoid agents, N=10, "
+             "50 iterations, FP32)", "",
+             "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of `" + kname + "`, each divided by the "
+             "ratio the same counter reads for a plain 1 GiB device copy (`bench.py --calibrate-copy`).",
+             "Commands (four passes, one counter each):", "", "```",
+             cmd.format(c="FETCH_SIZE", d="pmc_fetch_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
+             cmd.format(c="WRITE_SIZE", d="pmc_write_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
+             cmd.format(c="FETCH_SIZE", d="pmc_fetch_copy", a="--calibrate-copy"),
+             cmd.format(c="WRITE_SIZE", d="pmc_write_copy", a="--calibrate-copy"),
+             "python bench.py --summarize-pmc <the four counter_collection.csv files>", "```", "",
+             "| quantity | value |", "|---|---|",
+             f"| FETCH_SIZE per dispatch | {f_k:.0f} KiB |", f"| WRITE_SIZE per dispatch | {w_k:.0f} KiB |",
+             f"| copy: FETCH_SIZE / bytes read | {scale_r:.3f} |",
+             f"| copy: WRITE_SIZE / bytes written | {scale_w:.3f} |",
+             f"| traffic per launch | {traffic / 1e9:.3f} GB |", "",
+             "Machine-readable record (bench.py reports `traffic` from it while the kernel source "
+             "digest matches):", "", "```json", json.dumps(rec), "```", ""]
+    open(TRAFFIC_MD, "w").write("\n".join(lines))
+    print(json.dumps(rec))
+
+
+def recorded_traffic():
+    """Traffic per launch from the committed counter summary, or None if the kernel
+    source changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_MD).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_digest") != kernel_source_digest():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def calibrate_copy():
+    import torch
+    n = COPY_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": 5}))
+
+
+def uneven(args):
+    """Uneven batch: autotune the launch groups, capture one control step (warm
+    solve + plant step) into a HIP graph, time replays."""
+    import torch
+
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    n = args.agents if args.agents != 4096 else 8192
+    b = synth.config2(n, dtype=np.float32)
+    plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters)
+    prob = mpc.to_device(b, "fp32")
+    t_tune = time.perf_counter()
+    groups = plan.autotune(prob, reps=2)
+    t_tune = time.perf_counter() - t_tune
+    nx_tot = sum(s.nx for s in b.shapes)
+    noise = torch.empty(nx_tot, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(99)
+    plan.solve(prob)
+    plan.capture(prob, warm_start=True, noise=noise, x0_next=prob["x0"])
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        noise.normal_(0.0, 1e-2, generator=gen)
+        plan.replay(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        noise.normal_(0.0, 1e-2, generator=gen)
+        plan.replay(stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(c) for a, c in ev])
+    st = plan.get_solution()["status"]
+    out = {"metric": "MPC QP solves/sec, uneven batch (captured step, autotuned groups)",
+           "value": n * args.steps / wall, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} agents, N ~ U{{5..20}}, half humanoid (48, 30), half "
+                                  "quadruped (36, 24), stance p ~ U[0.3, 0.9] per foot, "
+                                  f"{args.iters} warm-started iterations", "agents": n,
+                      "admm_iters": args.iters},
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+           "groups": [(g["family"], g["nx"], g["N"], g["n_agents"], g["threads"]) for g in groups],
+           "autotune_s": t_tune, "status_ok": bool((st == 0).all().item())}
+    print(json.dumps(out))
 
 
 def serve(args):
@@ -106,27 +261,30 @@ def serve(args):
     srv.submit_many(np.arange(nc), rec_s, rec_p, u0_ptr, np.zeros(nc))
     srv.drain()
     srv.poll(cap=nc + 16)
-    arrival = {}
+    # tickets are consecutive integers: arrival times indexed by ticket
+    t_arr = np.full(len(at) + nc + 16, np.nan)
     lat = []
     t0 = srv.clock()
-    i, n = 0, len(at)
-    while i < n or len(arrival):
+    i, n, outstanding = 0, len(at), 0
+    while i < n or outstanding:
         now = srv.clock() - t0
         j = np.searchsorted(at, now, side="right")
         if j > i:
             idx = ac[i:j]
             tk = srv.submit_many(idx, rec_s[idx], rec_p[idx], u0_ptr[idx], t0 + at[i:j])
-            for k, t in zip(tk.tolist(), (t0 + at[i:j]).tolist()):
-                arrival[k] = t
+            t_arr[tk] = t0 + at[i:j]
+            outstanding += j - i
             i = j
         tk, tm = srv.poll()
-        for k, t in zip(tk.tolist(), tm.tolist()):
-            lat.append(t - arrival.pop(k))
-        if i >= n and arrival:
+        if len(tk):
+            lat.append(tm - t_arr[tk])
+            outstanding -= len(tk)
+        if i >= n and outstanding:
             srv.drain()
+    lat = np.concatenate(lat) if lat else np.zeros(1)
     t_end = srv.clock() - t0
     st = srv.stats()
-    lat = np.array(lat) * 1e3
+    lat = lat * 1e3
     out = {"metric": "served MPC QP solves/sec with p50/p95/p99 arrival-to-result latency",
            "value": n / t_end, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
            "dtype": "f32", "data": "synthetic",
@@ -149,8 +307,17 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(agents shard across GPUs with no exchange, see DESIGN.md)"}))
         sys.exit(2)
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.serve:
         serve(args)
+        return
+    if args.uneven:
+        uneven(args)
         return
     import torch
 
@@ -224,8 +391,9 @@ def main():
     achieved = fl_iter / avg_admm_s
     kname = ("k_admm_resident<%d, %d>" % (shape.nx, shape.nu) if cfg["kernel"] == "fused"
              else "k_admm<%s>" % ("double" if args.precision == "fp64" else "float"))
+    traffic = recorded_traffic() if cfg["kernel"] == "fused" else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "kernel": kname, "avg_launch_ms": avg_admm_s * 1e3,
                 "flops_per_launch": fl_iter}
 

@@ -11,14 +11,19 @@ namespace mpc {
 
 // True if the register-resident kernels have an instantiation for this shape.
 bool fused_supported(int N, int nx, int nu, int n_feet);
-// Threads per workgroup and dynamic LDS bytes of the iteration kernel for the shape.
+// Horizon bucket of the register-resident launch groups: horizons up to 6 share
+// a launch of at most 6 wavefronts per agent (two agents fit one compute
+// unit), longer ones a launch of up to 12.
+inline int fused_bucket(int N) { return N <= 6 ? 0 : 1; }
+// Threads per workgroup and dynamic LDS bytes of the iteration kernel for a
+// launch whose longest horizon is N.
 void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds);
 // Floats of operator workspace one agent of this shape class needs.
 size_t fused_agent_floats(int nx, int nu);
 // Raise the dynamic-LDS limits of every register-resident kernel (once per device).
 hipError_t fused_set_limits();
-// Launch for the n_launch agents list[0..n_launch) (all of one shape class and
-// horizon N).  phase_mask: 1 = factor kernel, 2 = iteration kernel.
+// Launch for the n_launch agents list[0..n_launch) (all of one shape class,
+// horizons at most N).  phase_mask: 1 = factor kernel, 2 = iteration kernel.
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
                            int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
                            int warm, State<float> st, float* fws, hipStream_t stream,

@@ -32,6 +32,7 @@
 
 #include "fused.h"
 #include "stage_rows.h"
+#include "xlane.h"
 
 namespace mpc {
 namespace {
@@ -62,19 +63,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Cross-lane moves without the LDS crossbar: DPP within rows of 16 lanes,
-// v_permlane16_swap / v_permlane32_swap across rows (gfx950).
-template <int C>
-__device__ inline float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), C, 0xF, 0xF, false));
-}
-template <int C>
-__device__ inline double dpp(double v) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, C, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), C, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
 // v + (the same register of the lane 16 or 32 lanes away): permlane swaps hand
 // each lane its partner's value; both lanes of a pair add in the same order.
 __device__ inline float swap_sum16(float v) {
@@ -118,6 +106,28 @@ __device__ inline T red_a(T v) {
   v = swap_sum16(v);
   v = swap_sum32(v);
   return v;
+}
+
+// Reduce-scatter over the 8 lanes b, b+8, .., b+56 (the a index): v[0..7] of
+// every lane in, and lane (a, b) returns the sum over a' of v[a] of lane
+// (a', b).  Three exchange levels move 4 + 2 + 1 values instead of 8 x 3:
+// v_permlane32_swap pairs a with a ^ 4, v_permlane16_swap a with a ^ 2 (each
+// returns the pair sum of one kept index per lane), DPP row_ror 8 a with a ^ 1.
+__device__ inline float rscatter_a(const float (&v)[8], int lane) {
+  float w[4], u[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[t]), __float_as_uint(v[4 + t]), false, false);
+    w[t] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[t]), __float_as_uint(w[2 + t]), false, false);
+    u[t] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool a0 = (lane >> 3) & 1;
+  const float mine = a0 ? u[1] : u[0], send = a0 ? u[0] : u[1];
+  return mine + dpp<0x128>(send);
 }
 
 // One 16x16 output tile of C = op(A) op(B) on the FP64 matrix cores.
@@ -193,7 +203,7 @@ template <int NX, int NU>
 constexpr int riccati_lds_bytes() {
   using S = FS<NX, NU>;
   return 8 * (3 * S::NXT * S::LX + 2 * S::NXT * S::LU + S::NUT * S::LX + S::NUT * S::LU +
-              S::NUT + S::MMAX + S::NXT + 4 * S::NUT) + 16;
+              S::NUT + S::MMAX + S::NXT + 8 * S::NUT) + 16;
 }
 
 // PREC == kProdF64: operators go to the register-resident layout at fws + ofw.
@@ -227,8 +237,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   double* rhok = rdg + NUT;                   // row penalties       MMAX
   double* ck = rhok + S::MMAX;                // c_k                 NXT
   double* xcol = ck + NXT;                    // Gauss-Jordan pivot column / row exchange
-  double* xrow = xcol + 2 * NUT;              //   (two buffers each)
-  int* flag = reinterpret_cast<int*>(xrow + 2 * NUT);
+  double* xrow = xcol + 4 * NUT;              //   (two buffers of 2 NUT each)
+  int* flag = reinterpret_cast<int*>(xrow + 4 * NUT);
 
   const float* A = in.A + d.oA;
   const float* B = in.B + d.oB;
@@ -271,11 +281,32 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     return;
   }
 
+  // A_k and B_k of the next stage are fetched into registers one stage ahead,
+  // so their global-load latency hides behind the current stage.
+  constexpr int kT = 64 * kFactorWaves;
+  constexpr int PFA = (NX * NX + kT - 1) / kT, PFB = (NX * NU + kT - 1) / kT;
+  float pfa[PFA], pfb[PFB];
+  auto prefetch = [&](int kk) {
+    const float* Ag = A + (int64_t)kk * NX * NX;
+    const float* Bg = B + (int64_t)kk * NX * NU;
+#pragma unroll
+    for (int t = 0; t < PFA; ++t) pfa[t] = tid + t * kT < NX * NX ? Ag[tid + t * kT] : 0.f;
+#pragma unroll
+    for (int t = 0; t < PFB; ++t) pfb[t] = tid + t * kT < NX * NU ? Bg[tid + t * kT] : 0.f;
+  };
+  prefetch(N - 1);
   for (int k = N - 1; k >= 0; --k) {
-    const float* Ag = A + (int64_t)k * NX * NX;
-    const float* Bg = B + (int64_t)k * NX * NU;
-    for (int i = tid; i < NX * NX; i += nt) Ak[(i / NX) * LX + i % NX] = (double)Ag[i];
-    for (int i = tid; i < NX * NU; i += nt) Bk[(i / NU) * LU + i % NU] = (double)Bg[i];
+#pragma unroll
+    for (int t = 0; t < PFA; ++t) {
+      const int i = tid + t * kT;
+      if (i < NX * NX) Ak[(i / NX) * LX + i % NX] = (double)pfa[t];
+    }
+#pragma unroll
+    for (int t = 0; t < PFB; ++t) {
+      const int i = tid + t * kT;
+      if (i < NX * NU) Bk[(i / NU) * LU + i % NU] = (double)pfb[t];
+    }
+    if (k > 0) prefetch(k - 1);
     for (int i = tid; i < M; i += nt) {
       double lo, hi;
       row_bounds<double, float>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rhok[i]);
@@ -342,51 +373,71 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       }
     }
     __syncthreads();
-    // H_k^{-1} in place by Gauss-Jordan sweeps without pivoting over the padded
-    // NUT x NUT matrix (padding is the identity).  H_k is SPD, so every pivot is
-    // a squared Cholesky diagonal and a pivot <= 0 means H_k is not positive
-    // definite.  Every thread of the workgroup keeps EPT consecutive entries of
-    // one row in registers; each sweep publishes the pivot row and column
-    // through a double-buffered LDS exchange, so one barrier per sweep orders
-    // a buffer's writes after its previous readers.
+    // H_k^{-1} in place by block Gauss-Jordan sweeps without pivoting over the
+    // padded NUT x NUT matrix (padding is the identity), eliminating the 2x2
+    // pivot block P = H[j..j+1][j..j+1] per sweep:
+    //   P <- P^{-1},  H[p][o] <- P^{-1} H[p][o],  H[o][p] <- -H[o][p] P^{-1},
+    //   H[o][o] <- H[o][o] - H[o][p] P^{-1} H[p][o].
+    // H_k is SPD, so every pivot block is SPD (a Schur complement); a pivot
+    // block that is not (P00 <= 0 or det P <= 0) means H_k is not positive
+    // definite.  Every thread keeps two entries of one row (an even column
+    // pair, so both lie inside or both outside a pivot block) in registers;
+    // each sweep publishes the pivot rows and columns through a
+    // double-buffered LDS exchange, so one barrier per sweep orders a
+    // buffer's writes after its previous readers.
     {
       static_assert(NUT * NUT == 2 * 64 * kFactorWaves, "two entries per thread");
-      constexpr int EPT = 2, TPR = NUT / EPT;  // entries per thread, threads per row
-      const int row = tid / TPR, c0 = (tid % TPR) * EPT;
-      double h[EPT];
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) h[e] = H[row * LU + c0 + e];
+      constexpr int TPR = NUT / 2;  // threads per row
+      const int row = tid / TPR, c0 = (tid % TPR) * 2;
+      double h0 = H[row * LU + c0], h1 = H[row * LU + c0 + 1];
       bool bad = false;
-      for (int j = 0; j < NUT; ++j) {
-        double* xc = xcol + (j & 1) * NUT;
-        double* xr = xrow + (j & 1) * NUT;
-        if (j >= c0 && j < c0 + EPT) xc[row] = h[j - c0];
-        if (row == j)
-#pragma unroll
-          for (int e = 0; e < EPT; ++e) xr[c0 + e] = h[e];
+      for (int j = 0; j < NUT; j += 2) {
+        double* xc = xcol + ((j >> 1) & 1) * 2 * NUT;  // [row][2]: columns j, j+1
+        double* xr = xrow + ((j >> 1) & 1) * 2 * NUT;  // [2][col]: rows j, j+1
+        if (c0 == j) {
+          xc[2 * row] = h0;
+          xc[2 * row + 1] = h1;
+        }
+        if ((row >> 1) == (j >> 1)) {
+          xr[(row - j) * NUT + c0] = h0;
+          xr[(row - j) * NUT + c0 + 1] = h1;
+        }
         __syncthreads();
-        const double piv = xr[j];
-        if (!(piv > 0.0)) {  // the same value in every thread: a uniform exit
+        const double a = xr[j], b = xr[j + 1], dd = xr[NUT + j + 1];
+        const double det = a * dd - b * b;
+        if (!(a > 0.0) || !(det > 0.0)) {  // the same values in every thread: a uniform exit
           bad = true;
           break;
         }
-        const double ip = 1.0 / piv;
-        const double cr = xc[row] * ip;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int cc = c0 + e;
-          const double rv = xr[cc];
-          if (row == j)
-            h[e] = cc == j ? ip : rv * ip;
-          else
-            h[e] = cc == j ? -cr : h[e] - cr * rv;
+        const double id = 1.0 / det;
+        const double i00 = dd * id, i01 = -b * id, i11 = a * id;  // P^{-1} (symmetric)
+        const bool rp = (row >> 1) == (j >> 1), cp = c0 == j;
+        if (rp && cp) {
+          const int t = row - j;
+          h0 = t == 0 ? i00 : i01;
+          h1 = t == 0 ? i01 : i11;
+        } else if (rp) {
+          const int t = row - j;
+          const double w0 = t == 0 ? i00 : i01, w1 = t == 0 ? i01 : i11;
+          h0 = w0 * xr[c0] + w1 * xr[NUT + c0];
+          h1 = w0 * xr[c0 + 1] + w1 * xr[NUT + c0 + 1];
+        } else {
+          const double q0 = xc[2 * row], q1 = xc[2 * row + 1];
+          const double v0 = q0 * i00 + q1 * i01, v1 = q0 * i01 + q1 * i11;  // H[o][p] P^{-1}
+          if (cp) {
+            h0 = -v0;
+            h1 = -v1;
+          } else {
+            h0 -= v0 * xr[c0] + v1 * xr[NUT + c0];
+            h1 -= v0 * xr[c0 + 1] + v1 * xr[NUT + c0 + 1];
+          }
         }
       }
       if (bad) {
         if (tid == 0) flag[1] = 1;
       } else {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) H[row * LU + c0 + e] = h[e];
+        H[row * LU + c0] = h0;
+        H[row * LU + c0 + 1] = h1;
       }
     }
     __syncthreads();
@@ -611,8 +662,9 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   // H_k^{-1} is used once per iteration: it stays in LDS, in register order
   {
     const float* src = fws + d.ofw + ((int64_t)w * SLOTS + RB * RB + 2 * CB * RB) * 64 + lane;
+    if (w < N)
 #pragma unroll
-    for (int e = 0; e < CB * CB; ++e) hml[(w * CB * CB + e) * 64 + lane] = src[e * 64];
+      for (int e = 0; e < CB * CB; ++e) hml[(w * CB * CB + e) * 64 + lane] = src[e * 64];
   }
   const float* sk = fws + d.ofw + (int64_t)kMaxStages * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
@@ -640,7 +692,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   __syncthreads();
 
   const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
-  const int k = w;  // this wavefront's stage (blockDim = 64 N)
+  const int k = w;  // this wavefront's stage (blockDim = 64 N_launch, N_launch >= N)
 
   // x^0: rollout of the dynamics under u^0, as x_{k+1} = A_cl x + B (u - K x) + c
   for (int kk = 0; kk < N; ++kk) {
@@ -681,65 +733,68 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         opaque(Bm[j][i]);
       }
     // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k; wavefront N-1 also p_N
-    if (lane < NUP) {
-      double v = 0.0;
-      if (lane < NU) {
-        const double* yk = yd + k * M;
-        const double* zk = zd + k * M;
-        const double* rk = rhod + k * M;
-        auto wv = [&](int i) { return yk[i] - rk[i] * zk[i]; };
-        v = wv(lane);
-        if (lane >= d.n_tau) {
-          const int f = (lane - d.n_tau) / d.foot_dim, cc = (lane - d.n_tau) % d.foot_dim;
-          const int b0 = NU + 4 * f;
-          if (cc == 0) v += wv(b0) - wv(b0 + 1);
-          if (cc == 1) v += wv(b0 + 2) - wv(b0 + 3);
-          if (cc == 2) v -= mu * (wv(b0) + wv(b0 + 1) + wv(b0 + 2) + wv(b0 + 3));
+    // (a launch may be wider than this agent: wavefronts past its horizon idle,
+    // joining only the workgroup barriers)
+    if (w < N) {
+      if (lane < NUP) {
+        double v = 0.0;
+        if (lane < NU) {
+          const double* yk = yd + k * M;
+          const double* zk = zd + k * M;
+          const double* rk = rhod + k * M;
+          auto wv = [&](int i) { return yk[i] - rk[i] * zk[i]; };
+          v = wv(lane);
+          if (lane >= d.n_tau) {
+            const int f = (lane - d.n_tau) / d.foot_dim, cc = (lane - d.n_tau) % d.foot_dim;
+            const int b0 = NU + 4 * f;
+            if (cc == 0) v += wv(b0) - wv(b0 + 1);
+            if (cc == 1) v += wv(b0 + 2) - wv(b0 + 3);
+            if (cc == 2) v -= mu * (wv(b0) + wv(b0 + 1) + wv(b0 + 2) + wv(b0 + 3));
+          }
+          v += -sigma * ud[k * NUP + lane];
+          if (uref) v -= (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
         }
-        v += -sigma * ud[k * NUP + lane];
-        if (uref) v -= (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
+        rtd[k * NUP + lane] = v;
       }
-      rtd[k * NUP + lane] = v;
-    }
-    if (k == N - 1)
-      for (int i = lane; i < NX; i += 64)
-        pbuf[N * NXP + i] = (float)(-qd[i] * xrd[N * NXP + i] - sigma * xd[N * NXP + i]);
-    wave_sync();
-    // Every product below forms all its partial sums first, then all its
-    // butterflies, then one guarded store, so the independent chains
-    // interleave instead of serialising behind the store's branch.
-    if (k >= 1) {
-      float rv[CB];
-      double sg[RB];
+      if (k == N - 1)
+        for (int i = lane; i < NX; i += 64)
+          pbuf[N * NXP + i] = (float)(-qd[i] * xrd[N * NXP + i] - sigma * xd[N * NXP + i]);
+      wave_sync();
+      // Every product below forms all its partial sums first, then all its
+      // butterflies, then one guarded store, so the independent chains
+      // interleave instead of serialising behind the store's branch.
+      if (k >= 1) {
+        float rv[CB];
+        double sg[RB];
 #pragma unroll
-      for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
+        for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) sg[j] = 0.0;
+        for (int j = 0; j < RB; ++j) sg[j] = 0.0;
 #pragma unroll
-      for (int i = 0; i < CB; ++i)
+        for (int i = 0; i < CB; ++i)
 #pragma unroll
-        for (int j = 0; j < RB; ++j) sg[j] += (double)(Km[i][j] * rv[i]);
+          for (int j = 0; j < RB; ++j) sg[j] += (double)(Km[i][j] * rv[i]);
 #pragma unroll
-      for (int j = 0; j < RB; ++j) sg[j] = red_b(sg[j]);
-      if (lb == 0)
+        for (int j = 0; j < RB; ++j) sg[j] = red_b(sg[j]);
+        if (lb == 0)
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-          const int idx = la * RB + j;
-          gf[k * NXP + idx] =
-              (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) + sg[j]);
-        }
+          for (int j = 0; j < RB; ++j) {
+            const int idx = la * RB + j;
+            gf[k * NXP + idx] =
+                (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) + sg[j]);
+          }
+      }
     }
     // (B) backward chain, one hop per barrier: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
     wave_sync();
     for (int kk = N - 1; kk >= 0; --kk) {
       if (w == kk) {
         // s_k and g_k are this wavefront's own: their loads issue with p_{k+1}'s
-        float pin[RB], sp[RB], sreg[RB], greg[RB];
+        static_assert(RB <= 8, "one output per lane of an 8-lane group");
+        float pin[RB], sreg[RB], sp[8];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          sreg[i] = sf[kk * NXP + la * RB + i];
-          greg[i] = gf[kk * NXP + lb * RB + i];
-        }
+        for (int i = 0; i < RB; ++i) sreg[i] = sf[kk * NXP + la * RB + i];
+        const float greg = (la < RB && kk >= 1) ? gf[kk * NXP + lb * RB + la] : 0.f;
 #pragma unroll
         for (int i = 0; i < RB; ++i) pin[i] = pbuf[(kk + 1) * NXP + la * RB + i] + sreg[i];
         if (lb == 0)
@@ -747,22 +802,20 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
           for (int i = 0; i < RB; ++i) ppf[kk * NXP + la * RB + i] = pin[i];
         if (kk >= 1) {
 #pragma unroll
-          for (int j = 0; j < RB; ++j) sp[j] = 0.f;
+          for (int j = 0; j < 8; ++j) sp[j] = 0.f;
 #pragma unroll
           for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int j = 0; j < RB; ++j) sp[j] += Acl[i][j] * pin[i];
-#pragma unroll
-          for (int j = 0; j < RB; ++j) sp[j] = red_a(sp[j]);
-          if (la == 0)
-#pragma unroll
-            for (int j = 0; j < RB; ++j) pbuf[kk * NXP + lb * RB + j] = greg[j] + sp[j];
+          // lane (a, b) ends with output column b*RB + a
+          const float pk = rscatter_a(sp, lane);
+          if (la < RB) pbuf[kk * NXP + lb * RB + la] = greg + pk;
         }
       }
       __syncthreads();
     }
     // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
-    {
+    if (w < N) {
       float pv[RB], hv[CB];
       double sh[CB], sd[CB], rtv[CB];
 #pragma unroll
@@ -835,7 +888,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       __syncthreads();
     }
     // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
-    {
+    if (w < N) {
       float xv[RB];
       double su[CB], dvv[CB];
 #pragma unroll

@@ -20,6 +20,7 @@
 
 #include "mpc_internal.h"
 #include "stage_rows.h"
+#include "xlane.h"
 
 #include <mutex>
 
@@ -621,6 +622,9 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
+  // every dot product is split over the 4 lanes of a quad (terms t = sub,
+  // sub + 4, ...) and summed with DPP; nq quads cover the outputs
+  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
   __shared__ double red[256];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lam = reinterpret_cast<double*>(smem_raw);  // (N+1)*nx
@@ -654,45 +658,63 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
     const double ee = (double)u[idx] - (uref ? (double)uref[idx] : 0.0);
     obj += 0.5 * (double)r[idx % nu] * ee * ee;
   }
+  // costates of the dynamics rows: lambda_N = Q(x_N - r_N),
+  // lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}
   for (int i = tid; i < nx; i += nt)
     lam[N * nx + i] = (double)q[i] * ((double)x[N * nx + i] - (double)xr[N * nx + i]);
   __syncthreads();
   for (int k = N - 1; k >= 1; --k) {
-    for (int i = tid; i < nx; i += nt) {
-      double acc = (double)q[i] * ((double)x[k * nx + i] - (double)xr[k * nx + i]);
-      const T* Ac = A + (int64_t)k * nx * nx + i;
-      for (int t = 0; t < nx; ++t) acc += (double)Ac[t * nx] * lam[(k + 1) * nx + t];
-      lam[k * nx + i] = acc;
+    for (int i0 = 0; i0 < nx; i0 += nq) {
+      const int i = i0 + qd;  // a quad shares i: whole quads are active or not
+      if (i < nx) {
+        const T* Ac = A + (int64_t)k * nx * nx + i;
+        double acc = 0.0;
+        for (int t = sub; t < nx; t += 4) acc += (double)Ac[t * nx] * lam[(k + 1) * nx + t];
+        acc = quad_sum(acc);
+        if (sub == 0) lam[k * nx + i] = (double)q[i] * ((double)x[k * nx + i] - (double)xr[k * nx + i]) + acc;
+      }
     }
     __syncthreads();
   }
   double rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
   for (int i = tid; i < nx; i += nt) ry = fmax(ry, fabs((double)x[i] - (double)x0[i]));
-  for (int idx = tid; idx < N * nu; idx += nt) {
-    const int k = idx / nu, j = idx % nu;
-    double acc = (double)r[j] * ((double)u[idx] - (uref ? (double)uref[idx] : 0.0));
-    const T* Bc = B + (int64_t)k * nx * nu + j;
-    for (int t = 0; t < nx; ++t) acc += (double)Bc[t * nu] * lam[(k + 1) * nx + t];
-    // (C' y)_j
-    const T* yk = y + k * m;
-    double v = (double)yk[j];
-    if (j >= d.n_tau) {
-      const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
-      const T* yp = yk + nu + 4 * f;
-      if (cc == 0) v += (double)yp[0] - (double)yp[1];
-      if (cc == 1) v += (double)yp[2] - (double)yp[3];
-      if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
+  // dual residual of the inputs: R(u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k
+  for (int o0 = 0; o0 < N * nu; o0 += nq) {
+    const int o = o0 + qd;
+    if (o < N * nu) {
+      const int k = o / nu, j = o % nu;
+      const T* Bc = B + (int64_t)k * nx * nu + j;
+      double acc = 0.0;
+      for (int t = sub; t < nx; t += 4) acc += (double)Bc[t * nu] * lam[(k + 1) * nx + t];
+      acc = quad_sum(acc);
+      if (sub == 0) {
+        acc += (double)r[j] * ((double)u[o] - (uref ? (double)uref[o] : 0.0));
+        const T* yk = y + k * m;
+        double v = (double)yk[j];
+        if (j >= d.n_tau) {
+          const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
+          const T* yp = yk + nu + 4 * f;
+          if (cc == 0) v += (double)yp[0] - (double)yp[1];
+          if (cc == 1) v += (double)yp[2] - (double)yp[3];
+          if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
+        }
+        rd = fmax(rd, fabs(acc + v));
+      }
     }
-    rd = fmax(rd, fabs(acc + v));
   }
-  for (int idx = tid; idx < N * nx; idx += nt) {
-    const int k = idx / nx, i = idx % nx;
-    double acc = (double)x[(k + 1) * nx + i] - (double)c[idx];
-    const T* Ar = A + (int64_t)k * nx * nx + i * nx;
-    const T* Br = B + (int64_t)k * nx * nu + i * nu;
-    for (int t = 0; t < nx; ++t) acc -= (double)Ar[t] * (double)x[k * nx + t];
-    for (int t = 0; t < nu; ++t) acc -= (double)Br[t] * (double)u[k * nu + t];
-    ry = fmax(ry, fabs(acc));
+  // dynamics residual x_{k+1} - A_k x_k - B_k u_k - c_k
+  for (int o0 = 0; o0 < N * nx; o0 += nq) {
+    const int o = o0 + qd;
+    if (o < N * nx) {
+      const int k = o / nx, i = o % nx;
+      const T* Ar = A + (int64_t)k * nx * nx + i * nx;
+      const T* Br = B + (int64_t)k * nx * nu + i * nu;
+      double acc = 0.0;
+      for (int t = sub; t < nx; t += 4) acc += (double)Ar[t] * (double)x[k * nx + t];
+      for (int t = sub; t < nu; t += 4) acc += (double)Br[t] * (double)u[k * nu + t];
+      acc = quad_sum(acc);
+      if (sub == 0) ry = fmax(ry, fabs((double)x[(k + 1) * nx + i] - (double)c[o] - acc));
+    }
   }
   for (int idx = tid; idx < N * m; idx += nt) {
     const int k = idx / m, i = idx % m;

@@ -255,7 +255,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       }
       const bool use_fused = fok && desc->kernel != 1 && !mixed;
       const int fam = mixed ? 4 : use_fused ? 2 : 1;
-      buckets[std::make_tuple(fam, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim, use_fused ? s.N : 0)]
+      buckets[std::make_tuple(fam, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim,
+                              use_fused ? fused_bucket(s.N) : 0)]
           .push_back(a);
     }
     for (auto& kv : buckets) {

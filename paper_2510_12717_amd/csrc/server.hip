@@ -118,9 +118,13 @@ struct Request {
   double t_arrival = 0;
 };
 
+constexpr int kSlotStreams = 4;  // streams per batch slot: the slot's own plus three
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  hipStream_t aux[kSlotStreams - 1] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kSlotStreams - 1] = {};
   bool busy = false;
   // device
   AgentDesc* d_desc = nullptr;
@@ -194,6 +198,11 @@ static int64_t to_units(int64_t bytes) { return (bytes + kUnit - 1) / kUnit; }
 static void free_slot_buffers(Slot& sl) {
   if (sl.stream) hipStreamDestroy(sl.stream);
   if (sl.done) hipEventDestroy(sl.done);
+  for (int i = 0; i < kSlotStreams - 1; ++i) {
+    if (sl.aux[i]) hipStreamDestroy(sl.aux[i]);
+    if (sl.ev_join[i]) hipEventDestroy(sl.ev_join[i]);
+  }
+  if (sl.ev_fork) hipEventDestroy(sl.ev_fork);
   hipFree(sl.d_desc);
   hipFree(sl.d_list);
   hipFree(sl.d_u0);
@@ -269,6 +278,11 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   for (auto& sl : s->slots) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_fork, hipEventDisableTiming);
+    for (int i = 0; i < kSlotStreams - 1 && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&sl.aux[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_join[i], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_desc, sizeof(AgentDesc) * B);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_list, sizeof(int32_t) * B);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_u0, sizeof(void*) * B);
@@ -452,7 +466,7 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
   if (misaligned) return api_fail(MPC_ERR_INVALID_ARG, "request arrays are not element-aligned");
   const SolverConsts sc{s->desc.solver.rho, s->desc.solver.sigma, s->desc.solver.alpha,
                         s->desc.solver.rho_eq_scale, s->desc.solver.rho_min};
-  // groups: (family, nx, nu, n_tau, n_feet, foot_dim, N for register-resident)
+  // groups: (family, nx, nu, n_tau, n_feet, foot_dim, horizon bucket for register-resident)
   std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> groups;
   for (int i = 0; i < n; ++i) {
     const Request& r = sl.reqs[i];
@@ -476,7 +490,8 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
     const int64_t wb = sl.ws_off[i] * kUnit;
     d.ows = wb / (int64_t)s->esz;
     d.ofw = fam == 2 ? wb / 4 : -1;
-    groups[std::make_tuple(fam, sh.nx, sh.nu, sh.n_tau, sh.n_feet, sh.foot_dim, fam == 2 ? sh.N : 0)]
+    groups[std::make_tuple(fam, sh.nx, sh.nu, sh.n_tau, sh.n_feet, sh.foot_dim,
+                           fam == 2 ? fused_bucket(sh.N) : 0)]
         .push_back(i);
     sl.h_u0[i] = r.u0_out;
     sl.h_st_out[i] = r.status_out;
@@ -486,7 +501,9 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
   struct G { int fam, N, nx, nu, n_feet, off, count; size_t lds_f, lds_a; };
   std::vector<G> gl;
   for (auto& kv : groups) {
-    const std::vector<int32_t>& v = kv.second;
+    std::vector<int32_t>& v = kv.second;
+    // longest horizon first so the tail of a launch is short
+    std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) { return desc[x].N > desc[y].N; });
     G g{std::get<0>(kv.first), 0, std::get<1>(kv.first), std::get<2>(kv.first),
         std::get<4>(kv.first), pos, (int)v.size(), 0, 0};
     for (int32_t i : v) {
@@ -505,8 +522,20 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
   State<T> state{(T*)s->arena_base, (T*)s->arena_base, (T*)s->arena_base, (T*)s->arena_base,
                  (T*)sl.d_obj, sl.d_res, sl.d_status};
   const int iters = s->desc.solver.admm_iters;
-  for (const G& g : gl) {
+  // groups spread over the slot's streams, forked from and joined back into its own
+  std::stable_sort(gl.begin(), gl.end(), [](const G& x, const G& y) {
+    return (int64_t)x.count * x.N * (x.nx + x.nu) > (int64_t)y.count * y.N * (y.nx + y.nu);
+  });
+  const int ns = std::min<int>(kSlotStreams, (int)gl.size());
+  if (ns > 1) {
+    MPC_HIP_TRY(hipEventRecord(sl.ev_fork, sl.stream));
+    for (int i = 0; i < ns - 1; ++i) MPC_HIP_TRY(hipStreamWaitEvent(sl.aux[i], sl.ev_fork, 0));
+  }
+  for (size_t gi = 0; gi < gl.size(); ++gi) {
+    const G& g = gl[gi];
     const int32_t* list = sl.d_list + g.off;
+    const int si = (int)(gi % ns);
+    hipStream_t st = si == 0 ? sl.stream : sl.aux[si - 1];
     if constexpr (std::is_same<T, float>::value) {
       if (g.fam == 2) {
         MPC_HIP_TRY(fused_solve_f32(sl.d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet, in, sc,
@@ -529,6 +558,11 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
     MPC_HIP_TRY(launch_generic_admm<T>(sl.d_desc, list, g.count, in, sc, iters, -1,
                                        (const T*)s->arena_base, state, g.lds_a, 256, st));
   }
+  for (int i = 0; i < ns - 1; ++i) {
+    MPC_HIP_TRY(hipEventRecord(sl.ev_join[i], sl.aux[i]));
+    MPC_HIP_TRY(hipStreamWaitEvent(sl.stream, sl.ev_join[i], 0));
+  }
+  st = sl.stream;
   int maxN = 1, maxnx = 1;
   for (const G& g : gl) {
     maxN = std::max(maxN, g.N);

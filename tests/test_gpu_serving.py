@@ -100,9 +100,11 @@ def test_alone_vs_mix():
     for step in range(3):
         ids = rng.permutation(b.n_agents)
         order.append(ids)
+    keep = []  # output buffers must outlive their requests
     for step in range(3):
         for j, a in enumerate(order[step]):
             buf = torch.empty(b.shapes[a].nu, device="cuda")
+            keep.append(buf)
             srv.submit(int(a), b.shapes[a], reqs[int(a)], buf, warm=True)
             if a in mixed:
                 mixed[a].append(buf)

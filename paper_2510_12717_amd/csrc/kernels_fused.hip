@@ -199,24 +199,34 @@ __device__ inline d4 prod_tile(int ti, int tj, int K, int lane, FA a, FB b) {
 // Riccati factor (FP64, MFMA)
 // ------------------------------------------------------------------------------------
 
+// LDS of the factor kernel (doubles unless noted): three NXT x LX buffers
+// (P_{k+1} -> G -> K -> P_k; A_k -> A_cl,k; P A_k), one NXT x LU buffer
+// (P B_k -> H_k -> H_k^{-1}), B_k as float, and small vectors.  Under 80 KB for
+// the shapes built here, so two workgroups share a compute unit.
 template <int NX, int NU>
 constexpr int riccati_lds_bytes() {
   using S = FS<NX, NU>;
-  return 8 * (3 * S::NXT * S::LX + 2 * S::NXT * S::LU + S::NUT * S::LX + S::NUT * S::LU +
-              S::NUT + S::MMAX + S::NXT + 8 * S::NUT) + 16;
+  return 8 * (3 * S::NXT * S::LX + S::NXT * S::LU + S::NUT + S::MMAX + S::NXT + 8 * S::NUT) +
+         4 * S::NXT * S::LU + 16;
 }
 
 // PREC == kProdF64: operators go to the register-resident layout at fws + ofw.
 // Otherwise (mixed precision) they go to the generic per-agent layout at
 // fws + ows: K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx],
 // then l, h, rho [N][m].
+//
+// Stage k: PB = P B_k, PA = P A_k, s_k = P c_k; H_k = Rt_k + B_k' PB and
+// G = B_k' PA; H_k^{-1}; K_k = -H_k^{-1} G; A_cl,k = A_k + B_k K_k; operators
+// out; then P_k = Q + sigma I + PA' A_cl,k (= Q + A'PA + G'K, as P is
+// symmetric), symmetrised.
 template <int NX, int NU, int PREC>
-__global__ void __launch_bounds__(64 * kFactorWaves)
+__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
           Inputs<float> in, SolverConsts sc, float* __restrict__ fws, int32_t* __restrict__ status) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NXT = S::NXT, NUT = S::NUT;
   constexpr int LX = S::LX, LU = S::LU, SLOTS = S::SLOTS;
+  static_assert(riccati_lds_bytes<NX, NU>() <= 80 * 1024, "two workgroups per compute unit");
   if ((int)blockIdx.x >= n_launch) return;
   const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[agent];
@@ -225,20 +235,20 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   const int w = tid >> 6, lane = tid & 63;
   const int nw = nt >> 6;
   extern __shared__ __align__(16) unsigned char sm[];
-  double* P = reinterpret_cast<double*>(sm);  // P_{k+1}, then P_k   NXT x LX
-  double* Ak = P + NXT * LX;                  // A_k                 NXT x LX
-  double* PA = Ak + NXT * LX;                 // P A_k, then A_cl,k  NXT x LX
-  double* Bk = PA + NXT * LX;                 // B_k                 NXT x LU
-  double* PB = Bk + NXT * LU;                 // P B_k, then K_k     NXT x LU | NUT x LX
-  double* Kd = PB;
-  double* G = PB + NXT * LU;                  // B_k' P A_k          NUT x LX
-  double* H = G + NUT * LX;                   // H_k, then H_k^{-1}  NUT x LU
-  double* rdg = H + NUT * LU;                 // diag Rt_k           NUT
-  double* rhok = rdg + NUT;                   // row penalties       MMAX
-  double* ck = rhok + S::MMAX;                // c_k                 NXT
+  double* P = reinterpret_cast<double*>(sm);  // P_{k+1} | G_k | K_k | P_k   NXT x LX
+  double* G = P;
+  double* Kd = P;
+  double* Ak = P + NXT * LX;                  // A_k, then A_cl,k           NXT x LX
+  double* PA = Ak + NXT * LX;                 // P A_k                      NXT x LX
+  double* PB = PA + NXT * LX;                 // P B_k, then H_k, H_k^{-1}  NXT x LU
+  double* H = PB;
+  double* rdg = PB + NXT * LU;                // diag Rt_k                  NUT
+  double* rhok = rdg + NUT;                   // row penalties              MMAX
+  double* ck = rhok + S::MMAX;                // c_k                        NXT
   double* xcol = ck + NXT;                    // Gauss-Jordan pivot column / row exchange
   double* xrow = xcol + 4 * NUT;              //   (two buffers of 2 NUT each)
-  int* flag = reinterpret_cast<int*>(xrow + 4 * NUT);
+  float* Bk = reinterpret_cast<float*>(xrow + 4 * NUT);  // B_k (float, exact)  NXT x LU
+  int* flag = reinterpret_cast<int*>(Bk + NXT * LU);
 
   const float* A = in.A + d.oA;
   const float* B = in.B + d.oB;
@@ -304,7 +314,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
 #pragma unroll
     for (int t = 0; t < PFB; ++t) {
       const int i = tid + t * kT;
-      if (i < NX * NU) Bk[(i / NU) * LU + i % NU] = (double)pfb[t];
+      if (i < NX * NU) Bk[(i / NU) * LU + i % NU] = pfb[t];
     }
     if (k > 0) prefetch(k - 1);
     for (int i = tid; i < M; i += nt) {
@@ -327,14 +337,14 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
         if (t < TB) {
           const int ti = t / (NUT / 16), tj = t % (NUT / 16);
           d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
-                             [&](int kk, int j) { return Bk[kk * LU + j]; });
+                                   [&](int kk, int j) { return (double)Bk[kk * LU + j]; });
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             PB[(ti * 16 + orow<PREC>(lane, v)) * LU + tj * 16 + (lane & 15)] = acc[v];
         } else {
           const int tt = t - TB, ti = tt / (NXT / 16), tj = tt % (NXT / 16);
           d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return P[i * LX + kk]; },
-                             [&](int kk, int j) { return Ak[kk * LX + j]; });
+                                   [&](int kk, int j) { return Ak[kk * LX + j]; });
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             PA[(ti * 16 + orow<PREC>(lane, v)) * LX + tj * 16 + (lane & 15)] = acc[v];
@@ -349,28 +359,31 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       }
     }
     __syncthreads();
-    // H = diag(Rt_k) + B_k' PB (NUT x NUT) and G = B_k' PA (NUT x NXT)
+    // H = diag(Rt_k) + B_k' PB (NUT x NUT), held in registers until PB is
+    // dead; G = B_k' PA (NUT x NXT) over the dead P_{k+1}
     {
       constexpr int TH = (NUT / 16) * (NUT / 16), TG = (NUT / 16) * (NXT / 16);
-      for (int t = w; t < TH + TG; t += nw) {
-        if (t < TH) {
-          const int ti = t / (NUT / 16), tj = t % (NUT / 16);
-          d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
-                             [&](int kk, int j) { return PB[kk * LU + j]; });
+      static_assert(TH <= 64 * kFactorWaves / 64, "one H tile per wavefront at most");
+      d4 hacc = {0.0, 0.0, 0.0, 0.0};
+      const int hti = w / (NUT / 16), htj = w % (NUT / 16);
+      if (w < TH)
+        hacc = prod_tile<PREC>(hti, htj, NXT, lane, [&](int i, int kk) { return (double)Bk[kk * LU + i]; },
+                               [&](int kk, int j) { return PB[kk * LU + j]; });
+      for (int t = w; t < TG; t += nw) {
+        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
+        d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return (double)Bk[kk * LU + i]; },
+                                 [&](int kk, int j) { return PA[kk * LX + j]; });
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
-            H[i * LU + j] = acc[v] + (i == j ? rdg[i] : 0.0);
-          }
-        } else {
-          const int tt = t - TH, ti = tt / (NXT / 16), tj = tt % (NXT / 16);
-          d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return Bk[kk * LU + i]; },
-                             [&](int kk, int j) { return PA[kk * LX + j]; });
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            G[(ti * 16 + orow<PREC>(lane, v)) * LX + tj * 16 + (lane & 15)] = acc[v];
-        }
+        for (int v = 0; v < 4; ++v)
+          G[(ti * 16 + orow<PREC>(lane, v)) * LX + tj * 16 + (lane & 15)] = acc[v];
       }
+      __syncthreads();
+      if (w < TH)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = hti * 16 + orow<PREC>(lane, v), j = htj * 16 + (lane & 15);
+          H[i * LU + j] = hacc[v] + (i == j ? rdg[i] : 0.0);
+        }
     }
     __syncthreads();
     // H_k^{-1} in place by block Gauss-Jordan sweeps without pivoting over the
@@ -445,57 +458,39 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       if (tid == 0) status[agent] = AGENT_NOT_PD;
       return;
     }
-    // K_k = -H_k^{-1} G (NUT x NXT) into the dead PB storage
+    // K_k = -H_k^{-1} G (NUT x NXT, FP64) in place of G: one wavefront per
+    // column block reads all of G's column block before it overwrites it
     {
-      constexpr int TK = (NUT / 16) * (NXT / 16);
-      for (int t = w; t < TK; t += nw) {
-        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
-        d4 acc = mfma_tile(ti, tj, NUT, lane,
-                           [&](int i, int kk) { return (i < NU && kk < NU) ? H[i * LU + kk] : 0.0; },
-                           [&](int kk, int j) { return G[kk * LX + j]; });
+      constexpr int TJ = NXT / 16, TI = NUT / 16;
+      static_assert(TI == 2, "two row tiles per column block");
+      if (w < TJ) {
+        const int tj = w;
+        d4 acc[TI];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          Kd[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = -acc[v];
+        for (int ti = 0; ti < TI; ++ti)
+          acc[ti] = mfma_tile(ti, tj, NUT, lane,
+                              [&](int i, int kk) { return (i < NU && kk < NU) ? H[i * LU + kk] : 0.0; },
+                              [&](int kk, int j) { return G[kk * LX + j]; });
+        wave_sync();
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            Kd[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = -acc[ti][v];
       }
     }
     __syncthreads();
-    // P_k = Q + sigma I + A_k' PA + G' K_k over the dead P_{k+1}
-    {
-      constexpr int TP = (NXT / 16) * (NXT / 16);
-      for (int t = w; t < TP; t += nw) {
-        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
-        d4 a1 = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return Ak[kk * LX + i]; },
-                          [&](int kk, int j) { return PA[kk * LX + j]; });
-        d4 a2 = prod_tile<PREC>(ti, tj, NUT, lane, [&](int i, int kk) { return G[kk * LX + i]; },
-                          [&](int kk, int j) { return Kd[kk * LX + j]; });
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
-          const double qv = (i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0;
-          P[i * LX + j] = qv + a1[v] + a2[v];
-        }
-      }
-    }
-    __syncthreads();
-    // symmetrise P_k; A_cl,k = A_k + B_k K_k over the dead PA
-    for (int e = tid; e < NXT * NXT; e += nt) {
-      const int i = e / NXT, j = e % NXT;
-      if (j > i) {
-        const double v = 0.5 * (P[i * LX + j] + P[j * LX + i]);
-        P[i * LX + j] = v;
-        P[j * LX + i] = v;
-      }
-    }
+    // A_cl,k = A_k + B_k K_k in place of A_k (each entry read and written by one lane)
     {
       constexpr int TA = (NXT / 16) * (NXT / 16);
       for (int t = w; t < TA; t += nw) {
         const int ti = t / (NXT / 16), tj = t % (NXT / 16);
-        d4 acc = prod_tile<PREC>(ti, tj, NUT, lane, [&](int i, int kk) { return Bk[i * LU + kk]; },
-                           [&](int kk, int j) { return Kd[kk * LX + j]; });
+        d4 acc = prod_tile<PREC>(ti, tj, NUT, lane, [&](int i, int kk) { return (double)Bk[i * LU + kk]; },
+                                 [&](int kk, int j) { return Kd[kk * LX + j]; });
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
-          PA[i * LX + j] = Ak[i * LX + j] + acc[v];
+          Ak[i * LX + j] += acc[v];
         }
       }
     }
@@ -504,7 +499,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     // the generic row-major layout for the mixed-precision iterations)
     if (!kResident) {
       for (int e = tid; e < NU * NX; e += nt) gK[(int64_t)k * NU * NX + e] = (float)Kd[(e / NX) * LX + e % NX];
-      for (int e = tid; e < NX * NX; e += nt) gAcl[(int64_t)k * NX * NX + e] = (float)PA[(e / NX) * LX + e % NX];
+      for (int e = tid; e < NX * NX; e += nt) gAcl[(int64_t)k * NX * NX + e] = (float)Ak[(e / NX) * LX + e % NX];
       for (int e = tid; e < NU * NU; e += nt) gHi[(int64_t)k * NU * NU + e] = (float)H[(e / NU) * LU + e % NU];
     }
     float* dst = ops + (int64_t)k * SLOTS * 64;
@@ -513,18 +508,45 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       double v = 0.0;
       if (slot < RB * RB) {
         const int ri = a * RB + slot / RB, cj = b * RB + slot % RB;
-        if (ri < NX && cj < NX) v = PA[ri * LX + cj];
+        if (ri < NX && cj < NX) v = Ak[ri * LX + cj];
       } else if (slot < RB * RB + CB * RB) {
         const int sl = slot - RB * RB, ri = b * CB + sl / RB, cj = a * RB + sl % RB;
         if (ri < NU && cj < NX) v = Kd[ri * LX + cj];
       } else if (slot < RB * RB + 2 * CB * RB) {
         const int sl = slot - RB * RB - CB * RB, ri = a * RB + sl / CB, cj = b * CB + sl % CB;
-        if (ri < NX && cj < NU) v = Bk[ri * LU + cj];
+        if (ri < NX && cj < NU) v = (double)Bk[ri * LU + cj];
       } else {
         const int sl = slot - RB * RB - 2 * CB * RB, ri = a * CB + sl / CB, cj = b * CB + sl % CB;
         if (ri < NU && cj < NU) v = H[ri * LU + cj];
       }
       dst[e] = (float)v;
+    }
+    __syncthreads();
+    // P_k = Q + sigma I + PA' A_cl,k over the dead K_k (the rows past NX of
+    // PA and A_cl are zero padding)
+    {
+      constexpr int TP = (NXT / 16) * (NXT / 16);
+      for (int t = w; t < TP; t += nw) {
+        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
+        d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return PA[kk * LX + i]; },
+                                 [&](int kk, int j) { return Ak[kk * LX + j]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
+          const double qv = (i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0;
+          P[i * LX + j] = qv + acc[v];
+        }
+      }
+    }
+    __syncthreads();
+    // symmetrise P_k
+    for (int e = tid; e < NXT * NXT; e += nt) {
+      const int i = e / NXT, j = e % NXT;
+      if (j > i) {
+        const double v = 0.5 * (P[i * LX + j] + P[j * LX + i]);
+        P[i * LX + j] = v;
+        P[j * LX + i] = v;
+      }
     }
     __syncthreads();
   }

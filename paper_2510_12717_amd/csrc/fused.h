@@ -29,12 +29,13 @@ hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_l
                            int warm, State<float> st, float* fws, hipStream_t stream,
                            int phase_mask);
 
-// Mixed precision: the same factor kernel with BF16 (bf16 != 0) or FP16 block
-// products on the matrix cores (FP32 accumulation) and the FP64 stage-Hessian
-// inverse, writing the generic operator layout at ws + ows.
+// The same factor kernel writing the generic operator layout at ws + ows (any
+// horizon): block products in FP64 (prod 0), or BF16 (1) / FP16 (2) operands
+// on the matrix cores with FP32 accumulation for the mixed-precision plans;
+// the stage-Hessian inverse is FP64 in every case.
 bool mixed_supported(int nx, int nu);
 hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch, int nx,
-                               int nu, int bf16, Inputs<float> in, SolverConsts sc, float* ws,
+                               int nu, int prod, Inputs<float> in, SolverConsts sc, float* ws,
                                int32_t* status, hipStream_t stream);
 
 }  // namespace mpc

@@ -210,16 +210,17 @@ constexpr int riccati_lds_bytes() {
          4 * S::NXT * S::LU + 16;
 }
 
-// PREC == kProdF64: operators go to the register-resident layout at fws + ofw.
-// Otherwise (mixed precision) they go to the generic per-agent layout at
-// fws + ows: K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx],
-// then l, h, rho [N][m].
+// RES: operators go to the register-resident layout at fws + ofw (N <= 12).
+// Otherwise (mixed precision, or FP64 products for the generic iteration
+// kernel at any horizon) they go to the generic per-agent layout at fws + ows:
+// K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx], then l, h,
+// rho [N][m].
 //
 // Stage k: PB = P B_k, PA = P A_k, s_k = P c_k; H_k = Rt_k + B_k' PB and
 // G = B_k' PA; H_k^{-1}; K_k = -H_k^{-1} G; A_cl,k = A_k + B_k K_k; operators
 // out; then P_k = Q + sigma I + PA' A_cl,k (= Q + A'PA + G'K, as P is
 // symmetric), symmetrised.
-template <int NX, int NU, int PREC>
+template <int NX, int NU, int PREC, bool RES>
 __global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
           Inputs<float> in, SolverConsts sc, float* __restrict__ fws, int32_t* __restrict__ status) {
@@ -259,7 +260,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   const uint8_t* stance = in.st + d.ost;
   const float muf = in.mu[d.omu];
   const double mu = (double)muf;
-  constexpr bool kResident = PREC == kProdF64;
+  constexpr bool kResident = RES;
+  static_assert(!RES || PREC == kProdF64, "the register-resident path takes FP64 products");
   float* ops = fws + (kResident ? d.ofw : d.ows);
   float* sk_out = kResident ? ops + (int64_t)kMaxStages * SLOTS * 64  // [stage][NXP]
                             : ops + (int64_t)N * (NU * NX + NX * NX + NU * NU);
@@ -363,10 +365,13 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     // dead; G = B_k' PA (NUT x NXT) over the dead P_{k+1}
     {
       constexpr int TH = (NUT / 16) * (NUT / 16), TG = (NUT / 16) * (NXT / 16);
-      static_assert(TH <= 64 * kFactorWaves / 64, "one H tile per wavefront at most");
+      static_assert(TH <= kFactorWaves, "one H tile per wavefront at most");
       d4 hacc = {0.0, 0.0, 0.0, 0.0};
-      const int hti = w / (NUT / 16), htj = w % (NUT / 16);
-      if (w < TH)
+      // H tiles on the wavefronts past the G tiles (wrapping), so the two
+      // products spread over all wavefronts
+      const int hw = (w - TG + 2 * nw) % nw;
+      const int hti = hw / (NUT / 16), htj = hw % (NUT / 16);
+      if (hw < TH)
         hacc = prod_tile<PREC>(hti, htj, NXT, lane, [&](int i, int kk) { return (double)Bk[kk * LU + i]; },
                                [&](int kk, int j) { return PB[kk * LU + j]; });
       for (int t = w; t < TG; t += nw) {
@@ -378,7 +383,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
           G[(ti * 16 + orow<PREC>(lane, v)) * LX + tj * 16 + (lane & 15)] = acc[v];
       }
       __syncthreads();
-      if (w < TH)
+      if (hw < TH)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = hti * 16 + orow<PREC>(lane, v), j = htj * 16 + (lane & 15);
@@ -458,26 +463,22 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       if (tid == 0) status[agent] = AGENT_NOT_PD;
       return;
     }
-    // K_k = -H_k^{-1} G (NUT x NXT, FP64) in place of G: one wavefront per
-    // column block reads all of G's column block before it overwrites it
+    // K_k = -H_k^{-1} G (NUT x NXT, FP64) in place of G: every tile is held in
+    // registers until all of G has been read
     {
-      constexpr int TJ = NXT / 16, TI = NUT / 16;
-      static_assert(TI == 2, "two row tiles per column block");
-      if (w < TJ) {
-        const int tj = w;
-        d4 acc[TI];
+      constexpr int TK = (NUT / 16) * (NXT / 16);
+      static_assert(TK <= kFactorWaves, "one K tile per wavefront");
+      const int ti = w / (NXT / 16), tj = w % (NXT / 16);
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (w < TK)
+        acc = mfma_tile(ti, tj, NUT, lane,
+                        [&](int i, int kk) { return (i < NU && kk < NU) ? H[i * LU + kk] : 0.0; },
+                        [&](int kk, int j) { return G[kk * LX + j]; });
+      __syncthreads();
+      if (w < TK)
 #pragma unroll
-        for (int ti = 0; ti < TI; ++ti)
-          acc[ti] = mfma_tile(ti, tj, NUT, lane,
-                              [&](int i, int kk) { return (i < NU && kk < NU) ? H[i * LU + kk] : 0.0; },
-                              [&](int kk, int j) { return G[kk * LX + j]; });
-        wave_sync();
-#pragma unroll
-        for (int ti = 0; ti < TI; ++ti)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            Kd[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = -acc[ti][v];
-      }
+        for (int v = 0; v < 4; ++v)
+          Kd[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = -acc[v];
     }
     __syncthreads();
     // A_cl,k = A_k + B_k K_k in place of A_k (each entry read and written by one lane)
@@ -979,7 +980,7 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
   const int lf = riccati_lds_bytes<NX, NU>();
   const int li = iter_lds_layout<NX, NU>(N, M).total;
   if (phase_mask & 1) {
-    hipLaunchKernelGGL((k_riccati<NX, NU, kProdF64>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
+    hipLaunchKernelGGL((k_riccati<NX, NU, kProdF64, true>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
                        d_desc, list, n_launch, in, sc, fws, st.status);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -995,14 +996,17 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
 
 template <int NX, int NU>
 hipError_t set_limits() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF64>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF64, true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdBF16>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF64, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF16>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdBF16, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF16, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
@@ -1040,31 +1044,35 @@ hipError_t fused_set_limits() {
 
 bool mixed_supported(int nx, int nu) { return (nx == 48 && nu == 30) || (nx == 36 && nu == 24); }
 
+template <int X, int U, int P>
+hipError_t launch_factor_generic_out(const AgentDesc* d_desc, const int32_t* list, int n_launch,
+                                     Inputs<float> in, SolverConsts sc, float* ws,
+                                     int32_t* status, hipStream_t stream) {
+  const int lf = riccati_lds_bytes<X, U>();
+  hipLaunchKernelGGL((k_riccati<X, U, P, false>), dim3(n_launch), dim3(64 * kFactorWaves), lf,
+                     stream, d_desc, list, n_launch, in, sc, ws, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch, int nx,
-                               int nu, int bf16, Inputs<float> in, SolverConsts sc, float* ws,
+                               int nu, int prod, Inputs<float> in, SolverConsts sc, float* ws,
                                int32_t* status, hipStream_t stream) {
   if (n_launch <= 0) return hipSuccess;
-  const dim3 grid(n_launch), block(64 * kFactorWaves);
   if (nx == 48 && nu == 30) {
-    const int lf = riccati_lds_bytes<48, 30>();
-    if (bf16)
-      hipLaunchKernelGGL((k_riccati<48, 30, kProdBF16>), grid, block, lf, stream, d_desc, list,
-                         n_launch, in, sc, ws, status);
-    else
-      hipLaunchKernelGGL((k_riccati<48, 30, kProdF16>), grid, block, lf, stream, d_desc, list,
-                         n_launch, in, sc, ws, status);
-  } else if (nx == 36 && nu == 24) {
-    const int lf = riccati_lds_bytes<36, 24>();
-    if (bf16)
-      hipLaunchKernelGGL((k_riccati<36, 24, kProdBF16>), grid, block, lf, stream, d_desc, list,
-                         n_launch, in, sc, ws, status);
-    else
-      hipLaunchKernelGGL((k_riccati<36, 24, kProdF16>), grid, block, lf, stream, d_desc, list,
-                         n_launch, in, sc, ws, status);
-  } else {
-    return hipErrorInvalidValue;
+    if (prod == kProdF64)
+      return launch_factor_generic_out<48, 30, kProdF64>(d_desc, list, n_launch, in, sc, ws, status, stream);
+    if (prod == kProdBF16)
+      return launch_factor_generic_out<48, 30, kProdBF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
+    return launch_factor_generic_out<48, 30, kProdF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
   }
-  return hipGetLastError();
+  if (nx == 36 && nu == 24) {
+    if (prod == kProdF64)
+      return launch_factor_generic_out<36, 24, kProdF64>(d_desc, list, n_launch, in, sc, ws, status, stream);
+    if (prod == kProdBF16)
+      return launch_factor_generic_out<36, 24, kProdBF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
+    return launch_factor_generic_out<36, 24, kProdF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,

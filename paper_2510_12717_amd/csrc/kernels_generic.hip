@@ -265,6 +265,23 @@ __device__ inline double block_sum(double v, double* red) {
   return out;
 }
 
+// store(i, sum_t m(i, t) v_t) for i < n_out: each output's dot product is
+// split over the 4 lanes of a quad (terms t = sub, sub + 4, ...) and summed
+// with DPP, so a serial chain step costs n_in / 4 dependent FMAs.
+template <typename V, class FM, class FS>
+__device__ inline void quad_matvec(int n_out, int n_in, FM m, const V* v, FS store, int tid, int nt) {
+  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
+  for (int i0 = 0; i0 < n_out; i0 += nq) {
+    const int i = i0 + qd;
+    if (i < n_out) {  // uniform within a quad
+      V acc = 0;
+      for (int t = sub; t < n_in; t += 4) acc += (V)m(i, t) * v[t];
+      acc = quad_sum(acc);
+      if (sub == 0) store(i, acc);
+    }
+  }
+}
+
 // Rollout under the exact dynamics with gains K:  u_k = K_k x_k + d_k,
 // x_{k+1} = A_k x_k + B_k u_k (+ c_k).  x_0 is x0p (zero if NULL); x_{k+1} is
 // written to Xn[k]; u may alias d (each entry reads only its own d).
@@ -272,26 +289,29 @@ template <typename T, typename V>
 __device__ inline void forward_exact(int N, int nx, int nu, const T* A, const T* B, const T* c,
                                      const T* wK, const V* d, const V* x0p, V* Xn, V* u, int tid,
                                      int nt) {
+  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
   for (int k = 0; k < N; ++k) {
     const V* xk = k == 0 ? x0p : Xn + (k - 1) * nx;
-    for (int j = tid; j < nu; j += nt) {
-      V acc = 0;
-      if (xk) {
-        const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
-        for (int t = 0; t < nx; ++t) acc += (V)Kr[t] * xk[t];
-      }
-      u[k * nu + j] = d[k * nu + j] + acc;
-    }
+    const T* Kk = wK + (int64_t)k * nu * nx;
+    const T* Ak = A + (int64_t)k * nx * nx;
+    const T* Bk = B + (int64_t)k * nx * nu;
+    if (xk)
+      quad_matvec<V>(nu, nx, [&](int j, int t) { return Kk[j * nx + t]; }, xk,
+                     [&](int j, V acc) { u[k * nu + j] = d[k * nu + j] + acc; }, tid, nt);
+    else
+      for (int j = tid; j < nu; j += nt) u[k * nu + j] = d[k * nu + j];
     __syncthreads();
-    for (int i = tid; i < nx; i += nt) {
-      V acc = 0;
-      if (xk) {
-        const T* Ar = A + (int64_t)k * nx * nx + i * nx;
-        for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * xk[t];
+    const V* uk = u + k * nu;
+    for (int i0 = 0; i0 < nx; i0 += nq) {
+      const int i = i0 + qd;
+      if (i < nx) {  // uniform within a quad
+        V acc = 0;
+        if (xk)
+          for (int t = sub; t < nx; t += 4) acc += (V)Ak[i * nx + t] * xk[t];
+        for (int t = sub; t < nu; t += 4) acc += (V)Bk[i * nu + t] * uk[t];
+        acc = quad_sum(acc);
+        if (sub == 0) Xn[k * nx + i] = c ? (V)c[(int64_t)k * nx + i] + acc : acc;
       }
-      const T* Br = B + (int64_t)k * nx * nu + i * nu;
-      for (int t = 0; t < nu; ++t) acc += (V)Br[t] * u[k * nu + t];
-      Xn[k * nx + i] = c ? (V)c[(int64_t)k * nx + i] + acc : acc;
     }
     __syncthreads();
   }
@@ -427,12 +447,9 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       for (int i = tid; i < nx; i += nt) pp[k * nx + i] = p[i] + (V)wS[(int64_t)k * nx + i];
       __syncthreads();
       if (k > 0) {
-        for (int i = tid; i < nx; i += nt) {
-          V acc = 0;
-          const T* Ac = wAcl + (int64_t)k * nx * nx + i;
-          for (int t = 0; t < nx; ++t) acc += (V)Ac[t * nx] * pp[k * nx + t];
-          p[i] = g[k * nx + i] + acc;
-        }
+        const T* Ac = wAcl + (int64_t)k * nx * nx;
+        quad_matvec<V>(nx, nx, [&](int i, int t) { return Ac[t * nx + i]; }, pp + k * nx,
+                       [&](int i, V acc) { p[i] = g[k * nx + i] + acc; }, tid, nt);
         __syncthreads();
       }
     }
@@ -464,12 +481,9 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       __syncthreads();
       // forward chain: xt_{k+1} = A_cl,k xt_k + e_k
       for (int k = 0; k < N; ++k) {
-        for (int i = tid; i < nx; i += nt) {
-          V acc = 0;
-          const T* Ar = wAcl + (int64_t)k * nx * nx + i * nx;
-          for (int t = 0; t < nx; ++t) acc += (V)Ar[t] * xt[k * nx + t];
-          xt[(k + 1) * nx + i] = e[k * nx + i] + acc;
-        }
+        const T* Ak = wAcl + (int64_t)k * nx * nx;
+        quad_matvec<V>(nx, nx, [&](int i, int t) { return Ak[i * nx + t]; }, xt + k * nx,
+                       [&](int i, V acc) { xt[(k + 1) * nx + i] = e[k * nx + i] + acc; }, tid, nt);
         __syncthreads();
       }
       // ut_k = K_k xt_k + d_k
@@ -505,14 +519,14 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         }
         __syncthreads();
         for (int k = N - 1; k >= 1; --k) {
-          for (int i = tid; i < nx; i += nt) {
-            V acc = 0;
-            const T* Ac = A + (int64_t)k * nx * nx + i;
-            for (int t = 0; t < nx; ++t) acc += (V)Ac[t * nx] * pp[k * nx + t];
-            const int idx = k * nx + i;
-            pp[(k - 1) * nx + i] =
-                ((V)q[i] + sigma) * xt[idx] + (-(V)q[i] * (V)xr[idx] - sigma * x[idx]) + acc;
-          }
+          const T* Ac = A + (int64_t)k * nx * nx;
+          quad_matvec<V>(nx, nx, [&](int i, int t) { return Ac[t * nx + i]; }, pp + k * nx,
+                         [&](int i, V acc) {
+                           const int idx = k * nx + i;
+                           pp[(k - 1) * nx + i] = ((V)q[i] + sigma) * xt[idx] +
+                                                  (-(V)q[i] * (V)xr[idx] - sigma * x[idx]) + acc;
+                         },
+                         tid, nt);
           __syncthreads();
         }
         // u-stationarity residual ru_k = Rt_k ut_k + rt_k + B_k' lam_{k+1}
@@ -543,12 +557,9 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
           for (int i = tid; i < nx; i += nt) e[k * nx + i] = p[i];
           __syncthreads();
           if (k > 0) {
-            for (int i = tid; i < nx; i += nt) {
-              V acc = 0;
-              const T* Ac = wAcl + (int64_t)k * nx * nx + i;
-              for (int t = 0; t < nx; ++t) acc += (V)Ac[t * nx] * e[k * nx + t];
-              p[i] = g[k * nx + i] + acc;
-            }
+            const T* Ac = wAcl + (int64_t)k * nx * nx;
+            quad_matvec<V>(nx, nx, [&](int i, int t) { return Ac[t * nx + i]; }, e + k * nx,
+                           [&](int i, V acc) { p[i] = g[k * nx + i] + acc; }, tid, nt);
             __syncthreads();
           }
         }

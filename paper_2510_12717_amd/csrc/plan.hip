@@ -309,7 +309,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     return fail(MPC_ERR_UNSUPPORTED_SHAPE, "shapes need more LDS than the device offers");
   }
   e = generic_set_lds_limits(p->lds_factor, p->lds_admm, p->lds_res);
-  if (e == hipSuccess && (p->nFWS > 0 || mixed)) e = fused_set_limits();
+  if (e == hipSuccess && !p->fp64) e = fused_set_limits();
   if (e != hipSuccess) {
     delete p;
     return fail(MPC_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
@@ -472,8 +472,8 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
     {
       PhaseTimer t(p, 0, s);
       HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu,
-                                  p->desc.precision == MPC_BF16_REFINE, make_inputs<float>(b), sc,
-                                  (float*)p->d_ws, p->d_status, s));
+                                  p->desc.precision == MPC_BF16_REFINE ? 1 : 2,
+                                  make_inputs<float>(b), sc, (float*)p->d_ws, p->d_status, s));
     }
     {
       PhaseTimer t(p, 1, s);
@@ -486,8 +486,14 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
     const Inputs<T> in = make_inputs<T>(b);
     {
       PhaseTimer t(p, 0, s);
-      HIP_TRY(launch_generic_factor<T>(p->d_desc, list, g.count, in, sc, (T*)p->d_ws, p->d_status,
-                                       g.lds_factor, g.gthreads, s));
+      // FP32 plans of the shapes the matrix-core factor is built for take it
+      // (FP64 products, generic operator layout) at any horizon
+      if (!p->fp64 && mixed_supported(g.nx, g.nu))
+        HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu, 0, make_inputs<float>(b),
+                                    sc, (float*)p->d_ws, p->d_status, s));
+      else
+        HIP_TRY(launch_generic_factor<T>(p->d_desc, list, g.count, in, sc, (T*)p->d_ws, p->d_status,
+                                         g.lds_factor, g.gthreads, s));
     }
     {
       PhaseTimer t(p, 1, s);

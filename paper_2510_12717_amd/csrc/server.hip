@@ -544,7 +544,7 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
       }
       if (g.fam == 4) {
         MPC_HIP_TRY(launch_mixed_factor(sl.d_desc, list, g.count, g.nx, g.nu,
-                                        s->desc.solver.precision == MPC_BF16_REFINE, in, sc,
+                                        s->desc.solver.precision == MPC_BF16_REFINE ? 1 : 2, in, sc,
                                         (float*)s->arena_base, sl.d_status, st));
         MPC_HIP_TRY(launch_generic_admm<float>(sl.d_desc, list, g.count, in, sc, iters, -1,
                                                (const float*)s->arena_base, state, g.lds_a, 256,
@@ -553,8 +553,13 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
         continue;
       }
     }
-    MPC_HIP_TRY(launch_generic_factor<T>(sl.d_desc, list, g.count, in, sc, (T*)s->arena_base,
-                                         sl.d_status, g.lds_f, 256, st));
+    if (!s->fp64 && mixed_supported(g.nx, g.nu))
+      MPC_HIP_TRY(launch_mixed_factor(sl.d_desc, list, g.count, g.nx, g.nu, 0,
+                                      *reinterpret_cast<const Inputs<float>*>(&in), sc,
+                                      (float*)s->arena_base, sl.d_status, st));
+    else
+      MPC_HIP_TRY(launch_generic_factor<T>(sl.d_desc, list, g.count, in, sc, (T*)s->arena_base,
+                                           sl.d_status, g.lds_f, 256, st));
     MPC_HIP_TRY(launch_generic_admm<T>(sl.d_desc, list, g.count, in, sc, iters, -1,
                                        (const T*)s->arena_base, state, g.lds_a, 256, st));
   }

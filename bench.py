@@ -59,6 +59,10 @@ def parse():
                     help="time the uneven batch instead (8192 agents, N ~ U{5..20}, half humanoid, "
                          "half quadruped): autotuned launch groups, captured-graph steps "
                          "(prints its own JSON line)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="time the mixed-precision sweep instead (16384 humanoid agents, N=16, "
+                         "Q/R condition 1e4): FP32 vs BF16 / FP16 products with refinement, "
+                         "step time and error vs the FP64 oracle per mode (prints its own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="run the served request loop instead: Poisson arrivals from independent "
                          "controllers of uneven shapes (prints its own JSON line)")
@@ -120,18 +124,22 @@ def summarize_pmc(paths):
            "dispatches": [n_f, n_w], "copy_fetch_kib": f_c, "copy_write_kib": w_c,
            "copy_bytes": COPY_BYTES, "read_scale": scale_r, "write_scale": scale_w,
            "traffic_bytes_per_launch": traffic}
-    cmd = ("cd /tmp && timeout -s KILL 60 rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
+    cmd = ("cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
            "-o run -- python3 <repo>/bench.py {a}")
     lines = ["# HBM traffic of the iteration kernel: config-1 workload (4096 humanoid agents, N=10, "
              "50 iterations, FP32)", "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of `" + kname + "`, each divided by the "
              "ratio the same counter reads for a plain 1 GiB device copy (`bench.py --calibrate-copy`).",
              "Commands (four passes, one counter each):", "", "```",
-             cmd.format(c="FETCH_SIZE", d="pmc_fetch_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
-             cmd.format(c="WRITE_SIZE", d="pmc_write_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
-             cmd.format(c="FETCH_SIZE", d="pmc_fetch_copy", a="--calibrate-copy"),
-             cmd.format(c="WRITE_SIZE", d="pmc_write_copy", a="--calibrate-copy"),
-             "python bench.py --summarize-pmc <the four counter_collection.csv files>", "```", "",
+             cmd.format(c="FETCH_SIZE", d="pmc_FETCH_SIZE_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
+             cmd.format(c="FETCH_SIZE", d="pmc_FETCH_SIZE_copy", a="--calibrate-copy"),
+             cmd.format(c="WRITE_SIZE", d="pmc_WRITE_SIZE_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
+             cmd.format(c="WRITE_SIZE", d="pmc_WRITE_SIZE_copy", a="--calibrate-copy"),
+             "python bench.py --summarize-pmc <repo>/gpurun_out/pmc_{FETCH_SIZE,WRITE_SIZE}_bench/run_counter_collection.csv "
+             "<repo>/gpurun_out/pmc_{FETCH_SIZE,WRITE_SIZE}_copy/run_counter_collection.csv", "```", "",
+             "Algorithmic bytes per launch (operators loaded once, 4096 agents x 10 stages x 100 "
+             "floats x 64 lanes; vectors and the resident state in and out): 1.09 GB read, 0.026 GB "
+             "written.", "",
              "| quantity | value |", "|---|---|",
              f"| FETCH_SIZE per dispatch | {f_k:.0f} KiB |", f"| WRITE_SIZE per dispatch | {w_k:.0f} KiB |",
              f"| copy: FETCH_SIZE / bytes read | {scale_r:.3f} |",
@@ -217,6 +225,58 @@ def uneven(args):
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
            "groups": [(g["family"], g["nx"], g["N"], g["n_agents"], g["threads"]) for g in groups],
            "autotune_s": t_tune, "status_ok": bool((st == 0).all().item())}
+    print(json.dumps(out))
+
+
+def mixed(args):
+    """Mixed-precision sweep: one cold solve per timed step of 16384 humanoid agents
+    (N = 16, Q/R condition 1e4) in each mode; errors of every 64th agent vs the
+    FP64 oracle (u_0 and trajectory, norm-wise relative)."""
+    import torch
+
+    import oracle
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    n = args.agents if args.agents != 4096 else 16384
+    kappa = 1e4
+    b = synth.config3(n, kappa=kappa, dtype=np.float32)
+    prob = mpc.to_device(b, "fp32")
+    ids = np.arange(0, n, 64)
+    ref = oracle.solve_batch(synth.config3(agent_ids=ids, kappa=kappa), iters=args.iters)
+    sh = b.shapes[0]
+    modes = {}
+    for prec, sweeps in (("fp32", 0), ("bf16", 0), ("bf16", 3), ("fp16", 0), ("fp16", 3)):
+        plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters, max_refine_sweeps=sweeps)
+        stream = torch.cuda.current_stream()
+        for _ in range(max(args.warmup, 1)):
+            plan.solve(prob, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.solve(prob, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        u = plan.get_solution()["u"].cpu().numpy().reshape(n, sh.N * sh.nu)[ids].astype(np.float64)
+        x = plan.get_solution()["x"].cpu().numpy().reshape(n, (sh.N + 1) * sh.nx)[ids].astype(np.float64)
+        uo = ref["u"].reshape(len(ids), -1)
+        xo = ref["x"].reshape(len(ids), -1)
+        tr = np.concatenate([x[:, sh.nx:], u], 1)
+        to = np.concatenate([xo[:, sh.nx:], uo], 1)
+        e_u0 = np.abs(u[:, :sh.nu] - uo[:, :sh.nu]).max(1) / np.abs(uo[:, :sh.nu]).max(1)
+        e_tr = np.abs(tr - to).max(1) / np.abs(to).max(1)
+        key = prec if prec == "fp32" else f"{prec}_sweeps{sweeps}"
+        modes[key] = {"ms_per_step": ms, "solves_per_s": n / ms * 1e3,
+                      "err_u0_max": float(e_u0.max()), "err_traj_max": float(e_tr.max()),
+                      "err_traj_p50": float(np.median(e_tr)), "kernel": plan.config()["kernel"]}
+        plan.close()
+    out = {"metric": "MPC QP solves/sec per precision mode and error vs FP64",
+           "value": modes["fp32"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "higher_is_better": True, "dtype": "mixed", "data": "synthetic",
+           "config": {"workload": f"{n} humanoid agents, N=16, Q/R condition {kappa:g}, "
+                                  f"{args.iters} cold ADMM iterations", "agents": n,
+                      "checked_agents": int(len(ids))},
+           "modes": modes}
     print(json.dumps(out))
 
 
@@ -318,6 +378,9 @@ def main():
         return
     if args.uneven:
         uneven(args)
+        return
+    if args.mixed:
+        mixed(args)
         return
     import torch
 

@@ -265,6 +265,23 @@ __device__ inline double block_sum(double v, double* red) {
   return out;
 }
 
+// store(i, sum_t term(i, t)) for i < n_out, t < n_in: each output's sum is
+// split over the 4 lanes of a quad (terms t = sub, sub + 4, ...) and summed
+// with DPP.
+template <typename V, class FT, class FS>
+__device__ inline void quad_dot(int n_out, int n_in, FT term, FS store, int tid, int nt) {
+  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
+  for (int i0 = 0; i0 < n_out; i0 += nq) {
+    const int i = i0 + qd;
+    if (i < n_out) {  // uniform within a quad
+      V acc = 0;
+      for (int t = sub; t < n_in; t += 4) acc += term(i, t);
+      acc = quad_sum(acc);
+      if (sub == 0) store(i, acc);
+    }
+  }
+}
+
 // store(i, sum_t m(i, t) v_t) for i < n_out: each output's dot product is
 // split over the 4 lanes of a quad (terms t = sub, sub + 4, ...) and summed
 // with DPP, so a serial chain step costs n_in / 4 dependent FMAs.
@@ -432,13 +449,16 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
     }
     __syncthreads();
     // g_k = qt_k + K_k' rt_k, qt_k = -Q r_k - sigma x_k
-    for (int idx = tid; idx < N * nx; idx += nt) {
-      const int k = idx / nx, i = idx % nx;
-      V acc = 0;
-      const T* Kc = wK + (int64_t)k * nu * nx + i;
-      for (int j = 0; j < nu; ++j) acc += (V)Kc[j * nx] * rt[k * nu + j];
-      g[idx] = (-(V)q[i] * (V)xr[(int64_t)k * nx + i] - sigma * x[idx]) + acc;
-    }
+    quad_dot<V>(N * nx, nu,
+                [&](int idx, int j) {
+                  const int k = idx / nx, i = idx % nx;
+                  return (V)wK[((int64_t)k * nu + j) * nx + i] * rt[k * nu + j];
+                },
+                [&](int idx, V acc) {
+                  const int k = idx / nx, i = idx % nx;
+                  g[idx] = (-(V)q[i] * (V)xr[(int64_t)k * nx + i] - sigma * x[idx]) + acc;
+                },
+                tid, nt);
     for (int i = tid; i < nx; i += nt)
       p[i] = -(V)q[i] * (V)xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
     __syncthreads();
@@ -454,30 +474,27 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       }
     }
     // d_k = -H_k^{-1}(rt_k + B_k' p'_k),  e_k = B_k d_k + c_k
-    for (int idx = tid; idx < N * nu; idx += nt) {
-      const int k = idx / nu, j = idx % nu;
-      V acc = 0;
-      const T* Bc = B + (int64_t)k * nx * nu + j;
-      for (int t = 0; t < nx; ++t) acc += (V)Bc[t * nu] * pp[k * nx + t];
-      hv[idx] = rt[idx] + acc;
-    }
+    quad_dot<V>(N * nu, nx,
+                [&](int idx, int t) {
+                  const int k = idx / nu, j = idx % nu;
+                  return (V)B[((int64_t)k * nx + t) * nu + j] * pp[k * nx + t];
+                },
+                [&](int idx, V acc) { hv[idx] = rt[idx] + acc; }, tid, nt);
     __syncthreads();
-    for (int idx = tid; idx < N * nu; idx += nt) {
-      const int k = idx / nu, j = idx % nu;
-      V acc = 0;
-      const T* Hr = wHi + (int64_t)k * nu * nu + j * nu;
-      for (int t = 0; t < nu; ++t) acc += (V)Hr[t] * hv[k * nu + t];
-      dv[idx] = -acc;
-    }
+    quad_dot<V>(N * nu, nu,
+                [&](int idx, int t) {
+                  const int k = idx / nu, j = idx % nu;
+                  return (V)wHi[((int64_t)k * nu + j) * nu + t] * hv[k * nu + t];
+                },
+                [&](int idx, V acc) { dv[idx] = -acc; }, tid, nt);
     __syncthreads();
     if (!mixed) {
-      for (int idx = tid; idx < N * nx; idx += nt) {
-        const int k = idx / nx, i = idx % nx;
-        V acc = 0;
-        const T* Br = B + (int64_t)k * nx * nu + i * nu;
-        for (int t = 0; t < nu; ++t) acc += (V)Br[t] * dv[k * nu + t];
-        e[idx] = (V)c[(int64_t)k * nx + i] + acc;
-      }
+      quad_dot<V>(N * nx, nu,
+                  [&](int idx, int t) {
+                    const int k = idx / nx;
+                    return (V)B[(int64_t)idx * nu + t] * dv[k * nu + t];
+                  },
+                  [&](int idx, V acc) { e[idx] = (V)c[idx] + acc; }, tid, nt);
       __syncthreads();
       // forward chain: xt_{k+1} = A_cl,k xt_k + e_k
       for (int k = 0; k < N; ++k) {
@@ -487,13 +504,12 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         __syncthreads();
       }
       // ut_k = K_k xt_k + d_k
-      for (int idx = tid; idx < N * nu; idx += nt) {
-        const int k = idx / nu, j = idx % nu;
-        V acc = 0;
-        const T* Kr = wK + (int64_t)k * nu * nx + j * nx;
-        for (int t = 0; t < nx; ++t) acc += (V)Kr[t] * xt[k * nx + t];
-        ut[idx] = dv[idx] + acc;
-      }
+      quad_dot<V>(N * nu, nx,
+                  [&](int idx, int t) {
+                    const int k = idx / nu;
+                    return (V)wK[(int64_t)idx * nx + t] * xt[k * nx + t];
+                  },
+                  [&](int idx, V acc) { ut[idx] = dv[idx] + acc; }, tid, nt);
       __syncthreads();
     } else {
       // Mixed precision: the gains come from low-precision products, so the

@@ -84,7 +84,11 @@ enum { MPC_AGENT_OK = 0, MPC_AGENT_CONVERGED = 1, MPC_AGENT_NOT_PD = 2, MPC_AGEN
 
 /* Shape of one agent's QP.  nu must equal n_tau + n_feet * foot_dim;
  * foot_dim is 6 (wrench f_x,f_y,f_z,m_x,m_y,m_z) or 3 (force f_x,f_y,f_z).
- * Limits: 1 <= N <= 64, 1 <= nx <= 64, 1 <= nu <= 32, n_feet <= 8. */
+ * Limits: 1 <= N <= 64, 1 <= nx <= 64, 1 <= nu <= 32, n_feet <= 8, and the
+ * generic iteration kernel's vectors, 8 (2(N+1)nx + 4N nu + 2N m + 3N nx + nx
+ * + N nu + 256) bytes, must fit one workgroup's LDS (160 KB on MI355X: N <= 43
+ * for nx = 48, nu = 30, m = 38); plan creation returns UNSUPPORTED_SHAPE
+ * otherwise. */
 typedef struct {
   int32_t N, nx, nu, n_tau, n_feet, foot_dim;
 } mpc_shape;

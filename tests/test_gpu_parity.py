@@ -266,3 +266,46 @@ def test_fused_horizon_limits():
     g, plan, _ = run_gpu(b, "fp32", kernel="fused")
     o = oracle.solve_batch(b, iters=50)
     assert agent_errors(b, g, o)[:, :2].max() < TOL["fp32"]
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp64", "auto"), ("fp32", "generic"),
+                                              ("fp32", "fused")])
+def test_input_reference(precision, kernel):
+    """A nonzero input reference ubar_k (cost (u - ubar)' R (u - ubar)) on every path."""
+    b = synth.config0(12)
+    rng = np.random.default_rng(17)
+    uref = rng.standard_normal(b.offsets()["u"][-1]) * 5.0
+    plan = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
+    prob = mpc.to_device(b, precision)
+    prob["u_ref"] = torch.from_numpy(uref).to(prob["A"].dtype).cuda()
+    plan.solve(prob)
+    g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    o = oracle.solve_batch(b, iters=50, u_ref=uref)
+    o0 = oracle.solve_batch(b, iters=50)
+    assert np.all(g["status"] == 0)
+    e = agent_errors(b, g, o)[:, :2].max()
+    shift = agent_errors(b, g, o0)[:, :2].max()
+    print(precision, kernel, "u_ref: max err %.2e (distance to the ubar = 0 solution %.2e)" % (e, shift))
+    assert e < TOL[precision] and shift > 100 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp64", "auto"), ("fp32", "fused")])
+def test_single_iteration(precision, kernel):
+    b = synth.config0(8)
+    g, _, _ = run_gpu(b, precision, iters=1, kernel=kernel)
+    o = oracle.solve_batch(b, iters=1)
+    assert agent_errors(b, g, o)[:, :2].max() < TOL[precision]
+
+
+def test_largest_supported_horizon():
+    """The longest humanoid horizon whose generic iteration workspace fits the
+    device's LDS solves to the FP64 tolerance; one stage more is rejected."""
+    big = synth.humanoid(43)
+    b = synth.make_batch([big] * 3, seed=4, config_id=53)
+    g, _, _ = run_gpu(b, "fp64", iters=20)
+    o = oracle.solve_batch(b, iters=20)
+    assert np.all(g["status"] == 0)
+    assert agent_errors(b, g, o)[:, :2].max() < TOL["fp64"]
+    with pytest.raises(mpc.MPCError) as ei:
+        mpc.Plan([synth.humanoid(44)], precision="fp64")
+    assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE

@@ -39,7 +39,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxStages = 12;   // wavefronts per iteration workgroup
+constexpr int kMaxStages = 12;   // wavefronts per iteration workgroup (stages + chain)
 constexpr int kFactorWaves = 8;  // wavefronts per factor workgroup
 
 template <int NX, int NU>
@@ -49,7 +49,8 @@ struct FS {
   static constexpr int NXT = (NX + 15) / 16 * 16;   // MFMA-padded sizes
   static constexpr int NUT = (NU + 15) / 16 * 16;
   static constexpr int LX = NXT + 1, LU = NUT + 1;  // odd strides: no bank conflicts
-  static constexpr int SLOTS = RB * RB + CB * RB + RB * CB + CB * CB;
+  static constexpr int AQ = (RB * RB + 3) / 4;  // float4 quads of the chain operator
+  static constexpr int SLOTS = 4 * AQ + CB * RB + RB * CB + CB * CB;
   static constexpr int MMAX = 64;
 };
 
@@ -210,7 +211,7 @@ constexpr int riccati_lds_bytes() {
          4 * S::NXT * S::LU + 16;
 }
 
-// RES: operators go to the register-resident layout at fws + ofw (N <= 12).
+// RES: operators go to the register-resident layout at fws + ofw (N < 12).
 // Otherwise (mixed precision, or FP64 products for the generic iteration
 // kernel at any horizon) they go to the generic per-agent layout at fws + ows:
 // K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx], then l, h,
@@ -504,20 +505,28 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       for (int e = tid; e < NU * NU; e += nt) gHi[(int64_t)k * NU * NU + e] = (float)H[(e / NU) * LU + e % NU];
     }
     float* dst = ops + (int64_t)k * SLOTS * 64;
+    constexpr int AQ = S::AQ;
     for (int e = tid; kResident && e < SLOTS * 64; e += nt) {
-      const int slot = e >> 6, ln = e & 63, a = ln >> 3, b = ln & 7;
       double v = 0.0;
-      if (slot < RB * RB) {
+      if (e < AQ * 256) {
+        // A_cl,k as [quad][lane][4], slot i*RB + j; the lane roles of a and b
+        // swap on odd stages
+        const int slot = 4 * (e >> 8) + (e & 3), ln = (e >> 2) & 63;
+        const int a = (k & 1) ? ln & 7 : ln >> 3, b = (k & 1) ? ln >> 3 : ln & 7;
         const int ri = a * RB + slot / RB, cj = b * RB + slot % RB;
-        if (ri < NX && cj < NX) v = Ak[ri * LX + cj];
-      } else if (slot < RB * RB + CB * RB) {
-        const int sl = slot - RB * RB, ri = b * CB + sl / RB, cj = a * RB + sl % RB;
+        if (slot < RB * RB && ri < NX && cj < NX) v = Ak[ri * LX + cj];
+        dst[e] = (float)v;
+        continue;
+      }
+      const int slot = (e >> 6) - 4 * AQ, ln = e & 63, a = ln >> 3, b = ln & 7;
+      if (slot < CB * RB) {
+        const int ri = b * CB + slot / RB, cj = a * RB + slot % RB;
         if (ri < NU && cj < NX) v = Kd[ri * LX + cj];
-      } else if (slot < RB * RB + 2 * CB * RB) {
-        const int sl = slot - RB * RB - CB * RB, ri = a * RB + sl / CB, cj = b * CB + sl % CB;
+      } else if (slot < 2 * CB * RB) {
+        const int sl = slot - CB * RB, ri = a * RB + sl / CB, cj = b * CB + sl % CB;
         if (ri < NX && cj < NU) v = (double)Bk[ri * LU + cj];
       } else {
-        const int sl = slot - RB * RB - 2 * CB * RB, ri = a * CB + sl / CB, cj = b * CB + sl % CB;
+        const int sl = slot - 2 * CB * RB, ri = a * CB + sl / CB, cj = b * CB + sl % CB;
         if (ri < NU && cj < NU) v = H[ri * LU + cj];
       }
       dst[e] = (float)v;
@@ -555,13 +564,40 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
 }
 
 // ------------------------------------------------------------------------------------
-// ADMM iterations with register-resident operators
+// ADMM iterations: N stage wavefronts with register-resident operators and one
+// chain wavefront
 // ------------------------------------------------------------------------------------
 
+// Progress flags between the chain wavefront and the stage wavefronts, in
+// LDS: each holds the number of the last iteration (from 1) whose data it
+// covers, is set with release order after that data is stored, and is polled
+// with acquire order before it is read.  Layout: g_k ready (A), p'_k ready
+// (backward chain), e_k ready (C), xt_k ready (forward chain), abort.
+constexpr int kSyncG = 0, kSyncP = kMaxStages, kSyncE = 2 * kMaxStages, kSyncX = 3 * kMaxStages;
+constexpr int kSyncAbort = 4 * kMaxStages + 1, kSyncInts = 4 * kMaxStages + 2;
+constexpr int kSpinLimit = 1 << 21;  // polls of one wait (about 0.1 s)
+
+__device__ inline void flag_set(int* f, int v) {
+  __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Waits until every one of f[0 .. n) (n <= 64, one lane each) is >= v.  The
+// wait is bounded: past kSpinLimit polls it raises the abort flag, and every
+// wait returns at once while that flag is up, so the workgroup always drains
+// (the agent then reports non-finite).
+__device__ inline void flag_wait(int* f, int n, int v, int* sync, int lane) {
+  for (int t = 0; t < kSpinLimit; ++t) {
+    const int x = lane < n ? __hip_atomic_load(f + lane, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) : v;
+    if (__all(x >= v)) return;
+    if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __hip_atomic_store(sync + kSyncAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 struct IterLds {
-  int xtf, pbuf, ppf, gf, ef, sf, cf, hml;                    // float
-  int xd, ud, zd, yd, lod, hid, rhod, rtd, dd, utd, qd, xrd;  // double
-  int flag, total;
+  int acl, xtf, ppf, gf, ef, sf, cf;                               // float
+  int xd, ud, zd, yd, lod, hid, rhod, irhod, rtd, dd, utd, qd, xrd, bvd;  // double
+  int flag, sync, total;
 };
 
 template <int NX, int NU>
@@ -574,14 +610,13 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
     o += (bytes + 15) & ~15;
     return r;
   };
+  L.acl = take(4 * N * S::AQ * 256);
   L.xtf = take(4 * (N + 1) * S::NXP);
-  L.pbuf = take(4 * (N + 1) * S::NXP);
   L.ppf = take(4 * N * S::NXP);
   L.gf = take(4 * N * S::NXP);
   L.ef = take(4 * N * S::NXP);
   L.sf = take(4 * N * S::NXP);
   L.cf = take(4 * N * S::NXP);
-  L.hml = take(4 * N * S::CB * S::CB * 64);
   L.xd = take(8 * (N + 1) * S::NXP);
   L.ud = take(8 * N * S::NUP);
   L.zd = take(8 * N * M);
@@ -589,23 +624,70 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
   L.lod = take(8 * N * M);
   L.hid = take(8 * N * M);
   L.rhod = take(8 * N * M);
+  L.irhod = take(8 * N * M);
   L.rtd = take(8 * N * S::NUP);
   L.dd = take(8 * N * S::NUP);
   L.utd = take(8 * N * S::NUP);
   L.qd = take(8 * S::NXP);
   L.xrd = take(8 * (N + 1) * S::NXP);
+  L.bvd = take(8 * S::NXP);
   L.flag = take(16);
+  L.sync = take(4 * kSyncInts);
   L.total = o;
   return L;
 }
 
+// red_a of every element of v[0..n): pairs share their 16- and 32-lane swaps
+// (a reduce-scatter of the pair, then a gather back), 3.5 swaps and adds per
+// value instead of 6.
+template <int n>
+__device__ inline void red_a_all(float (&v)[n]) {
+#pragma unroll
+  for (int i = 0; i < n; ++i) v[i] += dpp<0x128>(v[i]);
+#pragma unroll
+  for (int i = 0; i + 1 < n; i += 2) {
+    // rows (16 lanes) of v[i] = X0..X3, of v[i+1] = Y0..Y3
+    const auto r1 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 1]), false, false);
+    const float s = __uint_as_float(r1[0]) + __uint_as_float(r1[1]);  // X0+X1, Y0+Y1, X2+X3, Y2+Y3
+    const auto r2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    const float t = __uint_as_float(r2[0]) + __uint_as_float(r2[1]);  // X, Y, X, Y
+    const auto r3 = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+    v[i] = __uint_as_float(r3[0]);      // X in every row
+    v[i + 1] = __uint_as_float(r3[1]);  // Y in every row
+  }
+  if (n & 1) v[n - 1] = swap_sum32(swap_sum16(v[n - 1]));
+}
+
+// A_cl,k of the chain wavefront, one float4 quad at a time from LDS
+// ([stage][quad][lane][4]); slot i*RB + j of the lane's RB x RB block.
+template <int AQ>
+__device__ inline void load_chain_op(float (&M)[4 * AQ], const float4* acl4, int kk, int lane) {
+  const float4* src = acl4 + kk * AQ * 64 + lane;
+#pragma unroll
+  for (int q = 0; q < AQ; ++q) {
+    const float4 v = src[q * 64];
+    M[4 * q] = v.x;
+    M[4 * q + 1] = v.y;
+    M[4 * q + 2] = v.z;
+    M[4 * q + 3] = v.w;
+  }
+}
+
+// Stage wavefront k (k < N) keeps K_k, B_k and H_k^{-1} in registers and runs
+// everything that is independent across stages; the chain wavefront (the
+// last one) runs both serial chains alone, streaming A_cl,k from LDS one stage
+// ahead, with no barrier between hops.  Its operators alternate lane roles
+// with the stage's parity (even k: rows a*RB + i, columns b*RB + j; odd k:
+// rows b*RB + i, columns a*RB + j), so the butterfly of one hop leaves its
+// output vector spread over the lanes exactly as the next hop reads it.  The
+// two kinds of wavefront meet at four workgroup barriers per iteration.
 template <int NX, int NU>
 __global__ void __launch_bounds__(64 * kMaxStages)
 k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
                 Inputs<float> in, SolverConsts sc, int iters, int warm,
                 const float* __restrict__ fws, State<float> st) {
   using S = FS<NX, NU>;
-  constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS;
+  constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS, AQ = S::AQ;
   if ((int)blockIdx.x >= n_launch) return;
   const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[agent];
@@ -627,14 +709,13 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   }
   const IterLds L = iter_lds_layout<NX, NU>(N, M);
   extern __shared__ __align__(16) unsigned char sm[];
+  const float4* acl4 = reinterpret_cast<const float4*>(sm + L.acl);
   float* xtf = reinterpret_cast<float*>(sm + L.xtf);
-  float* pbuf = reinterpret_cast<float*>(sm + L.pbuf);
   float* ppf = reinterpret_cast<float*>(sm + L.ppf);
   float* gf = reinterpret_cast<float*>(sm + L.gf);
   float* ef = reinterpret_cast<float*>(sm + L.ef);
   float* sf = reinterpret_cast<float*>(sm + L.sf);
   float* cf = reinterpret_cast<float*>(sm + L.cf);
-  float* hml = reinterpret_cast<float*>(sm + L.hml);
   double* xd = reinterpret_cast<double*>(sm + L.xd);
   double* ud = reinterpret_cast<double*>(sm + L.ud);
   double* zd = reinterpret_cast<double*>(sm + L.zd);
@@ -642,12 +723,15 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   double* lod = reinterpret_cast<double*>(sm + L.lod);
   double* hid = reinterpret_cast<double*>(sm + L.hid);
   double* rhod = reinterpret_cast<double*>(sm + L.rhod);
+  double* irhod = reinterpret_cast<double*>(sm + L.irhod);
   double* rtd = reinterpret_cast<double*>(sm + L.rtd);
   double* dd = reinterpret_cast<double*>(sm + L.dd);
   double* utd = reinterpret_cast<double*>(sm + L.utd);
   double* qd = reinterpret_cast<double*>(sm + L.qd);
   double* xrd = reinterpret_cast<double*>(sm + L.xrd);
+  double* bvd = reinterpret_cast<double*>(sm + L.bvd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
+  int* sync = reinterpret_cast<int*>(sm + L.sync);
 
   const float* c = in.c + d.oc;
   const float* q = in.q + d.oq;
@@ -659,35 +743,16 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   const float* uref = in.uref ? in.uref + d.our : nullptr;
   const double mu = (double)in.mu[d.omu];
 
-  // this wavefront's stage operators: coalesced loads into registers
-  float Acl[RB][RB], Km[CB][RB], Bm[RB][CB];
-  {
-    const float* src = fws + d.ofw + (int64_t)w * SLOTS * 64 + lane;
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-      for (int j = 0; j < RB; ++j) Acl[i][j] = src[(i * RB + j) * 64];
-    src += RB * RB * 64;
-#pragma unroll
-    for (int i = 0; i < CB; ++i)
-#pragma unroll
-      for (int j = 0; j < RB; ++j) Km[i][j] = src[(i * RB + j) * 64];
-    src += CB * RB * 64;
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-      for (int j = 0; j < CB; ++j) Bm[i][j] = src[(i * CB + j) * 64];
-  }
-
-  // per-agent vectors into LDS (padding zero)
+  // per-agent vectors into LDS (padding zero), A_cl of every stage into LDS
   for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
-  // H_k^{-1} is used once per iteration: it stays in LDS, in register order
   {
-    const float* src = fws + d.ofw + ((int64_t)w * SLOTS + RB * RB + 2 * CB * RB) * 64 + lane;
-    if (w < N)
-#pragma unroll
-      for (int e = 0; e < CB * CB; ++e) hml[(w * CB * CB + e) * 64 + lane] = src[e * 64];
+    const float4* src = reinterpret_cast<const float4*>(fws + d.ofw);
+    float4* dst = reinterpret_cast<float4*>(sm + L.acl);
+    for (int i = tid; i < N * AQ * 64; i += nt) {
+      const int kk = i / (AQ * 64);
+      dst[i] = src[(int64_t)kk * SLOTS * 16 + (i - kk * AQ * 64)];
+    }
   }
   const float* sk = fws + d.ofw + (int64_t)kMaxStages * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
@@ -705,6 +770,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
     lod[i] = lo;
     hid[i] = hi;
     rhod[i] = rr;
+    irhod[i] = 1.0 / rr;
   }
   const bool wm = agent_warm(warm, d);
   for (int i = tid; i < N * NU; i += nt) ud[(i / NU) * NUP + i % NU] = wm ? (double)U[i] : 0.0;
@@ -714,239 +780,443 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   }
   __syncthreads();
 
-  const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
-  const int k = w;  // this wavefront's stage (blockDim = 64 N_launch, N_launch >= N)
 
-  // x^0: rollout of the dynamics under u^0, as x_{k+1} = A_cl x + B (u - K x) + c
-  for (int kk = 0; kk < N; ++kk) {
-    if (w == kk) {
-      float xa[RB], v[CB];
+  const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
+  const int k = w;  // a stage wavefront's stage
+
+  if (w == N) {
+    // ---------------- chain wavefront ----------------
+    float M0[4 * AQ], M1[4 * AQ];  // even / odd stage operators
+    // x^0 rollout: x_{k+1} = A_cl,k x_k + [B_k (u_k - K_k x_k) + c_k from stage wavefront k]
+    for (int kk = 0; kk < N; ++kk) {
+      __syncthreads();
+      if ((kk & 1) == 0) {
+        load_chain_op<AQ>(M0, acl4, kk, lane);
+        double sx[RB];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + la * RB + j];
+        for (int i = 0; i < RB; ++i) {
+          sx[i] = 0.0;
 #pragma unroll
-      for (int i = 0; i < CB; ++i) {
-        double s = 0.0;
+          for (int j = 0; j < RB; ++j) sx[i] += (double)(M0[i * RB + j] * (float)xd[kk * NXP + lb * RB + j]);
+        }
 #pragma unroll
-        for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xa[j]);
-        v[i] = (float)(ud[kk * NUP + lb * CB + i] - red_a(s));
+        for (int i = 0; i < RB; ++i) {
+          const double v = red_b(sx[i]);
+          const int idx = la * RB + i;
+          if (lb == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = bvd[idx] + v;
+        }
+      } else {
+        load_chain_op<AQ>(M1, acl4, kk, lane);
+        double sx[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          sx[i] = 0.0;
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sx[i] += (double)(M1[i * RB + j] * (float)xd[kk * NXP + la * RB + j]);
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const double v = red_a(sx[i]);
+          const int idx = lb * RB + i;
+          if (la == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = bvd[idx] + v;
+        }
       }
+      __syncthreads();
+    }
+
+    __builtin_amdgcn_s_setprio(2);
+    // Layout of the backward chain's first input (stage N-1) and of the
+    // forward chain's last output: a*RB + i for an even stage, b*RB + i odd.
+    const int pidx = ((N - 1) & 1) ? lb * RB : la * RB;
+    // p_N = -Q x_ref,N - sigma x_N, from the relaxed x_N (here the rollout's)
+    float pN[RB];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + lb * RB + j];
+    for (int i = 0; i < RB; ++i)
+      pN[i] = (float)(-qd[pidx + i] * xrd[N * NXP + pidx + i] - sigma * xd[N * NXP + pidx + i]);
+    double qxr[RB];  // Q x_ref,N
+#pragma unroll
+    for (int i = 0; i < RB; ++i) qxr[i] = qd[pidx + i] * xrd[N * NXP + pidx + i];
+    // A_cl,0 x_0 does not change: the first forward hop only adds e_0
+    float ax0[RB];
+    {
+      load_chain_op<AQ>(M0, acl4, 0, lane);
+      float x0v[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) x0v[j] = xtf[lb * RB + j];
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
-        double s = 0.0;
+        ax0[i] = 0.f;
 #pragma unroll
-        for (int j = 0; j < RB; ++j) s += (double)(Acl[i][j] * xa[j]);
-#pragma unroll
-        for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * v[j]);
-        s = red_b(s);
-        const int idx = la * RB + i;
-        if (lb == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = (double)cf[kk * NXP + idx] + s;
+        for (int j = 0; j < RB; ++j) ax0[i] += M0[i * RB + j] * x0v[j];
+        ax0[i] = red_b(ax0[i]);
       }
     }
-    __syncthreads();
-  }
 
-  for (int it = 0; it < iters; ++it) {
+    for (int it = 0; it < iters; ++it) {
+      const int T = it + 1;
+      // backward chain, k = N-1 .. 0: p'_k = p_{k+1} + s_k, stored and flagged;
+      // p_k = g_k + A_cl,k' p'_k.  p_N is this wavefront's own, so the first hop's
+      // product runs before g_{N-1} (the last stage's A) is waited for.  Every
+      // hop issues its loads (g_k, s_{k-1}, the next operator) first.
+      {
+        float pv[RB];  // p'_k of the coming hop, in its input layout
+        // odd k: p'_k on b*RB + i, product summed over b, p_k on a*RB + j
+        auto odd_hop = [&](int kk, bool first) {
+          if (la == 0)
 #pragma unroll
-    for (int i = 0; i < CB; ++i)
+            for (int i = 0; i < RB; ++i) ppf[kk * NXP + lb * RB + i] = pv[i];
+          float gv[RB], sv[RB], qv[RB];
 #pragma unroll
-      for (int j = 0; j < RB; ++j) {
-        opaque(Km[i][j]);
-        opaque(Bm[j][i]);
-      }
-    // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k; wavefront N-1 also p_N
-    // (a launch may be wider than this agent: wavefronts past its horizon idle,
-    // joining only the workgroup barriers)
-    if (w < N) {
-      if (lane < NUP) {
-        double v = 0.0;
-        if (lane < NU) {
-          const double* yk = yd + k * M;
-          const double* zk = zd + k * M;
-          const double* rk = rhod + k * M;
-          auto wv = [&](int i) { return yk[i] - rk[i] * zk[i]; };
-          v = wv(lane);
-          if (lane >= d.n_tau) {
-            const int f = (lane - d.n_tau) / d.foot_dim, cc = (lane - d.n_tau) % d.foot_dim;
-            const int b0 = NU + 4 * f;
-            if (cc == 0) v += wv(b0) - wv(b0 + 1);
-            if (cc == 1) v += wv(b0 + 2) - wv(b0 + 3);
-            if (cc == 2) v -= mu * (wv(b0) + wv(b0 + 1) + wv(b0 + 2) + wv(b0 + 3));
+          for (int i = 0; i < RB; ++i) {
+            sv[i] = sf[(kk - 1) * NXP + la * RB + i];
+            gv[i] = first ? 0.f : gf[kk * NXP + la * RB + i];
           }
-          v += -sigma * ud[k * NUP + lane];
-          if (uref) v -= (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
-        }
-        rtd[k * NUP + lane] = v;
-      }
-      if (k == N - 1)
-        for (int i = lane; i < NX; i += 64)
-          pbuf[N * NXP + i] = (float)(-qd[i] * xrd[N * NXP + i] - sigma * xd[N * NXP + i]);
-      wave_sync();
-      // Every product below forms all its partial sums first, then all its
-      // butterflies, then one guarded store, so the independent chains
-      // interleave instead of serialising behind the store's branch.
-      if (k >= 1) {
-        float rv[CB];
-        double sg[RB];
+          load_chain_op<AQ>(M0, acl4, kk - 1, lane);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
-#pragma unroll
-        for (int j = 0; j < RB; ++j) sg[j] = 0.0;
-#pragma unroll
-        for (int i = 0; i < CB; ++i)
-#pragma unroll
-          for (int j = 0; j < RB; ++j) sg[j] += (double)(Km[i][j] * rv[i]);
-#pragma unroll
-        for (int j = 0; j < RB; ++j) sg[j] = red_b(sg[j]);
-        if (lb == 0)
-#pragma unroll
-          for (int j = 0; j < RB; ++j) {
-            const int idx = la * RB + j;
-            gf[k * NXP + idx] =
-                (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) + sg[j]);
-          }
-      }
-    }
-    // (B) backward chain, one hop per barrier: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
-    wave_sync();
-    for (int kk = N - 1; kk >= 0; --kk) {
-      if (w == kk) {
-        // s_k and g_k are this wavefront's own: their loads issue with p_{k+1}'s
-        static_assert(RB <= 8, "one output per lane of an 8-lane group");
-        float pin[RB], sreg[RB], sp[8];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) sreg[i] = sf[kk * NXP + la * RB + i];
-        const float greg = (la < RB && kk >= 1) ? gf[kk * NXP + lb * RB + la] : 0.f;
-#pragma unroll
-        for (int i = 0; i < RB; ++i) pin[i] = pbuf[(kk + 1) * NXP + la * RB + i] + sreg[i];
-        if (lb == 0)
-#pragma unroll
-          for (int i = 0; i < RB; ++i) ppf[kk * NXP + la * RB + i] = pin[i];
-        if (kk >= 1) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) sp[j] = 0.f;
+          for (int j = 0; j < RB; ++j) qv[j] = 0.f;
 #pragma unroll
           for (int i = 0; i < RB; ++i)
 #pragma unroll
-            for (int j = 0; j < RB; ++j) sp[j] += Acl[i][j] * pin[i];
-          // lane (a, b) ends with output column b*RB + a
-          const float pk = rscatter_a(sp, lane);
-          if (la < RB) pbuf[kk * NXP + lb * RB + la] = greg + pk;
+            for (int j = 0; j < RB; ++j) qv[j] += M1[i * RB + j] * pv[i];
+#pragma unroll
+          for (int j = 0; j < RB; ++j) qv[j] = red_b(qv[j]);
+          flag_set(sync + kSyncP + kk, T);
+          if (first) {
+            flag_wait(sync + kSyncG, N, T, sync, lane);
+#pragma unroll
+            for (int i = 0; i < RB; ++i) gv[i] = gf[kk * NXP + la * RB + i];
+          }
+#pragma unroll
+          for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
+        };
+        // even k >= 2: p'_k on a*RB + i, product summed over a, p_k on b*RB + j
+        auto even_hop = [&](int kk, bool first) {
+          if (lb == 0)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) ppf[kk * NXP + la * RB + i] = pv[i];
+          float gv[RB], sv[RB], qv[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            sv[i] = sf[(kk - 1) * NXP + lb * RB + i];
+            gv[i] = first ? 0.f : gf[kk * NXP + lb * RB + i];
+          }
+          load_chain_op<AQ>(M1, acl4, kk - 1, lane);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int j = 0; j < RB; ++j) qv[j] = 0.f;
+#pragma unroll
+          for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) qv[j] += M0[i * RB + j] * pv[i];
+          red_a_all<RB>(qv);
+          flag_set(sync + kSyncP + kk, T);
+          if (first) {
+            flag_wait(sync + kSyncG, N, T, sync, lane);
+#pragma unroll
+            for (int i = 0; i < RB; ++i) gv[i] = gf[kk * NXP + lb * RB + i];
+          }
+#pragma unroll
+          for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
+        };
+        int kk = N - 1;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) pv[i] = pN[i] + sf[kk * NXP + pidx + i];
+        bool first = true;
+        if (kk & 1) {
+          load_chain_op<AQ>(M1, acl4, kk, lane);
+          odd_hop(kk, true);
+          first = false;
+          --kk;
+        } else {
+          load_chain_op<AQ>(M0, acl4, kk, lane);
         }
+        for (; kk >= 2; kk -= 2) {
+          even_hop(kk, first);
+          first = false;
+          odd_hop(kk - 1, false);
+        }
+        if (first) flag_wait(sync + kSyncG, N, T, sync, lane);  // N == 1: no hop waited
+        // k = 0: p'_0 only
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) ppf[la * RB + i] = pv[i];
+        flag_set(sync + kSyncP, T);
       }
-      __syncthreads();
+      // forward chain, k = 0 .. N-1: xt_{k+1} = A_cl,k xt_k + e_k, stored and
+      // flagged; the relaxed x_N and p_N for the next iteration come from xt_N
+      // before the last flag lets stage N-1 overwrite x_N
+      {
+        float xv[RB];  // xt_k of the coming hop, in its input layout
+        // even k: xt_k on b*RB + j, summed over b, xt_{k+1} on a*RB + i
+        auto even_hop = [&](int kk, int next) {
+          float ev[RB], sx[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) ev[i] = ef[kk * NXP + la * RB + i];
+          load_chain_op<AQ>(M1, acl4, next, lane);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+#pragma unroll
+          for (int j = 0; j < RB; ++j)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) sx[i] += M0[i * RB + j] * xv[j];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xv[i] = ev[i] + red_b(sx[i]);
+          if (lb == 0)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) xtf[(kk + 1) * NXP + la * RB + i] = xv[i];
+        };
+        // odd k: xt_k on a*RB + j, summed over a, xt_{k+1} on b*RB + i
+        auto odd_hop = [&](int kk, int next) {
+          float ev[RB], sx[RB];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) ev[i] = ef[kk * NXP + lb * RB + i];
+          if (next >= 0) load_chain_op<AQ>(M0, acl4, next, lane);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+#pragma unroll
+          for (int j = 0; j < RB; ++j)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) sx[i] += M1[i * RB + j] * xv[j];
+          red_a_all<RB>(sx);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xv[i] = ev[i] + sx[i];
+          if (la == 0)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) xtf[(kk + 1) * NXP + lb * RB + i] = xv[i];
+        };
+        // stage 0: A_cl,0 x_0 + e_0 once C_0 is out
+        if (N > 1) load_chain_op<AQ>(M1, acl4, 1, lane);
+        flag_wait(sync + kSyncE, N, T, sync, lane);  // e_k of the stage wavefronts
+#pragma unroll
+        for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + ef[la * RB + i];
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xtf[NXP + la * RB + i] = xv[i];
+        if (N > 1) flag_set(sync + kSyncX + 1, T);
+        int kk = 1;
+        for (; kk + 1 < N; kk += 2) {
+          odd_hop(kk, kk + 1);
+          flag_set(sync + kSyncX + kk + 1, T);
+          // the last pair prefetches stage N-1 again rather than branch
+          even_hop(kk + 1, kk + 2 < N ? kk + 2 : N - 1);
+          if (kk + 2 < N) flag_set(sync + kSyncX + kk + 2, T);
+        }
+        if (kk < N) odd_hop(kk, -1);
+        // xt_N is in xv now, in the layout pidx
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const double xn = alpha * (double)xv[i] + oma * xd[N * NXP + pidx + i];
+          pN[i] = (float)(-qxr[i] - sigma * xn);
+        }
+        flag_set(sync + kSyncX + N, T);
+      }
     }
-    // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
-    if (w < N) {
-      float pv[RB], hv[CB];
-      double sh[CB], sd[CB], rtv[CB];
+  } else {
+    // ---------------- stage wavefront k ----------------
+    // (a launch may be wider than this agent: wavefronts past its chain
+    // wavefront idle, joining only the workgroup barriers)
+    float Km[CB][RB], Bm[RB][CB], Hm[CB][CB];
+    {
+      const bool own = w < N;
+      const float* src = fws + d.ofw + ((int64_t)w * SLOTS + 4 * AQ) * 64 + lane;
 #pragma unroll
-      for (int i = 0; i < RB; ++i) pv[i] = ppf[k * NXP + la * RB + i];
+      for (int i = 0; i < CB; ++i)
 #pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        rtv[j] = rtd[k * NUP + lb * CB + j];
-        sh[j] = 0.0;
-      }
+        for (int j = 0; j < RB; ++j) Km[i][j] = own ? src[(i * RB + j) * 64] : 0.f;
+      src += CB * RB * 64;
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < CB; ++j) sh[j] += (double)(Bm[i][j] * pv[i]);
+        for (int j = 0; j < CB; ++j) Bm[i][j] = own ? src[(i * CB + j) * 64] : 0.f;
+      src += RB * CB * 64;
 #pragma unroll
-      for (int j = 0; j < CB; ++j) hv[j] = (float)(rtv[j] + red_a(sh[j]));
+      for (int i = 0; i < CB; ++i)
 #pragma unroll
-      for (int i = 0; i < CB; ++i) sd[i] = 0.0;
-#pragma unroll
-      for (int j = 0; j < CB; ++j)
-#pragma unroll
-        for (int i = 0; i < CB; ++i)
-          sd[i] += (double)(hml[(k * CB * CB + i * CB + j) * 64 + lane] * hv[j]);
-#pragma unroll
-      for (int i = 0; i < CB; ++i) sd[i] = red_b(sd[i]);
-      if (lb == 0)
-#pragma unroll
-        for (int i = 0; i < CB; ++i) dd[k * NUP + la * CB + i] = -sd[i];
-      wave_sync();
-      float dv[CB], cv[RB];
-      double se[RB];
-#pragma unroll
-      for (int j = 0; j < CB; ++j) dv[j] = (float)dd[k * NUP + lb * CB + j];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        cv[i] = cf[k * NXP + la * RB + i];
-        se[i] = 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < CB; ++j)
-#pragma unroll
-        for (int i = 0; i < RB; ++i) se[i] += (double)(Bm[i][j] * dv[j]);
-#pragma unroll
-      for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
-      if (lb == 0)
-#pragma unroll
-        for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = (float)((double)cv[i] + se[i]);
+        for (int j = 0; j < CB; ++j) Hm[i][j] = own ? src[(i * CB + j) * 64] : 0.f;
     }
-    __syncthreads();
-    // (D) forward chain: xt_{k+1} = A_cl,k xt_k + e_k
-    wave_sync();
+    // x^0 rollout: this stage's B_k (u_k - K_k x_k) + c_k when the chain reaches it
     for (int kk = 0; kk < N; ++kk) {
       if (w == kk) {
-        float xin[RB], sx[RB], ereg[RB];
+        float xa[RB], v[CB];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) ereg[i] = ef[kk * NXP + la * RB + i];
+        for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + la * RB + j];
 #pragma unroll
-        for (int j = 0; j < RB; ++j) xin[j] = xtf[kk * NXP + lb * RB + j];
+        for (int i = 0; i < CB; ++i) {
+          double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+          for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xa[j]);
+          v[i] = (float)(ud[kk * NUP + lb * CB + i] - red_a(s));
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * v[j]);
+          s = red_b(s);
+          const int idx = la * RB + i;
+          if (lb == 0 && idx < NX) bvd[idx] = (double)cf[kk * NXP + idx] + s;
+        }
+      }
+      __syncthreads();
+      __syncthreads();
+    }
+
+    const int n_it = w < N ? iters : 0;  // wavefronts past the chain wavefront idle
+    for (int it = 0; it < n_it; ++it) {
+      const int T = it + 1;
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          opaque(Km[i][j]);
+          opaque(Bm[j][i]);
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j) opaque(Hm[i][j]);
+      }
+      // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k
+      if (w < N) {
+        if (lane < NUP) {
+          double v = 0.0;
+          if (lane < NU) {
+            const double* yk = yd + k * M;
+            const double* zk = zd + k * M;
+            const double* rk = rhod + k * M;
+            auto wv = [&](int i) { return yk[i] - rk[i] * zk[i]; };
+            v = wv(lane);
+            if (lane >= d.n_tau) {
+              const int f = (lane - d.n_tau) / d.foot_dim, cc = (lane - d.n_tau) % d.foot_dim;
+              const int b0 = NU + 4 * f;
+              if (cc == 0) v += wv(b0) - wv(b0 + 1);
+              if (cc == 1) v += wv(b0 + 2) - wv(b0 + 3);
+              if (cc == 2) v -= mu * (wv(b0) + wv(b0 + 1) + wv(b0 + 2) + wv(b0 + 3));
+            }
+            v += -sigma * ud[k * NUP + lane];
+            if (uref) v -= (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
+          }
+          rtd[k * NUP + lane] = v;
+        }
+        wave_sync();
+        // Every product below forms all its partial sums first, then all its
+        // butterflies, then one guarded store, so the independent chains
+        // interleave instead of serialising behind the store's branch.
+        if (k >= 1) {
+          float rv[CB], sg[RB];
+#pragma unroll
+          for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sg[j] = 0.f;
+#pragma unroll
+          for (int i = 0; i < CB; ++i)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) sg[j] += Km[i][j] * rv[i];
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sg[j] = red_b(sg[j]);
+          if (lb == 0)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) {
+              const int idx = la * RB + j;
+              gf[k * NXP + idx] = (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) +
+                                          (double)sg[j]);
+            }
+        }
+      }
+      flag_set(sync + kSyncG + k, T);
+      // (B) backward chain on the chain wavefront; C_k starts once p'_k is out
+      flag_wait(sync + kSyncP + k, 1, T, sync, lane);
+      // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
+      if (w < N) {
+        float pv[RB], hv[CB], sh[CB], sd[CB];
+        double rtv[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) pv[i] = ppf[k * NXP + la * RB + i];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          rtv[j] = rtd[k * NUP + lb * CB + j];
+          sh[j] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j) sh[j] += Bm[i][j] * pv[i];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) hv[j] = (float)(rtv[j] + (double)red_a(sh[j]));
+#pragma unroll
+        for (int i = 0; i < CB; ++i) sd[i] = 0.f;
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int i = 0; i < CB; ++i) sd[i] += Hm[i][j] * hv[j];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) sd[i] = red_b(sd[i]);
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < CB; ++i) dd[k * NUP + la * CB + i] = -(double)sd[i];
+        wave_sync();
+        float dv[CB], cv[RB], se[RB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) dv[j] = (float)dd[k * NUP + lb * CB + j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          cv[i] = cf[k * NXP + la * RB + i];
+          se[i] = 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) se[i] += Bm[i][j] * dv[j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = cv[i] + se[i];
+      }
+      flag_set(sync + kSyncE + k, T);
+      // (D) forward chain on the chain wavefront; E_k starts once xt_k (and for
+      // the last stage xt_N) is out
+      if (k >= 1) flag_wait(sync + kSyncX + k, 1, T, sync, lane);
+      if (k == N - 1) flag_wait(sync + kSyncX + N, 1, T, sync, lane);
+      // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
+      if (w < N) {
+        float xv[RB], su[CB];
+        double dvv[CB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) xv[j] = xtf[k * NXP + la * RB + j];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+          dvv[i] = dd[k * NUP + lb * CB + i];
+          su[i] = 0.f;
+        }
 #pragma unroll
         for (int j = 0; j < RB; ++j)
 #pragma unroll
-          for (int i = 0; i < RB; ++i) sx[i] += Acl[i][j] * xin[j];
+          for (int i = 0; i < CB; ++i) su[i] += Km[i][j] * xv[j];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) sx[i] = red_b(sx[i]);
-        if (lb == 0)
+        for (int i = 0; i < CB; ++i) su[i] = red_a(su[i]);
+        if (la == 0)
 #pragma unroll
-          for (int i = 0; i < RB; ++i) xtf[(kk + 1) * NXP + la * RB + i] = ereg[i] + sx[i];
+          for (int i = 0; i < CB; ++i) utd[k * NUP + lb * CB + i] = dvv[i] + (double)su[i];
+        wave_sync();
+        if (k >= 1)
+          for (int i = lane; i < NX; i += 64)
+            xd[k * NXP + i] = alpha * (double)xtf[k * NXP + i] + oma * xd[k * NXP + i];
+        if (k == N - 1)
+          for (int i = lane; i < NX; i += 64)
+            xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
+        if (lane < M) {
+          const int idx = k * M + lane;
+          const double zeta = c_row<double>(d, lane, mu, utd + k * NUP);
+          const double wv = alpha * zeta + oma * zd[idx];
+          const double zn = fmin(fmax(wv + yd[idx] * irhod[idx], lod[idx]), hid[idx]);
+          yd[idx] = yd[idx] + rhod[idx] * (wv - zn);
+          zd[idx] = zn;
+        }
+        if (lane < NU) ud[k * NUP + lane] = alpha * utd[k * NUP + lane] + oma * ud[k * NUP + lane];
+        wave_sync();
       }
-      __syncthreads();
-    }
-    // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
-    if (w < N) {
-      float xv[RB];
-      double su[CB], dvv[CB];
-#pragma unroll
-      for (int j = 0; j < RB; ++j) xv[j] = xtf[k * NXP + la * RB + j];
-#pragma unroll
-      for (int i = 0; i < CB; ++i) {
-        dvv[i] = dd[k * NUP + lb * CB + i];
-        su[i] = 0.0;
-      }
-#pragma unroll
-      for (int j = 0; j < RB; ++j)
-#pragma unroll
-        for (int i = 0; i < CB; ++i) su[i] += (double)(Km[i][j] * xv[j]);
-#pragma unroll
-      for (int i = 0; i < CB; ++i) su[i] = red_a(su[i]);
-      if (la == 0)
-#pragma unroll
-        for (int i = 0; i < CB; ++i) utd[k * NUP + lb * CB + i] = dvv[i] + su[i];
-      wave_sync();
-      if (k >= 1)
-        for (int i = lane; i < NX; i += 64)
-          xd[k * NXP + i] = alpha * (double)xtf[k * NXP + i] + oma * xd[k * NXP + i];
-      if (k == N - 1)
-        for (int i = lane; i < NX; i += 64)
-          xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
-      if (lane < M) {
-        const int idx = k * M + lane;
-        const double zeta = c_row<double>(d, lane, mu, utd + k * NUP);
-        const double wv = alpha * zeta + oma * zd[idx];
-        const double zn = fmin(fmax(wv + yd[idx] / rhod[idx], lod[idx]), hid[idx]);
-        yd[idx] = yd[idx] + rhod[idx] * (wv - zn);
-        zd[idx] = zn;
-      }
-      if (lane < NU) ud[k * NUP + lane] = alpha * utd[k * NUP + lane] + oma * ud[k * NUP + lane];
-      wave_sync();
     }
   }
   __syncthreads();
@@ -967,7 +1237,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
     Y[i] = (float)yd[i];
     fin &= (bool)isfinite(Z[i]) && (bool)isfinite(Y[i]);
   }
-  if (!fin) atomicOr(flag, 1);
+  if (!fin || sync[kSyncAbort]) atomicOr(flag, 1);
   __syncthreads();
   if (tid == 0 && flag[0]) st.status[agent] = AGENT_NONFINITE;
 }
@@ -986,7 +1256,7 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
     if (e != hipSuccess) return e;
   }
   if (phase_mask & 2) {
-    hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_launch), dim3(64 * N), li, stream,
+    hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_launch), dim3(64 * (N + 1)), li, stream,
                        d_desc, list, n_launch, in, sc, iters, warm, fws, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1017,7 +1287,7 @@ hipError_t set_limits() {
 
 bool fused_supported(int N, int nx, int nu, int n_feet) {
   const int m = nu + 4 * n_feet;
-  if (N < 1 || N > kMaxStages || m > 64) return false;
+  if (N < 1 || N + 1 > kMaxStages || m > 64) return false;
   if (nx == 48 && nu == 30) return iter_lds_layout<48, 30>(N, m).total <= 160 * 1024;
   if (nx == 36 && nu == 24) return iter_lds_layout<36, 24>(N, m).total <= 160 * 1024;
   return false;
@@ -1025,7 +1295,7 @@ bool fused_supported(int N, int nx, int nu, int n_feet) {
 
 void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds) {
   const int m = nu + 4 * n_feet;
-  *threads = 64 * N;
+  *threads = 64 * (N + 1);
   *lds = (nx == 48) ? iter_lds_layout<48, 30>(N, m).total : iter_lds_layout<36, 24>(N, m).total;
   (void)nu;
 }

@@ -258,8 +258,8 @@ def test_quadruped_uniform_fp32(kernel):
 
 
 def test_fused_horizon_limits():
-    """The register-resident kernels serve N <= 12; longer horizons fall back."""
-    for N, want in ((1, "fused"), (12, "fused"), (13, "generic")):
+    """The register-resident kernels serve N <= 11; longer horizons fall back."""
+    for N, want in ((1, "fused"), (11, "fused"), (12, "generic")):
         plan = mpc.Plan([synth.humanoid(N)] * 2, precision="fp32")
         assert plan.config()["kernel"] == want, N
     b = synth.make_batch([synth.humanoid(1)] * 4, seed=2, config_id=52)

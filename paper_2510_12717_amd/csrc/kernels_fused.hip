@@ -581,15 +581,18 @@ __device__ inline void flag_set(int* f, int v) {
   __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 // Waits until every one of f[0 .. n) (n <= 64, one lane each) is >= v.  The
-// wait is bounded: past kSpinLimit polls it raises the abort flag, and every
-// wait returns at once while that flag is up, so the workgroup always drains
-// (the agent then reports non-finite).
+// first polls spin (the handovers on the critical path are short); later ones
+// sleep between polls.  The wait is bounded: past kSpinLimit polls it raises
+// the abort flag, and every wait returns at once while that flag is up (it is
+// read every 64 polls), so the workgroup always drains (the agent then reports
+// non-finite).
 __device__ inline void flag_wait(int* f, int n, int v, int* sync, int lane) {
   for (int t = 0; t < kSpinLimit; ++t) {
     const int x = lane < n ? __hip_atomic_load(f + lane, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) : v;
     if (__all(x >= v)) return;
-    if (__hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
-    __builtin_amdgcn_s_sleep(1);
+    if ((t & 63) == 63 && __hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+    if (t >= 32) __builtin_amdgcn_s_sleep(1);
   }
   __hip_atomic_store(sync + kSyncAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }

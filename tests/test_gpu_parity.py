@@ -309,3 +309,24 @@ def test_largest_supported_horizon():
     with pytest.raises(mpc.MPCError) as ei:
         mpc.Plan([synth.humanoid(44)], precision="fp64")
     assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE
+
+
+def test_fused_every_horizon_both_shapes():
+    """The register-resident kernels at every horizon they serve, both built shapes,
+    cold and warm: the chain wavefront's lane layouts alternate with the stage's
+    parity, so odd and even horizons end the chains in different layouts."""
+    shapes = [synth.humanoid(N) for N in range(1, 12)] + [synth.quadruped(N) for N in range(1, 12)]
+    b = synth.make_batch(shapes, seed=4, config_id=61)
+    g, plan, prob = run_gpu(b, "fp32", kernel="fused")
+    assert plan.config()["kernel"] == "fused"
+    o = oracle.solve_batch(b, iters=50)
+    assert np.all(g["status"] == 0)
+    e = agent_errors(b, g, o)
+    print("fused every horizon: max u0/traj %s" % e[:, :2].max(axis=0))
+    assert e[:, :2].max() < TOL["fp32"]
+    # a second, warm-started solve from the first one's iterate
+    warm = {k: g[k] for k in ("u", "z", "y")}
+    g2, _, _ = run_gpu(b, "fp32", kernel="fused", warm=warm)
+    o2 = oracle.solve_batch(b, iters=50, warm={k: o[k] for k in ("u", "z", "y")})
+    e2 = agent_errors(b, g2, o2)
+    assert np.all(g2["status"] == 0) and e2[:, :2].max() < TOL["fp32"]

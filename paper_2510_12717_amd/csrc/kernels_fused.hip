@@ -993,6 +993,10 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         // stage 0: A_cl,0 x_0 + e_0 once C_0 is out
         if (N > 1) load_chain_op<AQ>(M1, acl4, 1, lane);
         flag_wait(sync + kSyncE, N, T, sync, lane);  // e_k of the stage wavefronts
+        // x_N as relaxed in the previous iteration (stage N-1 wrote it before its C)
+        double xdN[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
 #pragma unroll
         for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + ef[la * RB + i];
         if (lb == 0)
@@ -1008,13 +1012,15 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
           if (kk + 2 < N) flag_set(sync + kSyncX + kk + 2, T);
         }
         if (kk < N) odd_hop(kk, -1);
-        // xt_N is in xv now, in the layout pidx
+        // xt_N is in xv now, in the layout pidx; x_N (the previous iteration's
+        // relaxation, which stage N-1 overwrites once xt_N is flagged) was read
+        // at the start of the chain
+        flag_set(sync + kSyncX + N, T);
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-          const double xn = alpha * (double)xv[i] + oma * xd[N * NXP + pidx + i];
+          const double xn = alpha * (double)xv[i] + oma * xdN[i];
           pN[i] = (float)(-qxr[i] - sigma * xn);
         }
-        flag_set(sync + kSyncX + N, T);
       }
     }
   } else {
@@ -1067,6 +1073,12 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       __syncthreads();
     }
 
+    // x_N <- alpha xt_N + (1 - alpha) x_N once the forward chain of iteration t is out
+    auto relax_xN = [&](int t) {
+      flag_wait(sync + kSyncX + N, 1, t, sync, lane);
+      for (int i = lane; i < NX; i += 64)
+        xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
+    };
     const int n_it = w < N ? iters : 0;  // wavefronts past the chain wavefront idle
     for (int it = 0; it < n_it; ++it) {
       const int T = it + 1;
@@ -1128,6 +1140,10 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         }
       }
       flag_set(sync + kSyncG + k, T);
+      // The relaxed x_N of the previous iteration (nothing else in this
+      // iteration needs it before the forward chain reads it again); the chain
+      // wavefront has taken its own copy for p_N before flagging xt_N.
+      if (k == N - 1 && it >= 1) relax_xN(T - 1);
       // (B) backward chain on the chain wavefront; C_k starts once p'_k is out
       flag_wait(sync + kSyncP + k, 1, T, sync, lane);
       // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
@@ -1178,10 +1194,8 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
           for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = cv[i] + se[i];
       }
       flag_set(sync + kSyncE + k, T);
-      // (D) forward chain on the chain wavefront; E_k starts once xt_k (and for
-      // the last stage xt_N) is out
+      // (D) forward chain on the chain wavefront; E_k starts once xt_k is out
       if (k >= 1) flag_wait(sync + kSyncX + k, 1, T, sync, lane);
-      if (k == N - 1) flag_wait(sync + kSyncX + N, 1, T, sync, lane);
       // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
       if (w < N) {
         float xv[RB], su[CB];
@@ -1206,9 +1220,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         if (k >= 1)
           for (int i = lane; i < NX; i += 64)
             xd[k * NXP + i] = alpha * (double)xtf[k * NXP + i] + oma * xd[k * NXP + i];
-        if (k == N - 1)
-          for (int i = lane; i < NX; i += 64)
-            xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
         if (lane < M) {
           const int idx = k * M + lane;
           const double zeta = c_row<double>(d, lane, mu, utd + k * NUP);
@@ -1221,6 +1232,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         wave_sync();
       }
     }
+    if (k == N - 1 && n_it > 0) relax_xN(n_it);
   }
   __syncthreads();
 

@@ -599,7 +599,7 @@ __device__ inline void flag_wait(int* f, int n, int v, int* sync, int lane) {
 
 struct IterLds {
   int acl, xtf, ppf, gf, ef, sf, cf;                               // float
-  int xd, ud, zd, yd, lod, hid, rhod, irhod, rtd, dd, utd, qd, xrd, bvd;  // double
+  int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd, bvd;  // double
   int flag, sync, total;
 };
 
@@ -628,11 +628,13 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
   L.hid = take(8 * N * M);
   L.rhod = take(8 * N * M);
   L.irhod = take(8 * N * M);
+  L.wvd = take(8 * N * M);
   L.rtd = take(8 * N * S::NUP);
   L.dd = take(8 * N * S::NUP);
   L.utd = take(8 * N * S::NUP);
   L.qd = take(8 * S::NXP);
   L.xrd = take(8 * (N + 1) * S::NXP);
+  L.qtd = take(8 * N * S::NXP);
   L.bvd = take(8 * S::NXP);
   L.flag = take(16);
   L.sync = take(4 * kSyncInts);
@@ -727,11 +729,13 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   double* hid = reinterpret_cast<double*>(sm + L.hid);
   double* rhod = reinterpret_cast<double*>(sm + L.rhod);
   double* irhod = reinterpret_cast<double*>(sm + L.irhod);
+  double* wvd = reinterpret_cast<double*>(sm + L.wvd);
   double* rtd = reinterpret_cast<double*>(sm + L.rtd);
   double* dd = reinterpret_cast<double*>(sm + L.dd);
   double* utd = reinterpret_cast<double*>(sm + L.utd);
   double* qd = reinterpret_cast<double*>(sm + L.qd);
   double* xrd = reinterpret_cast<double*>(sm + L.xrd);
+  double* qtd = reinterpret_cast<double*>(sm + L.qtd);
   double* bvd = reinterpret_cast<double*>(sm + L.bvd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
@@ -1079,6 +1083,37 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       for (int i = lane; i < NX; i += 64)
         xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
     };
+    // Per-lane row bookkeeping of this stage, fixed for the solve.  Row i < M:
+    // (C u)_i = zc_s1 u[zc_i1] + zc_s2 u[zc_i2].  Input j < NU: (C' w)_j = w_j
+    // plus, for a foot's pyramid components, its four pyramid rows from rt_b0
+    // (rt_cc picks the combination; other components add nothing).
+    int zc_i1 = 0, zc_i2 = 0, rt_b0 = 0, rt_cc = -1;
+    double zc_s1 = 0.0, zc_s2 = 0.0, u_own = 0.0, ru_own = 0.0;
+    if (lane < M) {
+      if (lane < NU) {
+        zc_i1 = zc_i2 = lane;
+        zc_s1 = 1.0;
+      } else {
+        const int f = (lane - NU) >> 2, pp = (lane - NU) & 3, b = d.n_tau + f * d.foot_dim;
+        zc_i1 = pp < 2 ? b : b + 1;
+        zc_s1 = (pp & 1) ? -1.0 : 1.0;
+        zc_i2 = b + 2;
+        zc_s2 = -mu;
+      }
+    }
+    if (lane < NU && lane >= d.n_tau) {
+      rt_b0 = NU + 4 * ((lane - d.n_tau) / d.foot_dim);
+      rt_cc = (lane - d.n_tau) % d.foot_dim;
+    }
+    if (k < N) {
+      if (lane < NU) {
+        u_own = ud[k * NUP + lane];
+        if (uref) ru_own = (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
+      }
+      if (lane < M) wvd[k * M + lane] = yd[k * M + lane] - rhod[k * M + lane] * zd[k * M + lane];
+      if (k >= 1 && lane < NX) qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xd[k * NXP + lane];
+      wave_sync();
+    }
     const int n_it = w < N ? iters : 0;  // wavefronts past the chain wavefront idle
     for (int it = 0; it < n_it; ++it) {
       const int T = it + 1;
@@ -1094,23 +1129,20 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       }
       // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k
       if (w < N) {
+        // rt_k = C_k'(y_k - rho_k z_k) - sigma u_k - R ubar_k, from the row
+        // terms w = y - rho z that E left in LDS (lane j < NU: its own row and
+        // the four pyramid rows of its foot)
         if (lane < NUP) {
           double v = 0.0;
           if (lane < NU) {
-            const double* yk = yd + k * M;
-            const double* zk = zd + k * M;
-            const double* rk = rhod + k * M;
-            auto wv = [&](int i) { return yk[i] - rk[i] * zk[i]; };
-            v = wv(lane);
-            if (lane >= d.n_tau) {
-              const int f = (lane - d.n_tau) / d.foot_dim, cc = (lane - d.n_tau) % d.foot_dim;
-              const int b0 = NU + 4 * f;
-              if (cc == 0) v += wv(b0) - wv(b0 + 1);
-              if (cc == 1) v += wv(b0 + 2) - wv(b0 + 3);
-              if (cc == 2) v -= mu * (wv(b0) + wv(b0 + 1) + wv(b0 + 2) + wv(b0 + 3));
-            }
-            v += -sigma * ud[k * NUP + lane];
-            if (uref) v -= (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
+            const double* wk = wvd + k * M;
+            const double w0 = wk[rt_b0], w1 = wk[rt_b0 + 1], w2 = wk[rt_b0 + 2], w3 = wk[rt_b0 + 3];
+            v = wk[lane];
+            if (rt_cc == 0) v += w0 - w1;
+            if (rt_cc == 1) v += w2 - w3;
+            if (rt_cc == 2) v -= mu * (w0 + w1 + w2 + w3);
+            v += -sigma * u_own;
+            v -= ru_own;
           }
           rtd[k * NUP + lane] = v;
         }
@@ -1120,8 +1152,11 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         // interleave instead of serialising behind the store's branch.
         if (k >= 1) {
           float rv[CB], sg[RB];
+          double qt[RB];
 #pragma unroll
           for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
+#pragma unroll
+          for (int j = 0; j < RB; ++j) qt[j] = qtd[k * NXP + la * RB + j];
 #pragma unroll
           for (int j = 0; j < RB; ++j) sg[j] = 0.f;
 #pragma unroll
@@ -1134,8 +1169,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 #pragma unroll
             for (int j = 0; j < RB; ++j) {
               const int idx = la * RB + j;
-              gf[k * NXP + idx] = (float)((-qd[idx] * xrd[k * NXP + idx] - sigma * xd[k * NXP + idx]) +
-                                          (double)sg[j]);
+              gf[k * NXP + idx] = (float)(qt[j] + (double)sg[j]);
             }
         }
       }
@@ -1211,24 +1245,32 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         for (int j = 0; j < RB; ++j)
 #pragma unroll
           for (int i = 0; i < CB; ++i) su[i] += Km[i][j] * xv[j];
-#pragma unroll
-        for (int i = 0; i < CB; ++i) su[i] = red_a(su[i]);
+        red_a_all<CB>(su);
         if (la == 0)
 #pragma unroll
           for (int i = 0; i < CB; ++i) utd[k * NUP + lb * CB + i] = dvv[i] + (double)su[i];
         wave_sync();
-        if (k >= 1)
-          for (int i = lane; i < NX; i += 64)
-            xd[k * NXP + i] = alpha * (double)xtf[k * NXP + i] + oma * xd[k * NXP + i];
+        // relaxed x_k and its qt_k = -Q x_ref,k - sigma x_k for the next A
+        if (k >= 1 && lane < NX) {
+          const double xn = alpha * (double)xtf[k * NXP + lane] + oma * xd[k * NXP + lane];
+          xd[k * NXP + lane] = xn;
+          qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xn;
+        }
+        // row `lane`: (C ut)_i, relaxation, projection, dual update, w = y - rho z
         if (lane < M) {
           const int idx = k * M + lane;
-          const double zeta = c_row<double>(d, lane, mu, utd + k * NUP);
+          const double zeta = zc_s1 * utd[k * NUP + zc_i1] + zc_s2 * utd[k * NUP + zc_i2];
           const double wv = alpha * zeta + oma * zd[idx];
           const double zn = fmin(fmax(wv + yd[idx] * irhod[idx], lod[idx]), hid[idx]);
-          yd[idx] = yd[idx] + rhod[idx] * (wv - zn);
+          const double yn = yd[idx] + rhod[idx] * (wv - zn);
+          yd[idx] = yn;
           zd[idx] = zn;
+          wvd[idx] = yn - rhod[idx] * zn;
         }
-        if (lane < NU) ud[k * NUP + lane] = alpha * utd[k * NUP + lane] + oma * ud[k * NUP + lane];
+        if (lane < NU) {
+          u_own = alpha * utd[k * NUP + lane] + oma * u_own;
+          ud[k * NUP + lane] = u_own;
+        }
         wave_sync();
       }
     }

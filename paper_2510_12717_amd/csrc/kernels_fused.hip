@@ -30,6 +30,8 @@
 // either the b index (lanes xor 1, 2, 4) or the a index (lanes xor 8, 16, 32).
 #include <math.h>
 
+#include <type_traits>
+
 #include "fused.h"
 #include "stage_rows.h"
 #include "xlane.h"
@@ -54,10 +56,10 @@ struct FS {
   static constexpr int MMAX = 64;
 };
 
-// Marks a register value as redefined here, so loop-invariant code motion
-// cannot hoist its float->double conversions out of the iteration loop (which
-// would keep a double copy of every operator alive and spill).
-__device__ inline void opaque(float& v) { asm volatile("" : "+v"(v)); }
+
+// Hides a uniform integer's value from the optimiser, so addresses built on it
+// are formed once instead of folded into others with negative offsets.
+__device__ inline void opaque_s(int& v) { asm volatile("" : "+s"(v)); }
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -663,11 +665,40 @@ __device__ inline void red_a_all(float (&v)[n]) {
   if (n & 1) v[n - 1] = swap_sum32(swap_sum16(v[n - 1]));
 }
 
+// R consecutive floats from / to LDS, in float2 pieces when R is even (the
+// callers' offsets are then even)
+template <int R>
+__device__ inline void lds_load(float (&v)[R], const float* p) {
+  if constexpr (R % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      const float2 t = reinterpret_cast<const float2*>(p)[i];
+      v[2 * i] = t.x;
+      v[2 * i + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = p[i];
+  }
+}
+template <int R>
+__device__ inline void lds_store(float* p, const float (&v)[R]) {
+  if constexpr (R % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) reinterpret_cast<float2*>(p)[i] = make_float2(v[2 * i], v[2 * i + 1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) p[i] = v[i];
+  }
+}
+
 // A_cl,k of the chain wavefront, one float4 quad at a time from LDS
 // ([stage][quad][lane][4]); slot i*RB + j of the lane's RB x RB block.
 template <int AQ>
 __device__ inline void load_chain_op(float (&M)[4 * AQ], const float4* acl4, int kk, int lane) {
-  const float4* src = acl4 + kk * AQ * 64 + lane;
+  int off = kk * AQ * 64;  // opaque: one base, then immediate offsets
+  asm volatile("" : "+s"(off));
+  const float4* src = acl4 + off + lane;
 #pragma unroll
   for (int q = 0; q < AQ; ++q) {
     const float4 v = src[q * 64];
@@ -840,9 +871,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 #pragma unroll
     for (int i = 0; i < RB; ++i)
       pN[i] = (float)(-qd[pidx + i] * xrd[N * NXP + pidx + i] - sigma * xd[N * NXP + pidx + i]);
-    double qxr[RB];  // Q x_ref,N
-#pragma unroll
-    for (int i = 0; i < RB; ++i) qxr[i] = qd[pidx + i] * xrd[N * NXP + pidx + i];
     // A_cl,0 x_0 does not change: the first forward hop only adds e_0
     float ax0[RB];
     {
@@ -867,87 +895,70 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       // hop issues its loads (g_k, s_{k-1}, the next operator) first.
       {
         float pv[RB];  // p'_k of the coming hop, in its input layout
-        // odd k: p'_k on b*RB + i, product summed over b, p_k on a*RB + j
-        auto odd_hop = [&](int kk, bool first) {
-          if (la == 0)
-#pragma unroll
-            for (int i = 0; i < RB; ++i) ppf[kk * NXP + lb * RB + i] = pv[i];
+        // Hop kk (first: the first hop of the chain, which waits for the g_k
+        // only after its product).  ODD: p'_k on b*RB + i, product summed over
+        // b, p_k on a*RB + j; even: the roles of a and b swap.
+        auto hop = [&](int kk, bool first, auto odd_c) {
+          constexpr bool ODD = decltype(odd_c)::value;
+          const int in_idx = ODD ? lb * RB : la * RB, out_idx = ODD ? la * RB : lb * RB;
+          // stage offsets kept opaque so each vector is one base plus immediates
+          int ok = kk * NXP, om = (kk - 1) * NXP;
+          opaque_s(ok);
+          opaque_s(om);
+          if ((ODD ? la : lb) == 0) lds_store<RB>(ppf + ok + in_idx, pv);
           float gv[RB], sv[RB], qv[RB];
-#pragma unroll
-          for (int i = 0; i < RB; ++i) {
-            sv[i] = sf[(kk - 1) * NXP + la * RB + i];
-            gv[i] = first ? 0.f : gf[kk * NXP + la * RB + i];
-          }
-          load_chain_op<AQ>(M0, acl4, kk - 1, lane);
-          __builtin_amdgcn_sched_barrier(0);
+          lds_load<RB>(sv, sf + om + out_idx);
+          lds_load<RB>(gv, gf + ok + out_idx);  // (reloaded below on the first hop)
 #pragma unroll
           for (int j = 0; j < RB; ++j) qv[j] = 0.f;
+          if constexpr (ODD) {
+            load_chain_op<AQ>(M0, acl4, kk - 1, lane);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int i = 0; i < RB; ++i)
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
-            for (int j = 0; j < RB; ++j) qv[j] += M1[i * RB + j] * pv[i];
+              for (int j = 0; j < RB; ++j) qv[j] += M1[i * RB + j] * pv[i];
 #pragma unroll
-          for (int j = 0; j < RB; ++j) qv[j] = red_b(qv[j]);
-          flag_set(sync + kSyncP + kk, T);
+            for (int j = 0; j < RB; ++j) qv[j] = red_b(qv[j]);
+          } else {
+            load_chain_op<AQ>(M1, acl4, kk - 1, lane);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+              for (int j = 0; j < RB; ++j) qv[j] += M0[i * RB + j] * pv[i];
+            red_a_all<RB>(qv);
+          }
           if (first) {
             flag_wait(sync + kSyncG, N, T, sync, lane);
-#pragma unroll
-            for (int i = 0; i < RB; ++i) gv[i] = gf[kk * NXP + la * RB + i];
+            lds_load<RB>(gv, gf + ok + out_idx);
           }
 #pragma unroll
           for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
-        };
-        // even k >= 2: p'_k on a*RB + i, product summed over a, p_k on b*RB + j
-        auto even_hop = [&](int kk, bool first) {
-          if (lb == 0)
-#pragma unroll
-            for (int i = 0; i < RB; ++i) ppf[kk * NXP + la * RB + i] = pv[i];
-          float gv[RB], sv[RB], qv[RB];
-#pragma unroll
-          for (int i = 0; i < RB; ++i) {
-            sv[i] = sf[(kk - 1) * NXP + lb * RB + i];
-            gv[i] = first ? 0.f : gf[kk * NXP + lb * RB + i];
-          }
-          load_chain_op<AQ>(M1, acl4, kk - 1, lane);
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int j = 0; j < RB; ++j) qv[j] = 0.f;
-#pragma unroll
-          for (int i = 0; i < RB; ++i)
-#pragma unroll
-            for (int j = 0; j < RB; ++j) qv[j] += M0[i * RB + j] * pv[i];
-          red_a_all<RB>(qv);
           flag_set(sync + kSyncP + kk, T);
-          if (first) {
-            flag_wait(sync + kSyncG, N, T, sync, lane);
-#pragma unroll
-            for (int i = 0; i < RB; ++i) gv[i] = gf[kk * NXP + lb * RB + i];
-          }
-#pragma unroll
-          for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
         };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
         int kk = N - 1;
 #pragma unroll
         for (int i = 0; i < RB; ++i) pv[i] = pN[i] + sf[kk * NXP + pidx + i];
         bool first = true;
         if (kk & 1) {
           load_chain_op<AQ>(M1, acl4, kk, lane);
-          odd_hop(kk, true);
+          hop(kk, true, T_{});
           first = false;
           --kk;
         } else {
           load_chain_op<AQ>(M0, acl4, kk, lane);
         }
         for (; kk >= 2; kk -= 2) {
-          even_hop(kk, first);
+          hop(kk, first, F_{});
           first = false;
-          odd_hop(kk - 1, false);
+          hop(kk - 1, false, T_{});
         }
         if (first) flag_wait(sync + kSyncG, N, T, sync, lane);  // N == 1: no hop waited
         // k = 0: p'_0 only
-        if (lb == 0)
-#pragma unroll
-          for (int i = 0; i < RB; ++i) ppf[la * RB + i] = pv[i];
+        if (lb == 0) lds_store<RB>(ppf + la * RB, pv);
         flag_set(sync + kSyncP, T);
       }
       // forward chain, k = 0 .. N-1: xt_{k+1} = A_cl,k xt_k + e_k, stored and
@@ -1023,7 +1034,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
           const double xn = alpha * (double)xv[i] + oma * xdN[i];
-          pN[i] = (float)(-qxr[i] - sigma * xn);
+          pN[i] = (float)(-(qd[pidx + i] * xrd[N * NXP + pidx + i]) - sigma * xn);
         }
       }
     }
@@ -1117,16 +1128,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
     const int n_it = w < N ? iters : 0;  // wavefronts past the chain wavefront idle
     for (int it = 0; it < n_it; ++it) {
       const int T = it + 1;
-#pragma unroll
-      for (int i = 0; i < CB; ++i) {
-#pragma unroll
-        for (int j = 0; j < RB; ++j) {
-          opaque(Km[i][j]);
-          opaque(Bm[j][i]);
-        }
-#pragma unroll
-        for (int j = 0; j < CB; ++j) opaque(Hm[i][j]);
-      }
       // (A) linear terms of stage k: rt_k, g_k = qt_k + K_k' rt_k
       if (w < N) {
         // rt_k = C_k'(y_k - rho_k z_k) - sigma u_k - R ubar_k, from the row
@@ -1195,8 +1196,9 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         for (int i = 0; i < RB; ++i)
 #pragma unroll
           for (int j = 0; j < CB; ++j) sh[j] += Bm[i][j] * pv[i];
+        red_a_all<CB>(sh);
 #pragma unroll
-        for (int j = 0; j < CB; ++j) hv[j] = (float)(rtv[j] + (double)red_a(sh[j]));
+        for (int j = 0; j < CB; ++j) hv[j] = (float)(rtv[j] + (double)sh[j]);
 #pragma unroll
         for (int i = 0; i < CB; ++i) sd[i] = 0.f;
 #pragma unroll

@@ -966,45 +966,41 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       // before the last flag lets stage N-1 overwrite x_N
       {
         float xv[RB];  // xt_k of the coming hop, in its input layout
-        // even k: xt_k on b*RB + j, summed over b, xt_{k+1} on a*RB + i
-        auto even_hop = [&](int kk, int next) {
+        // Hop kk, prefetching stage `next` (none if negative).  ODD: xt_k on
+        // a*RB + j, summed over a, xt_{k+1} on b*RB + i; even: roles swap.
+        auto hop = [&](int kk, int next, auto odd_c) {
+          constexpr bool ODD = decltype(odd_c)::value;
+          const int out_idx = ODD ? lb * RB : la * RB;
+          int ok = kk * NXP;
+          opaque_s(ok);
           float ev[RB], sx[RB];
-#pragma unroll
-          for (int i = 0; i < RB; ++i) ev[i] = ef[kk * NXP + la * RB + i];
-          load_chain_op<AQ>(M1, acl4, next, lane);
-          __builtin_amdgcn_sched_barrier(0);
+          lds_load<RB>(ev, ef + ok + out_idx);
 #pragma unroll
           for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+          if constexpr (ODD) {
+            if (next >= 0) load_chain_op<AQ>(M0, acl4, next, lane);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int j = 0; j < RB; ++j)
+            for (int j = 0; j < RB; ++j)
 #pragma unroll
-            for (int i = 0; i < RB; ++i) sx[i] += M0[i * RB + j] * xv[j];
+              for (int i = 0; i < RB; ++i) sx[i] += M1[i * RB + j] * xv[j];
+            red_a_all<RB>(sx);
+          } else {
+            load_chain_op<AQ>(M1, acl4, next, lane);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int i = 0; i < RB; ++i) xv[i] = ev[i] + red_b(sx[i]);
-          if (lb == 0)
+            for (int j = 0; j < RB; ++j)
 #pragma unroll
-            for (int i = 0; i < RB; ++i) xtf[(kk + 1) * NXP + la * RB + i] = xv[i];
-        };
-        // odd k: xt_k on a*RB + j, summed over a, xt_{k+1} on b*RB + i
-        auto odd_hop = [&](int kk, int next) {
-          float ev[RB], sx[RB];
+              for (int i = 0; i < RB; ++i) sx[i] += M0[i * RB + j] * xv[j];
 #pragma unroll
-          for (int i = 0; i < RB; ++i) ev[i] = ef[kk * NXP + lb * RB + i];
-          if (next >= 0) load_chain_op<AQ>(M0, acl4, next, lane);
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int i = 0; i < RB; ++i) sx[i] = 0.f;
-#pragma unroll
-          for (int j = 0; j < RB; ++j)
-#pragma unroll
-            for (int i = 0; i < RB; ++i) sx[i] += M1[i * RB + j] * xv[j];
-          red_a_all<RB>(sx);
+            for (int i = 0; i < RB; ++i) sx[i] = red_b(sx[i]);
+          }
 #pragma unroll
           for (int i = 0; i < RB; ++i) xv[i] = ev[i] + sx[i];
-          if (la == 0)
-#pragma unroll
-            for (int i = 0; i < RB; ++i) xtf[(kk + 1) * NXP + lb * RB + i] = xv[i];
+          if ((ODD ? la : lb) == 0) lds_store<RB>(xtf + ok + NXP + out_idx, xv);
         };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
         // stage 0: A_cl,0 x_0 + e_0 once C_0 is out
         if (N > 1) load_chain_op<AQ>(M1, acl4, 1, lane);
         flag_wait(sync + kSyncE, N, T, sync, lane);  // e_k of the stage wavefronts
@@ -1012,21 +1008,23 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         double xdN[RB];
 #pragma unroll
         for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
+        {
+          float e0[RB];
+          lds_load<RB>(e0, ef + la * RB);
 #pragma unroll
-        for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + ef[la * RB + i];
-        if (lb == 0)
-#pragma unroll
-          for (int i = 0; i < RB; ++i) xtf[NXP + la * RB + i] = xv[i];
+          for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + e0[i];
+        }
+        if (lb == 0) lds_store<RB>(xtf + NXP + la * RB, xv);
         if (N > 1) flag_set(sync + kSyncX + 1, T);
         int kk = 1;
         for (; kk + 1 < N; kk += 2) {
-          odd_hop(kk, kk + 1);
+          hop(kk, kk + 1, T_{});
           flag_set(sync + kSyncX + kk + 1, T);
           // the last pair prefetches stage N-1 again rather than branch
-          even_hop(kk + 1, kk + 2 < N ? kk + 2 : N - 1);
+          hop(kk + 1, kk + 2 < N ? kk + 2 : N - 1, F_{});
           if (kk + 2 < N) flag_set(sync + kSyncX + kk + 2, T);
         }
-        if (kk < N) odd_hop(kk, -1);
+        if (kk < N) hop(kk, -1, T_{});
         // xt_N is in xv now, in the layout pidx; x_N (the previous iteration's
         // relaxation, which stage N-1 overwrites once xt_N is flagged) was read
         // at the start of the chain

@@ -572,15 +572,21 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
 
 // Progress flags between the chain wavefront and the stage wavefronts, in
 // LDS: each holds the number of the last iteration (from 1) whose data it
-// covers, is set with release order after that data is stored, and is polled
-// with acquire order before it is read.  Layout: g_k ready (A), p'_k ready
+// covers, is set after that data is stored (and after the setter's last read
+// of data it hands back), and is polled with acquire order before the data is
+// read.  Layout: g_k ready (A), p'_k ready
 // (backward chain), e_k ready (C), xt_k ready (forward chain), abort.
 constexpr int kSyncG = 0, kSyncP = kMaxStages, kSyncE = 2 * kMaxStages, kSyncX = 3 * kMaxStages;
 constexpr int kSyncAbort = 4 * kMaxStages + 1, kSyncInts = 4 * kMaxStages + 2;
 constexpr int kSpinLimit = 1 << 21;  // polls of one wait (about 0.1 s)
 
+// Setting a flag does not wait for the wavefront's earlier LDS stores to
+// complete: one wavefront's LDS operations are performed in issue order, so a
+// reader that sees the flag and then loads sees the data.  The compiler-level
+// barrier keeps the stores before the flag in issue order.
 __device__ inline void flag_set(int* f, int v) {
-  __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  asm volatile("" ::: "memory");
+  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 // Waits until every one of f[0 .. n) (n <= 64, one lane each) is >= v.  The
 // first polls spin (the handovers on the critical path are short); later ones

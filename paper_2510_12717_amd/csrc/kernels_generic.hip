@@ -654,7 +654,9 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
   const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
   __shared__ double red[256];
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lam = reinterpret_cast<double*>(smem_raw);  // (N+1)*nx
+  double* lam = reinterpret_cast<double*>(smem_raw);     // (N+1)*nx
+  T* As = reinterpret_cast<T*>(lam + (N + 1) * nx);      // nx x (nx+1)
+  T* Bs = As + nx * (nx + 1);                            // nx x (nu+1)
   if (st.status[a] != AGENT_OK && st.status[a] != AGENT_CONVERGED) {
     if (tid < 4) st.res[(int64_t)a * 4 + tid] = NAN;
     if (tid == 0) st.obj[a] = (T)NAN;
@@ -685,63 +687,69 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
     const double ee = (double)u[idx] - (uref ? (double)uref[idx] : 0.0);
     obj += 0.5 * (double)r[idx % nu] * ee * ee;
   }
+  double rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
+  for (int i = tid; i < nx; i += nt) ry = fmax(ry, fabs((double)x[i] - (double)x0[i]));
   // costates of the dynamics rows: lambda_N = Q(x_N - r_N),
   // lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}
   for (int i = tid; i < nx; i += nt)
     lam[N * nx + i] = (double)q[i] * ((double)x[N * nx + i] - (double)xr[N * nx + i]);
-  __syncthreads();
-  for (int k = N - 1; k >= 1; --k) {
-    for (int i0 = 0; i0 < nx; i0 += nq) {
-      const int i = i0 + qd;  // a quad shares i: whole quads are active or not
-      if (i < nx) {
-        const T* Ac = A + (int64_t)k * nx * nx + i;
+  // Stage by stage, k = N-1 .. 0: A_k and B_k are read from HBM once, with
+  // coalesced loads, into LDS (rows padded by one element), and every residual
+  // that involves them is formed from there: lambda_k, the dual residual of
+  // u_k (it needs lambda_{k+1}) and the dynamics residual of stage k.
+  for (int k = N - 1; k >= 0; --k) {
+    const T* Ag = A + (int64_t)k * nx * nx;
+    const T* Bg = B + (int64_t)k * nx * nu;
+    for (int e = tid; e < nx * nx; e += nt) As[(e / nx) * (nx + 1) + e % nx] = Ag[e];
+    for (int e = tid; e < nx * nu; e += nt) Bs[(e / nu) * (nu + 1) + e % nu] = Bg[e];
+    __syncthreads();
+    const double* lk1 = lam + (k + 1) * nx;
+    if (k >= 1) {
+      for (int i0 = 0; i0 < nx; i0 += nq) {
+        const int i = i0 + qd;  // a quad shares i: whole quads are active or not
+        if (i < nx) {
+          double acc = 0.0;
+          for (int t = sub; t < nx; t += 4) acc += (double)As[t * (nx + 1) + i] * lk1[t];
+          acc = quad_sum(acc);
+          if (sub == 0) lam[k * nx + i] = (double)q[i] * ((double)x[k * nx + i] - (double)xr[k * nx + i]) + acc;
+        }
+      }
+    }
+    // dual residual of the inputs: R(u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k
+    for (int j0 = 0; j0 < nu; j0 += nq) {
+      const int j = j0 + qd;
+      if (j < nu) {
+        const int o = k * nu + j;
         double acc = 0.0;
-        for (int t = sub; t < nx; t += 4) acc += (double)Ac[t * nx] * lam[(k + 1) * nx + t];
+        for (int t = sub; t < nx; t += 4) acc += (double)Bs[t * (nu + 1) + j] * lk1[t];
         acc = quad_sum(acc);
-        if (sub == 0) lam[k * nx + i] = (double)q[i] * ((double)x[k * nx + i] - (double)xr[k * nx + i]) + acc;
+        if (sub == 0) {
+          acc += (double)r[j] * ((double)u[o] - (uref ? (double)uref[o] : 0.0));
+          const T* yk = y + k * m;
+          double v = (double)yk[j];
+          if (j >= d.n_tau) {
+            const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
+            const T* yp = yk + nu + 4 * f;
+            if (cc == 0) v += (double)yp[0] - (double)yp[1];
+            if (cc == 1) v += (double)yp[2] - (double)yp[3];
+            if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
+          }
+          rd = fmax(rd, fabs(acc + v));
+        }
+      }
+    }
+    // dynamics residual x_{k+1} - A_k x_k - B_k u_k - c_k
+    for (int i0 = 0; i0 < nx; i0 += nq) {
+      const int i = i0 + qd;
+      if (i < nx) {
+        double acc = 0.0;
+        for (int t = sub; t < nx; t += 4) acc += (double)As[i * (nx + 1) + t] * (double)x[k * nx + t];
+        for (int t = sub; t < nu; t += 4) acc += (double)Bs[i * (nu + 1) + t] * (double)u[k * nu + t];
+        acc = quad_sum(acc);
+        if (sub == 0) ry = fmax(ry, fabs((double)x[(k + 1) * nx + i] - (double)c[k * nx + i] - acc));
       }
     }
     __syncthreads();
-  }
-  double rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
-  for (int i = tid; i < nx; i += nt) ry = fmax(ry, fabs((double)x[i] - (double)x0[i]));
-  // dual residual of the inputs: R(u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k
-  for (int o0 = 0; o0 < N * nu; o0 += nq) {
-    const int o = o0 + qd;
-    if (o < N * nu) {
-      const int k = o / nu, j = o % nu;
-      const T* Bc = B + (int64_t)k * nx * nu + j;
-      double acc = 0.0;
-      for (int t = sub; t < nx; t += 4) acc += (double)Bc[t * nu] * lam[(k + 1) * nx + t];
-      acc = quad_sum(acc);
-      if (sub == 0) {
-        acc += (double)r[j] * ((double)u[o] - (uref ? (double)uref[o] : 0.0));
-        const T* yk = y + k * m;
-        double v = (double)yk[j];
-        if (j >= d.n_tau) {
-          const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
-          const T* yp = yk + nu + 4 * f;
-          if (cc == 0) v += (double)yp[0] - (double)yp[1];
-          if (cc == 1) v += (double)yp[2] - (double)yp[3];
-          if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
-        }
-        rd = fmax(rd, fabs(acc + v));
-      }
-    }
-  }
-  // dynamics residual x_{k+1} - A_k x_k - B_k u_k - c_k
-  for (int o0 = 0; o0 < N * nx; o0 += nq) {
-    const int o = o0 + qd;
-    if (o < N * nx) {
-      const int k = o / nx, i = o % nx;
-      const T* Ar = A + (int64_t)k * nx * nx + i * nx;
-      const T* Br = B + (int64_t)k * nx * nu + i * nu;
-      double acc = 0.0;
-      for (int t = sub; t < nx; t += 4) acc += (double)Ar[t] * (double)x[k * nx + t];
-      for (int t = sub; t < nu; t += 4) acc += (double)Br[t] * (double)u[k * nu + t];
-      acc = quad_sum(acc);
-      if (sub == 0) ry = fmax(ry, fabs((double)x[(k + 1) * nx + i] - (double)c[o] - acc));
-    }
   }
   for (int idx = tid; idx < N * m; idx += nt) {
     const int k = idx / m, i = idx % m;

@@ -231,7 +231,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->nWS = ows;
   p->lds_factor = generic_factor_lds(p->maxnx, p->maxnu, p->esz);
   p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz);
-  p->lds_res = sizeof(double) * (size_t)(p->maxN + 1) * p->maxnx;
+  p->lds_res = generic_residual_lds(p->maxN, p->maxnx, p->maxnu, p->esz);
 
   // Launch groups.  FP32 agents whose shape has a register-resident
   // instantiation are grouped per (shape class, horizon) and take those

@@ -357,7 +357,7 @@ static mpc_status submit_one(mpc_server_s* s, int64_t ctrl, const mpc_shape* sha
   // the generic kernels' LDS limits grow to what this shape needs
   MPC_HIP_TRY(generic_set_lds_limits(generic_factor_lds(sh.nx, sh.nu, s->esz),
                                      generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz),
-                                     sizeof(double) * (size_t)(sh.N + 1) * sh.nx));
+                                     generic_residual_lds(sh.N, sh.nx, sh.nu, s->esz)));
   const int64_t need = to_units(state_elems(sh) * (int64_t)s->esz) + to_units(ws_bytes(s, sh));
   if (need > s->arena_bytes / kUnit)
     return api_fail(MPC_ERR_OUT_OF_MEMORY, "one request of this shape exceeds the HBM budget");
@@ -568,13 +568,14 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
     MPC_HIP_TRY(hipStreamWaitEvent(sl.stream, sl.ev_join[i], 0));
   }
   st = sl.stream;
-  int maxN = 1, maxnx = 1;
+  int maxN = 1, maxnx = 1, maxnu = 1;
   for (const G& g : gl) {
     maxN = std::max(maxN, g.N);
     maxnx = std::max(maxnx, g.nx);
+    maxnu = std::max(maxnu, g.nu);
   }
   MPC_HIP_TRY(launch_residual<T>(sl.d_desc, nullptr, n, in, sc, state,
-                                 sizeof(double) * (size_t)(maxN + 1) * maxnx, st));
+                                 generic_residual_lds(maxN, maxnx, maxnu, s->esz), st));
   hipLaunchKernelGGL(k_gather_u0<T>, dim3(n), dim3(64), 0, st, sl.d_desc, n, (const T*)s->arena_base,
                      sl.d_status, sl.d_u0, sl.d_st_out);
   MPC_HIP_TRY(hipGetLastError());

@@ -108,7 +108,7 @@ typedef struct {
   int32_t device;           /* HIP device ordinal                                      */
   int32_t kernel;           /* 0 = auto, 1 = generic kernels only, 2 = register-      */
                             /* resident kernels only (UNSUPPORTED_SHAPE if an agent has */
-                            /* no instantiation: FP32, nx/nu 48/30 or 36/24, N <= 11)   */
+                            /* no instantiation: FP32, nx/nu 48/30 or 36/24, N <= 20)   */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */

@@ -1,6 +1,7 @@
 // Register-resident FP32 solve: an FP64 MFMA Riccati-factor kernel followed
 // by an iteration kernel that keeps every stage's operators in the VGPRs of
-// one wavefront per stage.
+// one wavefront per stage (horizons up to 11), or of one wavefront per two
+// stages with the closed-loop operators streamed through LDS (12 to 20).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,14 +13,14 @@ namespace mpc {
 // True if the register-resident kernels have an instantiation for this shape.
 bool fused_supported(int N, int nx, int nu, int n_feet);
 // Horizon bucket of the register-resident launch groups: horizons up to 6 share
-// a launch of at most 6 wavefronts per agent (two agents fit one compute
-// unit), longer ones a launch of up to 12.
-inline int fused_bucket(int N) { return N <= 6 ? 0 : 1; }
+// a launch of at most 7 wavefronts per agent (two agents fit one compute
+// unit), 7 to 11 a launch of up to 12, and 12 to 20 the streaming kernel's.
+inline int fused_bucket(int N) { return N <= 6 ? 0 : N <= 11 ? 1 : 2; }
 // Threads per workgroup and dynamic LDS bytes of the iteration kernel for a
 // launch whose longest horizon is N.
 void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds);
 // Floats of operator workspace one agent of this shape class needs.
-size_t fused_agent_floats(int nx, int nu);
+size_t fused_agent_floats(int N, int nx, int nu);
 // Raise the dynamic-LDS limits of every register-resident kernel (once per device).
 hipError_t fused_set_limits();
 // Launch for the n_launch agents list[0..n_launch) (all of one shape class,

@@ -213,7 +213,7 @@ constexpr int riccati_lds_bytes() {
          4 * S::NXT * S::LU + 16;
 }
 
-// RES: operators go to the register-resident layout at fws + ofw (N < 12).
+// RES: operators go to the register-resident layout at fws + ofw.
 // Otherwise (mixed precision, or FP64 products for the generic iteration
 // kernel at any horizon) they go to the generic per-agent layout at fws + ows:
 // K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx], then l, h,
@@ -266,7 +266,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   constexpr bool kResident = RES;
   static_assert(!RES || PREC == kProdF64, "the register-resident path takes FP64 products");
   float* ops = fws + (kResident ? d.ofw : d.ows);
-  float* sk_out = kResident ? ops + (int64_t)kMaxStages * SLOTS * 64  // [stage][NXP]
+  float* sk_out = kResident ? ops + (int64_t)N * SLOTS * 64  // [stage][NXP]
                             : ops + (int64_t)N * (NU * NX + NX * NX + NU * NU);
   float* gK = ops;
   float* gAcl = gK + (int64_t)N * NU * NX;
@@ -594,15 +594,15 @@ __device__ inline void flag_set(int* f, int v) {
 // the abort flag, and every wait returns at once while that flag is up (it is
 // read every 64 polls), so the workgroup always drains (the agent then reports
 // non-finite).
-__device__ inline void flag_wait(int* f, int n, int v, int* sync, int lane) {
+__device__ inline void flag_wait(int* f, int n, int v, int* abort, int lane) {
   for (int t = 0; t < kSpinLimit; ++t) {
     const int x = lane < n ? __hip_atomic_load(f + lane, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) : v;
     if (__all(x >= v)) return;
-    if ((t & 63) == 63 && __hip_atomic_load(sync + kSyncAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+    if ((t & 63) == 63 && __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
       return;
     if (t >= 32) __builtin_amdgcn_s_sleep(1);
   }
-  __hip_atomic_store(sync + kSyncAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 struct IterLds {
@@ -798,7 +798,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       dst[i] = src[(int64_t)kk * SLOTS * 16 + (i - kk * AQ * 64)];
     }
   }
-  const float* sk = fws + d.ofw + (int64_t)kMaxStages * SLOTS * 64;
+  const float* sk = fws + d.ofw + (int64_t)N * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
   for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
   for (int i = tid; i < NX; i += nt) {
@@ -936,7 +936,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
             red_a_all<RB>(qv);
           }
           if (first) {
-            flag_wait(sync + kSyncG, N, T, sync, lane);
+            flag_wait(sync + kSyncG, N, T, sync + kSyncAbort, lane);
             lds_load<RB>(gv, gf + ok + out_idx);
           }
 #pragma unroll
@@ -962,7 +962,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
           first = false;
           hop(kk - 1, false, T_{});
         }
-        if (first) flag_wait(sync + kSyncG, N, T, sync, lane);  // N == 1: no hop waited
+        if (first) flag_wait(sync + kSyncG, N, T, sync + kSyncAbort, lane);  // N == 1: no hop waited
         // k = 0: p'_0 only
         if (lb == 0) lds_store<RB>(ppf + la * RB, pv);
         flag_set(sync + kSyncP, T);
@@ -1009,7 +1009,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         using F_ = std::false_type;
         // stage 0: A_cl,0 x_0 + e_0 once C_0 is out
         if (N > 1) load_chain_op<AQ>(M1, acl4, 1, lane);
-        flag_wait(sync + kSyncE, N, T, sync, lane);  // e_k of the stage wavefronts
+        flag_wait(sync + kSyncE, N, T, sync + kSyncAbort, lane);  // e_k of the stage wavefronts
         // x_N as relaxed in the previous iteration (stage N-1 wrote it before its C)
         double xdN[RB];
 #pragma unroll
@@ -1094,7 +1094,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 
     // x_N <- alpha xt_N + (1 - alpha) x_N once the forward chain of iteration t is out
     auto relax_xN = [&](int t) {
-      flag_wait(sync + kSyncX + N, 1, t, sync, lane);
+      flag_wait(sync + kSyncX + N, 1, t, sync + kSyncAbort, lane);
       for (int i = lane; i < NX; i += 64)
         xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
     };
@@ -1184,7 +1184,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       // wavefront has taken its own copy for p_N before flagging xt_N.
       if (k == N - 1 && it >= 1) relax_xN(T - 1);
       // (B) backward chain on the chain wavefront; C_k starts once p'_k is out
-      flag_wait(sync + kSyncP + k, 1, T, sync, lane);
+      flag_wait(sync + kSyncP + k, 1, T, sync + kSyncAbort, lane);
       // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
       if (w < N) {
         float pv[RB], hv[CB], sh[CB], sd[CB];
@@ -1235,7 +1235,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       }
       flag_set(sync + kSyncE + k, T);
       // (D) forward chain on the chain wavefront; E_k starts once xt_k is out
-      if (k >= 1) flag_wait(sync + kSyncX + k, 1, T, sync, lane);
+      if (k >= 1) flag_wait(sync + kSyncX + k, 1, T, sync + kSyncAbort, lane);
       // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
       if (w < N) {
         float xv[RB], su[CB];
@@ -1305,13 +1305,695 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   if (tid == 0 && flag[0]) st.status[agent] = AGENT_NONFINITE;
 }
 
+// ------------------------------------------------------------------------------------
+// ADMM iterations for longer horizons (kMaxStages <= N <= kMaxStream): the same
+// split into stage wavefronts and one chain wavefront, with A_cl streamed from
+// HBM through an LDS ring by a loader wavefront
+// ------------------------------------------------------------------------------------
+
+constexpr int kMaxStream = 20;  // longest horizon of the streaming iteration kernel
+constexpr int kRing = 4;        // A_cl slots of its LDS ring
+// flags: g_k, p'_k, e_k, xt_k ready (as kSync*), the ring slots' element numbers,
+// the chain's consumed-element count, abort
+constexpr int kStG = 0, kStP = kMaxStream + 1, kStE = 2 * (kMaxStream + 1), kStX = 3 * (kMaxStream + 1);
+constexpr int kStRing = 4 * (kMaxStream + 1), kStUsed = kStRing + kRing, kStAbort = kStUsed + 1;
+constexpr int kStInts = kStAbort + 1;
+
+struct StreamLds {
+  int ring, xtf, ppf, gf, ef, sf, cf;                                     // float
+  int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd;  // double
+  int flag, sync, total;
+};
+
+template <int NX, int NU>
+__host__ __device__ inline StreamLds stream_lds_layout(int N, int M) {
+  using S = FS<NX, NU>;
+  StreamLds L{};
+  int o = 0;
+  auto take = [&](int bytes) {
+    const int r = o;
+    o += (bytes + 15) & ~15;
+    return r;
+  };
+  L.ring = take(4 * kRing * S::AQ * 256);
+  L.xtf = take(4 * (N + 1) * S::NXP);
+  L.ppf = take(4 * N * S::NXP);
+  L.gf = take(4 * N * S::NXP);
+  L.ef = take(4 * N * S::NXP);
+  L.sf = take(4 * N * S::NXP);
+  L.cf = take(4 * N * S::NXP);
+  L.xd = take(8 * (N + 1) * S::NXP);
+  L.ud = take(8 * N * S::NUP);
+  L.zd = take(8 * N * M);
+  L.yd = take(8 * N * M);
+  L.lod = take(8 * N * M);
+  L.hid = take(8 * N * M);
+  L.rhod = take(8 * N * M);
+  L.irhod = take(8 * N * M);
+  L.wvd = take(8 * N * M);
+  L.rtd = take(8 * N * S::NUP);
+  L.dd = take(8 * N * S::NUP);
+  L.utd = take(8 * N * S::NUP);
+  L.qd = take(8 * S::NXP);
+  L.xrd = take(8 * (N + 1) * S::NXP);
+  L.qtd = take(8 * N * S::NXP);
+  L.flag = take(16);
+  L.sync = take(4 * kStInts);
+  L.total = o;
+  return L;
+}
+
+// The chain wavefront's operator sequence: stages 0 (for the constant
+// A_cl,0 x_0), N-1 and N-2, then every iteration the backward chain's
+// N-3 .. 1 and the forward chain's 3 .. N-1.  The two operators a chain ends
+// on are the two the other chain starts with, still in registers, and A_cl,0
+// is not needed again.  N >= 4.
+__host__ __device__ inline int stream_stage(int g, int N) {
+  if (g < 3) return g == 0 ? 0 : N - g;
+  const int r = (g - 3) % (2 * N - 6);
+  return r < N - 3 ? N - 3 - r : r - N + 6;
+}
+__host__ __device__ inline int stream_elements(int N, int iters) { return 3 + iters * (2 * N - 6); }
+
+// Stage wavefront j owns stages j and j + SW (SW = ceil(N/2)) with K, B in
+// registers and H^{-1} read from HBM before each C; the chain wavefront (SW)
+// is the register-resident kernel's, taking A_cl,k from the ring; the loader
+// wavefront (SW + 1) keeps three ring elements in flight.
+template <int NX, int NU>
+__global__ void __launch_bounds__(64 * kMaxStages)
+k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+              Inputs<float> in, SolverConsts sc, int iters, int warm,
+              const float* __restrict__ fws, State<float> st) {
+  using S = FS<NX, NU>;
+  constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS, AQ = S::AQ;
+  if ((int)blockIdx.x >= n_launch) return;
+  const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const AgentDesc d = desc[agent];
+  const int N = d.N, M = d.m;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int w = tid >> 6, lane = tid & 63, la = lane >> 3, lb = lane & 7;
+  float* X = st.x + d.ox;
+  float* U = st.u + d.ou;
+  float* Z = st.z + d.oz;
+  float* Y = st.y + d.oy;
+  if (st.status[agent] != AGENT_OK) {
+    for (int i = tid; i < (N + 1) * d.nx; i += nt) X[i] = NAN;
+    for (int i = tid; i < N * d.nu; i += nt) U[i] = NAN;
+    for (int i = tid; i < N * M; i += nt) {
+      Z[i] = NAN;
+      Y[i] = NAN;
+    }
+    return;
+  }
+  const StreamLds L = stream_lds_layout<NX, NU>(N, M);
+  extern __shared__ __align__(16) unsigned char sm[];
+  float4* ring4 = reinterpret_cast<float4*>(sm + L.ring);
+  float* xtf = reinterpret_cast<float*>(sm + L.xtf);
+  float* ppf = reinterpret_cast<float*>(sm + L.ppf);
+  float* gf = reinterpret_cast<float*>(sm + L.gf);
+  float* ef = reinterpret_cast<float*>(sm + L.ef);
+  float* sf = reinterpret_cast<float*>(sm + L.sf);
+  float* cf = reinterpret_cast<float*>(sm + L.cf);
+  double* xd = reinterpret_cast<double*>(sm + L.xd);
+  double* ud = reinterpret_cast<double*>(sm + L.ud);
+  double* zd = reinterpret_cast<double*>(sm + L.zd);
+  double* yd = reinterpret_cast<double*>(sm + L.yd);
+  double* lod = reinterpret_cast<double*>(sm + L.lod);
+  double* hid = reinterpret_cast<double*>(sm + L.hid);
+  double* rhod = reinterpret_cast<double*>(sm + L.rhod);
+  double* irhod = reinterpret_cast<double*>(sm + L.irhod);
+  double* wvd = reinterpret_cast<double*>(sm + L.wvd);
+  double* rtd = reinterpret_cast<double*>(sm + L.rtd);
+  double* dd = reinterpret_cast<double*>(sm + L.dd);
+  double* utd = reinterpret_cast<double*>(sm + L.utd);
+  double* qd = reinterpret_cast<double*>(sm + L.qd);
+  double* xrd = reinterpret_cast<double*>(sm + L.xrd);
+  double* qtd = reinterpret_cast<double*>(sm + L.qtd);
+  int* flag = reinterpret_cast<int*>(sm + L.flag);
+  int* sync = reinterpret_cast<int*>(sm + L.sync);
+  int* abortp = sync + kStAbort;
+
+  const float* A = in.A + d.oA;
+  const float* B = in.B + d.oB;
+  const float* c = in.c + d.oc;
+  const float* q = in.q + d.oq;
+  const float* r = in.r + d.orr;
+  const float* xr = in.xr + d.oxr;
+  const float* x0 = in.x0 + d.ox0;
+  const float* tau = in.tau + d.otau;
+  const uint8_t* stance = in.st + d.ost;
+  const float* uref = in.uref ? in.uref + d.our : nullptr;
+  const double mu = (double)in.mu[d.omu];
+  const float* opg = fws + d.ofw;  // this agent's operators in HBM
+
+  // per-agent vectors into LDS (padding zero)
+  for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
+  __syncthreads();
+  const float* sk = opg + (int64_t)N * SLOTS * 64;
+  for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
+  for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
+  for (int i = tid; i < NX; i += nt) {
+    qd[i] = (double)q[i];
+    xd[i] = (double)x0[i];
+    xtf[i] = x0[i];
+  }
+  for (int i = tid; i < (N + 1) * NX; i += nt) xrd[(i / NX) * NXP + i % NX] = (double)xr[i];
+  for (int i = tid; i < N * M; i += nt) {
+    const int k = i / M, j = i % M;
+    double lo, hi, rr;
+    row_bounds<double, float>(d, j, stance + k * d.n_feet, tau, sc, lo, hi, rr);
+    lod[i] = lo;
+    hid[i] = hi;
+    rhod[i] = rr;
+    irhod[i] = 1.0 / rr;
+  }
+  const bool wm = agent_warm(warm, d);
+  for (int i = tid; i < N * NU; i += nt) ud[(i / NU) * NUP + i % NU] = wm ? (double)U[i] : 0.0;
+  for (int i = tid; i < N * M; i += nt) {
+    zd[i] = wm ? (double)Z[i] : 0.0;
+    yd[i] = wm ? (double)Y[i] : 0.0;
+  }
+  __syncthreads();
+  // x^0: rollout of the exact dynamics under u^0 over the whole workgroup; quad
+  // qq owns state row qq, its lanes every fourth column; the next stage's rows
+  // are loaded while the current one is summed
+  {
+    constexpr int TA = (NX + 3) / 4, TB = (NU + 3) / 4;
+    const int qq = tid >> 2, sub = tid & 3;
+    float an[TA], bn[TB];
+    auto load_rows = [&](int kk) __attribute__((always_inline)) {
+      const float* Ar = A + ((int64_t)kk * NX + qq) * NX;
+      const float* Br = B + ((int64_t)kk * NX + qq) * NU;
+#pragma unroll
+      for (int t = 0; t < TA; ++t) an[t] = (qq < NX && sub + 4 * t < NX) ? Ar[sub + 4 * t] : 0.f;
+#pragma unroll
+      for (int t = 0; t < TB; ++t) bn[t] = (qq < NX && sub + 4 * t < NU) ? Br[sub + 4 * t] : 0.f;
+    };
+    load_rows(0);
+    for (int kk = 0; kk < N; ++kk) {
+      float ac[TA], bc[TB];
+#pragma unroll
+      for (int t = 0; t < TA; ++t) ac[t] = an[t];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) bc[t] = bn[t];
+      if (kk + 1 < N) load_rows(kk + 1);
+      if (qq < NX) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < TA; ++t)
+          if (sub + 4 * t < NX) acc += (double)ac[t] * xd[kk * NXP + sub + 4 * t];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+          if (sub + 4 * t < NU) acc += (double)bc[t] * ud[kk * NUP + sub + 4 * t];
+        acc = quad_sum(acc);
+        if (sub == 0) xd[(kk + 1) * NXP + qq] = (double)c[kk * NX + qq] + acc;
+      }
+      __syncthreads();
+    }
+  }
+
+  const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
+  const int SW = (N + 1) / 2;  // stage wavefronts
+
+  if (w == SW) {
+    // ---------------- chain wavefront ----------------
+    __builtin_amdgcn_s_setprio(2);
+    float M0[4 * AQ], M1[4 * AQ];  // even / odd stage operators
+    int e = 0;                     // next element of the operator sequence
+    int el0 = 0, el1 = 0;          // elements held in M0 / M1
+    int seen0 = 0, seen1 = 0;      // their slot's flag as read with them
+    // Element e from the ring, read speculatively: the slot's flag first, then
+    // the operator (this wavefront's LDS reads complete in issue order, so the
+    // operator is the published one whenever the flag already was).
+    auto fetch = [&](float (&Mx)[4 * AQ], int& elx, int& seenx) __attribute__((always_inline)) {
+      const int slot = e & (kRing - 1);
+      seenx = __hip_atomic_load(sync + kStRing + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      asm volatile("" ::: "memory");
+      load_chain_op<AQ>(Mx, ring4, slot, lane);
+      elx = e++;
+    };
+    // Before an operator's first use: reread it if its flag was not yet set,
+    // then hand its slot back to the loader.
+    auto settle = [&](float (&Mx)[4 * AQ], int elx, int seenx) __attribute__((always_inline)) {
+      if (!__all(seenx >= elx + 1)) {
+        flag_wait(sync + kStRing + (elx & (kRing - 1)), 1, elx + 1, abortp, lane);
+        load_chain_op<AQ>(Mx, ring4, elx & (kRing - 1), lane);
+      }
+      flag_set(sync + kStUsed, elx + 1);
+    };
+    const int pidx = ((N - 1) & 1) ? lb * RB : la * RB;
+    float pN[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      pN[i] = (float)(-qd[pidx + i] * xrd[N * NXP + pidx + i] - sigma * xd[N * NXP + pidx + i]);
+    float ax0[RB];
+    {
+      fetch(M0, el0, seen0);  // stage 0
+      settle(M0, el0, seen0);
+      float x0v[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) x0v[j] = xtf[lb * RB + j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        ax0[i] = 0.f;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) ax0[i] += M0[i * RB + j] * x0v[j];
+        ax0[i] = red_b(ax0[i]);
+      }
+    }
+    // stages N-1 and N-2, the backward chain's first operators
+    for (int kk = N - 1; kk >= N - 2; --kk) {
+      if (kk & 1) {
+        fetch(M1, el1, seen1);
+        settle(M1, el1, seen1);
+      } else {
+        fetch(M0, el0, seen0);
+        settle(M0, el0, seen0);
+      }
+    }
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    for (int it = 0; it < iters; ++it) {
+      const int T = it + 1;
+      {
+        float pv[RB];
+        // hop kk of the backward chain: its operator is settled here unless it
+        // is stage N-1 or N-2 (already in registers); fetches stage kk-1 for
+        // 2 <= kk <= N-2
+        auto hop = [&](int kk, bool first, auto odd_c) __attribute__((always_inline)) {
+          constexpr bool ODD = decltype(odd_c)::value;
+          const int in_idx = ODD ? lb * RB : la * RB, out_idx = ODD ? la * RB : lb * RB;
+          if (kk <= N - 3) {
+            if constexpr (ODD) settle(M1, el1, seen1);
+            else settle(M0, el0, seen0);
+          }
+          int ok = kk * NXP, om = (kk - 1) * NXP;
+          opaque_s(ok);
+          opaque_s(om);
+          if ((ODD ? la : lb) == 0) lds_store<RB>(ppf + ok + in_idx, pv);
+          float gv[RB], sv[RB], qv[RB];
+          lds_load<RB>(sv, sf + om + out_idx);
+          lds_load<RB>(gv, gf + ok + out_idx);
+#pragma unroll
+          for (int j = 0; j < RB; ++j) qv[j] = 0.f;
+          if constexpr (ODD) {
+            if (kk >= 2 && kk <= N - 2) fetch(M0, el0, seen0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+              for (int j = 0; j < RB; ++j) qv[j] += M1[i * RB + j] * pv[i];
+#pragma unroll
+            for (int j = 0; j < RB; ++j) qv[j] = red_b(qv[j]);
+          } else {
+            if (kk <= N - 2) fetch(M1, el1, seen1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+              for (int j = 0; j < RB; ++j) qv[j] += M0[i * RB + j] * pv[i];
+            red_a_all<RB>(qv);
+          }
+          if (first) {
+            flag_wait(sync + kStG, N, T, abortp, lane);
+            lds_load<RB>(gv, gf + ok + out_idx);
+          }
+#pragma unroll
+          for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
+          flag_set(sync + kStP + kk, T);
+        };
+        int kk = N - 1;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) pv[i] = pN[i] + sf[kk * NXP + pidx + i];
+        bool first = true;
+        if (kk & 1) {
+          hop(kk, true, T_{});
+          first = false;
+          --kk;
+        }
+        for (; kk >= 2; kk -= 2) {
+          hop(kk, first, F_{});
+          first = false;
+          hop(kk - 1, false, T_{});
+        }
+        if (lb == 0) lds_store<RB>(ppf + la * RB, pv);
+        flag_set(sync + kStP, T);
+      }
+      {
+        float xv[RB];
+        // hop kk of the forward chain: its operator is settled here unless it
+        // is stage 1 or 2 (the backward chain's last two); fetches stage kk+1
+        // for 2 <= kk <= N-2
+        auto hop = [&](int kk, auto odd_c) __attribute__((always_inline)) {
+          constexpr bool ODD = decltype(odd_c)::value;
+          const int out_idx = ODD ? lb * RB : la * RB;
+          if (kk >= 3) {
+            if constexpr (ODD) settle(M1, el1, seen1);
+            else settle(M0, el0, seen0);
+          }
+          int ok = kk * NXP;
+          opaque_s(ok);
+          float ev[RB], sx[RB];
+          lds_load<RB>(ev, ef + ok + out_idx);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+          if constexpr (ODD) {
+            if (kk >= 2 && kk + 1 < N) fetch(M0, el0, seen0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+              for (int i = 0; i < RB; ++i) sx[i] += M1[i * RB + j] * xv[j];
+            red_a_all<RB>(sx);
+          } else {
+            if (kk >= 2 && kk + 1 < N) fetch(M1, el1, seen1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+#pragma unroll
+              for (int i = 0; i < RB; ++i) sx[i] += M0[i * RB + j] * xv[j];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) sx[i] = red_b(sx[i]);
+          }
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xv[i] = ev[i] + sx[i];
+          if ((ODD ? la : lb) == 0) lds_store<RB>(xtf + ok + NXP + out_idx, xv);
+        };
+        flag_wait(sync + kStE, N, T, abortp, lane);
+        double xdN[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
+        {
+          float e0[RB];
+          lds_load<RB>(e0, ef + la * RB);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + e0[i];
+        }
+        if (lb == 0) lds_store<RB>(xtf + NXP + la * RB, xv);
+        flag_set(sync + kStX + 1, T);
+        int kk = 1;
+        for (; kk + 1 < N; kk += 2) {
+          hop(kk, T_{});
+          flag_set(sync + kStX + kk + 1, T);
+          hop(kk + 1, F_{});
+          if (kk + 2 < N) flag_set(sync + kStX + kk + 2, T);
+        }
+        if (kk < N) hop(kk, T_{});
+        flag_set(sync + kStX + N, T);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const double xn = alpha * (double)xv[i] + oma * xdN[i];
+          pN[i] = (float)(-(qd[pidx + i] * xrd[N * NXP + pidx + i]) - sigma * xn);
+        }
+      }
+    }
+  } else if (w == SW + 1) {
+    // ---------------- loader wavefront ----------------
+    // element g: global loads into a register set, then (once the chain has
+    // handed back element g - kRing) into ring slot g % kRing and flagged;
+    // three elements are in flight
+    const int total = stream_elements(N, iters);
+    const f4* src4 = reinterpret_cast<const f4*>(opg) + lane;
+    f4 R[3][AQ];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const f4* src = src4 + (int64_t)stream_stage(j, N) * SLOTS * 16;
+#pragma unroll
+      for (int qv = 0; qv < AQ; ++qv) R[j][qv] = src[qv * 64];
+    }
+    for (int g0 = 0; g0 < total; g0 += 3) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int g = g0 + j;
+        if (g < total) {
+          if (g >= kRing) flag_wait(sync + kStUsed, 1, g - kRing + 1, abortp, lane);
+          f4* dst = reinterpret_cast<f4*>(ring4) + (g & (kRing - 1)) * AQ * 64 + lane;
+#pragma unroll
+          for (int qv = 0; qv < AQ; ++qv) dst[qv * 64] = R[j][qv];
+          flag_set(sync + kStRing + (g & (kRing - 1)), g + 1);
+          if (g + 3 < total) {
+            const f4* src = src4 + (int64_t)stream_stage(g + 3, N) * SLOTS * 16;
+#pragma unroll
+            for (int qv = 0; qv < AQ; ++qv) R[j][qv] = src[qv * 64];
+          }
+        }
+      }
+    }
+  } else if (w < SW) {
+    // ---------------- stage wavefront: stages w and w + SW ----------------
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int kS[2] = {wu, wu + SW};
+    const bool hasH = kS[1] < N;
+    float Km[2][CB][RB], Bm[2][RB][CB], Hm[CB][CB];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const bool own = kS[s2] < N;
+      const float* src = opg + ((int64_t)(own ? kS[s2] : 0) * SLOTS + 4 * AQ) * 64 + lane;
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) Km[s2][i][j] = own ? src[(i * RB + j) * 64] : 0.f;
+      src += CB * RB * 64;
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) Bm[s2][i][j] = own ? src[(i * CB + j) * 64] : 0.f;
+    }
+    auto load_H = [&](int k) __attribute__((always_inline)) {
+      const float* src = opg + ((int64_t)k * SLOTS + 4 * AQ + 2 * CB * RB) * 64 + lane;
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) Hm[i][j] = src[(i * CB + j) * 64];
+    };
+    auto relax_xN = [&](int t) __attribute__((always_inline)) {
+      flag_wait(sync + kStX + N, 1, t, abortp, lane);
+      for (int i = lane; i < NX; i += 64)
+        xd[N * NXP + i] = alpha * (double)xtf[N * NXP + i] + oma * xd[N * NXP + i];
+    };
+    int zc_i1 = 0, zc_i2 = 0, rt_b0 = 0, rt_cc = -1;
+    double zc_s1 = 0.0, zc_s2 = 0.0;
+    if (lane < M) {
+      if (lane < NU) {
+        zc_i1 = zc_i2 = lane;
+        zc_s1 = 1.0;
+      } else {
+        const int f = (lane - NU) >> 2, pp = (lane - NU) & 3, b = d.n_tau + f * d.foot_dim;
+        zc_i1 = pp < 2 ? b : b + 1;
+        zc_s1 = (pp & 1) ? -1.0 : 1.0;
+        zc_i2 = b + 2;
+        zc_s2 = -mu;
+      }
+    }
+    if (lane < NU && lane >= d.n_tau) {
+      rt_b0 = NU + 4 * ((lane - d.n_tau) / d.foot_dim);
+      rt_cc = (lane - d.n_tau) % d.foot_dim;
+    }
+    double u_own[2] = {0.0, 0.0}, ru_own[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int k = kS[s2];
+      if (k < N) {
+        if (lane < NU) {
+          u_own[s2] = ud[k * NUP + lane];
+          if (uref) ru_own[s2] = (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
+        }
+        if (lane < M) wvd[k * M + lane] = yd[k * M + lane] - rhod[k * M + lane] * zd[k * M + lane];
+        if (k >= 1 && lane < NX) qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xd[k * NXP + lane];
+      }
+    }
+    wave_sync();
+    // (A) of stage kS[s]: rt_k and g_k = qt_k + K_k' rt_k, flagged for iteration t
+    auto phaseA = [&](auto s_c, int t) __attribute__((always_inline)) {
+      constexpr int s2 = decltype(s_c)::value;
+      int k = kS[s2];
+      opaque_s(k);  // per-stage addresses formed here, not kept live across the loop
+      if (lane < NUP) {
+        double v = 0.0;
+        if (lane < NU) {
+          const double* wk = wvd + k * M;
+          const double w0 = wk[rt_b0], w1 = wk[rt_b0 + 1], w2 = wk[rt_b0 + 2], w3 = wk[rt_b0 + 3];
+          v = wk[lane];
+          if (rt_cc == 0) v += w0 - w1;
+          if (rt_cc == 1) v += w2 - w3;
+          if (rt_cc == 2) v -= mu * (w0 + w1 + w2 + w3);
+          v += -sigma * u_own[s2];
+          v -= ru_own[s2];
+        }
+        rtd[k * NUP + lane] = v;
+      }
+      wave_sync();
+      if (k >= 1) {
+        float rv[CB], sg[RB];
+        double qt[RB];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) rv[i] = (float)rtd[k * NUP + lb * CB + i];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) qt[j] = qtd[k * NXP + la * RB + j];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) sg[j] = 0.f;
+#pragma unroll
+        for (int i = 0; i < CB; ++i)
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sg[j] += Km[s2][i][j] * rv[i];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) sg[j] = red_b(sg[j]);
+        if (lb == 0)
+#pragma unroll
+          for (int j = 0; j < RB; ++j) gf[k * NXP + la * RB + j] = (float)(qt[j] + (double)sg[j]);
+      }
+      flag_set(sync + kStG + k, t);
+    };
+    // (C) of stage kS[s] (H^{-1} already in Hm)
+    auto phaseC = [&](auto s_c, int t) __attribute__((always_inline)) {
+      constexpr int s2 = decltype(s_c)::value;
+      int k = kS[s2];
+      opaque_s(k);  // per-stage addresses formed here, not kept live across the loop
+      float pv[RB], hv[CB], sh[CB], sd[CB];
+      double rtv[CB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) pv[i] = ppf[k * NXP + la * RB + i];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        rtv[j] = rtd[k * NUP + lb * CB + j];
+        sh[j] = 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) sh[j] += Bm[s2][i][j] * pv[i];
+      red_a_all<CB>(sh);
+#pragma unroll
+      for (int j = 0; j < CB; ++j) hv[j] = (float)(rtv[j] + (double)sh[j]);
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sd[i] = 0.f;
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) sd[i] += Hm[i][j] * hv[j];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sd[i] = red_b(sd[i]);
+      if (lb == 0)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) dd[k * NUP + la * CB + i] = -(double)sd[i];
+      wave_sync();
+      float dv[CB], cv[RB], se[RB];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) dv[j] = (float)dd[k * NUP + lb * CB + j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        cv[i] = cf[k * NXP + la * RB + i];
+        se[i] = 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) se[i] += Bm[s2][i][j] * dv[j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
+      if (lb == 0)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = cv[i] + se[i];
+      flag_set(sync + kStE + k, t);
+    };
+    // (E) of stage kS[s]
+    auto phaseE = [&](auto s_c) __attribute__((always_inline)) {
+      constexpr int s2 = decltype(s_c)::value;
+      int k = kS[s2];
+      opaque_s(k);  // per-stage addresses formed here, not kept live across the loop
+      float xv[RB], su[CB];
+      double dvv[CB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) xv[j] = xtf[k * NXP + la * RB + j];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        dvv[i] = dd[k * NUP + lb * CB + i];
+        su[i] = 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) su[i] += Km[s2][i][j] * xv[j];
+      red_a_all<CB>(su);
+      if (la == 0)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) utd[k * NUP + lb * CB + i] = dvv[i] + (double)su[i];
+      wave_sync();
+      if (k >= 1 && lane < NX) {
+        const double xn = alpha * (double)xtf[k * NXP + lane] + oma * xd[k * NXP + lane];
+        xd[k * NXP + lane] = xn;
+        qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xn;
+      }
+      if (lane < M) {
+        const int idx = k * M + lane;
+        const double zeta = zc_s1 * utd[k * NUP + zc_i1] + zc_s2 * utd[k * NUP + zc_i2];
+        const double wv = alpha * zeta + oma * zd[idx];
+        const double zn = fmin(fmax(wv + yd[idx] * irhod[idx], lod[idx]), hid[idx]);
+        const double yn = yd[idx] + rhod[idx] * (wv - zn);
+        yd[idx] = yn;
+        zd[idx] = zn;
+        wvd[idx] = yn - rhod[idx] * zn;
+      }
+      if (lane < NU) {
+        u_own[s2] = alpha * utd[k * NUP + lane] + oma * u_own[s2];
+        ud[k * NUP + lane] = u_own[s2];
+      }
+      wave_sync();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    if (iters > 0) phaseA(I0{}, 1);
+    for (int it = 0; it < iters; ++it) {
+      const int T = it + 1;
+      if (hasH) {
+        phaseA(I1{}, T);
+        if (kS[1] == N - 1 && it >= 1) relax_xN(T - 1);
+        load_H(kS[1]);
+        flag_wait(sync + kStP + kS[1], 1, T, abortp, lane);
+        phaseC(I1{}, T);
+      }
+      load_H(kS[0]);
+      flag_wait(sync + kStP + kS[0], 1, T, abortp, lane);
+      phaseC(I0{}, T);
+      if (kS[0] >= 1) flag_wait(sync + kStX + kS[0], 1, T, abortp, lane);
+      phaseE(I0{});
+      if (it + 1 < iters) phaseA(I0{}, T + 1);
+      if (hasH) {
+        flag_wait(sync + kStX + kS[1], 1, T, abortp, lane);
+        phaseE(I1{});
+      }
+    }
+    if (hasH && kS[1] == N - 1 && iters > 0) relax_xN(iters);
+  }
+  __syncthreads();
+
+  bool fin = true;
+  for (int i = tid; i < (N + 1) * NX; i += nt) {
+    const float v = (float)xd[(i / NX) * NXP + i % NX];
+    X[i] = v;
+    fin &= (bool)isfinite(v);
+  }
+  for (int i = tid; i < N * NU; i += nt) {
+    const float v = (float)ud[(i / NU) * NUP + i % NU];
+    U[i] = v;
+    fin &= (bool)isfinite(v);
+  }
+  for (int i = tid; i < N * M; i += nt) {
+    Z[i] = (float)zd[i];
+    Y[i] = (float)yd[i];
+    fin &= (bool)isfinite(Z[i]) && (bool)isfinite(Y[i]);
+  }
+  if (!fin || sync[kStAbort]) atomicOr(flag, 1);
+  __syncthreads();
+  if (tid == 0 && flag[0]) st.status[agent] = AGENT_NONFINITE;
+}
+
 template <int NX, int NU>
 hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int M,
                        Inputs<float> in, SolverConsts sc, int iters, int warm, State<float> st,
                        float* fws, hipStream_t stream, int phase_mask) {
   if (n_launch <= 0) return hipSuccess;
   const int lf = riccati_lds_bytes<NX, NU>();
-  const int li = iter_lds_layout<NX, NU>(N, M).total;
   if (phase_mask & 1) {
     hipLaunchKernelGGL((k_riccati<NX, NU, kProdF64, true>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
                        d_desc, list, n_launch, in, sc, fws, st.status);
@@ -1319,8 +2001,15 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
     if (e != hipSuccess) return e;
   }
   if (phase_mask & 2) {
-    hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_launch), dim3(64 * (N + 1)), li, stream,
-                       d_desc, list, n_launch, in, sc, iters, warm, fws, st);
+    if (N + 1 <= kMaxStages) {
+      const int li = iter_lds_layout<NX, NU>(N, M).total;
+      hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_launch), dim3(64 * (N + 1)), li, stream,
+                         d_desc, list, n_launch, in, sc, iters, warm, fws, st);
+    } else {
+      const int li = stream_lds_layout<NX, NU>(N, M).total;
+      hipLaunchKernelGGL((k_admm_stream<NX, NU>), dim3(n_launch), dim3(64 * ((N + 1) / 2 + 2)), li, stream,
+                         d_desc, list, n_launch, in, sc, iters, warm, fws, st);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1341,32 +2030,40 @@ hipError_t set_limits() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF16, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_stream<NX, NU>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <int NX, int NU>
+int fused_lds(int N, int m) {
+  return N + 1 <= kMaxStages ? iter_lds_layout<NX, NU>(N, m).total : stream_lds_layout<NX, NU>(N, m).total;
 }
 
 }  // namespace
 
 bool fused_supported(int N, int nx, int nu, int n_feet) {
   const int m = nu + 4 * n_feet;
-  if (N < 1 || N + 1 > kMaxStages || m > 64) return false;
-  if (nx == 48 && nu == 30) return iter_lds_layout<48, 30>(N, m).total <= 160 * 1024;
-  if (nx == 36 && nu == 24) return iter_lds_layout<36, 24>(N, m).total <= 160 * 1024;
+  if (N < 1 || N > kMaxStream || m > 64) return false;
+  if (nx == 48 && nu == 30) return fused_lds<48, 30>(N, m) <= 160 * 1024;
+  if (nx == 36 && nu == 24) return fused_lds<36, 24>(N, m) <= 160 * 1024;
   return false;
 }
 
 void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds) {
   const int m = nu + 4 * n_feet;
-  *threads = 64 * (N + 1);
-  *lds = (nx == 48) ? iter_lds_layout<48, 30>(N, m).total : iter_lds_layout<36, 24>(N, m).total;
+  *threads = N + 1 <= kMaxStages ? 64 * (N + 1) : 64 * ((N + 1) / 2 + 2);
+  *lds = (nx == 48) ? fused_lds<48, 30>(N, m) : fused_lds<36, 24>(N, m);
   (void)nu;
 }
 
-size_t fused_agent_floats(int nx, int nu) {
+size_t fused_agent_floats(int N, int nx, int nu) {
   (void)nu;
-  if (nx == 48) return (size_t)kMaxStages * (FS<48, 30>::SLOTS * 64 + FS<48, 30>::NXP);
-  return (size_t)kMaxStages * (FS<36, 24>::SLOTS * 64 + FS<36, 24>::NXP);
+  if (nx == 48) return (size_t)N * (FS<48, 30>::SLOTS * 64 + FS<48, 30>::NXP);
+  return (size_t)N * (FS<36, 24>::SLOTS * 64 + FS<36, 24>::NXP);
 }
 
 hipError_t fused_set_limits() {

@@ -288,10 +288,10 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   // register-resident workspace for every agent of a group that may use it
   for (const Group& g : p->groups) {
     if (!g.fused_ok) continue;
-    const int64_t per = (int64_t)fused_agent_floats(g.nx, g.nu);
     for (int i = 0; i < g.count; ++i) {
-      p->hdesc[p->hlist[g.list_off + i]].ofw = p->nFWS;
-      p->nFWS += per;
+      const int32_t a = p->hlist[g.list_off + i];
+      p->hdesc[a].ofw = p->nFWS;
+      p->nFWS += (int64_t)fused_agent_floats(p->shapes[a].N, g.nx, g.nu);
     }
   }
   p->kernel = 0;

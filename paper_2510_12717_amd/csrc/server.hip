@@ -189,7 +189,7 @@ static int family_of(const mpc_server_s* sv, const mpc_shape& s) {
 }
 
 static int64_t ws_bytes(const mpc_server_s* sv, const mpc_shape& s) {
-  if (family_of(sv, s) == 2) return (int64_t)fused_agent_floats(s.nx, s.nu) * 4;
+  if (family_of(sv, s) == 2) return (int64_t)fused_agent_floats(s.N, s.nx, s.nu) * 4;
   return generic_ws_elems(s.N, s.nx, s.nu, ctrl_m(s)) * (int64_t)sv->esz;
 }
 

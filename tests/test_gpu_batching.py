@@ -1,8 +1,9 @@
 """GPU: launch groups of uneven batches, the autotuner and captured-step replay.
 
 Uneven batches (horizons N ~ U{5..20}, half humanoid nx=48 nu=30, half
-quadruped nx=36 nu=24) split into launch groups: register-resident groups per
-(shape class, N) for N <= 11 and generic groups per shape class for the rest.
+quadruped nx=36 nu=24) split into register-resident launch groups per shape
+class and horizon bucket (N <= 6, 7..11, 12..20; the last on the streaming
+iteration kernel).
 Every configuration is checked against the FP64 oracle at the FP32 tolerance
 (1e-5, norm-wise relative per agent).
 """
@@ -32,13 +33,14 @@ def test_groups_of_uneven_batch():
     groups = plan.groups()
     assert sum(x["n_agents"] for x in groups) == 256
     for x in groups:
-        if x["family"] == "fused":
-            assert x["N"] <= 11 and (x["nx"], x["nu"]) in ((48, 30), (36, 24))
+        assert x["family"] == "fused"
+        assert x["N"] <= 20 and (x["nx"], x["nu"]) in ((48, 30), (36, 24))
+        if x["N"] <= 11:
             assert x["threads"] == 64 * (x["N"] + 1)  # stage wavefronts + chain
-    n_fused = sum(x["n_agents"] for x in groups if x["family"] == "fused")
-    n_short = sum(1 for s in b.shapes if s.N <= 11)
-    assert n_fused == n_short
-    assert plan.config()["kernel"] == "generic+fused"
+        else:
+            assert x["threads"] == 64 * ((x["N"] + 1) // 2 + 2)  # + loader
+    assert len(groups) == 6  # two shape classes x three horizon buckets
+    assert plan.config()["kernel"] == "fused"
     o = oracle.solve_batch(b, iters=50)
     assert np.all(g["status"] == 0)
     e = agent_errors(b, g, o)

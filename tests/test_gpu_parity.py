@@ -258,8 +258,9 @@ def test_quadruped_uniform_fp32(kernel):
 
 
 def test_fused_horizon_limits():
-    """The register-resident kernels serve N <= 11; longer horizons fall back."""
-    for N, want in ((1, "fused"), (11, "fused"), (12, "generic")):
+    """The register-resident kernels serve N <= 20 (N >= 12 on the streaming
+    iteration kernel); longer horizons fall back."""
+    for N, want in ((1, "fused"), (11, "fused"), (12, "fused"), (20, "fused"), (21, "generic")):
         plan = mpc.Plan([synth.humanoid(N)] * 2, precision="fp32")
         assert plan.config()["kernel"] == want, N
     b = synth.make_batch([synth.humanoid(1)] * 4, seed=2, config_id=52)
@@ -311,11 +312,15 @@ def test_largest_supported_horizon():
     assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE
 
 
-def test_fused_every_horizon_both_shapes():
+@pytest.mark.parametrize("lo,hi", [(1, 11), (12, 20)])
+def test_fused_every_horizon_both_shapes(lo, hi):
     """The register-resident kernels at every horizon they serve, both built shapes,
     cold and warm: the chain wavefront's lane layouts alternate with the stage's
-    parity, so odd and even horizons end the chains in different layouts."""
-    shapes = [synth.humanoid(N) for N in range(1, 12)] + [synth.quadruped(N) for N in range(1, 12)]
+    parity, so odd and even horizons end the chains in different layouts; from
+    N = 12 the streaming kernel pairs stages on a wavefront and loads the
+    operators from HBM in a horizon-dependent order."""
+    shapes = ([synth.humanoid(N) for N in range(lo, hi + 1)]
+              + [synth.quadruped(N) for N in range(lo, hi + 1)])
     b = synth.make_batch(shapes, seed=4, config_id=61)
     g, plan, prob = run_gpu(b, "fp32", kernel="fused")
     assert plan.config()["kernel"] == "fused"

@@ -648,15 +648,13 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
   const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x;  // nt = 256
   // every dot product is split over the 4 lanes of a quad (terms t = sub,
-  // sub + 4, ...) and summed with DPP; nq quads cover the outputs
-  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
+  // sub + 4, ...) and summed with DPP; quad qd owns output qd (nx <= 64)
+  const int qd = tid >> 2, sub = tid & 3;
   __shared__ double red[256];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* lam = reinterpret_cast<double*>(smem_raw);     // (N+1)*nx
-  T* As = reinterpret_cast<T*>(lam + (N + 1) * nx);      // nx x (nx+1)
-  T* Bs = As + nx * (nx + 1);                            // nx x (nu+1)
   if (st.status[a] != AGENT_OK && st.status[a] != AGENT_CONVERGED) {
     if (tid < 4) st.res[(int64_t)a * 4 + tid] = NAN;
     if (tid == 0) st.obj[a] = (T)NAN;
@@ -678,79 +676,116 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
   const T* z = st.z + d.oz;
   const T* y = st.y + d.oy;
 
+  double* xs = lam + (N + 1) * nx;                      // x as double  (N+1)*nx
+  double* us = xs + (N + 1) * nx;                       // u as double  N*nu
+  T* As = reinterpret_cast<T*>(us + N * nu);            // nx x (nx+1)
+  T* Bs = As + nx * (nx + 1);                           // nx x (nu+1)
+
   double obj = 0.0;
-  for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) {
-    const double ee = (double)x[idx] - (double)xr[idx];
-    obj += 0.5 * (double)q[idx % nx] * ee * ee;
+  for (int idx = tid; idx < (N + 1) * nx; idx += nt) {
+    const double xv = (double)x[idx];
+    xs[idx] = xv;
+    // lambda_k starts as Q(x_k - r_k); A_k' lambda_{k+1} is added stage by stage
+    const double ee = xv - (double)xr[idx];
+    lam[idx] = (double)q[idx % nx] * ee;
+    if (idx >= nx) obj += 0.5 * (double)q[idx % nx] * ee * ee;
   }
   for (int idx = tid; idx < N * nu; idx += nt) {
-    const double ee = (double)u[idx] - (uref ? (double)uref[idx] : 0.0);
+    const double uv = (double)u[idx];
+    us[idx] = uv;
+    const double ee = uv - (uref ? (double)uref[idx] : 0.0);
     obj += 0.5 * (double)r[idx % nu] * ee * ee;
   }
   double rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
   for (int i = tid; i < nx; i += nt) ry = fmax(ry, fabs((double)x[i] - (double)x0[i]));
-  // costates of the dynamics rows: lambda_N = Q(x_N - r_N),
-  // lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}
-  for (int i = tid; i < nx; i += nt)
-    lam[N * nx + i] = (double)q[i] * ((double)x[N * nx + i] - (double)xr[N * nx + i]);
-  // Stage by stage, k = N-1 .. 0: A_k and B_k are read from HBM once, with
-  // coalesced loads, into LDS (rows padded by one element), and every residual
-  // that involves them is formed from there: lambda_k, the dual residual of
-  // u_k (it needs lambda_{k+1}) and the dynamics residual of stage k.
-  for (int k = N - 1; k >= 0; --k) {
+  // Stage by stage, k = N-1 .. 0, every residual that involves A_k and B_k is
+  // formed from LDS: lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}, the dual
+  // residual of u_k, R(u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k, and the
+  // dynamics residual x_{k+1} - A_k x_k - B_k u_k - c_k.  Stage k-1's A, B and
+  // the per-output terms that come from HBM are loaded into registers while
+  // stage k is computed (a quad owns output qd of each product).
+  constexpr int kPA = (64 * 64 + 255) / 256, kPB = (64 * 32 + 255) / 256;
+  T ra[kPA], rb[kPB];
+  double cdyn = 0.0, cdual = 0.0;
+  const float inx = 1.0f / (float)nx, inu = 1.0f / (float)nu;
+  auto fetch = [&](int k) {
     const T* Ag = A + (int64_t)k * nx * nx;
     const T* Bg = B + (int64_t)k * nx * nu;
-    for (int e = tid; e < nx * nx; e += nt) As[(e / nx) * (nx + 1) + e % nx] = Ag[e];
-    for (int e = tid; e < nx * nu; e += nt) Bs[(e / nu) * (nu + 1) + e % nu] = Bg[e];
+#pragma unroll
+    for (int t = 0; t < kPA; ++t) {
+      const int e = tid + t * nt;
+      ra[t] = e < nx * nx ? Ag[e] : (T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < kPB; ++t) {
+      const int e = tid + t * nt;
+      rb[t] = e < nx * nu ? Bg[e] : (T)0;
+    }
+    // x_{k+1} - c_k of output qd, and R(u_k - ubar_k) + C_k' y_k of input qd
+    if (qd < nx) cdyn = (double)x[(k + 1) * nx + qd] - (double)c[(int64_t)k * nx + qd];
+    if (qd < nu) {
+      const int o = k * nu + qd;
+      double v = (double)r[qd] * ((double)u[o] - (uref ? (double)uref[o] : 0.0));
+      const T* yk = y + k * m;
+      v += (double)yk[qd];
+      if (qd >= d.n_tau) {
+        const int f = (qd - d.n_tau) / d.foot_dim, cc = (qd - d.n_tau) % d.foot_dim;
+        const T* yp = yk + nu + 4 * f;
+        if (cc == 0) v += (double)yp[0] - (double)yp[1];
+        if (cc == 1) v += (double)yp[2] - (double)yp[3];
+        if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
+      }
+      cdual = v;
+    }
+  };
+  fetch(N - 1);
+  for (int k = N - 1; k >= 0; --k) {
+    __syncthreads();  // the previous stage's readers of As, Bs and lambda are done
+    // rows padded by one element (row = e / n through a float reciprocal:
+    // exact here, the fraction (e mod n + 1/2) / n stays 1/(2n) away from 0 and 1)
+#pragma unroll
+    for (int t = 0; t < kPA; ++t) {
+      const int e = tid + t * nt;
+      if (e < nx * nx) {
+        const int row = (int)(((float)e + 0.5f) * inx);
+        As[row * (nx + 1) + (e - row * nx)] = ra[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kPB; ++t) {
+      const int e = tid + t * nt;
+      if (e < nx * nu) {
+        const int row = (int)(((float)e + 0.5f) * inu);
+        Bs[row * (nu + 1) + (e - row * nu)] = rb[t];
+      }
+    }
+    const double cd = cdyn, cu = cdual;
     __syncthreads();
+    if (k >= 1) fetch(k - 1);
     const double* lk1 = lam + (k + 1) * nx;
-    if (k >= 1) {
-      for (int i0 = 0; i0 < nx; i0 += nq) {
-        const int i = i0 + qd;  // a quad shares i: whole quads are active or not
-        if (i < nx) {
-          double acc = 0.0;
-          for (int t = sub; t < nx; t += 4) acc += (double)As[t * (nx + 1) + i] * lk1[t];
-          acc = quad_sum(acc);
-          if (sub == 0) lam[k * nx + i] = (double)q[i] * ((double)x[k * nx + i] - (double)xr[k * nx + i]) + acc;
-        }
-      }
+    if (k >= 1 && qd < nx) {
+      double acc = 0.0;
+      for (int t = sub; t < nx; t += 4) acc += (double)As[t * (nx + 1) + qd] * lk1[t];
+      acc = quad_sum(acc);
+      if (sub == 0) lam[k * nx + qd] += acc;
     }
-    // dual residual of the inputs: R(u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k
-    for (int j0 = 0; j0 < nu; j0 += nq) {
-      const int j = j0 + qd;
-      if (j < nu) {
-        const int o = k * nu + j;
-        double acc = 0.0;
-        for (int t = sub; t < nx; t += 4) acc += (double)Bs[t * (nu + 1) + j] * lk1[t];
-        acc = quad_sum(acc);
-        if (sub == 0) {
-          acc += (double)r[j] * ((double)u[o] - (uref ? (double)uref[o] : 0.0));
-          const T* yk = y + k * m;
-          double v = (double)yk[j];
-          if (j >= d.n_tau) {
-            const int f = (j - d.n_tau) / d.foot_dim, cc = (j - d.n_tau) % d.foot_dim;
-            const T* yp = yk + nu + 4 * f;
-            if (cc == 0) v += (double)yp[0] - (double)yp[1];
-            if (cc == 1) v += (double)yp[2] - (double)yp[3];
-            if (cc == 2) v -= mu * ((double)yp[0] + (double)yp[1] + (double)yp[2] + (double)yp[3]);
-          }
-          rd = fmax(rd, fabs(acc + v));
-        }
-      }
+    if (qd < nu) {
+      double acc = 0.0;
+      for (int t = sub; t < nx; t += 4) acc += (double)Bs[t * (nu + 1) + qd] * lk1[t];
+      acc = quad_sum(acc);
+      if (sub == 0) rd = fmax(rd, fabs(acc + cu));
     }
-    // dynamics residual x_{k+1} - A_k x_k - B_k u_k - c_k
-    for (int i0 = 0; i0 < nx; i0 += nq) {
-      const int i = i0 + qd;
-      if (i < nx) {
-        double acc = 0.0;
-        for (int t = sub; t < nx; t += 4) acc += (double)As[i * (nx + 1) + t] * (double)x[k * nx + t];
-        for (int t = sub; t < nu; t += 4) acc += (double)Bs[i * (nu + 1) + t] * (double)u[k * nu + t];
-        acc = quad_sum(acc);
-        if (sub == 0) ry = fmax(ry, fabs((double)x[(k + 1) * nx + i] - (double)c[k * nx + i] - acc));
-      }
+    if (qd < nx) {
+      double acc = 0.0;
+      const double* xk = xs + k * nx;
+      const double* uk = us + k * nu;
+      for (int t = sub; t < nx; t += 4) acc += (double)As[qd * (nx + 1) + t] * xk[t];
+      for (int t = sub; t < nu; t += 4) acc += (double)Bs[qd * (nu + 1) + t] * uk[t];
+      acc = quad_sum(acc);
+      if (sub == 0) ry = fmax(ry, fabs(cd - acc));
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int idx = tid; idx < N * m; idx += nt) {
     const int k = idx / m, i = idx % m;
     double cu;

@@ -60,11 +60,12 @@ inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz) {
   // + 256 doubles of reduction scratch for the refinement's stopping test
   return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu + 256);
 }
-// Residual kernel: costates (N+1) x nx in double, then stage k's A_k and B_k
-// staged in the io type with rows padded by one element.
+// Residual kernel: costates and x ((N+1) x nx each) and u (N x nu) in double,
+// then stage k's A_k and B_k staged in the io type with rows padded by one
+// element.
 inline size_t generic_residual_lds(int N, int nx, int nu, size_t esz) {
-  const size_t lam = 8 * (size_t)(N + 1) * nx;
-  return lam + esz * ((size_t)nx * (nx + 1) + (size_t)nx * (nu + 1)) + 16;
+  const size_t dbl = 8 * (2 * (size_t)(N + 1) * nx + (size_t)N * nu);
+  return dbl + esz * ((size_t)nx * (nx + 1) + (size_t)nx * (nu + 1)) + 16;
 }
 
 // Raise the dynamic-LDS limit of the generic kernels to what a plan needs.

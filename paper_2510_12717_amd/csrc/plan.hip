@@ -51,7 +51,24 @@ struct Group {
   int fthreads = 0;        // register-resident iteration-kernel workgroup size
   size_t flds = 0;
   double work = 0;         // relative cost used to order launches
+  double est = 0;          // cost estimate for the queue assignment (ms once autotuned)
+  int queue = 0;           // 0: the caller's stream, k > 0: aux stream k - 1
 };
+
+// Longest group first onto the least-loaded of nq queues (each queue runs its
+// groups in order, the queues run concurrently).
+void assign_queues(std::vector<Group>& groups, int nq) {
+  std::vector<size_t> order(groups.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return groups[x].est > groups[y].est; });
+  std::vector<double> load(std::max(nq, 1), 0.0);
+  for (size_t i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    groups[i].queue = k;
+    load[k] += groups[i].est;
+  }
+}
 
 }  // namespace
 
@@ -279,6 +296,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz);
       if (g.fused_ok) fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
       for (int32_t a : ag) g.work += (double)p->shapes[a].N * (s0.nx + s0.nu) * (s0.nx + s0.nu);
+      g.est = g.work;
       p->hlist.insert(p->hlist.end(), ag.begin(), ag.end());
       p->groups.push_back(g);
     }
@@ -352,6 +370,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) p->ev_join.push_back(ev);
   }
+  assign_queues(p->groups, 1 + (int)p->aux.size());
   if (e != hipSuccess) {
     free_plan(p);
     return fail(MPC_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
@@ -505,10 +524,10 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
   return MPC_OK;
 }
 
-// Groups run concurrently: group i goes to stream i mod (1 + aux streams),
-// the first of which is the caller's; the aux streams fork from and join
-// back into the caller's stream, so the solve stays stream-ordered (and
-// captures into one graph).
+// Groups run concurrently on the queues assign_queues picked (the caller's
+// stream and the aux streams); the aux streams fork from and join back into
+// the caller's stream, so the solve stays stream-ordered (and captures into
+// one graph).
 template <typename T>
 static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s) {
   const int ns = 1 + (int)p->aux.size();
@@ -517,7 +536,7 @@ static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
     for (hipStream_t a : p->aux) HIP_TRY(hipStreamWaitEvent(a, p->ev_fork, 0));
   }
   for (size_t i = 0; i < p->groups.size(); ++i) {
-    const int k = (int)(i % ns);
+    const int k = std::min(p->groups[i].queue, ns - 1);
     mpc_status r = run_group<T>(p, p->groups[i], b, k == 0 ? s : p->aux[k - 1], b->warm_start);
     if (r != MPC_OK) return r;
   }
@@ -745,7 +764,9 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
     if (r != MPC_OK) break;
     g.family = pick.family;
     if (pick.family != 2) g.gthreads = pick.threads;
+    g.est = best;
   }
+  if (r == MPC_OK) assign_queues(p->groups, 1 + (int)p->aux.size());
   p->timing = timing;
   hipEventDestroy(e0);
   hipEventDestroy(e1);

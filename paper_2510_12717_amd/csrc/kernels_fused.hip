@@ -202,6 +202,17 @@ __device__ inline d4 prod_tile(int ti, int tj, int K, int lane, FA a, FB b) {
 // Riccati factor (FP64, MFMA)
 // ------------------------------------------------------------------------------------
 
+// The t-th tile on or above the diagonal of a TT x TT grid of tiles, row by row
+// (t < TT (TT + 1) / 2).
+__device__ inline void upper_tile(int t, int TT, int& ti, int& tj) {
+  ti = 0;
+  while (ti < TT - 1 && t >= TT - ti) {
+    t -= TT - ti;
+    ++ti;
+  }
+  tj = ti + t;
+}
+
 // LDS of the factor kernel (doubles unless noted): three NXT x LX buffers
 // (P_{k+1} -> G -> K -> P_k; A_k -> A_cl,k; P A_k), one NXT x LU buffer
 // (P B_k -> H_k -> H_k^{-1}), B_k as float, and small vectors.  Under 80 KB for
@@ -222,7 +233,7 @@ constexpr int riccati_lds_bytes() {
 // Stage k: PB = P B_k, PA = P A_k, s_k = P c_k; H_k = Rt_k + B_k' PB and
 // G = B_k' PA; H_k^{-1}; K_k = -H_k^{-1} G; A_cl,k = A_k + B_k K_k; operators
 // out; then P_k = Q + sigma I + PA' A_cl,k (= Q + A'PA + G'K, as P is
-// symmetric), symmetrised.
+// symmetric), formed on and above the diagonal and mirrored.
 template <int NX, int NU, int PREC, bool RES>
 __global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
@@ -395,8 +406,9 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     }
     __syncthreads();
     // H_k^{-1} in place by block Gauss-Jordan sweeps without pivoting over the
-    // padded NUT x NUT matrix (padding is the identity), eliminating the 2x2
-    // pivot block P = H[j..j+1][j..j+1] per sweep:
+    // padded NUT x NUT matrix, eliminating the 2x2 pivot block
+    // P = H[j..j+1][j..j+1] per sweep for j < NU (the padding is an identity
+    // block with zero coupling: no sweep changes it, and it is its own inverse):
     //   P <- P^{-1},  H[p][o] <- P^{-1} H[p][o],  H[o][p] <- -H[o][p] P^{-1},
     //   H[o][o] <- H[o][o] - H[o][p] P^{-1} H[p][o].
     // H_k is SPD, so every pivot block is SPD (a Schur complement); a pivot
@@ -412,7 +424,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       const int row = tid / TPR, c0 = (tid % TPR) * 2;
       double h0 = H[row * LU + c0], h1 = H[row * LU + c0 + 1];
       bool bad = false;
-      for (int j = 0; j < NUT; j += 2) {
+      static_assert(NU % 2 == 0, "2x2 pivot blocks");
+      for (int j = 0; j < NU; j += 2) {
         double* xc = xcol + ((j >> 1) & 1) * 2 * NUT;  // [row][2]: columns j, j+1
         double* xr = xrow + ((j >> 1) & 1) * 2 * NUT;  // [2][col]: rows j, j+1
         if (c0 == j) {
@@ -499,6 +512,23 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       }
     }
     __syncthreads();
+    // P_k = Q + sigma I + PA' A_cl,k (= Q + sigma I + A'PA - G'H^{-1}G, symmetric):
+    // the tiles on and above the diagonal only, into registers here and into
+    // the P buffer (over the dead K_k) once the operators below are written;
+    // each value goes to both of its mirror positions
+    constexpr int TT = NXT / 16, TU = TT * (TT + 1) / 2;
+    constexpr int PR = (TU + kFactorWaves - 1) / kFactorWaves;
+    d4 pacc[PR];
+#pragma unroll
+    for (int rr = 0; rr < PR; ++rr) {
+      const int t = w + rr * kFactorWaves;
+      pacc[rr] = d4{0.0, 0.0, 0.0, 0.0};
+      if (t >= TU) continue;
+      int ti, tj;
+      upper_tile(t, TT, ti, tj);
+      pacc[rr] = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return PA[kk * LX + i]; },
+                                   [&](int kk, int j) { return Ak[kk * LX + j]; });
+    }
     // stage k's operators, rounded to float, in register-layout order (or in
     // the generic row-major layout for the mixed-precision iterations)
     if (!kResident) {
@@ -533,31 +563,20 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       }
       dst[e] = (float)v;
     }
-    __syncthreads();
-    // P_k = Q + sigma I + PA' A_cl,k over the dead K_k (the rows past NX of
-    // PA and A_cl are zero padding)
-    {
-      constexpr int TP = (NXT / 16) * (NXT / 16);
-      for (int t = w; t < TP; t += nw) {
-        const int ti = t / (NXT / 16), tj = t % (NXT / 16);
-        d4 acc = prod_tile<PREC>(ti, tj, NXT, lane, [&](int i, int kk) { return PA[kk * LX + i]; },
-                                 [&](int kk, int j) { return Ak[kk * LX + j]; });
+    __syncthreads();  // the last reads of K_k are done
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
-          const double qv = (i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0;
-          P[i * LX + j] = qv + acc[v];
-        }
-      }
-    }
-    __syncthreads();
-    // symmetrise P_k
-    for (int e = tid; e < NXT * NXT; e += nt) {
-      const int i = e / NXT, j = e % NXT;
-      if (j > i) {
-        const double v = 0.5 * (P[i * LX + j] + P[j * LX + i]);
-        P[i * LX + j] = v;
-        P[j * LX + i] = v;
+    for (int rr = 0; rr < PR; ++rr) {
+      const int t = w + rr * kFactorWaves;
+      if (t >= TU) continue;
+      int ti, tj;
+      upper_tile(t, TT, ti, tj);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
+        if (ti == tj && i > j) continue;
+        const double pv = pacc[rr][v] + ((i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0);
+        P[i * LX + j] = pv;
+        P[j * LX + i] = pv;
       }
     }
     __syncthreads();

@@ -67,6 +67,9 @@ def parse():
                     help="run the served request loop instead: Poisson arrivals from independent "
                          "controllers of uneven shapes (prints its own JSON line)")
     ap.add_argument("--controllers", type=int, default=8192)
+    ap.add_argument("--max-batch", type=int, default=4096,
+                    help="served loop: most requests per batch (with fewer than the controllers, a "
+                         "batch forms while another runs)")
     ap.add_argument("--rate-hz", type=float, default=100.0, help="request rate per controller")
     ap.add_argument("--sim-seconds", type=float, default=2.0)
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
@@ -315,7 +318,7 @@ def serve(args):
     order = np.argsort(at, kind="stable")
     at, ac = at[order], ac[order]
     srv = mpc.Server(precision="fp32", iters=args.iters,
-                     hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), max_batch=8192,
+                     hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), max_batch=args.max_batch,
                      max_inflight=3)
     # warm every controller once (cold first solves), outside the measurement
     srv.submit_many(np.arange(nc), rec_s, rec_p, u0_ptr, np.zeros(nc))
@@ -352,7 +355,8 @@ def serve(args):
                                   f"{args.sim_seconds:g} s, N ~ U{{5..20}}, half humanoid (48, 30), "
                                   "half quadruped (36, 24), warm-started", "controllers": nc,
                       "offered_rate": nc * args.rate_hz, "requests": int(n),
-                      "admm_iters": args.iters, "hbm_budget_gb": args.hbm_budget_gb},
+                      "admm_iters": args.iters, "hbm_budget_gb": args.hbm_budget_gb,
+                      "max_batch": args.max_batch},
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p95": float(np.percentile(lat, 95)),
                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},
            "server": {k: st[k] for k in ("batches", "evictions", "resident_controllers",

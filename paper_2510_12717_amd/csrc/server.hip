@@ -24,7 +24,6 @@
 #include <cstring>
 #include <deque>
 #include <map>
-#include <set>
 #include <string>
 #include <tuple>
 #include <type_traits>
@@ -55,8 +54,10 @@ k_gather_u0(const AgentDesc* __restrict__ desc, int n, const T* __restrict__ u,
   if (threadIdx.x == 0 && status_out[a]) *status_out[a] = status[a];
 }
 
-// First-fit allocator over [0, units) with coalescing (host bookkeeping of
-// the device arena).
+// Allocator over [0, units) with coalescing (host bookkeeping of the device
+// arena): state slots first-fit from the low end, workspace slots from the
+// highest fit down, so the workspace of a batch stays contiguous, apart from
+// the long-lived states, and coalesces back as the batch retires.
 class Arena {
  public:
   void init(int64_t units) {
@@ -70,6 +71,18 @@ class Arena {
         const int64_t off = it->first, len = it->second;
         free_.erase(it);
         if (len > units) free_[off + units] = len - units;
+        free_units_ -= units;
+        return off;
+      }
+    }
+    return -1;
+  }
+  int64_t alloc_high(int64_t units) {
+    for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
+      if (it->second >= units) {
+        const int64_t off = it->first + it->second - units;
+        if (it->second == units) free_.erase(std::next(it).base());
+        else it->second -= units;
         free_units_ -= units;
         return off;
       }
@@ -99,6 +112,14 @@ class Arena {
   int64_t free_units_ = 0;
 };
 
+struct Request {
+  int64_t ticket = 0, ctrl = 0;
+  mpc_problem_batch prob{};
+  void* u0_out = nullptr;
+  int32_t* status_out = nullptr;
+  double t_arrival = 0;
+};
+
 struct Ctrl {
   mpc_shape shape{};
   int64_t state_off = -1;  // arena units
@@ -106,16 +127,9 @@ struct Ctrl {
   bool has_state = false;  // resident iterate valid
   bool busy = false;       // a request of it is on the device
   bool ready = false;      // listed in the ready queue
-  uint64_t last_use = 0;
-  std::deque<int64_t> queue;  // pending tickets, arrival order
-};
-
-struct Request {
-  int64_t ticket = 0, ctrl = 0;
-  mpc_problem_batch prob{};
-  void* u0_out = nullptr;
-  int32_t* status_out = nullptr;
-  double t_arrival = 0;
+  bool idle = false;       // in the idle list: holds a state slot, not busy
+  int64_t prev = -1, next = -1;  // idle-list neighbours (less / more recently used)
+  std::deque<Request> queue;     // pending requests, arrival order
 };
 
 constexpr int kSlotStreams = 4;  // streams per batch slot: the slot's own plus three
@@ -126,6 +140,7 @@ struct Slot {
   hipStream_t aux[kSlotStreams - 1] = {};
   hipEvent_t ev_fork = nullptr, ev_join[kSlotStreams - 1] = {};
   bool busy = false;
+  uint64_t seq = 0;  // launch order of its batch
   // device
   AgentDesc* d_desc = nullptr;
   int32_t* d_list = nullptr;
@@ -157,12 +172,12 @@ struct mpc_server_s {
   Arena arena;
   std::vector<Slot> slots;
   std::unordered_map<int64_t, Ctrl> ctrls;
-  std::unordered_map<int64_t, Request> pending;  // by ticket
+  int64_t n_pending = 0;                         // requests queued, not yet launched
+  uint64_t launch_seq = 0;                       // batches launched
   std::deque<int64_t> ready;                     // controllers whose head request may run
-  std::set<std::pair<uint64_t, int64_t>> idle;   // (last_use, controller) with resident state, not busy
+  int64_t idle_head = -1, idle_tail = -1;        // idle list, least recently used first
   std::deque<std::pair<int64_t, double>> done;   // completed, not yet reported
   int64_t next_ticket = 1;
-  uint64_t use_clock = 1;
   hipEvent_t ev_ref = nullptr;
   std::chrono::steady_clock::time_point t0;
   double t_ref = 0;  // server clock at ev_ref
@@ -327,6 +342,26 @@ extern "C" mpc_status mpc_server_destroy(mpc_server_t s) {
 
 extern "C" double mpc_server_clock(mpc_server_t s) { return s ? server_now(s) : 0.0; }
 
+// The idle list (intrusive, O(1)): controllers join at the most recently used
+// end when their batch retires; eviction takes the least recently used.
+static void idle_push(mpc_server_s* s, int64_t id, Ctrl& c) {
+  c.prev = s->idle_tail;
+  c.next = -1;
+  c.idle = true;
+  if (s->idle_tail >= 0) s->ctrls[s->idle_tail].next = id;
+  else s->idle_head = id;
+  s->idle_tail = id;
+}
+static void idle_remove(mpc_server_s* s, Ctrl& c) {
+  if (!c.idle) return;
+  if (c.prev >= 0) s->ctrls[c.prev].next = c.next;
+  else s->idle_head = c.next;
+  if (c.next >= 0) s->ctrls[c.next].prev = c.prev;
+  else s->idle_tail = c.prev;
+  c.prev = c.next = -1;
+  c.idle = false;
+}
+
 static void mark_ready(mpc_server_s* s, int64_t id, Ctrl& c) {
   if (!c.ready && !c.busy && !c.queue.empty()) {
     c.ready = true;
@@ -339,62 +374,69 @@ static mpc_status submit_one(mpc_server_s* s, int64_t ctrl, const mpc_shape* sha
                              double t_arrival, int64_t* ticket) {
   if (!shape || !prob || !u0_out) return api_fail(MPC_ERR_INVALID_ARG, "null argument");
   const mpc_shape& sh = *shape;
-  if (sh.N < 1 || sh.N > 64 || sh.nx < 1 || sh.nx > 64 || sh.nu < 1 || sh.nu > 32 ||
-      sh.n_feet < 0 || sh.n_feet > 8 || sh.n_tau < 0 || (sh.foot_dim != 3 && sh.foot_dim != 6) ||
-      sh.nu != sh.n_tau + sh.n_feet * sh.foot_dim)
-    return api_fail(MPC_ERR_UNSUPPORTED_SHAPE, "unsupported controller shape");
-  if (s->mixed && !mixed_supported(sh.nx, sh.nu))
-    return api_fail(MPC_ERR_UNSUPPORTED_SHAPE,
-                    "mixed precision is built for (nx, nu) = (48, 30) and (36, 24) only");
+  auto it = s->ctrls.find(ctrl);
+  const bool known = it != s->ctrls.end();
+  if (known) {
+    // its shape passed every check below on its first request
+    if (memcmp(&it->second.shape, &sh, sizeof(sh)) != 0)
+      return api_fail(MPC_ERR_INVALID_ARG, "a controller keeps its shape");
+  } else {
+    if (sh.N < 1 || sh.N > 64 || sh.nx < 1 || sh.nx > 64 || sh.nu < 1 || sh.nu > 32 ||
+        sh.n_feet < 0 || sh.n_feet > 8 || sh.n_tau < 0 || (sh.foot_dim != 3 && sh.foot_dim != 6) ||
+        sh.nu != sh.n_tau + sh.n_feet * sh.foot_dim)
+      return api_fail(MPC_ERR_UNSUPPORTED_SHAPE, "unsupported controller shape");
+    if (s->mixed && !mixed_supported(sh.nx, sh.nu))
+      return api_fail(MPC_ERR_UNSUPPORTED_SHAPE,
+                      "mixed precision is built for (nx, nu) = (48, 30) and (36, 24) only");
+  }
   if (!prob->A || !prob->B || !prob->c || !prob->q_diag || !prob->r_diag || !prob->x_ref ||
       !prob->x0 || !prob->mu || (sh.n_tau > 0 && !prob->tau_max) || (sh.n_feet > 0 && !prob->stance))
     return api_fail(MPC_ERR_INVALID_ARG, "null input pointer in request");
   if (prob->u_ref) return api_fail(MPC_ERR_INVALID_ARG, "requests take no input reference (u_ref must be NULL)");
-  const int m = ctrl_m(sh);
-  if ((int64_t)generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz) > s->lds_max ||
-      (int64_t)generic_factor_lds(sh.nx, sh.nu, s->esz) > s->lds_max)
-    return api_fail(MPC_ERR_UNSUPPORTED_SHAPE, "controller shape needs more LDS than the device offers");
-  // the generic kernels' LDS limits grow to what this shape needs
-  MPC_HIP_TRY(generic_set_lds_limits(generic_factor_lds(sh.nx, sh.nu, s->esz),
-                                     generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz),
-                                     generic_residual_lds(sh.N, sh.nx, sh.nu, s->esz)));
-  const int64_t need = to_units(state_elems(sh) * (int64_t)s->esz) + to_units(ws_bytes(s, sh));
-  if (need > s->arena_bytes / kUnit)
-    return api_fail(MPC_ERR_OUT_OF_MEMORY, "one request of this shape exceeds the HBM budget");
-  auto it = s->ctrls.find(ctrl);
-  if (it == s->ctrls.end()) {
+  if (!known) {
+    const int m = ctrl_m(sh);
+    if ((int64_t)generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz) > s->lds_max ||
+        (int64_t)generic_factor_lds(sh.nx, sh.nu, s->esz) > s->lds_max)
+      return api_fail(MPC_ERR_UNSUPPORTED_SHAPE, "controller shape needs more LDS than the device offers");
+    // the generic kernels' LDS limits grow to what this shape needs
+    MPC_HIP_TRY(generic_set_lds_limits(generic_factor_lds(sh.nx, sh.nu, s->esz),
+                                       generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz),
+                                       generic_residual_lds(sh.N, sh.nx, sh.nu, s->esz)));
+    const int64_t need = to_units(state_elems(sh) * (int64_t)s->esz) + to_units(ws_bytes(s, sh));
+    if (need > s->arena_bytes / kUnit)
+      return api_fail(MPC_ERR_OUT_OF_MEMORY, "one request of this shape exceeds the HBM budget");
     it = s->ctrls.emplace(ctrl, Ctrl{}).first;
     it->second.shape = sh;
-  } else if (memcmp(&it->second.shape, &sh, sizeof(sh)) != 0) {
-    return api_fail(MPC_ERR_INVALID_ARG, "a controller keeps its shape");
   }
-  Request r;
+  Ctrl& c = it->second;
+  c.queue.emplace_back();
+  Request& r = c.queue.back();
   r.ticket = s->next_ticket++;
   r.ctrl = ctrl;
   r.prob = *prob;
   r.u0_out = u0_out;
   r.status_out = status_out;
   r.t_arrival = t_arrival;
-  s->pending.emplace(r.ticket, r);
-  it->second.queue.push_back(r.ticket);
-  mark_ready(s, ctrl, it->second);
+  s->n_pending++;
+  mark_ready(s, ctrl, c);
   if (ticket) *ticket = r.ticket;
   s->stats.submitted++;
   return MPC_OK;
 }
 
-// Evicts least recently used idle controllers until `units` can be allocated.
-static int64_t alloc_evicting(mpc_server_s* s, int64_t units) {
-  int64_t off = s->arena.alloc(units);
-  while (off < 0 && !s->idle.empty()) {
-    const int64_t id = s->idle.begin()->second;
-    s->idle.erase(s->idle.begin());
-    Ctrl& c = s->ctrls[id];
+// Evicts least recently used idle controllers until `units` can be allocated
+// (high: a workspace slot, from the top of the arena).
+static int64_t alloc_evicting(mpc_server_s* s, int64_t units, bool high = false) {
+  auto take = [&]() { return high ? s->arena.alloc_high(units) : s->arena.alloc(units); };
+  int64_t off = take();
+  while (off < 0 && s->idle_head >= 0) {
+    Ctrl& c = s->ctrls[s->idle_head];
+    idle_remove(s, c);
     s->arena.release(c.state_off, c.state_units);
     c.state_off = -1;
     c.has_state = false;
     s->stats.evictions++;
-    off = s->arena.alloc(units);
+    off = take();
   }
   return off;
 }
@@ -611,13 +653,14 @@ static mpc_status pump(mpc_server_s* s) {
         c.state_units = su;
         c.has_state = false;
       } else {
-        s->idle.erase({c.last_use, id});
+        idle_remove(s, c);
       }
       const int64_t wu = to_units(ws_bytes(s, c.shape));
-      const int64_t woff = alloc_evicting(s, wu);
+      const int64_t woff = alloc_evicting(s, wu, true);
       if (woff < 0) {
-        // put the controller back as it was
-        if (c.has_state) s->idle.insert({c.last_use, id});
+        // put the controller back (into the idle list at its most recently used
+        // end: its request is waiting, so its state is evicted last)
+        if (c.has_state) idle_push(s, id, c);
         else {
           s->arena.release(c.state_off, c.state_units);
           c.state_off = -1;
@@ -625,12 +668,10 @@ static mpc_status pump(mpc_server_s* s) {
         skipped.push_back(id);
         break;
       }
-      const int64_t t = c.queue.front();
-      c.queue.pop_front();
       c.busy = true;
-      auto pit = s->pending.find(t);
-      sl.reqs.push_back(pit->second);
-      s->pending.erase(pit);
+      sl.reqs.push_back(c.queue.front());
+      c.queue.pop_front();
+      s->n_pending--;
       sl.ws_off.push_back(woff);
       sl.ws_units.push_back(wu);
     }
@@ -645,16 +686,23 @@ static mpc_status pump(mpc_server_s* s) {
     const mpc_status r = s->fp64 ? launch_batch<double>(s, sl) : launch_batch<float>(s, sl);
     if (r != MPC_OK) return r;
     sl.busy = true;
+    sl.seq = ++s->launch_seq;
     s->stats.batches++;
   }
   return MPC_OK;
 }
 
-// Retires finished batches (non-blocking unless wait).
+// Retires finished batches; with wait, first waits for the oldest running one
+// (only: the others keep running while the freed slot takes the next batch).
 static mpc_status retire(mpc_server_s* s, bool wait) {
+  if (wait) {
+    Slot* oldest = nullptr;
+    for (auto& sl : s->slots)
+      if (sl.busy && (!oldest || sl.seq < oldest->seq)) oldest = &sl;
+    if (oldest) MPC_HIP_TRY(hipEventSynchronize(oldest->done));
+  }
   for (auto& sl : s->slots) {
     if (!sl.busy) continue;
-    if (wait) MPC_HIP_TRY(hipEventSynchronize(sl.done));
     const hipError_t q = hipEventQuery(sl.done);
     if (q == hipErrorNotReady) continue;
     MPC_HIP_TRY(q);
@@ -666,8 +714,7 @@ static mpc_status retire(mpc_server_s* s, bool wait) {
       Ctrl& c = s->ctrls[r.ctrl];
       c.busy = false;
       c.has_state = sl.h_status[i] == AGENT_OK;
-      c.last_use = s->use_clock++;
-      s->idle.insert({c.last_use, r.ctrl});
+      idle_push(s, r.ctrl, c);
       s->arena.release(sl.ws_off[i], sl.ws_units[i]);
       mark_ready(s, r.ctrl, c);
       s->done.push_back({r.ticket, t_done});
@@ -737,7 +784,7 @@ extern "C" mpc_status mpc_server_drain(mpc_server_t s) {
     bool any = false;
     for (auto& sl : s->slots) any |= sl.busy;
     if (!any) {
-      if (s->pending.empty()) return MPC_OK;
+      if (s->n_pending == 0) return MPC_OK;
       return api_fail(MPC_ERR_OUT_OF_MEMORY, "pending requests do not fit the HBM budget");
     }
     r = retire(s, true);
@@ -770,7 +817,7 @@ extern "C" mpc_status mpc_server_get_state(mpc_server_t s, int64_t controller_id
 extern "C" mpc_status mpc_server_get_stats(mpc_server_t s, mpc_server_stats* out) {
   if (!s || !out) return api_fail(MPC_ERR_INVALID_ARG, "null argument");
   *out = s->stats;
-  out->pending = (int64_t)s->pending.size();
+  out->pending = s->n_pending;
   int64_t inflight = 0;
   for (auto& sl : s->slots) inflight += (int64_t)sl.reqs.size();
   out->inflight = inflight;

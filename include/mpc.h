@@ -80,7 +80,8 @@ typedef enum {
 } mpc_precision;
 
 /* per-agent numerical status */
-enum { MPC_AGENT_OK = 0, MPC_AGENT_CONVERGED = 1, MPC_AGENT_NOT_PD = 2, MPC_AGENT_NONFINITE = 3 };
+enum { MPC_AGENT_OK = 0, MPC_AGENT_CONVERGED = 1, MPC_AGENT_NOT_PD = 2, MPC_AGENT_NONFINITE = 3,
+       MPC_AGENT_SUPERSEDED = 4 /* served loop: replaced by a newer request, not solved */ };
 
 /* Shape of one agent's QP.  nu must equal n_tau + n_feet * foot_dim;
  * foot_dim is 6 (wrench f_x,f_y,f_z,m_x,m_y,m_z) or 3 (force f_x,f_y,f_z).
@@ -237,7 +238,13 @@ mpc_status mpc_plan_replay(mpc_plan_t plan, void* stream);
  * requests that still do not fit wait.  A controller's requests run in
  * arrival order, one at a time.  Each request is solved exactly as the same
  * agent in a plan of the same precision: its result does not depend on the
- * other requests of its batch.
+ * other requests of its batch.  With supersede = 1 (for controllers whose
+ * newest state makes an older one moot, as in receding-horizon control under
+ * overload), a request still waiting when a newer request of the same
+ * controller arrives is dropped: *status_out (if given) receives
+ * MPC_AGENT_SUPERSEDED once a later batch launches, u0_out is not written, the
+ * ticket is never reported by mpc_server_poll, and stats.superseded counts it;
+ * the newer request then runs warm-started from the last solved one.
  * ------------------------------------------------------------------------- */
 typedef struct mpc_server_s* mpc_server_t;
 
@@ -247,6 +254,8 @@ typedef struct {
   int64_t hbm_budget_bytes;  /* device memory of the server (default 1 GiB)             */
   int32_t max_batch;         /* requests per batch (default 4096)                       */
   int32_t max_inflight;      /* batches on the device at once, 1..8 (default 3)        */
+  int32_t supersede;         /* 1: a controller's queued request that a newer one of it  */
+                             /* follows before it launches completes unsolved (default 0)*/
 } mpc_server_desc;
 
 typedef struct {
@@ -254,6 +263,7 @@ typedef struct {
   int64_t pending, inflight;             /* requests waiting / on the device now       */
   int64_t resident_controllers, resident_bytes;
   int64_t arena_bytes, arena_free_bytes;
+  int64_t superseded;                    /* requests completed unsolved (supersede = 1) */
 } mpc_server_stats;
 
 void mpc_server_desc_default(mpc_server_desc* desc);
@@ -290,14 +300,14 @@ mpc_status mpc_server_submit_many(mpc_server_t server, int32_t n, const int64_t*
                                   const double* t_arrival, int64_t* tickets);
 
 /* Non-blocking: retire finished batches, launch pending work into free
- * slots, and report up to cap completed tickets with their completion times
- * (server clock, taken from the batch's completion event). */
+ * slots, and report up to cap completed (solved) tickets with their
+ * completion times (server clock, taken from the batch's completion event). */
 mpc_status mpc_server_poll(mpc_server_t server, int64_t* done_tickets, double* done_time,
                            int32_t cap, int32_t* n_done);
 
-/* Blocks until every submitted request has completed (completions stay
- * reportable by mpc_server_poll).  OUT_OF_MEMORY if pending requests can
- * never fit the budget. */
+/* Blocks until every submitted request has completed or been superseded
+ * (completions stay reportable by mpc_server_poll; superseded statuses are
+ * written).  OUT_OF_MEMORY if pending requests can never fit the budget. */
 mpc_status mpc_server_drain(mpc_server_t server);
 
 /* Copy a controller's resident iterate (x [N+1][nx], u [N][nu], z, y [N][m],

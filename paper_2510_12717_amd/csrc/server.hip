@@ -54,6 +54,12 @@ k_gather_u0(const AgentDesc* __restrict__ desc, int n, const T* __restrict__ u,
   if (threadIdx.x == 0 && status_out[a]) *status_out[a] = status[a];
 }
 
+// Writes v to *p[i] for every i < n (statuses of superseded requests).
+__global__ void __launch_bounds__(256) k_mark_status(int32_t* const* __restrict__ p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *p[i] = v;
+}
+
 // Allocator over [0, units) with coalescing (host bookkeeping of the device
 // arena): state slots first-fit from the low end, workspace slots from the
 // highest fit down, so the workspace of a batch stays contiguous, apart from
@@ -155,6 +161,9 @@ struct Slot {
   void** h_u0 = nullptr;
   int32_t** h_st_out = nullptr;
   int32_t* h_status = nullptr;
+  // statuses of superseded requests written with this slot's next batch
+  int32_t** h_sup = nullptr;
+  int32_t** d_sup = nullptr;
   // the batch
   std::vector<Request> reqs;
   std::vector<int64_t> ws_off, ws_units;
@@ -173,6 +182,7 @@ struct mpc_server_s {
   std::vector<Slot> slots;
   std::unordered_map<int64_t, Ctrl> ctrls;
   int64_t n_pending = 0;                         // requests queued, not yet launched
+  std::deque<int32_t*> sup_status;               // superseded requests' status_out, not yet written
   uint64_t launch_seq = 0;                       // batches launched
   std::deque<int64_t> ready;                     // controllers whose head request may run
   int64_t idle_head = -1, idle_tail = -1;        // idle list, least recently used first
@@ -230,6 +240,8 @@ static void free_slot_buffers(Slot& sl) {
   hipHostFree(sl.h_u0);
   hipHostFree(sl.h_st_out);
   hipHostFree(sl.h_status);
+  hipHostFree(sl.h_sup);
+  hipFree(sl.d_sup);
 }
 
 static void free_server(mpc_server_s* s) {
@@ -264,6 +276,8 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   if (desc->max_batch < 1 || desc->max_batch > (1 << 20) || desc->max_inflight < 1 ||
       desc->max_inflight > 8)
     return api_fail(MPC_ERR_INVALID_ARG, "max_batch must be in 1..2^20 and max_inflight in 1..8");
+  if (desc->supersede != 0 && desc->supersede != 1)
+    return api_fail(MPC_ERR_INVALID_ARG, "supersede must be 0 or 1");
   if (desc->hbm_budget_bytes <= 0) return api_fail(MPC_ERR_INVALID_ARG, "hbm_budget_bytes must be > 0");
   int ndev = 0;
   MPC_HIP_TRY(hipGetDeviceCount(&ndev));
@@ -279,7 +293,7 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   s->esz = s->fp64 ? 8 : 4;
   const int B = desc->max_batch;
   // per-slot buffers come out of the budget first
-  const int64_t per_slot = (int64_t)B * (sizeof(AgentDesc) + sizeof(int32_t) + 2 * sizeof(void*) +
+  const int64_t per_slot = (int64_t)B * (sizeof(AgentDesc) + sizeof(int32_t) + 3 * sizeof(void*) +
                                          sizeof(int32_t) + 8 + 4 * sizeof(double));
   s->arena_bytes = desc->hbm_budget_bytes - per_slot * desc->max_inflight;
   s->arena_bytes = s->arena_bytes / kUnit * kUnit;
@@ -310,6 +324,8 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_u0, sizeof(void*) * B, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_st_out, sizeof(int32_t*) * B, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_status, sizeof(int32_t) * B, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.d_sup, sizeof(int32_t*) * B);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_sup, sizeof(int32_t*) * B, hipHostMallocDefault);
   }
   int lds_max = 0;
   if (e == hipSuccess)
@@ -409,6 +425,14 @@ static mpc_status submit_one(mpc_server_s* s, int64_t ctrl, const mpc_shape* sha
     it->second.shape = sh;
   }
   Ctrl& c = it->second;
+  if (s->desc.supersede && !c.queue.empty()) {
+    // the waiting requests of this controller are moot: drop them
+    for (const Request& old : c.queue)
+      if (old.status_out) s->sup_status.push_back(old.status_out);
+    s->n_pending -= (int64_t)c.queue.size();
+    s->stats.superseded += (int64_t)c.queue.size();
+    c.queue.clear();
+  }
   c.queue.emplace_back();
   Request& r = c.queue.back();
   r.ticket = s->next_ticket++;
@@ -499,6 +523,22 @@ static Inputs<T> batch_inputs(const std::vector<Request>& reqs, std::vector<Agen
   return in;
 }
 
+// Up to max_batch pending superseded statuses, written on the slot's stream
+// (the slot is idle: its staging buffer is free).
+static mpc_status flush_superseded(mpc_server_s* s, Slot& sl) {
+  const int n = (int)std::min<size_t>(s->sup_status.size(), (size_t)s->desc.max_batch);
+  if (n == 0) return MPC_OK;
+  for (int i = 0; i < n; ++i) {
+    sl.h_sup[i] = s->sup_status.front();
+    s->sup_status.pop_front();
+  }
+  MPC_HIP_TRY(hipMemcpyAsync(sl.d_sup, sl.h_sup, sizeof(int32_t*) * n, hipMemcpyHostToDevice, sl.stream));
+  hipLaunchKernelGGL(k_mark_status, dim3((n + 255) / 256), dim3(256), 0, sl.stream, sl.d_sup, n,
+                     (int32_t)MPC_AGENT_SUPERSEDED);
+  MPC_HIP_TRY(hipGetLastError());
+  return MPC_OK;
+}
+
 template <typename T>
 static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
   const int n = (int)sl.reqs.size();
@@ -557,6 +597,10 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
     gl.push_back(g);
   }
   hipStream_t st = sl.stream;
+  {
+    const mpc_status fr = flush_superseded(s, sl);
+    if (fr != MPC_OK) return fr;
+  }
   MPC_HIP_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(AgentDesc) * n, hipMemcpyHostToDevice, st));
   MPC_HIP_TRY(hipMemcpyAsync(sl.d_list, sl.h_list, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
   MPC_HIP_TRY(hipMemcpyAsync(sl.d_u0, sl.h_u0, sizeof(void*) * n, hipMemcpyHostToDevice, st));
@@ -784,7 +828,15 @@ extern "C" mpc_status mpc_server_drain(mpc_server_t s) {
     bool any = false;
     for (auto& sl : s->slots) any |= sl.busy;
     if (!any) {
-      if (s->n_pending == 0) return MPC_OK;
+      if (s->n_pending == 0) {
+        // every slot is idle: write the superseded statuses still waiting
+        while (!s->sup_status.empty()) {
+          r = flush_superseded(s, s->slots[0]);
+          if (r != MPC_OK) return r;
+          MPC_HIP_TRY(hipStreamSynchronize(s->slots[0].stream));
+        }
+        return MPC_OK;
+      }
       return api_fail(MPC_ERR_OUT_OF_MEMORY, "pending requests do not fit the HBM budget");
     }
     r = retire(s, true);

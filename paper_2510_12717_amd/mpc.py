@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmpc_hip.so")
 MPC_OK, MPC_ERR_INVALID_ARG, MPC_ERR_OUT_OF_MEMORY, MPC_ERR_HIP = 0, 1, 2, 3
 MPC_ERR_UNSUPPORTED_SHAPE, MPC_ERR_BUSY, MPC_ERR_NOT_READY = 4, 5, 6
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
-AGENT_OK, AGENT_CONVERGED, AGENT_NOT_PD, AGENT_NONFINITE = 0, 1, 2, 3
+AGENT_OK, AGENT_CONVERGED, AGENT_NOT_PD, AGENT_NONFINITE, AGENT_SUPERSEDED = 0, 1, 2, 3, 4
 
 
 class MPCError(RuntimeError):
@@ -53,13 +53,14 @@ class GroupInfo(ctypes.Structure):
 
 class ServerDesc(ctypes.Structure):
     _fields_ = [("solver", PlanDesc), ("hbm_budget_bytes", ctypes.c_int64),
-                ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("supersede", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "completed", "batches", "evictions", "pending", "inflight",
-        "resident_controllers", "resident_bytes", "arena_bytes", "arena_free_bytes")]
+        "resident_controllers", "resident_bytes", "arena_bytes", "arena_free_bytes", "superseded")]
 
 
 class Solution(ctypes.Structure):
@@ -339,7 +340,8 @@ class Server:
     """Served request loop (see ``mpc_server_create``)."""
 
     def __init__(self, precision: str = "fp32", iters: int = 50, hbm_budget_bytes: int = 1 << 30,
-                 max_batch: int = 4096, max_inflight: int = 3, device: int = 0, **consts):
+                 max_batch: int = 4096, max_inflight: int = 3, device: int = 0,
+                 supersede: bool = False, **consts):
         L = lib()
         d = ServerDesc()
         L.mpc_server_desc_default(ctypes.byref(d))
@@ -351,6 +353,7 @@ class Server:
         d.hbm_budget_bytes = int(hbm_budget_bytes)
         d.max_batch = int(max_batch)
         d.max_inflight = int(max_inflight)
+        d.supersede = 1 if supersede else 0
         h = ctypes.c_void_p()
         _check(L.mpc_server_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -382,18 +385,20 @@ class Server:
         return t.value
 
     def submit_many(self, ctrls: np.ndarray, shapes, problems, u0_ptrs: np.ndarray,
-                    t_arrival: np.ndarray) -> np.ndarray:
+                    t_arrival: np.ndarray, status_ptrs: Optional[np.ndarray] = None) -> np.ndarray:
         """Bulk submission: ``shapes``/``problems`` hold one Shape / ProblemBatch
         record per request (ctypes arrays, or numpy arrays of the raw records),
-        ``u0_ptrs`` device addresses (uint64)."""
+        ``u0_ptrs`` (and optionally ``status_ptrs``) device addresses (uint64)."""
         n = len(ctrls)
         ctrls = np.ascontiguousarray(ctrls, dtype=np.int64)
         u0 = np.ascontiguousarray(u0_ptrs, dtype=np.uint64)
         ta = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        st = None if status_ptrs is None else np.ascontiguousarray(status_ptrs, dtype=np.uint64)
         tk = np.empty(n, dtype=np.int64)
         addr = lambda a: a.ctypes.data if isinstance(a, np.ndarray) else ctypes.addressof(a)
         _check(lib().mpc_server_submit_many(self._h, n, ctrls.ctypes.data, addr(shapes),
-                                            addr(problems), u0.ctypes.data, None,
+                                            addr(problems), u0.ctypes.data,
+                                            None if st is None else st.ctypes.data,
                                             ta.ctypes.data, tk.ctypes.data))
         return tk
 

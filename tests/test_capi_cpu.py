@@ -111,8 +111,9 @@ def test_server_rejects_bad_descriptions():
     L = mpc.lib()
     d = mpc.ServerDesc()
     L.mpc_server_desc_default(ctypes.byref(d))
-    assert (d.max_batch, d.max_inflight, d.hbm_budget_bytes) == (4096, 3, 1 << 30)
-    for field, bad in (("max_batch", 0), ("max_inflight", 9), ("hbm_budget_bytes", 0)):
+    assert (d.max_batch, d.max_inflight, d.hbm_budget_bytes, d.supersede) == (4096, 3, 1 << 30, 0)
+    for field, bad in (("max_batch", 0), ("max_inflight", 9), ("hbm_budget_bytes", 0),
+                       ("supersede", 2)):
         dd = mpc.ServerDesc()
         L.mpc_server_desc_default(ctypes.byref(dd))
         setattr(dd, field, bad)

@@ -157,3 +157,35 @@ def test_server_rejects_bad_requests():
         srv.submit(1, big.shapes[0], mpc.agent_problems(pb, big)[0], buf)
     assert ei.value.code in (mpc.MPC_ERR_OUT_OF_MEMORY, mpc.MPC_ERR_UNSUPPORTED_SHAPE)
     srv.drain()
+
+
+def test_supersede_drops_waiting_requests():
+    """With supersede, a request still waiting when a newer one of its
+    controller arrives completes unsolved (status SUPERSEDED, output untouched,
+    never polled); the newer one runs warm-started from the last solved one."""
+    b = synth.config2(8)
+    prob = mpc.to_device(b, "fp32")
+    reqs = mpc.agent_problems(prob, b)
+    want = _plan_u0(b, prob, 2)  # cold, then warm-started
+    a, sh = 3, b.shapes[3]
+    srv = mpc.Server(precision="fp32", max_batch=16, max_inflight=1, supersede=True)
+    st = torch.full((3,), -1, dtype=torch.int32, device="cuda")
+    bufs = [torch.full((sh.nu,), float("nan"), device="cuda") for _ in range(3)]
+    t1 = srv.submit(a, sh, reqs[a], bufs[0], warm=True, status_out=st[0:1])
+    # the next two arrive in one call: no batch forms between them, so the
+    # second is superseded by the third whatever the first is doing
+    rec_s = (mpc.Shape * 2)(*[mpc.Shape(*sh.as_tuple())] * 2)
+    rec_p = (mpc.ProblemBatch * 2)(reqs[a], reqs[a])
+    u0 = np.array([bufs[1].data_ptr(), bufs[2].data_ptr()], dtype=np.uint64)
+    sp = np.array([st[1:2].data_ptr(), st[2:3].data_ptr()], dtype=np.uint64)
+    tk = srv.submit_many(np.array([a, a]), rec_s, rec_p, u0, np.zeros(2), status_ptrs=sp)
+    srv.drain()
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [mpc.AGENT_OK, mpc.AGENT_SUPERSEDED, mpc.AGENT_OK]
+    assert torch.equal(bufs[0].cpu(), want[0][a])
+    assert torch.isnan(bufs[1]).all().item()
+    assert torch.equal(bufs[2].cpu(), want[1][a])
+    got, _ = srv.poll()
+    assert sorted(got.tolist()) == sorted([t1, int(tk[1])])
+    stats = srv.stats()
+    assert stats["superseded"] == 1 and stats["completed"] == 2 and stats["pending"] == 0

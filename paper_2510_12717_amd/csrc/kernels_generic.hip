@@ -637,6 +637,37 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   if (!ok) st.status[a] = AGENT_NONFINITE;
 }
 
+// Workgroup max of rp, rd, ry, rc and sum of obj, valid in thread 0: a
+// butterfly within each wavefront, then one exchange of the wavefronts' values.
+__device__ inline void block_reduce_res(double& rp, double& rd, double& ry, double& rc, double& obj,
+                                        double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    rp = fmax(rp, __shfl_xor(rp, off));
+    rd = fmax(rd, __shfl_xor(rd, off));
+    ry = fmax(ry, __shfl_xor(ry, off));
+    rc = fmax(rc, __shfl_xor(rc, off));
+    obj += __shfl_xor(obj, off);
+  }
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[5 * w] = rp;
+    red[5 * w + 1] = rd;
+    red[5 * w + 2] = ry;
+    red[5 * w + 3] = rc;
+    red[5 * w + 4] = obj;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int v = 1; v < nw; ++v) {
+      rp = fmax(rp, red[5 * v]);
+      rd = fmax(rd, red[5 * v + 1]);
+      ry = fmax(ry, red[5 * v + 2]);
+      rc = fmax(rc, red[5 * v + 3]);
+      obj += red[5 * v + 4];
+    }
+}
+
 // FP64 KKT residuals of the returned iterate (the role of the solution check
 // that follows the QP loop in Alg. 1).  Costates of the dynamics rows come from
 // the adjoint sweep lambda_N = Q(x_N - r_N), lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}.
@@ -681,23 +712,6 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
   T* As = reinterpret_cast<T*>(us + N * nu);            // nx x (nx+1)
   T* Bs = As + nx * (nx + 1);                           // nx x (nu+1)
 
-  double obj = 0.0;
-  for (int idx = tid; idx < (N + 1) * nx; idx += nt) {
-    const double xv = (double)x[idx];
-    xs[idx] = xv;
-    // lambda_k starts as Q(x_k - r_k); A_k' lambda_{k+1} is added stage by stage
-    const double ee = xv - (double)xr[idx];
-    lam[idx] = (double)q[idx % nx] * ee;
-    if (idx >= nx) obj += 0.5 * (double)q[idx % nx] * ee * ee;
-  }
-  for (int idx = tid; idx < N * nu; idx += nt) {
-    const double uv = (double)u[idx];
-    us[idx] = uv;
-    const double ee = uv - (uref ? (double)uref[idx] : 0.0);
-    obj += 0.5 * (double)r[idx % nu] * ee * ee;
-  }
-  double rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
-  for (int i = tid; i < nx; i += nt) ry = fmax(ry, fabs((double)x[i] - (double)x0[i]));
   // Stage by stage, k = N-1 .. 0, every residual that involves A_k and B_k is
   // formed from LDS: lambda_k = Q(x_k - r_k) + A_k' lambda_{k+1}, the dual
   // residual of u_k, R(u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k, and the
@@ -738,7 +752,54 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
       cdual = v;
     }
   };
-  fetch(N - 1);
+  fetch(N - 1);  // first: its loads overlap the element-wise pass below
+  // One pass over the element-wise terms, its loads issued together: x and u
+  // into LDS as double, lambda_k = Q(x_k - r_k) (A_k' lambda_{k+1} is added
+  // stage by stage), the objective, x_0's residual, and the row residuals
+  // (primal C u - z and complementarity of y with the bounds)
+  double obj = 0.0, rp = 0.0, rd = 0.0, ry = 0.0, rc = 0.0;
+  {
+    const int nX = (N + 1) * nx, nU = N * nu, nR = N * m;
+    const int nmax = nX > nU ? (nX > nR ? nX : nR) : (nU > nR ? nU : nR);
+    for (int idx = tid; idx < nmax; idx += nt) {
+      if (idx < nX) {
+        const double xv = (double)x[idx];
+        xs[idx] = xv;
+        const double ee = xv - (double)xr[idx];
+        lam[idx] = (double)q[idx % nx] * ee;
+        if (idx >= nx) obj += 0.5 * (double)q[idx % nx] * ee * ee;
+        else ry = fmax(ry, fabs(xv - (double)x0[idx]));
+      }
+      if (idx < nU) {
+        const double uv = (double)u[idx];
+        us[idx] = uv;
+        const double ee = uv - (uref ? (double)uref[idx] : 0.0);
+        obj += 0.5 * (double)r[idx % nu] * ee * ee;
+      }
+      if (idx < nR) {
+        const int k = idx / m, i = idx % m;
+        double cu;
+        const T* uk = u + k * nu;
+        if (i < nu) {
+          cu = (double)uk[i];
+        } else {
+          const int f = (i - nu) >> 2, pp = (i - nu) & 3, b = d.n_tau + f * d.foot_dim;
+          const double t = (pp < 2) ? (double)uk[b] : (double)uk[b + 1];
+          cu = ((pp & 1) ? -t : t) - mu * (double)uk[b + 2];
+        }
+        rp = fmax(rp, fabs(cu - (double)z[idx]));
+        T lo_t, hi_t, rho_t;
+        row_bounds<T, T>(d, i, stance + k * d.n_feet, tau, sc, lo_t, hi_t, rho_t);
+        const double lo = (double)lo_t, hi = (double)hi_t, zz = (double)z[idx], yy = (double)y[idx];
+        const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
+        const double ca = isinf(hi) ? yp : fmin(yp, hi - zz);
+        const double cb = isinf(lo) ? ym : fmin(ym, zz - lo);
+        rc = fmax(rc, fmax(fabs(ca), fabs(cb)));
+        if (zz > hi) rc = fmax(rc, zz - hi);
+        if (zz < lo) rc = fmax(rc, lo - zz);
+      }
+    }
+  }
   for (int k = N - 1; k >= 0; --k) {
     __syncthreads();  // the previous stage's readers of As, Bs and lambda are done
     // rows padded by one element (row = e / n through a float reciprocal:
@@ -786,33 +847,7 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < N * m; idx += nt) {
-    const int k = idx / m, i = idx % m;
-    double cu;
-    const T* uk = u + k * nu;
-    if (i < nu) {
-      cu = (double)uk[i];
-    } else {
-      const int f = (i - nu) >> 2, pp = (i - nu) & 3, b = d.n_tau + f * d.foot_dim;
-      const double t = (pp < 2) ? (double)uk[b] : (double)uk[b + 1];
-      cu = ((pp & 1) ? -t : t) - mu * (double)uk[b + 2];
-    }
-    rp = fmax(rp, fabs(cu - (double)z[idx]));
-    T lo_t, hi_t, rho_t;
-    row_bounds<T, T>(d, i, stance + k * d.n_feet, tau, sc, lo_t, hi_t, rho_t);
-    const double lo = (double)lo_t, hi = (double)hi_t, zz = (double)z[idx], yy = (double)y[idx];
-    const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
-    const double ca = isinf(hi) ? yp : fmin(yp, hi - zz);
-    const double cb = isinf(lo) ? ym : fmin(ym, zz - lo);
-    rc = fmax(rc, fmax(fabs(ca), fabs(cb)));
-    if (zz > hi) rc = fmax(rc, zz - hi);
-    if (zz < lo) rc = fmax(rc, lo - zz);
-  }
-  rp = block_max(rp, red);
-  rd = block_max(rd, red);
-  ry = block_max(ry, red);
-  rc = block_max(rc, red);
-  obj = block_sum(obj, red);
+  block_reduce_res(rp, rd, ry, rc, obj, red);
   if (tid == 0) {
     double* res = st.res + (int64_t)a * 4;
     res[0] = rp;

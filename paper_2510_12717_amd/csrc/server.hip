@@ -34,6 +34,7 @@
 #include "fused.h"
 #include "host_api.h"
 #include "mpc_internal.h"
+#include "server_arena.h"
 
 using namespace mpc;
 
@@ -60,63 +61,6 @@ __global__ void __launch_bounds__(256) k_mark_status(int32_t* const* __restrict_
   if (i < n) *p[i] = v;
 }
 
-// Allocator over [0, units) with coalescing (host bookkeeping of the device
-// arena): state slots first-fit from the low end, workspace slots from the
-// highest fit down, so the workspace of a batch stays contiguous, apart from
-// the long-lived states, and coalesces back as the batch retires.
-class Arena {
- public:
-  void init(int64_t units) {
-    free_.clear();
-    if (units > 0) free_[0] = units;
-    free_units_ = units;
-  }
-  int64_t alloc(int64_t units) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= units) {
-        const int64_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > units) free_[off + units] = len - units;
-        free_units_ -= units;
-        return off;
-      }
-    }
-    return -1;
-  }
-  int64_t alloc_high(int64_t units) {
-    for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
-      if (it->second >= units) {
-        const int64_t off = it->first + it->second - units;
-        if (it->second == units) free_.erase(std::next(it).base());
-        else it->second -= units;
-        free_units_ -= units;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void release(int64_t off, int64_t units) {
-    free_units_ += units;
-    auto it = free_.emplace(off, units).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  int64_t free_units() const { return free_units_; }
-
- private:
-  std::map<int64_t, int64_t> free_;
-  int64_t free_units_ = 0;
-};
 
 struct Request {
   int64_t ticket = 0, ctrl = 0;

@@ -115,3 +115,27 @@ def test_replay_without_capture_is_not_ready():
     with pytest.raises(mpc.MPCError) as ei:
         plan.replay()
     assert ei.value.code == mpc.MPC_ERR_NOT_READY
+
+
+def test_config2_full_size_sampled():
+    """The uneven batch at full size (8192 agents) in the benchmark's launch
+    configuration: autotuned groups, one captured step replayed; every 64th
+    agent is checked against the oracle (cold start)."""
+    b = synth.config2(8192, dtype=np.float32)
+    plan = mpc.Plan(b.shapes, precision="fp32", iters=50)
+    prob = mpc.to_device(b, "fp32")
+    groups = plan.autotune(prob, reps=1)
+    assert all(x["family"] == "fused" for x in groups)
+    plan.capture(prob, warm_start=False)
+    plan.replay()
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    assert np.all(g["status"] == 0)
+    ids = np.arange(0, 8192, 64)
+    sub = synth.config2(agent_ids=ids)
+    o = oracle.solve_batch(sub, iters=50)
+    o["_off"] = sub.offsets()
+    e = agent_errors(b, g, o, agents=ids, go=np.arange(len(ids)))
+    print("config2 sampled: max u0/traj", e[:, :2].max(axis=0), "horizons",
+          sorted({b.shapes[i].N for i in ids}))
+    assert e[:, :2].max() < TOL["fp32"]

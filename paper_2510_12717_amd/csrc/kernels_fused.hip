@@ -931,6 +931,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
           opaque_s(ok);
           opaque_s(om);
           if ((ODD ? la : lb) == 0) lds_store<RB>(ppf + ok + in_idx, pv);
+          flag_set(sync + kSyncP + kk, T);  // C_kk may start now
           float gv[RB], sv[RB], qv[RB];
           lds_load<RB>(sv, sf + om + out_idx);
           lds_load<RB>(gv, gf + ok + out_idx);  // (reloaded below on the first hop)
@@ -960,7 +961,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
           }
 #pragma unroll
           for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
-          flag_set(sync + kSyncP + kk, T);
         };
         using T_ = std::true_type;
         using F_ = std::false_type;
@@ -1610,6 +1610,7 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
           opaque_s(ok);
           opaque_s(om);
           if ((ODD ? la : lb) == 0) lds_store<RB>(ppf + ok + in_idx, pv);
+          flag_set(sync + kStP + kk, T);  // C_kk may start now
           float gv[RB], sv[RB], qv[RB];
           lds_load<RB>(sv, sf + om + out_idx);
           lds_load<RB>(gv, gf + ok + out_idx);
@@ -1639,7 +1640,6 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
           }
 #pragma unroll
           for (int j = 0; j < RB; ++j) pv[j] = gv[j] + qv[j] + sv[j];
-          flag_set(sync + kStP + kk, T);
         };
         int kk = N - 1;
 #pragma unroll

@@ -260,11 +260,18 @@ def mixed(args):
         for _ in range(max(args.warmup, 1)):
             plan.solve(prob, stream=stream)
         torch.cuda.synchronize()
+        plan.set_timing(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             plan.solve(prob, stream=stream)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / args.steps * 1e3
+        tm = plan.get_timing()
+        fac_ms = tm["factor"][0] / max(tm["factor"][1], 1)
+        # the factor's block products on the matrix cores: FP64 MFMA in the FP32 mode,
+        # BF16 / FP16 MFMA (FP32 accumulation) in the mixed modes
+        fac_flops = flops_factor_stage(sh.nx, sh.nu) * sh.N * n
+        peak = 78.6 if prec == "fp32" else 2500.0
         u = plan.get_solution()["u"].cpu().numpy().reshape(n, sh.N * sh.nu)[ids].astype(np.float64)
         x = plan.get_solution()["x"].cpu().numpy().reshape(n, (sh.N + 1) * sh.nx)[ids].astype(np.float64)
         uo = ref["u"].reshape(len(ids), -1)
@@ -275,6 +282,11 @@ def mixed(args):
         e_tr = np.abs(tr - to).max(1) / np.abs(to).max(1)
         key = prec if prec == "fp32" else f"{prec}_sweeps{sweeps}"
         modes[key] = {"ms_per_step": ms, "solves_per_s": n / ms * 1e3,
+                      "factor_ms": fac_ms,
+                      "factor_roofline": {"bound": "mfma", "achieved": fac_flops / fac_ms / 1e9,
+                                          "peak": peak, "unit": "TFLOP/s",
+                                          "frac": fac_flops / fac_ms / 1e9 / peak,
+                                          "mfma_dtype": "f64" if prec == "fp32" else prec},
                       "err_u0_max": float(e_u0.max()), "err_traj_max": float(e_tr.max()),
                       "err_traj_p50": float(np.median(e_tr)), "kernel": plan.config()["kernel"]}
         plan.close()

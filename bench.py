@@ -134,7 +134,7 @@ def summarize_pmc(paths):
            "traffic_bytes_per_launch": traffic}
     cmd = ("cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
            "-o run -- python3 <repo>/bench.py {a}")
-    lines = ["# HBM traffic of the iteration kernel: config-1 workload (4096 humanoid agents, N=10, "
+    lines = ["# HBM traffic of the iteration kernel: 4096 humanoid agents (N=10, "
              "50 iterations, FP32)", "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of `" + kname + "`, each divided by the "
              "ratio the same counter reads for a plain 1 GiB device copy (`bench.py --calibrate-copy`).",
@@ -193,7 +193,7 @@ def uneven(args):
 
     torch.cuda.set_device(0)
     n = args.agents if args.agents != 4096 else 8192
-    b = synth.config2(n, dtype=np.float32)
+    b = synth.uneven_batch(n, dtype=np.float32)
     plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters)
     prob = mpc.to_device(b, "fp32")
     t_tune = time.perf_counter()
@@ -248,10 +248,10 @@ def mixed(args):
     torch.cuda.set_device(0)
     n = args.agents if args.agents != 4096 else 16384
     kappa = 1e4
-    b = synth.config3(n, kappa=kappa, dtype=np.float32)
+    b = synth.conditioned_humanoid_batch(n, kappa=kappa, dtype=np.float32)
     prob = mpc.to_device(b, "fp32")
     ids = np.arange(0, n, 64)
-    ref = oracle.solve_batch(synth.config3(agent_ids=ids, kappa=kappa), iters=args.iters)
+    ref = oracle.solve_batch(synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa), iters=args.iters)
     sh = b.shapes[0]
     modes = {}
     for prec, sweeps in (("fp32", 0), ("bf16", 0), ("bf16", 3), ("fp16", 0), ("fp16", 3)):
@@ -312,7 +312,7 @@ def serve(args):
 
     torch.cuda.set_device(0)
     nc = args.controllers
-    b = synth.config2(nc)
+    b = synth.uneven_batch(nc)
     prob = mpc.to_device(b, "fp32")
     reqs = mpc.agent_problems(prob, b)
     for r in reqs:
@@ -418,7 +418,7 @@ def main():
 
     torch.cuda.set_device(0)
     shape = synth.humanoid(args.horizon)
-    batch = synth.make_batch([shape] * args.agents, seed=0, config_id=1,
+    batch = synth.make_batch([shape] * args.agents, seed=0, stream_id=1,
                              dtype=np.float64 if args.precision == "fp64" else np.float32)
     plan = mpc.Plan(batch.shapes, precision=args.precision, iters=args.iters, kernel=args.kernel)
     prob = mpc.to_device(batch, args.precision)
@@ -442,7 +442,7 @@ def main():
     torch.cuda.synchronize()
     nchk = min(args.check_agents, args.agents)
     chk_ids = np.linspace(0, args.agents - 1, nchk).astype(int)
-    sub = synth.make_batch([shape] * nchk, seed=0, config_id=1, agent_ids=chk_ids)
+    sub = synth.make_batch([shape] * nchk, seed=0, stream_id=1, agent_ids=chk_ids)
     ref = oracle.solve_batch(sub, iters=args.iters)
     ug = sol["u"].cpu().numpy().reshape(args.agents, -1)[chk_ids].astype(np.float64)
     uo = ref["u"].reshape(nchk, -1)
@@ -493,7 +493,7 @@ def main():
     cpu = None
     if args.cpu_seconds > 0:
         n_s = min(args.agents, 512)
-        cb = synth.make_batch([shape] * n_s, seed=0, config_id=1)
+        cb = synth.make_batch([shape] * n_s, seed=0, stream_id=1)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
         t1 = time.perf_counter()
         steps_done, state, x0 = 0, None, cb.x0.copy()

@@ -14,8 +14,8 @@ and a friction pyramid.  The robot model itself is not available, so the
 stage matrices are random with the documented distributions.
 
 Random streams: every agent owns a PCG64 stream seeded with
-``SeedSequence([seed, config_id, agent_id])``; per-step disturbances use
-``SeedSequence([seed, config_id, agent_id, 1_000_000 + step])``.  Any agent
+``SeedSequence([seed, stream_id, agent_id])``; per-step disturbances use
+``SeedSequence([seed, stream_id, agent_id, 1_000_000 + step])``.  Any agent
 subset therefore reproduces exactly.
 
 Layout (all arrays row-major, agents concatenated in agent order, so a
@@ -77,9 +77,9 @@ def quadruped(N: int = 10) -> Shape:
     return Shape(N=N, nx=36, nu=24, n_tau=12, n_feet=4, foot_dim=3)
 
 
-def agent_rng(seed: int, config_id: int, agent_id: int, *extra: int) -> np.random.Generator:
+def agent_rng(seed: int, stream_id: int, agent_id: int, *extra: int) -> np.random.Generator:
     return np.random.Generator(
-        np.random.PCG64(np.random.SeedSequence([seed, config_id, agent_id, *extra])))
+        np.random.PCG64(np.random.SeedSequence([seed, stream_id, agent_id, *extra])))
 
 
 @dataclasses.dataclass
@@ -98,7 +98,7 @@ class Batch:
     mu: np.ndarray
     stance: np.ndarray
     seed: int = 0
-    config_id: int = 0
+    stream_id: int = 0
     agent_ids: Optional[np.ndarray] = None
 
     @property
@@ -129,7 +129,7 @@ class Batch:
         ids = self.agent_ids if self.agent_ids is not None else np.arange(self.n_agents)
         return Batch(shapes=[self.shapes[a] for a in idx],
                      mu=np.ascontiguousarray(self.mu[list(idx)]),
-                     seed=self.seed, config_id=self.config_id,
+                     seed=self.seed, stream_id=self.stream_id,
                      agent_ids=np.asarray([ids[a] for a in idx], dtype=np.int64),
                      **{k: np.ascontiguousarray(np.concatenate(v)) for k, v in parts.items()})
 
@@ -183,11 +183,11 @@ def _draw_agent(rng, s: Shape, *, stance_p, q_log, r_log, r_scale, dt=DT):
     return A, B, c, q, r, x_ref, x0, tau_max, mu, stance
 
 
-def make_batch(shapes: Sequence[Shape], *, seed: int = 0, config_id: int = 0,
+def make_batch(shapes: Sequence[Shape], *, seed: int = 0, stream_id: int = 0,
                agent_ids: Optional[Sequence[int]] = None, stance_p: Optional[float] = 0.6,
                q_log=(-2.0, 2.0), r_log=(-4.0, -1.0), r_scale: float = 1.0,
                dtype=np.float64) -> Batch:
-    """Draw a batch; agent ``i`` uses stream (seed, config_id, agent_ids[i])."""
+    """Draw a batch; agent ``i`` uses stream (seed, stream_id, agent_ids[i])."""
     shapes = list(shapes)
     if agent_ids is None:
         agent_ids = range(len(shapes))
@@ -198,7 +198,7 @@ def make_batch(shapes: Sequence[Shape], *, seed: int = 0, config_id: int = 0,
     stance = np.empty(int(off["stance"][-1]), dtype=np.uint8)
     mu = np.empty(len(shapes), dtype=dtype)
     for i, (s, aid) in enumerate(zip(shapes, agent_ids)):
-        rng = agent_rng(seed, config_id, int(aid))
+        rng = agent_rng(seed, stream_id, int(aid))
         A, B, c, q, r, x_ref, x0, tau_max, m_, st = _draw_agent(
             rng, s, stance_p=stance_p, q_log=q_log, r_log=r_log, r_scale=r_scale)
         for k, v in (("A", A), ("B", B), ("c", c), ("q", q), ("r", r), ("x_ref", x_ref),
@@ -206,58 +206,58 @@ def make_batch(shapes: Sequence[Shape], *, seed: int = 0, config_id: int = 0,
             out[k][off[k][i]:off[k][i + 1]] = v.ravel()
         stance[off["stance"][i]:off["stance"][i + 1]] = st.ravel()
         mu[i] = m_
-    return Batch(shapes=shapes, stance=stance, mu=mu, seed=seed, config_id=config_id,
+    return Batch(shapes=shapes, stance=stance, mu=mu, seed=seed, stream_id=stream_id,
                  agent_ids=agent_ids, **out)
 
 
 # --- the five benchmark configurations -------------------------------------------------
 
-def config0(n_agents: int = 64, seed: int = 0, agent_ids=None, dtype=np.float64) -> Batch:
+def small_humanoid_batch(n_agents: int = 64, seed: int = 0, agent_ids=None, dtype=np.float64) -> Batch:
     """64 humanoid agents, N=10, stance Bernoulli(0.6), solved in FP64 for 50 iterations."""
     ids = range(n_agents) if agent_ids is None else agent_ids
-    return make_batch([humanoid(10)] * len(list(ids)), seed=seed, config_id=0,
+    return make_batch([humanoid(10)] * len(list(ids)), seed=seed, stream_id=0,
                       agent_ids=ids, dtype=dtype)
 
 
-def config1(n_agents: int = 4096, seed: int = 0, agent_ids=None, dtype=np.float64) -> Batch:
-    """RL-training shape: config-0 generator at 4096 humanoid agents, N=10."""
+def humanoid_batch(n_agents: int = 4096, seed: int = 0, agent_ids=None, dtype=np.float64) -> Batch:
+    """RL-training shape: the small batch's generator at 4096 humanoid agents, N=10."""
     ids = range(n_agents) if agent_ids is None else agent_ids
-    return make_batch([humanoid(10)] * len(list(ids)), seed=seed, config_id=1,
+    return make_batch([humanoid(10)] * len(list(ids)), seed=seed, stream_id=1,
                       agent_ids=ids, dtype=dtype)
 
 
-def config2_shapes(n_agents: int = 8192, seed: int = 0, config_id: int = 2,
+def uneven_batch_shapes(n_agents: int = 8192, seed: int = 0, stream_id: int = 2,
                    agent_ids=None) -> List[Shape]:
     """Uneven batch: N ~ U{5..20}, 50/50 humanoid / quadruped, from a per-agent stream."""
     ids = range(n_agents) if agent_ids is None else agent_ids
     shapes = []
     for aid in ids:
-        rng = agent_rng(seed, config_id, int(aid), 7)
+        rng = agent_rng(seed, stream_id, int(aid), 7)
         kind = rng.integers(0, 2)
         N = int(rng.integers(5, 21))
         shapes.append(humanoid(N) if kind == 0 else quadruped(N))
     return shapes
 
 
-def config2(n_agents: int = 8192, seed: int = 0, agent_ids=None, dtype=np.float64,
-            config_id: int = 2) -> Batch:
+def uneven_batch(n_agents: int = 8192, seed: int = 0, agent_ids=None, dtype=np.float64,
+            stream_id: int = 2) -> Batch:
     ids = list(range(n_agents) if agent_ids is None else agent_ids)
-    shapes = config2_shapes(seed=seed, config_id=config_id, agent_ids=ids)
-    return make_batch(shapes, seed=seed, config_id=config_id, agent_ids=ids,
+    shapes = uneven_batch_shapes(seed=seed, stream_id=stream_id, agent_ids=ids)
+    return make_batch(shapes, seed=seed, stream_id=stream_id, agent_ids=ids,
                       stance_p=None, dtype=dtype)
 
 
-def config3(n_agents: int = 16384, kappa: float = 1e4, seed: int = 0, agent_ids=None,
+def conditioned_humanoid_batch(n_agents: int = 16384, kappa: float = 1e4, seed: int = 0, agent_ids=None,
             dtype=np.float64) -> Batch:
     """Mixed-precision sweep: humanoid N=16, Q and R with condition number ``kappa``.
 
     Q = diag(10^U[-h, h]) and R = 3.16e-3 * diag(10^U[-h, h]) with h = log10(kappa)/2,
-    centred on the geometric means of the config-0 draws (1 and 10^-2.5).
+    centred on the geometric means of the small humanoid batch's draws (1 and 10^-2.5).
     """
     ids = range(n_agents) if agent_ids is None else agent_ids
     h = 0.5 * np.log10(kappa)
     cid = 300 + int(round(np.log10(kappa)))
-    return make_batch([humanoid(16)] * len(list(ids)), seed=seed, config_id=cid,
+    return make_batch([humanoid(16)] * len(list(ids)), seed=seed, stream_id=cid,
                       agent_ids=ids, q_log=(-h, h), r_log=(-h, h), r_scale=10 ** -2.5,
                       dtype=dtype)
 
@@ -267,6 +267,6 @@ def step_noise(batch: Batch, step: int, std: float = 1e-2) -> np.ndarray:
     ids = batch.agent_ids if batch.agent_ids is not None else np.arange(batch.n_agents)
     parts = []
     for s, aid in zip(batch.shapes, ids):
-        rng = agent_rng(batch.seed, batch.config_id, int(aid), 1_000_000 + step)
+        rng = agent_rng(batch.seed, batch.stream_id, int(aid), 1_000_000 + step)
         parts.append(rng.standard_normal(s.nx) * std)
     return np.concatenate(parts)

@@ -91,7 +91,7 @@ def test_agent_problem_records_point_into_the_pool():
     """Per-request records of a served controller address its slice of a pool
     batch (checked on host tensors: only pointer arithmetic is involved)."""
     torch = pytest.importorskip("torch")
-    b = synth.config2(7)
+    b = synth.uneven_batch(7)
     prob = {k: torch.from_numpy(v.astype(np.float32) if v.dtype != np.uint8 else v)
             for k, v in (("A", b.A), ("B", b.B), ("c", b.c), ("q", b.q), ("r", b.r),
                          ("x_ref", b.x_ref), ("x0", b.x0), ("tau_max", b.tau_max),

@@ -28,7 +28,7 @@ def _need_gpu():
 
 
 def test_groups_of_uneven_batch():
-    b = synth.config2(256)
+    b = synth.uneven_batch(256)
     g, plan, _ = run_gpu(b, "fp32")
     groups = plan.groups()
     assert sum(x["n_agents"] for x in groups) == 256
@@ -51,7 +51,7 @@ def test_groups_of_uneven_batch():
 @pytest.mark.parametrize("precision,kernel", [("fp32", "auto"), ("fp64", "auto"),
                                               ("fp32", "generic")])
 def test_autotune_keeps_parity(precision, kernel):
-    b = synth.config2(128)
+    b = synth.uneven_batch(128)
     plan = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
     prob = mpc.to_device(b, precision)
     groups = plan.autotune(prob, reps=2)
@@ -77,7 +77,7 @@ def test_graph_replay_matches_eager(which):
     """A captured control step (warm solve + plant step) replayed several times,
     with unrelated eager work and synchronisations between replays, gives
     bit-identical results to the same steps issued eagerly."""
-    b = synth.config1(64) if which == "uniform" else synth.config2(96)
+    b = synth.humanoid_batch(64) if which == "uniform" else synth.uneven_batch(96)
     nx_tot = sum(s.nx for s in b.shapes)
     pe = mpc.Plan(b.shapes, precision="fp32", iters=50)
     pg = mpc.Plan(b.shapes, precision="fp32", iters=50)
@@ -110,18 +110,18 @@ def test_graph_replay_matches_eager(which):
 
 
 def test_replay_without_capture_is_not_ready():
-    b = synth.config0(4)
+    b = synth.small_humanoid_batch(4)
     plan = mpc.Plan(b.shapes, precision="fp32")
     with pytest.raises(mpc.MPCError) as ei:
         plan.replay()
     assert ei.value.code == mpc.MPC_ERR_NOT_READY
 
 
-def test_config2_full_size_sampled():
+def test_uneven_8192_sampled():
     """The uneven batch at full size (8192 agents) in the benchmark's launch
     configuration: autotuned groups, one captured step replayed; every 64th
     agent is checked against the oracle (cold start)."""
-    b = synth.config2(8192, dtype=np.float32)
+    b = synth.uneven_batch(8192, dtype=np.float32)
     plan = mpc.Plan(b.shapes, precision="fp32", iters=50)
     prob = mpc.to_device(b, "fp32")
     groups = plan.autotune(prob, reps=1)
@@ -132,10 +132,10 @@ def test_config2_full_size_sampled():
     g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
     assert np.all(g["status"] == 0)
     ids = np.arange(0, 8192, 64)
-    sub = synth.config2(agent_ids=ids)
+    sub = synth.uneven_batch(agent_ids=ids)
     o = oracle.solve_batch(sub, iters=50)
     o["_off"] = sub.offsets()
     e = agent_errors(b, g, o, agents=ids, go=np.arange(len(ids)))
-    print("config2 sampled: max u0/traj", e[:, :2].max(axis=0), "horizons",
+    print("uneven_batch sampled: max u0/traj", e[:, :2].max(axis=0), "horizons",
           sorted({b.shapes[i].N for i in ids}))
     assert e[:, :2].max() < TOL["fp32"]

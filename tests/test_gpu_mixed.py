@@ -45,8 +45,8 @@ def _solve(b, precision, sweeps):
 @pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
 def test_mixed_precision_error_table(kappa):
     ids = np.arange(0, 16384, 256)  # 64 agents of the 16384-agent sweep
-    b = synth.config3(agent_ids=ids, kappa=kappa, dtype=np.float32)
-    o = oracle.solve_batch(synth.config3(agent_ids=ids, kappa=kappa), iters=50)
+    b = synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa, dtype=np.float32)
+    o = oracle.solve_batch(synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa), iters=50)
     rows = []
     for precision in ("bf16", "fp16"):
         errs = {}
@@ -71,8 +71,8 @@ def test_mixed_precision_error_table(kappa):
 
 def test_mixed_precision_warm_closed_loop():
     """Warm-started steps of the mixed plan track the FP64 oracle from the same warm state."""
-    b = synth.config3(agent_ids=np.arange(0, 16384, 512), kappa=1e4, dtype=np.float32)
-    b64 = synth.config3(agent_ids=np.arange(0, 16384, 512), kappa=1e4)
+    b = synth.conditioned_humanoid_batch(agent_ids=np.arange(0, 16384, 512), kappa=1e4, dtype=np.float32)
+    b64 = synth.conditioned_humanoid_batch(agent_ids=np.arange(0, 16384, 512), kappa=1e4)
     plan = mpc.Plan(b.shapes, precision="fp16", iters=50)
     prob = mpc.to_device(b, "fp32")
     o = oracle.solve_batch(b64, iters=50)
@@ -90,7 +90,7 @@ def test_mixed_precision_warm_closed_loop():
 
 
 def test_mixed_precision_failures_stay_local():
-    b = synth.config3(agent_ids=np.arange(6), kappa=1e2, dtype=np.float32)
+    b = synth.conditioned_humanoid_batch(agent_ids=np.arange(6), kappa=1e2, dtype=np.float32)
     off = b.offsets()
     b.A[off["A"][2] + 5] = np.nan
     b.r[off["r"][4]:off["r"][5]] = -5.0

@@ -64,8 +64,8 @@ def agent_errors(batch, g, o, agents=None, go=None):
     return np.array(errs)
 
 
-def test_config0_fp64_every_agent():
-    b = synth.config0(64)
+def test_small_humanoid_fp64_every_agent():
+    b = synth.small_humanoid_batch(64)
     g, plan, _ = run_gpu(b, "fp64")
     o = oracle.solve_batch(b, iters=50)
     assert np.all(g["status"] == 0)
@@ -82,8 +82,8 @@ def test_config0_fp64_every_agent():
 
 
 @pytest.mark.parametrize("kernel", ["generic", "fused"])
-def test_config0_fp32_every_agent(kernel):
-    b = synth.config0(64)
+def test_small_humanoid_fp32_every_agent(kernel):
+    b = synth.small_humanoid_batch(64)
     g, plan, _ = run_gpu(b, "fp32", kernel=kernel)
     assert plan.config()["kernel"] == kernel
     o = oracle.solve_batch(b, iters=50)
@@ -95,7 +95,7 @@ def test_config0_fp32_every_agent(kernel):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_uneven_batch(precision):
-    b = synth.config2(96)
+    b = synth.uneven_batch(96)
     g, plan, _ = run_gpu(b, precision)
     o = oracle.solve_batch(b, iters=50)
     assert np.all(g["status"] == 0)
@@ -111,7 +111,7 @@ def test_uneven_batch(precision):
 ])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_edge_shapes(shape, precision):
-    b = synth.make_batch([shape] * 5, seed=1, config_id=50)
+    b = synth.make_batch([shape] * 5, seed=1, stream_id=50)
     g, plan, _ = run_gpu(b, precision, iters=30)
     o = oracle.solve_batch(b, iters=30)
     assert np.all(g["status"] == 0)
@@ -120,7 +120,7 @@ def test_edge_shapes(shape, precision):
 
 @pytest.mark.parametrize("pattern", ["all_stance", "all_swing"])
 def test_contact_extremes(pattern):
-    b = synth.config0(8)
+    b = synth.small_humanoid_batch(8)
     b.stance[:] = 1 if pattern == "all_stance" else 0
     g, _, _ = run_gpu(b, "fp64")
     o = oracle.solve_batch(b, iters=50)
@@ -128,7 +128,7 @@ def test_contact_extremes(pattern):
 
 
 def test_failures_stay_local():
-    b = synth.config0(6)
+    b = synth.small_humanoid_batch(6)
     o_ = b.offsets()
     b.A[o_["A"][2] + 17] = np.nan
     b.r[o_["r"][4]:o_["r"][5]] = -5.0
@@ -145,7 +145,7 @@ def test_failures_stay_local():
 @pytest.mark.parametrize("kernel", ["generic", "fused"])
 def test_batch_invariance(kernel):
     """An agent's result does not depend on which agents share the launch."""
-    full = synth.config0(32)
+    full = synth.small_humanoid_batch(32)
     sub = full.subset([3, 17, 30])
     gf, _, _ = run_gpu(full, "fp32", kernel=kernel)
     gs, _, _ = run_gpu(sub, "fp32", kernel=kernel)
@@ -163,7 +163,7 @@ def test_closed_loop_warm_start(precision, kernel):
     starts from the oracle's previous (u, z, y) and the oracle's x0, so both
     sides solve the same QP from the same point.  The drift of a GPU loop that
     warm-starts from its own iterates is reported alongside."""
-    b = synth.config1(128)
+    b = synth.humanoid_batch(128)
     plan = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
     own = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
     prob = mpc.to_device(b, precision)
@@ -198,7 +198,7 @@ def test_closed_loop_warm_start(precision, kernel):
 
 
 def test_warm_state_import():
-    b = synth.config0(16)
+    b = synth.small_humanoid_batch(16)
     o1 = oracle.solve_batch(b, iters=20)
     o2 = oracle.solve_batch(b, iters=20, warm={k: o1[k] for k in ("u", "z", "y")})
     g, _, _ = run_gpu(b, "fp64", iters=20, warm={k: o1[k] for k in ("u", "z", "y")})
@@ -206,7 +206,7 @@ def test_warm_state_import():
 
 
 def test_timing_and_config():
-    b = synth.config0(16)
+    b = synth.small_humanoid_batch(16)
     plan = mpc.Plan(b.shapes, precision="fp32")
     prob = mpc.to_device(b, "fp32")
     plan.set_timing(True)
@@ -218,7 +218,7 @@ def test_timing_and_config():
 
 
 def test_api_errors_on_device():
-    b = synth.config0(4)
+    b = synth.small_humanoid_batch(4)
     plan = mpc.Plan(b.shapes, precision="fp32")
     with pytest.raises(mpc.MPCError) as ei:
         plan.get_solution()
@@ -230,26 +230,26 @@ def test_api_errors_on_device():
 
 
 @pytest.mark.parametrize("kernel", ["auto", "generic"])
-def test_config1_full_size_sampled(kernel):
+def test_humanoid_4096_sampled(kernel):
     """4096 humanoid agents (the benchmark's batch and launch configuration),
     FP32, cold start; every 16th agent is checked against the oracle."""
-    b = synth.config1(4096, dtype=np.float32)
+    b = synth.humanoid_batch(4096, dtype=np.float32)
     g, plan, _ = run_gpu(b, "fp32", kernel=kernel)
     assert np.all(g["status"] == 0)
     ids = np.arange(0, 4096, 16)
-    sub = synth.config1(agent_ids=ids)
+    sub = synth.humanoid_batch(agent_ids=ids)
     o = oracle.solve_batch(sub, iters=50)
     e = agent_errors(b, g, o, agents=ids, go=np.arange(len(ids)))
     o["_off"] = sub.offsets()
     e = agent_errors(b, g, o, agents=ids, go=np.arange(len(ids)))
-    print("config1 sampled: kernel", plan.config()["kernel"], "max u0/traj", e[:, :2].max(axis=0),
+    print("humanoid_batch sampled: kernel", plan.config()["kernel"], "max u0/traj", e[:, :2].max(axis=0),
           "p99", np.percentile(e[:, :2], 99, axis=0))
     assert e[:, :2].max() < TOL["fp32"]
 
 
 @pytest.mark.parametrize("kernel", ["generic", "fused"])
 def test_quadruped_uniform_fp32(kernel):
-    b = synth.make_batch([synth.quadruped(8)] * 24, seed=3, config_id=51, stance_p=None)
+    b = synth.make_batch([synth.quadruped(8)] * 24, seed=3, stream_id=51, stance_p=None)
     g, plan, _ = run_gpu(b, "fp32", kernel=kernel)
     assert plan.config()["kernel"] == kernel
     o = oracle.solve_batch(b, iters=50)
@@ -263,7 +263,7 @@ def test_fused_horizon_limits():
     for N, want in ((1, "fused"), (11, "fused"), (12, "fused"), (20, "fused"), (21, "generic")):
         plan = mpc.Plan([synth.humanoid(N)] * 2, precision="fp32")
         assert plan.config()["kernel"] == want, N
-    b = synth.make_batch([synth.humanoid(1)] * 4, seed=2, config_id=52)
+    b = synth.make_batch([synth.humanoid(1)] * 4, seed=2, stream_id=52)
     g, plan, _ = run_gpu(b, "fp32", kernel="fused")
     o = oracle.solve_batch(b, iters=50)
     assert agent_errors(b, g, o)[:, :2].max() < TOL["fp32"]
@@ -273,7 +273,7 @@ def test_fused_horizon_limits():
                                               ("fp32", "fused")])
 def test_input_reference(precision, kernel):
     """A nonzero input reference ubar_k (cost (u - ubar)' R (u - ubar)) on every path."""
-    b = synth.config0(12)
+    b = synth.small_humanoid_batch(12)
     rng = np.random.default_rng(17)
     uref = rng.standard_normal(b.offsets()["u"][-1]) * 5.0
     plan = mpc.Plan(b.shapes, precision=precision, iters=50, kernel=kernel)
@@ -292,7 +292,7 @@ def test_input_reference(precision, kernel):
 
 @pytest.mark.parametrize("precision,kernel", [("fp64", "auto"), ("fp32", "fused")])
 def test_single_iteration(precision, kernel):
-    b = synth.config0(8)
+    b = synth.small_humanoid_batch(8)
     g, _, _ = run_gpu(b, precision, iters=1, kernel=kernel)
     o = oracle.solve_batch(b, iters=1)
     assert agent_errors(b, g, o)[:, :2].max() < TOL[precision]
@@ -302,7 +302,7 @@ def test_largest_supported_horizon():
     """The longest humanoid horizon whose generic iteration workspace fits the
     device's LDS solves to the FP64 tolerance; one stage more is rejected."""
     big = synth.humanoid(43)
-    b = synth.make_batch([big] * 3, seed=4, config_id=53)
+    b = synth.make_batch([big] * 3, seed=4, stream_id=53)
     g, _, _ = run_gpu(b, "fp64", iters=20)
     o = oracle.solve_batch(b, iters=20)
     assert np.all(g["status"] == 0)
@@ -321,7 +321,7 @@ def test_fused_every_horizon_both_shapes(lo, hi):
     operators from HBM in a horizon-dependent order."""
     shapes = ([synth.humanoid(N) for N in range(lo, hi + 1)]
               + [synth.quadruped(N) for N in range(lo, hi + 1)])
-    b = synth.make_batch(shapes, seed=4, config_id=61)
+    b = synth.make_batch(shapes, seed=4, stream_id=61)
     g, plan, prob = run_gpu(b, "fp32", kernel="fused")
     assert plan.config()["kernel"] == "fused"
     o = oracle.solve_batch(b, iters=50)

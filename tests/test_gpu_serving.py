@@ -42,7 +42,7 @@ def _plan_u0(batch, prob, steps):
 
 
 def test_server_matches_plan_and_oracle():
-    b = synth.config2(64)
+    b = synth.uneven_batch(64)
     prob = mpc.to_device(b, "fp32")
     want = _plan_u0(b, prob, 2)
     srv = mpc.Server(precision="fp32", max_batch=16, max_inflight=2)
@@ -78,7 +78,7 @@ def test_server_matches_plan_and_oracle():
 def test_alone_vs_mix():
     """A controller's sequence of warm-started results is the same alone and
     amid other controllers arriving at random times."""
-    b = synth.config2(160)
+    b = synth.uneven_batch(160)
     prob = mpc.to_device(b, "fp32")
     reqs = mpc.agent_problems(prob, b)
     watch = [3, 77, 150]
@@ -119,7 +119,7 @@ def test_alone_vs_mix():
 
 
 def test_small_budget_evicts_and_completes():
-    b = synth.config2(48)
+    b = synth.uneven_batch(48)
     prob = mpc.to_device(b, "fp32")
     reqs = mpc.agent_problems(prob, b)
     cold = _plan_u0(b, prob, 1)[0]
@@ -143,7 +143,7 @@ def test_small_budget_evicts_and_completes():
 
 def test_server_rejects_bad_requests():
     srv = mpc.Server(precision="fp32", hbm_budget_bytes=1 << 20, max_batch=4)
-    b = synth.config0(2)
+    b = synth.small_humanoid_batch(2)
     prob = mpc.to_device(b, "fp32")
     reqs = mpc.agent_problems(prob, b)
     buf = torch.empty(30, device="cuda")
@@ -151,7 +151,7 @@ def test_server_rejects_bad_requests():
     with pytest.raises(mpc.MPCError):  # a controller keeps its shape
         srv.submit(0, synth.humanoid(5), reqs[0], buf)
     big = synth.make_batch([synth.Shape(N=64, nx=64, nu=32, n_tau=8, n_feet=4, foot_dim=6)],
-                           seed=1, config_id=60)
+                           seed=1, stream_id=60)
     pb = mpc.to_device(big, "fp32")
     with pytest.raises(mpc.MPCError) as ei:  # one request exceeds the 1 MiB budget
         srv.submit(1, big.shapes[0], mpc.agent_problems(pb, big)[0], buf)
@@ -163,7 +163,7 @@ def test_supersede_drops_waiting_requests():
     """With supersede, a request still waiting when a newer one of its
     controller arrives completes unsolved (status SUPERSEDED, output untouched,
     never polled); the newer one runs warm-started from the last solved one."""
-    b = synth.config2(8)
+    b = synth.uneven_batch(8)
     prob = mpc.to_device(b, "fp32")
     reqs = mpc.agent_problems(prob, b)
     want = _plan_u0(b, prob, 2)  # cold, then warm-started

@@ -20,7 +20,7 @@ def tiny_shape(N=2, nx=3):
 
 
 def one_agent(shape, seed=0, **over):
-    b = synth.make_batch([shape], seed=seed, config_id=99)
+    b = synth.make_batch([shape], seed=seed, stream_id=99)
     ag = oracle.agent(b, 0)
     ag.update(over)
     return ag
@@ -301,10 +301,10 @@ def test_invariants_every_iteration():
         assert o["res"][2] < 1e-12 * max(1.0, np.abs(x).max())
 
 
-def test_config0_agent_converges_to_kkt_tolerance():
+def test_small_humanoid_agent_converges_to_kkt_tolerance():
     """Converge mode on a full humanoid agent reaches KKT, complementarity and
     dynamics residuals below 1e-9."""
-    b = synth.config0(1)
+    b = synth.small_humanoid_batch(1)
     ag = oracle.agent(b, 0)
     out = oracle.solve(*args(ag), iters=0, tol=1e-12, max_iters=400_000)
     assert out["status"] == oracle.CONVERGED, out["iters"]
@@ -314,7 +314,7 @@ def test_config0_agent_converges_to_kkt_tolerance():
 # --- failure handling and batching ---------------------------------------------------------
 
 def test_batch_equals_single_and_failures_stay_local():
-    b = synth.config0(6)
+    b = synth.small_humanoid_batch(6)
     b.A[b.offsets()["A"][2] + 17] = np.nan  # agent 2: NaN in A
     o = b.offsets()
     b.r[o["r"][4]:o["r"][5]] = -5.0  # agent 4: indefinite R
@@ -327,8 +327,8 @@ def test_batch_equals_single_and_failures_stay_local():
 
 
 def test_subset_reproduces_agents():
-    b = synth.config0(8)
-    sub = synth.config0(agent_ids=[5, 2])
+    b = synth.small_humanoid_batch(8)
+    sub = synth.small_humanoid_batch(agent_ids=[5, 2])
     full = oracle.solve_batch(b, iters=10)
     part = oracle.solve_batch(sub, iters=10)
     o, p = b.offsets(), sub.offsets()

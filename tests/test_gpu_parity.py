@@ -335,3 +335,38 @@ def test_fused_every_horizon_both_shapes(lo, hi):
     o2 = oracle.solve_batch(b, iters=50, warm={k: o[k] for k in ("u", "z", "y")})
     e2 = agent_errors(b, g2, o2)
     assert np.all(g2["status"] == 0) and e2[:, :2].max() < TOL["fp32"]
+
+
+def _long_horizon_batch(n, seed):
+    """Humanoid and quadruped agents at horizons the streaming iteration kernel serves."""
+    shapes = [synth.humanoid(N) if i % 2 == 0 else synth.quadruped(N)
+              for i, N in enumerate([12, 13, 16, 19, 20, 14][:n])]
+    return synth.make_batch(shapes, seed=seed, stream_id=62)
+
+
+@pytest.mark.parametrize("iters", [1, 2, 7])
+def test_streaming_kernel_few_iterations(iters):
+    """The streaming kernel's operator sequence (prologue, then 2N-6 ring
+    elements per iteration) at iteration counts where the loader ends early."""
+    b = _long_horizon_batch(6, seed=8)
+    g, plan, _ = run_gpu(b, "fp32", iters=iters, kernel="fused")
+    assert plan.config()["kernel"] == "fused"
+    o = oracle.solve_batch(b, iters=iters)
+    assert np.all(g["status"] == 0)
+    assert agent_errors(b, g, o)[:, :2].max() < TOL["fp32"]
+
+
+def test_streaming_kernel_failures_stay_local():
+    """A non-finite input and a non-convex stage Hessian on long horizons stop
+    only their own agents; the neighbours in the same streaming launch match
+    the oracle."""
+    b = _long_horizon_batch(6, seed=9)
+    o_ = b.offsets()
+    b.A[o_["A"][2] + 17] = np.nan
+    b.r[o_["r"][4]:o_["r"][5]] = -5.0
+    g, _, _ = run_gpu(b, "fp32", kernel="fused")
+    o = oracle.solve_batch(b, iters=50)
+    assert g["status"].tolist() == o["status"].tolist() == [0, 0, 3, 0, 2, 0]
+    e = agent_errors(b, g, o, agents=[0, 1, 3, 5])
+    assert e[:, :2].max() < TOL["fp32"]
+    assert np.all(np.isnan(g["u"][o_["u"][2]:o_["u"][3]]))

@@ -288,10 +288,9 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
 
   for (int i = tid; i < riccati_lds_bytes<NX, NU>() / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
-  // non-finite inputs mark the agent and stop it
+  // non-finite inputs mark the agent and stop it (A_k and B_k are checked as
+  // each stage's prefetch lands, below)
   bool ok = isfinite(muf);
-  for (int i = tid; i < N * NX * NX; i += nt) ok &= (bool)isfinite(A[i]);
-  for (int i = tid; i < N * NX * NU; i += nt) ok &= (bool)isfinite(B[i]);
   for (int i = tid; i < N * NX; i += nt) ok &= (bool)isfinite(c[i]);
   for (int i = tid; i < (N + 1) * NX; i += nt) ok &= (bool)isfinite(in.xr[d.oxr + i]);
   for (int i = tid; i < NX; i += nt) ok &= (bool)isfinite(q[i]) && (bool)isfinite(in.x0[d.ox0 + i]);
@@ -322,16 +321,24 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   };
   prefetch(N - 1);
   for (int k = N - 1; k >= 0; --k) {
+    bool fin = true;
 #pragma unroll
     for (int t = 0; t < PFA; ++t) {
       const int i = tid + t * kT;
-      if (i < NX * NX) Ak[(i / NX) * LX + i % NX] = (double)pfa[t];
+      if (i < NX * NX) {
+        Ak[(i / NX) * LX + i % NX] = (double)pfa[t];
+        fin &= (bool)isfinite(pfa[t]);
+      }
     }
 #pragma unroll
     for (int t = 0; t < PFB; ++t) {
       const int i = tid + t * kT;
-      if (i < NX * NU) Bk[(i / NU) * LU + i % NU] = pfb[t];
+      if (i < NX * NU) {
+        Bk[(i / NU) * LU + i % NU] = pfb[t];
+        fin &= (bool)isfinite(pfb[t]);
+      }
     }
+    if (!fin) atomicOr(flag, 1);
     if (k > 0) prefetch(k - 1);
     for (int i = tid; i < M; i += nt) {
       double lo, hi;
@@ -344,6 +351,10 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     }
     for (int i = tid; i < NX; i += nt) ck[i] = (double)c[(int64_t)k * NX + i];
     __syncthreads();
+    if (flag[0]) {  // a non-finite A_k or B_k (every thread reads the same flag)
+      if (tid == 0) status[agent] = AGENT_NONFINITE;
+      return;
+    }
     for (int j = tid; j < NUT; j += nt)
       rdg[j] = j < NU ? rtilde_diag<double, double>(d, j, (double)r[j], mu, rhok, sc) : 1.0;
     // PB = P B_k (NXT x NUT) and PA = P A_k (NXT x NXT); s_k = P c_k
@@ -626,7 +637,7 @@ __device__ inline void flag_wait(int* f, int n, int v, int* abort, int lane) {
 
 struct IterLds {
   int acl, xtf, ppf, gf, ef, sf, cf;                               // float
-  int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd, bvd;  // double
+  int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd;  // double
   int flag, sync, total;
 };
 
@@ -662,7 +673,6 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
   L.qd = take(8 * S::NXP);
   L.xrd = take(8 * (N + 1) * S::NXP);
   L.qtd = take(8 * N * S::NXP);
-  L.bvd = take(8 * S::NXP);
   L.flag = take(16);
   L.sync = take(4 * kSyncInts);
   L.total = o;
@@ -734,6 +744,77 @@ __device__ inline void load_chain_op(float (&M)[4 * AQ], const float4* acl4, int
   }
 }
 
+// x^0 = rollout of the exact dynamics x_{k+1} = A_k x_k + B_k u_k + c_k from x_0
+// under u^0, by the whole workgroup: quad qq owns state row qq (its lanes every
+// fourth column), the rows of stages k+1..k+3 are in flight while stage k is
+// summed.  xd [N+1][NXP] (x_0 set) and ud [N][NUP] in LDS; one barrier per stage.
+template <int NX, int NU>
+__device__ inline void rollout_exact(const float* __restrict__ A, const float* __restrict__ B,
+                                     const float* __restrict__ c, double* xd, const double* ud, int N,
+                                     int tid, int nt) {
+  using S = FS<NX, NU>;
+  constexpr int NXP = S::NXP, NUP = S::NUP;
+  constexpr int TA = (NX + 3) / 4, TB = (NU + 3) / 4;
+  const int qq = tid >> 2, sub = tid & 3;
+  if ((nt >> 2) < NX) {
+    // a workgroup with fewer quads than state rows (the shortest horizons):
+    // rows in turn, nothing prefetched
+    for (int kk = 0; kk < N; ++kk) {
+      for (int r = qq; r < NX; r += nt >> 2) {
+        const float* Ar = A + ((int64_t)kk * NX + r) * NX;
+        const float* Br = B + ((int64_t)kk * NX + r) * NU;
+        double acc = 0.0;
+        for (int t = sub; t < NX; t += 4) acc += (double)Ar[t] * xd[kk * NXP + t];
+        for (int t = sub; t < NU; t += 4) acc += (double)Br[t] * ud[kk * NUP + t];
+        acc = quad_sum(acc);
+        if (sub == 0) xd[(kk + 1) * NXP + r] = (double)c[(int64_t)kk * NX + r] + acc;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  const bool row = qq < NX;
+  auto load = [&](float (&a)[TA], float (&b)[TB], float& cv, int kk) __attribute__((always_inline)) {
+    const float* Ar = A + ((int64_t)kk * NX + (row ? qq : 0)) * NX;
+    const float* Br = B + ((int64_t)kk * NX + (row ? qq : 0)) * NU;
+#pragma unroll
+    for (int t = 0; t < TA; ++t) a[t] = (row && sub + 4 * t < NX) ? Ar[sub + 4 * t] : 0.f;
+#pragma unroll
+    for (int t = 0; t < TB; ++t) b[t] = (row && sub + 4 * t < NU) ? Br[sub + 4 * t] : 0.f;
+    cv = row ? c[(int64_t)kk * NX + qq] : 0.f;
+  };
+  auto step = [&](const float (&a)[TA], const float (&b)[TB], float cv, int kk) __attribute__((always_inline)) {
+    if (row) {
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < TA; ++t)
+        if (sub + 4 * t < NX) acc += (double)a[t] * xd[kk * NXP + sub + 4 * t];
+#pragma unroll
+      for (int t = 0; t < TB; ++t)
+        if (sub + 4 * t < NU) acc += (double)b[t] * ud[kk * NUP + sub + 4 * t];
+      acc = quad_sum(acc);
+      if (sub == 0) xd[(kk + 1) * NXP + qq] = (double)cv + acc;
+    }
+    __syncthreads();
+  };
+  float a0[TA], b0[TB], a1[TA], b1[TB], a2[TA], b2[TB], c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  load(a0, b0, c0, 0);
+  if (N > 1) load(a1, b1, c1, 1);
+  if (N > 2) load(a2, b2, c2, 2);
+  for (int kk = 0; kk < N; kk += 3) {
+    step(a0, b0, c0, kk);
+    if (kk + 3 < N) load(a0, b0, c0, kk + 3);
+    if (kk + 1 < N) {
+      step(a1, b1, c1, kk + 1);
+      if (kk + 4 < N) load(a1, b1, c1, kk + 4);
+    }
+    if (kk + 2 < N) {
+      step(a2, b2, c2, kk + 2);
+      if (kk + 5 < N) load(a2, b2, c2, kk + 5);
+    }
+  }
+}
+
 // Stage wavefront k (k < N) keeps K_k, B_k and H_k^{-1} in registers and runs
 // everything that is independent across stages; the chain wavefront (the
 // last one) runs both serial chains alone, streaming A_cl,k from LDS one stage
@@ -792,7 +873,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   double* qd = reinterpret_cast<double*>(sm + L.qd);
   double* xrd = reinterpret_cast<double*>(sm + L.xrd);
   double* qtd = reinterpret_cast<double*>(sm + L.qtd);
-  double* bvd = reinterpret_cast<double*>(sm + L.bvd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
 
@@ -807,16 +887,30 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   const double mu = (double)in.mu[d.omu];
 
   // per-agent vectors into LDS (padding zero), A_cl of every stage into LDS
-  for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
-  __syncthreads();
+  // (which it fills whole: the zeroing starts past it), eight float4 loads in
+  // flight per thread
+  for (int i = L.xtf / 4 + tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   {
-    const float4* src = reinterpret_cast<const float4*>(fws + d.ofw);
-    float4* dst = reinterpret_cast<float4*>(sm + L.acl);
-    for (int i = tid; i < N * AQ * 64; i += nt) {
-      const int kk = i / (AQ * 64);
-      dst[i] = src[(int64_t)kk * SLOTS * 16 + (i - kk * AQ * 64)];
+    const f4* src = reinterpret_cast<const f4*>(fws + d.ofw);
+    f4* dst = reinterpret_cast<f4*>(sm + L.acl);
+    const int total = N * AQ * 64;
+    constexpr int kBatch = 8;
+    for (int i0 = tid; i0 < total; i0 += kBatch * nt) {
+      f4 v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int i = i0 + u * nt;
+        const int kk = i / (AQ * 64);
+        if (i < total) v[u] = src[(int64_t)kk * SLOTS * 16 + (i - kk * AQ * 64)];
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int i = i0 + u * nt;
+        if (i < total) dst[i] = v[u];
+      }
     }
   }
+  __syncthreads();
   const float* sk = fws + d.ofw + (int64_t)N * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
   for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
@@ -844,49 +938,14 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   __syncthreads();
 
 
+  rollout_exact<NX, NU>(in.A + d.oA, in.B + d.oB, c, xd, ud, N, tid, nt);
+
   const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
   const int k = w;  // a stage wavefront's stage
 
   if (w == N) {
     // ---------------- chain wavefront ----------------
     float M0[4 * AQ], M1[4 * AQ];  // even / odd stage operators
-    // x^0 rollout: x_{k+1} = A_cl,k x_k + [B_k (u_k - K_k x_k) + c_k from stage wavefront k]
-    for (int kk = 0; kk < N; ++kk) {
-      __syncthreads();
-      if ((kk & 1) == 0) {
-        load_chain_op<AQ>(M0, acl4, kk, lane);
-        double sx[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          sx[i] = 0.0;
-#pragma unroll
-          for (int j = 0; j < RB; ++j) sx[i] += (double)(M0[i * RB + j] * (float)xd[kk * NXP + lb * RB + j]);
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const double v = red_b(sx[i]);
-          const int idx = la * RB + i;
-          if (lb == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = bvd[idx] + v;
-        }
-      } else {
-        load_chain_op<AQ>(M1, acl4, kk, lane);
-        double sx[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          sx[i] = 0.0;
-#pragma unroll
-          for (int j = 0; j < RB; ++j) sx[i] += (double)(M1[i * RB + j] * (float)xd[kk * NXP + la * RB + j]);
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const double v = red_a(sx[i]);
-          const int idx = lb * RB + i;
-          if (la == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = bvd[idx] + v;
-        }
-      }
-      __syncthreads();
-    }
-
     __builtin_amdgcn_s_setprio(2);
     // Layout of the backward chain's first input (stage N-1) and of the
     // forward chain's last output: a*RB + i for an even stage, b*RB + i odd.
@@ -1084,33 +1143,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 #pragma unroll
         for (int j = 0; j < CB; ++j) Hm[i][j] = own ? src[(i * CB + j) * 64] : 0.f;
     }
-    // x^0 rollout: this stage's B_k (u_k - K_k x_k) + c_k when the chain reaches it
-    for (int kk = 0; kk < N; ++kk) {
-      if (w == kk) {
-        float xa[RB], v[CB];
-#pragma unroll
-        for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + la * RB + j];
-#pragma unroll
-        for (int i = 0; i < CB; ++i) {
-          double s = 0.0;
-#pragma unroll
-          for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xa[j]);
-          v[i] = (float)(ud[kk * NUP + lb * CB + i] - red_a(s));
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          double s = 0.0;
-#pragma unroll
-          for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * v[j]);
-          s = red_b(s);
-          const int idx = la * RB + i;
-          if (lb == 0 && idx < NX) bvd[idx] = (double)cf[kk * NXP + idx] + s;
-        }
-      }
-      __syncthreads();
-      __syncthreads();
-    }
-
     // x_N <- alpha xt_N + (1 - alpha) x_N once the forward chain of iteration t is out
     auto relax_xN = [&](int t) {
       flag_wait(sync + kSyncX + N, 1, t, sync + kSyncAbort, lane);
@@ -1493,43 +1525,7 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
     yd[i] = wm ? (double)Y[i] : 0.0;
   }
   __syncthreads();
-  // x^0: rollout of the exact dynamics under u^0 over the whole workgroup; quad
-  // qq owns state row qq, its lanes every fourth column; the next stage's rows
-  // are loaded while the current one is summed
-  {
-    constexpr int TA = (NX + 3) / 4, TB = (NU + 3) / 4;
-    const int qq = tid >> 2, sub = tid & 3;
-    float an[TA], bn[TB];
-    auto load_rows = [&](int kk) __attribute__((always_inline)) {
-      const float* Ar = A + ((int64_t)kk * NX + qq) * NX;
-      const float* Br = B + ((int64_t)kk * NX + qq) * NU;
-#pragma unroll
-      for (int t = 0; t < TA; ++t) an[t] = (qq < NX && sub + 4 * t < NX) ? Ar[sub + 4 * t] : 0.f;
-#pragma unroll
-      for (int t = 0; t < TB; ++t) bn[t] = (qq < NX && sub + 4 * t < NU) ? Br[sub + 4 * t] : 0.f;
-    };
-    load_rows(0);
-    for (int kk = 0; kk < N; ++kk) {
-      float ac[TA], bc[TB];
-#pragma unroll
-      for (int t = 0; t < TA; ++t) ac[t] = an[t];
-#pragma unroll
-      for (int t = 0; t < TB; ++t) bc[t] = bn[t];
-      if (kk + 1 < N) load_rows(kk + 1);
-      if (qq < NX) {
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < TA; ++t)
-          if (sub + 4 * t < NX) acc += (double)ac[t] * xd[kk * NXP + sub + 4 * t];
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-          if (sub + 4 * t < NU) acc += (double)bc[t] * ud[kk * NUP + sub + 4 * t];
-        acc = quad_sum(acc);
-        if (sub == 0) xd[(kk + 1) * NXP + qq] = (double)c[kk * NX + qq] + acc;
-      }
-      __syncthreads();
-    }
-  }
+  rollout_exact<NX, NU>(A, B, c, xd, ud, N, tid, nt);
 
   const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
   const int SW = (N + 1) / 2;  // stage wavefronts

@@ -637,7 +637,7 @@ __device__ inline void flag_wait(int* f, int n, int v, int* abort, int lane) {
 
 struct IterLds {
   int acl, xtf, ppf, gf, ef, sf, cf;                               // float
-  int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd;  // double
+  int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd, bvd;  // double
   int flag, sync, total;
 };
 
@@ -673,6 +673,7 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
   L.qd = take(8 * S::NXP);
   L.xrd = take(8 * (N + 1) * S::NXP);
   L.qtd = take(8 * N * S::NXP);
+  L.bvd = take(8 * S::NXP);
   L.flag = take(16);
   L.sync = take(4 * kSyncInts);
   L.total = o;
@@ -748,6 +749,9 @@ __device__ inline void load_chain_op(float (&M)[4 * AQ], const float4* acl4, int
 // under u^0, by the whole workgroup: quad qq owns state row qq (its lanes every
 // fourth column), the rows of stages k+1..k+3 are in flight while stage k is
 // summed.  xd [N+1][NXP] (x_0 set) and ud [N][NUP] in LDS; one barrier per stage.
+// For the streaming kernel, whose LDS holds a few stages' operators at a time
+// (the register-resident kernel rolls out through A_cl in LDS and the stage
+// wavefronts' B_k, K_k instead, reading no A_k or B_k).
 template <int NX, int NU>
 __device__ inline void rollout_exact(const float* __restrict__ A, const float* __restrict__ B,
                                      const float* __restrict__ c, double* xd, const double* ud, int N,
@@ -873,6 +877,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   double* qd = reinterpret_cast<double*>(sm + L.qd);
   double* xrd = reinterpret_cast<double*>(sm + L.xrd);
   double* qtd = reinterpret_cast<double*>(sm + L.qtd);
+  double* bvd = reinterpret_cast<double*>(sm + L.bvd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
 
@@ -938,7 +943,6 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   __syncthreads();
 
 
-  rollout_exact<NX, NU>(in.A + d.oA, in.B + d.oB, c, xd, ud, N, tid, nt);
 
   const double sigma = sc.sigma, alpha = sc.alpha, oma = 1.0 - sc.alpha;
   const int k = w;  // a stage wavefront's stage
@@ -946,6 +950,42 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   if (w == N) {
     // ---------------- chain wavefront ----------------
     float M0[4 * AQ], M1[4 * AQ];  // even / odd stage operators
+    // x^0 rollout: x_{k+1} = A_cl,k x_k + [B_k (u_k - K_k x_k) + c_k from stage wavefront k]
+    for (int kk = 0; kk < N; ++kk) {
+      __syncthreads();
+      if ((kk & 1) == 0) {
+        load_chain_op<AQ>(M0, acl4, kk, lane);
+        double sx[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          sx[i] = 0.0;
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sx[i] += (double)(M0[i * RB + j] * (float)xd[kk * NXP + lb * RB + j]);
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const double v = red_b(sx[i]);
+          const int idx = la * RB + i;
+          if (lb == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = bvd[idx] + v;
+        }
+      } else {
+        load_chain_op<AQ>(M1, acl4, kk, lane);
+        double sx[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          sx[i] = 0.0;
+#pragma unroll
+          for (int j = 0; j < RB; ++j) sx[i] += (double)(M1[i * RB + j] * (float)xd[kk * NXP + la * RB + j]);
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const double v = red_a(sx[i]);
+          const int idx = lb * RB + i;
+          if (la == 0 && idx < NX) xd[(kk + 1) * NXP + idx] = bvd[idx] + v;
+        }
+      }
+      __syncthreads();
+    }
     __builtin_amdgcn_s_setprio(2);
     // Layout of the backward chain's first input (stage N-1) and of the
     // forward chain's last output: a*RB + i for an even stage, b*RB + i odd.
@@ -1142,6 +1182,32 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       for (int i = 0; i < CB; ++i)
 #pragma unroll
         for (int j = 0; j < CB; ++j) Hm[i][j] = own ? src[(i * CB + j) * 64] : 0.f;
+    }
+    // x^0 rollout: this stage's B_k (u_k - K_k x_k) + c_k when the chain reaches it
+    for (int kk = 0; kk < N; ++kk) {
+      if (w == kk) {
+        float xa[RB], v[CB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) xa[j] = (float)xd[kk * NXP + la * RB + j];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < RB; ++j) s += (double)(Km[i][j] * xa[j]);
+          v[i] = (float)(ud[kk * NUP + lb * CB + i] - red_a(s));
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < CB; ++j) s += (double)(Bm[i][j] * v[j]);
+          s = red_b(s);
+          const int idx = la * RB + i;
+          if (lb == 0 && idx < NX) bvd[idx] = (double)cf[kk * NXP + idx] + s;
+        }
+      }
+      __syncthreads();
+      __syncthreads();
     }
     // x_N <- alpha xt_N + (1 - alpha) x_N once the forward chain of iteration t is out
     auto relax_xN = [&](int t) {

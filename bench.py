@@ -7,7 +7,10 @@ plus Gaussian noise, x0 <- A_0 x0 + B_0 u_0* + c_0 + w, w ~ N(0, 1e-2^2).
 Default workload: 4096 humanoid agents (nx=48, nu=30, N=10), FP32.
 All inputs are synthetic and resident in HBM before timing starts.
 
-Prints ONE JSON line (see the design doc for the roofline and baseline fields).
+Prints ONE JSON line: throughput and latency, the iteration kernel's roofline
+(algorithmic FP32 FLOPs per launch over its HIP-event time, against the FP32
+vector peak, plus its recorded HBM traffic) and the FP64 CPU oracle's rate on
+a bounded sample.
 """
 from __future__ import annotations
 
@@ -132,19 +135,19 @@ def summarize_pmc(paths):
            "dispatches": [n_f, n_w], "copy_fetch_kib": f_c, "copy_write_kib": w_c,
            "copy_bytes": COPY_BYTES, "read_scale": scale_r, "write_scale": scale_w,
            "traffic_bytes_per_launch": traffic}
-    cmd = ("cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/{d} "
+    cmd = ("cd /tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d <out>/{d} "
            "-o run -- python3 <repo>/bench.py {a}")
     lines = ["# HBM traffic of the iteration kernel: 4096 humanoid agents (N=10, "
              "50 iterations, FP32)", "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of `" + kname + "`, each divided by the "
              "ratio the same counter reads for a plain 1 GiB device copy (`bench.py --calibrate-copy`).",
-             "Commands (four passes, one counter each):", "", "```",
+             "Commands (four passes, one counter each; <out> is the run's output folder):", "", "```",
              cmd.format(c="FETCH_SIZE", d="pmc_FETCH_SIZE_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
              cmd.format(c="FETCH_SIZE", d="pmc_FETCH_SIZE_copy", a="--calibrate-copy"),
              cmd.format(c="WRITE_SIZE", d="pmc_WRITE_SIZE_bench", a="--steps 2 --warmup 1 --cpu-seconds 0 --check-agents 4"),
              cmd.format(c="WRITE_SIZE", d="pmc_WRITE_SIZE_copy", a="--calibrate-copy"),
-             "python bench.py --summarize-pmc <repo>/gpurun_out/pmc_{FETCH_SIZE,WRITE_SIZE}_bench/run_counter_collection.csv "
-             "<repo>/gpurun_out/pmc_{FETCH_SIZE,WRITE_SIZE}_copy/run_counter_collection.csv", "```", "",
+             "python bench.py --summarize-pmc <out>/pmc_{FETCH_SIZE,WRITE_SIZE}_bench/run_counter_collection.csv "
+             "<out>/pmc_{FETCH_SIZE,WRITE_SIZE}_copy/run_counter_collection.csv", "```", "",
              "Algorithmic bytes per launch (operators loaded once, 4096 agents x 10 stages x 100 "
              "floats x 64 lanes; vectors and the resident state in and out): 1.09 GB read, 0.026 GB "
              "written.", "",
@@ -393,8 +396,8 @@ def serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(agents shard across GPUs with no exchange, see DESIGN.md)"}))
+        print(json.dumps({"error": "the solver runs on one GPU per process; --gpus must be 1 "
+                                   "(agents are independent: a batch shards across GPUs with no exchange)"}))
         sys.exit(2)
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc)

@@ -163,7 +163,8 @@ def compute_offsets(shapes: Sequence[Shape]) -> dict:
 
 
 def _draw_agent(rng, s: Shape, *, stance_p, q_log, r_log, r_scale, dt=DT):
-    """Draw one agent's data in a fixed order (documented in the design doc)."""
+    """Draw one agent's data in a fixed order: A, B, c, q, r, tau_max, mu, the
+    per-foot stance probabilities, stance, x0, x_ref."""
     G = rng.standard_normal((s.N, s.nx, s.nx)) / np.sqrt(s.nx)
     A = G * dt
     A[:, np.arange(s.nx), np.arange(s.nx)] += 1.0

@@ -29,6 +29,10 @@ MUTANTS = [
     ("P_{k+1} c instead of c in s", "acc += Pn[i * nx + t] * ck[t];", "acc += Pn[i * nx + t] * ck[i];"),
     ("dual residual sign", "for (int row = 0; row < m; ++row) acc += C[row * nu + j] * yk[row];",
      "for (int row = 0; row < m; ++row) acc -= C[row * nu + j] * yk[row];"),
+    ("plant step without c_0", "double acc = c[o[a].c + i] + noise[o[a].x0 + i];",
+     "double acc = noise[o[a].x0 + i];"),
+    ("plant step with A_0 transposed", "acc += A0[i * nx + t] * x0[o[a].x0 + t];",
+     "acc += A0[t * nx + i] * x0[o[a].x0 + t];"),
 ]
 
 CHECKS = [
@@ -39,6 +43,7 @@ CHECKS = [
     lambda: pins.test_constraint_rows_and_bounds_match_statement(pins.synth.quadruped(3)),
     lambda: pins.test_residuals_match_lagrangian_gradient(),
     lambda: pins.test_converged_equals_brute_force_active_set(2, 2),
+    lambda: pins.test_plant_step_is_the_solved_first_transition(),
 ]
 
 

@@ -364,3 +364,20 @@ def test_residuals_match_lagrangian_gradient():
     assert res[1] == pytest.approx(np.abs(dual).max(), rel=1e-9)
     assert res[2] == pytest.approx(np.abs(G @ v - b).max(), rel=1e-9)
     assert obj == pytest.approx(f, rel=1e-12)
+
+
+def test_plant_step_is_the_solved_first_transition():
+    """The closed-loop plant step x0 <- A_0 x0 + B_0 u_0 + c_0 + w: with w = 0 it
+    reproduces x_1 of the solved trajectory, which meets the dynamics exactly at
+    every iterate (rollout start, affine relaxation), over agents of different
+    shapes and horizons; w adds on unchanged."""
+    b = synth.uneven_batch(6)
+    o = oracle.solve_batch(b, iters=20)
+    off = b.offsets()
+    x1 = np.concatenate([o["x"][off["x"][a] + s.nx:off["x"][a] + 2 * s.nx]
+                         for a, s in enumerate(b.shapes)])
+    got = oracle.advance_batch(b, b.x0, o["u"], np.zeros_like(x1))
+    assert rel(got, x1) < 1e-12
+    w = np.random.default_rng(3).standard_normal(x1.size)
+    got_w = oracle.advance_batch(b, b.x0, o["u"], w)
+    assert np.abs(got_w - got - w).max() < 1e-12

@@ -148,8 +148,9 @@ def summarize_pmc(paths):
              cmd.format(c="WRITE_SIZE", d="pmc_WRITE_SIZE_copy", a="--calibrate-copy"),
              "python bench.py --summarize-pmc <out>/pmc_{FETCH_SIZE,WRITE_SIZE}_bench/run_counter_collection.csv "
              "<out>/pmc_{FETCH_SIZE,WRITE_SIZE}_copy/run_counter_collection.csv", "```", "",
-             "Algorithmic bytes per launch (operators loaded once, 4096 agents x 10 stages x 100 "
-             "floats x 64 lanes; vectors and the resident state in and out): 1.09 GB read, 0.026 GB "
+             "Algorithmic bytes per launch (operators loaded once, 4096 agents x (10 stages x 100 "
+             "floats x 64 lanes + S_0, 2304 floats); vectors and the resident state in and out): "
+             "1.13 GB read, 0.026 GB "
              "written.", "",
              "| quantity | value |", "|---|---|",
              f"| FETCH_SIZE per dispatch | {f_k:.0f} KiB |", f"| WRITE_SIZE per dispatch | {w_k:.0f} KiB |",

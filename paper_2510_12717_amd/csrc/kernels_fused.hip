@@ -16,7 +16,11 @@
 // carry one nx x nx product per stage (p_k = g_k + A_cl,k' p'_k backwards,
 // x_{k+1} = A_cl,k x_k + e_k forwards), executed by the wavefront that owns
 // the stage, one hop per workgroup barrier.  Everything independent across
-// stages runs in all wavefronts at once.  Chain hops are FP32; the
+// stages runs in all wavefronts at once.  The chain wavefront turns p'_0 into
+// x_1 itself, x_1 = A_cl,0 x_0 + g'_0 + S_0 p'_0 with S_0 = -B_0 H_0^{-1} B_0'
+// from the factor (per agent, after the stage slots and s_k) and
+// g'_0 = c_0 - B_0 H_0^{-1} rt_0 from stage 0's wavefront, formed before p'_0.
+// Chain hops are FP32; the
 // stage-parallel products accumulate in FP64 from FP32 operators, and the
 // ADMM state (x, u, z, y) and its relaxation / projection / dual update are
 // FP64.
@@ -592,6 +596,39 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     }
     __syncthreads();
   }
+  if (kResident) {
+    // S_0 = -B_0 H_0^{-1} B_0' (FP64 matrix-core tiles, once per agent), written in
+    // the chain operator order of an even stage: x~_1 = A_cl,0 x~_0 + c_0
+    // - B_0 H_0^{-1} rt_0 + S_0 p'_0, so the iterations' chain wavefront forms
+    // x~_1 from p'_0 in one product.  W = B_0 H_0^{-1} over P A_k and S_0 over P,
+    // neither of which stage 0 needs any more.
+    double* W = PA;
+    double* S0 = P;
+    constexpr int TW = (NXT / 16) * (NUT / 16), TS = (NXT / 16) * (NXT / 16);
+    for (int t = w; t < TW; t += nw) {
+      const int ti = t / (NUT / 16), tj = t % (NUT / 16);
+      const d4 acc = mfma_tile(ti, tj, NUT, lane,
+                               [&](int i, int kk) { return kk < NU ? (double)Bk[i * LU + kk] : 0.0; },
+                               [&](int kk, int j) { return (kk < NU && j < NU) ? H[kk * LU + j] : 0.0; });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[(ti * 16 + (lane >> 4) + 4 * v) * LU + tj * 16 + (lane & 15)] = acc[v];
+    }
+    __syncthreads();
+    for (int t = w; t < TS; t += nw) {
+      const int ti = t / (NXT / 16), tj = t % (NXT / 16);
+      const d4 acc = mfma_tile(ti, tj, NUT, lane, [&](int i, int kk) { return W[i * LU + kk]; },
+                               [&](int kk, int j) { return kk < NU ? (double)Bk[j * LU + kk] : 0.0; });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S0[(ti * 16 + (lane >> 4) + 4 * v) * LX + tj * 16 + (lane & 15)] = -acc[v];
+    }
+    __syncthreads();
+    float* s0 = ops + (int64_t)N * (SLOTS * 64 + S::NXP);
+    for (int e = tid; e < S::AQ * 256; e += nt) {
+      const int slot = 4 * (e >> 8) + (e & 3), ln = (e >> 2) & 63;
+      const int ri = (ln >> 3) * RB + slot / RB, cj = (ln & 7) * RB + slot % RB;
+      s0[e] = (slot < RB * RB && ri < NX && cj < NX) ? (float)S0[ri * LX + cj] : 0.f;
+    }
+  }
   if (tid == 0) status[agent] = AGENT_OK;
 }
 
@@ -878,6 +915,8 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   double* xrd = reinterpret_cast<double*>(sm + L.xrd);
   double* qtd = reinterpret_cast<double*>(sm + L.qtd);
   double* bvd = reinterpret_cast<double*>(sm + L.bvd);
+  // after the x^0 rollout: g'_0 of iterations of odd / even number
+  float* g0f = reinterpret_cast<float*>(sm + L.bvd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
 
@@ -1010,6 +1049,18 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         ax0[i] = red_b(ax0[i]);
       }
     }
+    // A_cl,0 is not read again (x^0 and A_cl,0 x_0 are done): its LDS slot
+    // takes S_0, which the backward chain's last hop then prefetches into M0
+    {
+      const float4* s0 = reinterpret_cast<const float4*>(fws + d.ofw + (int64_t)N * (SLOTS * 64 + NXP));
+      float4* acl_w = reinterpret_cast<float4*>(sm + L.acl);
+      float4 v[AQ];
+#pragma unroll
+      for (int q = 0; q < AQ; ++q) v[q] = s0[q * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < AQ; ++q) acl_w[q * 64 + lane] = v[q];
+    }
+    float p0[RB];  // p'_0 of the current iteration, on a*RB + i
 
     for (int it = 0; it < iters; ++it) {
       const int T = it + 1;
@@ -1084,6 +1135,8 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         // k = 0: p'_0 only
         if (lb == 0) lds_store<RB>(ppf + la * RB, pv);
         flag_set(sync + kSyncP, T);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) p0[i] = pv[i];
       }
       // forward chain, k = 0 .. N-1: xt_{k+1} = A_cl,k xt_k + e_k, stored and
       // flagged; the relaxed x_N and p_N for the next iteration come from xt_N
@@ -1125,21 +1178,38 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
         };
         using T_ = std::true_type;
         using F_ = std::false_type;
-        // stage 0: A_cl,0 x_0 + e_0 once C_0 is out
+        // stage 0: xt_1 = A_cl,0 x_0 + g'_0 + S_0 p'_0, without waiting for C_0;
+        // the wait for e_1 .. e_{N-1} comes after xt_1 is out
         if (N > 1) load_chain_op<AQ>(M1, acl4, 1, lane);
-        flag_wait(sync + kSyncE, N, T, sync + kSyncAbort, lane);  // e_k of the stage wavefronts
-        // x_N as relaxed in the previous iteration (stage N-1 wrote it before its C)
-        double xdN[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
         {
-          float e0[RB];
-          lds_load<RB>(e0, ef + la * RB);
+          // S_0 (in M0) acts in the even stages' form, which sums over b: p'_0
+          // moves from a*RB + j to b*RB + j first (lane (a, b) reads lane (b, a))
+          float g0[RB], pt[RB], sx[RB];
+          const int src = ((lb << 3) | la) << 2;
 #pragma unroll
-          for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + e0[i];
+          for (int j = 0; j < RB; ++j)
+            pt[j] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p0[j])));
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+#pragma unroll
+          for (int j = 0; j < RB; ++j)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) sx[i] += M0[i * RB + j] * pt[j];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = red_b(sx[i]);
+          flag_wait(sync + kSyncE, 1, T, sync + kSyncAbort, lane);  // g'_0
+          lds_load<RB>(g0, g0f + (T & 1) * NXP + la * RB);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + g0[i] + sx[i];
         }
         if (lb == 0) lds_store<RB>(xtf + NXP + la * RB, xv);
         if (N > 1) flag_set(sync + kSyncX + 1, T);
+        // e_k of stages k >= 1; x_N as relaxed in the previous iteration
+        // (stage N-1 wrote it before flagging)
+        if (N > 1) flag_wait(sync + kSyncE + 1, N - 1, T, sync + kSyncAbort, lane);
+        double xdN[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
         int kk = 1;
         for (; kk + 1 < N; kk += 2) {
           hop(kk, kk + 1, T_{});
@@ -1300,6 +1370,41 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
       // iteration needs it before the forward chain reads it again); the chain
       // wavefront has taken its own copy for p_N before flagging xt_N.
       if (k == N - 1 && it >= 1) relax_xN(T - 1);
+      if (k == 0) {
+        // g'_0 = c_0 - B_0 H_0^{-1} rt_0, the part of xt_1 that does not depend
+        // on p'_0 (the chain wavefront adds S_0 p'_0); flagged as stage 0's e
+        // (after the relaxation of x_N when stage 0 is the last).  dd_0 holds
+        // -H_0^{-1} rt_0 until C_0 overwrites it with d_0.
+        float hv[CB], sd[CB], dv[CB], se[RB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) hv[j] = (float)rtd[lb * CB + j];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) sd[i] = 0.f;
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int i = 0; i < CB; ++i) sd[i] += Hm[i][j] * hv[j];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) sd[i] = red_b(sd[i]);
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < CB; ++i) dd[la * CB + i] = -(double)sd[i];
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < CB; ++j) dv[j] = (float)dd[lb * CB + j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) se[i] = 0.f;
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) se[i] += Bm[i][j] * dv[j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
+        if (lb == 0)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) g0f[(T & 1) * NXP + la * RB + i] = cf[la * RB + i] + se[i];
+        flag_set(sync + kSyncE, T);
+      }
       // (B) backward chain on the chain wavefront; C_k starts once p'_k is out
       flag_wait(sync + kSyncP + k, 1, T, sync + kSyncAbort, lane);
       // (C) d_k = -H_k^{-1}(rt_k + B_k' p'_k), e_k = B_k d_k + c_k
@@ -1332,6 +1437,8 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 #pragma unroll
           for (int i = 0; i < CB; ++i) dd[k * NUP + la * CB + i] = -(double)sd[i];
         wave_sync();
+      }
+      if (w < N && k >= 1) {  // stage 0's part of xt_1 is g'_0 + S_0 p'_0
         float dv[CB], cv[RB], se[RB];
 #pragma unroll
         for (int j = 0; j < CB; ++j) dv[j] = (float)dd[k * NUP + lb * CB + j];
@@ -1350,7 +1457,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
 #pragma unroll
           for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = cv[i] + se[i];
       }
-      flag_set(sync + kSyncE + k, T);
+      if (k >= 1) flag_set(sync + kSyncE + k, T);  // stage 0 flagged g'_0 before its C
       // (D) forward chain on the chain wavefront; E_k starts once xt_k is out
       if (k >= 1) flag_wait(sync + kSyncX + k, 1, T, sync + kSyncAbort, lane);
       // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
@@ -2143,8 +2250,9 @@ void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t*
 
 size_t fused_agent_floats(int N, int nx, int nu) {
   (void)nu;
-  if (nx == 48) return (size_t)N * (FS<48, 30>::SLOTS * 64 + FS<48, 30>::NXP);
-  return (size_t)N * (FS<36, 24>::SLOTS * 64 + FS<36, 24>::NXP);
+  // per stage: operator slots and s_k; per agent: S_0 (register-resident kernel)
+  if (nx == 48) return (size_t)N * (FS<48, 30>::SLOTS * 64 + FS<48, 30>::NXP) + FS<48, 30>::AQ * 256;
+  return (size_t)N * (FS<36, 24>::SLOTS * 64 + FS<36, 24>::NXP) + FS<36, 24>::AQ * 256;
 }
 
 hipError_t fused_set_limits() {

@@ -44,6 +44,20 @@ def flops_factor_stage(nx, nu):
     return 2 * mac
 
 
+def sampled_errors(sol, ref, ids, shape, n_agents):
+    """Worst norm-wise relative error over the sampled agents of u_0 and of the
+    trajectory (x_1..N, u_0..N-1) against an oracle solution of those agents."""
+    nx, nu = shape.nx, shape.nu
+    x = sol["x"].cpu().numpy().reshape(n_agents, -1)[ids].astype(np.float64)[:, nx:]
+    u = sol["u"].cpu().numpy().reshape(n_agents, -1)[ids].astype(np.float64)
+    xo = ref["x"].reshape(len(ids), -1)[:, nx:]
+    uo = ref["u"].reshape(len(ids), -1)
+    tr, to = np.concatenate([x, u], 1), np.concatenate([xo, uo], 1)
+    e_tr = np.abs(tr - to).max(1) / np.abs(to).max(1)
+    e_u0 = np.abs(u[:, :nu] - uo[:, :nu]).max(1) / np.abs(uo[:, :nu]).max(1)
+    return float(e_u0.max()), float(e_tr.max())
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,11 +462,7 @@ def main():
     chk_ids = np.linspace(0, args.agents - 1, nchk).astype(int)
     sub = synth.make_batch([shape] * nchk, seed=0, stream_id=1, agent_ids=chk_ids)
     ref = oracle.solve_batch(sub, iters=args.iters)
-    ug = sol["u"].cpu().numpy().reshape(args.agents, -1)[chk_ids].astype(np.float64)
-    uo = ref["u"].reshape(nchk, -1)
-    err_traj = float((np.abs(ug - uo).max(1) / np.abs(uo).max(1)).max())
-    err_u0 = float((np.abs(ug[:, :shape.nu] - uo[:, :shape.nu]).max(1)
-                    / np.abs(uo[:, :shape.nu]).max(1)).max())
+    err_u0, err_traj = sampled_errors(sol, ref, chk_ids, shape, args.agents)
     status_ok = bool((sol["status"] == 0).all().item())
 
     # warmup (closed loop from the initial state)
@@ -474,6 +484,23 @@ def main():
     wall = time.perf_counter() - t0
     timing = plan.get_timing()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
+    # status of every agent after the last timed step (a failed agent still counts as a
+    # launched solve in `value`, so failures are reported beside it)
+    n_bad = int((plan.get_solution(stream=stream)["status"] != 0).sum().item())
+
+    # one more (untimed) warm step from the GPU's own resident iterate after the timed
+    # loop, checked against the oracle started from that same iterate and x0
+    plan.set_timing(False)
+    prev = plan.get_solution(stream=stream)
+    torch.cuda.synchronize()
+    warm = {k: prev[k].cpu().numpy().astype(np.float64).reshape(args.agents, -1)[chk_ids].ravel()
+            for k in ("u", "z", "y")}
+    x0_chk = prob["x0"].cpu().numpy().astype(np.float64).reshape(args.agents, -1)[chk_ids].ravel()
+    plan.solve(prob, warm_start=True, stream=stream)
+    sol_w = plan.get_solution(stream=stream)
+    torch.cuda.synchronize()
+    ref_w = oracle.solve_batch(sub, iters=args.iters, warm=warm, x0=x0_chk)
+    err_u0_w, err_traj_w = sampled_errors(sol_w, ref_w, chk_ids, shape, args.agents)
     solves = args.agents * args.steps
     value = solves / wall
 
@@ -532,7 +559,10 @@ def main():
         "kernel_ms": {"factor": fac_ms / max(fac_n, 1), "admm": admm_ms / max(admm_n, 1),
                       "residual": timing["residual"][0] / max(timing["residual"][1], 1)},
         "err_vs_fp64": {"u0": err_u0, "trajectory": err_traj, "agents_checked": int(nchk),
-                        "status_ok": status_ok},
+                        "status_ok": status_ok,
+                        "after_timed_loop": {"u0": err_u0_w, "trajectory": err_traj_w,
+                                             "steps_before": args.warmup + args.steps}},
+        "agents_not_ok_after_timed_loop": n_bad,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

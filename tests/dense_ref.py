@@ -56,6 +56,16 @@ def rho_table(l, h, rho=0.1, rho_eq=100.0, rho_min=1e-6):
     return out
 
 
+def complementarity_natural(l, h, z, y):
+    """Largest violation of "z in [l, h] and y in the normal cone of [l, h] at z",
+    as the projection (natural) residual |z - Pi_[l,h](z + y)| together with the
+    distance of z from [l, h].  Both vanish exactly at a complementary pair:
+    y > 0 only where z = h, y < 0 only where z = l."""
+    nat = np.abs(z - np.clip(z + y, l, h))
+    out = np.maximum(np.maximum(z - h, l - z), 0.0)
+    return float(max(nat.max(), out.max()))
+
+
 def dynamics_rows(s, A, B, c, x0):
     """G v = b for v = [x_1..x_N, u_0..u_{N-1}]: x_{k+1} - A_k x_k - B_k u_k = c_k."""
     N, nx, nu = s.N, s.nx, s.nu

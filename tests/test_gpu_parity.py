@@ -75,10 +75,35 @@ def test_small_humanoid_fp64_every_agent():
     # u0 export equals the first stage of u
     off = b.offsets()
     np.testing.assert_array_equal(g["u0"].reshape(64, 30), g["u"].reshape(64, 10 * 30)[:, :30])
-    # GPU FP64 KKT residuals of its iterate agree with the oracle's of its own
+    # GPU FP64 KKT residuals of its iterate agree with the oracle's of its own:
+    # primal and dual residuals, dynamics met, complementarity met at every
+    # iterate (y = rho (v - Pi(v)) lies in the normal cone at z = Pi(v))
     np.testing.assert_allclose(g["residuals"][:, :2], o["res"][:, :2], rtol=1e-7, atol=1e-12)
     assert np.all(g["residuals"][:, 2] < 1e-12)
+    assert np.all(o["res"][:, 3] < 1e-12) and np.all(g["residuals"][:, 3] < 1e-12)
     np.testing.assert_allclose(g["objective"], o["objective"], rtol=1e-10)
+    _residuals_of_own_iterate(b, g, io_dtype=np.float64, rtol=1e-9)
+
+
+def _residuals_of_own_iterate(b, g, io_dtype, rtol, agents=None):
+    """The residual kernel's FP64 report (primal, dual, dynamics, complementarity,
+    objective) equals the oracle's residual function on the same iterate and the
+    same (io-type rounded) problem data."""
+    off = b.offsets()
+    bio = b.astype(io_dtype).astype(np.float64)
+    agents = range(b.n_agents) if agents is None else agents
+    for a in agents:
+        ag = oracle.agent(bio, a)
+        s = ag["s"]
+        sl = lambda k, key: g[k][off[key][a]:off[key][a + 1]].astype(np.float64)
+        res, obj = oracle.residuals(s, ag["A"], ag["B"], ag["c"], ag["q"], ag["r"], ag["x_ref"],
+                                    ag["x0"], ag["tau_max"], ag["mu"], ag["stance"],
+                                    sl("x", "x"), sl("u", "u"), sl("z", "z"), sl("y", "z"))
+        scale = max(np.abs(sl("u", "u")).max(), np.abs(sl("z", "z")).max(),
+                    np.abs(sl("y", "z")).max())
+        np.testing.assert_allclose(g["residuals"][a], res, rtol=rtol, atol=rtol * scale,
+                                   err_msg=f"agent {a}")
+        assert g["objective"][a] == pytest.approx(obj, rel=max(rtol, 1e-6 if io_dtype == np.float32 else 0))
 
 
 @pytest.mark.parametrize("kernel", ["generic", "fused"])
@@ -91,6 +116,20 @@ def test_small_humanoid_fp32_every_agent(kernel):
     e = agent_errors(b, g, o)
     print("fp32 max errors u0/traj:", e[:, :2].max(axis=0))
     assert e[:, :2].max() < TOL["fp32"]
+    # FP32 plans: the FP64 residual report of the GPU's own iterate, and the
+    # objective, against the oracle's residual function on that iterate
+    _residuals_of_own_iterate(b, g, io_dtype=np.float32, rtol=1e-9)
+    # ... and against the oracle's report of its own FP64 iterate: the objective
+    # within the trajectory tolerance, primal / dual residuals within 1e-5 of
+    # the magnitude of the terms they difference
+    np.testing.assert_allclose(g["objective"], o["objective"], rtol=TOL["fp32"])
+    off = b.offsets()
+    for a in range(b.n_agents):
+        scale = max(np.abs(o["u"][off["u"][a]:off["u"][a + 1]]).max(),
+                    np.abs(o["z"][off["z"][a]:off["z"][a + 1]]).max(),
+                    np.abs(o["y"][off["z"][a]:off["z"][a + 1]]).max())
+        assert np.all(np.abs(g["residuals"][a, :2] - o["res"][a, :2]) <= TOL["fp32"] * scale), a
+    assert np.all(g["residuals"][:, 2] < 1e-5) and np.all(g["residuals"][:, 3] < 1e-5)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

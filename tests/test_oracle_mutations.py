@@ -33,6 +33,12 @@ MUTANTS = [
      "double acc = noise[o[a].x0 + i];"),
     ("plant step with A_0 transposed", "acc += A0[i * nx + t] * x0[o[a].x0 + t];",
      "acc += A0[t * nx + i] * x0[o[a].x0 + t];"),
+    ("complementarity signs swapped", "const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;",
+     "const double yp = yy < 0.0 ? -yy : 0.0, ym = yy > 0.0 ? yy : 0.0;"),
+    ("complementarity without the lower bound", "const double b = isinf(lo) ? ym : fmin(ym, zz - lo);",
+     "const double b = 0.0;"),
+    ("complementarity against the wrong bound", "const double a = isinf(hi) ? yp : fmin(yp, hi - zz);",
+     "const double a = isinf(lo) ? yp : fmin(yp, zz - lo);"),
 ]
 
 CHECKS = [
@@ -44,6 +50,7 @@ CHECKS = [
     lambda: pins.test_residuals_match_lagrangian_gradient(),
     lambda: pins.test_converged_equals_brute_force_active_set(2, 2),
     lambda: pins.test_plant_step_is_the_solved_first_transition(),
+    lambda: pins.test_complementarity_residual_is_the_projection_residual(),
 ]
 
 

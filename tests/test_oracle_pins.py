@@ -366,6 +366,44 @@ def test_residuals_match_lagrangian_gradient():
     assert obj == pytest.approx(f, rel=1e-12)
 
 
+def test_complementarity_residual_is_the_projection_residual():
+    """res[3] equals the projection residual |z - Pi(z + y)| with the distance of
+    z from [l, h] (a formulation of complementarity independent of the oracle's
+    per-sign minima): zero at a complementary pair built as z = Pi(v), y = v - z,
+    and equal to it once z leaves its bound, crosses it, or y takes the wrong sign."""
+    s = synth.quadruped(4)
+    ag = one_agent(s, seed=37)
+    l, h = D.bounds_table(s, ag["tau_max"], ag["stance"])
+    C = D.C_dense(s, ag["mu"])
+    rng = np.random.default_rng(37)
+    x = rng.standard_normal((s.N + 1, s.nx))
+    u = rng.standard_normal((s.N, s.nu))
+
+    def res3(z, y):
+        res, _ = oracle.residuals(s, ag["A"], ag["B"], ag["c"], ag["q"], ag["r"], ag["x_ref"],
+                                  ag["x0"], ag["tau_max"], ag["mu"], ag["stance"], x, u, z, y)
+        return res[3]
+
+    v = rng.standard_normal(l.shape) * 60.0
+    z0 = np.clip(v, l, h)
+    y0 = v - z0
+    assert np.count_nonzero(y0 > 0) > 3 and np.count_nonzero(y0 < 0) > 3
+    assert res3(z0, y0) == 0.0 and D.complementarity_natural(l, h, z0, y0) == 0.0
+    for trial in range(6):
+        z, y = z0.copy(), y0.copy()
+        pick = rng.random(l.shape) < 0.3
+        if trial % 3 == 0:    # z moved off (or across) its bound
+            z[pick] += rng.standard_normal(np.count_nonzero(pick)) * 5.0
+        elif trial % 3 == 1:  # multipliers of the wrong sign
+            y[pick] = -y[pick] + rng.standard_normal(np.count_nonzero(pick))
+        else:                 # both, with z also outside some bounds
+            z[pick] += rng.standard_normal(np.count_nonzero(pick)) * 50.0
+            y += rng.standard_normal(y.shape)
+        want = D.complementarity_natural(l, h, z, y)
+        assert want > 0.1
+        assert res3(z, y) == pytest.approx(want, rel=1e-12)
+
+
 def test_plant_step_is_the_solved_first_transition():
     """The closed-loop plant step x0 <- A_0 x0 + B_0 u_0 + c_0 + w: with w = 0 it
     reproduces x_1 of the solved trajectory, which meets the dynamics exactly at

@@ -117,7 +117,9 @@ void mpc_plan_desc_default(mpc_plan_desc* desc);
 
 typedef struct mpc_plan_s* mpc_plan_t;
 
-/* Validate the description, copy the shapes, and allocate device workspace:
+/* Set-up of Alg. 1 for a fixed batch of QPs of the form of Eq. (mpc_formulation)
+ * (one per agent, Sec. III-B).
+ * Validate the description, copy the shapes, and allocate device workspace:
  * factors, resident warm-start state (u, z, y), solution and status buffers.
  * Errors: INVALID_ARG (bad pointer, count or constant), UNSUPPORTED_SHAPE
  * (shape outside the limits), OUT_OF_MEMORY, HIP. */
@@ -133,7 +135,11 @@ typedef struct {
   int32_t warm_start;  /* 0: u = z = y = 0;  1: start from the plan's resident (u, z, y) */
 } mpc_problem_batch;
 
-/* Solve every agent: stage penalties and bounds, Riccati factor (once), then
+/* Alg. 1 for every agent, from the KKT data (f_KKT) to the end of the QP
+ * iterations: the factor plays the role of Eq. (ldl) (once per solve, Sec.
+ * III-B), each iteration the role of Eqs. (backsolve_1)-(backsolve_2) plus
+ * OSQP's projection and dual update (the ADMM of Eq. (kkt_system)).
+ * Solve every agent: stage penalties and bounds, Riccati factor (once), then
  * admm_iters iterations of back-sweep, rollout, relaxation, projection and
  * dual update, then the FP64 KKT residual check.  The solution stays
  * resident in the plan (it is the next warm start).  warm_start = 1 before
@@ -146,22 +152,31 @@ typedef struct {
   int32_t* status;                      /* [n],    may be NULL                   */
 } mpc_solution;
 
-/* Copy the resident solution into caller device buffers (stream-ordered).
+/* The QP solution Alg. 1 returns after its fixed iteration count; u_0 is
+ * the input of the first stage, the one real-time iteration applies (Sec.
+ * II-A).
+ * Copy the resident solution into caller device buffers (stream-ordered).
  * NOT_READY if no solve has been issued. */
 mpc_status mpc_get_solution(mpc_plan_t plan, const mpc_solution* out, void* stream);
 
-/* Replace the resident warm-start state with caller device buffers u [N][nu],
+/* Warm start of the next QP from a previous iterate (real-time iteration
+ * solves one QP per control step, Sec. II-A, seeded by the last solution).
+ * Replace the resident warm-start state with caller device buffers u [N][nu],
  * z [N][m], y [N][m] (io type), e.g. to resume a controller. */
 mpc_status mpc_set_warm_state(mpc_plan_t plan, const void* u, const void* z, const void* y,
                               void* stream);
 
-/* Closed-loop plant step of every agent under its own first stage:
+/* The system step x_{i+1} = f(x_i, u_i) of Eq. (OCP), linearised as the QP's
+ * first stage, driving a closed loop of control steps.
+ * Closed-loop plant step of every agent under its own first stage:
  * x0_next = A_0 x0 + B_0 u_0 + c_0 + noise, with u_0 the resident solution's
  * first input.  noise may be NULL.  x0_next may alias x0. */
 mpc_status mpc_advance_state(mpc_plan_t plan, const mpc_problem_batch* batch, const void* noise,
                              void* x0_next, void* stream);
 
-/* Per-kernel timing: when enabled, every launch of a solve is bracketed by
+/* Timing of the phases Table II times separately (factor, QP iterations)
+ * plus the residual check.
+ * Per-kernel timing: when enabled, every launch of a solve is bracketed by
  * HIP events on the stream it runs on.  mpc_plan_get_timing waits for those
  * events and returns the accumulated milliseconds and launch counts of
  * {stage setup + factor, ADMM iterations, KKT residual} in ms[0..2] /
@@ -177,7 +192,9 @@ mpc_status mpc_plan_get_timing(mpc_plan_t plan, double* ms, int64_t* launches);
 mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* threads_per_agent,
                                int32_t* lds_bytes);
 
-/* Copy agent `agent`'s Riccati factor of the last solve into caller device
+/* The factor of Eq. (ldl)'s role, in Riccati form (gains, closed-loop
+ * operators, stage-Hessian inverses).
+ * Copy agent `agent`'s Riccati factor of the last solve into caller device
  * buffers (io type): K [N][nu][nx], A_cl [N][nx][nx] (= A_k + B_k K_k),
  * Hinv [N][nu][nu] (= H_k^{-1}), s [N][nx] (= P_{k+1} c_k); any may be NULL.
  * Only plans running the generic kernels keep the factor in device memory
@@ -203,7 +220,9 @@ typedef struct {
 mpc_status mpc_plan_get_groups(mpc_plan_t plan, mpc_group_info* out, int32_t cap,
                                int32_t* n_groups);
 
-/* Autotuner: for every group, time each candidate launch configuration (the
+/* Launch configuration search for the parallel solve of Sec. III-D (one
+ * kernel launch serves every agent of a group).
+ * Autotuner: for every group, time each candidate launch configuration (the
  * register-resident kernels where the group has them; the generic kernels
  * with 256, 128 and 64 threads per workgroup) over `reps` cold solves of
  * that group's agents on `stream`, and keep the fastest.  Synchronous.
@@ -212,7 +231,9 @@ mpc_status mpc_plan_get_groups(mpc_plan_t plan, mpc_group_info* out, int32_t cap
 mpc_status mpc_plan_autotune(mpc_plan_t plan, const mpc_problem_batch* batch, int32_t reps,
                              void* stream);
 
-/* Capture one control step into a HIP graph held by the plan: mpc_solve on
+/* One control step of the parallel MPC of Alg. 1 (solve, then the plant
+ * step) as one replayable launch sequence.
+ * Capture one control step into a HIP graph held by the plan: mpc_solve on
  * `batch` (with its warm_start flag) and, if x0_next is not NULL,
  * mpc_advance_state with `noise` and x0_next.  The graph records the pointer
  * values of batch, noise and x0_next: every replay reads the memory they
@@ -268,7 +289,9 @@ typedef struct {
 
 void mpc_server_desc_default(mpc_server_desc* desc);
 
-/* Allocates the arena and the batch slots (each with its own stream).
+/* Every request is one QP of Eq. (mpc_formulation) for one controller's
+ * control step (real-time iteration, Sec. II-A), solved as in mpc_solve.
+ * Allocates the arena and the batch slots (each with its own stream).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP. */
 mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_t* out);
 
@@ -279,7 +302,9 @@ mpc_status mpc_server_destroy(mpc_server_t server);
  * completion times use it. */
 double mpc_server_clock(mpc_server_t server);
 
-/* Queue one request of controller controller_id (any int64 key).  problem
+/* One controller's QP of Eq. (mpc_formulation) for its current control step
+ * (Sec. II-A), to be solved by Alg. 1's iterations like an agent of a plan.
+ * Queue one request of controller controller_id (any int64 key).  problem
  * holds DEVICE pointers to this controller's data for ONE agent in the
  * layouts of mpc_problem_batch, in the io type of the server's precision;
  * u_ref must be NULL; they must stay valid until the request completes.
@@ -293,13 +318,15 @@ mpc_status mpc_server_submit(mpc_server_t server, int64_t controller_id, const m
                              const mpc_problem_batch* problem, void* u0_out, int32_t* status_out,
                              double t_arrival, int64_t* ticket);
 
-/* n requests at once (arrays of n; status_out and tickets may be NULL). */
+/* As mpc_server_submit (one QP of Eq. (mpc_formulation) per request), for
+ * n requests at once (arrays of n; status_out and tickets may be NULL). */
 mpc_status mpc_server_submit_many(mpc_server_t server, int32_t n, const int64_t* controller_ids,
                                   const mpc_shape* shapes, const mpc_problem_batch* problems,
                                   void* const* u0_out, int32_t* const* status_out,
                                   const double* t_arrival, int64_t* tickets);
 
-/* Non-blocking: retire finished batches, launch pending work into free
+/* Completion of the QP solves of Alg. 1 issued for queued requests.
+ * Non-blocking: retire finished batches, launch pending work into free
  * slots, and report up to cap completed (solved) tickets with their
  * completion times (server clock, taken from the batch's completion event). */
 mpc_status mpc_server_poll(mpc_server_t server, int64_t* done_tickets, double* done_time,
@@ -310,7 +337,9 @@ mpc_status mpc_server_poll(mpc_server_t server, int64_t* done_tickets, double* d
  * written).  OUT_OF_MEMORY if pending requests can never fit the budget. */
 mpc_status mpc_server_drain(mpc_server_t server);
 
-/* Copy a controller's resident iterate (x [N+1][nx], u [N][nu], z, y [N][m],
+/* The warm start real-time iteration carries to a controller's next QP
+ * (Sec. II-A).
+ * Copy a controller's resident iterate (x [N+1][nx], u [N][nu], z, y [N][m],
  * io type) to caller device buffers; any may be NULL.  BUSY while it has a
  * request on the device, NOT_READY if it has no resident state. */
 mpc_status mpc_server_get_state(mpc_server_t server, int64_t controller_id, void* x, void* u,

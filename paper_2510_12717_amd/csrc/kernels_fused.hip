@@ -10,20 +10,29 @@
 // register layout below, so the iteration kernel loads them with coalesced
 // loads: opws[agent][stage][slot][lane], SLOTS floats per lane.
 //
-// k_admm_resident -- one wavefront per stage; the QP iterations of Alg. 1
-// (the role of Eqs. (backsolve_1)-(backsolve_2), then projection and dual
-// update), with every operator read from registers.  The two serial chains
-// carry one nx x nx product per stage (p_k = g_k + A_cl,k' p'_k backwards,
-// x_{k+1} = A_cl,k x_k + e_k forwards), executed by the wavefront that owns
-// the stage, one hop per workgroup barrier.  Everything independent across
-// stages runs in all wavefronts at once.  The chain wavefront turns p'_0 into
-// x_1 itself, x_1 = A_cl,0 x_0 + g'_0 + S_0 p'_0 with S_0 = -B_0 H_0^{-1} B_0'
+// k_admm_resident -- the QP iterations of Alg. 1 (the role of
+// Eqs. (backsolve_1)-(backsolve_2), then projection and dual update) with
+// every operator on chip: one stage wavefront per stage keeps K_k, B_k and
+// H_k^{-1} in registers and runs the work that is independent across stages
+// (linear terms, input step, relaxation / projection / dual update); one
+// chain wavefront runs both serial chains alone (p_k = g_k + A_cl,k' p'_k
+// backwards, x_{k+1} = A_cl,k x_k + e_k forwards), reading A_cl,k from LDS,
+// with no workgroup barrier between hops.  The two kinds of wavefront hand
+// over through per-stage progress flags in LDS (value = iteration number):
+// a stage wavefront starts its input step as soon as p'_k is flagged and its
+// state update as soon as x_k is.  The chain wavefront turns p'_0 into x_1
+// itself, x_1 = A_cl,0 x_0 + g'_0 + S_0 p'_0 with S_0 = -B_0 H_0^{-1} B_0'
 // from the factor (per agent, after the stage slots and s_k) and
 // g'_0 = c_0 - B_0 H_0^{-1} rt_0 from stage 0's wavefront, formed before p'_0.
-// Chain hops are FP32; the
-// stage-parallel products accumulate in FP64 from FP32 operators, and the
-// ADMM state (x, u, z, y) and its relaxation / projection / dual update are
-// FP64.
+// Every product (chain hops and stage-parallel products) sums its per-lane
+// block and its cross-lane butterfly in FP32; the ADMM state (x, u, z, y),
+// the offsets added to the sums and the relaxation / projection / dual update
+// are FP64.
+//
+// k_admm_stream -- the same iterations for horizons 12 to 20: one stage
+// wavefront per two stages, the chain wavefront, and a loader wavefront that
+// streams A_cl,k from HBM through a ring of LDS slots in the order the chain
+// consumes them.
 //
 // Register layout of a stage's operators (lane = 8a + b, a, b in 0..7):
 //   Acl[i][j] = A_cl[a*RB + i][b*RB + j]      RB = ceil(nx/8)
@@ -113,28 +122,6 @@ __device__ inline T red_a(T v) {
   v = swap_sum16(v);
   v = swap_sum32(v);
   return v;
-}
-
-// Reduce-scatter over the 8 lanes b, b+8, .., b+56 (the a index): v[0..7] of
-// every lane in, and lane (a, b) returns the sum over a' of v[a] of lane
-// (a', b).  Three exchange levels move 4 + 2 + 1 values instead of 8 x 3:
-// v_permlane32_swap pairs a with a ^ 4, v_permlane16_swap a with a ^ 2 (each
-// returns the pair sum of one kept index per lane), DPP row_ror 8 a with a ^ 1.
-__device__ inline float rscatter_a(const float (&v)[8], int lane) {
-  float w[4], u[2];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[t]), __float_as_uint(v[4 + t]), false, false);
-    w[t] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[t]), __float_as_uint(w[2 + t]), false, false);
-    u[t] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-  const bool a0 = (lane >> 3) & 1;
-  const float mine = a0 ? u[1] : u[0], send = a0 ? u[0] : u[1];
-  return mine + dpp<0x128>(send);
 }
 
 // One 16x16 output tile of C = op(A) op(B) on the FP64 matrix cores.
@@ -596,7 +583,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     }
     __syncthreads();
   }
-  if (kResident) {
+  if (kResident && N + 1 <= kMaxStages) {
+    // (only the one-wavefront-per-stage iteration kernel reads S_0)
     // S_0 = -B_0 H_0^{-1} B_0' (FP64 matrix-core tiles, once per agent), written in
     // the chain operator order of an even stage: x~_1 = A_cl,0 x~_0 + c_0
     // - B_0 H_0^{-1} rt_0 + S_0 p'_0, so the iterations' chain wavefront forms
@@ -648,9 +636,13 @@ constexpr int kSyncAbort = 4 * kMaxStages + 1, kSyncInts = 4 * kMaxStages + 2;
 constexpr int kSpinLimit = 1 << 21;  // polls of one wait (about 0.1 s)
 
 // Setting a flag does not wait for the wavefront's earlier LDS stores to
-// complete: one wavefront's LDS operations are performed in issue order, so a
-// reader that sees the flag and then loads sees the data.  The compiler-level
-// barrier keeps the stores before the flag in issue order.
+// complete.  This rests on the CDNA memory model for LDS: the LDS unit
+// executes the DS instructions of one wavefront in the order they were issued
+// (which is also why LGKM_CNT counts LDS-only traffic down in order), so the
+// data stores are performed before the flag store, and a reader that sees the
+// flag and then loads sees the data.  The compiler-level barrier keeps the
+// stores before the flag in issue order.  A release store would add an
+// s_waitcnt lgkmcnt(0) before every flag on the critical path.
 __device__ inline void flag_set(int* f, int v) {
   asm volatile("" ::: "memory");
   __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -862,8 +854,10 @@ __device__ inline void rollout_exact(const float* __restrict__ A, const float* _
 // ahead, with no barrier between hops.  Its operators alternate lane roles
 // with the stage's parity (even k: rows a*RB + i, columns b*RB + j; odd k:
 // rows b*RB + i, columns a*RB + j), so the butterfly of one hop leaves its
-// output vector spread over the lanes exactly as the next hop reads it.  The
-// two kinds of wavefront meet at four workgroup barriers per iteration.
+// output vector spread over the lanes exactly as the next hop reads it.  Inside
+// the iteration loop the two kinds of wavefront meet only through the
+// progress flags; workgroup barriers separate the set-up, the iterations and
+// the write-out.
 template <int NX, int NU>
 __global__ void __launch_bounds__(64 * kMaxStages)
 k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,

@@ -70,6 +70,19 @@ void assign_queues(std::vector<Group>& groups, int nq) {
   }
 }
 
+// u_0 of every agent into a packed [sum nu] buffer (agent a's block at
+// u0off[a]), for batches whose u blocks are not evenly strided.
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_gather_u0_packed(const AgentDesc* __restrict__ desc, const int64_t* __restrict__ u0off, int n,
+                   const T* __restrict__ u, T* __restrict__ u0) {
+  const int a = blockIdx.x;
+  if (a >= n) return;
+  const int64_t src = desc[a].ou, dst = u0off[a];
+  const int nu = desc[a].nu;
+  for (int j = threadIdx.x; j < nu; j += blockDim.x) u0[dst + j] = u[src + j];
+}
+
 }  // namespace
 
 struct mpc_plan_s {
@@ -83,6 +96,8 @@ struct mpc_plan_s {
   int maxN = 0, maxnx = 0, maxnu = 0, maxm = 0;
   int64_t nX = 0, nU = 0, nZ = 0, nWS = 0;
   AgentDesc* d_desc = nullptr;
+  int64_t* d_u0off = nullptr;  // packed u_0 offset of every agent
+  bool uniform_u = true;       // every agent has the same N and nu
   void* d_ws = nullptr;
   void *d_x = nullptr, *d_u = nullptr, *d_z = nullptr, *d_y = nullptr, *d_obj = nullptr;
   double* d_res = nullptr;
@@ -153,6 +168,7 @@ static void free_plan(mpc_plan_s* p) {
   if (p->ev_fork) hipEventDestroy(p->ev_fork);
   for (auto e : p->ev_join) hipEventDestroy(e);
   hipFree(p->d_desc);
+  hipFree(p->d_u0off);
   hipFree(p->d_list);
   hipFree(p->d_fws);
   hipFree(p->d_ws);
@@ -335,8 +351,15 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
     return hipMalloc(ptr, bytes ? bytes : 16);
   };
-  hipError_t errs[11] = {
+  std::vector<int64_t> u0off(p->n);
+  for (int a = 0, off = 0; a < p->n; ++a) {
+    u0off[a] = off;
+    off += p->shapes[a].nu;
+    p->uniform_u &= p->shapes[a].N == p->shapes[0].N && p->shapes[a].nu == p->shapes[0].nu;
+  }
+  hipError_t errs[12] = {
       alloc((void**)&p->d_desc, sizeof(AgentDesc) * p->n),
+      alloc((void**)&p->d_u0off, sizeof(int64_t) * p->n),
       alloc((void**)&p->d_list, sizeof(int32_t) * p->hlist.size()),
       alloc((void**)&p->d_fws, sizeof(float) * (size_t)p->nFWS),
       alloc(&p->d_ws, p->esz * (size_t)p->nWS),
@@ -356,6 +379,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     }
   }
   e = hipMemcpy(p->d_desc, p->hdesc.data(), sizeof(AgentDesc) * p->n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_u0off, u0off.data(), sizeof(int64_t) * p->n, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_list, p->hlist.data(), sizeof(int32_t) * p->hlist.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int32_t) * p->n);
@@ -582,22 +607,19 @@ extern "C" mpc_status mpc_get_solution(mpc_plan_t p, const mpc_solution* o, void
   if (o->residuals) HIP_TRY(hipMemcpyAsync(o->residuals, p->d_res, sizeof(double) * 4 * p->n, hipMemcpyDeviceToDevice, s));
   if (o->status) HIP_TRY(hipMemcpyAsync(o->status, p->d_status, sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, s));
   if (o->u0) {
-    // u0 of agent a is the first nu entries of its u block: a strided gather.
-    if (p->n > 0) {
-      bool uniform = true;
-      for (int a = 1; a < p->n && uniform; ++a) uniform = p->hdesc[a].N == p->hdesc[0].N && p->hdesc[a].nu == p->hdesc[0].nu;
-      if (uniform) {
-        const size_t nu = p->hdesc[0].nu, N = p->hdesc[0].N;
-        HIP_TRY(hipMemcpy2DAsync(o->u0, nu * e, p->d_u, N * nu * e, nu * e, p->n, hipMemcpyDeviceToDevice, s));
-      } else {
-        size_t off = 0;
-        for (int a = 0; a < p->n; ++a) {
-          const size_t nu = p->hdesc[a].nu;
-          HIP_TRY(hipMemcpyAsync((char*)o->u0 + off * e, (char*)p->d_u + (size_t)p->hdesc[a].ou * e,
-                                 nu * e, hipMemcpyDeviceToDevice, s));
-          off += nu;
-        }
-      }
+    // u0 of agent a is the first nu entries of its u block: a strided copy
+    // when every block has one size, else one gather kernel.
+    if (p->uniform_u) {
+      const size_t nu = p->hdesc[0].nu, N = p->hdesc[0].N;
+      HIP_TRY(hipMemcpy2DAsync(o->u0, nu * e, p->d_u, N * nu * e, nu * e, p->n, hipMemcpyDeviceToDevice, s));
+    } else if (p->fp64) {
+      hipLaunchKernelGGL(k_gather_u0_packed<double>, dim3(p->n), dim3(64), 0, s, p->d_desc, p->d_u0off,
+                         p->n, (const double*)p->d_u, (double*)o->u0);
+      HIP_TRY(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(k_gather_u0_packed<float>, dim3(p->n), dim3(64), 0, s, p->d_desc, p->d_u0off,
+                         p->n, (const float*)p->d_u, (float*)o->u0);
+      HIP_TRY(hipGetLastError());
     }
   }
   return MPC_OK;

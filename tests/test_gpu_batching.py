@@ -41,6 +41,13 @@ def test_groups_of_uneven_batch():
             assert x["threads"] == 64 * ((x["N"] + 1) // 2 + 2)  # + loader
     assert len(groups) == 6  # two shape classes x three horizon buckets
     assert plan.config()["kernel"] == "fused"
+    # the u0 export of an uneven batch (one gather kernel) is each agent's first input
+    ou, o0 = 0, 0
+    for s in b.shapes:
+        np.testing.assert_array_equal(g["u0"][o0:o0 + s.nu], g["u"][ou:ou + s.nu])
+        ou += s.N * s.nu
+        o0 += s.nu
+    assert o0 == g["u0"].size
     o = oracle.solve_batch(b, iters=50)
     assert np.all(g["status"] == 0)
     e = agent_errors(b, g, o)

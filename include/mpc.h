@@ -347,6 +347,33 @@ mpc_status mpc_server_get_state(mpc_server_t server, int64_t controller_id, void
 
 mpc_status mpc_server_get_stats(mpc_server_t server, mpc_server_stats* out);
 
+/* ---------------------------------------------------------------------------
+ * Solve without any device allocation.  For callers that cannot allocate
+ * device memory: work recorded under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It is mpc_solve for a batch of agents of
+ * ONE shape with a register-resident instantiation ((nx, nu) = (48, 30) or
+ * (36, 24), N <= 20), MPC_FP32 only, and no plan: desc gives n_agents,
+ * shapes (host array, every entry equal), admm_iters and the solver
+ * constants (precision must be MPC_FP32; kernel, refinement fields ignored).
+ * The per-agent descriptors, the launch list and the Riccati operators live
+ * in a device array of MPC_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends (about 500 humanoid agents
+ * at N = 10); a batch that needs more is rejected with UNSUPPORTED_SHAPE and
+ * a message naming the limit.  The iterate lives in the caller's buffers:
+ * out->x, u, z, y, objective, residuals and status are required (device
+ * pointers, layouts of mpc_solution) and receive the solution; with
+ * batch->warm_start = 1 the solve starts from the u, z, y those buffers hold
+ * (a previous solution of the same batch shape).  out->u0 may be NULL.
+ * Nothing is allocated and nothing needs clearing between calls (every
+ * scratch byte a solve reads is written by that solve first), but every call
+ * on one device uses that device's one scratch array: calls that overlap on
+ * a device (concurrent streams, threads) race and corrupt each other.
+ * Stream-ordered on `stream`.  Errors: INVALID_ARG, UNSUPPORTED_SHAPE, HIP.
+ * ------------------------------------------------------------------------- */
+#define MPC_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+mpc_status mpc_solve_noalloc(const mpc_plan_desc* desc, const mpc_problem_batch* batch,
+                             const mpc_solution* out, void* stream);
+
 /* Thread-local description of the last error returned on this thread. */
 const char* mpc_last_error(void);
 

@@ -76,7 +76,7 @@ EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_
            "mpc_server_desc_default", "mpc_server_create", "mpc_server_destroy",
            "mpc_server_clock", "mpc_server_submit", "mpc_server_submit_many", "mpc_server_poll",
            "mpc_server_drain", "mpc_server_get_state", "mpc_server_get_stats",
-           "mpc_last_error", "mpc_version")
+           "mpc_solve_noalloc", "mpc_last_error", "mpc_version")
 
 _lib = None
 
@@ -120,6 +120,8 @@ def lib():
         L.mpc_server_drain.argtypes = [V]
         L.mpc_server_get_state.argtypes = [V, ctypes.c_int64, V, V, V, V, V]
         L.mpc_server_get_stats.argtypes = [V, P(ServerStats)]
+        L.mpc_solve_noalloc.argtypes = [P(PlanDesc), P(ProblemBatch), P(Solution), V]
+        L.mpc_solve_noalloc.restype = ctypes.c_int
         for f in ("mpc_server_create", "mpc_server_destroy", "mpc_server_submit",
                   "mpc_server_submit_many", "mpc_server_poll", "mpc_server_drain",
                   "mpc_server_get_state", "mpc_server_get_stats"):
@@ -311,6 +313,55 @@ class Plan:
         _check(lib().mpc_plan_export_factor(self._h, int(agent), _ptr(K), _ptr(Acl), _ptr(Hi),
                                             _ptr(sv), _stream_handle(stream)))
         return K, Acl, Hi, sv
+
+
+def solution_buffers(shapes, dtype: str = "fp32") -> Dict[str, "object"]:
+    """Device tensors for the solution of a batch of ``shapes`` (the caller's
+    buffers of ``mpc_get_solution`` / ``mpc_solve_noalloc``)."""
+    import torch
+    td = torch.float64 if dtype == "fp64" else torch.float32
+    dev = torch.device("cuda", torch.cuda.current_device())
+    n = len(shapes)
+    nx = sum((s.N + 1) * s.nx for s in shapes)
+    nu = sum(s.N * s.nu for s in shapes)
+    nz = sum(s.N * (s.nu + 4 * s.n_feet) for s in shapes)
+    return dict(u0=torch.empty(sum(s.nu for s in shapes), dtype=td, device=dev),
+                x=torch.empty(nx, dtype=td, device=dev), u=torch.empty(nu, dtype=td, device=dev),
+                z=torch.empty(nz, dtype=td, device=dev), y=torch.empty(nz, dtype=td, device=dev),
+                objective=torch.empty(n, dtype=td, device=dev),
+                residuals=torch.empty((n, 4), dtype=torch.float64, device=dev),
+                status=torch.empty(n, dtype=torch.int32, device=dev))
+
+
+def solve_noalloc(shapes: Sequence, prob, out, warm_start: bool = False, iters: int = 50,
+                  device: int = 0, stream=None, **consts):
+    """``mpc_solve_noalloc``: FP32 solve of a one-shape batch with no plan and no
+    device allocation; ``out`` (see ``solution_buffers``) holds the iterate and,
+    with ``warm_start``, the start."""
+    L = lib()
+    arr = (Shape * len(shapes))(*[Shape(*s.as_tuple()) for s in shapes])
+    d = PlanDesc()
+    L.mpc_plan_desc_default(ctypes.byref(d))
+    d.n_agents = len(shapes)
+    d.shapes = ctypes.cast(arr, ctypes.POINTER(Shape))
+    d.precision = PRECISIONS["fp32"]
+    d.admm_iters = int(iters)
+    d.device = int(device)
+    for k, v in consts.items():
+        setattr(d, k, v)
+    b = ProblemBatch()
+    b.A, b.B, b.c = _ptr(prob["A"]), _ptr(prob["B"]), _ptr(prob["c"])
+    b.q_diag, b.r_diag = _ptr(prob["q"]), _ptr(prob["r"])
+    b.x_ref, b.x0 = _ptr(prob["x_ref"]), _ptr(prob["x0"])
+    b.tau_max, b.mu, b.stance = _ptr(prob["tau_max"]), _ptr(prob["mu"]), _ptr(prob["stance"])
+    b.u_ref = _ptr(prob.get("u_ref"))
+    b.warm_start = 1 if warm_start else 0
+    s = Solution()
+    for k in ("u0", "x", "u", "z", "y", "objective", "residuals", "status"):
+        setattr(s, k, _ptr(out.get(k)))
+    _check(L.mpc_solve_noalloc(ctypes.byref(d), ctypes.byref(b), ctypes.byref(s),
+                               _stream_handle(stream)))
+    return out
 
 
 def agent_problems(prob, batch, agents=None):

@@ -6,9 +6,13 @@ with condition number kappa in {1e2, 1e4, 1e6}.
 Bounds (norm-wise relative error per agent on u_0 and on the trajectory,
 max over the checked agents):
   after 3 refinement sweeps: FP16 1e-5, BF16 1e-3;
-  before refinement (0 sweeps): 5e-2 -- a BF16 operand alone carries a
-  relative rounding error of 2^-9, and the 16-stage recursion amplifies it to
-  about 1e-2 on these problems; refinement must gain at least 10x.
+  before refinement (0 sweeps), per precision: the 50 fixed ADMM iterations
+  magnify a relative perturbation of the x-update operators about 60-fold
+  (an FP32 Riccati recursion, operator error ~5e-7, ends at ~3e-5), so an
+  operand rounding with unit roundoff 2^-8 = 3.9e-3 (BF16; measured
+  1.6e-2 - 4.1e-2) or 2^-11 = 4.9e-4 (FP16; measured 2.9e-3 - 4.8e-3), about
+  10 unit roundoffs either way, cannot meet 1e-3 before refinement; the gates
+  are 5e-2 (BF16) and 1e-2 (FP16), and refinement must gain at least 10x.
 """
 import numpy as np
 import pytest
@@ -23,7 +27,7 @@ from test_gpu_parity import agent_errors
 pytestmark = pytest.mark.gpu
 
 AFTER = {"bf16": 1e-3, "fp16": 1e-5}
-BEFORE = 5e-2
+BEFORE = {"bf16": 5e-2, "fp16": 1e-2}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -59,7 +63,7 @@ def test_mixed_precision_error_table(kappa):
             rows.append("kappa %.0e %s sweeps %d: u0 %.2e traj %.2e (p50 %.2e)"
                         % (kappa, precision, sweeps, e[:, 0].max(), e[:, 1].max(),
                            np.median(e[:, 1])))
-        assert errs[0] < BEFORE
+        assert errs[0] < BEFORE[precision]
         assert errs[3] < AFTER[precision]
         assert errs[3] * 10 < errs[0]
     g, _ = _solve(b, "fp32", 0)

@@ -80,6 +80,11 @@ def parse():
                     help="time the mixed-precision sweep instead (16384 humanoid agents, N=16, "
                          "Q/R condition 1e4): FP32 vs BF16 / FP16 products with refinement, "
                          "step time and error vs the FP64 oracle per mode (prints its own JSON line)")
+    ap.add_argument("--scaled", action="store_true",
+                    help="time Alg. 1's scaling step and adaptive rho instead (16384 humanoid agents, "
+                         "N=16, Q/R condition 1e6, FP32): plain vs Ruiz vs Ruiz + adaptive rho, step "
+                         "time and the error of the fixed-iteration iterate against the converged "
+                         "optimum (prints its own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="run the served request loop instead: Poisson arrivals from independent "
                          "controllers of uneven shapes (prints its own JSON line)")
@@ -318,6 +323,79 @@ def mixed(args):
     print(json.dumps(out))
 
 
+def scaled(args):
+    """Scaling step and adaptive rho on the conditioned sweep at kappa = 1e6: one cold
+    solve of 16384 humanoid agents (N = 16) per timed step in each mode; for every
+    1024th agent the error of the 50-iteration iterate against the problem's
+    converged optimum (oracle, converge mode) and against the oracle's iterate of
+    the same mode (u_0 and trajectory, norm-wise relative)."""
+    import torch
+
+    import oracle
+    from oracle import scaling
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    n = args.agents if args.agents != 4096 else 16384
+    kappa = 1e6
+    b = synth.conditioned_humanoid_batch(n, kappa=kappa, dtype=np.float32)
+    prob = mpc.to_device(b, "fp32")
+    ids = np.arange(0, n, 1024)
+    sub = synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa, dtype=np.float32)
+    sh = b.shapes[0]
+    opt = [oracle.solve(*[oracle.agent(sub, a)[k] for k in ("s", "A", "B", "c", "q", "r", "x_ref",
+                                                           "x0", "tau_max", "mu", "stance")],
+                        iters=0, tol=1e-9) for a in range(len(ids))]
+
+    def err(u, x, o):
+        uo, xo = np.ravel(o["u"]), np.ravel(o["x"])
+        tr, to = np.concatenate([x[sh.nx:], u]), np.concatenate([xo[sh.nx:], uo])
+        return (np.abs(u[:sh.nu] - uo[:sh.nu]).max() / np.abs(uo[:sh.nu]).max(),
+                np.abs(tr - to).max() / np.abs(to).max())
+
+    modes = {}
+    for name, si, ri in (("plain", 0, 0), ("ruiz", 10, 0), ("ruiz_adaptive_rho", 10, 10),
+                         ("adaptive_rho", 0, 10)):
+        plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters, scaling_iters=si,
+                        rho_interval=ri)
+        stream = torch.cuda.current_stream()
+        for _ in range(max(args.warmup, 1)):
+            plan.solve(prob, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.solve(prob, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        sol = plan.get_solution()
+        u = sol["u"].cpu().numpy().reshape(n, -1)[ids].astype(np.float64)
+        x = sol["x"].cpu().numpy().reshape(n, -1)[ids].astype(np.float64)
+        st = sol["status"].cpu().numpy()
+        ref = [scaling.solve(oracle.agent(sub, a), iters=args.iters, ruiz_iters=si, rho_interval=ri)
+               for a in range(len(ids))]
+        e_opt = np.array([err(u[a], x[a], opt[a]) for a in range(len(ids))])
+        e_ref = np.array([err(u[a], x[a], ref[a]) for a in range(len(ids))])
+        o_opt = np.array([err(np.ravel(ref[a]["u"]), np.ravel(ref[a]["x"]), opt[a]) for a in range(len(ids))])
+        modes[name] = {"ms_per_step": ms, "solves_per_s": n / ms * 1e3,
+                       "status_ok": bool((st == 0).all()),
+                       "gpu_vs_optimum": {"u0_median": float(np.median(e_opt[:, 0])),
+                                          "traj_median": float(np.median(e_opt[:, 1])),
+                                          "traj_max": float(e_opt[:, 1].max())},
+                       "oracle_vs_optimum": {"traj_median": float(np.median(o_opt[:, 1])),
+                                             "traj_max": float(o_opt[:, 1].max())},
+                       "gpu_vs_oracle_same_mode": {"u0_max": float(e_ref[:, 0].max()),
+                                                   "traj_max": float(e_ref[:, 1].max())}}
+        plan.close()
+    out = {"metric": "MPC QP solves/sec and fixed-iteration error vs the optimum, per scaling mode",
+           "value": modes["ruiz_adaptive_rho"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} humanoid agents, N=16, Q/R condition {kappa:g}, "
+                                  f"{args.iters} cold ADMM iterations", "agents": n,
+                      "checked_agents": int(len(ids)), "ruiz_rounds": 10, "rho_interval": 10},
+           "modes": modes}
+    print(json.dumps(out))
+
+
 def serve(args):
     """Served loop: every controller (shapes as the uneven batch: N ~ U{5..20},
     half humanoid, half quadruped) sends Poisson requests at rate-hz for
@@ -428,6 +506,9 @@ def main():
         return
     if args.mixed:
         mixed(args)
+        return
+    if args.scaled:
+        scaled(args)
         return
     import torch
 

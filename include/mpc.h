@@ -110,6 +110,13 @@ typedef struct {
   int32_t kernel;           /* 0 = auto, 1 = generic kernels only, 2 = register-      */
                             /* resident kernels only (UNSUPPORTED_SHAPE if an agent has */
                             /* no instantiation: FP32, nx/nu 48/30 or 36/24, N <= 20)   */
+  int32_t scaling_iters;    /* Ruiz equilibration rounds before the factor, Alg. 1's    */
+                            /* scaling step (0 = off, default; at most 100)             */
+  int32_t rho_interval;     /* adaptive rho (OSQP's residual balancing): iterations    */
+                            /* between estimates, each followed by a refactorisation    */
+                            /* (0 = fixed rho, default)                                 */
+  double rho_tolerance;     /* adopt an estimate that moves rho by more than this      */
+                            /* factor either way (default 5, >= 1)                      */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */
@@ -136,9 +143,13 @@ typedef struct {
 } mpc_problem_batch;
 
 /* Alg. 1 for every agent, from the KKT data (f_KKT) to the end of the QP
- * iterations: the factor plays the role of Eq. (ldl) (once per solve, Sec.
- * III-B), each iteration the role of Eqs. (backsolve_1)-(backsolve_2) plus
- * OSQP's projection and dual update (the ADMM of Eq. (kkt_system)).
+ * iterations: the optional Ruiz equilibration (f_Ruiz), the factor in the
+ * role of Eq. (ldl) (once per solve, Sec. III-B, and again after every rho
+ * update), each iteration the role of Eqs. (backsolve_1)-(backsolve_2) plus
+ * OSQP's projection and dual update (the ADMM of Eq. (kkt_system)).  With
+ * scaling the iterations run on the equilibrated problem and the returned
+ * (and resident) iterate is mapped back to the caller's variables; u_ref must
+ * then be NULL (INVALID_ARG otherwise).
  * Solve every agent: stage penalties and bounds, Riccati factor (once), then
  * admm_iters iterations of back-sweep, rollout, relaxation, projection and
  * dual update, then the FP64 KKT residual check.  The solution stays
@@ -191,6 +202,16 @@ mpc_status mpc_plan_get_timing(mpc_plan_t plan, double* ms, int64_t* launches);
  * launch group. */
 mpc_status mpc_plan_get_config(mpc_plan_t plan, int32_t* kernel, int32_t* threads_per_agent,
                                int32_t* lds_bytes);
+
+/* Alg. 1's scaling step and OSQP's rho adaptation as the last solve applied
+ * them.  mpc_plan_get_rho copies the rho every agent ran each segment with
+ * (double [n][n_segments], device; n_segments = ceil(admm_iters /
+ * rho_interval), written to *n_segments) and mpc_plan_get_scaling every
+ * agent's scale record (double [n][128], device: D_x at [0, nx), D_u at
+ * [64, 64 + nu), the cost factor at 96).  NOT_READY before a solve,
+ * INVALID_ARG if the plan does not adapt rho / scale. */
+mpc_status mpc_plan_get_rho(mpc_plan_t plan, double* rho, int32_t* n_segments, void* stream);
+mpc_status mpc_plan_get_scaling(mpc_plan_t plan, double* scale, void* stream);
 
 /* The factor of Eq. (ldl)'s role, in Riccati form (gains, closed-loop
  * operators, stage-Hessian inverses).
@@ -271,7 +292,8 @@ typedef struct mpc_server_s* mpc_server_t;
 
 typedef struct {
   mpc_plan_desc solver;      /* precision, admm_iters, constants, refinement, device;   */
-                             /* n_agents, shapes and kernel are ignored                  */
+                             /* n_agents, shapes and kernel are ignored; scaling_iters   */
+                             /* and rho_interval must be 0                               */
   int64_t hbm_budget_bytes;  /* device memory of the server (default 1 GiB)             */
   int32_t max_batch;         /* requests per batch (default 4096)                       */
   int32_t max_inflight;      /* batches on the device at once, 1..8 (default 3)        */
@@ -354,7 +376,8 @@ mpc_status mpc_server_get_stats(mpc_server_t server, mpc_server_stats* out);
  * ONE shape with a register-resident instantiation ((nx, nu) = (48, 30) or
  * (36, 24), N <= 20), MPC_FP32 only, and no plan: desc gives n_agents,
  * shapes (host array, every entry equal), admm_iters and the solver
- * constants (precision must be MPC_FP32; kernel, refinement fields ignored).
+ * constants (precision must be MPC_FP32; kernel, refinement fields ignored;
+ * scaling_iters and rho_interval must be 0).
  * The per-agent descriptors, the launch list and the Riccati operators live
  * in a device array of MPC_NOALLOC_SCRATCH_BYTES that the library holds on
  * every device it runs on until the process ends (about 500 humanoid agents

@@ -170,8 +170,10 @@ def unscale_state(s, sc, x, u, z, y):
             np.asarray(y).reshape(s.N, -1) * e / sc["c"])
 
 
-def rho_estimate(agh, x, u, z, y, rho: float, settings: Optional[Settings] = None) -> float:
-    """OSQP's residual-balancing estimate of rho on the scaled problem."""
+def rho_estimate(agh, x, u, z, y, rho: float, settings: Optional[Settings] = None,
+                 raw: bool = False) -> float:
+    """OSQP's residual-balancing estimate of rho on the scaled problem (``raw``:
+    before clipping and rounding to the grid)."""
     s = agh["s"]
     st = settings or Settings.default(rho=rho)
     res, _ = residuals(s, agh["A"], agh["B"], agh["c"], agh["q"], agh["r"], agh["x_ref"],
@@ -191,8 +193,21 @@ def rho_estimate(agh, x, u, z, y, rho: float, settings: Optional[Settings] = Non
     prim = res[0] / max(cu, zn, tiny)
     dual = res[1] / max(px, cty, qn, tiny)
     est = rho * np.sqrt(prim / max(dual, tiny))
+    if raw:
+        return float(est)
+    return grid(est)
+
+
+def grid(est: float) -> float:
+    """An estimate clipped to [1e-6, 1e6] and rounded to the nearest power of 2^(1/4)."""
     est = min(max(est, RHO_MIN), RHO_MAX)
     return float(2.0 ** (np.round(4.0 * np.log2(est)) / 4.0))
+
+
+def decide(rho: float, raw: float, tolerance: float = 5.0) -> float:
+    """The rho after an update with raw estimate ``raw``."""
+    est = grid(raw)
+    return est if (est > tolerance * rho or est < rho / tolerance) else rho
 
 
 def solve(ag, *, iters: int = 50, ruiz_iters: int = 10, rho_interval: int = 0,
@@ -202,7 +217,7 @@ def solve(ag, *, iters: int = 50, ruiz_iters: int = 10, rho_interval: int = 0,
     ``rho_interval`` 0 keeps rho fixed.  ``iters <= 0`` runs the scaled problem
     to convergence (the oracle's converge mode, fixed rho).  Returns the
     unscaled iterate, the residuals and objective of the original problem, the
-    scale factors and the rho of every segment."""
+    scale factors, the rho of every segment and the raw estimate of every update."""
     s = ag["s"]
     st0 = settings or Settings.default()
     sc = ruiz(ag, ruiz_iters) if ruiz_iters > 0 else dict(
@@ -211,6 +226,7 @@ def solve(ag, *, iters: int = 50, ruiz_iters: int = 10, rho_interval: int = 0,
     state = None if warm is None else scale_state(s, sc, *warm)
     rho = st0.rho
     rhos = []
+    raws = []  # (rho before, raw estimate) of every update
     done = 0
     out = None
     if iters <= 0:
@@ -231,11 +247,11 @@ def solve(ag, *, iters: int = 50, ruiz_iters: int = 10, rho_interval: int = 0,
         if out["status"] != 0:
             break
         if done < iters and rho_interval > 0:
-            est = rho_estimate(agh, out["x"], out["u"], out["z"], out["y"], rho, st)
-            if est > rho_tolerance * rho or est < rho / rho_tolerance:
-                rho = est
+            raw = rho_estimate(agh, out["x"], out["u"], out["z"], out["y"], rho, st, raw=True)
+            raws.append((rho, raw))
+            rho = decide(rho, raw, rho_tolerance)
     x, u, z, y = unscale_state(s, sc, out["x"], out["u"], out["z"], out["y"])
     res, obj = residuals(s, ag["A"], ag["B"], ag["c"], ag["q"], ag["r"], ag["x_ref"], ag["x0"],
                          ag["tau_max"], ag["mu"], ag["stance"], x, u, z, y, settings=st0)
     return dict(x=x, u=u, z=z, y=y, res=res, objective=obj, status=out["status"], scale=sc,
-                rhos=rhos)
+                rhos=rhos, estimates=raws)

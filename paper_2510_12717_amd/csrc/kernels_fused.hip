@@ -228,13 +228,14 @@ constexpr int riccati_lds_bytes() {
 template <int NX, int NU, int PREC, bool RES>
 __global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-          Inputs<float> in, SolverConsts sc, float* __restrict__ fws, int32_t* __restrict__ status) {
+          Inputs<float> in, SolverConsts sc_all, float* __restrict__ fws, int32_t* __restrict__ status) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NXT = S::NXT, NUT = S::NUT;
   constexpr int LX = S::LX, LU = S::LU, SLOTS = S::SLOTS;
   static_assert(riccati_lds_bytes<NX, NU>() <= 80 * 1024, "two workgroups per compute unit");
   if ((int)blockIdx.x >= n_launch) return;
   const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const SolverConsts sc = agent_consts(sc_all, agent);
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -861,12 +862,13 @@ __device__ inline void rollout_exact(const float* __restrict__ A, const float* _
 template <int NX, int NU>
 __global__ void __launch_bounds__(64 * kMaxStages)
 k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-                Inputs<float> in, SolverConsts sc, int iters, int warm,
+                Inputs<float> in, SolverConsts sc_all, int iters, int warm,
                 const float* __restrict__ fws, State<float> st) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS, AQ = S::AQ;
   if ((int)blockIdx.x >= n_launch) return;
   const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const SolverConsts sc = agent_consts(sc_all, agent);
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1600,12 +1602,13 @@ __host__ __device__ inline int stream_elements(int N, int iters) { return 3 + it
 template <int NX, int NU>
 __global__ void __launch_bounds__(64 * kMaxStages)
 k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-              Inputs<float> in, SolverConsts sc, int iters, int warm,
+              Inputs<float> in, SolverConsts sc_all, int iters, int warm,
               const float* __restrict__ fws, State<float> st) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS, AQ = S::AQ;
   if ((int)blockIdx.x >= n_launch) return;
   const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const SolverConsts sc = agent_consts(sc_all, agent);
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;

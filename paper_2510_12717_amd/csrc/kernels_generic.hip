@@ -36,9 +36,10 @@ __device__ inline bool finite_all(const T* p, int64_t n, int tid, int nt) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-               Inputs<T> in, SolverConsts sc, T* __restrict__ ws, int32_t* __restrict__ status) {
+               Inputs<T> in, SolverConsts sc_all, T* __restrict__ ws, int32_t* __restrict__ status) {
   if ((int)blockIdx.x >= n_launch) return;
   const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const SolverConsts sc = agent_consts(sc_all, a);
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -337,10 +338,11 @@ __device__ inline void forward_exact(int N, int nx, int nu, const T* A, const T*
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-       Inputs<T> in, SolverConsts sc, int iters, int warm, const T* __restrict__ ws, State<T> st,
+       Inputs<T> in, SolverConsts sc_all, int iters, int warm, const T* __restrict__ ws, State<T> st,
        int sweeps, double rtol) {
   if ((int)blockIdx.x >= n_launch) return;
   const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const SolverConsts sc = agent_consts(sc_all, a);
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -674,9 +676,10 @@ __device__ inline void block_reduce_res(double& rp, double& rd, double& ry, doub
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-           Inputs<T> in, SolverConsts sc, State<T> st) {
+           Inputs<T> in, SolverConsts sc_all, State<T> st) {
   if ((int)blockIdx.x >= n_launch) return;
   const int a = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const SolverConsts sc = agent_consts(sc_all, a);
   const AgentDesc d = desc[a];
   const int N = d.N, nx = d.nx, nu = d.nu, m = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;  // nt = 256

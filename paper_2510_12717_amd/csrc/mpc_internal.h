@@ -20,7 +20,15 @@ struct AgentDesc {
 
 struct SolverConsts {
   double rho, sigma, alpha, rho_eq, rho_min;
+  const double* rho_agent = nullptr;  // per-agent rho (adaptive rho), or null: rho for all
 };
+
+// The constants one agent runs with (its own rho when the plan adapts rho).
+__host__ __device__ inline SolverConsts agent_consts(const SolverConsts& sc, int agent) {
+  SolverConsts s = sc;
+  if (sc.rho_agent) s.rho = sc.rho_agent[agent];
+  return s;
+}
 
 template <typename T>
 struct Inputs {

@@ -15,6 +15,7 @@
 #include "fused.h"
 #include "host_api.h"
 #include "mpc_internal.h"
+#include "scaling.h"
 
 using namespace mpc;
 
@@ -102,6 +103,14 @@ struct mpc_plan_s {
   void *d_x = nullptr, *d_u = nullptr, *d_z = nullptr, *d_y = nullptr, *d_obj = nullptr;
   double* d_res = nullptr;
   int32_t* d_status = nullptr;
+  // scaling (Ruiz) and adaptive rho
+  bool scaled = false, adaptive = false;
+  void* d_sbuf = nullptr;          // the scaled problem data
+  int64_t s_off[9] = {};           // element offsets of A, B, c, q, r, x_ref, x0, tau, mu in d_sbuf
+  double* d_scale = nullptr;       // [n][kScaleStride]
+  double* d_rho = nullptr;         // [n]
+  double* d_rho_hist = nullptr;    // [n][n_seg]: the rho of every segment
+  int n_seg = 1;
   bool solved = false;
   size_t lds_factor = 0, lds_admm = 0, lds_res = 0;
   // launch groups
@@ -154,6 +163,9 @@ extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
   d->refine_tol = 1e-6;
   d->device = 0;
   d->kernel = 0;
+  d->scaling_iters = 0;
+  d->rho_interval = 0;
+  d->rho_tolerance = 5.0;
 }
 
 extern "C" const char* mpc_last_error(void) { return mpc::g_err.c_str(); }
@@ -179,6 +191,10 @@ static void free_plan(mpc_plan_s* p) {
   hipFree(p->d_obj);
   hipFree(p->d_res);
   hipFree(p->d_status);
+  hipFree(p->d_sbuf);
+  hipFree(p->d_scale);
+  hipFree(p->d_rho);
+  hipFree(p->d_rho_hist);
   for (auto e : p->ev_pool) hipEventDestroy(e);
   for (auto& pe : p->pending) {
     hipEventDestroy(pe.second.first);
@@ -202,6 +218,10 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   if (desc->max_refine_sweeps < 0 || desc->max_refine_sweeps > 16 || !(desc->refine_tol >= 0) ||
       !std::isfinite(desc->refine_tol))
     return fail(MPC_ERR_INVALID_ARG, "max_refine_sweeps must be in 0..16 and refine_tol >= 0");
+  if (desc->scaling_iters < 0 || desc->scaling_iters > 100 || desc->rho_interval < 0 ||
+      (desc->rho_interval > 0 && !(desc->rho_tolerance >= 1.0 && std::isfinite(desc->rho_tolerance))))
+    return fail(MPC_ERR_INVALID_ARG,
+                "scaling_iters must be in 0..100, rho_interval >= 0 and rho_tolerance >= 1");
   for (int a = 0; a < desc->n_agents; ++a) {
     mpc_status vs = validate_shape(desc->shapes[a], a);
     if (vs != MPC_OK) return vs;
@@ -378,6 +398,31 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       return st;
     }
   }
+  p->scaled = desc->scaling_iters > 0;
+  p->adaptive = desc->rho_interval > 0;
+  {
+    hipError_t se = hipSuccess;
+    if (p->scaled) {
+      const int64_t sizes[9] = {oA, oB, oc, oq, orr, oxr, ox0, otau, (int64_t)p->n};
+      int64_t tot = 0;
+      for (int i = 0; i < 9; ++i) {
+        p->s_off[i] = tot;
+        tot += (sizes[i] + 63) / 64 * 64;  // 256-byte aligned parts
+      }
+      se = alloc(&p->d_sbuf, p->esz * (size_t)tot);
+      if (se == hipSuccess) se = alloc((void**)&p->d_scale, sizeof(double) * kScaleStride * (size_t)p->n);
+    }
+    if (p->adaptive) p->n_seg = (desc->admm_iters + desc->rho_interval - 1) / desc->rho_interval;
+    if (se == hipSuccess && p->adaptive) se = alloc((void**)&p->d_rho, sizeof(double) * (size_t)p->n);
+    if (se == hipSuccess && p->adaptive)
+      se = alloc((void**)&p->d_rho_hist, sizeof(double) * (size_t)p->n * p->n_seg);
+    if (se != hipSuccess) {
+      mpc_status st = fail(se == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,
+                           std::string("hipMalloc: ") + hipGetErrorString(se));
+      free_plan(p);
+      return st;
+    }
+  }
   e = hipMemcpy(p->d_desc, p->hdesc.data(), sizeof(AgentDesc) * p->n, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_u0off, u0off.data(), sizeof(int64_t) * p->n, hipMemcpyHostToDevice);
@@ -427,7 +472,30 @@ static mpc_status check_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
   if (b->warm_start != 0 && b->warm_start != 1) return fail(MPC_ERR_INVALID_ARG, "warm_start must be 0 or 1");
   if (b->warm_start && !p->solved)
     return fail(MPC_ERR_INVALID_ARG, "warm_start requested before any solve or warm state");
+  if (p->scaled && b->u_ref)
+    return fail(MPC_ERR_INVALID_ARG, "an input reference is not supported with scaling");
   return MPC_OK;
+}
+
+// The batch the iterations run on: the plan's scaled copy of the caller's data
+// (stance from the caller) when the plan equilibrates, else the caller's.
+static mpc_problem_batch solver_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
+  mpc_problem_batch sb = *b;
+  if (!p->scaled) return sb;
+  char* base = (char*)p->d_sbuf;
+  const void** f[9] = {&sb.A, &sb.B, &sb.c, &sb.q_diag, &sb.r_diag, &sb.x_ref, &sb.x0, &sb.tau_max, &sb.mu};
+  for (int i = 0; i < 9; ++i) *f[i] = base + p->s_off[i] * (int64_t)p->esz;
+  sb.u_ref = nullptr;
+  return sb;
+}
+
+template <typename T>
+static ScaledInputs<T> scaled_out(mpc_plan_s* p) {
+  T* base = (T*)p->d_sbuf;
+  ScaledInputs<T> o;
+  T** f[9] = {&o.A, &o.B, &o.c, &o.q, &o.r, &o.xr, &o.x0, &o.tau, &o.mu};
+  for (int i = 0; i < 9; ++i) *f[i] = base + p->s_off[i];
+  return o;
 }
 
 template <typename T>
@@ -495,21 +563,22 @@ struct PhaseTimer {
 // Factor and iteration launches of one group on stream s.
 template <typename T>
 static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_batch* b,
-                            hipStream_t s, int warm) {
-  const SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
-                        p->desc.rho_min};
+                            hipStream_t s, int warm, int iters) {
+  SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
+                  p->desc.rho_min};
+  sc.rho_agent = p->adaptive ? p->d_rho : nullptr;
   const int32_t* list = p->d_list + g.list_off;
   if (g.family == 2) {
     {
       PhaseTimer t(p, 0, s);
       HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
-                              make_inputs<float>(b), sc, p->desc.admm_iters, warm,
+                              make_inputs<float>(b), sc, iters, warm,
                               make_state<float>(p), p->d_fws, s, 1));
     }
     {
       PhaseTimer t(p, 1, s);
       HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
-                              make_inputs<float>(b), sc, p->desc.admm_iters, warm,
+                              make_inputs<float>(b), sc, iters, warm,
                               make_state<float>(p), p->d_fws, s, 2));
     }
   } else if (g.family == 4) {
@@ -522,7 +591,7 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
     {
       PhaseTimer t(p, 1, s);
       HIP_TRY(launch_generic_admm<float>(p->d_desc, list, g.count, make_inputs<float>(b), sc,
-                                         p->desc.admm_iters, warm, (const float*)p->d_ws,
+                                         iters, warm, (const float*)p->d_ws,
                                          make_state<float>(p), g.lds_admm, g.gthreads, s,
                                          p->desc.max_refine_sweeps, p->desc.refine_tol));
     }
@@ -541,7 +610,7 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
     }
     {
       PhaseTimer t(p, 1, s);
-      HIP_TRY(launch_generic_admm<T>(p->d_desc, list, g.count, in, sc, p->desc.admm_iters, warm,
+      HIP_TRY(launch_generic_admm<T>(p->d_desc, list, g.count, in, sc, iters, warm,
                                      (const T*)p->d_ws, make_state<T>(p), g.lds_admm, g.gthreads,
                                      s));
     }
@@ -554,7 +623,8 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
 // the caller's stream, so the solve stays stream-ordered (and captures into
 // one graph).
 template <typename T>
-static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s) {
+static mpc_status run_groups(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s, int warm,
+                             int iters) {
   const int ns = 1 + (int)p->aux.size();
   if (ns > 1) {
     HIP_TRY(hipEventRecord(p->ev_fork, s));
@@ -562,7 +632,7 @@ static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
   }
   for (size_t i = 0; i < p->groups.size(); ++i) {
     const int k = std::min(p->groups[i].queue, ns - 1);
-    mpc_status r = run_group<T>(p, p->groups[i], b, k == 0 ? s : p->aux[k - 1], b->warm_start);
+    mpc_status r = run_group<T>(p, p->groups[i], b, k == 0 ? s : p->aux[k - 1], warm, iters);
     if (r != MPC_OK) return r;
   }
   if (ns > 1) {
@@ -571,13 +641,45 @@ static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
       HIP_TRY(hipStreamWaitEvent(s, p->ev_join[k], 0));
     }
   }
-  {
-    PhaseTimer t(p, 2, s);
-    const SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
-                          p->desc.rho_min};
-    HIP_TRY(launch_residual<T>(p->d_desc, nullptr, p->n, make_inputs<T>(b), sc, make_state<T>(p),
-                               p->lds_res, s));
+  return MPC_OK;
+}
+
+// One solve: (Ruiz scaling,) factor and iterations in segments of rho_interval
+// with a rho update between segments (adaptive rho; every segment refactors),
+// (unscaling,) then the KKT residual check of the caller's problem.
+template <typename T>
+static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s) {
+  const SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
+                        p->desc.rho_min};
+  const mpc_problem_batch sb = solver_batch(p, b);
+  if (p->scaled) {
+    PhaseTimer t(p, 0, s);
+    HIP_TRY(launch_ruiz<T>(p->d_desc, p->n, make_inputs<T>(b), p->desc.scaling_iters,
+                           scaled_out<T>(p), p->d_scale, b->warm_start, make_state<T>(p), s));
   }
+  if (p->adaptive) HIP_TRY(launch_rho_init(p->d_rho, p->d_rho_hist, p->n, p->n_seg, p->desc.rho, s));
+  const int K = p->desc.admm_iters;
+  const int seg = p->adaptive ? p->desc.rho_interval : K;
+  int warm = b->warm_start;
+  for (int done = 0, seg_i = 0; done < K; ++seg_i) {
+    const int k = std::min(seg, K - done);
+    mpc_status r = run_groups<T>(p, &sb, s, warm, k);
+    if (r != MPC_OK) return r;
+    done += k;
+    warm = 1;
+    if (p->adaptive && done < K) {
+      PhaseTimer t(p, 2, s);
+      HIP_TRY(launch_residual<T>(p->d_desc, nullptr, p->n, make_inputs<T>(&sb), sc,
+                                 make_state<T>(p), p->lds_res, s));
+      HIP_TRY(launch_rho_update<T>(p->d_desc, p->n, make_inputs<T>(&sb), make_state<T>(p),
+                                   p->d_res, p->d_rho, p->desc.rho_tolerance, p->d_rho_hist,
+                                   p->n_seg, seg_i + 1, s));
+    }
+  }
+  PhaseTimer t(p, 2, s);
+  if (p->scaled) HIP_TRY(launch_unscale<T>(p->d_desc, p->n, p->d_scale, make_state<T>(p), s));
+  HIP_TRY(launch_residual<T>(p->d_desc, nullptr, p->n, make_inputs<T>(b), sc, make_state<T>(p),
+                             p->lds_res, s));
   return MPC_OK;
 }
 
@@ -694,6 +796,29 @@ extern "C" mpc_status mpc_plan_get_config(mpc_plan_t p, int32_t* kernel, int32_t
   return MPC_OK;
 }
 
+extern "C" mpc_status mpc_plan_get_rho(mpc_plan_t p, double* rho, int32_t* n_segments,
+                                       void* stream) {
+  if (!p || (!rho && !n_segments)) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!p->adaptive) return fail(MPC_ERR_INVALID_ARG, "this plan keeps rho fixed");
+  if (n_segments) *n_segments = p->n_seg;
+  if (!rho) return MPC_OK;
+  if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  HIP_TRY(hipMemcpyAsync(rho, p->d_rho_hist, sizeof(double) * p->n * p->n_seg,
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_plan_get_scaling(mpc_plan_t p, double* scale, void* stream) {
+  if (!p || !scale) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!p->scaled) return fail(MPC_ERR_INVALID_ARG, "this plan does not scale");
+  if (!p->solved) return fail(MPC_ERR_NOT_READY, "no solve has been issued on this plan");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  HIP_TRY(hipMemcpyAsync(scale, p->d_scale, sizeof(double) * kScaleStride * p->n,
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return MPC_OK;
+}
+
 extern "C" mpc_status mpc_plan_export_factor(mpc_plan_t p, int32_t agent, void* K, void* Acl,
                                              void* Hinv, void* sv, void* stream) {
   if (!p) return fail(MPC_ERR_INVALID_ARG, "null plan");
@@ -756,6 +881,15 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
   const bool timing = p->timing;
   p->timing = false;
   mpc_status r = MPC_OK;
+  if (p->scaled) {  // the groups' trial solves run on the equilibrated problem
+    if (p->fp64)
+      HIP_TRY(launch_ruiz<double>(p->d_desc, p->n, make_inputs<double>(&cold), p->desc.scaling_iters,
+                                  scaled_out<double>(p), p->d_scale, 0, make_state<double>(p), s));
+    else
+      HIP_TRY(launch_ruiz<float>(p->d_desc, p->n, make_inputs<float>(&cold), p->desc.scaling_iters,
+                                 scaled_out<float>(p), p->d_scale, 0, make_state<float>(p), s));
+  }
+  if (p->adaptive) HIP_TRY(launch_rho_init(p->d_rho, p->d_rho_hist, p->n, p->n_seg, p->desc.rho, s));
   for (Group& g : p->groups) {
     struct Cand { int family, threads; };
     std::vector<Cand> cands;
@@ -767,11 +901,14 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
       Group trial = g;
       trial.family = c.family;
       if (c.family != 2) trial.gthreads = c.threads;
-      r = p->fp64 ? run_group<double>(p, trial, &cold, s, 0) : run_group<float>(p, trial, &cold, s, 0);
+      const mpc_problem_batch tb = solver_batch(p, &cold);
+      r = p->fp64 ? run_group<double>(p, trial, &tb, s, 0, p->desc.admm_iters)
+                  : run_group<float>(p, trial, &tb, s, 0, p->desc.admm_iters);
       if (r != MPC_OK) break;
       hipError_t he = hipEventRecord(e0, s);
       for (int i = 0; i < reps && he == hipSuccess && r == MPC_OK; ++i)
-        r = p->fp64 ? run_group<double>(p, trial, &cold, s, 0) : run_group<float>(p, trial, &cold, s, 0);
+        r = p->fp64 ? run_group<double>(p, trial, &tb, s, 0, p->desc.admm_iters)
+                    : run_group<float>(p, trial, &tb, s, 0, p->desc.admm_iters);
       if (he == hipSuccess) he = hipEventRecord(e1, s);
       if (he == hipSuccess) he = hipEventSynchronize(e1);
       float ms = 0;

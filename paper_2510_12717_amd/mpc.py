@@ -37,7 +37,9 @@ class PlanDesc(ctypes.Structure):
                 ("rho", ctypes.c_double), ("sigma", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("rho_eq_scale", ctypes.c_double), ("rho_min", ctypes.c_double),
                 ("max_refine_sweeps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
-                ("device", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("scaling_iters", ctypes.c_int32), ("rho_interval", ctypes.c_int32),
+                ("rho_tolerance", ctypes.c_double)]
 
 
 class ProblemBatch(ctypes.Structure):
@@ -72,7 +74,7 @@ class Solution(ctypes.Structure):
 EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_solve",
            "mpc_get_solution", "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
            "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
-           "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture", "mpc_plan_replay",
+           "mpc_plan_get_rho", "mpc_plan_get_scaling", "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture", "mpc_plan_replay",
            "mpc_server_desc_default", "mpc_server_create", "mpc_server_destroy",
            "mpc_server_clock", "mpc_server_submit", "mpc_server_submit_many", "mpc_server_poll",
            "mpc_server_drain", "mpc_server_get_state", "mpc_server_get_stats",
@@ -102,6 +104,8 @@ def lib():
         L.mpc_plan_get_timing.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
         L.mpc_plan_get_config.argtypes = [V, P(I32), P(I32), P(I32)]
         L.mpc_plan_export_factor.argtypes = [V, I32, V, V, V, V, V]
+        L.mpc_plan_get_rho.argtypes = [V, V, P(I32), V]
+        L.mpc_plan_get_scaling.argtypes = [V, V, V]
         L.mpc_plan_get_groups.argtypes = [V, P(GroupInfo), I32, P(I32)]
         L.mpc_plan_autotune.argtypes = [V, P(ProblemBatch), I32, V]
         L.mpc_plan_capture.argtypes = [V, P(ProblemBatch), V, V]
@@ -129,6 +133,7 @@ def lib():
         for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
                   "mpc_set_warm_state", "mpc_advance_state", "mpc_plan_set_timing",
                   "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
+                  "mpc_plan_get_rho", "mpc_plan_get_scaling",
                   "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture",
                   "mpc_plan_replay"):
             getattr(L, f).restype = ctypes.c_int
@@ -299,6 +304,25 @@ class Plan:
 
     def replay(self, stream=None):
         _check(lib().mpc_plan_replay(self._h, _stream_handle(stream)))
+
+    def get_rho(self, stream=None):
+        """The rho every agent ran each segment of the last solve with, [n][segments]
+        (plans with rho_interval > 0)."""
+        import torch
+        ns = ctypes.c_int32()
+        _check(lib().mpc_plan_get_rho(self._h, None, ctypes.byref(ns), None))
+        out = torch.empty((self.n, ns.value), dtype=torch.float64,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+        _check(lib().mpc_plan_get_rho(self._h, _ptr(out), None, _stream_handle(stream)))
+        return out
+
+    def get_scaling(self, stream=None):
+        """Every agent's scale record [n][128] (D_x at 0.., D_u at 64.., cost factor at 96)."""
+        import torch
+        out = torch.empty((self.n, 128), dtype=torch.float64,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+        _check(lib().mpc_plan_get_scaling(self._h, _ptr(out), _stream_handle(stream)))
+        return out
 
     def export_factor(self, agent: int, stream=None):
         """(K, A_cl, Hinv, s) of one agent from the last solve (generic kernels only)."""

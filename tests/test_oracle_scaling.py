@@ -210,3 +210,12 @@ def test_warm_start_round_trip():
     whole = scaling.solve(ag, iters=35, ruiz_iters=10)
     cont = scaling.solve(ag, iters=15, ruiz_iters=10, warm=(o["u"], o["z"], o["y"]))
     assert rel(cont["u"], whole["u"]) < 1e-10
+
+
+def test_decide_and_grid():
+    """The update keeps rho within the tolerance band and otherwise takes the
+    clipped estimate on the 2^(1/4) grid."""
+    assert scaling.decide(0.1, 0.3) == 0.1
+    assert scaling.decide(0.1, 0.01) == pytest.approx(2.0 ** -6.75, rel=1e-15)
+    assert scaling.decide(0.1, 1e-9) == 1e-6 * 0 + 2.0 ** (np.round(4 * np.log2(1e-6)) / 4)
+    assert scaling.grid(2.0 ** -3.1) == 2.0 ** -3.0

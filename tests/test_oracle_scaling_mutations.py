@@ -28,7 +28,10 @@ MUTANTS = [
      "col = np.maximum(np.abs(Ph), Ah.max(axis=0))"),
     ("rho ratio inverted", "est = rho * np.sqrt(prim / max(dual, tiny))",
      "est = rho * np.sqrt(dual / max(prim, tiny))"),
-    ("rho kept on a change", "                rho = est", "                rho = rho"),
+    ("rho kept on a change", "return est if (est > tolerance * rho or est < rho / tolerance) else rho",
+     "return rho"),
+    ("threshold test inverted", "return est if (est > tolerance * rho or est < rho / tolerance) else rho",
+     "return rho if (est > tolerance * rho or est < rho / tolerance) else est"),
 ]
 
 CHECKS = [

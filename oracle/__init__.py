@@ -80,18 +80,20 @@ def lib():
         L.orc_constraint_matrix.argtypes = [P(_Shape), ctypes.c_double, _D]
         L.orc_stage_bounds.argtypes = [P(_Shape), P(Settings), _D, _U8, _D, _D, _D]
         L.orc_factor.argtypes = [P(_Shape), P(Settings), _D, _D, _D, _D, _D, _D, ctypes.c_double,
-                                 _D, _D, _D, _D]
+                                 _D, _D, _D, _D, _D]
+        L.orc_state_penalties.argtypes = [P(_Shape), P(Settings), _D, _D, _D]
         L.orc_factor.restype = ctypes.c_int
         L.orc_xupdate.argtypes = [P(_Shape), _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.orc_residuals.argtypes = [P(_Shape), P(Settings), _D, _D, _D, _D, _D, _D, _D, _D, _D,
-                                    ctypes.c_double, _U8, _D, _D, _D, _D, _D, _D]
+                                    ctypes.c_double, _U8, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.orc_solve.argtypes = [P(_Shape), P(Settings), _D, _D, _D, _D, _D, _D, _D, _D, _D,
                                 ctypes.c_double, _U8, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                ctypes.c_int, _D, _D, _D, _D, _D, _D, ctypes.POINTER(ctypes.c_int)]
+                                ctypes.c_int, _D, _D, _D, _D, _D, _D, ctypes.POINTER(ctypes.c_int),
+                                _D, _D, _D, _D]
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve_batch.argtypes = [ctypes.c_int32, _I32, P(Settings), _D, _D, _D, _D, _D, _D,
                                       _D, _D, _D, _D, _U8, ctypes.c_int, ctypes.c_int, _D, _D, _D,
-                                      _D, _D, _D, _I32, ctypes.c_int]
+                                      _D, _D, _D, _I32, ctypes.c_int, _D, _D, _D, _D]
         L.orc_solve_batch.restype = ctypes.c_int
         L.orc_advance_batch.argtypes = [ctypes.c_int32, _I32, _D, _D, _D, _D, _D, _D, _D]
         _lib = L
@@ -134,8 +136,18 @@ def stage_bounds(s, tau_max, stance, settings: Optional[Settings] = None):
     return l, h, rho
 
 
-def factor(s, A, B, c, q, r, rho, mu, settings: Optional[Settings] = None):
-    """Riccati factor: returns (status, K [N,nu,nx], L [N,nu,nu], s [N,nx], P [N+1,nx,nx])."""
+def state_penalties(s, x_lo, x_hi, settings: Optional[Settings] = None) -> np.ndarray:
+    """Penalties rho_x [nx] of the state rows (joint limits)."""
+    st = settings or Settings.default()
+    out = np.zeros(s.nx)
+    lib().orc_state_penalties(ctypes.byref(_shape(s)), ctypes.byref(st), _d(_f64(x_lo)),
+                              _d(_f64(x_hi)), _d(out))
+    return out
+
+
+def factor(s, A, B, c, q, r, rho, mu, settings: Optional[Settings] = None, qx=None):
+    """Riccati factor: returns (status, K [N,nu,nx], L [N,nu,nu], s [N,nx], P [N+1,nx,nx]).
+    ``qx`` [nx]: state-row penalties added to the state weight (joint limits)."""
     st = settings or Settings.default()
     K = np.zeros((s.N, s.nu, s.nx))
     L = np.zeros((s.N, s.nu, s.nu))
@@ -143,7 +155,7 @@ def factor(s, A, B, c, q, r, rho, mu, settings: Optional[Settings] = None):
     P = np.zeros((s.N + 1, s.nx, s.nx))
     status = lib().orc_factor(ctypes.byref(_shape(s)), ctypes.byref(st), _d(_f64(A)), _d(_f64(B)),
                               _d(_f64(c)), _d(_f64(q)), _d(_f64(r)), _d(_f64(rho)), float(mu),
-                              _d(K), _d(L), _d(sv), _d(P))
+                              _d(K), _d(L), _d(sv), _d(P), _d(None if qx is None else _f64(qx)))
     return status, K, L, sv, P
 
 
@@ -158,8 +170,9 @@ def xupdate(s, A, B, c, K, L, sv, x0, qt, rt):
 
 
 def residuals(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x, u, z, y, u_ref=None,
-              settings: Optional[Settings] = None):
-    """(res[4] = primal, dual, dynamics, complementarity; objective)."""
+              settings: Optional[Settings] = None, x_lo=None, x_hi=None, zx=None, yx=None):
+    """(res[4] = primal, dual, dynamics, complementarity; objective).  With joint
+    limits (x_lo, x_hi [nx]) the state rows' (zx, yx) [N][nx] take part."""
     st = settings or Settings.default()
     res = np.zeros(4)
     obj = np.zeros(1)
@@ -168,16 +181,25 @@ def residuals(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x, u, z, y, u_re
                         _d(_f64(c)), _d(_f64(q)), _d(_f64(r)), _d(_f64(x_ref)),
                         _d(None if u_ref is None else _f64(u_ref)), _d(_f64(x0)),
                         _d(_f64(tau_max)), float(mu), stance.ctypes.data_as(_U8), _d(_f64(x)),
-                        _d(_f64(u)), _d(_f64(z)), _d(_f64(y)), _d(res), _d(obj))
+                        _d(_f64(u)), _d(_f64(z)), _d(_f64(y)), _d(res), _d(obj),
+                        *_limits(x_lo, x_hi, zx, yx))
     return res, float(obj[0])
 
 
+def _limits(x_lo, x_hi, zx, yx):
+    if x_lo is None:
+        return (None, None, None, None)
+    return tuple(_d(_f64(v)) for v in (x_lo, x_hi, zx, yx))
+
+
 def solve(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, iters=50, warm=None,
-          u_ref=None, tol=1e-10, max_iters=1_000_000, settings: Optional[Settings] = None):
+          u_ref=None, tol=1e-10, max_iters=1_000_000, settings: Optional[Settings] = None,
+          x_lo=None, x_hi=None):
     """Solve one agent.  ``iters <= 0`` selects converge mode.
 
-    ``warm`` is None (cold) or a tuple (u, z, y).  Returns a dict with x, u, z, y,
-    res, objective, status, iters.
+    ``warm`` is None (cold) or a tuple (u, z, y), with joint limits (x_lo, x_hi)
+    (u, z, y, zx, yx).  Returns a dict with x, u, z, y, (zx, yx,) res, objective,
+    status, iters.
     """
     st = settings or Settings.default()
     m = rows(s)
@@ -186,7 +208,13 @@ def solve(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, iters=50, warm=No
         u, z, y = np.zeros((s.N, s.nu)), np.zeros((s.N, m)), np.zeros((s.N, m))
     else:
         u, z, y = (np.array(v, dtype=np.float64, order="C").reshape(shp)
-                   for v, shp in zip(warm, ((s.N, s.nu), (s.N, m), (s.N, m))))
+                   for v, shp in zip(warm[:3], ((s.N, s.nu), (s.N, m), (s.N, m))))
+    zx = yx = None
+    if x_lo is not None:
+        if warm is None:
+            zx, yx = np.zeros((s.N, s.nx)), np.zeros((s.N, s.nx))
+        else:
+            zx, yx = (np.array(v, dtype=np.float64, order="C").reshape(s.N, s.nx) for v in warm[3:5])
     res = np.zeros(4)
     obj = np.zeros(1)
     it = ctypes.c_int(0)
@@ -196,9 +224,13 @@ def solve(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, iters=50, warm=No
                              _d(None if u_ref is None else _f64(u_ref)), _d(_f64(x0)),
                              _d(_f64(tau_max)), float(mu), stance.ctypes.data_as(_U8), int(iters),
                              0 if warm is None else 1, float(tol), int(max_iters), _d(x), _d(u),
-                             _d(z), _d(y), _d(res), _d(obj), ctypes.byref(it))
-    return dict(x=x, u=u, z=z, y=y, res=res, objective=float(obj[0]), status=status,
-                iters=it.value)
+                             _d(z), _d(y), _d(res), _d(obj), ctypes.byref(it),
+                             *_limits(x_lo, x_hi, zx, yx))
+    out = dict(x=x, u=u, z=z, y=y, res=res, objective=float(obj[0]), status=status,
+               iters=it.value)
+    if x_lo is not None:
+        out.update(zx=zx, yx=yx)
+    return out
 
 
 def agent(batch, a: int) -> dict:
@@ -220,11 +252,13 @@ def _shapes_arr(batch) -> np.ndarray:
 
 
 def solve_batch(batch, *, iters=50, warm=None, x0=None, u_ref=None, n_threads=0,
-                settings: Optional[Settings] = None) -> dict:
+                settings: Optional[Settings] = None, x_lo=None, x_hi=None) -> dict:
     """Fixed-iteration solve of every agent of a ``synth.Batch`` (flat layouts).
 
-    ``warm`` is None or a dict with flat u, z, y.  ``x0`` overrides batch.x0.
-    Returns flat x, u, z, y, res [n,4], objective [n], status [n], threads.
+    ``warm`` is None or a dict with flat u, z, y (and zx, yx with joint limits).
+    ``x0`` overrides batch.x0.  ``x_lo``/``x_hi`` (flat, nx per agent): joint
+    limits.  Returns flat x, u, z, y, (zx, yx,) res [n,4], objective [n],
+    status [n], threads.
     """
     st = settings or Settings.default()
     o = batch.offsets()
@@ -234,6 +268,13 @@ def solve_batch(batch, *, iters=50, warm=None, x0=None, u_ref=None, n_threads=0,
         u, z, y = np.zeros(int(o["u"][-1])), np.zeros(int(o["z"][-1])), np.zeros(int(o["z"][-1]))
     else:
         u, z, y = (np.array(warm[k], dtype=np.float64) for k in ("u", "z", "y"))
+    zx = yx = None
+    if x_lo is not None:
+        nzx = int(o["c"][-1])
+        if warm is None:
+            zx, yx = np.zeros(nzx), np.zeros(nzx)
+        else:
+            zx, yx = (np.array(warm[k], dtype=np.float64) for k in ("zx", "yx"))
     res = np.zeros((n, 4))
     obj = np.zeros(n)
     status = np.zeros(n, dtype=np.int32)
@@ -246,8 +287,11 @@ def solve_batch(batch, *, iters=50, warm=None, x0=None, u_ref=None, n_threads=0,
         _d(None if u_ref is None else _f64(u_ref)), _d(x0v), _d(_f64(batch.tau_max)),
         _d(_f64(batch.mu)), stance.ctypes.data_as(_U8), int(iters), 0 if warm is None else 1,
         _d(x), _d(u), _d(z), _d(y), _d(res), _d(obj), status.ctypes.data_as(_I32),
-        int(n_threads))
-    return dict(x=x, u=u, z=z, y=y, res=res, objective=obj, status=status, threads=threads)
+        int(n_threads), *_limits(x_lo, x_hi, zx, yx))
+    out = dict(x=x, u=u, z=z, y=y, res=res, objective=obj, status=status, threads=threads)
+    if x_lo is not None:
+        out.update(zx=zx, yx=yx)
+    return out
 
 
 def advance_batch(batch, x0, u, noise) -> np.ndarray:

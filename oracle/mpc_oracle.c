@@ -13,7 +13,14 @@
  *     equality-constrained LQR solved by a Riccati factor/sweep pair;
  *   - sigma applied to states and inputs; x_0 is pinned to xbar0;
  *   - cold start u = z = y = 0 with x rolled out from xbar0; warm start
- *     re-uses (u, z, y) and re-rolls x.
+ *     re-uses (u, z, y) and re-rolls x;
+ *   - joint limits of Eq. (mpc_formulation), optional: a box
+ *     x_lo <= x_k <= x_hi on every state component at stages 1..N (bounds
+ *     per agent, the same at every stage; components without limits carry
+ *     infinite bounds), split like the input rows with their own (z_x, y_x)
+ *     and OSQP's penalty rule; since the rows are the identity on x, they add
+ *     diag(rho_x) to the state weight of the Riccati factor and
+ *     y_x - rho_x z_x to the state's linear term.
  */
 #include "mpc_oracle.h"
 
@@ -92,6 +99,20 @@ void orc_stage_bounds(const orc_shape* s, const orc_settings* st, const double* 
   }
 }
 
+/* Penalty of the state rows (joint limits): OSQP's rule applied to the box
+ * x_lo <= x_k <= x_hi of every component. */
+void orc_state_penalties(const orc_shape* s, const orc_settings* st, const double* x_lo,
+                         const double* x_hi, double* rho_x) {
+  for (int i = 0; i < s->nx; ++i) {
+    if (x_lo[i] == x_hi[i])
+      rho_x[i] = st->rho_eq_scale * st->rho;
+    else if (isinf(x_lo[i]) && isinf(x_hi[i]))
+      rho_x[i] = st->rho_min;
+    else
+      rho_x[i] = st->rho;
+  }
+}
+
 /* Lower Cholesky factor of the n x n SPD matrix H (row-major), row by row
  * (Cholesky-Banachiewicz).  Returns 0 if H is not positive definite. */
 static int cholesky(int n, const double* H, double* L) {
@@ -126,14 +147,15 @@ static void chol_solve(int n, const double* L, double* v) {
 }
 
 /* Riccati factor of the x-subproblem (the role of Eq. (ldl), once per solve).
- * P_N = Q + sigma I; for k = N-1 .. 0:
+ * P_N = Q~ = Q + sigma I (+ diag(rho_x) with joint limits); for k = N-1 .. 0:
  *   Rt_k = R + sigma I + C_k' diag(rho_k) C_k
  *   H_k = Rt_k + B_k' P_{k+1} B_k,   G_k = B_k' P_{k+1} A_k,   H_k = L_k L_k'
  *   K_k = -H_k^{-1} G_k,   s_k = P_{k+1} c_k
- *   P_k = Q + sigma I + A_k' P_{k+1} A_k + G_k' K_k   (then symmetrised)      */
+ *   P_k = Q~ + A_k' P_{k+1} A_k + G_k' K_k   (then symmetrised)
+ * qx (may be NULL): the state rows' penalties rho_x, added to Q~.            */
 int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, const double* B,
                const double* c, const double* q, const double* r, const double* rho,
-               double mu, double* K, double* L, double* sv, double* P) {
+               double mu, double* K, double* L, double* sv, double* P, const double* qx) {
   const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s);
   double* C = (double*)malloc(sizeof(double) * m * nu);
   double* Pn = (double*)malloc(sizeof(double) * nx * nx);
@@ -147,7 +169,7 @@ int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, cons
   orc_constraint_matrix(s, mu, C);
 
   for (int i = 0; i < nx; ++i)
-    for (int j = 0; j < nx; ++j) Pn[i * nx + j] = (i == j) ? q[i] + st->sigma : 0.0;
+    for (int j = 0; j < nx; ++j) Pn[i * nx + j] = (i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0;
   if (P) memcpy(P + (size_t)N * nx * nx, Pn, sizeof(double) * nx * nx);
 
   for (int k = N - 1; k >= 0; --k) {
@@ -199,7 +221,7 @@ int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, cons
     }
     for (int i = 0; i < nx; ++i)
       for (int j = 0; j < nx; ++j) {
-        double acc = (i == j) ? q[i] + st->sigma : 0.0;
+        double acc = (i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0;
         for (int t = 0; t < nx; ++t) acc += Ak[t * nx + i] * PA[t * nx + j];
         for (int t = 0; t < nu; ++t) acc += G[t * nx + i] * Kk[t * nx + j];
         Pk[i * nx + j] = acc;
@@ -278,12 +300,18 @@ static double maxabs(double a, double b) { return fabs(a) > b ? fabs(a) : b; }
  *   res[1] dual     max |R (u_k - ubar_k) + B_k' lambda_{k+1} + C_k' y_k|
  *   res[2] dynamics max |x_{k+1} - A_k x_k - B_k u_k - c_k|, |x_0 - xbar0|
  *   res[3] complementarity / bounds: y_i > 0 needs z_i = h_i, y_i < 0 needs
- *          z_i = l_i (y in the normal cone of [l, h] at z), and l <= z <= h. */
+ *          z_i = l_i (y in the normal cone of [l, h] at z), and l <= z <= h.
+ * With joint limits (x_lo != NULL) the state rows join: their multipliers y_x
+ * enter the costates, lambda_k = Q (x_k - r_k) + y_x,k + A_k' lambda_{k+1},
+ * |x_k - z_x,k| the primal residual and (z_x, y_x) the complementarity test. */
+static void complementarity(double lo, double hi, double zz, double yy, double* rc);
+
 void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, const double* B,
                    const double* c, const double* q, const double* r, const double* x_ref,
                    const double* u_ref, const double* x0, const double* tau_max, double mu,
                    const uint8_t* stance, const double* x, const double* u, const double* z,
-                   const double* y, double* res, double* objective) {
+                   const double* y, double* res, double* objective, const double* x_lo,
+                   const double* x_hi, const double* zx, const double* yx) {
   const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s);
   double* lam = (double*)malloc(sizeof(double) * (size_t)(N + 1) * nx);
   double* C = (double*)malloc(sizeof(double) * m * nu);
@@ -307,11 +335,13 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
   *objective = obj;
 
   for (int i = 0; i < nx; ++i)
-    lam[(size_t)N * nx + i] = q[i] * (x[(size_t)N * nx + i] - x_ref[(size_t)N * nx + i]);
+    lam[(size_t)N * nx + i] = q[i] * (x[(size_t)N * nx + i] - x_ref[(size_t)N * nx + i]) +
+                              (x_lo ? yx[(size_t)(N - 1) * nx + i] : 0.0);
   for (int k = N - 1; k >= 1; --k) {
     const double* Ak = A + (size_t)k * nx * nx;
     for (int i = 0; i < nx; ++i) {
       double acc = q[i] * (x[(size_t)k * nx + i] - x_ref[(size_t)k * nx + i]);
+      if (x_lo) acc += yx[(size_t)(k - 1) * nx + i];
       for (int t = 0; t < nx; ++t) acc += Ak[t * nx + i] * lam[(size_t)(k + 1) * nx + t];
       lam[(size_t)k * nx + i] = acc;
     }
@@ -341,23 +371,32 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
       for (int t = 0; t < nu; ++t) acc -= Bk[i * nu + t] * uk[t];
       ry = maxabs(acc, ry);
     }
-    for (int row = 0; row < m; ++row) {
-      const double lo = l[(size_t)k * m + row], hi = h[(size_t)k * m + row];
-      const double zz = zk[row], yy = yk[row];
-      const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
-      const double a = isinf(hi) ? yp : fmin(yp, hi - zz);
-      const double b = isinf(lo) ? ym : fmin(ym, zz - lo);
-      rc = maxabs(a, rc);
-      rc = maxabs(b, rc);
-      if (zz > hi) rc = maxabs(zz - hi, rc);
-      if (zz < lo) rc = maxabs(lo - zz, rc);
-    }
+    for (int row = 0; row < m; ++row)
+      complementarity(l[(size_t)k * m + row], h[(size_t)k * m + row], zk[row], yk[row], &rc);
+    if (x_lo)  /* the state rows of x_{k+1} */
+      for (int i = 0; i < nx; ++i) {
+        const size_t idx = (size_t)k * nx + i;
+        rp = maxabs(x[(size_t)(k + 1) * nx + i] - zx[idx], rp);
+        complementarity(x_lo[i], x_hi[i], zx[idx], yx[idx], &rc);
+      }
   }
   res[0] = rp;
   res[1] = rd;
   res[2] = ry;
   res[3] = rc;
   free(lam); free(C); free(l); free(h); free(rho);
+}
+
+/* Complementarity test of one row: y > 0 needs z = h, y < 0 needs z = l, and
+ * l <= z <= h; the largest violation goes to *rc. */
+static void complementarity(double lo, double hi, double zz, double yy, double* rc) {
+  const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
+  const double a = isinf(hi) ? yp : fmin(yp, hi - zz);
+  const double b = isinf(lo) ? ym : fmin(ym, zz - lo);
+  *rc = maxabs(a, *rc);
+  *rc = maxabs(b, *rc);
+  if (zz > hi) *rc = maxabs(zz - hi, *rc);
+  if (zz < lo) *rc = maxabs(lo - zz, *rc);
 }
 
 static int all_finite(const double* v, size_t n) {
@@ -375,8 +414,9 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
               const double* u_ref, const double* x0, const double* tau_max, double mu,
               const uint8_t* stance, int iters, int warm, double tol, int max_iters,
               double* x, double* u, double* z, double* y, double* res, double* objective,
-              int* iters_done) {
+              int* iters_done, const double* x_lo, const double* x_hi, double* zx, double* yx) {
   const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s);
+  const size_t nZx = (size_t)N * nx;
   const double alpha = st->alpha, sigma = st->sigma;
   const size_t nX = (size_t)(N + 1) * nx, nU = (size_t)N * nu, nZ = (size_t)N * m;
   int status = ORC_OK, it = 0;
@@ -387,9 +427,15 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
                         all_finite(x_ref, nX) && all_finite(x0, nx) &&
                         all_finite(tau_max, s->n_tau) && isfinite(mu) &&
                         (!u_ref || all_finite(u_ref, nU)) &&
-                        (!warm || (all_finite(u, nU) && all_finite(z, nZ) && all_finite(y, nZ)));
-  if (!finite_in) {
+                        (!warm || (all_finite(u, nU) && all_finite(z, nZ) && all_finite(y, nZ))) &&
+                        (!x_lo || !warm || (all_finite(zx, nZx) && all_finite(yx, nZx)));
+  int bounds_ok = 1;
+  if (x_lo)
+    for (int i = 0; i < nx; ++i)
+      bounds_ok &= !isnan(x_lo[i]) && !isnan(x_hi[i]) && x_lo[i] <= x_hi[i];
+  if (!finite_in || !bounds_ok) {
     fill_nan(x, nX); fill_nan(u, nU); fill_nan(z, nZ); fill_nan(y, nZ);
+    if (x_lo) { fill_nan(zx, nZx); fill_nan(yx, nZx); }
     fill_nan(res, 4); *objective = NAN;
     return ORC_NONFINITE;
   }
@@ -405,10 +451,12 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
   double* rt = (double*)malloc(sizeof(double) * nU);
   double* xt = (double*)malloc(sizeof(double) * nX);
   double* ut = (double*)malloc(sizeof(double) * nU);
+  double* rho_x = (double*)malloc(sizeof(double) * (size_t)nx);
   orc_constraint_matrix(s, mu, C);
   orc_stage_bounds(s, st, tau_max, stance, l, h, rho);
+  if (x_lo) orc_state_penalties(s, st, x_lo, x_hi, rho_x);
 
-  if (orc_factor(s, st, A, B, c, q, r, rho, mu, K, L, sv, NULL) != ORC_OK) {
+  if (orc_factor(s, st, A, B, c, q, r, rho, mu, K, L, sv, NULL, x_lo ? rho_x : NULL) != ORC_OK) {
     status = ORC_NOT_PD;
     goto done;
   }
@@ -417,6 +465,10 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
     memset(u, 0, sizeof(double) * nU);
     memset(z, 0, sizeof(double) * nZ);
     memset(y, 0, sizeof(double) * nZ);
+    if (x_lo) {
+      memset(zx, 0, sizeof(double) * nZx);
+      memset(yx, 0, sizeof(double) * nZx);
+    }
   }
   /* x^0: rollout of the dynamics from xbar0 under u^0 */
   for (int i = 0; i < nx; ++i) x[i] = x0[i];
@@ -433,7 +485,10 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
     /* linear terms of the x-subproblem (right-hand side of Eq. (kkt_system)) */
     for (int k = 0; k <= N; ++k)
       for (int i = 0; i < nx; ++i)
-        qt[(size_t)k * nx + i] = -q[i] * x_ref[(size_t)k * nx + i] - sigma * x[(size_t)k * nx + i];
+        qt[(size_t)k * nx + i] = -q[i] * x_ref[(size_t)k * nx + i] - sigma * x[(size_t)k * nx + i] +
+                                 ((x_lo && k >= 1) ? yx[(size_t)(k - 1) * nx + i] -
+                                                         rho_x[i] * zx[(size_t)(k - 1) * nx + i]
+                                                   : 0.0);
     for (int k = 0; k < N; ++k)
       for (int j = 0; j < nu; ++j) {
         double acc = -sigma * u[(size_t)k * nu + j];
@@ -457,10 +512,19 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
         y[idx] = y[idx] + rho[idx] * (w - zn);
         z[idx] = zn;
       }
+    if (x_lo)  /* the state rows: zeta = xt_k, k = 1..N */
+      for (int k = 1; k <= N; ++k)
+        for (int i = 0; i < nx; ++i) {
+          const size_t idx = (size_t)(k - 1) * nx + i;
+          const double w = alpha * xt[(size_t)k * nx + i] + (1.0 - alpha) * zx[idx];
+          const double zn = fmin(fmax(w + yx[idx] / rho_x[i], x_lo[i]), x_hi[i]);
+          yx[idx] = yx[idx] + rho_x[i] * (w - zn);
+          zx[idx] = zn;
+        }
     if (iters <= 0) {
       double obj;
       orc_residuals(s, st, A, B, c, q, r, x_ref, u_ref, x0, tau_max, mu, stance, x, u, z, y,
-                    res, &obj);
+                    res, &obj, x_lo, x_hi, zx, yx);
       double su = 1.0, sd = 1.0;
       for (int k = 0; k < N; ++k)
         for (int row = 0; row < m; ++row) {
@@ -468,6 +532,11 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
           sd = maxabs(y[(size_t)k * m + row], sd);
         }
       for (size_t i = 0; i < nU; ++i) su = maxabs(u[i], su);
+      if (x_lo)
+        for (size_t i = 0; i < nZx; ++i) {
+          su = maxabs(zx[i], su);
+          sd = maxabs(yx[i], sd);
+        }
       if (res[0] <= tol * su && res[1] <= tol * sd) {
         ++it;
         status = ORC_CONVERGED;
@@ -477,17 +546,19 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
   }
   *iters_done = it;
   orc_residuals(s, st, A, B, c, q, r, x_ref, u_ref, x0, tau_max, mu, stance, x, u, z, y, res,
-                objective);
-  if (!(all_finite(x, nX) && all_finite(u, nU) && all_finite(z, nZ) && all_finite(y, nZ)))
+                objective, x_lo, x_hi, zx, yx);
+  if (!(all_finite(x, nX) && all_finite(u, nU) && all_finite(z, nZ) && all_finite(y, nZ)) ||
+      (x_lo && !(all_finite(zx, nZx) && all_finite(yx, nZx))))
     status = ORC_NONFINITE;
 
 done:
   if (status == ORC_NOT_PD || status == ORC_NONFINITE) {
     fill_nan(x, nX); fill_nan(u, nU); fill_nan(z, nZ); fill_nan(y, nZ);
+    if (x_lo) { fill_nan(zx, nZx); fill_nan(yx, nZx); }
     fill_nan(res, 4); *objective = NAN;
   }
   free(C); free(l); free(h); free(rho); free(K); free(L); free(sv);
-  free(qt); free(rt); free(xt); free(ut);
+  free(qt); free(rt); free(xt); free(ut); free(rho_x);
   return status;
 }
 
@@ -524,7 +595,8 @@ int orc_solve_batch(int32_t n, const int32_t* shapes, const orc_settings* st,
                     const double* x0, const double* tau_max, const double* mu,
                     const uint8_t* stance, int iters, int warm, double* x, double* u,
                     double* z, double* y, double* res, double* objective, int32_t* status,
-                    int n_threads) {
+                    int n_threads, const double* x_lo, const double* x_hi, double* zx,
+                    double* yx) {
   offs* o = (offs*)malloc(sizeof(offs) * (n > 0 ? n : 1));
   agent_offsets(n, shapes, o);
   int used = 1;
@@ -540,7 +612,9 @@ int orc_solve_batch(int32_t n, const int32_t* shapes, const orc_settings* st,
                           x_ref + o[a].xr, u_ref ? u_ref + o[a].u : NULL, x0 + o[a].x0,
                           tau_max + o[a].tau, mu[a], stance + o[a].st, iters, warm, 0.0, 0,
                           x + o[a].x, u + o[a].u, z + o[a].z, y + o[a].z, res + 4 * (size_t)a,
-                          objective + a, &done_it);
+                          objective + a, &done_it, x_lo ? x_lo + o[a].q : NULL,
+                          x_lo ? x_hi + o[a].q : NULL, x_lo ? zx + o[a].c : NULL,
+                          x_lo ? yx + o[a].c : NULL);
   }
 #ifdef _OPENMP
   used = n_threads;

@@ -320,3 +320,127 @@ def osqp_dense(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, rho=0.1, sig
             break
     xs, us = split(s, x, x0)
     return xs, us
+
+
+def state_rho(x_lo, x_hi, rho=0.1, rho_eq=100.0, rho_min=1e-6):
+    """OSQP's penalty rule for the state rows (joint limits), per component."""
+    x_lo, x_hi = np.asarray(x_lo, dtype=float), np.asarray(x_hi, dtype=float)
+    out = np.full(x_lo.shape, rho)
+    out[x_lo == x_hi] = rho_eq
+    out[np.isinf(x_lo) & np.isinf(x_hi)] = rho_min
+    return out
+
+
+def dense_admm_limits(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x_lo, x_hi, iters, *,
+                      rho=0.1, sigma=1e-6, alpha=1.6, rho_eq=100.0, rho_min=1e-6):
+    """dense_admm with the joint-limit rows x_lo <= x_k <= x_hi (k = 1..N) added
+    to the splitting: one more row block C_x = I on every state, its own
+    (z_x, y_x), projection and dual update; the x-subproblem gains
+    rho_x/2 |x_k - z_x + y_x/rho_x|^2."""
+    C = C_dense(s, mu)
+    l, h = bounds_table(s, tau_max, stance)
+    rr = rho_table(l, h, rho, rho_eq, rho_min)
+    rx = state_rho(x_lo, x_hi, rho, rho_eq, rho_min)
+    G, b = dynamics_rows(s, A, B, c, x0)
+    m = C.shape[0]
+    N, nx = s.N, s.nx
+    u = np.zeros((N, s.nu))
+    z = np.zeros((N, m))
+    y = np.zeros((N, m))
+    zx = np.zeros((N, nx))
+    yx = np.zeros((N, nx))
+    x = rollout(s, A, B, c, x0, u)
+    for _ in range(iters):
+        H, g = x_subproblem(s, q, r, x_ref, C, rr, sigma, x, u, z, y)
+        for k in range(1, N + 1):
+            sl = slice((k - 1) * nx, k * nx)
+            H[sl, sl] += np.diag(rx)
+            g[sl] += rx * (-zx[k - 1] + yx[k - 1] / rx)
+        v, _ = kkt_solve(H, g, G, b)
+        xt, ut = split(s, v, x0)
+        zeta = ut @ C.T
+        x = alpha * xt + (1 - alpha) * x
+        x[0] = x0
+        u = alpha * ut + (1 - alpha) * u
+        w = alpha * zeta + (1 - alpha) * z
+        zn = np.clip(w + y / rr, l, h)
+        y = y + rr * (w - zn)
+        z = zn
+        wx = alpha * xt[1:] + (1 - alpha) * zx
+        zxn = np.clip(wx + yx / rx, x_lo, x_hi)
+        yx = yx + rx * (wx - zxn)
+        zx = zxn
+    return x, u, z, y, zx, yx
+
+
+def brute_force_qp_limits(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x_lo, x_hi,
+                          tol=1e-9):
+    """brute_force_qp with the joint-limit rows x_lo <= x_k <= x_hi (k = 1..N)
+    among the enumerated rows.  Returns (x, u, y, y_x) or None."""
+    C = C_dense(s, mu)
+    l, h = bounds_table(s, tau_max, stance)
+    G, b = dynamics_rows(s, A, B, c, x0)
+    N, nx, nu = s.N, s.nx, s.nu
+    nv = N * nx + N * nu
+    H = np.zeros((nv, nv))
+    g = np.zeros(nv)
+    for k in range(1, N + 1):
+        sl = slice((k - 1) * nx, k * nx)
+        H[sl, sl] = np.diag(q)
+        g[sl] = -q * x_ref[k]
+    H[N * nx:, N * nx:] = np.kron(np.eye(N), np.diag(r))
+    rows = []  # (row vector, lo, hi)
+    for k in range(N):
+        for i in range(C.shape[0]):
+            vec = np.zeros(nv)
+            vec[N * nx + k * nu:N * nx + (k + 1) * nu] = C[i]
+            rows.append((vec, l[k, i], h[k, i], ("u", k, i)))
+    for k in range(1, N + 1):
+        for i in range(nx):
+            vec = np.zeros(nv)
+            vec[(k - 1) * nx + i] = 1.0
+            rows.append((vec, x_lo[i], x_hi[i], ("x", k - 1, i)))
+    choices = []
+    for vec, lo, hi, _ in rows:
+        if lo == hi:
+            choices.append(("eq",))
+            continue
+        ch = ["free"]
+        if np.isfinite(lo):
+            ch.append("lo")
+        if np.isfinite(hi):
+            ch.append("hi")
+        choices.append(tuple(ch))
+    for combo in itertools.product(*choices):
+        E, e, kinds, tags = [], [], [], []
+        for (vec, lo, hi, tag), kind in zip(rows, combo):
+            if kind == "free":
+                continue
+            E.append(vec)
+            e.append(lo if kind in ("lo", "eq") else hi)
+            kinds.append(kind)
+            tags.append(tag)
+        GG = np.vstack([G] + ([np.array(E)] if E else []))
+        bb = np.concatenate([b, np.array(e)])
+        try:
+            v, lam = kkt_solve(H, g, GG, bb)
+        except np.linalg.LinAlgError:
+            continue
+        mult = lam[G.shape[0]:]
+        vals = np.array([vec @ v for vec, _, _, _ in rows])
+        los = np.array([lo for _, lo, _, _ in rows])
+        his = np.array([hi for _, _, hi, _ in rows])
+        if np.any(vals < los - tol) or np.any(vals > his + tol):
+            continue
+        if any((kd == "hi" and mm < -tol) or (kd == "lo" and mm > tol) for kd, mm in zip(kinds, mult)):
+            continue
+        x, u = split(s, v, x0)
+        y = np.zeros((N, C.shape[0]))
+        yx = np.zeros((N, nx))
+        for (kind_, k, i), mm in zip(tags, mult):
+            if kind_ == "u":
+                y[k, i] = mm
+            else:
+                yx[k, i] = mm
+        return x, u, y, yx
+    return None

@@ -8,6 +8,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_limits as limits
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "mpc_oracle.c")
@@ -19,7 +20,7 @@ MUTANTS = [
     ("wrong sign of d", "for (int j = 0; j < nu; ++j) dk[j] = -hv[j];",
      "for (int j = 0; j < nu; ++j) dk[j] = hv[j];"),
     ("K' h dropped from p", "for (int t = 0; t < nu; ++t) acc += Kk[t * nx + i] * hv[t];", ""),
-    ("sigma sign in qt", "- sigma * x[(size_t)k * nx + i];", "+ sigma * x[(size_t)k * nx + i];"),
+    ("sigma sign in qt", "- sigma * x[(size_t)k * nx + i] +", "+ sigma * x[(size_t)k * nx + i] +"),
     ("dual update sign", "y[idx] = y[idx] + rho[idx] * (w - zn);", "y[idx] = y[idx] - rho[idx] * (w - zn);"),
     ("no relaxation of z", "const double w = alpha * zeta + (1.0 - alpha) * z[idx];",
      "const double w = zeta;"),
@@ -39,6 +40,19 @@ MUTANTS = [
      "const double b = 0.0;"),
     ("complementarity against the wrong bound", "const double a = isinf(hi) ? yp : fmin(yp, hi - zz);",
      "const double a = isinf(lo) ? yp : fmin(yp, zz - lo);"),
+    ("state penalty missing from P_N",
+     "Pn[i * nx + j] = (i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0;",
+     "Pn[i * nx + j] = (i == j) ? q[i] + st->sigma : 0.0;"),
+    ("state rows' linear term with the wrong sign",
+     "((x_lo && k >= 1) ? yx[(size_t)(k - 1) * nx + i] -", "((x_lo && k >= 1) ? -yx[(size_t)(k - 1) * nx + i] -"),
+    ("state rows projected on the wrong stage",
+     "const double w = alpha * xt[(size_t)k * nx + i] + (1.0 - alpha) * zx[idx];",
+     "const double w = alpha * xt[(size_t)(k - 1) * nx + i] + (1.0 - alpha) * zx[idx];"),
+    ("state multipliers left out of the costates", "      if (x_lo) acc += yx[(size_t)(k - 1) * nx + i];\n", ""),
+    ("state rows left out of the primal residual",
+     "rp = maxabs(x[(size_t)(k + 1) * nx + i] - zx[idx], rp);", ""),
+    ("equality state rows with the inequality penalty", "      rho_x[i] = st->rho_eq_scale * st->rho;",
+     "      rho_x[i] = st->rho;"),
 ]
 
 CHECKS = [
@@ -51,6 +65,9 @@ CHECKS = [
     lambda: pins.test_converged_equals_brute_force_active_set(2, 2),
     lambda: pins.test_plant_step_is_the_solved_first_transition(),
     lambda: pins.test_complementarity_residual_is_the_projection_residual(),
+    lambda: limits.test_xupdate_with_state_rows_equals_dense_kkt(limits.synth.quadruped(3), 2),
+    lambda: limits.test_fixed_iterates_with_limits_equal_dense_admm(limits.synth.quadruped(3), 5, 6),
+    lambda: limits.test_residuals_with_state_multipliers(),
 ]
 
 

@@ -117,6 +117,9 @@ typedef struct {
                             /* (0 = fixed rho, default)                                 */
   double rho_tolerance;     /* adopt an estimate that moves rho by more than this      */
                             /* factor either way (default 5, >= 1)                      */
+  int32_t joint_limits;     /* 1: every solve carries joint limits x_lo <= x_k <= x_hi  */
+                            /* (Eq. (mpc_formulation)); the agents then run the generic */
+                            /* kernels, FP64 or FP32 only, without scaling (default 0)  */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */
@@ -140,6 +143,10 @@ typedef struct {
   const uint8_t* stance;
   const void* u_ref;   /* may be NULL */
   int32_t warm_start;  /* 0: u = z = y = 0;  1: start from the plan's resident (u, z, y) */
+  /* joint limits of Eq. (mpc_formulation): x_lo <= x_k <= x_hi at stages 1..N, [nx]
+   * per agent (io type; +-infinity where a component has no limit); required by
+   * plans with joint_limits = 1, NULL otherwise */
+  const void *x_lo, *x_hi;
 } mpc_problem_batch;
 
 /* Alg. 1 for every agent, from the KKT data (f_KKT) to the end of the QP
@@ -161,6 +168,9 @@ typedef struct {
   void *u0, *x, *u, *z, *y, *objective; /* io type; any may be NULL (not copied) */
   double* residuals;                    /* [n][4], may be NULL                   */
   int32_t* status;                      /* [n],    may be NULL                   */
+  void *zx, *yx;                        /* joint-limit rows' (z_x, y_x) [N][nx],  */
+                                        /* io type (plans with joint limits);    */
+                                        /* may be NULL                           */
 } mpc_solution;
 
 /* The QP solution Alg. 1 returns after its fixed iteration count; u_0 is
@@ -176,6 +186,11 @@ mpc_status mpc_get_solution(mpc_plan_t plan, const mpc_solution* out, void* stre
  * z [N][m], y [N][m] (io type), e.g. to resume a controller. */
 mpc_status mpc_set_warm_state(mpc_plan_t plan, const void* u, const void* z, const void* y,
                               void* stream);
+
+/* The joint-limit rows' part of the warm start (plans with joint limits):
+ * z_x, y_x [N][nx] per agent (io type, device), e.g. to resume a controller
+ * together with mpc_set_warm_state. */
+mpc_status mpc_set_warm_limits(mpc_plan_t plan, const void* zx, const void* yx, void* stream);
 
 /* The system step x_{i+1} = f(x_i, u_i) of Eq. (OCP), linearised as the QP's
  * first stage, driving a closed loop of control steps.
@@ -292,8 +307,8 @@ typedef struct mpc_server_s* mpc_server_t;
 
 typedef struct {
   mpc_plan_desc solver;      /* precision, admm_iters, constants, refinement, device;   */
-                             /* n_agents, shapes and kernel are ignored; scaling_iters   */
-                             /* and rho_interval must be 0                               */
+                             /* n_agents, shapes and kernel are ignored; scaling_iters,  */
+                             /* rho_interval and joint_limits must be 0                  */
   int64_t hbm_budget_bytes;  /* device memory of the server (default 1 GiB)             */
   int32_t max_batch;         /* requests per batch (default 4096)                       */
   int32_t max_inflight;      /* batches on the device at once, 1..8 (default 3)        */
@@ -377,7 +392,7 @@ mpc_status mpc_server_get_stats(mpc_server_t server, mpc_server_stats* out);
  * (36, 24), N <= 20), MPC_FP32 only, and no plan: desc gives n_agents,
  * shapes (host array, every entry equal), admm_iters and the solver
  * constants (precision must be MPC_FP32; kernel, refinement fields ignored;
- * scaling_iters and rho_interval must be 0).
+ * scaling_iters, rho_interval and joint_limits must be 0).
  * The per-agent descriptors, the launch list and the Riccati operators live
  * in a device array of MPC_NOALLOC_SCRATCH_BYTES that the library holds on
  * every device it runs on until the process ends (about 500 humanoid agents

@@ -290,8 +290,14 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   for (int i = tid; i < d.n_tau; i += nt) ok &= (bool)isfinite(tau[i]);
   if (in.uref)
     for (int i = tid; i < N * NU; i += nt) ok &= (bool)isfinite(in.uref[d.our + i]);
+  if (in.xlo)  // joint limits: no NaN bound, and an interval that is not empty
+    for (int i = tid; i < NX; i += nt) {
+      const float lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
+      ok &= !isnan(lo) && !isnan(hi) && lo <= hi;
+    }
   if (!ok) atomicOr(flag, 1);
-  for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma;
+  // state weight Q + sigma I (+ the joint-limit rows' penalties)
+  for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma + state_rho<double>(in, d, i, sc);
   __syncthreads();
   if (flag[0]) {
     if (tid == 0) status[agent] = AGENT_NONFINITE;
@@ -577,7 +583,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       for (int v = 0; v < 4; ++v) {
         const int i = ti * 16 + orow<PREC>(lane, v), j = tj * 16 + (lane & 15);
         if (ti == tj && i > j) continue;
-        const double pv = pacc[rr][v] + ((i == j && i < NX) ? (double)q[i] + sc.sigma : 0.0);
+        const double pv =
+            pacc[rr][v] + ((i == j && i < NX) ? (double)q[i] + sc.sigma + state_rho<double>(in, d, i, sc) : 0.0);
         P[i * LX + j] = pv;
         P[j * LX + i] = pv;
       }

@@ -85,6 +85,11 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
             finite_all(r, nu, tid, nt) && finite_all(in.xr + d.oxr, (int64_t)(N + 1) * nx, tid, nt) &&
             finite_all(in.x0 + d.ox0, nx, tid, nt) && finite_all(tau, d.n_tau, tid, nt) &&
             (bool)isfinite(mu) && (!in.uref || finite_all(in.uref + d.our, (int64_t)N * nu, tid, nt));
+  if (in.xlo)
+    for (int i = tid; i < nx; i += nt) {
+      const T lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
+      ok &= !isnan(lo) && !isnan(hi) && lo <= hi;
+    }
   if (!ok) atomicOr(&s_flag, 1);
   __syncthreads();
   if (s_flag) {
@@ -103,7 +108,7 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
   }
   for (int idx = tid; idx < nx * nx; idx += nt) {
     const int i = idx / nx, j = idx % nx;
-    P[idx] = (i == j) ? (D)q[i] + sc.sigma : 0.0;
+    P[idx] = (i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0;
   }
   __syncthreads();
 
@@ -217,7 +222,7 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
     for (int idx = tid; idx < nx * nx; idx += nt) {
       const int i = idx / nx, j = idx % nx;
       if (j >= i) {
-        D a1 = (i == j) ? (D)q[i] + sc.sigma : 0.0, a2 = a1;
+        D a1 = (i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0, a2 = a1;
         for (int t = 0; t < nx; ++t) {
           a1 += Ak[t * nx + i] * PA[t * nx + j];
           a2 += Ak[t * nx + j] * PA[t * nx + i];
@@ -358,6 +363,11 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       Z[i] = nan;
       Y[i] = nan;
     }
+    if (st.zx)
+      for (int i = tid; i < N * nx; i += nt) {
+        st.zx[d.oc + i] = nan;
+        st.yx[d.oc + i] = nan;
+      }
     return;
   }
   // Operators are read in the io type T; every vector, every accumulation and
@@ -381,6 +391,10 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   V* p = e + N * nx;                      // nx
   V* hv = p + nx;                         // N*nu
   V* red = hv + N * nu;                   // 256 (refinement stopping test)
+  // joint-limit rows (with limits): z_x, y_x of x_1..x_N
+  const bool lim = in.xlo != nullptr;
+  V* zx = red + 256;                      // N*nx
+  V* yx = zx + N * nx;                    // N*nx
 
   const T* A = in.A + d.oA;
   const T* B = in.B + d.oB;
@@ -407,6 +421,11 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
     z[i] = wm ? (V)Z[i] : 0.0;
     y[i] = wm ? (V)Y[i] : 0.0;
   }
+  if (lim)
+    for (int i = tid; i < N * nx; i += nt) {
+      zx[i] = wm ? (V)st.zx[d.oc + i] : 0.0;
+      yx[i] = wm ? (V)st.yx[d.oc + i] : 0.0;
+    }
   for (int i = tid; i < nx; i += nt) {
     x[i] = (V)x0[i];
     xt[i] = (V)x0[i];
@@ -458,11 +477,17 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
                 },
                 [&](int idx, V acc) {
                   const int k = idx / nx, i = idx % nx;
-                  g[idx] = (-(V)q[i] * (V)xr[(int64_t)k * nx + i] - sigma * x[idx]) + acc;
+                  V qt = -(V)q[i] * (V)xr[(int64_t)k * nx + i] - sigma * x[idx];
+                  if (lim && k >= 1)  // the state rows of x_k: y_x - rho_x z_x
+                    qt += yx[idx - nx] - state_rho<V>(in, d, i, sc) * zx[idx - nx];
+                  g[idx] = qt + acc;
                 },
                 tid, nt);
-    for (int i = tid; i < nx; i += nt)
-      p[i] = -(V)q[i] * (V)xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
+    for (int i = tid; i < nx; i += nt) {
+      V qt = -(V)q[i] * (V)xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
+      if (lim) qt += yx[(N - 1) * nx + i] - state_rho<V>(in, d, i, sc) * zx[(N - 1) * nx + i];
+      p[i] = qt;
+    }
     __syncthreads();
     // backward chain: p'_k = p_{k+1} + s_k, p_k = g_k + A_cl,k' p'_k
     for (int k = N - 1; k >= 0; --k) {
@@ -605,7 +630,18 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         __syncthreads();
       }
     }
-    // relaxation, projection onto [l, h], dual update
+    // relaxation, projection onto [l, h], dual update (the joint-limit rows
+    // take xt_k, k = 1..N, before x is relaxed)
+    if (lim)
+      for (int idx = tid; idx < N * nx; idx += nt) {
+        const int i = idx % nx;
+        const V rr = state_rho<V>(in, d, i, sc);
+        const V lo = (V)in.xlo[d.oq + i], hi = (V)in.xhi[d.oq + i];
+        const V w = alpha * xt[idx + nx] + oma * zx[idx];
+        const V zn = fmin(fmax(w + yx[idx] / rr, lo), hi);
+        yx[idx] = yx[idx] + rr * (w - zn);
+        zx[idx] = zn;
+      }
     for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) x[idx] = alpha * xt[idx] + oma * x[idx];
     for (int idx = tid; idx < N * m; idx += nt) {
       const int k = idx / m, i = idx % m;
@@ -636,6 +672,12 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
     Y[i] = (T)y[i];
     ok &= (bool)isfinite(Z[i]) && (bool)isfinite(Y[i]);
   }
+  if (lim)
+    for (int i = tid; i < N * nx; i += nt) {
+      st.zx[d.oc + i] = (T)zx[i];
+      st.yx[d.oc + i] = (T)yx[i];
+      ok &= (bool)isfinite(zx[i]) && (bool)isfinite(yx[i]);
+    }
   if (!ok) st.status[a] = AGENT_NONFINITE;
 }
 
@@ -772,6 +814,19 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
         lam[idx] = (double)q[idx % nx] * ee;
         if (idx >= nx) obj += 0.5 * (double)q[idx % nx] * ee * ee;
         else ry = fmax(ry, fabs(xv - (double)x0[idx]));
+        if (in.xlo && idx >= nx) {  // joint-limit row of x_k: multiplier, primal, complementarity
+          const int i = idx % nx;
+          const double zz = (double)st.zx[d.oc + idx - nx], yy = (double)st.yx[d.oc + idx - nx];
+          lam[idx] += yy;
+          rp = fmax(rp, fabs(xv - zz));
+          const double lo = (double)in.xlo[d.oq + i], hi = (double)in.xhi[d.oq + i];
+          const double yp = yy > 0.0 ? yy : 0.0, ym = yy < 0.0 ? -yy : 0.0;
+          const double ca = isinf(hi) ? yp : fmin(yp, hi - zz);
+          const double cb = isinf(lo) ? ym : fmin(ym, zz - lo);
+          rc = fmax(rc, fmax(fabs(ca), fabs(cb)));
+          if (zz > hi) rc = fmax(rc, zz - hi);
+          if (zz < lo) rc = fmax(rc, lo - zz);
+        }
       }
       if (idx < nU) {
         const double uv = (double)u[idx];

@@ -35,6 +35,10 @@ struct Inputs {
   const T *A, *B, *c, *q, *r, *xr, *x0, *tau, *mu;
   const uint8_t* st;
   const T* uref;  // may be null
+  // joint limits x_lo <= x_k <= x_hi (k = 1..N), [nx] per agent at the q offset;
+  // null: no state rows
+  const T* xlo = nullptr;
+  const T* xhi = nullptr;
 };
 
 template <typename T>
@@ -43,6 +47,9 @@ struct State {
   T* obj;
   double* res;
   int32_t* status;
+  // the joint-limit rows' (z_x, y_x), [N][nx] per agent at the c offset (with limits)
+  T* zx = nullptr;
+  T* yx = nullptr;
 };
 
 enum : int32_t { AGENT_OK = 0, AGENT_CONVERGED = 1, AGENT_NOT_PD = 2, AGENT_NONFINITE = 3 };
@@ -63,10 +70,12 @@ inline size_t generic_factor_lds(int nx, int nu, size_t esz) {
   (void)esz;  // the recursion runs in double whatever the io type
   return 8 * (size_t)(nu * nu + 3 * nx * nx + 3 * nx * nu + nu + 64);
 }
-inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz) {
+inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz, bool limits = false) {
   (void)esz;  // vectors are held in double whatever the io type
   // + 256 doubles of reduction scratch for the refinement's stopping test
-  return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu + 256);
+  // (+ the joint-limit rows' z_x, y_x)
+  return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu + 256 +
+                      (limits ? 2 * N * nx : 0));
 }
 // Residual kernel: costates and x ((N+1) x nx each) and u (N x nu) in double,
 // then stage k's A_k and B_k staged in the io type with rows padded by one

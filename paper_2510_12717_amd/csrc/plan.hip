@@ -110,6 +110,10 @@ struct mpc_plan_s {
   double* d_scale = nullptr;       // [n][kScaleStride]
   double* d_rho = nullptr;         // [n]
   double* d_rho_hist = nullptr;    // [n][n_seg]: the rho of every segment
+  // joint limits
+  bool limits = false;
+  void *d_zx = nullptr, *d_yx = nullptr;  // [sum N nx]: the state rows' (z_x, y_x)
+  int64_t nZX = 0;
   int n_seg = 1;
   bool solved = false;
   size_t lds_factor = 0, lds_admm = 0, lds_res = 0;
@@ -166,6 +170,7 @@ extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
   d->scaling_iters = 0;
   d->rho_interval = 0;
   d->rho_tolerance = 5.0;
+  d->joint_limits = 0;
 }
 
 extern "C" const char* mpc_last_error(void) { return mpc::g_err.c_str(); }
@@ -195,6 +200,8 @@ static void free_plan(mpc_plan_s* p) {
   hipFree(p->d_scale);
   hipFree(p->d_rho);
   hipFree(p->d_rho_hist);
+  hipFree(p->d_zx);
+  hipFree(p->d_yx);
   for (auto e : p->ev_pool) hipEventDestroy(e);
   for (auto& pe : p->pending) {
     hipEventDestroy(pe.second.first);
@@ -222,6 +229,13 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       (desc->rho_interval > 0 && !(desc->rho_tolerance >= 1.0 && std::isfinite(desc->rho_tolerance))))
     return fail(MPC_ERR_INVALID_ARG,
                 "scaling_iters must be in 0..100, rho_interval >= 0 and rho_tolerance >= 1");
+  if (desc->joint_limits != 0 && desc->joint_limits != 1)
+    return fail(MPC_ERR_INVALID_ARG, "joint_limits must be 0 or 1");
+  if (desc->joint_limits &&
+      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
+       desc->scaling_iters > 0 || desc->kernel == 2))
+    return fail(MPC_ERR_INVALID_ARG,
+                "joint limits run on the generic kernels in FP64 or FP32, without scaling");
   for (int a = 0; a < desc->n_agents; ++a) {
     mpc_status vs = validate_shape(desc->shapes[a], a);
     if (vs != MPC_OK) return vs;
@@ -237,6 +251,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->desc.shapes = nullptr;
   p->fp64 = desc->precision == MPC_FP64;
   p->esz = p->fp64 ? 8 : 4;
+  p->limits = desc->joint_limits != 0;
 
   p->hdesc.resize(p->n);
   AgentDesc cur{};
@@ -283,7 +298,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->nZ = oz;
   p->nWS = ows;
   p->lds_factor = generic_factor_lds(p->maxnx, p->maxnu, p->esz);
-  p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz);
+  p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz, p->limits);
   p->lds_res = generic_residual_lds(p->maxN, p->maxnx, p->maxnu, p->esz);
 
   // Launch groups.  FP32 agents whose shape has a register-resident
@@ -295,7 +310,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
     for (int a = 0; a < p->n; ++a) {
       const mpc_shape& s = p->shapes[a];
-      const bool fok = desc->precision == MPC_FP32 && fused_supported(s.N, s.nx, s.nu, s.n_feet);
+      const bool fok = desc->precision == MPC_FP32 && !p->limits &&
+                       fused_supported(s.N, s.nx, s.nu, s.n_feet);
       if (desc->kernel == 2 && !fok) {
         delete p;
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
@@ -329,7 +345,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       g.list_off = (int64_t)p->hlist.size();
       const int m = s0.nu + 4 * s0.n_feet;
       g.lds_factor = generic_factor_lds(s0.nx, s0.nu, p->esz);
-      g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz);
+      g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz, p->limits);
       if (g.fused_ok) fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
       for (int32_t a : ag) g.work += (double)p->shapes[a].N * (s0.nx + s0.nu) * (s0.nx + s0.nu);
       g.est = g.work;
@@ -416,6 +432,11 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     if (se == hipSuccess && p->adaptive) se = alloc((void**)&p->d_rho, sizeof(double) * (size_t)p->n);
     if (se == hipSuccess && p->adaptive)
       se = alloc((void**)&p->d_rho_hist, sizeof(double) * (size_t)p->n * p->n_seg);
+    if (p->limits) {
+      p->nZX = oc;  // N nx per agent, the layout of c
+      if (se == hipSuccess) se = alloc(&p->d_zx, p->esz * (size_t)p->nZX);
+      if (se == hipSuccess) se = alloc(&p->d_yx, p->esz * (size_t)p->nZX);
+    }
     if (se != hipSuccess) {
       mpc_status st = fail(se == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,
                            std::string("hipMalloc: ") + hipGetErrorString(se));
@@ -474,6 +495,10 @@ static mpc_status check_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
     return fail(MPC_ERR_INVALID_ARG, "warm_start requested before any solve or warm state");
   if (p->scaled && b->u_ref)
     return fail(MPC_ERR_INVALID_ARG, "an input reference is not supported with scaling");
+  if (p->limits != (b->x_lo != nullptr) || (b->x_lo == nullptr) != (b->x_hi == nullptr))
+    return fail(MPC_ERR_INVALID_ARG,
+                p->limits ? "this plan solves with joint limits: x_lo and x_hi are required"
+                          : "x_lo / x_hi given to a plan created without joint limits");
   return MPC_OK;
 }
 
@@ -512,6 +537,8 @@ static Inputs<T> make_inputs(const mpc_problem_batch* b) {
   in.mu = (const T*)b->mu;
   in.st = b->stance;
   in.uref = (const T*)b->u_ref;
+  in.xlo = (const T*)b->x_lo;
+  in.xhi = (const T*)b->x_hi;
   return in;
 }
 
@@ -525,6 +552,8 @@ static State<T> make_state(mpc_plan_s* p) {
   s.obj = (T*)p->d_obj;
   s.res = p->d_res;
   s.status = p->d_status;
+  s.zx = (T*)p->d_zx;
+  s.yx = (T*)p->d_yx;
   return s;
 }
 
@@ -708,6 +737,8 @@ extern "C" mpc_status mpc_get_solution(mpc_plan_t p, const mpc_solution* o, void
   if (o->objective) HIP_TRY(hipMemcpyAsync(o->objective, p->d_obj, e * p->n, hipMemcpyDeviceToDevice, s));
   if (o->residuals) HIP_TRY(hipMemcpyAsync(o->residuals, p->d_res, sizeof(double) * 4 * p->n, hipMemcpyDeviceToDevice, s));
   if (o->status) HIP_TRY(hipMemcpyAsync(o->status, p->d_status, sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, s));
+  if (p->limits && o->zx) HIP_TRY(hipMemcpyAsync(o->zx, p->d_zx, e * p->nZX, hipMemcpyDeviceToDevice, s));
+  if (p->limits && o->yx) HIP_TRY(hipMemcpyAsync(o->yx, p->d_yx, e * p->nZX, hipMemcpyDeviceToDevice, s));
   if (o->u0) {
     // u0 of agent a is the first nu entries of its u block: a strided copy
     // when every block has one size, else one gather kernel.
@@ -736,6 +767,17 @@ extern "C" mpc_status mpc_set_warm_state(mpc_plan_t p, const void* u, const void
   HIP_TRY(hipMemcpyAsync(p->d_z, z, p->esz * p->nZ, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(p->d_y, y, p->esz * p->nZ, hipMemcpyDeviceToDevice, s));
   p->solved = true;
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_set_warm_limits(mpc_plan_t p, const void* zx, const void* yx,
+                                          void* stream) {
+  if (!p || !zx || !yx) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!p->limits) return fail(MPC_ERR_INVALID_ARG, "this plan has no joint limits");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(p->d_zx, zx, p->esz * p->nZX, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_yx, yx, p->esz * p->nZX, hipMemcpyDeviceToDevice, s));
   return MPC_OK;
 }
 

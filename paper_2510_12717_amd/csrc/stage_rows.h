@@ -56,6 +56,18 @@ __device__ inline void row_bounds(const AgentDesc& d, int i, const uint8_t* st, 
     rho = (T)sc.rho;
 }
 
+// Penalty of the joint-limit row of state component i (0 without limits):
+// rho_eq_scale * rho for an equality, rho_min with both bounds infinite, rho
+// otherwise -- the penalty rule of the input rows.
+template <typename T, typename TT>
+__device__ inline T state_rho(const Inputs<TT>& in, const AgentDesc& d, int i, const SolverConsts& sc) {
+  if (!in.xlo) return (T)0;
+  const TT lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
+  if (lo == hi) return (T)(sc.rho_eq * sc.rho);
+  if (isinf(lo) && isinf(hi)) return (T)sc.rho_min;
+  return (T)sc.rho;
+}
+
 // Diagonal of R + sigma I + C' diag(rho) C for input j (rho = this stage's row penalties).
 template <typename T, typename R>
 __device__ inline T rtilde_diag(const AgentDesc& d, int j, T rj, T mu, const R* rho,

@@ -263,6 +263,36 @@ def conditioned_humanoid_batch(n_agents: int = 16384, kappa: float = 1e4, seed: 
                       dtype=dtype)
 
 
+def joint_limits(batch: Batch, seed: int = 0):
+    """Joint position and velocity limits (Eq. (mpc_formulation)), flat, nx per
+    agent: the state is (q, v) of a floating base (6 coordinates) plus joints,
+    so components 6 .. nx/2 - 1 (positions) and nx/2 + 6 .. nx - 1 (velocities)
+    get a box, drawn per agent and component (positions +-U[1, 2], velocities
+    +-U[1.5, 3]) and widened to hold the agent's x0 with a margin of 0.3;
+    the base components are free (+-inf).  Own stream per agent (extra key
+    2_000_000), so the problem draws are untouched."""
+    ids = batch.agent_ids if batch.agent_ids is not None else np.arange(batch.n_agents)
+    off = batch.offsets()
+    lo_all, hi_all = [], []
+    for a, (s, aid) in enumerate(zip(batch.shapes, ids)):
+        rng = agent_rng(seed, batch.stream_id, int(aid), 2_000_000)
+        half = s.nx // 2
+        lo = np.full(s.nx, -np.inf)
+        hi = np.full(s.nx, np.inf)
+        for base, (wlo, whi) in ((0, (1.0, 2.0)), (half, (1.5, 3.0))):
+            j = np.arange(base + 6, base + half)
+            lo[j] = -rng.uniform(wlo, whi, j.size)
+            hi[j] = rng.uniform(wlo, whi, j.size)
+        x0 = np.asarray(batch.x0[off["x0"][a]:off["x0"][a + 1]], dtype=np.float64)
+        lim = np.isfinite(lo)
+        lo[lim] = np.minimum(lo[lim], x0[lim] - 0.3)
+        hi[lim] = np.maximum(hi[lim], x0[lim] + 0.3)
+        lo_all.append(lo)
+        hi_all.append(hi)
+    dt = batch.A.dtype
+    return np.concatenate(lo_all).astype(dt), np.concatenate(hi_all).astype(dt)
+
+
 def step_noise(batch: Batch, step: int, std: float = 1e-2) -> np.ndarray:
     """Per-step state disturbance, N(0, std^2), laid out like ``x0``."""
     ids = batch.agent_ids if batch.agent_ids is not None else np.arange(batch.n_agents)

@@ -98,7 +98,8 @@ def parse():
                     help="served loop: most requests per batch (with fewer than the controllers, a "
                          "batch forms while another runs)")
     ap.add_argument("--rate-hz", type=float, default=100.0, help="request rate per controller")
-    ap.add_argument("--sim-seconds", type=float, default=2.0)
+    ap.add_argument("--sim-seconds", type=float, default=60.0, help="length of the served trace")
+    ap.add_argument("--max-inflight", type=int, default=3, help="batch slots of the server")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 1 GiB (x5), the reference kernel for "
@@ -419,48 +420,66 @@ def serve(args):
     nu = np.array([s.nu for s in b.shapes])
     u0 = torch.zeros(int(nu.sum()), device="cuda")
     u0_ptr = (u0.data_ptr() + 4 * np.concatenate([[0], np.cumsum(nu)[:-1]])).astype(np.uint64)
+    # arrivals: the superposition of nc independent Poisson processes of rate
+    # rate_hz is one Poisson process of rate nc * rate_hz whose events pick a
+    # controller uniformly; drawn in windows of 0.1 s as the trace advances
     rng = np.random.default_rng(11)
-    arr_t, arr_c = [], []
-    for c in range(nc):
-        t = np.cumsum(rng.exponential(1.0 / args.rate_hz, size=int(args.sim_seconds * args.rate_hz * 2) + 8))
-        t = t[t < args.sim_seconds]
-        arr_t.append(t)
-        arr_c.append(np.full(len(t), c))
-    at = np.concatenate(arr_t)
-    ac = np.concatenate(arr_c)
-    order = np.argsort(at, kind="stable")
-    at, ac = at[order], ac[order]
+    total_rate = nc * args.rate_hz
+    win = 0.1
+
+    def window(t_lo):
+        t_hi = min(t_lo + win, args.sim_seconds)
+        k = rng.poisson(total_rate * (t_hi - t_lo))
+        return np.sort(rng.uniform(t_lo, t_hi, k)), rng.integers(0, nc, k), t_hi
+
     srv = mpc.Server(precision=args.serve_precision, iters=args.iters,
                      hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)), max_batch=args.max_batch,
-                     max_inflight=3, supersede=args.supersede)
+                     max_inflight=args.max_inflight, supersede=args.supersede)
     # warm every controller once (cold first solves), outside the measurement
     srv.submit_many(np.arange(nc), rec_s, rec_p, u0_ptr, np.zeros(nc))
     srv.drain()
     srv.poll(cap=nc + 16)
     # tickets are consecutive integers: arrival times indexed by ticket
-    t_arr = np.full(len(at) + nc + 16, np.nan)
+    tk_base = nc
+    t_arr = np.full(int(total_rate * args.sim_seconds * 1.01) + 1024, np.nan)
     lat = []
     t0 = srv.clock()
-    i, n, outstanding = 0, len(at), 0
+    n, outstanding = 0, 0
+    at, ac, t_next = window(0.0)
+    i = 0
     sup_seen = srv.stats()["superseded"]
-    while i < n or outstanding:
+    next_report = 10.0
+    while True:
         now = srv.clock() - t0
+        while i == len(at) and t_next < args.sim_seconds and t_next <= now + win:
+            at, ac, t_next = window(t_next)
+            i = 0
         j = np.searchsorted(at, now, side="right")
         if j > i:
             idx = ac[i:j]
             tk = srv.submit_many(idx, rec_s[idx], rec_p[idx], u0_ptr[idx], t0 + at[i:j])
-            t_arr[tk] = t0 + at[i:j]
+            if tk[-1] - tk_base >= len(t_arr):
+                t_arr = np.concatenate([t_arr, np.full(len(t_arr) // 2 + j - i, np.nan)])
+            t_arr[tk - tk_base] = t0 + at[i:j]
             outstanding += j - i
+            n += j - i
             i = j
         tk, tm = srv.poll()
         if len(tk):
-            lat.append(tm - t_arr[tk])
+            lat.append(tm - t_arr[tk - tk_base])
             outstanding -= len(tk)
         if args.supersede:
             sup = srv.stats()["superseded"]
             outstanding -= sup - sup_seen
             sup_seen = sup
-        if i >= n and outstanding:
+        if now >= next_report:
+            print(f"serve: {now:.0f} s of {args.sim_seconds:g}, {n} requests, {outstanding} outstanding",
+                  file=sys.stderr, flush=True)
+            next_report += 10.0
+        done_arriving = i == len(at) and t_next >= args.sim_seconds
+        if done_arriving and not outstanding:
+            break
+        if done_arriving:
             srv.drain()
     lat = np.concatenate(lat) if lat else np.zeros(1)
     t_end = srv.clock() - t0
@@ -476,7 +495,8 @@ def serve(args):
                                   "half quadruped (36, 24), warm-started", "controllers": nc,
                       "offered_rate": nc * args.rate_hz, "requests": int(n),
                       "admm_iters": args.iters, "hbm_budget_gb": args.hbm_budget_gb,
-                      "max_batch": args.max_batch, "supersede": bool(args.supersede)},
+                      "max_batch": args.max_batch, "max_inflight": args.max_inflight,
+                      "supersede": bool(args.supersede)},
            "superseded": int(n_sup), "superseded_per_s": n_sup / t_end,
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p95": float(np.percentile(lat, 95)),
                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max())},

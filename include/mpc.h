@@ -302,6 +302,8 @@ mpc_status mpc_plan_replay(mpc_plan_t plan, void* stream);
  * MPC_AGENT_SUPERSEDED once a later batch launches, u0_out is not written, the
  * ticket is never reported by mpc_server_poll, and stats.superseded counts it;
  * the newer request then runs warm-started from the last solved one.
+ * A server runs its batches on four streams of its own (one per hardware
+ * queue of the process), split among its batch slots.
  * ------------------------------------------------------------------------- */
 typedef struct mpc_server_s* mpc_server_t;
 

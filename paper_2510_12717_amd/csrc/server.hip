@@ -82,13 +82,18 @@ struct Ctrl {
   std::deque<Request> queue;     // pending requests, arrival order
 };
 
-constexpr int kSlotStreams = 4;  // streams per batch slot: the slot's own plus three
+// Streams of one server: a process has four hardware queues on this device, so
+// more streams would only share queues, and a batch's launch could then wait
+// in a queue behind another batch's long launch.  With S batch slots each slot
+// owns 4 / S of them (S <= 4; slots beyond four share one stream each, in
+// turn); a batch starts and ends on its slot's first stream and forks its
+// launch groups over the slot's streams, longest first onto the least loaded.
+constexpr int kServerStreams = 4;
 
 struct Slot {
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the shared stream its batch starts and ends on (not owned)
   hipEvent_t done = nullptr;
-  hipStream_t aux[kSlotStreams - 1] = {};
-  hipEvent_t ev_fork = nullptr, ev_join[kSlotStreams - 1] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kServerStreams - 1] = {};
   bool busy = false;
   uint64_t seq = 0;  // launch order of its batch
   // device
@@ -123,6 +128,7 @@ struct mpc_server_s {
   char* arena_base = nullptr;
   int64_t arena_bytes = 0;
   Arena arena;
+  hipStream_t streams[kServerStreams] = {};
   std::vector<Slot> slots;
   std::unordered_map<int64_t, Ctrl> ctrls;
   int64_t n_pending = 0;                         // requests queued, not yet launched
@@ -165,12 +171,9 @@ static int64_t ws_bytes(const mpc_server_s* sv, const mpc_shape& s) {
 static int64_t to_units(int64_t bytes) { return (bytes + kUnit - 1) / kUnit; }
 
 static void free_slot_buffers(Slot& sl) {
-  if (sl.stream) hipStreamDestroy(sl.stream);
   if (sl.done) hipEventDestroy(sl.done);
-  for (int i = 0; i < kSlotStreams - 1; ++i) {
-    if (sl.aux[i]) hipStreamDestroy(sl.aux[i]);
+  for (int i = 0; i < kServerStreams - 1; ++i)
     if (sl.ev_join[i]) hipEventDestroy(sl.ev_join[i]);
-  }
   if (sl.ev_fork) hipEventDestroy(sl.ev_fork);
   hipFree(sl.d_desc);
   hipFree(sl.d_list);
@@ -191,6 +194,8 @@ static void free_slot_buffers(Slot& sl) {
 static void free_server(mpc_server_s* s) {
   if (!s) return;
   for (auto& sl : s->slots) free_slot_buffers(sl);
+  for (hipStream_t& st : s->streams)
+    if (st) hipStreamDestroy(st);
   hipFree(s->arena_base);
   if (s->ev_ref) hipEventDestroy(s->ev_ref);
   delete s;
@@ -250,15 +255,15 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   }
   hipError_t e = hipMalloc((void**)&s->arena_base, (size_t)s->arena_bytes);
   s->arena.init(s->arena_bytes / kUnit);
+  for (hipStream_t& st : s->streams)
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   s->slots.resize(desc->max_inflight);
   for (auto& sl : s->slots) {
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    sl.stream = s->streams[0];
     if (e == hipSuccess) e = hipEventCreate(&sl.done);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_fork, hipEventDisableTiming);
-    for (int i = 0; i < kSlotStreams - 1 && e == hipSuccess; ++i) {
-      e = hipStreamCreateWithFlags(&sl.aux[i], hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_join[i], hipEventDisableTiming);
-    }
+    for (int i = 0; i < kServerStreams - 1 && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&sl.ev_join[i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_desc, sizeof(AgentDesc) * B);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_list, sizeof(int32_t) * B);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_u0, sizeof(void*) * B);
@@ -280,7 +285,7 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   s->lds_max = lds_max;
   if (e == hipSuccess && !s->fp64) e = fused_set_limits();
   if (e == hipSuccess) e = hipEventCreate(&s->ev_ref);
-  if (e == hipSuccess) e = hipEventRecord(s->ev_ref, s->slots[0].stream);
+  if (e == hipSuccess) e = hipEventRecord(s->ev_ref, s->streams[0]);
   if (e == hipSuccess) e = hipEventSynchronize(s->ev_ref);
   if (e != hipSuccess) {
     const mpc_status st = api_fail(e == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,
@@ -297,8 +302,8 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
 extern "C" mpc_status mpc_server_destroy(mpc_server_t s) {
   if (!s) return api_fail(MPC_ERR_INVALID_ARG, "null server");
   hipSetDevice(s->desc.solver.device);
-  for (auto& sl : s->slots)
-    if (sl.stream) hipStreamSynchronize(sl.stream);
+  for (hipStream_t st : s->streams)
+    if (st) hipStreamSynchronize(st);
   free_server(s);
   return MPC_OK;
 }
@@ -545,6 +550,10 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
     g.lds_a = generic_admm_lds(g.N, g.nx, g.nu, g.nu + 4 * g.n_feet, s->esz);
     gl.push_back(g);
   }
+  const int n_slots = (int)s->slots.size();
+  const int per_slot = std::max(1, kServerStreams / n_slots);
+  const int base = (int)((&sl - s->slots.data()) * per_slot % kServerStreams);
+  sl.stream = s->streams[base];
   hipStream_t st = sl.stream;
   {
     const mpc_status fr = flush_superseded(s, sl);
@@ -557,20 +566,23 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
   State<T> state{(T*)s->arena_base, (T*)s->arena_base, (T*)s->arena_base, (T*)s->arena_base,
                  (T*)sl.d_obj, sl.d_res, sl.d_status};
   const int iters = s->desc.solver.admm_iters;
-  // groups spread over the slot's streams, forked from and joined back into its own
-  std::stable_sort(gl.begin(), gl.end(), [](const G& x, const G& y) {
-    return (int64_t)x.count * x.N * (x.nx + x.nu) > (int64_t)y.count * y.N * (y.nx + y.nu);
-  });
-  const int ns = std::min<int>(kSlotStreams, (int)gl.size());
+  // groups spread over the slot's streams, forked from and joined back into its
+  // own; longest group first onto the stream with the least work so far
+  auto cost = [](const G& g) { return (int64_t)g.count * g.N * (g.nx + g.nu); };
+  std::stable_sort(gl.begin(), gl.end(), [&](const G& x, const G& y) { return cost(x) > cost(y); });
+  const int ns = std::min<int>(per_slot, (int)gl.size());
+  auto aux = [&](int i) { return s->streams[(base + 1 + i) % kServerStreams]; };
+  std::vector<int64_t> load(ns, 0);
   if (ns > 1) {
     MPC_HIP_TRY(hipEventRecord(sl.ev_fork, sl.stream));
-    for (int i = 0; i < ns - 1; ++i) MPC_HIP_TRY(hipStreamWaitEvent(sl.aux[i], sl.ev_fork, 0));
+    for (int i = 0; i < ns - 1; ++i) MPC_HIP_TRY(hipStreamWaitEvent(aux(i), sl.ev_fork, 0));
   }
   for (size_t gi = 0; gi < gl.size(); ++gi) {
     const G& g = gl[gi];
     const int32_t* list = sl.d_list + g.off;
-    const int si = (int)(gi % ns);
-    hipStream_t st = si == 0 ? sl.stream : sl.aux[si - 1];
+    const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[si] += cost(g);
+    hipStream_t st = si == 0 ? sl.stream : aux(si - 1);
     if constexpr (std::is_same<T, float>::value) {
       if (g.fam == 2) {
         MPC_HIP_TRY(fused_solve_f32(sl.d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet, in, sc,
@@ -599,7 +611,7 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
                                        (const T*)s->arena_base, state, g.lds_a, 256, st));
   }
   for (int i = 0; i < ns - 1; ++i) {
-    MPC_HIP_TRY(hipEventRecord(sl.ev_join[i], sl.aux[i]));
+    MPC_HIP_TRY(hipEventRecord(sl.ev_join[i], aux(i)));
     MPC_HIP_TRY(hipStreamWaitEvent(sl.stream, sl.ev_join[i], 0));
   }
   st = sl.stream;
@@ -779,10 +791,11 @@ extern "C" mpc_status mpc_server_drain(mpc_server_t s) {
     if (!any) {
       if (s->n_pending == 0) {
         // every slot is idle: write the superseded statuses still waiting
+        s->slots[0].stream = s->streams[0];
         while (!s->sup_status.empty()) {
           r = flush_superseded(s, s->slots[0]);
           if (r != MPC_OK) return r;
-          MPC_HIP_TRY(hipStreamSynchronize(s->slots[0].stream));
+          MPC_HIP_TRY(hipStreamSynchronize(s->streams[0]));
         }
         return MPC_OK;
       }

@@ -80,20 +80,25 @@ def lib():
         L.orc_constraint_matrix.argtypes = [P(_Shape), ctypes.c_double, _D]
         L.orc_stage_bounds.argtypes = [P(_Shape), P(Settings), _D, _U8, _D, _D, _D]
         L.orc_factor.argtypes = [P(_Shape), P(Settings), _D, _D, _D, _D, _D, _D, ctypes.c_double,
-                                 _D, _D, _D, _D, _D]
+                                 _D, _D, _D, _D, _D, _D]
+        L.orc_contact_rows.argtypes = [P(_Shape)]
+        L.orc_contact_rows.restype = ctypes.c_int32
+        L.orc_contact_bounds.argtypes = [P(_Shape), P(Settings), _U8, _D, _D, _D]
+        L.orc_contact_weight.argtypes = [P(_Shape), _D, _D, _D]
         L.orc_state_penalties.argtypes = [P(_Shape), P(Settings), _D, _D, _D]
         L.orc_factor.restype = ctypes.c_int
         L.orc_xupdate.argtypes = [P(_Shape), _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.orc_residuals.argtypes = [P(_Shape), P(Settings), _D, _D, _D, _D, _D, _D, _D, _D, _D,
-                                    ctypes.c_double, _U8, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+                                    ctypes.c_double, _U8, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D,
+                                    _D, _D, _D]
         L.orc_solve.argtypes = [P(_Shape), P(Settings), _D, _D, _D, _D, _D, _D, _D, _D, _D,
                                 ctypes.c_double, _U8, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_int, _D, _D, _D, _D, _D, _D, ctypes.POINTER(ctypes.c_int),
-                                _D, _D, _D, _D]
+                                _D, _D, _D, _D, _D, _D, _D]
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve_batch.argtypes = [ctypes.c_int32, _I32, P(Settings), _D, _D, _D, _D, _D, _D,
                                       _D, _D, _D, _D, _U8, ctypes.c_int, ctypes.c_int, _D, _D, _D,
-                                      _D, _D, _D, _I32, ctypes.c_int, _D, _D, _D, _D]
+                                      _D, _D, _D, _I32, ctypes.c_int, _D, _D, _D, _D, _D, _D, _D]
         L.orc_solve_batch.restype = ctypes.c_int
         L.orc_advance_batch.argtypes = [ctypes.c_int32, _I32, _D, _D, _D, _D, _D, _D, _D]
         _lib = L
@@ -145,9 +150,33 @@ def state_penalties(s, x_lo, x_hi, settings: Optional[Settings] = None) -> np.nd
     return out
 
 
-def factor(s, A, B, c, q, r, rho, mu, settings: Optional[Settings] = None, qx=None):
+def contact_rows(s) -> int:
+    """No-slip rows per stage: n_feet * foot_dim."""
+    return int(lib().orc_contact_rows(ctypes.byref(_shape(s))))
+
+
+def contact_bounds(s, stance, settings: Optional[Settings] = None):
+    """(l, h, rho) [N, nc] of the no-slip rows of x_1..x_N."""
+    st = settings or Settings.default()
+    nc = contact_rows(s)
+    l, h, rho = (np.zeros((s.N, nc)) for _ in range(3))
+    stance = np.ascontiguousarray(stance, dtype=np.uint8)
+    lib().orc_contact_bounds(ctypes.byref(_shape(s)), ctypes.byref(st), stance.ctypes.data_as(_U8),
+                             _d(l), _d(h), _d(rho))
+    return l, h, rho
+
+
+def contact_weight(s, J, rho_c) -> np.ndarray:
+    """Qadd [N+1, nx, nx] = J' diag(rho_c,k) J per stage (zero at k = 0)."""
+    out = np.zeros((s.N + 1, s.nx, s.nx))
+    lib().orc_contact_weight(ctypes.byref(_shape(s)), _d(_f64(J)), _d(_f64(rho_c)), _d(out))
+    return out
+
+
+def factor(s, A, B, c, q, r, rho, mu, settings: Optional[Settings] = None, qx=None, Qadd=None):
     """Riccati factor: returns (status, K [N,nu,nx], L [N,nu,nu], s [N,nx], P [N+1,nx,nx]).
-    ``qx`` [nx]: state-row penalties added to the state weight (joint limits)."""
+    ``qx`` [nx]: joint-limit penalties added to the state weight; ``Qadd``
+    [N+1, nx, nx]: per-stage additions to it (no-slip rows)."""
     st = settings or Settings.default()
     K = np.zeros((s.N, s.nu, s.nx))
     L = np.zeros((s.N, s.nu, s.nu))
@@ -155,7 +184,8 @@ def factor(s, A, B, c, q, r, rho, mu, settings: Optional[Settings] = None, qx=No
     P = np.zeros((s.N + 1, s.nx, s.nx))
     status = lib().orc_factor(ctypes.byref(_shape(s)), ctypes.byref(st), _d(_f64(A)), _d(_f64(B)),
                               _d(_f64(c)), _d(_f64(q)), _d(_f64(r)), _d(_f64(rho)), float(mu),
-                              _d(K), _d(L), _d(sv), _d(P), _d(None if qx is None else _f64(qx)))
+                              _d(K), _d(L), _d(sv), _d(P), _d(None if qx is None else _f64(qx)),
+                              _d(None if Qadd is None else _f64(Qadd)))
     return status, K, L, sv, P
 
 
@@ -170,9 +200,11 @@ def xupdate(s, A, B, c, K, L, sv, x0, qt, rt):
 
 
 def residuals(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x, u, z, y, u_ref=None,
-              settings: Optional[Settings] = None, x_lo=None, x_hi=None, zx=None, yx=None):
+              settings: Optional[Settings] = None, x_lo=None, x_hi=None, zx=None, yx=None,
+              J=None, zc=None, yc=None):
     """(res[4] = primal, dual, dynamics, complementarity; objective).  With joint
-    limits (x_lo, x_hi [nx]) the state rows' (zx, yx) [N][nx] take part."""
+    limits (x_lo, x_hi [nx]) the state rows' (zx, yx) [N][nx] take part, with
+    no-slip rows (J [nc, nx]) their (zc, yc) [N][nc]."""
     st = settings or Settings.default()
     res = np.zeros(4)
     obj = np.zeros(1)
@@ -182,7 +214,7 @@ def residuals(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x, u, z, y, u_re
                         _d(None if u_ref is None else _f64(u_ref)), _d(_f64(x0)),
                         _d(_f64(tau_max)), float(mu), stance.ctypes.data_as(_U8), _d(_f64(x)),
                         _d(_f64(u)), _d(_f64(z)), _d(_f64(y)), _d(res), _d(obj),
-                        *_limits(x_lo, x_hi, zx, yx))
+                        *_limits(x_lo, x_hi, zx, yx), *_contacts(J, zc, yc))
     return res, float(obj[0])
 
 
@@ -192,14 +224,21 @@ def _limits(x_lo, x_hi, zx, yx):
     return tuple(_d(_f64(v)) for v in (x_lo, x_hi, zx, yx))
 
 
+def _contacts(J, zc, yc):
+    if J is None:
+        return (None, None, None)
+    return tuple(_d(_f64(v)) for v in (J, zc, yc))
+
+
 def solve(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, iters=50, warm=None,
           u_ref=None, tol=1e-10, max_iters=1_000_000, settings: Optional[Settings] = None,
-          x_lo=None, x_hi=None):
+          x_lo=None, x_hi=None, J=None):
     """Solve one agent.  ``iters <= 0`` selects converge mode.
 
-    ``warm`` is None (cold) or a tuple (u, z, y), with joint limits (x_lo, x_hi)
-    (u, z, y, zx, yx).  Returns a dict with x, u, z, y, (zx, yx,) res, objective,
-    status, iters.
+    ``warm`` is None (cold) or a tuple (u, z, y), followed by (zx, yx) with
+    joint limits (x_lo, x_hi) and by (zc, yc) with no-slip rows (J [nc, nx]).
+    Returns a dict with x, u, z, y, (zx, yx,) (zc, yc,) res, objective, status,
+    iters.
     """
     st = settings or Settings.default()
     m = rows(s)
@@ -215,6 +254,15 @@ def solve(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, iters=50, warm=No
             zx, yx = np.zeros((s.N, s.nx)), np.zeros((s.N, s.nx))
         else:
             zx, yx = (np.array(v, dtype=np.float64, order="C").reshape(s.N, s.nx) for v in warm[3:5])
+    zc = yc = None
+    if J is not None:
+        nc = contact_rows(s)
+        if warm is None:
+            zc, yc = np.zeros((s.N, nc)), np.zeros((s.N, nc))
+        else:
+            w0 = 5 if x_lo is not None else 3
+            zc, yc = (np.array(v, dtype=np.float64, order="C").reshape(s.N, nc)
+                      for v in warm[w0:w0 + 2])
     res = np.zeros(4)
     obj = np.zeros(1)
     it = ctypes.c_int(0)
@@ -225,11 +273,13 @@ def solve(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, *, iters=50, warm=No
                              _d(_f64(tau_max)), float(mu), stance.ctypes.data_as(_U8), int(iters),
                              0 if warm is None else 1, float(tol), int(max_iters), _d(x), _d(u),
                              _d(z), _d(y), _d(res), _d(obj), ctypes.byref(it),
-                             *_limits(x_lo, x_hi, zx, yx))
+                             *_limits(x_lo, x_hi, zx, yx), *_contacts(J, zc, yc))
     out = dict(x=x, u=u, z=z, y=y, res=res, objective=float(obj[0]), status=status,
                iters=it.value)
     if x_lo is not None:
         out.update(zx=zx, yx=yx)
+    if J is not None:
+        out.update(zc=zc, yc=yc)
     return out
 
 
@@ -252,13 +302,14 @@ def _shapes_arr(batch) -> np.ndarray:
 
 
 def solve_batch(batch, *, iters=50, warm=None, x0=None, u_ref=None, n_threads=0,
-                settings: Optional[Settings] = None, x_lo=None, x_hi=None) -> dict:
+                settings: Optional[Settings] = None, x_lo=None, x_hi=None, J=None) -> dict:
     """Fixed-iteration solve of every agent of a ``synth.Batch`` (flat layouts).
 
-    ``warm`` is None or a dict with flat u, z, y (and zx, yx with joint limits).
-    ``x0`` overrides batch.x0.  ``x_lo``/``x_hi`` (flat, nx per agent): joint
-    limits.  Returns flat x, u, z, y, (zx, yx,) res [n,4], objective [n],
-    status [n], threads.
+    ``warm`` is None or a dict with flat u, z, y (and zx, yx with joint limits,
+    zc, yc with no-slip rows).  ``x0`` overrides batch.x0.  ``x_lo``/``x_hi``
+    (flat, nx per agent): joint limits.  ``J`` (flat, n_feet*foot_dim x nx per
+    agent): no-slip rows.  Returns flat x, u, z, y, (zx, yx,) (zc, yc,) res
+    [n,4], objective [n], status [n], threads.
     """
     st = settings or Settings.default()
     o = batch.offsets()
@@ -275,6 +326,13 @@ def solve_batch(batch, *, iters=50, warm=None, x0=None, u_ref=None, n_threads=0,
             zx, yx = np.zeros(nzx), np.zeros(nzx)
         else:
             zx, yx = (np.array(warm[k], dtype=np.float64) for k in ("zx", "yx"))
+    zc = yc = None
+    if J is not None:
+        nzc = sum(sh.N * sh.n_feet * sh.foot_dim for sh in batch.shapes)
+        if warm is None:
+            zc, yc = np.zeros(nzc), np.zeros(nzc)
+        else:
+            zc, yc = (np.array(warm[k], dtype=np.float64) for k in ("zc", "yc"))
     res = np.zeros((n, 4))
     obj = np.zeros(n)
     status = np.zeros(n, dtype=np.int32)
@@ -287,10 +345,12 @@ def solve_batch(batch, *, iters=50, warm=None, x0=None, u_ref=None, n_threads=0,
         _d(None if u_ref is None else _f64(u_ref)), _d(x0v), _d(_f64(batch.tau_max)),
         _d(_f64(batch.mu)), stance.ctypes.data_as(_U8), int(iters), 0 if warm is None else 1,
         _d(x), _d(u), _d(z), _d(y), _d(res), _d(obj), status.ctypes.data_as(_I32),
-        int(n_threads), *_limits(x_lo, x_hi, zx, yx))
+        int(n_threads), *_limits(x_lo, x_hi, zx, yx), *_contacts(J, zc, yc))
     out = dict(x=x, u=u, z=z, y=y, res=res, objective=obj, status=status, threads=threads)
     if x_lo is not None:
         out.update(zx=zx, yx=yx)
+    if J is not None:
+        out.update(zc=zc, yc=yc)
     return out
 
 

@@ -20,7 +20,15 @@
  *     infinite bounds), split like the input rows with their own (z_x, y_x)
  *     and OSQP's penalty rule; since the rows are the identity on x, they add
  *     diag(rho_x) to the state weight of the Riccati factor and
- *     y_x - rho_x z_x to the state's linear term.
+ *     y_x - rho_x z_x to the state's linear term;
+ *   - no-slip rows of Eq. (mpc_formulation), optional: J_f v_k = 0 for every
+ *     foot f in stance, as rows Jc (n_feet * foot_dim rows over the whole
+ *     state, zero on the positions; the Jacobian at the linearisation point,
+ *     the same at every stage) on x_k, k = 1..N, with the stance of stage
+ *     min(k, N-1) (x_N keeps the last stage's contacts); rows of a swinging
+ *     foot are free.  Split like the input rows with their own (z_c, y_c) and
+ *     OSQP's penalty rule, they add Jc' diag(rho_c,k) Jc to the state weight
+ *     of stage k and Jc'(y_c - rho_c z_c) to the state's linear term.
  */
 #include "mpc_oracle.h"
 
@@ -113,6 +121,44 @@ void orc_state_penalties(const orc_shape* s, const orc_settings* st, const doubl
   }
 }
 
+int32_t orc_contact_rows(const orc_shape* s) { return s->n_feet * s->foot_dim; }
+
+/* Bounds and penalties of the no-slip rows of x_k (k = 1..N, stored at k-1):
+ * the foot_dim rows of foot f are J_f v_k = 0 (an equality row, penalty
+ * rho_eq_scale * rho) while f is in stance at stage min(k, N-1), and free
+ * (both bounds infinite, penalty rho_min) while it swings. */
+void orc_contact_bounds(const orc_shape* s, const orc_settings* st, const uint8_t* stance,
+                        double* l, double* h, double* rho) {
+  const int nc = orc_contact_rows(s);
+  for (int k = 1; k <= s->N; ++k) {
+    const int sk = k < s->N ? k : s->N - 1;
+    for (int f = 0; f < s->n_feet; ++f) {
+      const int in_stance = stance[sk * s->n_feet + f] != 0;
+      for (int j = 0; j < s->foot_dim; ++j) {
+        const size_t idx = (size_t)(k - 1) * nc + f * s->foot_dim + j;
+        l[idx] = in_stance ? 0.0 : -INFINITY;
+        h[idx] = in_stance ? 0.0 : INFINITY;
+        rho[idx] = in_stance ? st->rho_eq_scale * st->rho : st->rho_min;
+      }
+    }
+  }
+}
+
+/* Qadd [N+1][nx][nx]: Jc' diag(rho_c,k) Jc for the no-slip rows of x_k,
+ * k = 1..N, and zero at k = 0 (x_0 is fixed). */
+void orc_contact_weight(const orc_shape* s, const double* Jc, const double* rho_c, double* Qadd) {
+  const int nx = s->nx, nc = orc_contact_rows(s);
+  memset(Qadd, 0, sizeof(double) * (size_t)(s->N + 1) * nx * nx);
+  for (int k = 1; k <= s->N; ++k)
+    for (int i = 0; i < nx; ++i)
+      for (int j = 0; j < nx; ++j) {
+        double acc = 0.0;
+        for (int row = 0; row < nc; ++row)
+          acc += Jc[row * nx + i] * rho_c[(size_t)(k - 1) * nc + row] * Jc[row * nx + j];
+        Qadd[((size_t)k * nx + i) * nx + j] = acc;
+      }
+}
+
 /* Lower Cholesky factor of the n x n SPD matrix H (row-major), row by row
  * (Cholesky-Banachiewicz).  Returns 0 if H is not positive definite. */
 static int cholesky(int n, const double* H, double* L) {
@@ -147,15 +193,18 @@ static void chol_solve(int n, const double* L, double* v) {
 }
 
 /* Riccati factor of the x-subproblem (the role of Eq. (ldl), once per solve).
- * P_N = Q~ = Q + sigma I (+ diag(rho_x) with joint limits); for k = N-1 .. 0:
+ * P_N = Q~_N; for k = N-1 .. 0, with Q~_k = Q + sigma I (+ diag(rho_x) with
+ * joint limits, + Qadd_k with no-slip rows):
  *   Rt_k = R + sigma I + C_k' diag(rho_k) C_k
  *   H_k = Rt_k + B_k' P_{k+1} B_k,   G_k = B_k' P_{k+1} A_k,   H_k = L_k L_k'
  *   K_k = -H_k^{-1} G_k,   s_k = P_{k+1} c_k
- *   P_k = Q~ + A_k' P_{k+1} A_k + G_k' K_k   (then symmetrised)
- * qx (may be NULL): the state rows' penalties rho_x, added to Q~.            */
+ *   P_k = Q~_k + A_k' P_{k+1} A_k + G_k' K_k   (then symmetrised)
+ * qx (may be NULL): the joint-limit rows' penalties rho_x, added to Q~;
+ * Qadd (may be NULL): [N+1][nx][nx], added to Q~_k (no-slip rows).          */
 int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, const double* B,
                const double* c, const double* q, const double* r, const double* rho,
-               double mu, double* K, double* L, double* sv, double* P, const double* qx) {
+               double mu, double* K, double* L, double* sv, double* P, const double* qx,
+               const double* Qadd) {
   const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s);
   double* C = (double*)malloc(sizeof(double) * m * nu);
   double* Pn = (double*)malloc(sizeof(double) * nx * nx);
@@ -169,7 +218,9 @@ int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, cons
   orc_constraint_matrix(s, mu, C);
 
   for (int i = 0; i < nx; ++i)
-    for (int j = 0; j < nx; ++j) Pn[i * nx + j] = (i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0;
+    for (int j = 0; j < nx; ++j)
+      Pn[i * nx + j] = ((i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0) +
+                       (Qadd ? Qadd[((size_t)N * nx + i) * nx + j] : 0.0);
   if (P) memcpy(P + (size_t)N * nx * nx, Pn, sizeof(double) * nx * nx);
 
   for (int k = N - 1; k >= 0; --k) {
@@ -221,7 +272,8 @@ int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, cons
     }
     for (int i = 0; i < nx; ++i)
       for (int j = 0; j < nx; ++j) {
-        double acc = (i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0;
+        double acc = ((i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0) +
+                     (Qadd ? Qadd[((size_t)k * nx + i) * nx + j] : 0.0);
         for (int t = 0; t < nx; ++t) acc += Ak[t * nx + i] * PA[t * nx + j];
         for (int t = 0; t < nu; ++t) acc += G[t * nx + i] * Kk[t * nx + j];
         Pk[i * nx + j] = acc;
@@ -303,7 +355,9 @@ static double maxabs(double a, double b) { return fabs(a) > b ? fabs(a) : b; }
  *          z_i = l_i (y in the normal cone of [l, h] at z), and l <= z <= h.
  * With joint limits (x_lo != NULL) the state rows join: their multipliers y_x
  * enter the costates, lambda_k = Q (x_k - r_k) + y_x,k + A_k' lambda_{k+1},
- * |x_k - z_x,k| the primal residual and (z_x, y_x) the complementarity test. */
+ * |x_k - z_x,k| the primal residual and (z_x, y_x) the complementarity test.
+ * No-slip rows (Jc != NULL) likewise: Jc' y_c,k joins lambda_k, |Jc x_k - z_c,k|
+ * the primal residual and (z_c, y_c) the complementarity test. */
 static void complementarity(double lo, double hi, double zz, double yy, double* rc);
 
 void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, const double* B,
@@ -311,9 +365,14 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
                    const double* u_ref, const double* x0, const double* tau_max, double mu,
                    const uint8_t* stance, const double* x, const double* u, const double* z,
                    const double* y, double* res, double* objective, const double* x_lo,
-                   const double* x_hi, const double* zx, const double* yx) {
-  const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s);
+                   const double* x_hi, const double* zx, const double* yx, const double* Jc,
+                   const double* zc, const double* yc) {
+  const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s), nc = orc_contact_rows(s);
   double* lam = (double*)malloc(sizeof(double) * (size_t)(N + 1) * nx);
+  double* lc = (double*)malloc(sizeof(double) * (size_t)N * (nc > 0 ? nc : 1));
+  double* hc = (double*)malloc(sizeof(double) * (size_t)N * (nc > 0 ? nc : 1));
+  double* rc_pen = (double*)malloc(sizeof(double) * (size_t)N * (nc > 0 ? nc : 1));
+  if (Jc) orc_contact_bounds(s, st, stance, lc, hc, rc_pen);
   double* C = (double*)malloc(sizeof(double) * m * nu);
   double* l = (double*)malloc(sizeof(double) * (size_t)N * m);
   double* h = (double*)malloc(sizeof(double) * (size_t)N * m);
@@ -334,14 +393,20 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
     }
   *objective = obj;
 
-  for (int i = 0; i < nx; ++i)
-    lam[(size_t)N * nx + i] = q[i] * (x[(size_t)N * nx + i] - x_ref[(size_t)N * nx + i]) +
-                              (x_lo ? yx[(size_t)(N - 1) * nx + i] : 0.0);
+  for (int i = 0; i < nx; ++i) {
+    double acc = q[i] * (x[(size_t)N * nx + i] - x_ref[(size_t)N * nx + i]) +
+                 (x_lo ? yx[(size_t)(N - 1) * nx + i] : 0.0);
+    if (Jc)
+      for (int row = 0; row < nc; ++row) acc += Jc[row * nx + i] * yc[(size_t)(N - 1) * nc + row];
+    lam[(size_t)N * nx + i] = acc;
+  }
   for (int k = N - 1; k >= 1; --k) {
     const double* Ak = A + (size_t)k * nx * nx;
     for (int i = 0; i < nx; ++i) {
       double acc = q[i] * (x[(size_t)k * nx + i] - x_ref[(size_t)k * nx + i]);
       if (x_lo) acc += yx[(size_t)(k - 1) * nx + i];
+      if (Jc)
+        for (int row = 0; row < nc; ++row) acc += Jc[row * nx + i] * yc[(size_t)(k - 1) * nc + row];
       for (int t = 0; t < nx; ++t) acc += Ak[t * nx + i] * lam[(size_t)(k + 1) * nx + t];
       lam[(size_t)k * nx + i] = acc;
     }
@@ -379,12 +444,20 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
         rp = maxabs(x[(size_t)(k + 1) * nx + i] - zx[idx], rp);
         complementarity(x_lo[i], x_hi[i], zx[idx], yx[idx], &rc);
       }
+    if (Jc)  /* the no-slip rows of x_{k+1} */
+      for (int row = 0; row < nc; ++row) {
+        const size_t idx = (size_t)k * nc + row;
+        double acc = 0.0;
+        for (int t = 0; t < nx; ++t) acc += Jc[row * nx + t] * x[(size_t)(k + 1) * nx + t];
+        rp = maxabs(acc - zc[idx], rp);
+        complementarity(lc[idx], hc[idx], zc[idx], yc[idx], &rc);
+      }
   }
   res[0] = rp;
   res[1] = rd;
   res[2] = ry;
   res[3] = rc;
-  free(lam); free(C); free(l); free(h); free(rho);
+  free(lam); free(C); free(l); free(h); free(rho); free(lc); free(hc); free(rc_pen);
 }
 
 /* Complementarity test of one row: y > 0 needs z = h, y < 0 needs z = l, and
@@ -414,9 +487,10 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
               const double* u_ref, const double* x0, const double* tau_max, double mu,
               const uint8_t* stance, int iters, int warm, double tol, int max_iters,
               double* x, double* u, double* z, double* y, double* res, double* objective,
-              int* iters_done, const double* x_lo, const double* x_hi, double* zx, double* yx) {
-  const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s);
-  const size_t nZx = (size_t)N * nx;
+              int* iters_done, const double* x_lo, const double* x_hi, double* zx, double* yx,
+              const double* Jc, double* zc, double* yc) {
+  const int N = s->N, nx = s->nx, nu = s->nu, m = orc_rows(s), nc = orc_contact_rows(s);
+  const size_t nZx = (size_t)N * nx, nZc = (size_t)N * nc;
   const double alpha = st->alpha, sigma = st->sigma;
   const size_t nX = (size_t)(N + 1) * nx, nU = (size_t)N * nu, nZ = (size_t)N * m;
   int status = ORC_OK, it = 0;
@@ -428,7 +502,9 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
                         all_finite(tau_max, s->n_tau) && isfinite(mu) &&
                         (!u_ref || all_finite(u_ref, nU)) &&
                         (!warm || (all_finite(u, nU) && all_finite(z, nZ) && all_finite(y, nZ))) &&
-                        (!x_lo || !warm || (all_finite(zx, nZx) && all_finite(yx, nZx)));
+                        (!x_lo || !warm || (all_finite(zx, nZx) && all_finite(yx, nZx))) &&
+                        (!Jc || all_finite(Jc, (size_t)nc * nx)) &&
+                        (!Jc || !warm || (all_finite(zc, nZc) && all_finite(yc, nZc)));
   int bounds_ok = 1;
   if (x_lo)
     for (int i = 0; i < nx; ++i)
@@ -436,6 +512,7 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
   if (!finite_in || !bounds_ok) {
     fill_nan(x, nX); fill_nan(u, nU); fill_nan(z, nZ); fill_nan(y, nZ);
     if (x_lo) { fill_nan(zx, nZx); fill_nan(yx, nZx); }
+    if (Jc) { fill_nan(zc, nZc); fill_nan(yc, nZc); }
     fill_nan(res, 4); *objective = NAN;
     return ORC_NONFINITE;
   }
@@ -452,11 +529,19 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
   double* xt = (double*)malloc(sizeof(double) * nX);
   double* ut = (double*)malloc(sizeof(double) * nU);
   double* rho_x = (double*)malloc(sizeof(double) * (size_t)nx);
+  double* lc = (double*)malloc(sizeof(double) * (nZc > 0 ? nZc : 1));
+  double* hc = (double*)malloc(sizeof(double) * (nZc > 0 ? nZc : 1));
+  double* rho_c = (double*)malloc(sizeof(double) * (nZc > 0 ? nZc : 1));
+  double* Qadd = Jc ? (double*)malloc(sizeof(double) * (size_t)(N + 1) * nx * nx) : NULL;
   orc_constraint_matrix(s, mu, C);
   orc_stage_bounds(s, st, tau_max, stance, l, h, rho);
   if (x_lo) orc_state_penalties(s, st, x_lo, x_hi, rho_x);
+  if (Jc) {
+    orc_contact_bounds(s, st, stance, lc, hc, rho_c);
+    orc_contact_weight(s, Jc, rho_c, Qadd);
+  }
 
-  if (orc_factor(s, st, A, B, c, q, r, rho, mu, K, L, sv, NULL, x_lo ? rho_x : NULL) != ORC_OK) {
+  if (orc_factor(s, st, A, B, c, q, r, rho, mu, K, L, sv, NULL, x_lo ? rho_x : NULL, Qadd) != ORC_OK) {
     status = ORC_NOT_PD;
     goto done;
   }
@@ -468,6 +553,10 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
     if (x_lo) {
       memset(zx, 0, sizeof(double) * nZx);
       memset(yx, 0, sizeof(double) * nZx);
+    }
+    if (Jc) {
+      memset(zc, 0, sizeof(double) * nZc);
+      memset(yc, 0, sizeof(double) * nZc);
     }
   }
   /* x^0: rollout of the dynamics from xbar0 under u^0 */
@@ -484,11 +573,16 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
   for (it = 0; it < limit; ++it) {
     /* linear terms of the x-subproblem (right-hand side of Eq. (kkt_system)) */
     for (int k = 0; k <= N; ++k)
-      for (int i = 0; i < nx; ++i)
-        qt[(size_t)k * nx + i] = -q[i] * x_ref[(size_t)k * nx + i] - sigma * x[(size_t)k * nx + i] +
-                                 ((x_lo && k >= 1) ? yx[(size_t)(k - 1) * nx + i] -
-                                                         rho_x[i] * zx[(size_t)(k - 1) * nx + i]
-                                                   : 0.0);
+      for (int i = 0; i < nx; ++i) {
+        double acc = -q[i] * x_ref[(size_t)k * nx + i] - sigma * x[(size_t)k * nx + i];
+        if (x_lo && k >= 1) acc += yx[(size_t)(k - 1) * nx + i] - rho_x[i] * zx[(size_t)(k - 1) * nx + i];
+        if (Jc && k >= 1)
+          for (int row = 0; row < nc; ++row) {
+            const size_t idx = (size_t)(k - 1) * nc + row;
+            acc += Jc[row * nx + i] * (yc[idx] - rho_c[idx] * zc[idx]);
+          }
+        qt[(size_t)k * nx + i] = acc;
+      }
     for (int k = 0; k < N; ++k)
       for (int j = 0; j < nu; ++j) {
         double acc = -sigma * u[(size_t)k * nu + j];
@@ -521,10 +615,21 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
           yx[idx] = yx[idx] + rho_x[i] * (w - zn);
           zx[idx] = zn;
         }
+    if (Jc)  /* the no-slip rows: zeta = Jc xt_k, k = 1..N */
+      for (int k = 1; k <= N; ++k)
+        for (int row = 0; row < nc; ++row) {
+          const size_t idx = (size_t)(k - 1) * nc + row;
+          double zeta = 0.0;
+          for (int t = 0; t < nx; ++t) zeta += Jc[row * nx + t] * xt[(size_t)k * nx + t];
+          const double w = alpha * zeta + (1.0 - alpha) * zc[idx];
+          const double zn = fmin(fmax(w + yc[idx] / rho_c[idx], lc[idx]), hc[idx]);
+          yc[idx] = yc[idx] + rho_c[idx] * (w - zn);
+          zc[idx] = zn;
+        }
     if (iters <= 0) {
       double obj;
       orc_residuals(s, st, A, B, c, q, r, x_ref, u_ref, x0, tau_max, mu, stance, x, u, z, y,
-                    res, &obj, x_lo, x_hi, zx, yx);
+                    res, &obj, x_lo, x_hi, zx, yx, Jc, zc, yc);
       double su = 1.0, sd = 1.0;
       for (int k = 0; k < N; ++k)
         for (int row = 0; row < m; ++row) {
@@ -537,6 +642,11 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
           su = maxabs(zx[i], su);
           sd = maxabs(yx[i], sd);
         }
+      if (Jc)
+        for (size_t i = 0; i < nZc; ++i) {
+          su = maxabs(zc[i], su);
+          sd = maxabs(yc[i], sd);
+        }
       if (res[0] <= tol * su && res[1] <= tol * sd) {
         ++it;
         status = ORC_CONVERGED;
@@ -546,24 +656,26 @@ int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const
   }
   *iters_done = it;
   orc_residuals(s, st, A, B, c, q, r, x_ref, u_ref, x0, tau_max, mu, stance, x, u, z, y, res,
-                objective, x_lo, x_hi, zx, yx);
+                objective, x_lo, x_hi, zx, yx, Jc, zc, yc);
   if (!(all_finite(x, nX) && all_finite(u, nU) && all_finite(z, nZ) && all_finite(y, nZ)) ||
-      (x_lo && !(all_finite(zx, nZx) && all_finite(yx, nZx))))
+      (x_lo && !(all_finite(zx, nZx) && all_finite(yx, nZx))) ||
+      (Jc && !(all_finite(zc, nZc) && all_finite(yc, nZc))))
     status = ORC_NONFINITE;
 
 done:
   if (status == ORC_NOT_PD || status == ORC_NONFINITE) {
     fill_nan(x, nX); fill_nan(u, nU); fill_nan(z, nZ); fill_nan(y, nZ);
     if (x_lo) { fill_nan(zx, nZx); fill_nan(yx, nZx); }
+    if (Jc) { fill_nan(zc, nZc); fill_nan(yc, nZc); }
     fill_nan(res, 4); *objective = NAN;
   }
   free(C); free(l); free(h); free(rho); free(K); free(L); free(sv);
-  free(qt); free(rt); free(xt); free(ut); free(rho_x);
+  free(qt); free(rt); free(xt); free(ut); free(rho_x); free(lc); free(hc); free(rho_c); free(Qadd);
   return status;
 }
 
 typedef struct {
-  size_t A, B, c, q, r, xr, x0, tau, st, x, u, z;
+  size_t A, B, c, q, r, xr, x0, tau, st, x, u, z, J, zc;
 } offs;
 
 static void agent_offsets(int32_t n, const int32_t* shapes, offs* o) {
@@ -586,6 +698,8 @@ static void agent_offsets(int32_t n, const int32_t* shapes, offs* o) {
     cur.x += (N + 1) * nx;
     cur.u += N * nu;
     cur.z += N * m;
+    cur.J += nf * (size_t)sh[5] * nx;
+    cur.zc += N * nf * (size_t)sh[5];
   }
 }
 
@@ -596,7 +710,7 @@ int orc_solve_batch(int32_t n, const int32_t* shapes, const orc_settings* st,
                     const uint8_t* stance, int iters, int warm, double* x, double* u,
                     double* z, double* y, double* res, double* objective, int32_t* status,
                     int n_threads, const double* x_lo, const double* x_hi, double* zx,
-                    double* yx) {
+                    double* yx, const double* Jc, double* zc, double* yc) {
   offs* o = (offs*)malloc(sizeof(offs) * (n > 0 ? n : 1));
   agent_offsets(n, shapes, o);
   int used = 1;
@@ -614,7 +728,8 @@ int orc_solve_batch(int32_t n, const int32_t* shapes, const orc_settings* st,
                           x + o[a].x, u + o[a].u, z + o[a].z, y + o[a].z, res + 4 * (size_t)a,
                           objective + a, &done_it, x_lo ? x_lo + o[a].q : NULL,
                           x_lo ? x_hi + o[a].q : NULL, x_lo ? zx + o[a].c : NULL,
-                          x_lo ? yx + o[a].c : NULL);
+                          x_lo ? yx + o[a].c : NULL, Jc ? Jc + o[a].J : NULL,
+                          Jc ? zc + o[a].zc : NULL, Jc ? yc + o[a].zc : NULL);
   }
 #ifdef _OPENMP
   used = n_threads;

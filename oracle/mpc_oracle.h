@@ -63,14 +63,27 @@ void orc_stage_bounds(const orc_shape* s, const orc_settings* st, const double* 
 void orc_state_penalties(const orc_shape* s, const orc_settings* st, const double* x_lo,
                          const double* x_hi, double* rho_x);
 
+/* no-slip rows per stage: n_feet * foot_dim */
+int32_t orc_contact_rows(const orc_shape* s);
+
+/* Bounds and penalties [N][nc] of the no-slip rows of x_1..x_N (stance of
+ * stage min(k, N-1): equality rows; swing: free rows). */
+void orc_contact_bounds(const orc_shape* s, const orc_settings* st, const uint8_t* stance,
+                        double* l, double* h, double* rho);
+
+/* Qadd [N+1][nx][nx] = Jc' diag(rho_c,k) Jc (zero at k = 0); Jc [nc][nx]. */
+void orc_contact_weight(const orc_shape* s, const double* Jc, const double* rho_c, double* Qadd);
+
 /* Riccati factor of the x-update (once per solve).  Outputs:
  *   K [N][nu][nx], L [N][nu][nu] (lower Cholesky factor of H_k, upper part 0),
  *   s [N][nx] = P_{k+1} c_k, P [N+1][nx][nx] (may be NULL).
- * qx [nx] (may be NULL) is added to the state weight (state-row penalties).
+ * qx [nx] (may be NULL) is added to the state weight (joint-limit penalties),
+ * Qadd [N+1][nx][nx] (may be NULL) to the state weight of each stage.
  * Returns ORC_OK or ORC_NOT_PD (at the first stage whose H_k is not PD). */
 int orc_factor(const orc_shape* s, const orc_settings* st, const double* A, const double* B,
                const double* c, const double* q, const double* r, const double* rho,
-               double mu, double* K, double* L, double* sv, double* P, const double* qx);
+               double mu, double* K, double* L, double* sv, double* P, const double* qx,
+               const double* Qadd);
 
 /* One x-update: given the linear terms qt [N+1][nx] and rt [N][nu], run the
  * back-sweep and the forward rollout from x0.  Outputs xt [N+1][nx], ut [N][nu]. */
@@ -85,7 +98,8 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
                    const double* u_ref, const double* x0, const double* tau_max, double mu,
                    const uint8_t* stance, const double* x, const double* u, const double* z,
                    const double* y, double* res, double* objective, const double* x_lo,
-                   const double* x_hi, const double* zx, const double* yx);
+                   const double* x_hi, const double* zx, const double* yx, const double* Jc,
+                   const double* zc, const double* yc);
 
 /* Solve one agent.
  *   warm == 0: u, z, y start at 0; warm == 1: u, z, y are read from the
@@ -95,13 +109,16 @@ void orc_residuals(const orc_shape* s, const orc_settings* st, const double* A, 
  * Outputs x [N+1][nx], u [N][nu], z [N][m], y [N][m], res[4], objective.
  * Joint limits (x_lo, x_hi [nx], may be NULL): the state rows' iterate
  * z_x, y_x [N][nx] (stages 1..N) is read on warm start and written.
+ * No-slip rows (Jc [n_feet*foot_dim][nx], may be NULL): likewise z_c, y_c
+ * [N][n_feet*foot_dim].
  * Returns a status code; *iters_done receives the iteration count. */
 int orc_solve(const orc_shape* s, const orc_settings* st, const double* A, const double* B,
               const double* c, const double* q, const double* r, const double* x_ref,
               const double* u_ref, const double* x0, const double* tau_max, double mu,
               const uint8_t* stance, int iters, int warm, double tol, int max_iters,
               double* x, double* u, double* z, double* y, double* res, double* objective,
-              int* iters_done, const double* x_lo, const double* x_hi, double* zx, double* yx);
+              int* iters_done, const double* x_lo, const double* x_hi, double* zx, double* yx,
+              const double* Jc, double* zc, double* yc);
 
 /* Batched solve over agents with concatenated per-agent arrays (agent order),
  * OpenMP-parallel over agents.  shapes is [n][6] int32 (N,nx,nu,n_tau,n_feet,
@@ -114,7 +131,7 @@ int orc_solve_batch(int32_t n, const int32_t* shapes, const orc_settings* st,
                     const uint8_t* stance, int iters, int warm, double* x, double* u,
                     double* z, double* y, double* res, double* objective, int32_t* status,
                     int n_threads, const double* x_lo, const double* x_hi, double* zx,
-                    double* yx);
+                    double* yx, const double* Jc, double* zc, double* yc);
 
 /* Closed-loop state advance of the agents' own dynamics:
  * x0_next = A_0 x0 + B_0 u_0 + c_0 + noise (all [n] agents, concatenated). */

@@ -293,6 +293,34 @@ def joint_limits(batch: Batch, seed: int = 0):
     return np.concatenate(lo_all).astype(dt), np.concatenate(hi_all).astype(dt)
 
 
+def foot_jacobians(batch: Batch, seed: int = 0):
+    """Velocity Jacobians of the feet for the no-slip rows J_f v = 0 of
+    Eq. (mpc_formulation), flat, n_feet * foot_dim rows of nx columns per
+    agent (row-major): the state is (q, v) of a floating base plus joints, so
+    the position half is zero; each foot's rows act on the base twist
+    (columns nx/2 .. nx/2 + 5, entries N(0, 1/4)) and on the joints of its own
+    leg (the joints split into n_feet consecutive blocks, entries N(0, 1)).
+    The Jacobian at the linearisation point, the same at every stage.  Own
+    stream per agent (extra key 3_000_000)."""
+    ids = batch.agent_ids if batch.agent_ids is not None else np.arange(batch.n_agents)
+    out = []
+    for s, aid in zip(batch.shapes, ids):
+        rng = agent_rng(seed, batch.stream_id, int(aid), 3_000_000)
+        half = s.nx // 2
+        nj = half - 6
+        J = np.zeros((s.n_feet * s.foot_dim, s.nx))
+        for f in range(s.n_feet):
+            rows = slice(f * s.foot_dim, (f + 1) * s.foot_dim)
+            J[rows, half:half + 6] = 0.5 * rng.standard_normal((s.foot_dim, 6))
+            j0, j1 = half + 6 + f * nj // s.n_feet, half + 6 + (f + 1) * nj // s.n_feet
+            J[rows, j0:j1] = rng.standard_normal((s.foot_dim, j1 - j0))
+        out.append(J.ravel())
+    dt = batch.A.dtype
+    if not out:
+        return np.zeros(0, dtype=dt)
+    return np.concatenate(out).astype(dt)
+
+
 def step_noise(batch: Batch, step: int, std: float = 1e-2) -> np.ndarray:
     """Per-step state disturbance, N(0, std^2), laid out like ``x0``."""
     ids = batch.agent_ids if batch.agent_ids is not None else np.arange(batch.n_agents)

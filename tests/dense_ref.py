@@ -444,3 +444,159 @@ def brute_force_qp_limits(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, x_lo
                 yx[k, i] = mm
         return x, u, y, yx
     return None
+
+
+def contact_table(s, stance, rho=0.1, rho_eq=100.0, rho_min=1e-6):
+    """Bounds and penalties [N, n_feet*foot_dim] of the no-slip rows of x_k,
+    k = 1..N (row k-1): equality rows J_f v_k = 0 for a foot in stance at stage
+    min(k, N-1), free rows for a swinging foot."""
+    nc = s.n_feet * s.foot_dim
+    l = np.full((s.N, nc), -np.inf)
+    h = np.full((s.N, nc), np.inf)
+    rr = np.full((s.N, nc), rho_min)
+    for k in range(1, s.N + 1):
+        phase = stance[min(k, s.N - 1)]
+        for f in range(s.n_feet):
+            if phase[f]:
+                sl = slice(f * s.foot_dim, (f + 1) * s.foot_dim)
+                l[k - 1, sl] = 0.0
+                h[k - 1, sl] = 0.0
+                rr[k - 1, sl] = rho_eq
+    return l, h, rr
+
+
+def dense_admm_state_rows(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, iters, *, x_lo=None,
+                          x_hi=None, J=None, rho=0.1, sigma=1e-6, alpha=1.6, rho_eq=100.0,
+                          rho_min=1e-6):
+    """dense_admm with state rows on x_1..x_N added to the splitting: the joint
+    limits (identity rows, x_lo/x_hi) and the no-slip rows (rows J, bounds of
+    contact_table), each block with its own (z, y), projection and dual update;
+    the x-subproblem gains rho/2 |Cx x_k - z + y/rho|^2 for each block."""
+    C = C_dense(s, mu)
+    l, h = bounds_table(s, tau_max, stance)
+    rr = rho_table(l, h, rho, rho_eq, rho_min)
+    G, b = dynamics_rows(s, A, B, c, x0)
+    N, nx = s.N, s.nx
+    blocks = []  # (Cx [rows, nx], lo [N, rows], hi [N, rows], rho [N, rows])
+    if x_lo is not None:
+        rx = state_rho(x_lo, x_hi, rho, rho_eq, rho_min)
+        blocks.append((np.eye(nx), np.tile(x_lo, (N, 1)), np.tile(x_hi, (N, 1)), np.tile(rx, (N, 1))))
+    if J is not None:
+        blocks.append((np.asarray(J, dtype=float),) + contact_table(s, stance, rho, rho_eq, rho_min))
+    m = C.shape[0]
+    u = np.zeros((N, s.nu))
+    z = np.zeros((N, m))
+    y = np.zeros((N, m))
+    zs = [np.zeros((N, Cx.shape[0])) for Cx, *_ in blocks]
+    ys = [np.zeros((N, Cx.shape[0])) for Cx, *_ in blocks]
+    x = rollout(s, A, B, c, x0, u)
+    for _ in range(iters):
+        H, g = x_subproblem(s, q, r, x_ref, C, rr, sigma, x, u, z, y)
+        for (Cx, lo, hi, rb), zb, yb in zip(blocks, zs, ys):
+            for k in range(1, N + 1):
+                sl = slice((k - 1) * nx, k * nx)
+                H[sl, sl] += Cx.T @ np.diag(rb[k - 1]) @ Cx
+                g[sl] += Cx.T @ (yb[k - 1] - rb[k - 1] * zb[k - 1])
+        v, _ = kkt_solve(H, g, G, b)
+        xt, ut = split(s, v, x0)
+        zeta = ut @ C.T
+        x = alpha * xt + (1 - alpha) * x
+        x[0] = x0
+        u = alpha * ut + (1 - alpha) * u
+        w = alpha * zeta + (1 - alpha) * z
+        zn = np.clip(w + y / rr, l, h)
+        y = y + rr * (w - zn)
+        z = zn
+        for bi, (Cx, lo, hi, rb) in enumerate(blocks):
+            wb = alpha * (xt[1:] @ Cx.T) + (1 - alpha) * zs[bi]
+            zbn = np.clip(wb + ys[bi] / rb, lo, hi)
+            ys[bi] = ys[bi] + rb * (wb - zbn)
+            zs[bi] = zbn
+    out = dict(x=x, u=u, z=z, y=y)
+    bi = 0
+    if x_lo is not None:
+        out.update(zx=zs[bi], yx=ys[bi])
+        bi += 1
+    if J is not None:
+        out.update(zc=zs[bi], yc=ys[bi])
+    return out
+
+
+def brute_force_qp_contacts(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, J, tol=1e-9):
+    """brute_force_qp with the no-slip rows of stance feet as equality
+    constraints on x_1..x_N (contact_table); only the input rows are
+    enumerated.  Returns (x, u, y, y_c) or None."""
+    C = C_dense(s, mu)
+    l, h = bounds_table(s, tau_max, stance)
+    lc, hc, _ = contact_table(s, stance)
+    G, b = dynamics_rows(s, A, B, c, x0)
+    N, nx, nu = s.N, s.nx, s.nu
+    J = np.asarray(J, dtype=float)
+    nc = J.shape[0]
+    nv = N * nx + N * nu
+    H = np.zeros((nv, nv))
+    g = np.zeros(nv)
+    for k in range(1, N + 1):
+        sl = slice((k - 1) * nx, k * nx)
+        H[sl, sl] = np.diag(q)
+        g[sl] = -q * x_ref[k]
+    H[N * nx:, N * nx:] = np.kron(np.eye(N), np.diag(r))
+    eq_rows, eq_tags = [], []
+    for k in range(1, N + 1):
+        for i in range(nc):
+            if lc[k - 1, i] == hc[k - 1, i]:
+                vec = np.zeros(nv)
+                vec[(k - 1) * nx:k * nx] = J[i]
+                eq_rows.append(vec)
+                eq_tags.append((k - 1, i))
+    rows = []
+    for k in range(N):
+        for i in range(C.shape[0]):
+            vec = np.zeros(nv)
+            vec[N * nx + k * nu:N * nx + (k + 1) * nu] = C[i]
+            rows.append((vec, l[k, i], h[k, i], (k, i)))
+    choices = []
+    for vec, lo, hi, _ in rows:
+        if lo == hi:
+            choices.append(("eq",))
+            continue
+        ch = ["free"]
+        if np.isfinite(lo):
+            ch.append("lo")
+        if np.isfinite(hi):
+            ch.append("hi")
+        choices.append(tuple(ch))
+    G2 = np.vstack([G] + ([np.array(eq_rows)] if eq_rows else []))
+    b2 = np.concatenate([b, np.zeros(len(eq_rows))])
+    for combo in itertools.product(*choices):
+        E, e, kinds, tags = [], [], [], []
+        for (vec, lo, hi, tag), kind in zip(rows, combo):
+            if kind == "free":
+                continue
+            E.append(vec)
+            e.append(lo if kind in ("lo", "eq") else hi)
+            kinds.append(kind)
+            tags.append(tag)
+        GG = np.vstack([G2] + ([np.array(E)] if E else []))
+        bb = np.concatenate([b2, np.array(e)])
+        try:
+            v, lam = kkt_solve(H, g, GG, bb)
+        except np.linalg.LinAlgError:
+            continue
+        mult = lam[G2.shape[0]:]
+        vals = np.array([vec @ v for vec, _, _, _ in rows])
+        los = np.array([lo for _, lo, _, _ in rows])
+        his = np.array([hi for _, _, hi, _ in rows])
+        if np.any(vals < los - tol) or np.any(vals > his + tol):
+            continue
+        if any((kd == "hi" and mm < -tol) or (kd == "lo" and mm > tol) for kd, mm in zip(kinds, mult)):
+            continue
+        x, u = split(s, v, x0)
+        y = np.zeros((N, C.shape[0]))
+        for (k, i), mm in zip(tags, mult):
+            y[k, i] = mm
+        yc = np.zeros((N, nc))
+        for (k, i), mm in zip(eq_tags, lam[G.shape[0]:G2.shape[0]]):
+            yc[k, i] = mm
+        return x, u, y, yc
+    return None

@@ -8,6 +8,7 @@ import tempfile
 import pytest
 
 import oracle
+import test_oracle_contacts as contacts
 import test_oracle_limits as limits
 import test_oracle_pins as pins
 
@@ -20,7 +21,8 @@ MUTANTS = [
     ("wrong sign of d", "for (int j = 0; j < nu; ++j) dk[j] = -hv[j];",
      "for (int j = 0; j < nu; ++j) dk[j] = hv[j];"),
     ("K' h dropped from p", "for (int t = 0; t < nu; ++t) acc += Kk[t * nx + i] * hv[t];", ""),
-    ("sigma sign in qt", "- sigma * x[(size_t)k * nx + i] +", "+ sigma * x[(size_t)k * nx + i] +"),
+    ("sigma sign in qt", "x_ref[(size_t)k * nx + i] - sigma * x[(size_t)k * nx + i];",
+     "x_ref[(size_t)k * nx + i] + sigma * x[(size_t)k * nx + i];"),
     ("dual update sign", "y[idx] = y[idx] + rho[idx] * (w - zn);", "y[idx] = y[idx] - rho[idx] * (w - zn);"),
     ("no relaxation of z", "const double w = alpha * zeta + (1.0 - alpha) * z[idx];",
      "const double w = zeta;"),
@@ -41,10 +43,11 @@ MUTANTS = [
     ("complementarity against the wrong bound", "const double a = isinf(hi) ? yp : fmin(yp, hi - zz);",
      "const double a = isinf(lo) ? yp : fmin(yp, zz - lo);"),
     ("state penalty missing from P_N",
-     "Pn[i * nx + j] = (i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0;",
-     "Pn[i * nx + j] = (i == j) ? q[i] + st->sigma : 0.0;"),
+     "Pn[i * nx + j] = ((i == j) ? q[i] + st->sigma + (qx ? qx[i] : 0.0) : 0.0) +",
+     "Pn[i * nx + j] = ((i == j) ? q[i] + st->sigma : 0.0) +"),
     ("state rows' linear term with the wrong sign",
-     "((x_lo && k >= 1) ? yx[(size_t)(k - 1) * nx + i] -", "((x_lo && k >= 1) ? -yx[(size_t)(k - 1) * nx + i] -"),
+     "if (x_lo && k >= 1) acc += yx[(size_t)(k - 1) * nx + i] -",
+     "if (x_lo && k >= 1) acc += -yx[(size_t)(k - 1) * nx + i] -"),
     ("state rows projected on the wrong stage",
      "const double w = alpha * xt[(size_t)k * nx + i] + (1.0 - alpha) * zx[idx];",
      "const double w = alpha * xt[(size_t)(k - 1) * nx + i] + (1.0 - alpha) * zx[idx];"),
@@ -53,6 +56,20 @@ MUTANTS = [
      "rp = maxabs(x[(size_t)(k + 1) * nx + i] - zx[idx], rp);", ""),
     ("equality state rows with the inequality penalty", "      rho_x[i] = st->rho_eq_scale * st->rho;",
      "      rho_x[i] = st->rho;"),
+    ("no-slip weight dropped from P_k", "                     (Qadd ? Qadd[((size_t)k * nx + i) * nx + j] : 0.0);",
+     "                     0.0;"),
+    ("no-slip rows with the stance of the previous stage",
+     "const int sk = k < s->N ? k : s->N - 1;", "const int sk = k - 1;"),
+    ("no-slip weight with a repeated index",
+     "acc += Jc[row * nx + i] * rho_c[(size_t)(k - 1) * nc + row] * Jc[row * nx + j];",
+     "acc += Jc[row * nx + i] * rho_c[(size_t)(k - 1) * nc + row] * Jc[row * nx + i];"),
+    ("no-slip linear term with the wrong sign", "acc += Jc[row * nx + i] * (yc[idx] - rho_c[idx] * zc[idx]);",
+     "acc += Jc[row * nx + i] * (yc[idx] + rho_c[idx] * zc[idx]);"),
+    ("no-slip rows projected from the relaxed state",
+     "zeta += Jc[row * nx + t] * xt[(size_t)k * nx + t];", "zeta += Jc[row * nx + t] * x[(size_t)k * nx + t];"),
+    ("no-slip multipliers left out of the costates",
+     "        for (int row = 0; row < nc; ++row) acc += Jc[row * nx + i] * yc[(size_t)(k - 1) * nc + row];\n", ""),
+    ("no-slip rows left out of the primal residual", "rp = maxabs(acc - zc[idx], rp);", ""),
 ]
 
 CHECKS = [
@@ -68,6 +85,10 @@ CHECKS = [
     lambda: limits.test_xupdate_with_state_rows_equals_dense_kkt(limits.synth.quadruped(3), 2),
     lambda: limits.test_fixed_iterates_with_limits_equal_dense_admm(limits.synth.quadruped(3), 5, 6),
     lambda: limits.test_residuals_with_state_multipliers(),
+    lambda: contacts.test_row_table_and_state_weight(contacts.TINY),
+    lambda: contacts.test_xupdate_with_contact_rows_equals_dense_kkt(contacts.synth.quadruped(3), 2),
+    lambda: contacts.test_fixed_iterates_with_contacts_equal_dense_admm(contacts.synth.quadruped(3), 5, 6, False),
+    lambda: contacts.test_residuals_with_contact_multipliers(),
 ]
 
 

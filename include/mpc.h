@@ -120,6 +120,10 @@ typedef struct {
   int32_t joint_limits;     /* 1: every solve carries joint limits x_lo <= x_k <= x_hi  */
                             /* (Eq. (mpc_formulation)); the agents then run the generic */
                             /* kernels, FP64 or FP32 only, without scaling (default 0)  */
+  int32_t no_slip;          /* 1: every solve carries the no-slip rows J_f v_k = 0 of   */
+                            /* the feet in stance (Eq. (mpc_formulation)) on x_1..x_N,  */
+                            /* stance of stage min(k, N-1); generic kernels, FP64 or    */
+                            /* FP32 only, without scaling (default 0)                   */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */
@@ -147,6 +151,11 @@ typedef struct {
    * per agent (io type; +-infinity where a component has no limit); required by
    * plans with joint_limits = 1, NULL otherwise */
   const void *x_lo, *x_hi;
+  /* no-slip rows of Eq. (mpc_formulation): per agent the foot velocity Jacobian
+   * rows [n_feet * foot_dim][nx] over the whole state (row-major, io type; the
+   * rows of foot f are rows f*foot_dim .. f*foot_dim + foot_dim - 1), the same
+   * at every stage; required by plans with no_slip = 1, NULL otherwise */
+  const void* J_foot;
 } mpc_problem_batch;
 
 /* Alg. 1 for every agent, from the KKT data (f_KKT) to the end of the QP
@@ -171,6 +180,9 @@ typedef struct {
   void *zx, *yx;                        /* joint-limit rows' (z_x, y_x) [N][nx],  */
                                         /* io type (plans with joint limits);    */
                                         /* may be NULL                           */
+  void *zc, *yc;                        /* no-slip rows' (z_c, y_c) [N][n_feet*   */
+                                        /* foot_dim], io type (plans with no-slip */
+                                        /* rows); may be NULL                    */
 } mpc_solution;
 
 /* The QP solution Alg. 1 returns after its fixed iteration count; u_0 is
@@ -191,6 +203,11 @@ mpc_status mpc_set_warm_state(mpc_plan_t plan, const void* u, const void* z, con
  * z_x, y_x [N][nx] per agent (io type, device), e.g. to resume a controller
  * together with mpc_set_warm_state. */
 mpc_status mpc_set_warm_limits(mpc_plan_t plan, const void* zx, const void* yx, void* stream);
+
+/* The no-slip rows' part of the warm start (plans with no-slip rows, the
+ * stance constraint of Eq. (mpc_formulation)): z_c, y_c [N][n_feet*foot_dim]
+ * per agent (io type, device).  INVALID_ARG for a plan without the rows. */
+mpc_status mpc_set_warm_contacts(mpc_plan_t plan, const void* zc, const void* yc, void* stream);
 
 /* The system step x_{i+1} = f(x_i, u_i) of Eq. (OCP), linearised as the QP's
  * first stage, driving a closed loop of control steps.
@@ -310,7 +327,7 @@ typedef struct mpc_server_s* mpc_server_t;
 typedef struct {
   mpc_plan_desc solver;      /* precision, admm_iters, constants, refinement, device;   */
                              /* n_agents, shapes and kernel are ignored; scaling_iters,  */
-                             /* rho_interval and joint_limits must be 0                  */
+                             /* rho_interval, joint_limits and no_slip must be 0         */
   int64_t hbm_budget_bytes;  /* device memory of the server (default 1 GiB)             */
   int32_t max_batch;         /* requests per batch (default 4096)                       */
   int32_t max_inflight;      /* batches on the device at once, 1..8 (default 3)        */
@@ -394,7 +411,7 @@ mpc_status mpc_server_get_stats(mpc_server_t server, mpc_server_stats* out);
  * (36, 24), N <= 20), MPC_FP32 only, and no plan: desc gives n_agents,
  * shapes (host array, every entry equal), admm_iters and the solver
  * constants (precision must be MPC_FP32; kernel, refinement fields ignored;
- * scaling_iters, rho_interval and joint_limits must be 0).
+ * scaling_iters, rho_interval, joint_limits and no_slip must be 0).
  * The per-agent descriptors, the launch list and the Riccati operators live
  * in a device array of MPC_NOALLOC_SCRATCH_BYTES that the library holds on
  * every device it runs on until the process ends (about 500 humanoid agents

@@ -90,6 +90,7 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
       const T lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
       ok &= !isnan(lo) && !isnan(hi) && lo <= hi;
     }
+  if (in.J) ok &= finite_all(in.J + d.oJ, (int64_t)d.n_feet * d.foot_dim * nx, tid, nt);
   if (!ok) atomicOr(&s_flag, 1);
   __syncthreads();
   if (s_flag) {
@@ -108,7 +109,8 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
   }
   for (int idx = tid; idx < nx * nx; idx += nt) {
     const int i = idx / nx, j = idx % nx;
-    P[idx] = (i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0;
+    P[idx] = ((i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0) +
+             contact_weight<D>(in, d, N, i, j, sc);
   }
   __syncthreads();
 
@@ -222,7 +224,9 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
     for (int idx = tid; idx < nx * nx; idx += nt) {
       const int i = idx / nx, j = idx % nx;
       if (j >= i) {
-        D a1 = (i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0, a2 = a1;
+        D a1 = ((i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0) +
+               contact_weight<D>(in, d, k, i, j, sc),
+          a2 = a1;
         for (int t = 0; t < nx; ++t) {
           a1 += Ak[t * nx + i] * PA[t * nx + j];
           a2 += Ak[t * nx + j] * PA[t * nx + i];
@@ -368,6 +372,11 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         st.zx[d.oc + i] = nan;
         st.yx[d.oc + i] = nan;
       }
+    if (st.zc)
+      for (int i = tid; i < N * d.n_feet * d.foot_dim; i += nt) {
+        st.zc[d.ozc + i] = nan;
+        st.yc[d.ozc + i] = nan;
+      }
     return;
   }
   // Operators are read in the io type T; every vector, every accumulation and
@@ -395,6 +404,13 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
   const bool lim = in.xlo != nullptr;
   V* zx = red + 256;                      // N*nx
   V* yx = zx + N * nx;                    // N*nx
+  // no-slip rows (with them): z_c, y_c of x_1..x_N and w_c = y_c - rho_c z_c
+  const bool ctc = in.J != nullptr;
+  const int nc = ctc ? d.n_feet * d.foot_dim : 0;
+  V* zc = zx + (lim ? 2 * N * nx : 0);    // N*nc
+  V* yc = zc + N * nc;                    // N*nc
+  V* wc = yc + N * nc;                    // N*nc
+  const T* Jc = ctc ? in.J + d.oJ : nullptr;
 
   const T* A = in.A + d.oA;
   const T* B = in.B + d.oB;
@@ -426,6 +442,10 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       zx[i] = wm ? (V)st.zx[d.oc + i] : 0.0;
       yx[i] = wm ? (V)st.yx[d.oc + i] : 0.0;
     }
+  for (int i = tid; i < N * nc; i += nt) {
+    zc[i] = wm ? (V)st.zc[d.ozc + i] : 0.0;
+    yc[i] = wm ? (V)st.yc[d.ozc + i] : 0.0;
+  }
   for (int i = tid; i < nx; i += nt) {
     x[i] = (V)x0[i];
     xt[i] = (V)x0[i];
@@ -468,6 +488,12 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       if (uref) acc -= (V)r[j] * (V)uref[idx];
       rt[idx] = acc;
     }
+    // w_c = y_c - rho_c z_c of the no-slip rows of x_1..x_N
+    for (int idx = tid; idx < N * nc; idx += nt) {
+      double rr;
+      contact_row(d, stance, idx / nc + 1, idx % nc, sc, rr);
+      wc[idx] = yc[idx] - (V)rr * zc[idx];
+    }
     __syncthreads();
     // g_k = qt_k + K_k' rt_k, qt_k = -Q r_k - sigma x_k
     quad_dot<V>(N * nx, nu,
@@ -480,12 +506,15 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
                   V qt = -(V)q[i] * (V)xr[(int64_t)k * nx + i] - sigma * x[idx];
                   if (lim && k >= 1)  // the state rows of x_k: y_x - rho_x z_x
                     qt += yx[idx - nx] - state_rho<V>(in, d, i, sc) * zx[idx - nx];
+                  if (k >= 1)  // the no-slip rows of x_k: Jc' w_c,k
+                    for (int row = 0; row < nc; ++row) qt += (V)Jc[row * nx + i] * wc[(k - 1) * nc + row];
                   g[idx] = qt + acc;
                 },
                 tid, nt);
     for (int i = tid; i < nx; i += nt) {
       V qt = -(V)q[i] * (V)xr[(int64_t)N * nx + i] - sigma * x[N * nx + i];
       if (lim) qt += yx[(N - 1) * nx + i] - state_rho<V>(in, d, i, sc) * zx[(N - 1) * nx + i];
+      for (int row = 0; row < nc; ++row) qt += (V)Jc[row * nx + i] * wc[(N - 1) * nc + row];
       p[i] = qt;
     }
     __syncthreads();
@@ -642,6 +671,20 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         yx[idx] = yx[idx] + rr * (w - zn);
         zx[idx] = zn;
       }
+    // the no-slip rows take Jc xt_k (k = 1..N): equality rows project to 0,
+    // free rows keep w + y_c / rho_c
+    if (ctc)
+      quad_dot<V>(N * nc, nx,
+                  [&](int idx, int t) { return (V)Jc[(idx % nc) * nx + t] * xt[(idx / nc + 1) * nx + t]; },
+                  [&](int idx, V zeta) {
+                    double rr;
+                    const bool eq = contact_row(d, stance, idx / nc + 1, idx % nc, sc, rr);
+                    const V w = alpha * zeta + oma * zc[idx];
+                    const V zn = eq ? (V)0 : w + yc[idx] / (V)rr;
+                    yc[idx] = yc[idx] + (V)rr * (w - zn);
+                    zc[idx] = zn;
+                  },
+                  tid, nt);
     for (int idx = nx + tid; idx < (N + 1) * nx; idx += nt) x[idx] = alpha * xt[idx] + oma * x[idx];
     for (int idx = tid; idx < N * m; idx += nt) {
       const int k = idx / m, i = idx % m;
@@ -678,6 +721,11 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
       st.yx[d.oc + i] = (T)yx[i];
       ok &= (bool)isfinite(zx[i]) && (bool)isfinite(yx[i]);
     }
+  for (int i = tid; i < N * nc; i += nt) {
+    st.zc[d.ozc + i] = (T)zc[i];
+    st.yc[d.ozc + i] = (T)yc[i];
+    ok &= (bool)isfinite(zc[i]) && (bool)isfinite(yc[i]);
+  }
   if (!ok) st.status[a] = AGENT_NONFINITE;
 }
 
@@ -827,6 +875,14 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
           if (zz > hi) rc = fmax(rc, zz - hi);
           if (zz < lo) rc = fmax(rc, lo - zz);
         }
+        if (in.J && idx >= nx) {  // no-slip rows of x_k: Jc' y_c,k joins the costate
+          const int i = idx % nx, k = idx / nx, ncr = d.n_feet * d.foot_dim;
+          const T* Jc = in.J + d.oJ;
+          const T* yck = st.yc + d.ozc + (int64_t)(k - 1) * ncr;
+          double acc = 0.0;
+          for (int row = 0; row < ncr; ++row) acc += (double)Jc[row * nx + i] * (double)yck[row];
+          lam[idx] += acc;
+        }
       }
       if (idx < nU) {
         const double uv = (double)u[idx];
@@ -855,6 +911,24 @@ k_residual(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list,
         rc = fmax(rc, fmax(fabs(ca), fabs(cb)));
         if (zz > hi) rc = fmax(rc, zz - hi);
         if (zz < lo) rc = fmax(rc, lo - zz);
+      }
+    }
+    // no-slip rows of x_1..x_N: primal |Jc x_k - z_c| and complementarity
+    // (equality rows: z_c = 0; free rows: y_c = 0)
+    if (in.J) {
+      const int ncr = d.n_feet * d.foot_dim;
+      const T* Jc = in.J + d.oJ;
+      for (int idx = tid; idx < N * ncr; idx += nt) {
+        const int k = idx / ncr + 1, row = idx % ncr;
+        double jx = 0.0;
+        for (int t = 0; t < nx; ++t) jx += (double)Jc[row * nx + t] * (double)x[k * nx + t];
+        const double zz = (double)st.zc[d.ozc + idx], yy = (double)st.yc[d.ozc + idx];
+        rp = fmax(rp, fabs(jx - zz));
+        double rr;
+        if (contact_row(d, stance, k, row, sc, rr))
+          rc = fmax(rc, fabs(zz));
+        else
+          rc = fmax(rc, fabs(yy));
       }
     }
   }

@@ -16,6 +16,9 @@ struct AgentDesc {
   int64_t ox, ou, oz, oy;
   int64_t ows;  // generic-kernel factor workspace (elements of the io type)
   int64_t ofw;  // register-resident workspace (floats), -1 if the agent has none
+  // no-slip rows (plans with them): Jacobian rows [n_feet*foot_dim][nx] and
+  // the rows' (z_c, y_c) [N][n_feet*foot_dim]
+  int64_t oJ = 0, ozc = 0;
 };
 
 struct SolverConsts {
@@ -39,6 +42,9 @@ struct Inputs {
   // null: no state rows
   const T* xlo = nullptr;
   const T* xhi = nullptr;
+  // no-slip rows J_f v_k = 0 of feet in stance (k = 1..N): the rows
+  // [n_feet*foot_dim][nx] per agent at the oJ offset; null: none
+  const T* J = nullptr;
 };
 
 template <typename T>
@@ -50,6 +56,9 @@ struct State {
   // the joint-limit rows' (z_x, y_x), [N][nx] per agent at the c offset (with limits)
   T* zx = nullptr;
   T* yx = nullptr;
+  // the no-slip rows' (z_c, y_c), [N][n_feet*foot_dim] per agent at the ozc offset
+  T* zc = nullptr;
+  T* yc = nullptr;
 };
 
 enum : int32_t { AGENT_OK = 0, AGENT_CONVERGED = 1, AGENT_NOT_PD = 2, AGENT_NONFINITE = 3 };
@@ -70,12 +79,14 @@ inline size_t generic_factor_lds(int nx, int nu, size_t esz) {
   (void)esz;  // the recursion runs in double whatever the io type
   return 8 * (size_t)(nu * nu + 3 * nx * nx + 3 * nx * nu + nu + 64);
 }
-inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz, bool limits = false) {
+inline size_t generic_admm_lds(int N, int nx, int nu, int m, size_t esz, bool limits = false,
+                               int nc = 0) {
   (void)esz;  // vectors are held in double whatever the io type
   // + 256 doubles of reduction scratch for the refinement's stopping test
-  // (+ the joint-limit rows' z_x, y_x)
+  // (+ the joint-limit rows' z_x, y_x; + the no-slip rows' z_c, y_c and
+  // y_c - rho_c z_c)
   return 8 * (size_t)(2 * (N + 1) * nx + 4 * N * nu + 2 * N * m + 3 * N * nx + nx + N * nu + 256 +
-                      (limits ? 2 * N * nx : 0));
+                      (limits ? 2 * N * nx : 0) + 3 * N * nc);
 }
 // Residual kernel: costates and x ((N+1) x nx each) and u (N x nu) in double,
 // then stage k's A_k and B_k staged in the io type with rows padded by one

@@ -114,6 +114,10 @@ struct mpc_plan_s {
   bool limits = false;
   void *d_zx = nullptr, *d_yx = nullptr;  // [sum N nx]: the state rows' (z_x, y_x)
   int64_t nZX = 0;
+  // no-slip rows
+  bool contacts = false;
+  void *d_zc = nullptr, *d_yc = nullptr;  // [sum N n_feet foot_dim]: the rows' (z_c, y_c)
+  int64_t nZC = 0, maxnc = 0;
   int n_seg = 1;
   bool solved = false;
   size_t lds_factor = 0, lds_admm = 0, lds_res = 0;
@@ -171,6 +175,7 @@ extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
   d->rho_interval = 0;
   d->rho_tolerance = 5.0;
   d->joint_limits = 0;
+  d->no_slip = 0;
 }
 
 extern "C" const char* mpc_last_error(void) { return mpc::g_err.c_str(); }
@@ -202,6 +207,8 @@ static void free_plan(mpc_plan_s* p) {
   hipFree(p->d_rho_hist);
   hipFree(p->d_zx);
   hipFree(p->d_yx);
+  hipFree(p->d_zc);
+  hipFree(p->d_yc);
   for (auto e : p->ev_pool) hipEventDestroy(e);
   for (auto& pe : p->pending) {
     hipEventDestroy(pe.second.first);
@@ -236,6 +243,12 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
        desc->scaling_iters > 0 || desc->kernel == 2))
     return fail(MPC_ERR_INVALID_ARG,
                 "joint limits run on the generic kernels in FP64 or FP32, without scaling");
+  if (desc->no_slip != 0 && desc->no_slip != 1) return fail(MPC_ERR_INVALID_ARG, "no_slip must be 0 or 1");
+  if (desc->no_slip &&
+      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
+       desc->scaling_iters > 0 || desc->kernel == 2))
+    return fail(MPC_ERR_INVALID_ARG,
+                "no-slip rows run on the generic kernels in FP64 or FP32, without scaling");
   for (int a = 0; a < desc->n_agents; ++a) {
     mpc_status vs = validate_shape(desc->shapes[a], a);
     if (vs != MPC_OK) return vs;
@@ -252,11 +265,12 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->fp64 = desc->precision == MPC_FP64;
   p->esz = p->fp64 ? 8 : 4;
   p->limits = desc->joint_limits != 0;
+  p->contacts = desc->no_slip != 0;
 
   p->hdesc.resize(p->n);
   AgentDesc cur{};
   int64_t oA = 0, oB = 0, oc = 0, oq = 0, orr = 0, oxr = 0, ox0 = 0, otau = 0, ost = 0, ox = 0,
-          ou = 0, oz = 0, ows = 0;
+          ou = 0, oz = 0, ows = 0, oJ = 0, ozc = 0;
   for (int a = 0; a < p->n; ++a) {
     const mpc_shape& s = p->shapes[a];
     cur.N = s.N;
@@ -274,7 +288,12 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     cur.omu = a;
     cur.our = ou;
     cur.flags = 0;
+    cur.oJ = oJ;
+    cur.ozc = ozc;
     p->hdesc[a] = cur;
+    oJ += (int64_t)s.n_feet * s.foot_dim * s.nx;
+    ozc += (int64_t)s.N * s.n_feet * s.foot_dim;
+    p->maxnc = std::max<int64_t>(p->maxnc, (int64_t)s.n_feet * s.foot_dim);
     oA += (int64_t)s.N * s.nx * s.nx;
     oB += (int64_t)s.N * s.nx * s.nu;
     oc += (int64_t)s.N * s.nx;
@@ -298,7 +317,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->nZ = oz;
   p->nWS = ows;
   p->lds_factor = generic_factor_lds(p->maxnx, p->maxnu, p->esz);
-  p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz, p->limits);
+  p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz, p->limits,
+                                 p->contacts ? (int)p->maxnc : 0);
   p->lds_res = generic_residual_lds(p->maxN, p->maxnx, p->maxnu, p->esz);
 
   // Launch groups.  FP32 agents whose shape has a register-resident
@@ -310,7 +330,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
     for (int a = 0; a < p->n; ++a) {
       const mpc_shape& s = p->shapes[a];
-      const bool fok = desc->precision == MPC_FP32 && !p->limits &&
+      const bool fok = desc->precision == MPC_FP32 && !p->limits && !p->contacts &&
                        fused_supported(s.N, s.nx, s.nu, s.n_feet);
       if (desc->kernel == 2 && !fok) {
         delete p;
@@ -345,7 +365,8 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       g.list_off = (int64_t)p->hlist.size();
       const int m = s0.nu + 4 * s0.n_feet;
       g.lds_factor = generic_factor_lds(s0.nx, s0.nu, p->esz);
-      g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz, p->limits);
+      g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz, p->limits,
+                                    p->contacts ? s0.n_feet * s0.foot_dim : 0);
       if (g.fused_ok) fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
       for (int32_t a : ag) g.work += (double)p->shapes[a].N * (s0.nx + s0.nu) * (s0.nx + s0.nu);
       g.est = g.work;
@@ -437,6 +458,11 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       if (se == hipSuccess) se = alloc(&p->d_zx, p->esz * (size_t)p->nZX);
       if (se == hipSuccess) se = alloc(&p->d_yx, p->esz * (size_t)p->nZX);
     }
+    if (p->contacts) {
+      p->nZC = ozc;
+      if (se == hipSuccess) se = alloc(&p->d_zc, p->esz * (size_t)std::max<int64_t>(p->nZC, 1));
+      if (se == hipSuccess) se = alloc(&p->d_yc, p->esz * (size_t)std::max<int64_t>(p->nZC, 1));
+    }
     if (se != hipSuccess) {
       mpc_status st = fail(se == hipErrorOutOfMemory ? MPC_ERR_OUT_OF_MEMORY : MPC_ERR_HIP,
                            std::string("hipMalloc: ") + hipGetErrorString(se));
@@ -499,6 +525,10 @@ static mpc_status check_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
     return fail(MPC_ERR_INVALID_ARG,
                 p->limits ? "this plan solves with joint limits: x_lo and x_hi are required"
                           : "x_lo / x_hi given to a plan created without joint limits");
+  if (p->contacts != (b->J_foot != nullptr))
+    return fail(MPC_ERR_INVALID_ARG,
+                p->contacts ? "this plan solves with no-slip rows: J_foot is required"
+                            : "J_foot given to a plan created without no-slip rows");
   return MPC_OK;
 }
 
@@ -539,6 +569,7 @@ static Inputs<T> make_inputs(const mpc_problem_batch* b) {
   in.uref = (const T*)b->u_ref;
   in.xlo = (const T*)b->x_lo;
   in.xhi = (const T*)b->x_hi;
+  in.J = (const T*)b->J_foot;
   return in;
 }
 
@@ -554,6 +585,8 @@ static State<T> make_state(mpc_plan_s* p) {
   s.status = p->d_status;
   s.zx = (T*)p->d_zx;
   s.yx = (T*)p->d_yx;
+  s.zc = (T*)p->d_zc;
+  s.yc = (T*)p->d_yc;
   return s;
 }
 
@@ -630,7 +663,8 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
       PhaseTimer t(p, 0, s);
       // FP32 plans of the shapes the matrix-core factor is built for take it
       // (FP64 products, generic operator layout) at any horizon
-      if (!p->fp64 && mixed_supported(g.nx, g.nu))
+      // (the no-slip rows' dense state weight is added by the generic factor only)
+      if (!p->fp64 && !p->contacts && mixed_supported(g.nx, g.nu))
         HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu, 0, make_inputs<float>(b),
                                     sc, (float*)p->d_ws, p->d_status, s));
       else
@@ -739,6 +773,10 @@ extern "C" mpc_status mpc_get_solution(mpc_plan_t p, const mpc_solution* o, void
   if (o->status) HIP_TRY(hipMemcpyAsync(o->status, p->d_status, sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, s));
   if (p->limits && o->zx) HIP_TRY(hipMemcpyAsync(o->zx, p->d_zx, e * p->nZX, hipMemcpyDeviceToDevice, s));
   if (p->limits && o->yx) HIP_TRY(hipMemcpyAsync(o->yx, p->d_yx, e * p->nZX, hipMemcpyDeviceToDevice, s));
+  if (p->contacts && p->nZC > 0 && o->zc)
+    HIP_TRY(hipMemcpyAsync(o->zc, p->d_zc, e * p->nZC, hipMemcpyDeviceToDevice, s));
+  if (p->contacts && p->nZC > 0 && o->yc)
+    HIP_TRY(hipMemcpyAsync(o->yc, p->d_yc, e * p->nZC, hipMemcpyDeviceToDevice, s));
   if (o->u0) {
     // u0 of agent a is the first nu entries of its u block: a strided copy
     // when every block has one size, else one gather kernel.
@@ -778,6 +816,19 @@ extern "C" mpc_status mpc_set_warm_limits(mpc_plan_t p, const void* zx, const vo
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipMemcpyAsync(p->d_zx, zx, p->esz * p->nZX, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(p->d_yx, yx, p->esz * p->nZX, hipMemcpyDeviceToDevice, s));
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_set_warm_contacts(mpc_plan_t p, const void* zc, const void* yc,
+                                            void* stream) {
+  if (!p || !zc || !yc) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!p->contacts) return fail(MPC_ERR_INVALID_ARG, "this plan has no no-slip rows");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  if (p->nZC > 0) {
+    HIP_TRY(hipMemcpyAsync(p->d_zc, zc, p->esz * p->nZC, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->d_yc, yc, p->esz * p->nZC, hipMemcpyDeviceToDevice, s));
+  }
   return MPC_OK;
 }
 

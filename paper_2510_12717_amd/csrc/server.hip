@@ -222,9 +222,9 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
     return api_fail(MPC_ERR_INVALID_ARG, "solver constants out of range");
   if (sd.max_refine_sweeps < 0 || sd.max_refine_sweeps > 16 || !(sd.refine_tol >= 0))
     return api_fail(MPC_ERR_INVALID_ARG, "refinement settings out of range");
-  if (sd.scaling_iters != 0 || sd.rho_interval != 0 || sd.joint_limits != 0)
+  if (sd.scaling_iters != 0 || sd.rho_interval != 0 || sd.joint_limits != 0 || sd.no_slip != 0)
     return api_fail(MPC_ERR_INVALID_ARG,
-                    "the served loop runs without scaling or joint limits and with a fixed rho");
+                    "the served loop runs without scaling, joint limits or no-slip rows and with a fixed rho");
   if (desc->max_batch < 1 || desc->max_batch > (1 << 20) || desc->max_inflight < 1 ||
       desc->max_inflight > 8)
     return api_fail(MPC_ERR_INVALID_ARG, "max_batch must be in 1..2^20 and max_inflight in 1..8");
@@ -361,8 +361,9 @@ static mpc_status submit_one(mpc_server_s* s, int64_t ctrl, const mpc_shape* sha
       !prob->x0 || !prob->mu || (sh.n_tau > 0 && !prob->tau_max) || (sh.n_feet > 0 && !prob->stance))
     return api_fail(MPC_ERR_INVALID_ARG, "null input pointer in request");
   if (prob->u_ref) return api_fail(MPC_ERR_INVALID_ARG, "requests take no input reference (u_ref must be NULL)");
-  if (prob->x_lo || prob->x_hi)
-    return api_fail(MPC_ERR_INVALID_ARG, "the served loop runs without joint limits (x_lo, x_hi must be NULL)");
+  if (prob->x_lo || prob->x_hi || prob->J_foot)
+    return api_fail(MPC_ERR_INVALID_ARG,
+                    "the served loop runs without joint limits or no-slip rows (x_lo, x_hi, J_foot must be NULL)");
   if (!known) {
     const int m = ctrl_m(sh);
     if ((int64_t)generic_admm_lds(sh.N, sh.nx, sh.nu, m, s->esz) > s->lds_max ||

@@ -68,6 +68,36 @@ __device__ inline T state_rho(const Inputs<TT>& in, const AgentDesc& d, int i, c
   return (T)sc.rho;
 }
 
+// No-slip row `row` (foot row / foot_dim) of state x_k, k = 1..N: an equality
+// J_f v_k = 0 while the foot is in stance at stage min(k, N-1) (penalty
+// rho_eq_scale * rho), a free row while it swings (rho_min).  Returns whether
+// the row is an equality; rho receives its penalty.
+__device__ inline bool contact_row(const AgentDesc& d, const uint8_t* stance, int k, int row,
+                                   const SolverConsts& sc, double& rho) {
+  const int sk = k < d.N ? k : d.N - 1;
+  const bool eq = stance[sk * d.n_feet + row / d.foot_dim] != 0;
+  rho = eq ? sc.rho_eq * sc.rho : sc.rho_min;
+  return eq;
+}
+
+// Entry (i, j) of Jc' diag(rho_c,k) Jc, the no-slip rows' term in the state
+// weight of stage k (0 without the rows or at k = 0).
+template <typename T, typename TT>
+__device__ inline T contact_weight(const Inputs<TT>& in, const AgentDesc& d, int k, int i, int j,
+                                   const SolverConsts& sc) {
+  if (!in.J || k == 0) return (T)0;
+  const TT* Jc = in.J + d.oJ;
+  const uint8_t* stance = in.st + d.ost;
+  const int nc = d.n_feet * d.foot_dim;
+  T acc = 0;
+  for (int row = 0; row < nc; ++row) {
+    double rr;
+    contact_row(d, stance, k, row, sc, rr);
+    acc += (T)Jc[row * d.nx + i] * (T)rr * (T)Jc[row * d.nx + j];
+  }
+  return acc;
+}
+
 // Diagonal of R + sigma I + C' diag(rho) C for input j (rho = this stage's row penalties).
 template <typename T, typename R>
 __device__ inline T rtilde_diag(const AgentDesc& d, int j, T rj, T mu, const R* rho,

@@ -39,13 +39,15 @@ class PlanDesc(ctypes.Structure):
                 ("max_refine_sweeps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("device", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("scaling_iters", ctypes.c_int32), ("rho_interval", ctypes.c_int32),
-                ("rho_tolerance", ctypes.c_double), ("joint_limits", ctypes.c_int32)]
+                ("rho_tolerance", ctypes.c_double), ("joint_limits", ctypes.c_int32),
+                ("no_slip", ctypes.c_int32)]
 
 
 class ProblemBatch(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("A", "B", "c", "q_diag", "r_diag", "x_ref", "x0",
                                                "tau_max", "mu", "stance", "u_ref")] + \
-               [("warm_start", ctypes.c_int32), ("x_lo", ctypes.c_void_p), ("x_hi", ctypes.c_void_p)]
+               [("warm_start", ctypes.c_int32), ("x_lo", ctypes.c_void_p), ("x_hi", ctypes.c_void_p),
+                ("J_foot", ctypes.c_void_p)]
 
 
 class GroupInfo(ctypes.Structure):
@@ -67,13 +69,13 @@ class ServerStats(ctypes.Structure):
 
 class Solution(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "x", "u", "z", "y", "objective",
-                                               "residuals", "status", "zx", "yx")]
+                                               "residuals", "status", "zx", "yx", "zc", "yc")]
 
 
 # every symbol the header declares
 EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_solve",
-           "mpc_get_solution", "mpc_set_warm_state", "mpc_set_warm_limits", "mpc_advance_state",
-           "mpc_plan_set_timing",
+           "mpc_get_solution", "mpc_set_warm_state", "mpc_set_warm_limits", "mpc_set_warm_contacts",
+           "mpc_advance_state", "mpc_plan_set_timing",
            "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
            "mpc_plan_get_rho", "mpc_plan_get_scaling", "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture", "mpc_plan_replay",
            "mpc_server_desc_default", "mpc_server_create", "mpc_server_destroy",
@@ -101,6 +103,7 @@ def lib():
         L.mpc_get_solution.argtypes = [V, P(Solution), V]
         L.mpc_set_warm_state.argtypes = [V, V, V, V, V]
         L.mpc_set_warm_limits.argtypes = [V, V, V, V]
+        L.mpc_set_warm_contacts.argtypes = [V, V, V, V]
         L.mpc_advance_state.argtypes = [V, P(ProblemBatch), V, V, V]
         L.mpc_plan_set_timing.argtypes = [V, I32]
         L.mpc_plan_get_timing.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -133,7 +136,8 @@ def lib():
                   "mpc_server_get_state", "mpc_server_get_stats"):
             getattr(L, f).restype = ctypes.c_int
         for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
-                  "mpc_set_warm_state", "mpc_set_warm_limits", "mpc_advance_state",
+                  "mpc_set_warm_state", "mpc_set_warm_limits", "mpc_set_warm_contacts",
+                  "mpc_advance_state",
                   "mpc_plan_set_timing",
                   "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
                   "mpc_plan_get_rho", "mpc_plan_get_scaling",
@@ -203,8 +207,10 @@ class Plan:
         self.dtype = "fp64" if precision == "fp64" else "fp32"  # io type
         m = [s.nu + 4 * s.n_feet for s in self.shapes]
         self.limits = bool(consts.get("joint_limits", 0))
+        self.contacts = bool(consts.get("no_slip", 0))
         self.sizes = dict(x=sum((s.N + 1) * s.nx for s in self.shapes),
                           zx=sum(s.N * s.nx for s in self.shapes),
+                          zc=sum(s.N * s.n_feet * s.foot_dim for s in self.shapes),
                           u=sum(s.N * s.nu for s in self.shapes),
                           z=sum(s.N * mm for s, mm in zip(self.shapes, m)),
                           u0=sum(s.nu for s in self.shapes))
@@ -228,6 +234,7 @@ class Plan:
         b.tau_max, b.mu, b.stance = _ptr(prob["tau_max"]), _ptr(prob["mu"]), _ptr(prob["stance"])
         b.u_ref = _ptr(prob.get("u_ref"))
         b.x_lo, b.x_hi = _ptr(prob.get("x_lo")), _ptr(prob.get("x_hi"))
+        b.J_foot = _ptr(prob.get("J_foot"))
         b.warm_start = 1 if warm_start else 0
         self._keep = prob  # inputs must outlive the stream's use of them
         return b
@@ -252,8 +259,11 @@ class Plan:
             if self.limits:
                 out["zx"] = torch.empty(self.sizes["zx"], dtype=td, device=dev)
                 out["yx"] = torch.empty(self.sizes["zx"], dtype=td, device=dev)
+            if self.contacts:
+                out["zc"] = torch.empty(self.sizes["zc"], dtype=td, device=dev)
+                out["yc"] = torch.empty(self.sizes["zc"], dtype=td, device=dev)
         s = Solution()
-        for k in ("u0", "x", "u", "z", "y", "objective", "residuals", "status", "zx", "yx"):
+        for k in ("u0", "x", "u", "z", "y", "objective", "residuals", "status", "zx", "yx", "zc", "yc"):
             setattr(s, k, _ptr(out.get(k)))
         _check(lib().mpc_get_solution(self._h, ctypes.byref(s), _stream_handle(stream)))
         return out
@@ -264,6 +274,9 @@ class Plan:
 
     def set_warm_limits(self, zx, yx, stream=None):
         _check(lib().mpc_set_warm_limits(self._h, _ptr(zx), _ptr(yx), _stream_handle(stream)))
+
+    def set_warm_contacts(self, zc, yc, stream=None):
+        _check(lib().mpc_set_warm_contacts(self._h, _ptr(zc), _ptr(yc), _stream_handle(stream)))
 
     def advance_state(self, prob, noise, x0_next, stream=None):
         b = self._batch(prob, False)

@@ -1,0 +1,150 @@
+"""GPU: no-slip rows of Eq. (mpc_formulation) (J_f v_k = 0 for feet in stance,
+on x_1..x_N) against the oracle, through the C ABI.
+
+Plans created with no_slip = 1 run the generic kernels (FP64 and FP32); each
+agent is compared with the oracle's solve on the same data and Jacobians (FP32
+data widened exactly): u_0 and the trajectory at 1e-10 (FP64) / 1e-5 (FP32),
+z, y and the rows' z_c, y_c at the same bars for FP64, the residual report,
+cold and warm-started from the GPU's own first solve, alone and together with
+joint limits.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2510_12717_amd import mpc, synth
+
+from test_gpu_parity import agent_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    mpc.lib()
+
+
+def _batch(kind, precision):
+    dt = np.float64 if precision == "fp64" else np.float32
+    if kind == "humanoid":
+        return synth.humanoid_batch(agent_ids=np.arange(0, 4096, 256), dtype=dt)
+    return synth.uneven_batch(agent_ids=np.arange(0, 8192, 512), dtype=dt)
+
+
+def _zc_offsets(b):
+    return np.cumsum([0] + [s.N * s.n_feet * s.foot_dim for s in b.shapes])
+
+
+def _rel_rows(b, got, want, scale, key_scale):
+    """Per-agent max |got - want| over the agent's no-slip rows, relative to the
+    largest of |want| and of the agent's ``scale`` block."""
+    off, oc = b.offsets(), _zc_offsets(b)
+    e = []
+    for a in range(b.n_agents):
+        g = got[oc[a]:oc[a + 1]].astype(np.float64)
+        w = want[oc[a]:oc[a + 1]]
+        sc = scale[off[key_scale][a]:off[key_scale][a + 1]]
+        e.append(np.abs(g - w).max() / max(np.abs(w).max(), np.abs(sc).max(), 1e-300))
+    return np.array(e)
+
+
+def _prob(b, precision, J, limits=None):
+    prob = mpc.to_device(b, precision)
+    td = prob["A"].dtype
+    prob["J_foot"] = torch.from_numpy(J).to(td).cuda()
+    if limits is not None:
+        prob["x_lo"] = torch.from_numpy(limits[0]).to(td).cuda()
+        prob["x_hi"] = torch.from_numpy(limits[1]).to(td).cuda()
+    return prob
+
+
+@pytest.mark.parametrize("precision,kind,with_limits",
+                         [("fp64", "humanoid", False), ("fp32", "humanoid", False),
+                          ("fp64", "uneven", False), ("fp32", "uneven", False),
+                          ("fp64", "uneven", True), ("fp32", "humanoid", True)])
+def test_no_slip_rows_match_oracle_cold_and_warm(precision, kind, with_limits):
+    b = _batch(kind, precision)
+    J = synth.foot_jacobians(b)
+    lim = synth.joint_limits(b) if with_limits else None
+    plan = mpc.Plan(b.shapes, precision=precision, iters=50, no_slip=1,
+                    joint_limits=1 if with_limits else 0)
+    assert plan.config()["kernel"] == "generic"
+    prob = _prob(b, precision, J, lim)
+    plan.solve(prob)
+    g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    assert np.all(g["status"] == 0)
+    kw = dict(x_lo=lim[0], x_hi=lim[1]) if with_limits else {}
+    o = oracle.solve_batch(b, iters=50, J=J, **kw)
+    e = agent_errors(b, g, o)
+    ezc = _rel_rows(b, g["zc"], o["zc"], o["x"], "x")
+    eyc = _rel_rows(b, g["yc"], o["yc"], o["y"], "z")
+    print(f"{precision} {kind} limits={with_limits} cold: max u0/traj/z/y {e.max(axis=0)} "
+          f"zc {ezc.max():.2e} yc {eyc.max():.2e}")
+    assert e[:, :2].max() < TOL[precision]
+    if precision == "fp64":
+        assert max(e.max(), ezc.max(), eyc.max()) < TOL["fp64"]
+        assert np.allclose(g["residuals"], o["res"], rtol=1e-7, atol=1e-12)
+    # warm: the next control step from the GPU's own iterate
+    x0n = (b.x0 + 0.01 * np.random.default_rng(3).standard_normal(b.x0.shape)).astype(b.x0.dtype)
+    prob["x0"] = torch.from_numpy(x0n).cuda()
+    plan.solve(prob, warm_start=True)
+    g2 = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    keys = ("u", "z", "y", "zc", "yc") + (("zx", "yx") if with_limits else ())
+    warm = {k: g[k].astype(np.float64) for k in keys}
+    o2 = oracle.solve_batch(b, iters=50, warm=warm, x0=x0n, J=J, **kw)
+    e2 = agent_errors(b, g2, o2)
+    print(f"{precision} {kind} limits={with_limits} warm: max u0/traj/z/y {e2.max(axis=0)}")
+    assert np.all(g2["status"] == 0) and e2[:, :2].max() < TOL[precision]
+
+
+def test_set_warm_contacts_resumes_the_rows():
+    b = _batch("humanoid", "fp64")
+    J = synth.foot_jacobians(b)
+    o = oracle.solve_batch(b, iters=30, J=J)
+    plan = mpc.Plan(b.shapes, precision="fp64", iters=20, no_slip=1)
+    prob = _prob(b, "fp64", J)
+    plan.set_warm_state(*(torch.from_numpy(o[k]).cuda() for k in ("u", "z", "y")))
+    plan.set_warm_contacts(torch.from_numpy(o["zc"]).cuda(), torch.from_numpy(o["yc"]).cuda())
+    plan.solve(prob, warm_start=True)
+    g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    whole = oracle.solve_batch(b, iters=50, J=J)
+    assert agent_errors(b, g, whole).max() < 1e-9
+
+
+def test_no_slip_plans_check_their_inputs():
+    b = _batch("humanoid", "fp32")
+    J = synth.foot_jacobians(b)
+    prob = mpc.to_device(b, "fp32")
+    plan = mpc.Plan(b.shapes, precision="fp32", no_slip=1)
+    with pytest.raises(mpc.MPCError) as ei:
+        plan.solve(prob)  # the rows are required
+    assert ei.value.code == mpc.MPC_ERR_INVALID_ARG
+    with pytest.raises(mpc.MPCError):
+        plan.set_warm_limits(torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda"))
+    plain = mpc.Plan(b.shapes, precision="fp32")
+    prob["J_foot"] = torch.from_numpy(J).cuda()
+    with pytest.raises(mpc.MPCError):
+        plain.solve(prob)  # a plan without the rows refuses them
+    with pytest.raises(mpc.MPCError):
+        plain.set_warm_contacts(torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda"))
+    for bad in (dict(precision="bf16"), dict(precision="fp32", scaling_iters=5),
+                dict(precision="fp32", kernel="fused"), dict(precision="fp32", no_slip=2)):
+        kw = dict(no_slip=1)
+        kw.update(bad)
+        with pytest.raises(mpc.MPCError):
+            mpc.Plan(b.shapes, **kw)
+    # a non-finite Jacobian marks its agent only
+    Jb = J.copy()
+    Jb[3] = np.nan
+    prob["J_foot"] = torch.from_numpy(Jb).cuda()
+    plan.solve(prob)
+    sol = plan.get_solution()
+    st = sol["status"].cpu().numpy()
+    assert st[0] == mpc.AGENT_NONFINITE and np.all(st[1:] == 0)
+    assert np.all(np.isnan(sol["zc"].cpu().numpy()[: b.shapes[0].N * 12]))

@@ -591,8 +591,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     }
     __syncthreads();
   }
-  if (kResident && N + 1 <= kMaxStages) {
-    // (only the one-wavefront-per-stage iteration kernel reads S_0)
+  if (kResident) {
     // S_0 = -B_0 H_0^{-1} B_0' (FP64 matrix-core tiles, once per agent), written in
     // the chain operator order of an even stage: x~_1 = A_cl,0 x~_0 + c_0
     // - B_0 H_0^{-1} rt_0 + S_0 p'_0, so the iterations' chain wavefront forms
@@ -640,6 +639,21 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
 // read.  Layout: g_k ready (A), p'_k ready
 // (backward chain), e_k ready (C), xt_k ready (forward chain), abort.
 constexpr int kSyncG = 0, kSyncP = kMaxStages, kSyncE = 2 * kMaxStages, kSyncX = 3 * kMaxStages;
+
+// Role of hardware wavefront hw of a register-resident iteration workgroup
+// (stage roles 0 .. chain-1, the chain wavefront `chain`, idle roles past
+// it).  A CU places a workgroup's wavefronts on its four SIMDs in turn
+// (wavefronts 3, 7, 11 share one), so the chain goes to wavefront 3, which
+// then shares its SIMD with fewer stage wavefronts than the last wavefront
+// would for N = 6, 8, 9, 10; the stage roles keep their order on the others.
+// (Measured: 5.17 -> 5.09 ms per launch at N = 10.  The streaming kernel keeps
+// its order: there the same move made every horizon slower.)
+__device__ inline int wave_role(int hw, int chain) {
+  if (chain < 3) return hw;
+  if (hw == 3) return chain;
+  const int r = hw < 3 ? hw : hw - 1;
+  return r >= chain ? r + 1 : r;
+}
 constexpr int kSyncAbort = 4 * kMaxStages + 1, kSyncInts = 4 * kMaxStages + 2;
 constexpr int kSpinLimit = 1 << 21;  // polls of one wait (about 0.1 s)
 
@@ -879,7 +893,7 @@ k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ 
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int w = tid >> 6, lane = tid & 63, la = lane >> 3, lb = lane & 7;
+  const int w = wave_role(tid >> 6, N), lane = tid & 63, la = lane >> 3, lb = lane & 7;
   float* X = st.x + d.ox;
   float* U = st.u + d.ou;
   float* Z = st.z + d.oz;
@@ -1547,7 +1561,7 @@ constexpr int kStRing = 4 * (kMaxStream + 1), kStUsed = kStRing + kRing, kStAbor
 constexpr int kStInts = kStAbort + 1;
 
 struct StreamLds {
-  int ring, xtf, ppf, gf, ef, sf, cf;                                     // float
+  int ring, s0, xtf, ppf, gf, ef, sf, cf, g0f;                            // float
   int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd;  // double
   int flag, sync, total;
 };
@@ -1563,12 +1577,14 @@ __host__ __device__ inline StreamLds stream_lds_layout(int N, int M) {
     return r;
   };
   L.ring = take(4 * kRing * S::AQ * 256);
+  L.s0 = take(4 * S::AQ * 256);
   L.xtf = take(4 * (N + 1) * S::NXP);
   L.ppf = take(4 * N * S::NXP);
   L.gf = take(4 * N * S::NXP);
   L.ef = take(4 * N * S::NXP);
   L.sf = take(4 * N * S::NXP);
   L.cf = take(4 * N * S::NXP);
+  L.g0f = take(4 * 2 * S::NXP);
   L.xd = take(8 * (N + 1) * S::NXP);
   L.ud = take(8 * N * S::NUP);
   L.zd = take(8 * N * M);
@@ -1642,6 +1658,7 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
   float* ef = reinterpret_cast<float*>(sm + L.ef);
   float* sf = reinterpret_cast<float*>(sm + L.sf);
   float* cf = reinterpret_cast<float*>(sm + L.cf);
+  float* g0f = reinterpret_cast<float*>(sm + L.g0f);  // g'_0 of iterations of odd / even number
   double* xd = reinterpret_cast<double*>(sm + L.xd);
   double* ud = reinterpret_cast<double*>(sm + L.ud);
   double* zd = reinterpret_cast<double*>(sm + L.zd);
@@ -1677,6 +1694,12 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
   // per-agent vectors into LDS (padding zero)
   for (int i = tid; i < L.total / 4; i += nt) reinterpret_cast<int*>(sm)[i] = 0;
   __syncthreads();
+  {
+    // S_0 from the factor (after the stage slots and s_k) into its LDS slot
+    const float4* src = reinterpret_cast<const float4*>(opg + (int64_t)N * (SLOTS * 64 + NXP));
+    float4* dst = reinterpret_cast<float4*>(sm + L.s0);
+    for (int i = tid; i < AQ * 64; i += nt) dst[i] = src[i];
+  }
   const float* sk = opg + (int64_t)N * SLOTS * 64;
   for (int i = tid; i < N * NXP; i += nt) sf[i] = sk[i];
   for (int i = tid; i < N * NX; i += nt) cf[(i / NX) * NXP + i % NX] = c[i];
@@ -1711,6 +1734,8 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
     // ---------------- chain wavefront ----------------
     __builtin_amdgcn_s_setprio(2);
     float M0[4 * AQ], M1[4 * AQ];  // even / odd stage operators
+    // S_0 = -B_0 H_0^{-1} B_0' in LDS (xt_1 = A_cl,0 x_0 + g'_0 + S_0 p'_0)
+    const float4* s04 = reinterpret_cast<const float4*>(sm + L.s0);
     int e = 0;                     // next element of the operator sequence
     int el0 = 0, el1 = 0;          // elements held in M0 / M1
     int seen0 = 0, seen1 = 0;      // their slot's flag as read with them
@@ -1765,6 +1790,7 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
     }
     using T_ = std::true_type;
     using F_ = std::false_type;
+    float p0[RB];  // p'_0 of the current iteration, on a*RB + i
     for (int it = 0; it < iters; ++it) {
       const int T = it + 1;
       {
@@ -1830,6 +1856,8 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
         }
         if (lb == 0) lds_store<RB>(ppf + la * RB, pv);
         flag_set(sync + kStP, T);
+#pragma unroll
+        for (int i = 0; i < RB; ++i) p0[i] = pv[i];
       }
       {
         float xv[RB];
@@ -1871,18 +1899,52 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
           for (int i = 0; i < RB; ++i) xv[i] = ev[i] + sx[i];
           if ((ODD ? la : lb) == 0) lds_store<RB>(xtf + ok + NXP + out_idx, xv);
         };
-        flag_wait(sync + kStE, N, T, abortp, lane);
-        double xdN[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
+        // stage 0: xt_1 = A_cl,0 x_0 + g'_0 + S_0 p'_0, without waiting for
+        // C_0; S_0 acts in the even stages' form (summed over b), so p'_0
+        // moves from a*RB + j to b*RB + j first (lane (a, b) reads (b, a))
         {
-          float e0[RB];
-          lds_load<RB>(e0, ef + la * RB);
+          float g0[RB], pt[RB], sx[RB];
+          const int src = ((lb << 3) | la) << 2;
 #pragma unroll
-          for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + e0[i];
+          for (int j = 0; j < RB; ++j)
+            pt[j] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(p0[j])));
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = 0.f;
+          // S_0 read from LDS three quads at a time: the chain keeps A_cl,1 and
+          // A_cl,2 in registers across the turn, so S_0 gets no register set
+#pragma unroll
+          for (int q0 = 0; q0 < AQ; q0 += 3) {
+            float4 v[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+              if (q0 + u < AQ) v[u] = s04[(q0 + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+              for (int c4 = 0; c4 < 4; ++c4) {
+                const int e = 4 * (q0 + u) + c4;
+                if (q0 + u < AQ && e < RB * RB) {
+                  const float sv = c4 == 0 ? v[u].x : c4 == 1 ? v[u].y : c4 == 2 ? v[u].z : v[u].w;
+                  sx[e / RB] += sv * pt[e % RB];
+                }
+              }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+          for (int i = 0; i < RB; ++i) sx[i] = red_b(sx[i]);
+          flag_wait(sync + kStE, 1, T, abortp, lane);  // g'_0
+          lds_load<RB>(g0, g0f + (T & 1) * NXP + la * RB);
+#pragma unroll
+          for (int i = 0; i < RB; ++i) xv[i] = ax0[i] + g0[i] + sx[i];
         }
         if (lb == 0) lds_store<RB>(xtf + NXP + la * RB, xv);
         flag_set(sync + kStX + 1, T);
+        // e_k of stages k >= 1; x_N as relaxed in the previous iteration
+        // (the wavefront of stage N-1 wrote it before flagging e_{N-1})
+        flag_wait(sync + kStE + 1, N - 1, T, abortp, lane);
+        double xdN[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) xdN[i] = xd[N * NXP + pidx + i];
         int kk = 1;
         for (; kk + 1 < N; kk += 2) {
           hop(kk, T_{});
@@ -1981,15 +2043,13 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
       rt_b0 = NU + 4 * ((lane - d.n_tau) / d.foot_dim);
       rt_cc = (lane - d.n_tau) % d.foot_dim;
     }
-    double u_own[2] = {0.0, 0.0}, ru_own[2] = {0.0, 0.0};
+    // (u_k stays in LDS, ud: register copies of it spill in this kernel)
+    double ru_own[2] = {0.0, 0.0};
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       const int k = kS[s2];
       if (k < N) {
-        if (lane < NU) {
-          u_own[s2] = ud[k * NUP + lane];
-          if (uref) ru_own[s2] = (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
-        }
+        if (lane < NU && uref) ru_own[s2] = (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
         if (lane < M) wvd[k * M + lane] = yd[k * M + lane] - rhod[k * M + lane] * zd[k * M + lane];
         if (k >= 1 && lane < NX) qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xd[k * NXP + lane];
       }
@@ -2009,7 +2069,7 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
           if (rt_cc == 0) v += w0 - w1;
           if (rt_cc == 1) v += w2 - w3;
           if (rt_cc == 2) v -= mu * (w0 + w1 + w2 + w3);
-          v += -sigma * u_own[s2];
+          v += -sigma * ud[k * NUP + lane];
           v -= ru_own[s2];
         }
         rtd[k * NUP + lane] = v;
@@ -2083,10 +2143,45 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
         for (int i = 0; i < RB; ++i) se[i] += Bm[s2][i][j] * dv[j];
 #pragma unroll
       for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
-      if (lb == 0)
+      // (stage 0's part of xt_1 is g'_0 + S_0 p'_0, formed by the chain)
+      if (lb == 0 && k >= 1)
 #pragma unroll
         for (int i = 0; i < RB; ++i) ef[k * NXP + la * RB + i] = cv[i] + se[i];
-      flag_set(sync + kStE + k, t);
+      if (k >= 1) flag_set(sync + kStE + k, t);
+    };
+    // g'_0 = c_0 - B_0 H_0^{-1} rt_0 of iteration t (stage 0's wavefront, H_0 in
+    // Hm): the part of xt_1 that does not depend on p'_0, flagged as stage 0's
+    // e.  dd_0 holds -H_0^{-1} rt_0 until C_0 overwrites it with d_0.
+    auto gprime0 = [&](int t) __attribute__((always_inline)) {
+      float hv[CB], sd[CB], dv[CB], se[RB];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) hv[j] = (float)rtd[lb * CB + j];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sd[i] = 0.f;
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) sd[i] += Hm[i][j] * hv[j];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sd[i] = red_b(sd[i]);
+      if (lb == 0)
+#pragma unroll
+        for (int i = 0; i < CB; ++i) dd[la * CB + i] = -(double)sd[i];
+      wave_sync();
+#pragma unroll
+      for (int j = 0; j < CB; ++j) dv[j] = (float)dd[lb * CB + j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) se[i] = 0.f;
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) se[i] += Bm[0][i][j] * dv[j];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) se[i] = red_b(se[i]);
+      if (lb == 0)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) g0f[(t & 1) * NXP + la * RB + i] = cf[la * RB + i] + se[i];
+      flag_set(sync + kStE, t);
     };
     // (E) of stage kS[s]
     auto phaseE = [&](auto s_c) __attribute__((always_inline)) {
@@ -2127,14 +2222,17 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
         wvd[idx] = yn - rhod[idx] * zn;
       }
       if (lane < NU) {
-        u_own[s2] = alpha * utd[k * NUP + lane] + oma * u_own[s2];
-        ud[k * NUP + lane] = u_own[s2];
+        ud[k * NUP + lane] = alpha * utd[k * NUP + lane] + oma * ud[k * NUP + lane];
       }
       wave_sync();
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     if (iters > 0) phaseA(I0{}, 1);
+    if (iters > 0 && kS[0] == 0) {
+      load_H(0);
+      gprime0(1);
+    }
     for (int it = 0; it < iters; ++it) {
       const int T = it + 1;
       if (hasH) {
@@ -2149,7 +2247,10 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
       phaseC(I0{}, T);
       if (kS[0] >= 1) flag_wait(sync + kStX + kS[0], 1, T, abortp, lane);
       phaseE(I0{});
-      if (it + 1 < iters) phaseA(I0{}, T + 1);
+      if (it + 1 < iters) {
+        phaseA(I0{}, T + 1);
+        if (kS[0] == 0) gprime0(T + 1);  // H_0 is still in Hm from C_0
+      }
       if (hasH) {
         flag_wait(sync + kStX + kS[1], 1, T, abortp, lane);
         phaseE(I1{});

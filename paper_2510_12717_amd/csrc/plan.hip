@@ -625,7 +625,7 @@ struct PhaseTimer {
 // Factor and iteration launches of one group on stream s.
 template <typename T>
 static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_batch* b,
-                            hipStream_t s, int warm, int iters) {
+                            hipStream_t s, int warm, int iters, bool residual = false) {
   SolverConsts sc{p->desc.rho, p->desc.sigma, p->desc.alpha, p->desc.rho_eq_scale,
                   p->desc.rho_min};
   sc.rho_agent = p->adaptive ? p->d_rho : nullptr;
@@ -678,6 +678,13 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
                                      s));
     }
   }
+  if (residual) {
+    // the group's KKT residual check on its own queue, so that it overlaps
+    // the groups still iterating instead of following the slowest of them
+    PhaseTimer t(p, 2, s);
+    HIP_TRY(launch_residual<T>(p->d_desc, list, g.count, make_inputs<T>(b), sc, make_state<T>(p),
+                               generic_residual_lds(g.N, g.nx, g.nu, p->esz), s));
+  }
   return MPC_OK;
 }
 
@@ -687,7 +694,7 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
 // one graph).
 template <typename T>
 static mpc_status run_groups(mpc_plan_s* p, const mpc_problem_batch* b, hipStream_t s, int warm,
-                             int iters) {
+                             int iters, bool residual = false) {
   const int ns = 1 + (int)p->aux.size();
   if (ns > 1) {
     HIP_TRY(hipEventRecord(p->ev_fork, s));
@@ -695,7 +702,7 @@ static mpc_status run_groups(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
   }
   for (size_t i = 0; i < p->groups.size(); ++i) {
     const int k = std::min(p->groups[i].queue, ns - 1);
-    mpc_status r = run_group<T>(p, p->groups[i], b, k == 0 ? s : p->aux[k - 1], warm, iters);
+    mpc_status r = run_group<T>(p, p->groups[i], b, k == 0 ? s : p->aux[k - 1], warm, iters, residual);
     if (r != MPC_OK) return r;
   }
   if (ns > 1) {
@@ -724,9 +731,12 @@ static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
   const int K = p->desc.admm_iters;
   const int seg = p->adaptive ? p->desc.rho_interval : K;
   int warm = b->warm_start;
+  // without scaling the last segment's groups check their own residuals (the
+  // iterate is already the caller's); with it, after the unscaling below
+  const bool group_res = !p->scaled;
   for (int done = 0, seg_i = 0; done < K; ++seg_i) {
     const int k = std::min(seg, K - done);
-    mpc_status r = run_groups<T>(p, &sb, s, warm, k);
+    mpc_status r = run_groups<T>(p, &sb, s, warm, k, group_res && done + k == K);
     if (r != MPC_OK) return r;
     done += k;
     warm = 1;
@@ -739,10 +749,12 @@ static mpc_status solve_impl(mpc_plan_s* p, const mpc_problem_batch* b, hipStrea
                                    p->n_seg, seg_i + 1, s));
     }
   }
-  PhaseTimer t(p, 2, s);
-  if (p->scaled) HIP_TRY(launch_unscale<T>(p->d_desc, p->n, p->d_scale, make_state<T>(p), s));
-  HIP_TRY(launch_residual<T>(p->d_desc, nullptr, p->n, make_inputs<T>(b), sc, make_state<T>(p),
-                             p->lds_res, s));
+  if (p->scaled) {
+    PhaseTimer t(p, 2, s);
+    HIP_TRY(launch_unscale<T>(p->d_desc, p->n, p->d_scale, make_state<T>(p), s));
+    HIP_TRY(launch_residual<T>(p->d_desc, nullptr, p->n, make_inputs<T>(b), sc, make_state<T>(p),
+                               p->lds_res, s));
+  }
   return MPC_OK;
 }
 

@@ -600,3 +600,54 @@ def brute_force_qp_contacts(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, J,
             yc[k, i] = mm
         return x, u, y, yc
     return None
+
+
+def osqp_dense_fixed(s, A, B, c, q, r, x_ref, x0, tau_max, mu, stance, iters, *, rho=0.1,
+                     sigma=1e-6, alpha=1.6, rho_eq_scale=1e3, rho_min=1e-6, warm=None):
+    """``iters`` OSQP iterations on the stacked QP with the dynamics as equality
+    rows (finite rho_eq), each solving the quasi-definite KKT system of
+    Eq. (kkt_system) with a dense solve.  Cold start: u = 0, x rolled out
+    from x0, z = A v (the rows' values), y = 0; ``warm`` = (v, z, y).
+    Returns x [N+1, nx], u [N, nu], the input rows' z, y [N, m] and the
+    dynamics rows' zd, yd [N, nx]."""
+    C = C_dense(s, mu)
+    l, h = bounds_table(s, tau_max, stance)
+    G, b = dynamics_rows(s, A, B, c, x0)
+    N, nx, nu = s.N, s.nx, s.nu
+    m = C.shape[0]
+    nv = N * nx + N * nu
+    P = np.zeros((nv, nv))
+    qv = np.zeros(nv)
+    for k in range(1, N + 1):
+        sl = slice((k - 1) * nx, k * nx)
+        P[sl, sl] = np.diag(q)
+        qv[sl] = -q * x_ref[k]
+    P[N * nx:, N * nx:] = np.kron(np.eye(N), np.diag(r))
+    Cb = np.zeros((N * m, nv))
+    for k in range(N):
+        Cb[k * m:(k + 1) * m, N * nx + k * nu:N * nx + (k + 1) * nu] = C
+    Am = np.vstack([G, Cb])
+    lo = np.concatenate([b, l.ravel()])
+    hi = np.concatenate([b, h.ravel()])
+    rv = np.where(lo == hi, rho * rho_eq_scale, rho)
+    rv = np.where(np.isinf(lo) & np.isinf(hi), rho_min, rv)
+    K = np.block([[P + sigma * np.eye(nv), Am.T], [Am, -np.diag(1.0 / rv)]])
+    if warm is None:
+        xs = rollout(s, A, B, c, x0, np.zeros((N, nu)))
+        v = np.concatenate([xs[1:].ravel(), np.zeros(N * nu)])
+        z = Am @ v
+        y = np.zeros(Am.shape[0])
+    else:
+        v, z, y = (np.array(w, dtype=float) for w in warm)
+    for _ in range(iters):
+        sol = np.linalg.solve(K, np.concatenate([sigma * v - qv, z - y / rv]))
+        vt, nu_ = sol[:nv], sol[nv:]
+        zt = z + (nu_ - y) / rv
+        v = alpha * vt + (1 - alpha) * v
+        w = alpha * zt + (1 - alpha) * z
+        zn = np.clip(w + y / rv, lo, hi)
+        y = y + rv * (w - zn)
+        z = zn
+    xs, us = split(s, v, x0)
+    return dict(x=xs, u=us, z=z[N * nx:].reshape(N, m), y=y[N * nx:].reshape(N, m),
+                zd=z[:N * nx].reshape(N, nx), yd=y[:N * nx].reshape(N, nx), v=v, z_all=z, y_all=y)

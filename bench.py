@@ -85,6 +85,9 @@ def parse():
                          "N=16, Q/R condition 1e6, FP32): plain vs Ruiz vs Ruiz + adaptive rho, step "
                          "time and the error of the fixed-iteration iterate against the converged "
                          "optimum (prints its own JSON line)")
+    ap.add_argument("--inner", action="store_true",
+                    help="time the two inner solves side by side instead (exact-dynamics Riccati vs the "
+                         "paper's KKT LDL^T with finite rho_eq; prints its own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="run the served request loop instead: Poisson arrivals from independent "
                          "controllers of uneven shapes (prints its own JSON line)")
@@ -397,6 +400,83 @@ def scaled(args):
     print(json.dumps(out))
 
 
+def inner(args):
+    """The two inner solves side by side on the N = 10 humanoid workload (4096
+    agents, FP32, 50 cold iterations per timed solve): the exact-dynamics
+    Riccati path (register-resident kernels) and the paper's form (dynamics as
+    equality rows with rho_eq, quasi-definite KKT factored by LDL^T, generic
+    kernels).  Per mode: time per solve, the largest dynamics residual of the
+    returned iterates, and for every 256th agent the error of the 50-iteration
+    iterate against the QP's converged optimum (oracle, converge mode) and
+    against the oracle of the same mode."""
+    import torch
+
+    import oracle
+    from oracle import kkt as okkt
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    n = args.agents
+    b = synth.humanoid_batch(n, dtype=np.float32)
+    prob = mpc.to_device(b, "fp32")
+    ids = np.arange(0, n, 256)
+    sub = synth.humanoid_batch(agent_ids=ids, dtype=np.float32)
+    sh = b.shapes[0]
+    keys = ("s", "A", "B", "c", "q", "r", "x_ref", "x0", "tau_max", "mu", "stance")
+    opt = [oracle.solve(*[oracle.agent(sub, a)[k] for k in keys], iters=0, tol=1e-10)
+           for a in range(len(ids))]
+
+    def err(u, x, o):
+        uo, xo = np.ravel(o["u"]), np.ravel(o["x"])
+        tr, to = np.concatenate([x[sh.nx:], u]), np.concatenate([xo[sh.nx:], uo])
+        return (np.abs(u[:sh.nu] - uo[:sh.nu]).max() / np.abs(uo[:sh.nu]).max(),
+                np.abs(tr - to).max() / np.abs(to).max())
+
+    modes = {}
+    for name, kw in (("riccati_exact_dynamics", {}), ("kkt_ldl_finite_rho_eq", {"inner_solve": 1})):
+        plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters, **kw)
+        stream = torch.cuda.current_stream()
+        for _ in range(max(args.warmup, 1)):
+            plan.solve(prob, stream=stream)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.solve(prob, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        tm = plan.get_timing()
+        sol = plan.get_solution()
+        u = sol["u"].cpu().numpy().reshape(n, -1)[ids].astype(np.float64)
+        x = sol["x"].cpu().numpy().reshape(n, -1)[ids].astype(np.float64)
+        res = sol["residuals"].cpu().numpy()
+        st = sol["status"].cpu().numpy()
+        if kw:
+            ref = [okkt.solve(oracle.agent(sub, a), iters=args.iters) for a in range(len(ids))]
+        else:
+            ref = [oracle.solve(*[oracle.agent(sub, a)[k] for k in keys], iters=args.iters)
+                   for a in range(len(ids))]
+        e_opt = np.array([err(u[a], x[a], opt[a]) for a in range(len(ids))])
+        e_ref = np.array([err(u[a], x[a], ref[a]) for a in range(len(ids))])
+        modes[name] = {"ms_per_step": ms, "solves_per_s": n / ms * 1e3,
+                       "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in tm.items()},
+                       "status_ok": bool((st == 0).all()),
+                       "dynamics_residual_max": float(res[:, 2].max()),
+                       "gpu_vs_optimum": {"u0_median": float(np.median(e_opt[:, 0])),
+                                          "traj_median": float(np.median(e_opt[:, 1])),
+                                          "traj_max": float(e_opt[:, 1].max())},
+                       "gpu_vs_oracle_same_mode": {"u0_max": float(e_ref[:, 0].max()),
+                                                   "traj_max": float(e_ref[:, 1].max())}}
+        plan.close()
+    out = {"metric": "MPC QP solves/sec and fixed-iteration error vs the optimum, per inner solve",
+           "value": modes["kkt_ldl_finite_rho_eq"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n} humanoid agents (nx=48, nu=30), N=10, {args.iters} cold ADMM "
+                                  "iterations", "agents": n, "checked_agents": int(len(ids))},
+           "modes": modes}
+    print(json.dumps(out))
+
+
 def serve(args):
     """Served loop: every controller (shapes as the uneven batch: N ~ U{5..20},
     half humanoid, half quadruped) sends Poisson requests at rate-hz for
@@ -520,6 +600,9 @@ def main():
         return
     if args.serve:
         serve(args)
+        return
+    if args.inner:
+        inner(args)
         return
     if args.uneven:
         uneven(args)

@@ -124,6 +124,13 @@ typedef struct {
                             /* the feet in stance (Eq. (mpc_formulation)) on x_1..x_N,  */
                             /* stance of stage min(k, N-1); generic kernels, FP64 or    */
                             /* FP32 only, without scaling (default 0)                   */
+  int32_t inner_solve;      /* 0: exact dynamics, Riccati factor and sweeps (default);  */
+                            /* 1: the paper's form, dynamics as equality rows with      */
+                            /* penalty rho_eq_scale * rho and the quasi-definite KKT    */
+                            /* matrix of Eq. (kkt_system) factored once by LDL^T        */
+                            /* (Eq. (ldl)) and solved by substitution (Eqs.             */
+                            /* (backsolve_1)-(backsolve_2)); FP64 or FP32, fixed rho,   */
+                            /* no scaling, joint limits or no-slip rows                 */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */
@@ -183,6 +190,9 @@ typedef struct {
   void *zc, *yc;                        /* no-slip rows' (z_c, y_c) [N][n_feet*   */
                                         /* foot_dim], io type (plans with no-slip */
                                         /* rows); may be NULL                    */
+  void *zd, *yd;                        /* dynamics rows' (z, y) [N][nx], io type */
+                                        /* (plans with inner_solve = 1); may be  */
+                                        /* NULL                                  */
 } mpc_solution;
 
 /* The QP solution Alg. 1 returns after its fixed iteration count; u_0 is
@@ -203,6 +213,14 @@ mpc_status mpc_set_warm_state(mpc_plan_t plan, const void* u, const void* z, con
  * z_x, y_x [N][nx] per agent (io type, device), e.g. to resume a controller
  * together with mpc_set_warm_state. */
 mpc_status mpc_set_warm_limits(mpc_plan_t plan, const void* zx, const void* yx, void* stream);
+
+/* The warm start of the paper-form inner solve (plans with inner_solve = 1,
+ * Eq. (kkt_system)): its iterate also holds the states, which are not re-rolled
+ * from xbar0, and the dynamics rows' (z, y).  x [N+1][nx] (x_0 is replaced by
+ * the next batch's xbar0), zd, yd [N][nx] per agent (io type, device), beside
+ * mpc_set_warm_state's u, z, y.  INVALID_ARG for other plans. */
+mpc_status mpc_set_warm_kkt(mpc_plan_t plan, const void* x, const void* zd, const void* yd,
+                            void* stream);
 
 /* The no-slip rows' part of the warm start (plans with no-slip rows, the
  * stance constraint of Eq. (mpc_formulation)): z_c, y_c [N][n_feet*foot_dim]

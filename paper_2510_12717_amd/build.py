@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpc_hip.so")
-SOURCES = ["plan.hip", "server.hip", "kernels_generic.hip", "kernels_fused.hip", "noalloc.hip", "scaling.hip"]
+SOURCES = ["plan.hip", "server.hip", "kernels_generic.hip", "kernels_fused.hip", "kernels_kkt.hip",
+           "noalloc.hip", "scaling.hip"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,80 @@
+// Workgroup-level building blocks of the generic kernels (one workgroup per
+// agent, up to 256 threads): finiteness checks, block reductions through LDS
+// and quad-split dot products / matrix-vector products.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "xlane.h"
+
+namespace mpc {
+
+template <typename T>
+__device__ inline bool finite_all(const T* p, int64_t n, int tid, int nt) {
+  bool ok = true;
+  for (int64_t i = tid; i < n; i += nt) ok &= (bool)isfinite(p[i]);
+  return ok;
+}
+
+// Block-wide reductions through LDS (blockDim.x <= 256).
+__device__ inline double block_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// store(i, sum_t term(i, t)) for i < n_out, t < n_in: each output's sum is
+// split over the 4 lanes of a quad (terms t = sub, sub + 4, ...) and summed
+// with DPP.
+template <typename V, class FT, class FS>
+__device__ inline void quad_dot(int n_out, int n_in, FT term, FS store, int tid, int nt) {
+  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
+  for (int i0 = 0; i0 < n_out; i0 += nq) {
+    const int i = i0 + qd;
+    if (i < n_out) {  // uniform within a quad
+      V acc = 0;
+      for (int t = sub; t < n_in; t += 4) acc += term(i, t);
+      acc = quad_sum(acc);
+      if (sub == 0) store(i, acc);
+    }
+  }
+}
+
+// store(i, sum_t m(i, t) v_t) for i < n_out: each output's dot product is
+// split over the 4 lanes of a quad (terms t = sub, sub + 4, ...) and summed
+// with DPP, so a serial chain step costs n_in / 4 dependent FMAs.
+template <typename V, class FM, class FS>
+__device__ inline void quad_matvec(int n_out, int n_in, FM m, const V* v, FS store, int tid, int nt) {
+  const int qd = tid >> 2, sub = tid & 3, nq = nt >> 2;
+  for (int i0 = 0; i0 < n_out; i0 += nq) {
+    const int i = i0 + qd;
+    if (i < n_out) {  // uniform within a quad
+      V acc = 0;
+      for (int t = sub; t < n_in; t += 4) acc += (V)m(i, t) * v[t];
+      acc = quad_sum(acc);
+      if (sub == 0) store(i, acc);
+    }
+  }
+}
+
+}  // namespace mpc

@@ -96,6 +96,30 @@ inline size_t generic_residual_lds(int N, int nx, int nu, size_t esz) {
   return dbl + esz * ((size_t)nx * (nx + 1) + (size_t)nx * (nu + 1)) + 16;
 }
 
+// The paper-form inner solve (quasi-definite KKT factored by LDL^T, finite
+// rho_eq): S_k^{-1} of every stage, [N][nu+nx][nu+nx] per agent (io type).
+inline int64_t kkt_ws_elems(int N, int nx, int nu) {
+  return (int64_t)N * (nu + nx) * (nu + nx);
+}
+inline size_t kkt_factor_lds(int nx, int nu, int m) {
+  const size_t nw = (size_t)(nu + nx);
+  return 8 * (nw * nw + 4 * (size_t)nx * nx + 2 * (size_t)nu * nx + (size_t)m);
+}
+inline size_t kkt_admm_lds(int N, int nx, int nu, int m) {
+  return 8 * ((size_t)(N + 1) * nx + (size_t)N * nu + 2 * (size_t)N * m + 2 * (size_t)N * nx +
+              2 * (size_t)N * (nu + nx) + 3 * (size_t)nx);
+}
+hipError_t kkt_set_lds_limits(size_t lds_factor, size_t lds_admm);
+template <typename T>
+hipError_t launch_kkt_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
+                             SolverConsts sc, T* ws, int32_t* status, size_t lds,
+                             hipStream_t stream);
+// zd, yd: the dynamics rows' (z, y), [N][nx] per agent at the c offset.
+template <typename T>
+hipError_t launch_kkt_admm(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
+                           SolverConsts sc, int iters, int warm, const T* ws, State<T> st,
+                           T* zd, T* yd, size_t lds, hipStream_t stream);
+
 // Raise the dynamic-LDS limit of the generic kernels to what a plan needs.
 hipError_t generic_set_lds_limits(size_t lds_factor, size_t lds_admm, size_t lds_res);
 

@@ -96,6 +96,7 @@ struct mpc_plan_s {
   int kernel = 1;
   int maxN = 0, maxnx = 0, maxnu = 0, maxm = 0;
   int64_t nX = 0, nU = 0, nZ = 0, nWS = 0;
+  int64_t nC = 0;  // sum of N nx (the layout of c)
   AgentDesc* d_desc = nullptr;
   int64_t* d_u0off = nullptr;  // packed u_0 offset of every agent
   bool uniform_u = true;       // every agent has the same N and nu
@@ -114,12 +115,17 @@ struct mpc_plan_s {
   bool limits = false;
   void *d_zx = nullptr, *d_yx = nullptr;  // [sum N nx]: the state rows' (z_x, y_x)
   int64_t nZX = 0;
+  // paper-form inner solve (finite rho_eq, KKT factored by LDL^T)
+  bool kkt = false;
+  void *d_zd = nullptr, *d_yd = nullptr;  // [sum N nx]: the dynamics rows' (z, y)
+  size_t lds_kkt_factor = 0, lds_kkt_admm = 0;
   // no-slip rows
   bool contacts = false;
   void *d_zc = nullptr, *d_yc = nullptr;  // [sum N n_feet foot_dim]: the rows' (z_c, y_c)
   int64_t nZC = 0, maxnc = 0;
   int n_seg = 1;
   bool solved = false;
+  bool kkt_state = false;  // x, zd, yd hold an iterate (KKT inner solve)
   size_t lds_factor = 0, lds_admm = 0, lds_res = 0;
   // launch groups
   std::vector<Group> groups;
@@ -176,6 +182,7 @@ extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
   d->rho_tolerance = 5.0;
   d->joint_limits = 0;
   d->no_slip = 0;
+  d->inner_solve = 0;
 }
 
 extern "C" const char* mpc_last_error(void) { return mpc::g_err.c_str(); }
@@ -209,6 +216,8 @@ static void free_plan(mpc_plan_s* p) {
   hipFree(p->d_yx);
   hipFree(p->d_zc);
   hipFree(p->d_yc);
+  hipFree(p->d_zd);
+  hipFree(p->d_yd);
   for (auto e : p->ev_pool) hipEventDestroy(e);
   for (auto& pe : p->pending) {
     hipEventDestroy(pe.second.first);
@@ -249,6 +258,15 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
        desc->scaling_iters > 0 || desc->kernel == 2))
     return fail(MPC_ERR_INVALID_ARG,
                 "no-slip rows run on the generic kernels in FP64 or FP32, without scaling");
+  if (desc->inner_solve != 0 && desc->inner_solve != 1)
+    return fail(MPC_ERR_INVALID_ARG, "inner_solve must be 0 or 1");
+  if (desc->inner_solve &&
+      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
+       desc->scaling_iters > 0 || desc->rho_interval > 0 || desc->kernel == 2 ||
+       desc->joint_limits || desc->no_slip))
+    return fail(MPC_ERR_INVALID_ARG,
+                "the KKT inner solve runs on its own kernels in FP64 or FP32, with a fixed rho and "
+                "without scaling, joint limits or no-slip rows");
   for (int a = 0; a < desc->n_agents; ++a) {
     mpc_status vs = validate_shape(desc->shapes[a], a);
     if (vs != MPC_OK) return vs;
@@ -266,6 +284,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->esz = p->fp64 ? 8 : 4;
   p->limits = desc->joint_limits != 0;
   p->contacts = desc->no_slip != 0;
+  p->kkt = desc->inner_solve != 0;
 
   p->hdesc.resize(p->n);
   AgentDesc cur{};
@@ -306,7 +325,11 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     ox += (int64_t)(s.N + 1) * s.nx;
     ou += (int64_t)s.N * s.nu;
     oz += (int64_t)s.N * cur.m;
-    ows += generic_ws_elems(s.N, s.nx, s.nu, cur.m);
+    ows += p->kkt ? kkt_ws_elems(s.N, s.nx, s.nu) : generic_ws_elems(s.N, s.nx, s.nu, cur.m);
+    if (p->kkt) {
+      p->lds_kkt_factor = std::max(p->lds_kkt_factor, kkt_factor_lds(s.nx, s.nu, cur.m));
+      p->lds_kkt_admm = std::max(p->lds_kkt_admm, kkt_admm_lds(s.N, s.nx, s.nu, cur.m));
+    }
     p->maxN = std::max(p->maxN, s.N);
     p->maxnx = std::max(p->maxnx, s.nx);
     p->maxnu = std::max(p->maxnu, s.nu);
@@ -316,6 +339,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->nU = ou;
   p->nZ = oz;
   p->nWS = ows;
+  p->nC = oc;
   p->lds_factor = generic_factor_lds(p->maxnx, p->maxnu, p->esz);
   p->lds_admm = generic_admm_lds(p->maxN, p->maxnx, p->maxnu, p->maxm, p->esz, p->limits,
                                  p->contacts ? (int)p->maxnc : 0);
@@ -330,7 +354,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
     for (int a = 0; a < p->n; ++a) {
       const mpc_shape& s = p->shapes[a];
-      const bool fok = desc->precision == MPC_FP32 && !p->limits && !p->contacts &&
+      const bool fok = desc->precision == MPC_FP32 && !p->limits && !p->contacts && !p->kkt &&
                        fused_supported(s.N, s.nx, s.nu, s.n_feet);
       if (desc->kernel == 2 && !fok) {
         delete p;
@@ -395,11 +419,13 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   }
   int lds_max = 0;
   hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device);
-  if ((int64_t)p->lds_factor > lds_max || (int64_t)p->lds_admm > lds_max) {
+  if ((int64_t)p->lds_factor > lds_max || (int64_t)p->lds_admm > lds_max ||
+      (int64_t)p->lds_kkt_factor > lds_max || (int64_t)p->lds_kkt_admm > lds_max) {
     delete p;
     return fail(MPC_ERR_UNSUPPORTED_SHAPE, "shapes need more LDS than the device offers");
   }
   e = generic_set_lds_limits(p->lds_factor, p->lds_admm, p->lds_res);
+  if (e == hipSuccess && p->kkt) e = kkt_set_lds_limits(p->lds_kkt_factor, p->lds_kkt_admm);
   if (e == hipSuccess && !p->fp64) e = fused_set_limits();
   if (e != hipSuccess) {
     delete p;
@@ -457,6 +483,10 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       p->nZX = oc;  // N nx per agent, the layout of c
       if (se == hipSuccess) se = alloc(&p->d_zx, p->esz * (size_t)p->nZX);
       if (se == hipSuccess) se = alloc(&p->d_yx, p->esz * (size_t)p->nZX);
+    }
+    if (p->kkt) {
+      if (se == hipSuccess) se = alloc(&p->d_zd, p->esz * (size_t)oc);
+      if (se == hipSuccess) se = alloc(&p->d_yd, p->esz * (size_t)oc);
     }
     if (p->contacts) {
       p->nZC = ozc;
@@ -519,6 +549,9 @@ static mpc_status check_batch(mpc_plan_s* p, const mpc_problem_batch* b) {
   if (b->warm_start != 0 && b->warm_start != 1) return fail(MPC_ERR_INVALID_ARG, "warm_start must be 0 or 1");
   if (b->warm_start && !p->solved)
     return fail(MPC_ERR_INVALID_ARG, "warm_start requested before any solve or warm state");
+  if (b->warm_start && p->kkt && !p->kkt_state)
+    return fail(MPC_ERR_INVALID_ARG,
+                "warm_start of the KKT inner solve needs a previous solve or mpc_set_warm_kkt");
   if (p->scaled && b->u_ref)
     return fail(MPC_ERR_INVALID_ARG, "an input reference is not supported with scaling");
   if (p->limits != (b->x_lo != nullptr) || (b->x_lo == nullptr) != (b->x_hi == nullptr))
@@ -657,6 +690,19 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
                                          make_state<float>(p), g.lds_admm, g.gthreads, s,
                                          p->desc.max_refine_sweeps, p->desc.refine_tol));
     }
+  } else if (p->kkt) {
+    const Inputs<T> in = make_inputs<T>(b);
+    {
+      PhaseTimer t(p, 0, s);
+      HIP_TRY(launch_kkt_factor<T>(p->d_desc, list, g.count, in, sc, (T*)p->d_ws, p->d_status,
+                                   kkt_factor_lds(g.nx, g.nu, g.nu + 4 * g.n_feet), s));
+    }
+    {
+      PhaseTimer t(p, 1, s);
+      HIP_TRY(launch_kkt_admm<T>(p->d_desc, list, g.count, in, sc, iters, warm,
+                                 (const T*)p->d_ws, make_state<T>(p), (T*)p->d_zd, (T*)p->d_yd,
+                                 kkt_admm_lds(g.N, g.nx, g.nu, g.nu + 4 * g.n_feet), s));
+    }
   } else {
     const Inputs<T> in = make_inputs<T>(b);
     {
@@ -767,6 +813,7 @@ extern "C" mpc_status mpc_solve(mpc_plan_t p, const mpc_problem_batch* b, void* 
   p->last_stream = s;
   mpc_status r = p->fp64 ? solve_impl<double>(p, b, s) : solve_impl<float>(p, b, s);
   if (r == MPC_OK) p->solved = true;
+  if (r == MPC_OK && p->kkt) p->kkt_state = true;
   return r;
 }
 
@@ -785,6 +832,8 @@ extern "C" mpc_status mpc_get_solution(mpc_plan_t p, const mpc_solution* o, void
   if (o->status) HIP_TRY(hipMemcpyAsync(o->status, p->d_status, sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, s));
   if (p->limits && o->zx) HIP_TRY(hipMemcpyAsync(o->zx, p->d_zx, e * p->nZX, hipMemcpyDeviceToDevice, s));
   if (p->limits && o->yx) HIP_TRY(hipMemcpyAsync(o->yx, p->d_yx, e * p->nZX, hipMemcpyDeviceToDevice, s));
+  if (p->kkt && o->zd) HIP_TRY(hipMemcpyAsync(o->zd, p->d_zd, e * p->nC, hipMemcpyDeviceToDevice, s));
+  if (p->kkt && o->yd) HIP_TRY(hipMemcpyAsync(o->yd, p->d_yd, e * p->nC, hipMemcpyDeviceToDevice, s));
   if (p->contacts && p->nZC > 0 && o->zc)
     HIP_TRY(hipMemcpyAsync(o->zc, p->d_zc, e * p->nZC, hipMemcpyDeviceToDevice, s));
   if (p->contacts && p->nZC > 0 && o->yc)
@@ -828,6 +877,19 @@ extern "C" mpc_status mpc_set_warm_limits(mpc_plan_t p, const void* zx, const vo
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipMemcpyAsync(p->d_zx, zx, p->esz * p->nZX, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(p->d_yx, yx, p->esz * p->nZX, hipMemcpyDeviceToDevice, s));
+  return MPC_OK;
+}
+
+extern "C" mpc_status mpc_set_warm_kkt(mpc_plan_t p, const void* x, const void* zd, const void* yd,
+                                        void* stream) {
+  if (!p || !x || !zd || !yd) return fail(MPC_ERR_INVALID_ARG, "null argument");
+  if (!p->kkt) return fail(MPC_ERR_INVALID_ARG, "this plan does not run the KKT inner solve");
+  HIP_TRY(hipSetDevice(p->desc.device));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(p->d_x, x, p->esz * p->nX, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_zd, zd, p->esz * p->nC, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_yd, yd, p->esz * p->nC, hipMemcpyDeviceToDevice, s));
+  p->kkt_state = true;
   return MPC_OK;
 }
 
@@ -1100,5 +1162,6 @@ extern "C" mpc_status mpc_plan_replay(mpc_plan_t p, void* stream) {
   HIP_TRY(hipSetDevice(p->desc.device));
   HIP_TRY(hipGraphLaunch(p->gexec, (hipStream_t)stream));
   p->solved = true;
+  if (p->kkt) p->kkt_state = true;
   return MPC_OK;
 }

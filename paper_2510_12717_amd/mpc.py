@@ -40,7 +40,7 @@ class PlanDesc(ctypes.Structure):
                 ("device", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("scaling_iters", ctypes.c_int32), ("rho_interval", ctypes.c_int32),
                 ("rho_tolerance", ctypes.c_double), ("joint_limits", ctypes.c_int32),
-                ("no_slip", ctypes.c_int32)]
+                ("no_slip", ctypes.c_int32), ("inner_solve", ctypes.c_int32)]
 
 
 class ProblemBatch(ctypes.Structure):
@@ -69,12 +69,14 @@ class ServerStats(ctypes.Structure):
 
 class Solution(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "x", "u", "z", "y", "objective",
-                                               "residuals", "status", "zx", "yx", "zc", "yc")]
+                                               "residuals", "status", "zx", "yx", "zc", "yc", "zd",
+                                               "yd")]
 
 
 # every symbol the header declares
 EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_solve",
            "mpc_get_solution", "mpc_set_warm_state", "mpc_set_warm_limits", "mpc_set_warm_contacts",
+           "mpc_set_warm_kkt",
            "mpc_advance_state", "mpc_plan_set_timing",
            "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
            "mpc_plan_get_rho", "mpc_plan_get_scaling", "mpc_plan_get_groups", "mpc_plan_autotune", "mpc_plan_capture", "mpc_plan_replay",
@@ -104,6 +106,7 @@ def lib():
         L.mpc_set_warm_state.argtypes = [V, V, V, V, V]
         L.mpc_set_warm_limits.argtypes = [V, V, V, V]
         L.mpc_set_warm_contacts.argtypes = [V, V, V, V]
+        L.mpc_set_warm_kkt.argtypes = [V, V, V, V, V]
         L.mpc_advance_state.argtypes = [V, P(ProblemBatch), V, V, V]
         L.mpc_plan_set_timing.argtypes = [V, I32]
         L.mpc_plan_get_timing.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -137,7 +140,7 @@ def lib():
             getattr(L, f).restype = ctypes.c_int
         for f in ("mpc_plan_create", "mpc_plan_destroy", "mpc_solve", "mpc_get_solution",
                   "mpc_set_warm_state", "mpc_set_warm_limits", "mpc_set_warm_contacts",
-                  "mpc_advance_state",
+                  "mpc_set_warm_kkt", "mpc_advance_state",
                   "mpc_plan_set_timing",
                   "mpc_plan_get_timing", "mpc_plan_get_config", "mpc_plan_export_factor",
                   "mpc_plan_get_rho", "mpc_plan_get_scaling",
@@ -208,6 +211,7 @@ class Plan:
         m = [s.nu + 4 * s.n_feet for s in self.shapes]
         self.limits = bool(consts.get("joint_limits", 0))
         self.contacts = bool(consts.get("no_slip", 0))
+        self.kkt = bool(consts.get("inner_solve", 0))
         self.sizes = dict(x=sum((s.N + 1) * s.nx for s in self.shapes),
                           zx=sum(s.N * s.nx for s in self.shapes),
                           zc=sum(s.N * s.n_feet * s.foot_dim for s in self.shapes),
@@ -262,8 +266,12 @@ class Plan:
             if self.contacts:
                 out["zc"] = torch.empty(self.sizes["zc"], dtype=td, device=dev)
                 out["yc"] = torch.empty(self.sizes["zc"], dtype=td, device=dev)
+            if self.kkt:
+                out["zd"] = torch.empty(self.sizes["zx"], dtype=td, device=dev)
+                out["yd"] = torch.empty(self.sizes["zx"], dtype=td, device=dev)
         s = Solution()
-        for k in ("u0", "x", "u", "z", "y", "objective", "residuals", "status", "zx", "yx", "zc", "yc"):
+        for k in ("u0", "x", "u", "z", "y", "objective", "residuals", "status", "zx", "yx", "zc", "yc",
+                  "zd", "yd"):
             setattr(s, k, _ptr(out.get(k)))
         _check(lib().mpc_get_solution(self._h, ctypes.byref(s), _stream_handle(stream)))
         return out
@@ -274,6 +282,9 @@ class Plan:
 
     def set_warm_limits(self, zx, yx, stream=None):
         _check(lib().mpc_set_warm_limits(self._h, _ptr(zx), _ptr(yx), _stream_handle(stream)))
+
+    def set_warm_kkt(self, x, zd, yd, stream=None):
+        _check(lib().mpc_set_warm_kkt(self._h, _ptr(x), _ptr(zd), _ptr(yd), _stream_handle(stream)))
 
     def set_warm_contacts(self, zc, yc, stream=None):
         _check(lib().mpc_set_warm_contacts(self._h, _ptr(zc), _ptr(yc), _stream_handle(stream)))

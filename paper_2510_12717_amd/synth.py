@@ -329,3 +329,116 @@ def step_noise(batch: Batch, step: int, std: float = 1e-2) -> np.ndarray:
         rng = agent_rng(batch.seed, batch.stream_id, int(aid), 1_000_000 + step)
         parts.append(rng.standard_normal(s.nx) * std)
     return np.concatenate(parts)
+
+
+# ------------------------------------------------------------------------------
+# Synthetic articulated models (the front and back end of the real-time
+# iteration need a robot model; the paper's MIT Humanoid is not available, so a
+# tree of the same size stands in).  Only parameters are drawn here.
+# ------------------------------------------------------------------------------
+
+JOINT_REVOLUTE, JOINT_PRISMATIC = 0, 1
+
+
+def _limb(parent, joints, rng, mass, length, first_offset):
+    """Bodies of one limb: (parent, joint type, axis, offset of the joint in the
+    parent frame, mass, centre of mass, principal inertia)."""
+    out = []
+    for i, ax in enumerate(joints):
+        off = np.array(first_offset if i == 0 else [0.0, 0.0, -length[i - 1]])
+        m = mass[i] * rng.uniform(0.8, 1.2)
+        ln = length[i] if i < len(length) else 0.05
+        com = np.array([rng.uniform(-0.01, 0.01), rng.uniform(-0.01, 0.01), -0.5 * ln])
+        rad = 0.04 * rng.uniform(0.8, 1.2)
+        ic = m * np.array([(3 * rad ** 2 + ln ** 2) / 12, (3 * rad ** 2 + ln ** 2) / 12, rad ** 2 / 2])
+        out.append((parent, JOINT_REVOLUTE, np.eye(3)[ax], off, m, com, ic))
+        parent = None  # the next joint hangs from this body
+    return out
+
+
+def articulated_model(kind: str = "humanoid", seed: int = 0) -> dict:
+    """A floating-base tree with the size of the humanoid (18 joints: two legs
+    of hip yaw/roll/pitch, knee, ankle; two arms of shoulder pitch/roll/yaw,
+    elbow) or of the quadruped (4 legs of hip abduction/flexion, knee).  The
+    floating base is a chain of three prismatic joints along the world axes and
+    three revolute joints z, y, x (yaw, pitch, roll) carrying the base body, so
+    the generalised coordinates are additive (q = base position, ZYX angles,
+    joint angles; qd their rates).  Returns per body: parent (-1 for the first),
+    joint type, joint axis (joint frame), the joint frame's offset in the
+    parent frame (rotation identity), mass, centre of mass and principal
+    inertia (body frame); per foot: its body and the contact point's offset
+    in that body's frame; foot_dim (6: force and moment, 3: force)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4_000_000, 0 if kind == "humanoid" else 1])))
+    bodies = []
+    # virtual base joints: x, y, z translation, then z, y, x rotation; massless
+    for ax in range(3):
+        bodies.append((len(bodies) - 1, JOINT_PRISMATIC, np.eye(3)[ax], np.zeros(3), 0.0, np.zeros(3), np.zeros(3)))
+    for ax in (2, 1, 0):
+        bodies.append((len(bodies) - 1, JOINT_REVOLUTE, np.eye(3)[ax], np.zeros(3), 0.0, np.zeros(3), np.zeros(3)))
+    base = len(bodies) - 1  # the roll joint's body is the base
+    if kind == "humanoid":
+        mb = 12.0 * rng.uniform(0.9, 1.1)
+        bodies[base] = bodies[base][:4] + (mb, np.array([0.0, 0.0, 0.1]), mb * np.array([0.12, 0.10, 0.05]))
+        feet = []
+        for side in (1.0, -1.0):
+            leg = _limb(base, [2, 0, 1, 1, 1], rng, [1.0, 1.0, 3.0, 2.0, 0.6], [0.05, 0.05, 0.30, 0.30, 0.05],
+                        [0.0, 0.09 * side, -0.05])
+            first = len(bodies)
+            for i, b in enumerate(leg):
+                bodies.append(((first + i - 1) if i else base,) + b[1:])
+            feet.append((len(bodies) - 1, np.array([0.03, 0.0, -0.05])))
+        for side in (1.0, -1.0):
+            arm = _limb(base, [1, 0, 2, 1], rng, [0.8, 0.8, 1.0, 0.6], [0.05, 0.05, 0.25, 0.25],
+                        [0.0, 0.17 * side, 0.35])
+            first = len(bodies)
+            for i, b in enumerate(arm):
+                bodies.append(((first + i - 1) if i else base,) + b[1:])
+        foot_dim = 6
+    else:
+        mb = 9.0 * rng.uniform(0.9, 1.1)
+        bodies[base] = bodies[base][:4] + (mb, np.zeros(3), mb * np.array([0.04, 0.10, 0.12]))
+        feet = []
+        for sx in (1.0, -1.0):
+            for sy in (1.0, -1.0):
+                leg = _limb(base, [0, 1, 1], rng, [0.6, 1.2, 0.3], [0.08, 0.21, 0.21],
+                            [0.19 * sx, 0.05 * sy, 0.0])
+                first = len(bodies)
+                for i, b in enumerate(leg):
+                    bodies.append(((first + i - 1) if i else base,) + b[1:])
+                feet.append((len(bodies) - 1, np.array([0.0, 0.0, -0.21])))
+        foot_dim = 3
+    nb = len(bodies)
+    return dict(
+        kind=kind, n=nb, n_joints=nb - 6, gravity=9.81,
+        parent=np.array([b[0] for b in bodies], dtype=np.int32),
+        jtype=np.array([b[1] for b in bodies], dtype=np.int32),
+        axis=np.array([b[2] for b in bodies]), offset=np.array([b[3] for b in bodies]),
+        mass=np.array([b[4] for b in bodies]), com=np.array([b[5] for b in bodies]),
+        inertia=np.array([b[6] for b in bodies]),
+        foot_body=np.array([f[0] for f in feet], dtype=np.int32), foot_offset=np.array([f[1] for f in feet]),
+        foot_dim=foot_dim)
+
+
+def model_states(model: dict, n: int, seed: int = 0, dt: float = 0.02):
+    """n seeded configurations near a standing pose for the model: q (base
+    height 0.6 m, small base angles, joint angles N(0, 0.2)), qd N(0, 0.3),
+    qdd N(0, 1), joint torques N(0, 5) and foot forces (vertical ~ weight per
+    foot, tangential within the friction cone; moments N(0, 0.5) for 6D)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4_100_000])))
+    nq = model["n"]
+    nf, fd = len(model["foot_body"]), model["foot_dim"]
+    q = np.zeros((n, nq))
+    q[:, 0:2] = rng.uniform(-0.5, 0.5, (n, 2))
+    q[:, 2] = 0.6 + rng.uniform(-0.05, 0.05, n)
+    q[:, 3:6] = rng.normal(0, 0.1, (n, 3))
+    q[:, 6:] = rng.normal(0, 0.2, (n, nq - 6))
+    qd = rng.normal(0, 0.3, (n, nq))
+    qdd = rng.normal(0, 1.0, (n, nq))
+    tau = rng.normal(0, 5.0, (n, nq - 6))
+    w = model["mass"].sum() * model["gravity"] / nf
+    F = np.zeros((n, nf, fd))
+    F[:, :, 2] = w * rng.uniform(0.5, 1.5, (n, nf))
+    F[:, :, :2] = rng.uniform(-0.3, 0.3, (n, nf, 2)) * F[:, :, 2:3]
+    if fd == 6:
+        F[:, :, 3:] = rng.normal(0, 0.5, (n, nf, 3))
+    return dict(q=q, qd=qd, qdd=qdd, tau=tau, F=F.reshape(n, nf * fd), dt=dt)

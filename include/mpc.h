@@ -455,6 +455,71 @@ const char* mpc_last_error(void);
 /* Library version string. */
 const char* mpc_version(void);
 
+/* ---------------------------------------------------------------------------
+ * The real-time iteration's front and back end (Alg. 1's f_KKT and f_RNEA) on
+ * a kinematic tree: one degree of freedom per body, bodies in topological
+ * order, the first six a chain of three prismatic joints along the world axes
+ * and three revolute joints (the floating base, so every coordinate is
+ * additive), the others revolute or prismatic joints hanging from earlier
+ * bodies.  A joint's frame sits at its offset in the parent frame with the
+ * parent's orientation; a revolute joint rotates the body about its axis by
+ * q, a prismatic one moves it along the axis.  Feet carry world-frame wrenches
+ * at a contact point (force, then moment for foot_dim = 6).  State x = (q, qd)
+ * (nx = 2 n_bodies), input u = (joint torques, foot wrenches) -- the QP's
+ * layouts.  All arrays FP64, device memory; model arrays on the host.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_bodies;           /* 7..24                                              */
+  int32_t n_feet, foot_dim;   /* <= 8 feet, foot_dim 3 or 6                         */
+  double gravity;             /* along -z of the world                              */
+  const int32_t* parent;      /* [n] (-1 for body 0)                                */
+  const int32_t* joint_type;  /* [n] 0 revolute, 1 prismatic                        */
+  const double* axis;         /* [n][3] unit joint axes                             */
+  const double* offset;       /* [n][3] joint frame origin in the parent frame      */
+  const double* mass;         /* [n]                                                */
+  const double* com;          /* [n][3] centre of mass, body frame                  */
+  const double* inertia;      /* [n][3] principal inertia about the centre of mass  */
+  const int32_t* foot_body;   /* [n_feet]                                           */
+  const double* foot_offset;  /* [n_feet][3] contact point, foot body frame         */
+} mpc_model_desc;
+
+typedef struct mpc_model_s* mpc_model_t;
+
+/* Validate the tree and copy it to the device (one allocation, freed by
+ * mpc_model_destroy, which waits for the device first).  INVALID_ARG for a
+ * malformed tree (order, joint types, axes, a non-positive mass or inertia
+ * from the sixth body on, a negative one before, feet on the base),
+ * UNSUPPORTED_SHAPE for one outside the size limits. */
+mpc_status mpc_model_create(const mpc_model_desc* desc, int32_t device, mpc_model_t* out);
+mpc_status mpc_model_destroy(mpc_model_t model);
+
+/* Eq. (rnea): tau = M(q) qdd + h(q, qd) - J(q)' F for count configurations
+ * (q, qd, qdd, tau [count][n], F [count][n_feet*foot_dim] or NULL). */
+mpc_status mpc_rnea(mpc_model_t model, int32_t count, const double* q, const double* qd,
+                    const double* qdd, const double* F, double* tau, void* stream);
+
+/* f_KKT of Alg. 1: the QP data of every stage about (x_k, u_k), k = 0..N-1,
+ * of the semi-implicit Euler step of Eq. (mpc_formulation) (qd+ = qd + dt
+ * qdd(q, qd, u), q+ = q + dt qd+, qdd from M qdd = S'tau + J'F - h):
+ * A_k = df/dx, B_k = df/du by central differences (step 1e-5), c_k = f(x_k, u_k)
+ * - A_k x_k - B_k u_k.  x [n][N][nx], u [n][N][nu]; A [n][N][nx][nx],
+ * B [n][N][nx][nu], c [n][N][nx] -- the plan's layouts for agents of one shape.
+ * status [n] (cleared by the caller): an agent with a non-finite x_k or u_k
+ * gets MPC_AGENT_NONFINITE, else one whose mass matrix fails to factor at an
+ * evaluated point MPC_AGENT_NOT_PD; its A, B, c are then not meaningful. */
+mpc_status mpc_linearize(mpc_model_t model, int32_t n_agents, int32_t N, double dt, const double* x,
+                         const double* u, double* A, double* B, double* c, int32_t* status,
+                         void* stream);
+
+/* f_RNEA and Eq. (mpc_torque): from the first stage of a QP solution (x0 = x*_0,
+ * x1 = x*_1 [count][nx], u0 = u*_0 [count][nu]), qdd* = (qd*_1 - qd*_0) / dt,
+ * tau_rnea = RNEA(q*_0, qd*_0, qdd*, F*) with F* the wrench part of u*_0, and
+ * the joint torques tau = kp (q*_0 - q) + kd (qd*_0 - qd) + tau_rnea
+ * ([count][n_bodies - 6]; q, qd [count][n] the measured state). */
+mpc_status mpc_rti_torque(mpc_model_t model, int32_t count, double dt, double kp, double kd,
+                          const double* x0, const double* x1, const double* u0, const double* q,
+                          const double* qd, double* tau, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

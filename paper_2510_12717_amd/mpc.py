@@ -67,6 +67,15 @@ class ServerStats(ctypes.Structure):
         "resident_controllers", "resident_bytes", "arena_bytes", "arena_free_bytes", "superseded")]
 
 
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("n_bodies", ctypes.c_int32), ("n_feet", ctypes.c_int32),
+                ("foot_dim", ctypes.c_int32), ("gravity", ctypes.c_double),
+                ("parent", ctypes.c_void_p), ("joint_type", ctypes.c_void_p),
+                ("axis", ctypes.c_void_p), ("offset", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("com", ctypes.c_void_p), ("inertia", ctypes.c_void_p),
+                ("foot_body", ctypes.c_void_p), ("foot_offset", ctypes.c_void_p)]
+
+
 class Solution(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "x", "u", "z", "y", "objective",
                                                "residuals", "status", "zx", "yx", "zc", "yc", "zd",
@@ -83,7 +92,8 @@ EXPORTS = ("mpc_plan_desc_default", "mpc_plan_create", "mpc_plan_destroy", "mpc_
            "mpc_server_desc_default", "mpc_server_create", "mpc_server_destroy",
            "mpc_server_clock", "mpc_server_submit", "mpc_server_submit_many", "mpc_server_poll",
            "mpc_server_drain", "mpc_server_get_state", "mpc_server_get_stats",
-           "mpc_solve_noalloc", "mpc_last_error", "mpc_version")
+           "mpc_solve_noalloc", "mpc_model_create", "mpc_model_destroy", "mpc_rnea",
+           "mpc_linearize", "mpc_rti_torque", "mpc_last_error", "mpc_version")
 
 _lib = None
 
@@ -134,6 +144,14 @@ def lib():
         L.mpc_server_get_stats.argtypes = [V, P(ServerStats)]
         L.mpc_solve_noalloc.argtypes = [P(PlanDesc), P(ProblemBatch), P(Solution), V]
         L.mpc_solve_noalloc.restype = ctypes.c_int
+        L.mpc_model_create.argtypes = [P(ModelDesc), I32, P(V)]
+        L.mpc_model_destroy.argtypes = [V]
+        L.mpc_rnea.argtypes = [V, I32, V, V, V, V, V, V]
+        L.mpc_linearize.argtypes = [V, I32, I32, D, V, V, V, V, V, V, V]
+        L.mpc_rti_torque.argtypes = [V, I32, D, D, D, V, V, V, V, V, V, V]
+        for f in ("mpc_model_create", "mpc_model_destroy", "mpc_rnea", "mpc_linearize",
+                  "mpc_rti_torque"):
+            getattr(L, f).restype = ctypes.c_int
         for f in ("mpc_server_create", "mpc_server_destroy", "mpc_server_submit",
                   "mpc_server_submit_many", "mpc_server_poll", "mpc_server_drain",
                   "mpc_server_get_state", "mpc_server_get_stats"):
@@ -540,3 +558,81 @@ class Server:
         st = ServerStats()
         _check(lib().mpc_server_get_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+
+class RobotModel:
+    """A kinematic tree on the device (``mpc_model_create``) with the real-time
+    iteration's front and back end: ``rnea`` (Eq. (rnea)), ``linearize``
+    (f_KKT of Alg. 1: A_k, B_k, c_k of the semi-implicit Euler step about a
+    trajectory) and ``rti_torque`` (f_RNEA and Eq. (mpc_torque)).  ``model`` is
+    a dict with the fields of ``synth.articulated_model``; arrays are FP64 device
+    tensors."""
+
+    def __init__(self, model, device: int = 0):
+        L = lib()
+        n = int(model["n"])
+        self.n = n
+        self.n_feet = len(model["foot_body"])
+        self.foot_dim = int(model["foot_dim"])
+        self.nx = 2 * n
+        self.nj = n - 6
+        self.nu = self.nj + self.n_feet * self.foot_dim
+        f64 = lambda a, k: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, k))
+        i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+        self._keep = dict(parent=i32(model["parent"]), jtype=i32(model["jtype"]),
+                          axis=f64(model["axis"], 3), offset=f64(model["offset"], 3),
+                          mass=f64(model["mass"], 1), com=f64(model["com"], 3),
+                          inertia=f64(model["inertia"], 3),
+                          foot_body=i32(model["foot_body"]),
+                          foot_offset=f64(model["foot_offset"], 3))
+        k = self._keep
+        d = ModelDesc()
+        d.n_bodies, d.n_feet, d.foot_dim = n, self.n_feet, self.foot_dim
+        d.gravity = float(model["gravity"])
+        d.parent, d.joint_type = k["parent"].ctypes.data, k["jtype"].ctypes.data
+        d.axis, d.offset, d.mass = k["axis"].ctypes.data, k["offset"].ctypes.data, k["mass"].ctypes.data
+        d.com, d.inertia = k["com"].ctypes.data, k["inertia"].ctypes.data
+        d.foot_body = k["foot_body"].ctypes.data if self.n_feet else None
+        d.foot_offset = k["foot_offset"].ctypes.data if self.n_feet else None
+        h = ctypes.c_void_p()
+        _check(L.mpc_model_create(ctypes.byref(d), int(device), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().mpc_model_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rnea(self, q, qd, qdd, F=None, stream=None):
+        import torch
+        tau = torch.empty_like(q)
+        _check(lib().mpc_rnea(self._h, int(q.shape[0]), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(F),
+                              _ptr(tau), _stream_handle(stream)))
+        return tau
+
+    def linearize(self, x, u, dt: float, stream=None):
+        """x [n_agents, N, nx], u [n_agents, N, nu] -> A, B, c, status."""
+        import torch
+        na, N = int(x.shape[0]), int(x.shape[1])
+        dev = x.device
+        A = torch.empty((na, N, self.nx, self.nx), dtype=torch.float64, device=dev)
+        B = torch.empty((na, N, self.nx, self.nu), dtype=torch.float64, device=dev)
+        c = torch.empty((na, N, self.nx), dtype=torch.float64, device=dev)
+        status = torch.zeros(na, dtype=torch.int32, device=dev)
+        _check(lib().mpc_linearize(self._h, na, N, float(dt), _ptr(x), _ptr(u), _ptr(A), _ptr(B),
+                                   _ptr(c), _ptr(status), _stream_handle(stream)))
+        return A, B, c, status
+
+    def rti_torque(self, dt: float, kp: float, kd: float, x0, x1, u0, q, qd, stream=None):
+        import torch
+        tau = torch.empty((int(x0.shape[0]), self.nj), dtype=torch.float64, device=x0.device)
+        _check(lib().mpc_rti_torque(self._h, int(x0.shape[0]), float(dt), float(kp), float(kd),
+                                    _ptr(x0), _ptr(x1), _ptr(u0), _ptr(q), _ptr(qd), _ptr(tau),
+                                    _stream_handle(stream)))
+        return tau

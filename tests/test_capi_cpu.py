@@ -120,3 +120,59 @@ def test_server_rejects_bad_descriptions():
         h = ctypes.c_void_p()
         assert L.mpc_server_create(ctypes.byref(dd), ctypes.byref(h)) == mpc.MPC_ERR_INVALID_ARG
         assert not h.value
+
+
+def _model_error(**over):
+    m = dict(synth.articulated_model("quadruped", seed=3))
+    for k, v in over.items():
+        m[k] = v(m) if callable(v) else v
+    with pytest.raises(mpc.MPCError) as e:
+        mpc.RobotModel(m)
+    return e.value.code, str(e.value)
+
+
+def _set(key, idx, val):
+    def f(m):
+        a = np.array(m[key], copy=True)
+        a[idx] = val
+        return a
+    return f
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(parent=_set("parent", 9, 12)), mpc.MPC_ERR_INVALID_ARG),     # parent after child
+    (dict(parent=_set("parent", 3, 1)), mpc.MPC_ERR_INVALID_ARG),      # base not a chain
+    (dict(parent=_set("parent", 7, 2)), mpc.MPC_ERR_INVALID_ARG),      # limb on a base frame
+    (dict(jtype=_set("jtype", 8, 2)), mpc.MPC_ERR_INVALID_ARG),
+    (dict(axis=_set("axis", (8, 0), 2.0)), mpc.MPC_ERR_INVALID_ARG),   # not a unit axis
+    (dict(mass=_set("mass", 5, 0.0)), mpc.MPC_ERR_INVALID_ARG),        # massless base body
+    (dict(mass=_set("mass", 2, -1.0)), mpc.MPC_ERR_INVALID_ARG),
+    (dict(inertia=_set("inertia", (9, 1), np.nan)), mpc.MPC_ERR_INVALID_ARG),
+    (dict(foot_body=_set("foot_body", 0, 4)), mpc.MPC_ERR_INVALID_ARG),
+    (dict(foot_dim=4), mpc.MPC_ERR_UNSUPPORTED_SHAPE),
+])
+def test_robot_model_rejected_before_the_device(over, code):
+    """mpc_model_create validates the tree on the host, before any HIP call
+    (here there is no device, so a valid tree would fail at hipSetDevice)."""
+    rc, msg = _model_error(**over)
+    assert rc == code, msg
+
+
+def test_robot_model_size_limits():
+    m = synth.articulated_model("humanoid", seed=3)
+    big = {k: (np.concatenate([v, v[6:8]]) if isinstance(v, np.ndarray) and len(v) == m["n"] else v)
+           for k, v in m.items()}
+    big["n"] = m["n"] + 2  # 26 bodies
+    with pytest.raises(mpc.MPCError) as e:
+        mpc.RobotModel(big)
+    assert e.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE
+
+
+def test_rigid_body_calls_reject_null_model():
+    L = mpc.lib()
+    assert L.mpc_model_destroy(None) == mpc.MPC_ERR_INVALID_ARG
+    assert L.mpc_rnea(None, 1, None, None, None, None, None, None) == mpc.MPC_ERR_INVALID_ARG
+    assert L.mpc_linearize(None, 1, 10, 0.02, None, None, None, None, None, None,
+                           None) == mpc.MPC_ERR_INVALID_ARG
+    assert L.mpc_rti_torque(None, 1, 0.02, 1.0, 1.0, None, None, None, None, None, None,
+                            None) == mpc.MPC_ERR_INVALID_ARG

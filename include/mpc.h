@@ -501,8 +501,8 @@ mpc_status mpc_rnea(mpc_model_t model, int32_t count, const double* q, const dou
 /* f_KKT of Alg. 1: the QP data of every stage about (x_k, u_k), k = 0..N-1,
  * of the semi-implicit Euler step of Eq. (mpc_formulation) (qd+ = qd + dt
  * qdd(q, qd, u), q+ = q + dt qd+, qdd from M qdd = S'tau + J'F - h):
- * A_k = df/dx, B_k = df/du by central differences (step 1e-5), c_k = f(x_k, u_k)
- * - A_k x_k - B_k u_k.  x [n][N][nx], u [n][N][nu]; A [n][N][nx][nx],
+ * A_k = df/dx and B_k = df/du exactly (the derivatives of inverse dynamics in
+ * closed form, mapped through M^-1), c_k = f(x_k, u_k) - A_k x_k - B_k u_k.  x [n][N][nx], u [n][N][nu]; A [n][N][nx][nx],
  * B [n][N][nx][nu], c [n][N][nx] -- the plan's layouts for agents of one shape.
  * status [n] (cleared by the caller): an agent with a non-finite x_k or u_k
  * gets MPC_AGENT_NONFINITE, else one whose mass matrix fails to factor at an

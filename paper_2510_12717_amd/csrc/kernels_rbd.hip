@@ -3,12 +3,12 @@
 //
 //   k_rnea        : inverse dynamics (Eq. (rnea)) M(q) qdd + h(q, qd) - J(q)' F,
 //                   one thread per configuration;
-//   k_linearize   : the QP data of every stage of every agent, A_k = df/dx and
-//                   B_k = df/du of the semi-implicit Euler step of
-//                   Eq. (mpc_formulation) by central differences, one thread
-//                   per (agent, stage, column) evaluating the step twice, and
-//                   f(x_k, u_k) itself; k_lin_offset then forms
-//                   c_k = f(x_k, u_k) - A_k x_k - B_k u_k;
+//   k_linearize   : the QP data of every stage of every agent, A_k = df/dx,
+//                   B_k = df/du and c_k = f(x_k, u_k) - A_k x_k - B_k u_k of the
+//                   semi-implicit Euler step of Eq. (mpc_formulation), one
+//                   workgroup per (agent, stage): mass matrix, forward dynamics
+//                   and the derivatives of inverse dynamics in closed form from
+//                   the tree's world-frame composite quantities, in LDS;
 //   k_rti_torque  : Eq. (mpc_torque), tau = Kp (q* - q) + Kd (qd* - qd) + tau_rnea
 //                   for the joints, tau_rnea from the first stage of the QP
 //                   solution (qdd* = (qd*_1 - qd*_0) / dt, F* = the wrench part of u*_0).
@@ -178,144 +178,376 @@ __device__ void rnea_dev(const ModelDev& md, const double* q, const double* qd, 
   }
 }
 
-// Spatial inertia (6x6, row-major) of body i at its origin.
-__device__ inline void inertia6(const ModelDev& md, int i, double* I) {
-  const double m = md.mass[i];
-  const V3 c = ld3(md.com + 3 * i), J = ld3(md.inertia + 3 * i);
-  const double C[9] = {0, -c.z, c.y, c.z, 0, -c.x, -c.y, c.x, 0};
-  for (int u = 0; u < 3; ++u)
-    for (int v = 0; v < 3; ++v) {
-      double cc = 0;  // (C C')_uv
-      for (int t = 0; t < 3; ++t) cc += C[3 * u + t] * C[3 * v + t];
-      I[6 * u + v] = (u == v ? (u == 0 ? J.x : u == 1 ? J.y : J.z) : 0.0) + m * cc;
-      I[6 * u + 3 + v] = m * C[3 * u + v];
-      I[6 * (3 + u) + v] = m * C[3 * v + u];
-      I[6 * (3 + u) + 3 + v] = u == v ? m : 0.0;
-    }
+// ---- world-frame spatial algebra for the linearisation -----------------------
+// A 6-vector is (angular, linear) for motions and (moment, force) for forces,
+// all about the world origin.
+struct S6 {
+  V3 a, b;
+};
+__device__ inline S6 s6(V3 a, V3 b) { return S6{a, b}; }
+__device__ inline S6 operator+(S6 x, S6 y) { return s6(x.a + y.a, x.b + y.b); }
+__device__ inline S6 operator-(S6 x, S6 y) { return s6(x.a - y.a, x.b - y.b); }
+__device__ inline S6 operator*(double t, S6 x) { return s6(t * x.a, t * x.b); }
+__device__ inline S6 ld6(const double* p) { return s6(ld3(p), ld3(p + 3)); }
+__device__ inline void st6(double* p, S6 x) {
+  p[0] = x.a.x; p[1] = x.a.y; p[2] = x.a.z;
+  p[3] = x.b.x; p[4] = x.b.y; p[5] = x.b.z;
+}
+// m x n (motion on motion) and m x* f (motion on force)
+__device__ inline S6 crm(S6 m, S6 n) { return s6(cross(m.a, n.a), cross(m.a, n.b) + cross(m.b, n.a)); }
+__device__ inline S6 crf(S6 m, S6 f) { return s6(cross(m.a, f.a) + cross(m.b, f.b), cross(m.a, f.b)); }
+__device__ inline double dot6(S6 m, S6 f) { return dot(m.a, f.a) + dot(m.b, f.b); }
+// 6x6 row-major matrix times a 6-vector
+__device__ inline S6 mul6(const double* M, S6 x) {
+  const double in[6] = {x.a.x, x.a.y, x.a.z, x.b.x, x.b.y, x.b.z};
+  double o[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t += M[6 * r + c] * in[c];
+    o[r] = t;
+  }
+  return s6(v3(o[0], o[1], o[2]), v3(o[3], o[4], o[5]));
 }
 
-// 6x6 motion transform of (E, r): [E 0; -E r^ E].
-__device__ inline void xform6(const M3& E, V3 r, double* X) {
-  const double R[9] = {0, -r.z, r.y, r.z, 0, -r.x, -r.y, r.x, 0};
-  for (int u = 0; u < 3; ++u)
-    for (int v = 0; v < 3; ++v) {
-      double er = 0;
-      for (int t = 0; t < 3; ++t) er += E.m[3 * u + t] * R[3 * t + v];
-      X[6 * u + v] = E.m[3 * u + v];
-      X[6 * u + 3 + v] = 0.0;
-      X[6 * (3 + u) + v] = -er;
-      X[6 * (3 + u) + 3 + v] = E.m[3 * u + v];
-    }
-}
-
-// Mass matrix by the composite-rigid-body algorithm into M (n x n, row-major).
-// Transforms are kept as (E, r) and expanded to 6x6 one at a time.
-__device__ void crba_dev(const ModelDev& md, const double* q, double* M) {
-  const int n = md.n;
-  double Ic[kMaxBodies][36];
-  M3 Eb[kMaxBodies];
-  V3 rb[kMaxBodies];
-  for (int i = 0; i < n; ++i) {
-    joint_xform(md, i, q[i], Eb[i], rb[i]);
-    inertia6(md, i, Ic[i]);
-  }
-  // bodies on different branches couple through no joint: their entries stay 0
-  for (int k = 0; k < n * n; ++k) M[k] = 0.0;
-  double X[36];
-  for (int i = n - 1; i >= 0; --i) {
-    const int par = md.parent[i];
-    if (par < 0) continue;
-    xform6(Eb[i], rb[i], X);
-    // Ic_par += X' Ic X
-    double T[36];
-    for (int u = 0; u < 6; ++u)
-      for (int v = 0; v < 6; ++v) {
-        double s = 0;
-        for (int t = 0; t < 6; ++t) s += Ic[i][6 * u + t] * X[6 * t + v];
-        T[6 * u + v] = s;
-      }
-    for (int u = 0; u < 6; ++u)
-      for (int v = 0; v < 6; ++v) {
-        double s = 0;
-        for (int t = 0; t < 6; ++t) s += X[6 * t + u] * T[6 * t + v];
-        Ic[par][6 * u + v] += s;
-      }
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double S[6] = {0, 0, 0, 0, 0, 0};
-    const V3 ax = ld3(md.axis + 3 * i);
-    const int o = md.jtype[i] == 1 ? 3 : 0;
-    S[o] = ax.x;
-    S[o + 1] = ax.y;
-    S[o + 2] = ax.z;
-    // F = Ic S as a force (n, f), carried to the ancestors by X' (n, f) =
-    // (E'n + r x E'f, E'f)
-    V3 fn = v3(0, 0, 0), ff = v3(0, 0, 0);
-    {
-      double Fv[6];
-      for (int u = 0; u < 6; ++u) {
-        double s = 0;
-        for (int t = 0; t < 6; ++t) s += Ic[i][6 * u + t] * S[t];
-        Fv[u] = s;
-      }
-      fn = v3(Fv[0], Fv[1], Fv[2]);
-      ff = v3(Fv[3], Fv[4], Fv[5]);
-    }
-    M[i * n + i] = md.jtype[i] == 1 ? dot(ax, ff) : dot(ax, fn);
-    int j = i;
-    while (md.parent[j] >= 0) {
-      const V3 fp = mulT(Eb[j], ff);
-      fn = mulT(Eb[j], fn) + cross(rb[j], fp);
-      ff = fp;
-      j = md.parent[j];
-      const V3 aj = ld3(md.axis + 3 * j);
-      const double mij = md.jtype[j] == 1 ? dot(aj, ff) : dot(aj, fn);
-      M[i * n + j] = mij;
-      M[j * n + i] = mij;
-    }
+// Body i's placement relative to its parent at joint value qi: rotation (body
+// axes in parent coordinates) and origin.
+__device__ inline void joint_local(const ModelDev& md, int i, double qi, M3& R, V3& p) {
+  const V3 a = ld3(md.axis + 3 * i), off = ld3(md.offset + 3 * i);
+  if (md.jtype[i] == 1) {
+    for (int k = 0; k < 9; ++k) R.m[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    p = off + qi * a;
+  } else {
+    R = axis_rotation(a, qi);
+    p = off;
   }
 }
 
-// Semi-implicit Euler step f(x, u) into xn (x = (q, qd), u = (joint torques,
-// foot wrenches)).  Returns false if M is not positive definite.
-__device__ bool step_dev(const ModelDev& md, const double* x, const double* u, double dt, double* xn) {
-  const int n = md.n, nj = md.n - 6;
-  double M[kMaxBodies * kMaxBodies];
-  double b[kMaxBodies], z[kMaxBodies];
-  for (int i = 0; i < n; ++i) z[i] = 0.0;
-  crba_dev(md, x, M);
-  // b = S' tau - (h - J'F) = S' tau - rnea(q, qd, 0, F)
-  rnea_dev(md, x, x + n, z, u + nj, b);
-  for (int i = 0; i < n; ++i) b[i] = (i >= 6 ? u[i - 6] : 0.0) - b[i];
-  // Cholesky M = L L' in place (lower), then two substitutions
+constexpr int kLinThreads = 128;
+constexpr int kMaxCols = 2 * kMaxBodies + kMaxU;  // x and u columns
+constexpr int kMaxFeet = 8;
+
+// Shared state of one stage's linearisation (world frame, per body).
+struct LinLds {
+  double S[kMaxBodies][6];      // joint motion subspace
+  double v[kMaxBodies][6];      // velocity
+  double a[kMaxBodies][6];      // acceleration: qdd = 0 first, then qdd = qdd0
+  double Io[kMaxBodies][36];    // own spatial inertia
+  double IC[kMaxBodies][36];    // composite inertia of the subtree
+  double BC[kMaxBodies][36];    // composite of v x* I - I v x
+  double hC[kMaxBodies][6];     // composite momentum
+  double fC[kMaxBodies][6];     // composite force, feet's wrenches subtracted
+  double fiC[kMaxBodies][6];    // composite force of the bodies alone
+  double M[kMaxBodies * kMaxBodies];  // mass matrix, then its Cholesky factor below the diagonal
+  double Ld[kMaxBodies];        // the factor's diagonal
+  double qdd[kMaxBodies];       // generalised force, then qdd0
+  double z[kMaxCols];           // (x, u) of the stage
+  double D[kMaxBodies][kMaxCols];  // d qdd / d(x, u), column per thread
+  double pf[kMaxFeet][3];       // contact points, world
+  uint32_t anc[kMaxBodies];     // ancestors of body i, itself included
+  int bad;                      // 1 non-finite input, 2 mass matrix not positive definite
+};
+
+// One workgroup per (agent, stage): the derivatives of forward dynamics from
+// those of inverse dynamics, d qdd / d x = -M^-1 d ID / d x at qdd = qdd0 and
+// d qdd / d u = M^-1 d(S'tau + J'F) / d u, with d ID / d q and d ID / d qd in
+// closed form from the tree's composite quantities: moving coordinate j moves
+// its subtree rigidly along S_j, so each world-frame quantity of the subtree
+// changes by S_j x (.), apart from terms through the parent's velocity and
+// acceleration, which do not move, and the feet's world-fixed wrenches.
+__global__ void __launch_bounds__(kLinThreads)
+k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const double* __restrict__ U,
+            double* __restrict__ A, double* __restrict__ B, double* __restrict__ C,
+            int32_t* __restrict__ status) {
+  __shared__ LinLds L;
+  const int tid = threadIdx.x;
+  const int n = md.n, nx = 2 * n, nj = n - 6, nf = md.n_feet, fd = md.foot_dim;
+  const int nu = nj + nf * fd, ncol = nx + nu;
+  const int64_t ak = blockIdx.x;  // agent * N + stage
+  const S6 a_root = s6(v3(0, 0, 0), v3(0, 0, md.gravity));
+  const double* q = L.z;
+  const double* qd = L.z + n;
+  const double* F = L.z + nx + nj;
+
+  if (tid == 0) L.bad = 0;
+  __syncthreads();
+  if (tid < ncol) {
+    const double val = tid < nx ? X[ak * nx + tid] : U[ak * nu + tid - nx];
+    L.z[tid] = val;
+    if (!isfinite(val)) L.bad = 1;
+  }
+  if (tid < n) {
+    uint32_t m = 1u << tid;
+    for (int k = md.parent[tid]; k >= 0; k = md.parent[k]) m |= 1u << k;
+    L.anc[tid] = m;
+  }
+  __syncthreads();
+  if (L.bad) {
+    if (tid == 0) atomicMax(status + ak / N, (int32_t)AGENT_NONFINITE);
+    return;
+  }
+  // (1) world placement, motion subspace and inertia of body tid
+  if (tid < n) {
+    const int i = tid;
+    M3 R;
+    V3 p;
+    joint_local(md, i, q[i], R, p);
+    for (int k = md.parent[i]; k >= 0; k = md.parent[k]) {
+      M3 Rk;
+      V3 pk;
+      joint_local(md, k, q[k], Rk, pk);
+      p = pk + mul(Rk, p);
+      R = mulM(Rk, R);
+    }
+    const V3 ax = mul(R, ld3(md.axis + 3 * i));
+    st6(L.S[i], md.jtype[i] == 1 ? s6(v3(0, 0, 0), ax) : s6(ax, cross(p, ax)));
+    const double m = md.mass[i];
+    const V3 c = p + mul(R, ld3(md.com + 3 * i));
+    const V3 J = ld3(md.inertia + 3 * i);
+    double* I = L.Io[i];
+    for (int u = 0; u < 3; ++u)
+      for (int w = 0; w < 3; ++w) {
+        // R diag(J) R' + m [c]x [c]x'
+        double r = R.m[3 * u] * J.x * R.m[3 * w] + R.m[3 * u + 1] * J.y * R.m[3 * w + 1] +
+                   R.m[3 * u + 2] * J.z * R.m[3 * w + 2];
+        const double cu[3] = {c.x, c.y, c.z};
+        r += m * ((u == w ? dot(c, c) : 0.0) - cu[u] * cu[w]);
+        I[6 * u + w] = r;
+        I[6 * (3 + u) + 3 + w] = u == w ? m : 0.0;
+      }
+    // m [c]x top right, its transpose bottom left
+    const double cx[9] = {0, -c.z, c.y, c.z, 0, -c.x, -c.y, c.x, 0};
+    for (int u = 0; u < 3; ++u)
+      for (int w = 0; w < 3; ++w) {
+        I[6 * u + 3 + w] = m * cx[3 * u + w];
+        I[6 * (3 + u) + w] = m * cx[3 * w + u];
+      }
+    for (int f = 0; f < nf; ++f)
+      if (md.foot_body[f] == i) {
+        const V3 pt = p + mul(R, ld3(md.foot_offset + 3 * f));
+        L.pf[f][0] = pt.x;
+        L.pf[f][1] = pt.y;
+        L.pf[f][2] = pt.z;
+      }
+  }
+  __syncthreads();
+  // (2) velocities
+  if (tid < n) {
+    S6 v = s6(v3(0, 0, 0), v3(0, 0, 0));
+    for (int k = 0; k <= tid; ++k)
+      if (L.anc[tid] >> k & 1u) v = v + qd[k] * ld6(L.S[k]);
+    st6(L.v[tid], v);
+  }
+  __syncthreads();
+  // (3) accelerations at qdd = 0, own forces, momenta and B = v x* I - I v x
+  auto ext = [&](int i) {  // the feet's wrenches on body i
+    S6 w = s6(v3(0, 0, 0), v3(0, 0, 0));
+    for (int f = 0; f < nf; ++f)
+      if (md.foot_body[f] == i) {
+        const V3 force = ld3(F + f * fd);
+        const V3 mom = fd == 6 ? ld3(F + f * fd + 3) : v3(0, 0, 0);
+        w = w + s6(mom + cross(ld3(L.pf[f]), force), force);
+      }
+    return w;
+  };
+  if (tid < n) {
+    const int i = tid;
+    S6 a0 = a_root;
+    for (int k = 0; k <= i; ++k)
+      if (L.anc[i] >> k & 1u) a0 = a0 + qd[k] * crm(ld6(L.v[k]), ld6(L.S[k]));
+    const S6 v = ld6(L.v[i]);
+    const S6 h = mul6(L.Io[i], v);
+    st6(L.a[i], a0);
+    st6(L.hC[i], h);
+    st6(L.fC[i], mul6(L.Io[i], a0) + crf(v, h) - ext(i));
+    for (int c = 0; c < 6; ++c) {
+      S6 e = s6(v3(0, 0, 0), v3(0, 0, 0));
+      if (c < 3) (c == 0 ? e.a.x : c == 1 ? e.a.y : e.a.z) = 1.0;
+      else (c == 3 ? e.b.x : c == 4 ? e.b.y : e.b.z) = 1.0;
+      const S6 Ie = mul6(L.Io[i], e);
+      const S6 col = crf(v, Ie) - mul6(L.Io[i], crm(v, e));
+      const double cc[6] = {col.a.x, col.a.y, col.a.z, col.b.x, col.b.y, col.b.z};
+      for (int r = 0; r < 6; ++r) L.BC[i][6 * r + c] = cc[r];
+    }
+    for (int e = 0; e < 36; ++e) L.IC[i][e] = L.Io[i][e];
+  }
+  __syncthreads();
+  // (4) composites over subtrees (children come after their parents): one
+  // thread per entry, bodies in reverse order
+  if (tid < 84) {
+    double* base;
+    int stride, e;
+    if (tid < 36) { base = &L.IC[0][0]; stride = 36; e = tid; }
+    else if (tid < 72) { base = &L.BC[0][0]; stride = 36; e = tid - 36; }
+    else if (tid < 78) { base = &L.hC[0][0]; stride = 6; e = tid - 72; }
+    else { base = &L.fC[0][0]; stride = 6; e = tid - 78; }
+    for (int i = n - 1; i > 0; --i) {
+      const int par = md.parent[i];
+      if (par >= 0) base[par * stride + e] += base[i * stride + e];
+    }
+  }
+  __syncthreads();
+  // (5) mass matrix M_ij = S_i' IC_j S_j (i an ancestor of j) and the
+  // generalised force S'tau - ID(q, qd, 0, F)
+  for (int idx = tid; idx < n * n; idx += kLinThreads) {
+    const int i = idx / n, j = idx % n;
+    double val = 0.0;
+    if (L.anc[j] >> i & 1u) val = dot6(ld6(L.S[i]), mul6(L.IC[j], ld6(L.S[j])));
+    else if (L.anc[i] >> j & 1u) val = dot6(ld6(L.S[j]), mul6(L.IC[i], ld6(L.S[i])));
+    L.M[idx] = val;
+  }
+  if (tid < n) L.qdd[tid] = (tid >= 6 ? L.z[nx + tid - 6] : 0.0) - dot6(ld6(L.S[tid]), ld6(L.fC[tid]));
+  __syncthreads();
+  // (6) Cholesky factor, column by column (every thread forms the same pivot)
   for (int j = 0; j < n; ++j) {
-    double s = M[j * n + j];
-    for (int t = 0; t < j; ++t) s -= M[j * n + t] * M[j * n + t];
-    if (!(s > 0.0)) return false;
-    const double l = sqrt(s);
-    M[j * n + j] = l;
-    for (int i = j + 1; i < n; ++i) {
-      double v = M[i * n + j];
-      for (int t = 0; t < j; ++t) v -= M[i * n + t] * M[j * n + t];
-      M[i * n + j] = v / l;
+    double d = L.M[j * n + j];
+    for (int t = 0; t < j; ++t) d -= L.M[j * n + t] * L.M[j * n + t];
+    if (!(d > 0.0)) {
+      if (tid == 0) atomicMax(status + ak / N, (int32_t)AGENT_NOT_PD);
+      return;
+    }
+    const double l = sqrt(d);
+    const int i = j + 1 + tid;
+    if (i < n) {
+      double s = L.M[i * n + j];
+      for (int t = 0; t < j; ++t) s -= L.M[i * n + t] * L.M[j * n + t];
+      L.M[i * n + j] = s / l;
+    }
+    if (tid == 0) L.Ld[j] = l;
+    __syncthreads();
+  }
+  // (7) qdd0 = M^-1 (S'tau + J'F - h)
+  if (tid == 0) {
+    for (int i = 0; i < n; ++i) {
+      double s = L.qdd[i];
+      for (int t = 0; t < i; ++t) s -= L.M[i * n + t] * L.qdd[t];
+      L.qdd[i] = s / L.Ld[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = L.qdd[i];
+      for (int t = i + 1; t < n; ++t) s -= L.M[t * n + i] * L.qdd[t];
+      L.qdd[i] = s / L.Ld[i];
     }
   }
-  for (int i = 0; i < n; ++i) {
-    double s = b[i];
-    for (int t = 0; t < i; ++t) s -= M[i * n + t] * b[t];
-    b[i] = s / M[i * n + i];
+  __syncthreads();
+  // (8) accelerations and forces at qdd0
+  if (tid < n) {
+    const int i = tid;
+    S6 a = ld6(L.a[i]);
+    for (int k = 0; k <= i; ++k)
+      if (L.anc[i] >> k & 1u) a = a + L.qdd[k] * ld6(L.S[k]);
+    st6(L.a[i], a);
+    const S6 v = ld6(L.v[i]);
+    const S6 fi = mul6(L.Io[i], a) + crf(v, mul6(L.Io[i], v));
+    st6(L.fiC[i], fi);
+    st6(L.fC[i], fi - ext(i));
   }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = b[i];
-    for (int t = i + 1; t < n; ++t) s -= M[t * n + i] * b[t];
-    b[i] = s / M[i * n + i];
+  __syncthreads();
+  if (tid < 12) {
+    double* base = tid < 6 ? &L.fiC[0][0] : &L.fC[0][0];
+    const int e = tid % 6;
+    for (int i = n - 1; i > 0; --i) {
+      const int par = md.parent[i];
+      if (par >= 0) base[par * 6 + e] += base[i * 6 + e];
+    }
   }
-  for (int i = 0; i < n; ++i) {
-    const double qd1 = x[n + i] + dt * b[i];
-    xn[n + i] = qd1;
-    xn[i] = x[i] + dt * qd1;
+  __syncthreads();
+  // (9) one column of d qdd / d(x, u) per thread
+  if (tid < ncol) {
+    const int t = tid;
+    if (t < nx) {
+      const int j = t % n;
+      const S6 Sj = ld6(L.S[j]);
+      const int par = md.parent[j];
+      const S6 vp = par >= 0 ? ld6(L.v[par]) : s6(v3(0, 0, 0), v3(0, 0, 0));
+      if (t < n) {
+        // d ID / d q_j
+        const S6 ap = par >= 0 ? ld6(L.a[par]) : a_root;
+        const S6 dv = crm(Sj, vp);
+        const S6 al = crm(Sj, ap) - crm(dv, vp);
+        auto psi = [&](int i) {
+          S6 r = crf(Sj, ld6(L.fiC[i])) - mul6(L.IC[i], al) - mul6(L.BC[i], dv) - crf(dv, ld6(L.hC[i]));
+          for (int f = 0; f < nf; ++f) {
+            const int b = md.foot_body[f];
+            if (L.anc[b] >> i & 1u) {  // foot in the subtree of i
+              const V3 pt = ld3(L.pf[f]);
+              r.a = r.a - cross(Sj.b + cross(Sj.a, pt), ld3(F + f * fd));
+            }
+          }
+          return r;
+        };
+        const S6 psij = psi(j);
+        for (int i = 0; i < n; ++i) {
+          double d = 0.0;
+          const S6 Si = ld6(L.S[i]);
+          if (L.anc[i] >> j & 1u) d = dot6(crm(Sj, Si), ld6(L.fC[i])) + dot6(Si, i == j ? psij : psi(i));
+          else if (L.anc[j] >> i & 1u) d = dot6(Si, psij);
+          L.D[i][t] = -d;
+        }
+      } else {
+        // d ID / d qd_j
+        const S6 w = crm(Sj, vp);
+        auto phi = [&](int i) {
+          return mul6(L.BC[i], Sj) + crf(Sj, ld6(L.hC[i])) - 2.0 * mul6(L.IC[i], w);
+        };
+        const S6 phij = phi(j);
+        for (int i = 0; i < n; ++i) {
+          double d = 0.0;
+          const S6 Si = ld6(L.S[i]);
+          if (L.anc[i] >> j & 1u) d = dot6(Si, i == j ? phij : phi(i));
+          else if (L.anc[j] >> i & 1u) d = dot6(Si, phij);
+          L.D[i][t] = -d;
+        }
+      }
+    } else if (t < nx + nj) {
+      for (int i = 0; i < n; ++i) L.D[i][t] = i == 6 + (t - nx) ? 1.0 : 0.0;
+    } else {
+      const int w = t - nx - nj, f = w / fd, comp = w % fd;
+      S6 e = s6(v3(0, 0, 0), v3(0, 0, 0));
+      V3 unit = v3(comp % 3 == 0, comp % 3 == 1, comp % 3 == 2);
+      if (comp < 3) e = s6(cross(ld3(L.pf[f]), unit), unit);
+      else e = s6(unit, v3(0, 0, 0));
+      const uint32_t up = L.anc[md.foot_body[f]];
+      for (int i = 0; i < n; ++i) L.D[i][t] = (up >> i & 1u) ? dot6(ld6(L.S[i]), e) : 0.0;
+    }
+    // M^-1 on the column
+    for (int i = 0; i < n; ++i) {
+      double s = L.D[i][t];
+      for (int k = 0; k < i; ++k) s -= L.M[i * n + k] * L.D[k][t];
+      L.D[i][t] = s / L.Ld[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = L.D[i][t];
+      for (int k = i + 1; k < n; ++k) s -= L.M[k * n + i] * L.D[k][t];
+      L.D[i][t] = s / L.Ld[i];
+    }
+    // q+ = q + dt qd + dt^2 qdd, qd+ = qd + dt qdd
+    const double dt2 = dt * dt;
+    if (t < nx) {
+      double* Ak = A + ak * nx * nx;
+      for (int r = 0; r < n; ++r) {
+        const double dq = L.D[r][t];
+        Ak[r * nx + t] = (r == t ? 1.0 : 0.0) + (r + n == t ? dt : 0.0) + dt2 * dq;
+        Ak[(n + r) * nx + t] = (r + n == t ? 1.0 : 0.0) + dt * dq;
+      }
+    } else {
+      double* Bk = B + ak * nx * nu;
+      const int c = t - nx;
+      for (int r = 0; r < n; ++r) {
+        Bk[r * nu + c] = dt2 * L.D[r][t];
+        Bk[(n + r) * nu + c] = dt * L.D[r][t];
+      }
+    }
   }
-  return true;
+  __syncthreads();
+  // (10) c = f(x, u) - A x - B u = (dt^2 r, dt r), r = qdd0 - D (x, u)
+  if (tid < n) {
+    double r = L.qdd[tid];
+    for (int t = 0; t < ncol; ++t) r -= L.D[tid][t] * L.z[t];
+    C[ak * nx + tid] = dt * dt * r;
+    C[ak * nx + n + tid] = dt * r;
+  }
 }
 
 __global__ void __launch_bounds__(64)
@@ -326,70 +558,6 @@ k_rnea(ModelDev md, int count, const double* __restrict__ q, const double* __res
   const int n = md.n, nf = md.n_feet * md.foot_dim;
   rnea_dev(md, q + (int64_t)t * n, qd + (int64_t)t * n, qdd + (int64_t)t * n,
            F ? F + (int64_t)t * nf : nullptr, tau + (int64_t)t * n);
-}
-
-// Thread (agent, stage, column j): column j < nx + nu of A_k | B_k by central
-// differences with step h; column nx + nu: f(x_k, u_k) itself, into c.
-__global__ void __launch_bounds__(64)
-k_linearize(ModelDev md, int n_agents, int N, double dt, double h, const double* __restrict__ X,
-            const double* __restrict__ U, double* __restrict__ A, double* __restrict__ B,
-            double* __restrict__ C, int32_t* __restrict__ status) {
-  const int nx = 2 * md.n, nu = md.n - 6 + md.n_feet * md.foot_dim, ncol = nx + nu + 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n_agents * N * ncol) return;
-  const int j = (int)(t % ncol);
-  const int64_t ak = t / ncol;  // agent * N + stage
-  const double* x = X + ak * nx;
-  const double* u = U + ak * nu;
-  double xp[2 * kMaxBodies], up[kMaxU], fp[2 * kMaxBodies], fm[2 * kMaxBodies];
-  bool finite = true;
-  for (int i = 0; i < nx; ++i) {
-    xp[i] = x[i];
-    finite = finite && isfinite(xp[i]);
-  }
-  for (int i = 0; i < nu; ++i) {
-    up[i] = u[i];
-    finite = finite && isfinite(up[i]);
-  }
-  // one call site of the step (two evaluations for a column, one for f), so
-  // that the step's private arrays exist once
-  const bool value = j == nx + nu;
-  double* var = value ? nullptr : (j < nx ? xp + j : up + (j - nx));
-  const double v0 = value ? 0.0 : *var;
-  bool ok = true;
-  for (int e = 0; e < (value ? 1 : 2); ++e) {
-    if (!value) *var = e == 0 ? v0 + h : v0 - h;
-    ok = step_dev(md, xp, up, dt, e == 0 ? fp : fm) && ok;
-  }
-  if (value) {
-    for (int i = 0; i < nx; ++i) C[ak * nx + i] = fp[i];
-  } else {
-    const double ih = 0.5 / h;
-    if (j < nx)
-      for (int i = 0; i < nx; ++i) A[(ak * nx + i) * nx + j] = (fp[i] - fm[i]) * ih;
-    else
-      for (int i = 0; i < nx; ++i) B[(ak * nx + i) * nu + (j - nx)] = (fp[i] - fm[i]) * ih;
-  }
-  // a non-finite point outranks a failed factorisation, whichever thread of
-  // the agent writes last
-  if (!finite) atomicMax(status + ak / N, (int32_t)AGENT_NONFINITE);
-  else if (!ok) atomicMax(status + ak / N, (int32_t)AGENT_NOT_PD);
-}
-
-// c_k = f(x_k, u_k) - A_k x_k - B_k u_k (C holds f(x_k, u_k) on entry).
-__global__ void __launch_bounds__(64)
-k_lin_offset(int nx, int nu, int64_t rows, const double* __restrict__ X, const double* __restrict__ U,
-             const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= rows) return;
-  const int64_t ak = t / nx;
-  const int i = (int)(t % nx);
-  const double* x = X + ak * nx;
-  const double* u = U + ak * nu;
-  double s = C[t];
-  for (int k = 0; k < nx; ++k) s -= A[(ak * nx + i) * nx + k] * x[k];
-  for (int k = 0; k < nu; ++k) s -= B[(ak * nx + i) * nu + k] * u[k];
-  C[t] = s;
 }
 
 __global__ void __launch_bounds__(64)
@@ -421,16 +589,10 @@ hipError_t launch_rnea(const ModelDev& md, int count, const double* q, const dou
 hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const double* X,
                             const double* U, double* A, double* B, double* C, int32_t* status,
                             hipStream_t s) {
-  const int nx = 2 * md.n, nu = md.n - 6 + md.n_feet * md.foot_dim;
-  const int64_t threads = (int64_t)n_agents * N * (nx + nu + 1);
-  if (threads <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_linearize, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, md, n_agents, N,
-                     dt, 1e-5, X, U, A, B, C, status);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t rows = (int64_t)n_agents * N * nx;
-  hipLaunchKernelGGL(k_lin_offset, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, nx, nu, rows, X, U,
-                     A, B, C);
+  const int64_t blocks = (int64_t)n_agents * N;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_linearize, dim3((unsigned)blocks), dim3(kLinThreads), 0, s, md, N, dt, X, U, A, B,
+                     C, status);
   return hipGetLastError();
 }
 

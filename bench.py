@@ -85,6 +85,9 @@ def parse():
                          "N=16, Q/R condition 1e6, FP32): plain vs Ruiz vs Ruiz + adaptive rho, step "
                          "time and the error of the fixed-iteration iterate against the converged "
                          "optimum (prints its own JSON line)")
+    ap.add_argument("--rti", action="store_true",
+                    help="time the real-time iteration's control step on the articulated humanoid "
+                         "(linearise, solve, torques, plant step)")
     ap.add_argument("--inner", action="store_true",
                     help="time the two inner solves side by side instead (exact-dynamics Riccati vs the "
                          "paper's KKT LDL^T with finite rho_eq; prints its own JSON line)")
@@ -586,6 +589,119 @@ def serve(args):
     print(json.dumps(out))
 
 
+def rti(args):
+    """The real-time iteration's control step on the N = 10 humanoid workload
+    (4096 agents, --precision io) with the articulated humanoid tree holding
+    its pose (balance costs, both feet in stance): linearise the
+    dynamics about the current solution (mpc_linearize, written into the
+    batch's A, B, c), solve the QP warm-started (mpc_solve), command joint
+    torques from its first stage (mpc_rti_torque), step the plant on the
+    linearised dynamics (mpc_advance_state).  Each part is timed with events on
+    the one stream; the first linearisation is about seeded configurations."""
+    import torch
+
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    n, N = args.agents, args.horizon
+    model = synth.articulated_model("humanoid", seed=3)
+    robot = mpc.RobotModel(model)
+    sh = synth.humanoid(N)
+    prec = args.precision
+    npd = np.float64 if prec == "fp64" else np.float32
+    b = synth.make_batch([sh] * n, seed=0, stream_id=1, dtype=npd)
+    prob = mpc.to_device(b, prec)
+    plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters)
+    st = synth.model_states(model, n * (N + 1), seed=5)
+    X = torch.from_numpy(np.concatenate([st["q"], st["qd"]], 1).reshape(n, N + 1, sh.nx)
+                         .astype(npd)).cuda()
+    U = torch.from_numpy(np.ascontiguousarray(
+        np.concatenate([st["tau"], st["F"]], 1).reshape(n, N + 1, sh.nu)[:, :N]
+        .astype(npd))).cuda()
+    # a balancing task: hold each agent's first configuration at rest (base
+    # height 0.6 m, level, joints at zero), both feet in stance
+    nq = sh.nx // 2
+    hold = X[:, 0].clone()
+    hold[:, 2] = 0.6
+    hold[:, 3:nq] = 0.0
+    hold[:, nq:] = 0.0
+    prob["x_ref"].copy_(hold[:, None, :].expand(n, N + 1, sh.nx).reshape(-1))
+    qw = torch.cat([torch.tensor([10.0, 10.0, 100.0, 100.0, 100.0, 100.0]), torch.full((nq - 6,), 10.0),
+                    torch.ones(nq)]).to(X.dtype)
+    rw = torch.cat([torch.full((sh.n_tau,), 1e-3), torch.full((sh.nu - sh.n_tau,), 1e-5)]).to(X.dtype)
+    prob["q"].copy_(qw.repeat(n))
+    prob["r"].copy_(rw.repeat(n))
+    prob["stance"].fill_(1)
+    prob["tau_max"].fill_(200.0)
+    prob["mu"].fill_(0.8)
+    prob["x0"].copy_(X[:, 0].reshape(-1))
+    sol = mpc.solution_buffers(b.shapes, prec)
+    sol["x"], sol["u"] = X.view(-1), U.view(-1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    noise = torch.empty((args.warmup + args.steps, n * sh.nx), dtype=X.dtype, device="cuda")
+    noise.normal_(0.0, 1e-3, generator=gen)
+    stream = torch.cuda.current_stream()
+    dt, kp, kd = 0.02, 150.0, 5.0
+    parts = ("linearize", "solve", "torque", "advance")
+    acc = {k: 0.0 for k in parts}
+    lin_status = torch.zeros(n, dtype=torch.int32, device="cuda")
+
+    def step(i, warm, timed):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if timed else None
+        if timed:
+            ev[0].record(stream)
+        _, _, _, ls = robot.linearize(X, U, dt, out=(prob["A"], prob["B"], prob["c"]), stream=stream)
+        lin_status.bitwise_or_(ls)
+        if timed:
+            ev[1].record(stream)
+        plan.solve(prob, warm_start=warm, stream=stream)
+        plan.get_solution(stream=stream, out=sol)
+        if timed:
+            ev[2].record(stream)
+        tau = robot.rti_torque(dt, kp, kd, X, U, prob["x0"].view(n, sh.nx), stream=stream)
+        if timed:
+            ev[3].record(stream)
+        plan.advance_state(prob, noise[i], prob["x0"], stream=stream)
+        if timed:
+            ev[4].record(stream)
+        return ev, tau
+
+    bad_by_step = []
+    for i in range(args.warmup):
+        step(i, i > 0, False)
+        bad_by_step.append(int((sol["status"] >= 2).sum()))
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev, tau = step(args.warmup + i, True, True)
+        evs.append(ev)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps * 1e3
+    for ev in evs:
+        for k, name in enumerate(parts):
+            acc[name] += ev[k].elapsed_time(ev[k + 1])
+    status = sol["status"].cpu().numpy()
+    out = {"mode": "rti", "workload": f"humanoid tree (6 + 18 coordinates, two 6D feet), {n} agents, N = {N}",
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
+           "steps_per_s_per_agent": 1e3 / wall,
+           "part_ms": {k: v / args.steps for k, v in acc.items()},
+           "linearize_status_ok": bool(int(lin_status.abs().sum()) == 0),
+           "linearize_status_counts": {str(k): int(v) for k, v in
+                                       zip(*np.unique(lin_status.cpu().numpy(), return_counts=True))},
+           "qp_status_ok": bool(np.isin(status, (0, 1)).all()),
+           "qp_status_counts": {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+           "qp_failed_after_warmup_steps": bad_by_step,
+           "max_abs_x_finite_agents": float(X[torch.isfinite(X).flatten(1).all(1)].abs().max()),
+           "torque_finite": bool(torch.isfinite(tau).all()),
+           "iters": args.iters, "precision": prec,
+           "dtype": ("f64" if prec == "fp64" else "f32 io, f64 dynamics and Riccati factor")}
+    print(json.dumps(out))
+    plan.close()
+    robot.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -603,6 +719,9 @@ def main():
         return
     if args.inner:
         inner(args)
+        return
+    if args.rti:
+        rti(args)
         return
     if args.uneven:
         uneven(args)

@@ -466,7 +466,8 @@ const char* mpc_version(void);
  * q, a prismatic one moves it along the axis.  Feet carry world-frame wrenches
  * at a contact point (force, then moment for foot_dim = 6).  State x = (q, qd)
  * (nx = 2 n_bodies), input u = (joint torques, foot wrenches) -- the QP's
- * layouts.  All arrays FP64, device memory; model arrays on the host.
+ * layouts.  Device arrays (FP64 for mpc_rnea, the io type of the precision
+ * argument otherwise); model arrays on the host.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t n_bodies;           /* 7..24                                              */
@@ -479,6 +480,8 @@ typedef struct {
   const double* mass;         /* [n]                                                */
   const double* com;          /* [n][3] centre of mass, body frame                  */
   const double* inertia;      /* [n][3] principal inertia about the centre of mass  */
+  const double* armature;     /* [n] the joint's reflected actuator inertia, added  */
+                              /* to M's diagonal (NULL: none; 0 for the base)      */
   const int32_t* foot_body;   /* [n_feet]                                           */
   const double* foot_offset;  /* [n_feet][3] contact point, foot body frame         */
 } mpc_model_desc;
@@ -502,23 +505,28 @@ mpc_status mpc_rnea(mpc_model_t model, int32_t count, const double* q, const dou
  * of the semi-implicit Euler step of Eq. (mpc_formulation) (qd+ = qd + dt
  * qdd(q, qd, u), q+ = q + dt qd+, qdd from M qdd = S'tau + J'F - h):
  * A_k = df/dx and B_k = df/du exactly (the derivatives of inverse dynamics in
- * closed form, mapped through M^-1), c_k = f(x_k, u_k) - A_k x_k - B_k u_k.  x [n][N][nx], u [n][N][nu]; A [n][N][nx][nx],
- * B [n][N][nx][nu], c [n][N][nx] -- the plan's layouts for agents of one shape.
- * status [n] (cleared by the caller): an agent with a non-finite x_k or u_k
- * gets MPC_AGENT_NONFINITE, else one whose mass matrix fails to factor at an
- * evaluated point MPC_AGENT_NOT_PD; its A, B, c are then not meaningful. */
-mpc_status mpc_linearize(mpc_model_t model, int32_t n_agents, int32_t N, double dt, const double* x,
-                         const double* u, double* A, double* B, double* c, int32_t* status,
+ * closed form, mapped through M^-1), c_k = f(x_k, u_k) - A_k x_k - B_k u_k.
+ * x [n][N+1][nx] and u [n][N][nu] in mpc_get_solution's layouts (x_N unused),
+ * so a solve's trajectory feeds the next linearisation; A [n][N][nx][nx],
+ * B [n][N][nx][nu], c [n][N][nx] in mpc_problem_batch's layouts for agents of
+ * one shape.  precision: MPC_FP64 (double io) or MPC_FP32 (float io; the
+ * arithmetic stays double).  status [n] (cleared by the caller): an agent with
+ * a non-finite x_k or u_k gets MPC_AGENT_NONFINITE, else one whose mass
+ * matrix fails to factor MPC_AGENT_NOT_PD; its A, B, c are then left as they
+ * were or partly written. */
+mpc_status mpc_linearize(mpc_model_t model, int32_t n_agents, int32_t N, double dt, int32_t precision,
+                         const void* x, const void* u, void* A, void* B, void* c, int32_t* status,
                          void* stream);
 
-/* f_RNEA and Eq. (mpc_torque): from the first stage of a QP solution (x0 = x*_0,
- * x1 = x*_1 [count][nx], u0 = u*_0 [count][nu]), qdd* = (qd*_1 - qd*_0) / dt,
- * tau_rnea = RNEA(q*_0, qd*_0, qdd*, F*) with F* the wrench part of u*_0, and
- * the joint torques tau = kp (q*_0 - q) + kd (qd*_0 - qd) + tau_rnea
- * ([count][n_bodies - 6]; q, qd [count][n] the measured state). */
-mpc_status mpc_rti_torque(mpc_model_t model, int32_t count, double dt, double kp, double kd,
-                          const double* x0, const double* x1, const double* u0, const double* q,
-                          const double* qd, double* tau, void* stream);
+/* f_RNEA and Eq. (mpc_torque): from the first stages of a QP solution (x
+ * [count][N+1][nx], u [count][N][nu], mpc_get_solution's layouts),
+ * qdd* = (qd*_1 - qd*_0) / dt, tau_rnea = RNEA(q*_0, qd*_0, qdd*, F*) with F*
+ * the wrench part of u*_0, and the joint torques
+ * tau = kp (q*_0 - q) + kd (qd*_0 - qd) + tau_rnea ([count][n_bodies - 6];
+ * x_meas [count][nx] the measured state (q, qd)).  precision as mpc_linearize. */
+mpc_status mpc_rti_torque(mpc_model_t model, int32_t count, int32_t N, double dt, double kp, double kd,
+                          int32_t precision, const void* x, const void* u, const void* x_meas,
+                          void* tau, void* stream);
 
 #ifdef __cplusplus
 }

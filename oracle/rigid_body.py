@@ -14,7 +14,8 @@ that tests can differentiate it by complex steps:
 
 * ``rnea``: inverse dynamics M(q) qdd + h(q, qd) - J(q)' F, gravity entering
   as an upward acceleration of the root, foot wrenches F (world frame, at the
-  contact points; force then moment for 6D feet) as external forces;
+  contact points; force then moment for 6D feet) as external forces, and each
+  joint's armature (its actuator's reflected rotor inertia) times its qdd;
 * ``mass_matrix``: M(q), column j = rnea(q, 0, e_j) - rnea(q, 0, 0);
 * ``forward_dynamics``: qdd = M^-1 (S' tau + J' F - h), with S' tau the joint
   torques in the joint coordinates (the six base coordinates unactuated);
@@ -29,7 +30,9 @@ that tests can differentiate it by complex steps:
 Conventions (readings): a joint's frame sits at its offset in the parent
 frame with the parent's orientation; a revolute joint rotates the body frame
 about its axis by q, a prismatic one translates it along the axis; a body's
-inertia is its mass, centre of mass and principal inertia in the body frame.
+inertia is its mass, centre of mass and principal inertia in the body frame;
+a joint's armature adds armature_i qdd_i to its torque, so M(q) gains it on
+the diagonal (models without the key have none).
 """
 from __future__ import annotations
 
@@ -162,8 +165,10 @@ def rnea(model, q, qd, qdd, F=None):
         for b, fw in foot_wrench_world(model, q, F):
             f[b] = f[b] - np.linalg.inv(X0[b]).T @ fw  # world force into body coordinates
     tau = np.zeros(n, dtype=dt)
+    if "armature" in model:
+        tau = tau + np.asarray(model["armature"]) * qdd
     for i in range(n - 1, -1, -1):
-        tau[i] = motion_subspace(model, i) @ f[i]
+        tau[i] = tau[i] + motion_subspace(model, i) @ f[i]
         par = model["parent"][i]
         if par >= 0:
             f[par] = f[par] + X[i].T @ f[i]

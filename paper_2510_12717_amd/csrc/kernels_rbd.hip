@@ -168,7 +168,7 @@ __device__ void rnea_dev(const ModelDev& md, const double* q, const double* qd, 
   }
   for (int i = n - 1; i >= 0; --i) {
     const V3 ax = ld3(md.axis + 3 * i);
-    tau[i] = md.jtype[i] == 1 ? dot(ax, ff[i]) : dot(ax, fn[i]);
+    tau[i] = (md.jtype[i] == 1 ? dot(ax, ff[i]) : dot(ax, fn[i])) + md.armature[i] * qdd[i];
     const int par = md.parent[i];
     if (par >= 0) {
       const V3 fp = mulT(E[i], ff[i]);
@@ -211,6 +211,14 @@ __device__ inline S6 mul6(const double* M, S6 x) {
   return s6(v3(o[0], o[1], o[2]), v3(o[3], o[4], o[5]));
 }
 
+// Lane `lane`'s value of v (lane a compile-time or wave-uniform index).
+__device__ inline double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffu), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Body i's placement relative to its parent at joint value qi: rotation (body
 // axes in parent coordinates) and origin.
 __device__ inline void joint_local(const ModelDev& md, int i, double qi, M3& R, V3& p) {
@@ -233,17 +241,38 @@ struct LinLds {
   double S[kMaxBodies][6];      // joint motion subspace
   double v[kMaxBodies][6];      // velocity
   double a[kMaxBodies][6];      // acceleration: qdd = 0 first, then qdd = qdd0
-  double Io[kMaxBodies][36];    // own spatial inertia
+  union {
+    double Io[kMaxBodies][36];       // own spatial inertia (until the forces at qdd0)
+    double D[kMaxBodies][kMaxCols];  // d qdd / d(x, u), column per thread (from then on)
+  };
+  union {
+    struct {
+      double Rl[kMaxBodies][9];  // body's rotation relative to its parent (placement only)
+      double pl[kMaxBodies][3];  // body's origin in the parent frame (placement only)
+    };
+    struct {
+      double dv[kMaxBodies][6];   // S_j x v_parent(j)
+      double al[kMaxBodies][6];   // S_j x a_parent(j) - dv_j x v_parent(j)
+      double psi[kMaxBodies][6];  // d(composite force of j's subtree)/d q_j
+      double phi[kMaxBodies][6];  // d(composite force of j's subtree)/d qd_j
+    };
+  };
   double IC[kMaxBodies][36];    // composite inertia of the subtree
   double BC[kMaxBodies][36];    // composite of v x* I - I v x
   double hC[kMaxBodies][6];     // composite momentum
   double fC[kMaxBodies][6];     // composite force, feet's wrenches subtracted
   double fiC[kMaxBodies][6];    // composite force of the bodies alone
-  double M[kMaxBodies * kMaxBodies];  // mass matrix, then its Cholesky factor below the diagonal
-  double Ld[kMaxBodies];        // the factor's diagonal
+  double Fv[kMaxBodies][6];     // IC_i S_i
+  double G[kMaxBodies][6];      // BC_i' S_i
+  double eC[kMaxBodies][6];     // the feet's wrenches on i's subtree (fiC - fC)
+  double PF[kMaxBodies][9];     // sum over the feet below i of p_f F_f'
+  double sF[kMaxBodies];        // sum over the feet below i of p_f . F_f
+  // mass matrix, then its Cholesky factor on and below the diagonal, row
+  // stride kMaxBodies, rows and columns past n padded with the identity
+  double M[kMaxBodies * kMaxBodies];
+  double iLd[kMaxBodies];       // reciprocals of the factor's diagonal
   double qdd[kMaxBodies];       // generalised force, then qdd0
   double z[kMaxCols];           // (x, u) of the stage
-  double D[kMaxBodies][kMaxCols];  // d qdd / d(x, u), column per thread
   double pf[kMaxFeet][3];       // contact points, world
   uint32_t anc[kMaxBodies];     // ancestors of body i, itself included
   int bad;                      // 1 non-finite input, 2 mass matrix not positive definite
@@ -256,10 +285,10 @@ struct LinLds {
 // its subtree rigidly along S_j, so each world-frame quantity of the subtree
 // changes by S_j x (.), apart from terms through the parent's velocity and
 // acceleration, which do not move, and the feet's world-fixed wrenches.
+template <typename T>
 __global__ void __launch_bounds__(kLinThreads)
-k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const double* __restrict__ U,
-            double* __restrict__ A, double* __restrict__ B, double* __restrict__ C,
-            int32_t* __restrict__ status) {
+k_linearize(ModelDev md, int N, double dt, const T* __restrict__ X, const T* __restrict__ U,
+            T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, int32_t* __restrict__ status) {
   __shared__ LinLds L;
   const int tid = threadIdx.x;
   const int n = md.n, nx = 2 * n, nj = n - 6, nf = md.n_feet, fd = md.foot_dim;
@@ -273,7 +302,8 @@ k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const d
   if (tid == 0) L.bad = 0;
   __syncthreads();
   if (tid < ncol) {
-    const double val = tid < nx ? X[ak * nx + tid] : U[ak * nu + tid - nx];
+    // x of the stage in the solution layout (N + 1 states per agent)
+    const double val = tid < nx ? (double)X[(ak + ak / N) * nx + tid] : (double)U[ak * nu + tid - nx];
     L.z[tid] = val;
     if (!isfinite(val)) L.bad = 1;
   }
@@ -287,17 +317,27 @@ k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const d
     if (tid == 0) atomicMax(status + ak / N, (int32_t)AGENT_NONFINITE);
     return;
   }
-  // (1) world placement, motion subspace and inertia of body tid
+  // (1) world placement, motion subspace and inertia of body tid (each body's
+  // placement relative to its parent first, then composed up the chain)
+  if (tid < n) {
+    M3 R;
+    V3 p;
+    joint_local(md, tid, q[tid], R, p);
+    for (int k = 0; k < 9; ++k) L.Rl[tid][k] = R.m[k];
+    L.pl[tid][0] = p.x;
+    L.pl[tid][1] = p.y;
+    L.pl[tid][2] = p.z;
+  }
+  __syncthreads();
   if (tid < n) {
     const int i = tid;
     M3 R;
-    V3 p;
-    joint_local(md, i, q[i], R, p);
+    for (int k = 0; k < 9; ++k) R.m[k] = L.Rl[i][k];
+    V3 p = ld3(L.pl[i]);
     for (int k = md.parent[i]; k >= 0; k = md.parent[k]) {
       M3 Rk;
-      V3 pk;
-      joint_local(md, k, q[k], Rk, pk);
-      p = pk + mul(Rk, p);
+      for (int e = 0; e < 9; ++e) Rk.m[e] = L.Rl[k][e];
+      p = ld3(L.pl[k]) + mul(Rk, p);
       R = mulM(Rk, R);
     }
     const V3 ax = mul(R, ld3(md.axis + 3 * i));
@@ -357,20 +397,30 @@ k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const d
     for (int k = 0; k <= i; ++k)
       if (L.anc[i] >> k & 1u) a0 = a0 + qd[k] * crm(ld6(L.v[k]), ld6(L.S[k]));
     const S6 v = ld6(L.v[i]);
-    const S6 h = mul6(L.Io[i], v);
+    double I[36];  // the body's inertia, in registers for this phase
+#pragma unroll
+    for (int e = 0; e < 36; ++e) I[e] = L.Io[i][e];
+    const S6 h = mul6(I, v);
     st6(L.a[i], a0);
     st6(L.hC[i], h);
-    st6(L.fC[i], mul6(L.Io[i], a0) + crf(v, h) - ext(i));
+    st6(L.fC[i], mul6(I, a0) + crf(v, h) - ext(i));
+    // B e_c = v x* (I e_c) - I (v x e_c), column by column
+#pragma unroll
     for (int c = 0; c < 6; ++c) {
+      const S6 Ie = s6(v3(I[c], I[6 + c], I[12 + c]), v3(I[18 + c], I[24 + c], I[30 + c]));
       S6 e = s6(v3(0, 0, 0), v3(0, 0, 0));
       if (c < 3) (c == 0 ? e.a.x : c == 1 ? e.a.y : e.a.z) = 1.0;
       else (c == 3 ? e.b.x : c == 4 ? e.b.y : e.b.z) = 1.0;
-      const S6 Ie = mul6(L.Io[i], e);
-      const S6 col = crf(v, Ie) - mul6(L.Io[i], crm(v, e));
-      const double cc[6] = {col.a.x, col.a.y, col.a.z, col.b.x, col.b.y, col.b.z};
-      for (int r = 0; r < 6; ++r) L.BC[i][6 * r + c] = cc[r];
+      const S6 col = crf(v, Ie) - mul6(I, crm(v, e));
+      L.BC[i][c] = col.a.x;
+      L.BC[i][6 + c] = col.a.y;
+      L.BC[i][12 + c] = col.a.z;
+      L.BC[i][18 + c] = col.b.x;
+      L.BC[i][24 + c] = col.b.y;
+      L.BC[i][30 + c] = col.b.z;
     }
-    for (int e = 0; e < 36; ++e) L.IC[i][e] = L.Io[i][e];
+#pragma unroll
+    for (int e = 0; e < 36; ++e) L.IC[i][e] = I[e];
   }
   __syncthreads();
   // (4) composites over subtrees (children come after their parents): one
@@ -388,47 +438,87 @@ k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const d
     }
   }
   __syncthreads();
-  // (5) mass matrix M_ij = S_i' IC_j S_j (i an ancestor of j) and the
-  // generalised force S'tau - ID(q, qd, 0, F)
-  for (int idx = tid; idx < n * n; idx += kLinThreads) {
-    const int i = idx / n, j = idx % n;
-    double val = 0.0;
-    if (L.anc[j] >> i & 1u) val = dot6(ld6(L.S[i]), mul6(L.IC[j], ld6(L.S[j])));
-    else if (L.anc[i] >> j & 1u) val = dot6(ld6(L.S[j]), mul6(L.IC[i], ld6(L.S[i])));
+  // (5) per-body IC_i S_i and BC_i' S_i; the generalised force
+  // S'tau - ID(q, qd, 0, F)
+  if (tid < n) {
+    const int i = tid;
+    const S6 Si = ld6(L.S[i]);
+    st6(L.Fv[i], mul6(L.IC[i], Si));
+    double g[6];
+    const double sv[6] = {Si.a.x, Si.a.y, Si.a.z, Si.b.x, Si.b.y, Si.b.z};
+    for (int c = 0; c < 6; ++c) {
+      double t = 0.0;
+      for (int r = 0; r < 6; ++r) t += L.BC[i][6 * r + c] * sv[r];
+      g[c] = t;
+    }
+    for (int c = 0; c < 6; ++c) L.G[i][c] = g[c];
+    L.qdd[i] = (i >= 6 ? L.z[nx + i - 6] : 0.0) - dot6(Si, ld6(L.fC[i]));
+  } else if (tid < kMaxBodies) {
+    L.qdd[tid] = 0.0;
+  }
+  __syncthreads();
+  // (6) mass matrix M_ij = S_i' IC_j S_j (i an ancestor of j), padded
+  for (int idx = tid; idx < kMaxBodies * kMaxBodies; idx += kLinThreads) {
+    const int i = idx / kMaxBodies, j = idx % kMaxBodies;
+    double val = i == j ? 1.0 : 0.0;
+    if (i < n && j < n) {
+      if (i == j) val = dot6(ld6(L.S[i]), ld6(L.Fv[i])) + md.armature[i];
+      else if (L.anc[j] >> i & 1u) val = dot6(ld6(L.S[i]), ld6(L.Fv[j]));
+      else if (L.anc[i] >> j & 1u) val = dot6(ld6(L.S[j]), ld6(L.Fv[i]));
+      else val = 0.0;
+    }
     L.M[idx] = val;
   }
-  if (tid < n) L.qdd[tid] = (tid >= 6 ? L.z[nx + tid - 6] : 0.0) - dot6(ld6(L.S[tid]), ld6(L.fC[tid]));
   __syncthreads();
-  // (6) Cholesky factor, column by column (every thread forms the same pivot)
-  for (int j = 0; j < n; ++j) {
-    double d = L.M[j * n + j];
-    for (int t = 0; t < j; ++t) d -= L.M[j * n + t] * L.M[j * n + t];
-    if (!(d > 0.0)) {
-      if (tid == 0) atomicMax(status + ak / N, (int32_t)AGENT_NOT_PD);
-      return;
+  // (7) wavefront 0: Cholesky factor with lane i holding row i in registers
+  // (pivots and multipliers broadcast with readlane), then the forward sweep
+  // of qdd0; the transposed sweep after the factor is in LDS
+  if (tid < 64) {
+    const int i = tid;
+    double r[kMaxBodies];
+#pragma unroll
+    for (int k = 0; k < kMaxBodies; ++k) r[k] = i < kMaxBodies ? L.M[i * kMaxBodies + k] : 0.0;
+    bool ok = true;
+    double inv_own = 1.0;  // reciprocal of this lane's pivot
+#pragma unroll
+    for (int j = 0; j < kMaxBodies; ++j) {
+      const double d = readlane_d(r[j], j);
+      ok = ok && d > 0.0;
+      const double l = sqrt(d), inv = 1.0 / l;
+      r[j] = i == j ? l : r[j] * inv;
+      inv_own = i == j ? inv : inv_own;
+#pragma unroll
+      for (int k = j + 1; k < kMaxBodies; ++k) r[k] -= r[j] * readlane_d(r[j], k);
     }
-    const double l = sqrt(d);
-    const int i = j + 1 + tid;
-    if (i < n) {
-      double s = L.M[i * n + j];
-      for (int t = 0; t < j; ++t) s -= L.M[i * n + t] * L.M[j * n + t];
-      L.M[i * n + j] = s / l;
+    if (!ok) {
+      if (i == 0) atomicMax(status + ak / N, (int32_t)AGENT_NOT_PD);
+    } else if (i < kMaxBodies) {
+#pragma unroll
+      for (int k = 0; k < kMaxBodies; ++k)
+        if (k <= i) L.M[i * kMaxBodies + k] = r[k];
+      L.iLd[i] = inv_own;
     }
-    if (tid == 0) L.Ld[j] = l;
-    __syncthreads();
+    double g = i < kMaxBodies ? L.qdd[i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxBodies; ++k) {
+      const double yk = readlane_d(g, k) * readlane_d(inv_own, k);
+      g = i == k ? yk : (i > k ? g - r[k] * yk : g);
+    }
+    if (i < kMaxBodies) L.qdd[i] = g;
+    if (i == 0) L.bad = ok ? 0 : 2;
   }
-  // (7) qdd0 = M^-1 (S'tau + J'F - h)
-  if (tid == 0) {
-    for (int i = 0; i < n; ++i) {
-      double s = L.qdd[i];
-      for (int t = 0; t < i; ++t) s -= L.M[i * n + t] * L.qdd[t];
-      L.qdd[i] = s / L.Ld[i];
+  __syncthreads();
+  if (L.bad) return;
+  if (tid < 64) {
+    const int i = tid;
+    double g = i < kMaxBodies ? L.qdd[i] : 0.0;
+#pragma unroll
+    for (int k = kMaxBodies - 1; k >= 0; --k) {
+      const double xk = readlane_d(g, k) * L.iLd[k];
+      const double lki = i < k ? L.M[k * kMaxBodies + i] : 0.0;
+      g = i == k ? xk : g - lki * xk;
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = L.qdd[i];
-      for (int t = i + 1; t < n; ++t) s -= L.M[t * n + i] * L.qdd[t];
-      L.qdd[i] = s / L.Ld[i];
-    }
+    if (i < kMaxBodies) L.qdd[i] = g;
   }
   __syncthreads();
   // (8) accelerations and forces at qdd0
@@ -439,7 +529,10 @@ k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const d
       if (L.anc[i] >> k & 1u) a = a + L.qdd[k] * ld6(L.S[k]);
     st6(L.a[i], a);
     const S6 v = ld6(L.v[i]);
-    const S6 fi = mul6(L.Io[i], a) + crf(v, mul6(L.Io[i], v));
+    double I[36];
+#pragma unroll
+    for (int e = 0; e < 36; ++e) I[e] = L.Io[i][e];
+    const S6 fi = mul6(I, a) + crf(v, mul6(I, v));
     st6(L.fiC[i], fi);
     st6(L.fC[i], fi - ext(i));
   }
@@ -453,100 +546,151 @@ k_linearize(ModelDev md, int N, double dt, const double* __restrict__ X, const d
     }
   }
   __syncthreads();
-  // (9) one column of d qdd / d(x, u) per thread
-  if (tid < ncol) {
-    const int t = tid;
+  // (9) per coordinate j (wavefront 0: q_j, wavefront 1: qd_j): the change of
+  // the composite force of j's subtree.  Moving q_j moves the subtree rigidly
+  // along S_j except for the parent's velocity and acceleration and the feet's
+  // world-fixed wrenches; qd_j enters the subtree's velocities as S_j.
+  if ((tid & 63) < n) {
+    const int j = tid & 63;
+    const S6 Sj = ld6(L.S[j]);
+    const int par = md.parent[j];
+    const S6 vp = par >= 0 ? ld6(L.v[par]) : s6(v3(0, 0, 0), v3(0, 0, 0));
+    const S6 dvj = crm(Sj, vp);
+    if (tid < 64) {
+      const S6 ap = par >= 0 ? ld6(L.a[par]) : a_root;
+      const S6 alj = crm(Sj, ap) - crm(dvj, vp);
+      S6 ps = crf(Sj, ld6(L.fiC[j])) - mul6(L.IC[j], alj) - mul6(L.BC[j], dvj) - crf(dvj, ld6(L.hC[j]));
+      for (int f = 0; f < nf; ++f)
+        if (L.anc[md.foot_body[f]] >> j & 1u)
+          ps.a = ps.a - cross(Sj.b + cross(Sj.a, ld3(L.pf[f])), ld3(F + f * fd));
+      st6(L.dv[j], dvj);
+      st6(L.al[j], alj);
+      st6(L.psi[j], ps);
+    } else {
+      st6(L.phi[j], mul6(L.BC[j], Sj) + crf(Sj, ld6(L.hC[j])) - 2.0 * mul6(L.IC[j], dvj));
+      st6(L.eC[j], ld6(L.fiC[j]) - ld6(L.fC[j]));
+      double P[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, sp = 0.0;
+      for (int f = 0; f < nf; ++f)
+        if (L.anc[md.foot_body[f]] >> j & 1u) {
+          const V3 pt = ld3(L.pf[f]), fo = ld3(F + f * fd);
+          const double pa[3] = {pt.x, pt.y, pt.z}, fa[3] = {fo.x, fo.y, fo.z};
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int w = 0; w < 3; ++w) P[3 * u + w] += pa[u] * fa[w];
+          sp += dot(pt, fo);
+        }
+#pragma unroll
+      for (int e = 0; e < 9; ++e) L.PF[j][e] = P[e];
+      L.sF[j] = sp;
+    }
+  }
+  __syncthreads();
+  // (10) columns of d qdd / d(x, u): wavefront 0 takes the q columns and the
+  // joint torques, wavefront 1 the qd columns and the foot wrenches, one per
+  // lane.  For body i in the subtree of coordinate j the derivative of ID_i
+  // reduces to products with the per-body vectors IC_i S_i and BC_i' S_i; for
+  // an ancestor i of j it is S_i' times the composite change at j.
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nw = nf * fd;
+  const int t = wave == 0 ? (lane < n ? lane : (lane < n + nj ? nx + lane - n : -1))
+                          : (lane < n ? n + lane : (lane < n + nw ? nx + nj + lane - n : -1));
+  if (t >= 0) {
     if (t < nx) {
       const int j = t % n;
       const S6 Sj = ld6(L.S[j]);
-      const int par = md.parent[j];
-      const S6 vp = par >= 0 ? ld6(L.v[par]) : s6(v3(0, 0, 0), v3(0, 0, 0));
+      const S6 dv = ld6(L.dv[j]);
       if (t < n) {
         // d ID / d q_j
-        const S6 ap = par >= 0 ? ld6(L.a[par]) : a_root;
-        const S6 dv = crm(Sj, vp);
-        const S6 al = crm(Sj, ap) - crm(dv, vp);
-        auto psi = [&](int i) {
-          S6 r = crf(Sj, ld6(L.fiC[i])) - mul6(L.IC[i], al) - mul6(L.BC[i], dv) - crf(dv, ld6(L.hC[i]));
-          for (int f = 0; f < nf; ++f) {
-            const int b = md.foot_body[f];
-            if (L.anc[b] >> i & 1u) {  // foot in the subtree of i
-              const V3 pt = ld3(L.pf[f]);
-              r.a = r.a - cross(Sj.b + cross(Sj.a, pt), ld3(F + f * fd));
-            }
-          }
-          return r;
-        };
-        const S6 psij = psi(j);
+        const S6 al = ld6(L.al[j]);
+        const S6 psij = ld6(L.psi[j]);
         for (int i = 0; i < n; ++i) {
           double d = 0.0;
           const S6 Si = ld6(L.S[i]);
-          if (L.anc[i] >> j & 1u) d = dot6(crm(Sj, Si), ld6(L.fC[i])) + dot6(Si, i == j ? psij : psi(i));
-          else if (L.anc[j] >> i & 1u) d = dot6(Si, psij);
+          if (L.anc[i] >> j & 1u) {
+            // the feet below body i: sum of (velocity of the contact point
+            // under S_j) x force = S_j.lin x F_sum + PF S_j.ang - S_j.ang sF
+            const S6 eC = ld6(L.eC[i]);
+            const double* P = L.PF[i];
+            const V3 PS = v3(P[0] * Sj.a.x + P[1] * Sj.a.y + P[2] * Sj.a.z,
+                             P[3] * Sj.a.x + P[4] * Sj.a.y + P[5] * Sj.a.z,
+                             P[6] * Sj.a.x + P[7] * Sj.a.y + P[8] * Sj.a.z);
+            const V3 ft = cross(Sj.b, eC.b) + PS - L.sF[i] * Sj.a;
+            d = -dot6(crm(Sj, Si), eC) - dot6(al, ld6(L.Fv[i])) - dot6(dv, ld6(L.G[i])) +
+                dot6(crm(dv, Si), ld6(L.hC[i])) - dot(Si.a, ft);
+          } else if (L.anc[j] >> i & 1u) {
+            d = dot6(Si, psij);
+          }
           L.D[i][t] = -d;
         }
       } else {
         // d ID / d qd_j
-        const S6 w = crm(Sj, vp);
-        auto phi = [&](int i) {
-          return mul6(L.BC[i], Sj) + crf(Sj, ld6(L.hC[i])) - 2.0 * mul6(L.IC[i], w);
-        };
-        const S6 phij = phi(j);
+        const S6 phij = ld6(L.phi[j]);
         for (int i = 0; i < n; ++i) {
           double d = 0.0;
           const S6 Si = ld6(L.S[i]);
-          if (L.anc[i] >> j & 1u) d = dot6(Si, i == j ? phij : phi(i));
-          else if (L.anc[j] >> i & 1u) d = dot6(Si, phij);
+          if (L.anc[i] >> j & 1u)
+            d = dot6(Sj, ld6(L.G[i])) - dot6(crm(Sj, Si), ld6(L.hC[i])) - 2.0 * dot6(dv, ld6(L.Fv[i]));
+          else if (L.anc[j] >> i & 1u)
+            d = dot6(Si, phij);
           L.D[i][t] = -d;
         }
       }
     } else if (t < nx + nj) {
       for (int i = 0; i < n; ++i) L.D[i][t] = i == 6 + (t - nx) ? 1.0 : 0.0;
     } else {
-      const int w = t - nx - nj, f = w / fd, comp = w % fd;
-      S6 e = s6(v3(0, 0, 0), v3(0, 0, 0));
-      V3 unit = v3(comp % 3 == 0, comp % 3 == 1, comp % 3 == 2);
-      if (comp < 3) e = s6(cross(ld3(L.pf[f]), unit), unit);
-      else e = s6(unit, v3(0, 0, 0));
+      const int wi = t - nx - nj, f = wi / fd, comp = wi % fd;
+      const V3 unit = v3(comp % 3 == 0, comp % 3 == 1, comp % 3 == 2);
+      const S6 e = comp < 3 ? s6(cross(ld3(L.pf[f]), unit), unit) : s6(unit, v3(0, 0, 0));
       const uint32_t up = L.anc[md.foot_body[f]];
       for (int i = 0; i < n; ++i) L.D[i][t] = (up >> i & 1u) ? dot6(ld6(L.S[i]), e) : 0.0;
     }
-    // M^-1 on the column
-    for (int i = 0; i < n; ++i) {
-      double s = L.D[i][t];
-      for (int k = 0; k < i; ++k) s -= L.M[i * n + k] * L.D[k][t];
-      L.D[i][t] = s / L.Ld[i];
+    // M^-1 on the column, in registers (rows past n: identity)
+    double y[kMaxBodies];
+#pragma unroll
+    for (int i = 0; i < kMaxBodies; ++i) y[i] = i < n ? L.D[i][t] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxBodies; ++k) {
+      y[k] *= L.iLd[k];
+#pragma unroll
+      for (int i = k + 1; i < kMaxBodies; ++i) y[i] -= L.M[i * kMaxBodies + k] * y[k];
+      __builtin_amdgcn_sched_barrier(0);
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = L.D[i][t];
-      for (int k = i + 1; k < n; ++k) s -= L.M[k * n + i] * L.D[k][t];
-      L.D[i][t] = s / L.Ld[i];
+#pragma unroll
+    for (int k = kMaxBodies - 1; k >= 0; --k) {
+      y[k] *= L.iLd[k];
+#pragma unroll
+      for (int i = 0; i < k; ++i) y[i] -= L.M[k * kMaxBodies + i] * y[k];
+      __builtin_amdgcn_sched_barrier(0);
     }
-    // q+ = q + dt qd + dt^2 qdd, qd+ = qd + dt qdd
+#pragma unroll
+    for (int r = 0; r < kMaxBodies; ++r)
+      if (r < n) L.D[r][t] = y[r];
+  }
+  __syncthreads();
+  // (11) A and B column by column (q+ = q + dt qd + dt^2 qdd, qd+ = qd + dt
+  // qdd), after the barrier so that it waits on no global store
+  if (t >= 0) {
     const double dt2 = dt * dt;
-    if (t < nx) {
-      double* Ak = A + ak * nx * nx;
-      for (int r = 0; r < n; ++r) {
-        const double dq = L.D[r][t];
-        Ak[r * nx + t] = (r == t ? 1.0 : 0.0) + (r + n == t ? dt : 0.0) + dt2 * dq;
-        Ak[(n + r) * nx + t] = (r + n == t ? 1.0 : 0.0) + dt * dq;
-      }
-    } else {
-      double* Bk = B + ak * nx * nu;
-      const int c = t - nx;
-      for (int r = 0; r < n; ++r) {
-        Bk[r * nu + c] = dt2 * L.D[r][t];
-        Bk[(n + r) * nu + c] = dt * L.D[r][t];
+    for (int r = 0; r < n; ++r) {
+      const double yr = L.D[r][t];
+      if (t < nx) {
+        T* Ak = A + ak * nx * nx;
+        Ak[r * nx + t] = (T)((r == t ? 1.0 : 0.0) + (r + n == t ? dt : 0.0) + dt2 * yr);
+        Ak[(n + r) * nx + t] = (T)((r + n == t ? 1.0 : 0.0) + dt * yr);
+      } else {
+        T* Bk = B + ak * nx * nu;
+        Bk[r * nu + t - nx] = (T)(dt2 * yr);
+        Bk[(n + r) * nu + t - nx] = (T)(dt * yr);
       }
     }
   }
-  __syncthreads();
-  // (10) c = f(x, u) - A x - B u = (dt^2 r, dt r), r = qdd0 - D (x, u)
+  // (12) c = f(x, u) - A x - B u = (dt^2 r, dt r), r = qdd0 - D (x, u)
   if (tid < n) {
     double r = L.qdd[tid];
     for (int t = 0; t < ncol; ++t) r -= L.D[tid][t] * L.z[t];
-    C[ak * nx + tid] = dt * dt * r;
-    C[ak * nx + n + tid] = dt * r;
+    C[ak * nx + tid] = (T)(dt * dt * r);
+    C[ak * nx + n + tid] = (T)(dt * r);
   }
 }
 
@@ -560,21 +704,26 @@ k_rnea(ModelDev md, int count, const double* __restrict__ q, const double* __res
            F ? F + (int64_t)t * nf : nullptr, tau + (int64_t)t * n);
 }
 
+// Thread per agent; x [count][N + 1][nx] and u [count][N][nu] in the solution
+// layout (x_0, x_1 and u_0 used), measured state xm [count][nx], tau [count][nj].
+template <typename T>
 __global__ void __launch_bounds__(64)
-k_rti_torque(ModelDev md, int count, double dt, double kp, double kd, const double* __restrict__ x0,
-             const double* __restrict__ x1, const double* __restrict__ u0,
-             const double* __restrict__ qm, const double* __restrict__ qdm, double* __restrict__ tau) {
+k_rti_torque(ModelDev md, int count, int N, double dt, double kp, double kd, const T* __restrict__ X,
+             const T* __restrict__ U, const T* __restrict__ xm, T* __restrict__ tau) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
-  const int n = md.n, nx = 2 * n, nj = n - 6, nu = nj + md.n_feet * md.foot_dim;
-  const double* a = x0 + (int64_t)t * nx;
-  const double* b = x1 + (int64_t)t * nx;
-  double qdd[kMaxBodies], tr[kMaxBodies];
-  for (int i = 0; i < n; ++i) qdd[i] = (b[n + i] - a[n + i]) / dt;
-  rnea_dev(md, a, a + n, qdd, u0 + (int64_t)t * nu + nj, tr);
+  const int n = md.n, nx = 2 * n, nj = n - 6, nf = md.n_feet * md.foot_dim, nu = nj + nf;
+  const T* x = X + (int64_t)t * (N + 1) * nx;
+  const T* u = U + (int64_t)t * N * nu;
+  double x0[2 * kMaxBodies], qdd[kMaxBodies], F[kMaxU], tr[kMaxBodies];
+  for (int i = 0; i < nx; ++i) x0[i] = (double)x[i];
+  for (int i = 0; i < n; ++i) qdd[i] = ((double)x[nx + n + i] - x0[n + i]) / dt;
+  for (int i = 0; i < nf; ++i) F[i] = (double)u[nj + i];
+  rnea_dev(md, x0, x0 + n, qdd, F, tr);
   for (int i = 0; i < nj; ++i)
-    tau[(int64_t)t * nj + i] = kp * (a[6 + i] - qm[(int64_t)t * n + 6 + i]) +
-                               kd * (a[n + 6 + i] - qdm[(int64_t)t * n + 6 + i]) + tr[6 + i];
+    tau[(int64_t)t * nj + i] = (T)(kp * (x0[6 + i] - (double)xm[(int64_t)t * nx + 6 + i]) +
+                                   kd * (x0[n + 6 + i] - (double)xm[(int64_t)t * nx + n + 6 + i]) +
+                                   tr[6 + i]);
 }
 
 }  // namespace
@@ -586,22 +735,22 @@ hipError_t launch_rnea(const ModelDev& md, int count, const double* q, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const double* X,
-                            const double* U, double* A, double* B, double* C, int32_t* status,
-                            hipStream_t s) {
+template <typename T>
+hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const T* X, const T* U,
+                            T* A, T* B, T* C, int32_t* status, hipStream_t s) {
   const int64_t blocks = (int64_t)n_agents * N;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_linearize, dim3((unsigned)blocks), dim3(kLinThreads), 0, s, md, N, dt, X, U, A, B,
-                     C, status);
+  hipLaunchKernelGGL(k_linearize<T>, dim3((unsigned)blocks), dim3(kLinThreads), 0, s, md, N, dt, X, U, A,
+                     B, C, status);
   return hipGetLastError();
 }
 
-hipError_t launch_rti_torque(const ModelDev& md, int count, double dt, double kp, double kd,
-                             const double* x0, const double* x1, const double* u0, const double* qm,
-                             const double* qdm, double* tau, hipStream_t s) {
+template <typename T>
+hipError_t launch_rti_torque(const ModelDev& md, int count, int N, double dt, double kp, double kd,
+                             const T* X, const T* U, const T* xm, T* tau, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rti_torque, dim3((count + 63) / 64), dim3(64), 0, s, md, count, dt, kp, kd, x0,
-                     x1, u0, qm, qdm, tau);
+  hipLaunchKernelGGL(k_rti_torque<T>, dim3((count + 63) / 64), dim3(64), 0, s, md, count, N, dt, kp, kd,
+                     X, U, xm, tau);
   return hipGetLastError();
 }
 
@@ -659,8 +808,13 @@ extern "C" mpc_status mpc_model_create(const mpc_model_desc* d, int32_t device, 
   for (int f = 0; f < nf; ++f)
     if (d->foot_body[f] < 6 || d->foot_body[f] >= n)
       return api_fail(MPC_ERR_INVALID_ARG, "model: a foot on a body past the base");
+  for (int i = 0; i < n; ++i) {
+    const double a = d->armature ? d->armature[i] : 0.0;
+    if (!(std::isfinite(a) && a >= 0.0))
+      return api_fail(MPC_ERR_INVALID_ARG, "model: armature must be finite and non-negative");
+  }
   MPC_HIP_TRY(hipSetDevice(device));
-  const size_t dbl = (size_t)n * (3 + 3 + 1 + 3 + 3) + (size_t)nf * 3;
+  const size_t dbl = (size_t)n * (3 + 3 + 1 + 3 + 3 + 1) + (size_t)nf * 3;
   const size_t ints = (size_t)n * 2 + (size_t)nf;
   std::vector<unsigned char> host(8 * dbl + 4 * ints);
   double* hd = reinterpret_cast<double*>(host.data());
@@ -673,8 +827,11 @@ extern "C" mpc_status mpc_model_create(const mpc_model_desc* d, int32_t device, 
     return at;
   };
   const size_t oa = putd(d->axis, 3 * n), oo = putd(d->offset, 3 * n), om = putd(d->mass, n),
-               oc = putd(d->com, 3 * n), oi = putd(d->inertia, 3 * n),
-               of = nf ? putd(d->foot_offset, 3 * nf) : o;
+               oc = putd(d->com, 3 * n), oi = putd(d->inertia, 3 * n);
+  const size_t oar = o;
+  for (int i = 0; i < n; ++i) hd[o + i] = d->armature ? d->armature[i] : 0.0;
+  o += n;
+  const size_t of = nf ? putd(d->foot_offset, 3 * nf) : o;
   for (int i = 0; i < n; ++i) {
     hi[i] = d->parent[i];
     hi[n + i] = d->joint_type[i];
@@ -693,7 +850,7 @@ extern "C" mpc_status mpc_model_create(const mpc_model_desc* d, int32_t device, 
   const double* dd = reinterpret_cast<const double*>(m->buf);
   const int32_t* di = reinterpret_cast<const int32_t*>((const unsigned char*)m->buf + 8 * dbl);
   m->md = ModelDev{n, nf, d->foot_dim, d->gravity, di, di + n, dd + oa, dd + oo, dd + om, dd + oc, dd + oi,
-                   nf ? di + 2 * n : nullptr, nf ? dd + of : nullptr};
+                   dd + oar, nf ? di + 2 * n : nullptr, nf ? dd + of : nullptr};
   *out = m;
   return MPC_OK;
 }
@@ -718,26 +875,41 @@ extern "C" mpc_status mpc_rnea(mpc_model_t m, int32_t count, const double* q, co
 }
 
 extern "C" mpc_status mpc_linearize(mpc_model_t m, int32_t n_agents, int32_t N, double dt,
-                                    const double* x, const double* u, double* A, double* B, double* c,
-                                    int32_t* status, void* stream) {
+                                    int32_t precision, const void* x, const void* u, void* A, void* B,
+                                    void* c, int32_t* status, void* stream) {
   using namespace mpc;
   if (!m || n_agents < 0 || N < 1 || N > 64 || !(dt > 0))
     return api_fail(MPC_ERR_INVALID_ARG, "n_agents >= 0, 1 <= N <= 64 and dt > 0 required");
+  if (precision != MPC_FP64 && precision != MPC_FP32)
+    return api_fail(MPC_ERR_INVALID_ARG, "precision: MPC_FP64 (double io) or MPC_FP32 (float io)");
   if (n_agents > 0 && (!x || !u || !A || !B || !c || !status))
     return api_fail(MPC_ERR_INVALID_ARG, "null argument");
   MPC_HIP_TRY(hipSetDevice(m->device));
-  MPC_HIP_TRY(launch_linearize(m->md, n_agents, N, dt, x, u, A, B, c, status, (hipStream_t)stream));
+  const hipStream_t s = (hipStream_t)stream;
+  if (precision == MPC_FP64)
+    MPC_HIP_TRY(launch_linearize(m->md, n_agents, N, dt, (const double*)x, (const double*)u, (double*)A,
+                                 (double*)B, (double*)c, status, s));
+  else
+    MPC_HIP_TRY(launch_linearize(m->md, n_agents, N, dt, (const float*)x, (const float*)u, (float*)A,
+                                 (float*)B, (float*)c, status, s));
   return MPC_OK;
 }
 
-extern "C" mpc_status mpc_rti_torque(mpc_model_t m, int32_t count, double dt, double kp, double kd,
-                                     const double* x0, const double* x1, const double* u0,
-                                     const double* q, const double* qd, double* tau, void* stream) {
+extern "C" mpc_status mpc_rti_torque(mpc_model_t m, int32_t count, int32_t N, double dt, double kp,
+                                     double kd, int32_t precision, const void* x, const void* u,
+                                     const void* x_meas, void* tau, void* stream) {
   using namespace mpc;
-  if (!m || count < 0 || !(dt > 0) ||
-      (count > 0 && (!x0 || !x1 || !u0 || !q || !qd || !tau)))
-    return api_fail(MPC_ERR_INVALID_ARG, "null argument, or dt <= 0");
+  if (!m || count < 0 || N < 1 || N > 64 || !(dt > 0) || (count > 0 && (!x || !u || !x_meas || !tau)))
+    return api_fail(MPC_ERR_INVALID_ARG, "null argument, N outside 1..64, or dt <= 0");
+  if (precision != MPC_FP64 && precision != MPC_FP32)
+    return api_fail(MPC_ERR_INVALID_ARG, "precision: MPC_FP64 (double io) or MPC_FP32 (float io)");
   MPC_HIP_TRY(hipSetDevice(m->device));
-  MPC_HIP_TRY(launch_rti_torque(m->md, count, dt, kp, kd, x0, x1, u0, q, qd, tau, (hipStream_t)stream));
+  const hipStream_t s = (hipStream_t)stream;
+  if (precision == MPC_FP64)
+    MPC_HIP_TRY(launch_rti_torque(m->md, count, N, dt, kp, kd, (const double*)x, (const double*)u,
+                                  (const double*)x_meas, (double*)tau, s));
+  else
+    MPC_HIP_TRY(launch_rti_torque(m->md, count, N, dt, kp, kd, (const float*)x, (const float*)u,
+                                  (const float*)x_meas, (float*)tau, s));
   return MPC_OK;
 }

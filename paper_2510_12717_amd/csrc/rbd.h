@@ -26,17 +26,18 @@ struct ModelDev {
   const double* mass;        // [n]
   const double* com;         // [n][3], body frame
   const double* inertia;     // [n][3], principal, about the centre of mass
+  const double* armature;    // [n], added to the mass matrix's diagonal
   const int32_t* foot_body;  // [n_feet]
   const double* foot_offset; // [n_feet][3], body frame
 };
 
 hipError_t launch_rnea(const ModelDev& md, int count, const double* q, const double* qd,
                        const double* qdd, const double* F, double* tau, hipStream_t s);
-hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const double* X,
-                            const double* U, double* A, double* B, double* C, int32_t* status,
-                            hipStream_t s);
-hipError_t launch_rti_torque(const ModelDev& md, int count, double dt, double kp, double kd,
-                             const double* x0, const double* x1, const double* u0, const double* qm,
-                             const double* qdm, double* tau, hipStream_t s);
+template <typename T>
+hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const T* X, const T* U,
+                            T* A, T* B, T* C, int32_t* status, hipStream_t s);
+template <typename T>
+hipError_t launch_rti_torque(const ModelDev& md, int count, int N, double dt, double kp, double kd,
+                             const T* X, const T* U, const T* xm, T* tau, hipStream_t s);
 
 }  // namespace mpc

@@ -73,6 +73,7 @@ class ModelDesc(ctypes.Structure):
                 ("parent", ctypes.c_void_p), ("joint_type", ctypes.c_void_p),
                 ("axis", ctypes.c_void_p), ("offset", ctypes.c_void_p), ("mass", ctypes.c_void_p),
                 ("com", ctypes.c_void_p), ("inertia", ctypes.c_void_p),
+                ("armature", ctypes.c_void_p),
                 ("foot_body", ctypes.c_void_p), ("foot_offset", ctypes.c_void_p)]
 
 
@@ -147,8 +148,8 @@ def lib():
         L.mpc_model_create.argtypes = [P(ModelDesc), I32, P(V)]
         L.mpc_model_destroy.argtypes = [V]
         L.mpc_rnea.argtypes = [V, I32, V, V, V, V, V, V]
-        L.mpc_linearize.argtypes = [V, I32, I32, D, V, V, V, V, V, V, V]
-        L.mpc_rti_torque.argtypes = [V, I32, D, D, D, V, V, V, V, V, V, V]
+        L.mpc_linearize.argtypes = [V, I32, I32, D, I32, V, V, V, V, V, V, V]
+        L.mpc_rti_torque.argtypes = [V, I32, I32, D, D, D, I32, V, V, V, V, V]
         for f in ("mpc_model_create", "mpc_model_destroy", "mpc_rnea", "mpc_linearize",
                   "mpc_rti_torque"):
             getattr(L, f).restype = ctypes.c_int
@@ -583,6 +584,7 @@ class RobotModel:
                           axis=f64(model["axis"], 3), offset=f64(model["offset"], 3),
                           mass=f64(model["mass"], 1), com=f64(model["com"], 3),
                           inertia=f64(model["inertia"], 3),
+                          armature=f64(model.get("armature", np.zeros(n)), 1),
                           foot_body=i32(model["foot_body"]),
                           foot_offset=f64(model["foot_offset"], 3))
         k = self._keep
@@ -592,6 +594,7 @@ class RobotModel:
         d.parent, d.joint_type = k["parent"].ctypes.data, k["jtype"].ctypes.data
         d.axis, d.offset, d.mass = k["axis"].ctypes.data, k["offset"].ctypes.data, k["mass"].ctypes.data
         d.com, d.inertia = k["com"].ctypes.data, k["inertia"].ctypes.data
+        d.armature = k["armature"].ctypes.data
         d.foot_body = k["foot_body"].ctypes.data if self.n_feet else None
         d.foot_offset = k["foot_offset"].ctypes.data if self.n_feet else None
         h = ctypes.c_void_p()
@@ -616,23 +619,53 @@ class RobotModel:
                               _ptr(tau), _stream_handle(stream)))
         return tau
 
-    def linearize(self, x, u, dt: float, stream=None):
-        """x [n_agents, N, nx], u [n_agents, N, nu] -> A, B, c, status."""
+    def linearize(self, x, u, dt: float, out=None, stream=None):
+        """x [n_agents, N + 1, nx] (x_N unused) and u [n_agents, N, nu], the
+        solution's layouts, float64 or float32 -> A, B, c (same dtype), status.
+        ``out``: optional (A, B, c) tensors to write into (e.g. a batch's)."""
         import torch
-        na, N = int(x.shape[0]), int(x.shape[1])
+        na, N = int(x.shape[0]), int(u.shape[1])
+        if tuple(x.shape[1:]) != (N + 1, self.nx) or tuple(u.shape[1:]) != (N, self.nu):
+            raise ValueError("x must be [n, N+1, nx] and u [n, N, nu]")
+        prec = _io_precision(x, u)
         dev = x.device
-        A = torch.empty((na, N, self.nx, self.nx), dtype=torch.float64, device=dev)
-        B = torch.empty((na, N, self.nx, self.nu), dtype=torch.float64, device=dev)
-        c = torch.empty((na, N, self.nx), dtype=torch.float64, device=dev)
+        if out is None:
+            A = torch.empty((na, N, self.nx, self.nx), dtype=x.dtype, device=dev)
+            B = torch.empty((na, N, self.nx, self.nu), dtype=x.dtype, device=dev)
+            c = torch.empty((na, N, self.nx), dtype=x.dtype, device=dev)
+        else:
+            A, B, c = out
+            for t, k in ((A, na * N * self.nx * self.nx), (B, na * N * self.nx * self.nu),
+                         (c, na * N * self.nx)):
+                if t.dtype != x.dtype or t.numel() != k or not t.is_contiguous():
+                    raise ValueError("out tensors must match the shapes and dtype")
         status = torch.zeros(na, dtype=torch.int32, device=dev)
-        _check(lib().mpc_linearize(self._h, na, N, float(dt), _ptr(x), _ptr(u), _ptr(A), _ptr(B),
-                                   _ptr(c), _ptr(status), _stream_handle(stream)))
+        _check(lib().mpc_linearize(self._h, na, N, float(dt), prec, _ptr(x), _ptr(u), _ptr(A),
+                                   _ptr(B), _ptr(c), _ptr(status), _stream_handle(stream)))
         return A, B, c, status
 
-    def rti_torque(self, dt: float, kp: float, kd: float, x0, x1, u0, q, qd, stream=None):
+    def rti_torque(self, dt: float, kp: float, kd: float, x, u, x_meas, stream=None):
+        """x [count, N + 1, nx], u [count, N, nu] (a solution), measured state
+        x_meas [count, nx] -> joint torques [count, n - 6] (same dtype)."""
         import torch
-        tau = torch.empty((int(x0.shape[0]), self.nj), dtype=torch.float64, device=x0.device)
-        _check(lib().mpc_rti_torque(self._h, int(x0.shape[0]), float(dt), float(kp), float(kd),
-                                    _ptr(x0), _ptr(x1), _ptr(u0), _ptr(q), _ptr(qd), _ptr(tau),
-                                    _stream_handle(stream)))
+        cnt, N = int(x.shape[0]), int(u.shape[1])
+        if (tuple(x.shape[1:]) != (N + 1, self.nx) or tuple(u.shape[1:]) != (N, self.nu)
+                or tuple(x_meas.shape) != (cnt, self.nx)):
+            raise ValueError("x must be [n, N+1, nx], u [n, N, nu] and x_meas [n, nx]")
+        prec = _io_precision(x, u, x_meas)
+        tau = torch.empty((cnt, self.nj), dtype=x.dtype, device=x.device)
+        _check(lib().mpc_rti_torque(self._h, cnt, N, float(dt), float(kp), float(kd), prec, _ptr(x),
+                                    _ptr(u), _ptr(x_meas), _ptr(tau), _stream_handle(stream)))
         return tau
+
+
+def _io_precision(*ts):
+    import torch
+    dt = ts[0].dtype
+    if any(t.dtype != dt or not t.is_contiguous() for t in ts):
+        raise ValueError("arrays must be contiguous and share one dtype")
+    if dt == torch.float64:
+        return PRECISIONS["fp64"]
+    if dt == torch.float32:
+        return PRECISIONS["fp32"]
+    raise ValueError("float64 or float32 arrays")

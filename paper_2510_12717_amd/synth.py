@@ -366,8 +366,11 @@ def articulated_model(kind: str = "humanoid", seed: int = 0) -> dict:
     joint angles; qd their rates).  Returns per body: parent (-1 for the first),
     joint type, joint axis (joint frame), the joint frame's offset in the
     parent frame (rotation identity), mass, centre of mass and principal
-    inertia (body frame); per foot: its body and the contact point's offset
-    in that body's frame; foot_dim (6: force and moment, 3: force)."""
+    inertia (body frame), and the armature: the reflected inertia of the
+    joint's geared actuator, U(0.01, 0.05) kg m^2 per actuated joint (0 for the
+    six base coordinates), which adds to the mass matrix's diagonal; per foot:
+    its body and the contact point's offset in that body's frame; foot_dim (6:
+    force and moment, 3: force)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4_000_000, 0 if kind == "humanoid" else 1])))
     bodies = []
     # virtual base joints: x, y, z translation, then z, y, x rotation; massless
@@ -408,13 +411,16 @@ def articulated_model(kind: str = "humanoid", seed: int = 0) -> dict:
                 feet.append((len(bodies) - 1, np.array([0.0, 0.0, -0.21])))
         foot_dim = 3
     nb = len(bodies)
+    arng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+        [seed, 4_000_001, 0 if kind == "humanoid" else 1])))
+    armature = np.concatenate([np.zeros(6), arng.uniform(0.01, 0.05, nb - 6)])
     return dict(
         kind=kind, n=nb, n_joints=nb - 6, gravity=9.81,
         parent=np.array([b[0] for b in bodies], dtype=np.int32),
         jtype=np.array([b[1] for b in bodies], dtype=np.int32),
         axis=np.array([b[2] for b in bodies]), offset=np.array([b[3] for b in bodies]),
         mass=np.array([b[4] for b in bodies]), com=np.array([b[5] for b in bodies]),
-        inertia=np.array([b[6] for b in bodies]),
+        inertia=np.array([b[6] for b in bodies]), armature=armature,
         foot_body=np.array([f[0] for f in feet], dtype=np.int32), foot_offset=np.array([f[1] for f in feet]),
         foot_dim=foot_dim)
 

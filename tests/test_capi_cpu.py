@@ -148,6 +148,7 @@ def _set(key, idx, val):
     (dict(mass=_set("mass", 5, 0.0)), mpc.MPC_ERR_INVALID_ARG),        # massless base body
     (dict(mass=_set("mass", 2, -1.0)), mpc.MPC_ERR_INVALID_ARG),
     (dict(inertia=_set("inertia", (9, 1), np.nan)), mpc.MPC_ERR_INVALID_ARG),
+    (dict(armature=_set("armature", 9, -0.01)), mpc.MPC_ERR_INVALID_ARG),
     (dict(foot_body=_set("foot_body", 0, 4)), mpc.MPC_ERR_INVALID_ARG),
     (dict(foot_dim=4), mpc.MPC_ERR_UNSUPPORTED_SHAPE),
 ])
@@ -172,7 +173,7 @@ def test_rigid_body_calls_reject_null_model():
     L = mpc.lib()
     assert L.mpc_model_destroy(None) == mpc.MPC_ERR_INVALID_ARG
     assert L.mpc_rnea(None, 1, None, None, None, None, None, None) == mpc.MPC_ERR_INVALID_ARG
-    assert L.mpc_linearize(None, 1, 10, 0.02, None, None, None, None, None, None,
+    assert L.mpc_linearize(None, 1, 10, 0.02, 1, None, None, None, None, None, None,
                            None) == mpc.MPC_ERR_INVALID_ARG
-    assert L.mpc_rti_torque(None, 1, 0.02, 1.0, 1.0, None, None, None, None, None, None,
+    assert L.mpc_rti_torque(None, 1, 10, 0.02, 1.0, 1.0, 1, None, None, None, None,
                             None) == mpc.MPC_ERR_INVALID_ARG

@@ -56,11 +56,12 @@ def rel(got, want):
 
 
 def trajectory(m, n_agents, N, seed):
-    """x_k = (q, qd), u_k = (tau, F) of seeded configurations, [n_agents, N, .]."""
-    s = synth.model_states(m, n_agents * N, seed=seed)
-    x = np.concatenate([s["q"], s["qd"]], axis=1).reshape(n_agents, N, -1)
-    u = np.concatenate([s["tau"], s["F"]], axis=1).reshape(n_agents, N, -1)
-    return x, u
+    """x_k = (q, qd), u_k = (tau, F) of seeded configurations in the solution's
+    layouts: x [n_agents, N + 1, nx], u [n_agents, N, nu]."""
+    s = synth.model_states(m, n_agents * (N + 1), seed=seed)
+    x = np.concatenate([s["q"], s["qd"]], axis=1).reshape(n_agents, N + 1, -1)
+    u = np.concatenate([s["tau"], s["F"]], axis=1).reshape(n_agents, N + 1, -1)[:, :N]
+    return x, np.ascontiguousarray(u)
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -121,10 +122,29 @@ def test_linearize_step_structure_and_offset(small_lin, models, kind):
 def test_linearize_flags_nonfinite_agent(models):
     m, g = models[0]["quadruped"], models[1]["quadruped"]
     x, u = trajectory(m, 3, 2, seed=41)
+    x[0, 2, 0] = np.nan  # x_N is not a linearisation point
     x[1, 1, 4] = np.nan
     u[2, 0, 0] = np.inf
     _, _, _, st = g.linearize(dev(x), dev(u), DT)
     assert st.cpu().tolist() == [mpc.AGENT_OK, mpc.AGENT_NONFINITE, mpc.AGENT_NONFINITE]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_linearize_float_io(small_lin, models, kind):
+    """MPC_FP32 io: float inputs and outputs, double arithmetic -- the oracle on
+    the rounded inputs, to the outputs' rounding."""
+    m, g = models[0][kind], models[1][kind]
+    x, u = trajectory(m, 2, 2, seed=31)
+    xf, uf = x.astype(np.float32), u.astype(np.float32)
+    A, B, c, st = (t.cpu().numpy() for t in g.linearize(torch.from_numpy(xf).cuda(),
+                                                          torch.from_numpy(uf).cuda(), DT))
+    assert A.dtype == np.float32 and np.all(st == 0)
+    for a in range(2):
+        for k in range(2):
+            Ao, Bo, co = RB.linearize(m, xf[a, k].astype(np.float64), uf[a, k].astype(np.float64), DT)
+            e = rel(A[a, k], Ao), rel(B[a, k], Bo), rel(c[a, k], co)
+            print(kind, a, k, "float io A/B/c rel err", e)
+            assert max(e) < 2e-7
 
 
 def test_linearize_full_size_sampled(models):
@@ -153,11 +173,11 @@ def test_rti_torque_matches_oracle(models, kind):
     m, g = models[0][kind], models[1][kind]
     n = m["n"]
     cnt = 70
-    x, u = trajectory(m, cnt, 2, seed=61)
+    x, u = trajectory(m, cnt, 3, seed=61)
     meas = synth.model_states(m, cnt, seed=62)
     kp, kd = 120.0, 4.0
-    tau = g.rti_torque(DT, kp, kd, dev(x[:, 0]), dev(x[:, 1]), dev(u[:, 0]), dev(meas["q"]),
-                       dev(meas["qd"])).cpu().numpy()
+    xm = np.concatenate([meas["q"], meas["qd"]], axis=1)
+    tau = g.rti_torque(DT, kp, kd, dev(x), dev(u), dev(xm)).cpu().numpy()
     nj = n - 6
     want = []
     for i in range(cnt):
@@ -221,8 +241,8 @@ def test_rti_iteration_end_to_end(models):
         xg, ug, xo, uo = xs(sol), us(sol), xs(o), us(o)
         q_meas = meas[kind][:n] + 0.01
         qd_meas = meas[kind][n:] - 0.02
-        tau = g.rti_torque(DT, kp, kd, dev(xg[0:1]), dev(xg[1:2]), dev(ug[0:1]), dev(q_meas[None]),
-                           dev(qd_meas[None])).cpu().numpy()[0]
+        xm = np.concatenate([q_meas, qd_meas])[None]
+        tau = g.rti_torque(DT, kp, kd, dev(xg[None]), dev(ug[None]), dev(xm)).cpu().numpy()[0]
         tr = RB.rnea(m, xo[0, :n], xo[0, n:], (xo[1, n:] - xo[0, n:]) / DT, uo[0, nj:])
         want = RB.mpc_torque(m, tr, xo[0, :n], xo[0, n:], q_meas, qd_meas, kp, kd)
         e = rel(tau, want)

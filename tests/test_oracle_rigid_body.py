@@ -32,10 +32,11 @@ def potential(m, q):
 
 def kinetic(m, q, qd, h=1e-30):
     """Kinetic energy from the world poses only: centre-of-mass velocities and
-    angular velocities (Rdot R' = w x) by complex steps along qd."""
+    angular velocities (Rdot R' = w x) by complex steps along qd, plus each
+    actuator rotor's energy (armature_i qd_i^2 / 2)."""
     R, p = poses(m, q)
     Rc, pc = poses(m, q.astype(complex) + 1j * h * qd)
-    T = 0.0
+    T = 0.5 * float(np.sum(m["armature"] * qd * qd))
     for i in range(m["n"]):
         vc = (pc[i] + Rc[i] @ m["com"][i]).imag / h
         W = (Rc[i].imag / h) @ R[i].T
@@ -173,6 +174,7 @@ MUTANTS = [
     ("gravity downward", "a_root[5] = model[\"gravity\"]", "a_root[5] = -model[\"gravity\"]"),
     ("explicit instead of semi-implicit Euler", "return np.concatenate([q + dt * qd1, qd1])",
      "return np.concatenate([q + dt * qd, qd1])"),
+    ("armature dropped", "tau = tau + np.asarray(model[\"armature\"]) * qdd", "tau = tau"),
 ]
 
 

@@ -241,15 +241,9 @@ struct LinLds {
   double S[kMaxBodies][6];      // joint motion subspace
   double v[kMaxBodies][6];      // velocity
   double a[kMaxBodies][6];      // acceleration: qdd = 0 first, then qdd = qdd0
+  // arrays whose lifetimes do not overlap share storage
   union {
-    double Io[kMaxBodies][36];       // own spatial inertia (until the forces at qdd0)
-    double D[kMaxBodies][kMaxCols];  // d qdd / d(x, u), column per thread (from then on)
-  };
-  union {
-    struct {
-      double Rl[kMaxBodies][9];  // body's rotation relative to its parent (placement only)
-      double pl[kMaxBodies][3];  // body's origin in the parent frame (placement only)
-    };
+    double Io[kMaxBodies][36];  // own spatial inertia (until the forces at qdd0)
     struct {
       double dv[kMaxBodies][6];   // S_j x v_parent(j)
       double al[kMaxBodies][6];   // S_j x a_parent(j) - dv_j x v_parent(j)
@@ -257,11 +251,20 @@ struct LinLds {
       double phi[kMaxBodies][6];  // d(composite force of j's subtree)/d qd_j
     };
   };
-  double IC[kMaxBodies][36];    // composite inertia of the subtree
-  double BC[kMaxBodies][36];    // composite of v x* I - I v x
+  union {
+    struct {
+      double Rl[kMaxBodies][9];   // body's rotation relative to its parent (placement only)
+      double pl[kMaxBodies][3];   // body's origin in the parent frame (placement only)
+    };
+    struct {
+      double IC[kMaxBodies][36];  // composite inertia of the subtree
+      double BC[kMaxBodies][36];  // composite of v x* I - I v x
+      double fC[kMaxBodies][6];   // composite force, feet's wrenches subtracted
+      double fiC[kMaxBodies][6];  // composite force of the bodies alone
+    };
+    double D[kMaxBodies][kMaxCols];  // d qdd / d(x, u), column per thread (columns phase on)
+  };
   double hC[kMaxBodies][6];     // composite momentum
-  double fC[kMaxBodies][6];     // composite force, feet's wrenches subtracted
-  double fiC[kMaxBodies][6];    // composite force of the bodies alone
   double Fv[kMaxBodies][6];     // IC_i S_i
   double G[kMaxBodies][6];      // BC_i' S_i
   double eC[kMaxBodies][6];     // the feet's wrenches on i's subtree (fiC - fC)
@@ -277,6 +280,7 @@ struct LinLds {
   uint32_t anc[kMaxBodies];     // ancestors of body i, itself included
   int bad;                      // 1 non-finite input, 2 mass matrix not positive definite
 };
+static_assert(sizeof(LinLds) <= 40 * 1024, "four workgroups per CU");
 
 // One workgroup per (agent, stage): the derivatives of forward dynamics from
 // those of inverse dynamics, d qdd / d x = -M^-1 d ID / d x at qdd = qdd0 and

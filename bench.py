@@ -67,7 +67,9 @@ def parse():
     ap.add_argument("--horizon", type=int, default=10)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "fused"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "fused", "persistent"],
+                    help="persistent (with --uneven): one persistent iteration launch per shape "
+                         "class over every horizon instead of one launch per horizon bucket")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate wall time budget of the CPU-oracle baseline (0 = skip)")
     ap.add_argument("--check-agents", type=int, default=64,
@@ -224,7 +226,7 @@ def uneven(args):
     torch.cuda.set_device(0)
     n = args.agents if args.agents != 4096 else 8192
     b = synth.uneven_batch(n, dtype=np.float32)
-    plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters)
+    plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters, kernel=args.kernel)
     prob = mpc.to_device(b, "fp32")
     t_tune = time.perf_counter()
     groups = plan.autotune(prob, reps=2)
@@ -253,6 +255,7 @@ def uneven(args):
     lat = np.array([a.elapsed_time(c) for a, c in ev])
     st = plan.get_solution()["status"]
     out = {"metric": "MPC QP solves/sec, uneven batch (captured step, autotuned groups)",
+           "kernel": args.kernel,
            "value": n * args.steps / wall, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",

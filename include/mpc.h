@@ -109,7 +109,11 @@ typedef struct {
   int32_t device;           /* HIP device ordinal                                      */
   int32_t kernel;           /* 0 = auto, 1 = generic kernels only, 2 = register-      */
                             /* resident kernels only (UNSUPPORTED_SHAPE if an agent has */
-                            /* no instantiation: FP32, nx/nu 48/30 or 36/24, N <= 20)   */
+                            /* no instantiation: FP32, nx/nu 48/30 or 36/24, N <= 20),  */
+                            /* 3 = as 2, the iterations of each shape class in one      */
+                            /* persistent launch over every horizon (agents taken       */
+                            /* longest first from a work queue) instead of one launch   */
+                            /* per horizon bucket                                       */
   int32_t scaling_iters;    /* Ruiz equilibration rounds before the factor, Alg. 1's    */
                             /* scaling step (0 = off, default; at most 100)             */
   int32_t rho_interval;     /* adaptive rho (OSQP's residual balancing): iterations    */

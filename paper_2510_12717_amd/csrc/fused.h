@@ -25,10 +25,14 @@ size_t fused_agent_floats(int N, int nx, int nu);
 hipError_t fused_set_limits();
 // Launch for the n_launch agents list[0..n_launch) (all of one shape class,
 // horizons at most N).  phase_mask: 1 = factor kernel, 2 = iteration kernel.
+// counter (device int, or nullptr): the iterations run as one persistent
+// launch over the whole list, every horizon, agents taken from the counter.
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
                            int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
                            int warm, State<float> st, float* fws, hipStream_t stream,
-                           int phase_mask);
+                           int phase_mask, int* counter = nullptr);
+// Workgroup size and dynamic LDS of the persistent launch for longest horizon N.
+void fused_persistent_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds);
 
 // The same factor kernel writing the generic operator layout at ws + ows (any
 // horizon): block products in FP64 (prod 0), or BF16 (1) / FP16 (2) operands

@@ -881,14 +881,12 @@ __device__ inline void rollout_exact(const float* __restrict__ A, const float* _
 // progress flags; workgroup barriers separate the set-up, the iterations and
 // the write-out.
 template <int NX, int NU>
-__global__ void __launch_bounds__(64 * kMaxStages)
-k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-                Inputs<float> in, SolverConsts sc_all, int iters, int warm,
-                const float* __restrict__ fws, State<float> st) {
+__device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict__ desc, int agent,
+                                                    Inputs<float> in, SolverConsts sc_all, int iters,
+                                                    int warm, const float* __restrict__ fws,
+                                                    State<float> st) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS, AQ = S::AQ;
-  if ((int)blockIdx.x >= n_launch) return;
-  const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
   const SolverConsts sc = agent_consts(sc_all, agent);
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
@@ -1623,14 +1621,12 @@ __host__ __device__ inline int stream_elements(int N, int iters) { return 3 + it
 // is the register-resident kernel's, taking A_cl,k from the ring; the loader
 // wavefront (SW + 1) keeps three ring elements in flight.
 template <int NX, int NU>
-__global__ void __launch_bounds__(64 * kMaxStages)
-k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
-              Inputs<float> in, SolverConsts sc_all, int iters, int warm,
-              const float* __restrict__ fws, State<float> st) {
+__device__ __forceinline__ void admm_stream_agent(const AgentDesc* __restrict__ desc, int agent,
+                                                  Inputs<float> in, SolverConsts sc_all, int iters,
+                                                  int warm, const float* __restrict__ fws,
+                                                  State<float> st) {
   using S = FS<NX, NU>;
   constexpr int RB = S::RB, CB = S::CB, NXP = S::NXP, NUP = S::NUP, SLOTS = S::SLOTS, AQ = S::AQ;
-  if ((int)blockIdx.x >= n_launch) return;
-  const int agent = list ? list[blockIdx.x] : (int)blockIdx.x;
   const SolverConsts sc = agent_consts(sc_all, agent);
   const AgentDesc d = desc[agent];
   const int N = d.N, M = d.m;
@@ -2281,10 +2277,75 @@ k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ li
   if (tid == 0 && flag[0]) st.status[agent] = AGENT_NONFINITE;
 }
 
+// One workgroup per agent of the launch list.
+template <int NX, int NU>
+__global__ void __launch_bounds__(64 * kMaxStages)
+k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+                Inputs<float> in, SolverConsts sc_all, int iters, int warm,
+                const float* __restrict__ fws, State<float> st) {
+  if ((int)blockIdx.x >= n_launch) return;
+  admm_resident_agent<NX, NU>(desc, list ? list[blockIdx.x] : (int)blockIdx.x, in, sc_all, iters, warm,
+                              fws, st);
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(64 * kMaxStages)
+k_admm_stream(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+              Inputs<float> in, SolverConsts sc_all, int iters, int warm,
+              const float* __restrict__ fws, State<float> st) {
+  if ((int)blockIdx.x >= n_launch) return;
+  admm_stream_agent<NX, NU>(desc, list ? list[blockIdx.x] : (int)blockIdx.x, in, sc_all, iters, warm,
+                            fws, st);
+}
+
+// Persistent form: as many workgroups as the device holds at once, each
+// taking the next agent of the list (longest horizon first) from a counter in
+// device memory until the list is drained; an agent of horizon N <= 11 runs
+// the register-resident body, a longer one the streaming body, in the same
+// workgroup.  Every wavefront of the workgroup takes part in every agent
+// (roles the agent does not need idle at its barriers), so the barriers
+// between agents are met by all of them; the counter is zeroed by k_zero_counter
+// on the same stream before the launch.
+template <int NX, int NU>
+__global__ void __launch_bounds__(64 * kMaxStages)
+k_admm_persistent(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
+                  Inputs<float> in, SolverConsts sc_all, int iters, int warm,
+                  const float* __restrict__ fws, State<float> st, int* __restrict__ counter) {
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();  // the previous agent is written out before its LDS is reused
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = next;
+    if (idx >= n_launch) break;
+    __builtin_amdgcn_s_setprio(0);
+    const int agent = list[idx];
+    if (desc[agent].N + 1 <= kMaxStages)
+      admm_resident_agent<NX, NU>(desc, agent, in, sc_all, iters, warm, fws, st);
+    else
+      admm_stream_agent<NX, NU>(desc, agent, in, sc_all, iters, warm, fws, st);
+  }
+}
+
+__global__ void k_zero_counter(int* counter) { *counter = 0; }
+
+// Workgroup size and dynamic LDS of a persistent launch whose longest horizon
+// is N: enough wavefronts and LDS for the longest agent of either body.
+template <int NX, int NU>
+void persistent_shape(int N, int M, int* threads, size_t* lds) {
+  const int nr = std::min(N, kMaxStages - 1);
+  *threads = 64 * (nr + 1);
+  *lds = iter_lds_layout<NX, NU>(nr, M).total;
+  if (N + 1 > kMaxStages) {
+    *threads = std::max(*threads, 64 * ((N + 1) / 2 + 2));
+    *lds = std::max(*lds, (size_t)stream_lds_layout<NX, NU>(N, M).total);
+  }
+}
+
 template <int NX, int NU>
 hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int M,
                        Inputs<float> in, SolverConsts sc, int iters, int warm, State<float> st,
-                       float* fws, hipStream_t stream, int phase_mask) {
+                       float* fws, hipStream_t stream, int phase_mask, int* counter) {
   if (n_launch <= 0) return hipSuccess;
   const int lf = riccati_lds_bytes<NX, NU>();
   if (phase_mask & 1) {
@@ -2292,6 +2353,23 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
                        d_desc, list, n_launch, in, sc, fws, st.status);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if ((phase_mask & 2) && counter) {
+    int threads = 0;
+    size_t li = 0;
+    persistent_shape<NX, NU>(N, M, &threads, &li);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(k_admm_persistent<NX, NU>), threads, li);
+    if (e != hipSuccess) return e;
+    const int grid = std::max(1, std::min(n_launch, cus * std::max(per_cu, 1)));
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, stream, counter);
+    hipLaunchKernelGGL((k_admm_persistent<NX, NU>), dim3(grid), dim3(threads), li, stream, d_desc, list,
+                       n_launch, in, sc, iters, warm, fws, st, counter);
+    return hipGetLastError();
   }
   if (phase_mask & 2) {
     if (N + 1 <= kMaxStages) {
@@ -2326,9 +2404,13 @@ hipError_t set_limits() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_stream<NX, NU>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_stream<NX, NU>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  // the persistent kernel's own __shared__ word sits before the dynamic LDS
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_persistent<NX, NU>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 16);
 }
 
 template <int NX, int NU>
@@ -2402,15 +2484,21 @@ hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
                            int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
                            int warm, State<float> st, float* fws, hipStream_t stream,
-                           int phase_mask) {
+                           int phase_mask, int* counter) {
   const int m = nu + 4 * n_feet;
   if (nx == 48 && nu == 30)
     return launch_pair<48, 30>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
-                               phase_mask);
+                               phase_mask, counter);
   if (nx == 36 && nu == 24)
     return launch_pair<36, 24>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
-                               phase_mask);
+                               phase_mask, counter);
   return hipErrorInvalidValue;
+}
+
+void fused_persistent_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds) {
+  const int m = nu + 4 * n_feet;
+  if (nx == 48) persistent_shape<48, 30>(N, m, threads, lds);
+  else persistent_shape<36, 24>(N, m, threads, lds);
 }
 
 }  // namespace mpc

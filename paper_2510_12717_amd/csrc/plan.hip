@@ -54,6 +54,8 @@ struct Group {
   double work = 0;         // relative cost used to order launches
   double est = 0;          // cost estimate for the queue assignment (ms once autotuned)
   int queue = 0;           // 0: the caller's stream, k > 0: aux stream k - 1
+  bool persistent = false; // register-resident family: one persistent launch, every horizon
+  int counter = -1;        // its work-queue counter: d_counters[counter]
 };
 
 // Longest group first onto the least-loaded of nq queues (each queue runs its
@@ -131,6 +133,7 @@ struct mpc_plan_s {
   std::vector<Group> groups;
   std::vector<int32_t> hlist;
   int32_t* d_list = nullptr;
+  int* d_counters = nullptr;  // one work-queue counter per persistent group
   float* d_fws = nullptr;
   int64_t nFWS = 0;
   std::vector<hipStream_t> aux;
@@ -199,6 +202,7 @@ static void free_plan(mpc_plan_s* p) {
   hipFree(p->d_desc);
   hipFree(p->d_u0off);
   hipFree(p->d_list);
+  hipFree(p->d_counters);
   hipFree(p->d_fws);
   hipFree(p->d_ws);
   hipFree(p->d_x);
@@ -237,7 +241,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       !(desc->rho_eq_scale > 0) || !(desc->rho_min > 0) || !std::isfinite(desc->rho) ||
       !std::isfinite(desc->sigma) || !std::isfinite(desc->rho_eq_scale) || !std::isfinite(desc->rho_min))
     return fail(MPC_ERR_INVALID_ARG, "solver constants out of range (rho>0, sigma>=0, 0<alpha<2, rho_eq_scale>0, rho_min>0)");
-  if (desc->kernel < 0 || desc->kernel > 2) return fail(MPC_ERR_INVALID_ARG, "unknown kernel selector");
+  if (desc->kernel < 0 || desc->kernel > 3) return fail(MPC_ERR_INVALID_ARG, "unknown kernel selector");
   if (desc->max_refine_sweeps < 0 || desc->max_refine_sweeps > 16 || !(desc->refine_tol >= 0) ||
       !std::isfinite(desc->refine_tol))
     return fail(MPC_ERR_INVALID_ARG, "max_refine_sweeps must be in 0..16 and refine_tol >= 0");
@@ -350,13 +354,14 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   // kernels; every other agent is grouped per shape class and takes the
   // generic kernels, sized for the group's longest horizon.
   const bool mixed = desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE;
+  int n_counters = 0;
   {
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
     for (int a = 0; a < p->n; ++a) {
       const mpc_shape& s = p->shapes[a];
       const bool fok = desc->precision == MPC_FP32 && !p->limits && !p->contacts && !p->kkt &&
                        fused_supported(s.N, s.nx, s.nu, s.n_feet);
-      if (desc->kernel == 2 && !fok) {
+      if ((desc->kernel == 2 || desc->kernel == 3) && !fok) {
         delete p;
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
                     "register-resident kernels requested for an agent they do not support");
@@ -369,7 +374,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       const bool use_fused = fok && desc->kernel != 1 && !mixed;
       const int fam = mixed ? 4 : use_fused ? 2 : 1;
       buckets[std::make_tuple(fam, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim,
-                              use_fused ? fused_bucket(s.N) : 0)]
+                              use_fused && desc->kernel != 3 ? fused_bucket(s.N) : 0)]
           .push_back(a);
     }
     for (auto& kv : buckets) {
@@ -392,6 +397,11 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz, p->limits,
                                     p->contacts ? s0.n_feet * s0.foot_dim : 0);
       if (g.fused_ok) fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
+      if (g.fused_ok && desc->kernel == 3) {
+        g.persistent = true;
+        g.counter = n_counters++;
+        fused_persistent_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
+      }
       for (int32_t a : ag) g.work += (double)p->shapes[a].N * (s0.nx + s0.nu) * (s0.nx + s0.nu);
       g.est = g.work;
       p->hlist.insert(p->hlist.end(), ag.begin(), ag.end());
@@ -440,10 +450,11 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     off += p->shapes[a].nu;
     p->uniform_u &= p->shapes[a].N == p->shapes[0].N && p->shapes[a].nu == p->shapes[0].nu;
   }
-  hipError_t errs[12] = {
+  hipError_t errs[13] = {
       alloc((void**)&p->d_desc, sizeof(AgentDesc) * p->n),
       alloc((void**)&p->d_u0off, sizeof(int64_t) * p->n),
       alloc((void**)&p->d_list, sizeof(int32_t) * p->hlist.size()),
+      alloc((void**)&p->d_counters, sizeof(int) * (size_t)std::max(n_counters, 1)),
       alloc((void**)&p->d_fws, sizeof(float) * (size_t)p->nFWS),
       alloc(&p->d_ws, p->esz * (size_t)p->nWS),
       alloc(&p->d_x, p->esz * (size_t)p->nX),
@@ -674,7 +685,8 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
       PhaseTimer t(p, 1, s);
       HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
                               make_inputs<float>(b), sc, iters, warm,
-                              make_state<float>(p), p->d_fws, s, 2));
+                              make_state<float>(p), p->d_fws, s, 2,
+                              g.persistent ? p->d_counters + g.counter : nullptr));
     }
   } else if (g.family == 4) {
     {

@@ -219,7 +219,7 @@ class Plan:
         d.precision = PRECISIONS[precision]
         d.admm_iters = int(iters)
         d.device = int(device)
-        d.kernel = {"auto": 0, "generic": 1, "fused": 2}[kernel]
+        d.kernel = {"auto": 0, "generic": 1, "fused": 2, "persistent": 3}[kernel]
         for k, v in consts.items():
             setattr(d, k, v)
         h = ctypes.c_void_p()

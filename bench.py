@@ -87,6 +87,8 @@ def parse():
                          "N=16, Q/R condition 1e6, FP32): plain vs Ruiz vs Ruiz + adaptive rho, step "
                          "time and the error of the fixed-iteration iterate against the converged "
                          "optimum (prints its own JSON line)")
+    ap.add_argument("--scan", action="store_true",
+                    help="parallel-in-time against serial Riccati factor on long horizons")
     ap.add_argument("--rti", action="store_true",
                     help="time the real-time iteration's control step on the articulated humanoid "
                          "(linearise, solve, torques, plant step)")
@@ -705,6 +707,44 @@ def rti(args):
     robot.close()
 
 
+def scan(args):
+    """The parallel-in-time Riccati factor against the serial one on long
+    horizons: FP32 plans of humanoid agents (generic kernels, 50 cold
+    iterations), factor time per solve from the plan's phase timers and the
+    whole solve, for a few batch sizes at N = 40 (about the longest horizon whose
+    humanoid iterate fits the generic kernel's LDS) and N = 20."""
+    import torch
+
+    from paper_2510_12717_amd import mpc, synth
+
+    torch.cuda.set_device(0)
+    rows = []
+    for n, N in ((4, 40), (16, 40), (64, 40), (256, 40), (1024, 40), (64, 20), (1024, 20)):
+        b = synth.make_batch([synth.humanoid(N)] * n, seed=0, stream_id=1, dtype=np.float32)
+        prob = mpc.to_device(b, "fp32")
+        row = {"agents": n, "N": N}
+        for name, kw in (("serial", {}), ("scan", {"riccati_scan": 1})):
+            plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters, kernel="generic", **kw)
+            for _ in range(2):
+                plan.solve(prob)
+            torch.cuda.synchronize()
+            plan.set_timing(True)
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                plan.solve(prob)
+            torch.cuda.synchronize()
+            tm = plan.get_timing()
+            row[name] = {"solve_ms": (time.perf_counter() - t0) / reps * 1e3,
+                         "factor_ms": tm["factor"][0] / max(tm["factor"][1], 1)}
+            st = plan.get_solution()["status"]
+            row[name]["status_ok"] = bool((st == 0).all().item())
+            plan.close()
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "riccati_scan", "iters": args.iters, "rows": rows}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -725,6 +765,9 @@ def main():
         return
     if args.rti:
         rti(args)
+        return
+    if args.scan:
+        scan(args)
         return
     if args.uneven:
         uneven(args)

@@ -135,6 +135,15 @@ typedef struct {
                             /* (Eq. (ldl)) and solved by substitution (Eqs.             */
                             /* (backsolve_1)-(backsolve_2)); FP64 or FP32, fixed rho,   */
                             /* no scaling, joint limits or no-slip rows                 */
+  int32_t riccati_scan;     /* 1: the generic path's Riccati factor by a parallel-in-   */
+                            /* time scan over the stages (the backward recursion as a  */
+                            /* product of maps P -> J + A'P(I + CP)^{-1}A, C = B Rt^-1 */
+                            /* B', composed in ceil(log2(N + 1)) doubling rounds, each */
+                            /* round one launch over every agent and stage; then each  */
+                            /* stage's operators from P_{k+1}, stage-parallel): for    */
+                            /* long horizons served with few agents; FP64 arithmetic, */
+                            /* FP64 or FP32 io, nx <= 48, generic kernels, not with    */
+                            /* inner_solve (default 0)                                  */
 } mpc_plan_desc;
 
 /* Fill *desc with the defaults above for n_agents agents of the given shapes. */

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpc_hip.so")
 SOURCES = ["plan.hip", "server.hip", "kernels_generic.hip", "kernels_fused.hip", "kernels_kkt.hip",
-           "kernels_rbd.hip", "noalloc.hip", "scaling.hip"]
+           "kernels_rbd.hip", "kernels_scan.hip", "noalloc.hip", "scaling.hip"]
 ARCH = "gfx950"
 
 

@@ -18,6 +18,7 @@
 // independent across stages.
 #include <math.h>
 
+#include "factor_stage.h"
 #include "generic_ops.h"
 #include "mpc_internal.h"
 #include "stage_rows.h"
@@ -50,43 +51,23 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
   D* PA = Ak + nx * nx;                    // P_{k+1} A_k              nx*nx
   D* Bk = PA + nx * nx;                    // B_k                      nx*nu
   D* PB = Bk + nx * nu;                    // P_{k+1} B_k, then K_k    nx*nu
-  D* Kk = PB;
   D* G = PB + nx * nu;                     // B_k' P A_k               nu*nx
   D* rdg = G + nu * nx;                    // diag Rt_k                nu
   D* rhok = rdg + nu;                      // row penalties of stage k m
   __shared__ int s_flag;
 
-  const T* A = in.A + d.oA;
-  const T* B = in.B + d.oB;
-  const T* c = in.c + d.oc;
   const T* q = in.q + d.oq;
-  const T* r = in.r + d.orr;
   const T* tau = in.tau + d.otau;
   const uint8_t* stance = in.st + d.ost;
-  const T mu = in.mu[d.omu];
-  T* wK = ws + d.ows;
-  T* wAcl = wK + (int64_t)N * nu * nx;
-  T* wHi = wAcl + (int64_t)N * nx * nx;
-  T* wS = wHi + (int64_t)N * nu * nu;
-  T* wl = wS + (int64_t)N * nx;
+  // workspace: K, A_cl, H^-1, s per stage (written by factor_stage), then the row bounds
+  T* wl = ws + d.ows + (int64_t)N * (nu * nx + nx * nx + nu * nu + nx);
   T* wh = wl + (int64_t)N * m;
   T* wrho = wh + (int64_t)N * m;
 
   // Non-finite inputs mark the agent and stop it (no other agent is touched).
   if (tid == 0) s_flag = 0;
   __syncthreads();
-  bool ok = finite_all(A, (int64_t)N * nx * nx, tid, nt) && finite_all(B, (int64_t)N * nx * nu, tid, nt) &&
-            finite_all(c, (int64_t)N * nx, tid, nt) && finite_all(q, nx, tid, nt) &&
-            finite_all(r, nu, tid, nt) && finite_all(in.xr + d.oxr, (int64_t)(N + 1) * nx, tid, nt) &&
-            finite_all(in.x0 + d.ox0, nx, tid, nt) && finite_all(tau, d.n_tau, tid, nt) &&
-            (bool)isfinite(mu) && (!in.uref || finite_all(in.uref + d.our, (int64_t)N * nu, tid, nt));
-  if (in.xlo)
-    for (int i = tid; i < nx; i += nt) {
-      const T lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
-      ok &= !isnan(lo) && !isnan(hi) && lo <= hi;
-    }
-  if (in.J) ok &= finite_all(in.J + d.oJ, (int64_t)d.n_feet * d.foot_dim * nx, tid, nt);
-  if (!ok) atomicOr(&s_flag, 1);
+  if (!agent_inputs_ok(in, d, tid, nt)) atomicOr(&s_flag, 1);
   __syncthreads();
   if (s_flag) {
     if (tid == 0) status[a] = AGENT_NONFINITE;
@@ -110,136 +91,11 @@ k_setup_factor(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ l
   __syncthreads();
 
   for (int k = N - 1; k >= 0; --k) {
-    const T* Ag = A + (int64_t)k * nx * nx;
-    const T* Bg = B + (int64_t)k * nx * nu;
-    for (int idx = tid; idx < nx * nx; idx += nt) Ak[idx] = (D)Ag[idx];
-    for (int idx = tid; idx < nx * nu; idx += nt) Bk[idx] = (D)Bg[idx];
-    for (int i = tid; i < m; i += nt) {
-      D lo, hi;
-      row_bounds<D, T>(d, i, stance + k * d.n_feet, tau, sc, lo, hi, rhok[i]);
-    }
-    __syncthreads();
-    for (int j = tid; j < nu; j += nt) rdg[j] = rtilde_diag<D, D>(d, j, (D)r[j], (D)mu, rhok, sc);
-    __syncthreads();
-    for (int idx = tid; idx < nx * nu; idx += nt) {
-      const int i = idx / nu, j = idx % nu;
-      D acc = 0;
-      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Bk[t * nu + j];
-      PB[idx] = acc;
-    }
-    for (int idx = tid; idx < nx * nx; idx += nt) {
-      const int i = idx / nx, j = idx % nx;
-      D acc = 0;
-      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Ak[t * nx + j];
-      PA[idx] = acc;
-    }
-    for (int i = tid; i < nx; i += nt) {
-      D acc = 0;
-      for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * (D)c[(int64_t)k * nx + t];
-      wS[(int64_t)k * nx + i] = (T)acc;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nu * nu; idx += nt) {
-      const int i = idx / nu, j = idx % nu;
-      D acc = (i == j) ? rdg[i] : 0.0;
-      for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PB[t * nu + j];
-      H[idx] = acc;
-    }
-    for (int idx = tid; idx < nu * nx; idx += nt) {
-      const int i = idx / nx, j = idx % nx;
-      D acc = 0;
-      for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PA[t * nx + j];
-      G[idx] = acc;
-    }
-    __syncthreads();
-    // Right-looking Cholesky of H_k in place (lower triangle).
-    for (int j = 0; j < nu; ++j) {
-      if (tid == 0) {
-        const double v = H[j * nu + j];
-        if (!(v > 0.0)) s_flag = 1;
-        H[j * nu + j] = sqrt(v);
-      }
-      __syncthreads();
-      if (s_flag) break;
-      for (int i = j + 1 + tid; i < nu; i += nt) H[i * nu + j] /= H[j * nu + j];
-      __syncthreads();
-      const int rem = nu - j - 1;
-      for (int idx = tid; idx < rem * rem; idx += nt) {
-        const int i = j + 1 + idx / rem, cc = j + 1 + idx % rem;
-        if (cc <= i) H[i * nu + cc] -= H[i * nu + j] * H[cc * nu + j];
-      }
-      __syncthreads();
-    }
-    if (s_flag) {
+    FactorLds<D> F{H, P, Ak, PA, Bk, PB, G, rdg, rhok};
+    if (!factor_stage<T>(in, sc, d, k, F, ws, &s_flag, true, tid, nt)) {
       if (tid == 0) status[a] = AGENT_NOT_PD;
       return;
     }
-    // K_k = -H_k^{-1} G_k into LDS (over the dead P B_k) and H_k^{-1} straight
-    // into the workspace, one column per thread.
-    // The column is carried in double registers (nu <= 32, loops unrolled so
-    // the array stays in VGPRs) and rounded to T once at the end.
-    for (int col = tid; col < nx + nu; col += nt) {
-      const bool isK = col < nx;
-      const int cc = isK ? col : col - nx;
-      const int ld = isK ? nx : nu;
-      double v[32];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        if (i < nu) {
-          double acc = isK ? -G[i * nx + cc] : (i == cc ? 1.0 : 0.0);
-#pragma unroll
-          for (int t = 0; t < i; ++t) acc -= H[i * nu + t] * v[t];
-          v[i] = acc / H[i * nu + i];
-        }
-      }
-#pragma unroll
-      for (int i = 31; i >= 0; --i) {
-        if (i < nu) {
-          double acc = v[i];
-#pragma unroll
-          for (int t = i + 1; t < 32; ++t)
-            if (t < nu) acc -= H[t * nu + i] * v[t];
-          v[i] = acc / H[i * nu + i];
-        }
-      }
-      if (isK) {
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-          if (i < nu) Kk[i * ld + cc] = v[i];
-      } else {
-        T* dst = wHi + (int64_t)k * nu * nu;
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-          if (i < nu) dst[i * ld + cc] = (T)v[i];
-      }
-    }
-    __syncthreads();
-    // P_k = Q + sigma I + A_k' P A_k + G_k' K_k, symmetrised as (P_k + P_k')/2:
-    // one thread owns the pair (i, j), (j, i) and overwrites P (P_{k+1} is dead).
-    for (int idx = tid; idx < nx * nx; idx += nt) {
-      const int i = idx / nx, j = idx % nx;
-      if (j >= i) {
-        D a1 = ((i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0) +
-               contact_weight<D>(in, d, k, i, j, sc),
-          a2 = a1;
-        for (int t = 0; t < nx; ++t) {
-          a1 += Ak[t * nx + i] * PA[t * nx + j];
-          a2 += Ak[t * nx + j] * PA[t * nx + i];
-        }
-        for (int t = 0; t < nu; ++t) {
-          a1 += G[t * nx + i] * Kk[t * nx + j];
-          a2 += G[t * nx + j] * Kk[t * nx + i];
-        }
-        const D v = 0.5 * (a1 + a2);
-        P[i * nx + j] = v;
-        P[j * nx + i] = v;
-      }
-      D acl = Ak[idx];
-      for (int t = 0; t < nu; ++t) acl += Bk[i * nu + t] * Kk[t * nx + j];
-      wAcl[(int64_t)k * nx * nx + idx] = (T)acl;
-    }
-    for (int idx = tid; idx < nu * nx; idx += nt) wK[(int64_t)k * nu * nx + idx] = (T)Kk[idx];
-    __syncthreads();
   }
   if (tid == 0) status[a] = AGENT_OK;
 }

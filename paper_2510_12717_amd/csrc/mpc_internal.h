@@ -110,6 +110,15 @@ inline size_t kkt_admm_lds(int N, int nx, int nu, int m) {
               2 * (size_t)N * (nu + nx) + 3 * (size_t)nx);
 }
 hipError_t kkt_set_lds_limits(size_t lds_factor, size_t lds_admm);
+
+// The generic Riccati factor as a parallel-in-time scan (kernels_scan.hip):
+// element buffers E0, E1 of scan_elements_bytes each for the launch list.
+size_t scan_elements_bytes(int n_agents, int Nmax, int nx);
+template <typename T>
+hipError_t launch_scan_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch, int Nmax, int nx,
+                              int nu, int m, Inputs<T> in, SolverConsts sc, T* ws, double* E0, double* E1,
+                              int32_t* status, size_t lds_ops, hipStream_t s);
+hipError_t scan_set_limits();
 template <typename T>
 hipError_t launch_kkt_factor(const AgentDesc* d_desc, const int32_t* list, int n_launch, Inputs<T> in,
                              SolverConsts sc, T* ws, int32_t* status, size_t lds,

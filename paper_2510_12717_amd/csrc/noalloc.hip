@@ -99,10 +99,10 @@ extern "C" mpc_status mpc_solve_noalloc(const mpc_plan_desc* desc, const mpc_pro
     return api_fail(MPC_ERR_INVALID_ARG, "the no-allocation solve is FP32 only");
   if (desc->admm_iters <= 0) return api_fail(MPC_ERR_INVALID_ARG, "admm_iters must be > 0");
   if (desc->scaling_iters != 0 || desc->rho_interval != 0 || desc->joint_limits != 0 ||
-      desc->no_slip != 0 || desc->inner_solve != 0 || b->x_lo || b->J_foot ||
-      b->x_hi)
+      desc->no_slip != 0 || desc->inner_solve != 0 || desc->riccati_scan != 0 || b->x_lo ||
+      b->J_foot || b->x_hi)
     return api_fail(MPC_ERR_INVALID_ARG,
-                    "the no-allocation solve runs the Riccati solve without scaling, joint limits or no-slip rows and with a fixed rho");
+                    "the no-allocation solve runs the serial Riccati solve without scaling, joint limits or no-slip rows and with a fixed rho");
   if (!(desc->rho > 0) || !(desc->sigma >= 0) || !(desc->alpha > 0 && desc->alpha < 2) ||
       !(desc->rho_eq_scale > 0) || !(desc->rho_min > 0))
     return api_fail(MPC_ERR_INVALID_ARG, "solver constants out of range");

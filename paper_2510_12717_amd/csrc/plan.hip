@@ -56,6 +56,7 @@ struct Group {
   int queue = 0;           // 0: the caller's stream, k > 0: aux stream k - 1
   bool persistent = false; // register-resident family: one persistent launch, every horizon
   int counter = -1;        // its work-queue counter: d_counters[counter]
+  int64_t scan_off = 0;    // parallel-in-time factor: its element buffers at d_scan + scan_off
 };
 
 // Longest group first onto the least-loaded of nq queues (each queue runs its
@@ -134,6 +135,8 @@ struct mpc_plan_s {
   std::vector<int32_t> hlist;
   int32_t* d_list = nullptr;
   int* d_counters = nullptr;  // one work-queue counter per persistent group
+  bool scan = false;          // generic factor by the parallel-in-time scan
+  double* d_scan = nullptr;   // its element buffers (Group::scan_off)
   float* d_fws = nullptr;
   int64_t nFWS = 0;
   std::vector<hipStream_t> aux;
@@ -186,6 +189,7 @@ extern "C" void mpc_plan_desc_default(mpc_plan_desc* d) {
   d->joint_limits = 0;
   d->no_slip = 0;
   d->inner_solve = 0;
+  d->riccati_scan = 0;
 }
 
 extern "C" const char* mpc_last_error(void) { return mpc::g_err.c_str(); }
@@ -203,6 +207,7 @@ static void free_plan(mpc_plan_s* p) {
   hipFree(p->d_u0off);
   hipFree(p->d_list);
   hipFree(p->d_counters);
+  hipFree(p->d_scan);
   hipFree(p->d_fws);
   hipFree(p->d_ws);
   hipFree(p->d_x);
@@ -264,6 +269,14 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
                 "no-slip rows run on the generic kernels in FP64 or FP32, without scaling");
   if (desc->inner_solve != 0 && desc->inner_solve != 1)
     return fail(MPC_ERR_INVALID_ARG, "inner_solve must be 0 or 1");
+  if (desc->riccati_scan != 0 && desc->riccati_scan != 1)
+    return fail(MPC_ERR_INVALID_ARG, "riccati_scan must be 0 or 1");
+  if (desc->riccati_scan &&
+      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE || desc->inner_solve ||
+       desc->kernel == 2 || desc->kernel == 3))
+    return fail(MPC_ERR_INVALID_ARG,
+                "the parallel-in-time factor runs on the generic kernels in FP64 or FP32, "
+                "not with the KKT inner solve");
   if (desc->inner_solve &&
       (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
        desc->scaling_iters > 0 || desc->rho_interval > 0 || desc->kernel == 2 ||
@@ -274,6 +287,9 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   for (int a = 0; a < desc->n_agents; ++a) {
     mpc_status vs = validate_shape(desc->shapes[a], a);
     if (vs != MPC_OK) return vs;
+    if (desc->riccati_scan && desc->shapes[a].nx > 48)
+      return fail(MPC_ERR_UNSUPPORTED_SHAPE,
+                  "the parallel-in-time factor keeps a combine's six nx x nx blocks in LDS: nx <= 48");
   }
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
@@ -289,6 +305,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   p->limits = desc->joint_limits != 0;
   p->contacts = desc->no_slip != 0;
   p->kkt = desc->inner_solve != 0;
+  p->scan = desc->riccati_scan != 0;
 
   p->hdesc.resize(p->n);
   AgentDesc cur{};
@@ -371,7 +388,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
                     "mixed precision is built for (nx, nu) = (48, 30) and (36, 24) only");
       }
-      const bool use_fused = fok && desc->kernel != 1 && !mixed;
+      const bool use_fused = fok && desc->kernel != 1 && !mixed && !p->scan;
       const int fam = mixed ? 4 : use_fused ? 2 : 1;
       buckets[std::make_tuple(fam, s.nx, s.nu, s.n_tau, s.n_feet, s.foot_dim,
                               use_fused && desc->kernel != 3 ? fused_bucket(s.N) : 0)]
@@ -436,6 +453,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   }
   e = generic_set_lds_limits(p->lds_factor, p->lds_admm, p->lds_res);
   if (e == hipSuccess && p->kkt) e = kkt_set_lds_limits(p->lds_kkt_factor, p->lds_kkt_admm);
+  if (e == hipSuccess && p->scan) e = scan_set_limits();
   if (e == hipSuccess && !p->fp64) e = fused_set_limits();
   if (e != hipSuccess) {
     delete p;
@@ -498,6 +516,15 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     if (p->kkt) {
       if (se == hipSuccess) se = alloc(&p->d_zd, p->esz * (size_t)oc);
       if (se == hipSuccess) se = alloc(&p->d_yd, p->esz * (size_t)oc);
+    }
+    if (p->scan) {
+      // two element buffers per group, side by side
+      size_t off = 0;
+      for (Group& g : p->groups) {
+        g.scan_off = (int64_t)(off / sizeof(double));
+        off += 2 * scan_elements_bytes(g.count, g.N, g.nx);
+      }
+      if (se == hipSuccess) se = alloc((void**)&p->d_scan, std::max<size_t>(off, 16));
     }
     if (p->contacts) {
       p->nZC = ozc;
@@ -722,7 +749,12 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
       // FP32 plans of the shapes the matrix-core factor is built for take it
       // (FP64 products, generic operator layout) at any horizon
       // (the no-slip rows' dense state weight is added by the generic factor only)
-      if (!p->fp64 && !p->contacts && mixed_supported(g.nx, g.nu))
+      if (p->scan) {
+        double* E0 = p->d_scan + g.scan_off;
+        HIP_TRY(launch_scan_factor<T>(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.nu + 4 * g.n_feet, in, sc,
+                                      (T*)p->d_ws, E0, E0 + scan_elements_bytes(g.count, g.N, g.nx) / sizeof(double),
+                                      p->d_status, g.lds_factor, s));
+      } else if (!p->fp64 && !p->contacts && mixed_supported(g.nx, g.nu))
         HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu, 0, make_inputs<float>(b),
                                     sc, (float*)p->d_ws, p->d_status, s));
       else

@@ -223,9 +223,9 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   if (sd.max_refine_sweeps < 0 || sd.max_refine_sweeps > 16 || !(sd.refine_tol >= 0))
     return api_fail(MPC_ERR_INVALID_ARG, "refinement settings out of range");
   if (sd.scaling_iters != 0 || sd.rho_interval != 0 || sd.joint_limits != 0 || sd.no_slip != 0 ||
-      sd.inner_solve != 0)
+      sd.inner_solve != 0 || sd.riccati_scan != 0)
     return api_fail(MPC_ERR_INVALID_ARG,
-                    "the served loop runs the Riccati solve without scaling, joint limits or no-slip rows and with a fixed rho");
+                    "the served loop runs the serial Riccati solve without scaling, joint limits or no-slip rows and with a fixed rho");
   if (desc->max_batch < 1 || desc->max_batch > (1 << 20) || desc->max_inflight < 1 ||
       desc->max_inflight > 8)
     return api_fail(MPC_ERR_INVALID_ARG, "max_batch must be in 1..2^20 and max_inflight in 1..8");

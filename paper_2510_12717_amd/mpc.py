@@ -40,7 +40,8 @@ class PlanDesc(ctypes.Structure):
                 ("device", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("scaling_iters", ctypes.c_int32), ("rho_interval", ctypes.c_int32),
                 ("rho_tolerance", ctypes.c_double), ("joint_limits", ctypes.c_int32),
-                ("no_slip", ctypes.c_int32), ("inner_solve", ctypes.c_int32)]
+                ("no_slip", ctypes.c_int32), ("inner_solve", ctypes.c_int32),
+                ("riccati_scan", ctypes.c_int32)]
 
 
 class ProblemBatch(ctypes.Structure):

@@ -89,6 +89,8 @@ def parse():
                          "optimum (prints its own JSON line)")
     ap.add_argument("--scan", action="store_true",
                     help="parallel-in-time against serial Riccati factor on long horizons")
+    ap.add_argument("--no-slip", action="store_true",
+                    help="with --rti: the QP carries the feet's no-slip rows from the linearisation")
     ap.add_argument("--rti", action="store_true",
                     help="time the real-time iteration's control step on the articulated humanoid "
                          "(linearise, solve, torques, plant step)")
@@ -616,7 +618,7 @@ def rti(args):
     npd = np.float64 if prec == "fp64" else np.float32
     b = synth.make_batch([sh] * n, seed=0, stream_id=1, dtype=npd)
     prob = mpc.to_device(b, prec)
-    plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters)
+    plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters, no_slip=1 if args.no_slip else 0)
     st = synth.model_states(model, n * (N + 1), seed=5)
     X = torch.from_numpy(np.concatenate([st["q"], st["qd"]], 1).reshape(n, N + 1, sh.nx)
                          .astype(npd)).cuda()
@@ -640,7 +642,13 @@ def rti(args):
     prob["tau_max"].fill_(200.0)
     prob["mu"].fill_(0.8)
     prob["x0"].copy_(X[:, 0].reshape(-1))
+    if args.no_slip:  # the feet's no-slip rows, re-linearised every step with A, B, c
+        prob["J_foot"] = torch.empty(n * sh.n_feet * sh.foot_dim * sh.nx, dtype=X.dtype, device="cuda")
     sol = mpc.solution_buffers(b.shapes, prec)
+    if args.no_slip:
+        nzc = n * N * sh.n_feet * sh.foot_dim
+        sol["zc"] = torch.empty(nzc, dtype=X.dtype, device="cuda")
+        sol["yc"] = torch.empty(nzc, dtype=X.dtype, device="cuda")
     sol["x"], sol["u"] = X.view(-1), U.view(-1)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1234)
@@ -656,7 +664,8 @@ def rti(args):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if timed else None
         if timed:
             ev[0].record(stream)
-        _, _, _, ls = robot.linearize(X, U, dt, out=(prob["A"], prob["B"], prob["c"]), stream=stream)
+        _, _, _, ls = robot.linearize(X, U, dt, out=(prob["A"], prob["B"], prob["c"]),
+                                      J_foot=prob.get("J_foot"), stream=stream)
         lin_status.bitwise_or_(ls)
         if timed:
             ev[1].record(stream)
@@ -700,7 +709,7 @@ def rti(args):
            "qp_failed_after_warmup_steps": bad_by_step,
            "max_abs_x_finite_agents": float(X[torch.isfinite(X).flatten(1).all(1)].abs().max()),
            "torque_finite": bool(torch.isfinite(tau).all()),
-           "iters": args.iters, "precision": prec,
+           "iters": args.iters, "precision": prec, "no_slip_rows": bool(args.no_slip),
            "dtype": ("f64" if prec == "fp64" else "f32 io, f64 dynamics and Riccati factor")}
     print(json.dumps(out))
     plan.close()

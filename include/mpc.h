@@ -526,10 +526,14 @@ mpc_status mpc_rnea(mpc_model_t model, int32_t count, const double* q, const dou
  * arithmetic stays double).  status [n] (cleared by the caller): an agent with
  * a non-finite x_k or u_k gets MPC_AGENT_NONFINITE, else one whose mass
  * matrix fails to factor MPC_AGENT_NOT_PD; its A, B, c are then left as they
- * were or partly written. */
+ * were or partly written.  J_foot (NULL to skip) [n][n_feet*foot_dim][nx]:
+ * the no-slip rows of Eq. (mpc_formulation) at x_0 in mpc_problem_batch's
+ * J_foot layout -- zero on the positions; on the velocities, per foot, the
+ * contact point's world linear velocity and (6D feet) the foot's angular
+ * velocity per unit qd. */
 mpc_status mpc_linearize(mpc_model_t model, int32_t n_agents, int32_t N, double dt, int32_t precision,
-                         const void* x, const void* u, void* A, void* B, void* c, int32_t* status,
-                         void* stream);
+                         const void* x, const void* u, void* A, void* B, void* c, void* J_foot,
+                         int32_t* status, void* stream);
 
 /* f_RNEA and Eq. (mpc_torque): from the first stages of a QP solution (x
  * [count][N+1][nx], u [count][N][nu], mpc_get_solution's layouts),

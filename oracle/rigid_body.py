@@ -25,7 +25,9 @@ that tests can differentiate it by complex steps:
 * ``linearize``: the QP data of one stage about (x, u): A = df/dx, B = df/du
   by complex steps (exact to rounding), c = f(x, u) - A x - B u;
 * ``mpc_torque``: Eq. (mpc_torque) for the joints, tau = Kp (q_mpc - q) +
-  Kd (qd_mpc - qd) + tau_rnea.
+  Kd (qd_mpc - qd) + tau_rnea;
+* ``foot_jacobian``, ``noslip_rows``: the feet's velocity Jacobian and the
+  no-slip rows J_f v = 0 of Eq. (mpc_formulation) over the state.
 
 Conventions (readings): a joint's frame sits at its offset in the parent
 frame with the parent's orientation; a revolute joint rotates the body frame
@@ -140,6 +142,33 @@ def foot_wrench_world(model, q, F):
         moment = F[f * fd + 3:f * fd + 6] if fd == 6 else np.zeros(3)
         out.append((b, np.concatenate([moment + np.cross(pt, force), force])))
     return out
+
+
+def foot_jacobian(model, q, h: float = 1e-30):
+    """The feet's velocity Jacobian in the world frame: per foot, the contact
+    point's linear velocity (3 rows), then for 6D feet the foot body's angular
+    velocity (3 rows), per unit generalised velocity ([n_feet*foot_dim][n]),
+    by complex steps of the world poses along each coordinate (the coordinates
+    are additive, so d/dq_j of a pose is its velocity for qd = e_j)."""
+    n, fd = model["n"], model["foot_dim"]
+    _, _, R, p = kinematics(model, q)
+    J = np.zeros((len(model["foot_body"]) * fd, n))
+    for j in range(n):
+        _, _, Rc, pc = kinematics(model, q + 1j * h * np.eye(n)[j])
+        for f, b in enumerate(model["foot_body"]):
+            J[f * fd:f * fd + 3, j] = (pc[b] + Rc[b] @ model["foot_offset"][f]).imag / h
+            if fd == 6:
+                W = (Rc[b].imag / h) @ R[b].T
+                J[f * fd + 3:f * fd + 6, j] = [W[2, 1], W[0, 2], W[1, 0]]
+    return J
+
+
+def noslip_rows(model, x):
+    """The no-slip rows J_f v = 0 over the state x = (q, qd): zero on the
+    positions, the feet's velocity Jacobian at q on the velocities."""
+    n = model["n"]
+    J = foot_jacobian(model, np.asarray(x[:n], dtype=float))
+    return np.hstack([np.zeros_like(J), J])
 
 
 def rnea(model, q, qd, qdd, F=None):

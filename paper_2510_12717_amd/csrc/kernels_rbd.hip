@@ -292,7 +292,8 @@ static_assert(sizeof(LinLds) <= 40 * 1024, "four workgroups per CU");
 template <typename T>
 __global__ void __launch_bounds__(kLinThreads)
 k_linearize(ModelDev md, int N, double dt, const T* __restrict__ X, const T* __restrict__ U,
-            T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, int32_t* __restrict__ status) {
+            T* __restrict__ A, T* __restrict__ B, T* __restrict__ C, T* __restrict__ Jf,
+            int32_t* __restrict__ status) {
   __shared__ LinLds L;
   const int tid = threadIdx.x;
   const int n = md.n, nx = 2 * n, nj = n - 6, nf = md.n_feet, fd = md.foot_dim;
@@ -376,6 +377,24 @@ k_linearize(ModelDev md, int N, double dt, const T* __restrict__ X, const T* __r
       }
   }
   __syncthreads();
+  // the feet's no-slip rows J_f v = 0 at the stage-0 configuration: zero on
+  // the positions; on the velocities the contact point's linear velocity and
+  // (6D feet) the foot's angular velocity per unit qd_i, i an ancestor of the foot
+  if (Jf && ak % N == 0) {
+    const int nfd = nf * fd;
+    T* Jo = Jf + (ak / N) * (int64_t)nfd * nx;
+    for (int idx = tid; idx < nfd * nx; idx += kLinThreads) {
+      const int row = idx / nx, col = idx % nx, f = row / fd, comp = row % fd;
+      double v = 0.0;
+      if (col >= n && (L.anc[md.foot_body[f]] >> (col - n) & 1u)) {
+        const S6 Si = ld6(L.S[col - n]);
+        const V3 sel = comp < 3 ? Si.b + cross(Si.a, ld3(L.pf[f])) : Si.a;
+        const int c3 = comp % 3;
+        v = c3 == 0 ? sel.x : c3 == 1 ? sel.y : sel.z;
+      }
+      Jo[idx] = (T)v;
+    }
+  }
   // (2) velocities
   if (tid < n) {
     S6 v = s6(v3(0, 0, 0), v3(0, 0, 0));
@@ -741,11 +760,11 @@ hipError_t launch_rnea(const ModelDev& md, int count, const double* q, const dou
 
 template <typename T>
 hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const T* X, const T* U,
-                            T* A, T* B, T* C, int32_t* status, hipStream_t s) {
+                            T* A, T* B, T* C, T* Jf, int32_t* status, hipStream_t s) {
   const int64_t blocks = (int64_t)n_agents * N;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_linearize<T>, dim3((unsigned)blocks), dim3(kLinThreads), 0, s, md, N, dt, X, U, A,
-                     B, C, status);
+                     B, C, Jf, status);
   return hipGetLastError();
 }
 
@@ -880,7 +899,7 @@ extern "C" mpc_status mpc_rnea(mpc_model_t m, int32_t count, const double* q, co
 
 extern "C" mpc_status mpc_linearize(mpc_model_t m, int32_t n_agents, int32_t N, double dt,
                                     int32_t precision, const void* x, const void* u, void* A, void* B,
-                                    void* c, int32_t* status, void* stream) {
+                                    void* c, void* J_foot, int32_t* status, void* stream) {
   using namespace mpc;
   if (!m || n_agents < 0 || N < 1 || N > 64 || !(dt > 0))
     return api_fail(MPC_ERR_INVALID_ARG, "n_agents >= 0, 1 <= N <= 64 and dt > 0 required");
@@ -892,10 +911,10 @@ extern "C" mpc_status mpc_linearize(mpc_model_t m, int32_t n_agents, int32_t N, 
   const hipStream_t s = (hipStream_t)stream;
   if (precision == MPC_FP64)
     MPC_HIP_TRY(launch_linearize(m->md, n_agents, N, dt, (const double*)x, (const double*)u, (double*)A,
-                                 (double*)B, (double*)c, status, s));
+                                 (double*)B, (double*)c, (double*)J_foot, status, s));
   else
     MPC_HIP_TRY(launch_linearize(m->md, n_agents, N, dt, (const float*)x, (const float*)u, (float*)A,
-                                 (float*)B, (float*)c, status, s));
+                                 (float*)B, (float*)c, (float*)J_foot, status, s));
   return MPC_OK;
 }
 

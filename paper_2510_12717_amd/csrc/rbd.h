@@ -35,7 +35,7 @@ hipError_t launch_rnea(const ModelDev& md, int count, const double* q, const dou
                        const double* qdd, const double* F, double* tau, hipStream_t s);
 template <typename T>
 hipError_t launch_linearize(const ModelDev& md, int n_agents, int N, double dt, const T* X, const T* U,
-                            T* A, T* B, T* C, int32_t* status, hipStream_t s);
+                            T* A, T* B, T* C, T* Jf, int32_t* status, hipStream_t s);
 template <typename T>
 hipError_t launch_rti_torque(const ModelDev& md, int count, int N, double dt, double kp, double kd,
                              const T* X, const T* U, const T* xm, T* tau, hipStream_t s);

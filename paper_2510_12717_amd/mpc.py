@@ -149,7 +149,7 @@ def lib():
         L.mpc_model_create.argtypes = [P(ModelDesc), I32, P(V)]
         L.mpc_model_destroy.argtypes = [V]
         L.mpc_rnea.argtypes = [V, I32, V, V, V, V, V, V]
-        L.mpc_linearize.argtypes = [V, I32, I32, D, I32, V, V, V, V, V, V, V]
+        L.mpc_linearize.argtypes = [V, I32, I32, D, I32, V, V, V, V, V, V, V, V]
         L.mpc_rti_torque.argtypes = [V, I32, I32, D, D, D, I32, V, V, V, V, V]
         for f in ("mpc_model_create", "mpc_model_destroy", "mpc_rnea", "mpc_linearize",
                   "mpc_rti_torque"):
@@ -620,10 +620,12 @@ class RobotModel:
                               _ptr(tau), _stream_handle(stream)))
         return tau
 
-    def linearize(self, x, u, dt: float, out=None, stream=None):
+    def linearize(self, x, u, dt: float, out=None, J_foot=None, stream=None):
         """x [n_agents, N + 1, nx] (x_N unused) and u [n_agents, N, nu], the
         solution's layouts, float64 or float32 -> A, B, c (same dtype), status.
-        ``out``: optional (A, B, c) tensors to write into (e.g. a batch's)."""
+        ``out``: optional (A, B, c) tensors to write into (e.g. a batch's);
+        ``J_foot``: optional tensor [n_agents * n_feet * foot_dim * nx] that
+        receives the no-slip rows at x_0."""
         import torch
         na, N = int(x.shape[0]), int(u.shape[1])
         if tuple(x.shape[1:]) != (N + 1, self.nx) or tuple(u.shape[1:]) != (N, self.nu):
@@ -640,9 +642,13 @@ class RobotModel:
                          (c, na * N * self.nx)):
                 if t.dtype != x.dtype or t.numel() != k or not t.is_contiguous():
                     raise ValueError("out tensors must match the shapes and dtype")
+        if J_foot is not None and (J_foot.dtype != x.dtype or not J_foot.is_contiguous() or
+                                   J_foot.numel() != na * self.n_feet * self.foot_dim * self.nx):
+            raise ValueError("J_foot must hold n_agents * n_feet * foot_dim * nx of x's dtype")
         status = torch.zeros(na, dtype=torch.int32, device=dev)
         _check(lib().mpc_linearize(self._h, na, N, float(dt), prec, _ptr(x), _ptr(u), _ptr(A),
-                                   _ptr(B), _ptr(c), _ptr(status), _stream_handle(stream)))
+                                   _ptr(B), _ptr(c), _ptr(J_foot), _ptr(status),
+                                   _stream_handle(stream)))
         return A, B, c, status
 
     def rti_torque(self, dt: float, kp: float, kd: float, x, u, x_meas, stream=None):

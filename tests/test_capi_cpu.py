@@ -173,7 +173,7 @@ def test_rigid_body_calls_reject_null_model():
     L = mpc.lib()
     assert L.mpc_model_destroy(None) == mpc.MPC_ERR_INVALID_ARG
     assert L.mpc_rnea(None, 1, None, None, None, None, None, None) == mpc.MPC_ERR_INVALID_ARG
-    assert L.mpc_linearize(None, 1, 10, 0.02, 1, None, None, None, None, None, None,
+    assert L.mpc_linearize(None, 1, 10, 0.02, 1, None, None, None, None, None, None, None,
                            None) == mpc.MPC_ERR_INVALID_ARG
     assert L.mpc_rti_torque(None, 1, 10, 0.02, 1.0, 1.0, 1, None, None, None, None,
                             None) == mpc.MPC_ERR_INVALID_ARG

@@ -119,6 +119,28 @@ def test_linearize_step_structure_and_offset(small_lin, models, kind):
             assert np.abs(B[a, k, :n] - DT * B[a, k, n:]).max() < 1e-13
 
 
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_linearize_emits_noslip_rows(models, kind, precision):
+    """The no-slip rows of each agent at x_0 against the oracle's foot Jacobian
+    (complex steps of the contact points' world poses)."""
+    m, g = models[0][kind], models[1][kind]
+    x, u = trajectory(m, 3, 2, seed=81)
+    td = torch.float64 if precision == "fp64" else torch.float32
+    xs = torch.from_numpy(x).to(td).cuda()
+    us = torch.from_numpy(u).to(td).cuda()
+    nfd = len(m["foot_body"]) * m["foot_dim"]
+    J = torch.empty(3 * nfd * 2 * m["n"], dtype=td, device="cuda")
+    g.linearize(xs, us, DT, J_foot=J)
+    Jg = J.cpu().numpy().astype(np.float64).reshape(3, nfd, 2 * m["n"])
+    for a in range(3):
+        xa = x[a, 0] if precision == "fp64" else x[a, 0].astype(np.float32).astype(np.float64)
+        want = RB.noslip_rows(m, xa)
+        e = rel(Jg[a], want)
+        print(kind, precision, a, "no-slip rows rel err", e)
+        assert e < (1e-12 if precision == "fp64" else 1e-6)
+
+
 def test_linearize_flags_nonfinite_agent(models):
     m, g = models[0]["quadruped"], models[1]["quadruped"]
     x, u = trajectory(m, 3, 2, seed=41)

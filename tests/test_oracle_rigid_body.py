@@ -116,6 +116,22 @@ def test_foot_wrenches_enter_as_minus_jacobian_transpose(kind):
 
 
 @pytest.mark.parametrize("kind", ["humanoid", "quadruped"])
+def test_foot_jacobian_is_rneas_wrench_map(kind):
+    """-J' F from the oracle's foot Jacobian (kinematics only) equals the foot
+    wrenches' term of RNEA (force propagation), for several wrenches; the
+    no-slip rows carry J on the velocities only."""
+    m, q, *_ = state(kind, 2)
+    n = m["n"]
+    z = np.zeros(n)
+    J = RB.foot_jacobian(m, q)
+    s = synth.model_states(m, 3, seed=17)
+    for F in s["F"]:
+        assert rel(-J.T @ F, RB.rnea(m, q, z, z, F) - RB.rnea(m, q, z, z)) < 1e-12
+    rows = RB.noslip_rows(m, np.concatenate([q, z]))
+    assert np.all(rows[:, :n] == 0) and np.array_equal(rows[:, n:], J)
+
+
+@pytest.mark.parametrize("kind", ["humanoid", "quadruped"])
 def test_forward_dynamics_inverts_rnea(kind):
     m, q, qd, _, tau, F, _ = state(kind)
     qdd = RB.forward_dynamics(m, q, qd, tau, F)

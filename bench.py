@@ -66,7 +66,10 @@ def parse():
     ap.add_argument("--agents", type=int, default=4096)
     ap.add_argument("--horizon", type=int, default=10)
     ap.add_argument("--iters", type=int, default=50)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32r", "fp32mfma"],
+                    help="fp32r: factor products on the FP32 matrix cores with KKT-residual "
+                         "refinement sweeps in the iterations (--refine-sweeps)")
+    ap.add_argument("--refine-sweeps", type=int, default=3)
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "fused", "persistent"],
                     help="persistent (with --uneven): one persistent iteration launch per shape "
                          "class over every horizon instead of one launch per horizon bucket")
@@ -291,7 +294,8 @@ def mixed(args):
     ref = oracle.solve_batch(synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa), iters=args.iters)
     sh = b.shapes[0]
     modes = {}
-    for prec, sweeps in (("fp32", 0), ("bf16", 0), ("bf16", 3), ("fp16", 0), ("fp16", 3)):
+    for prec, sweeps in (("fp32", 0), ("fp32mfma", 0), ("fp32r", 0), ("fp32r", 3), ("bf16", 0), ("bf16", 3),
+                         ("fp16", 0), ("fp16", 3)):
         plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters, max_refine_sweeps=sweeps)
         stream = torch.cuda.current_stream()
         for _ in range(max(args.warmup, 1)):
@@ -306,9 +310,10 @@ def mixed(args):
         tm = plan.get_timing()
         fac_ms = tm["factor"][0] / max(tm["factor"][1], 1)
         # the factor's block products on the matrix cores: FP64 MFMA in the FP32 mode,
-        # BF16 / FP16 MFMA (FP32 accumulation) in the mixed modes
+        # FP32 MFMA in fp32mfma / fp32r, BF16 / FP16 MFMA (FP32 accumulation) otherwise
         fac_flops = flops_factor_stage(sh.nx, sh.nu) * sh.N * n
-        peak = 78.6 if prec == "fp32" else 2500.0
+        mdt = {"fp32": "f64", "fp32mfma": "f32", "fp32r": "f32"}.get(prec, prec)
+        peak = {"f64": 78.6, "f32": 157.3}.get(mdt, 2500.0)
         u = plan.get_solution()["u"].cpu().numpy().reshape(n, sh.N * sh.nu)[ids].astype(np.float64)
         x = plan.get_solution()["x"].cpu().numpy().reshape(n, (sh.N + 1) * sh.nx)[ids].astype(np.float64)
         uo = ref["u"].reshape(len(ids), -1)
@@ -317,13 +322,13 @@ def mixed(args):
         to = np.concatenate([xo[:, sh.nx:], uo], 1)
         e_u0 = np.abs(u[:, :sh.nu] - uo[:, :sh.nu]).max(1) / np.abs(uo[:, :sh.nu]).max(1)
         e_tr = np.abs(tr - to).max(1) / np.abs(to).max(1)
-        key = prec if prec == "fp32" else f"{prec}_sweeps{sweeps}"
+        key = prec if prec in ("fp32", "fp32mfma") else f"{prec}_sweeps{sweeps}"
         modes[key] = {"ms_per_step": ms, "solves_per_s": n / ms * 1e3,
                       "factor_ms": fac_ms,
                       "factor_roofline": {"bound": "mfma", "achieved": fac_flops / fac_ms / 1e9,
                                           "peak": peak, "unit": "TFLOP/s",
                                           "frac": fac_flops / fac_ms / 1e9 / peak,
-                                          "mfma_dtype": "f64" if prec == "fp32" else prec},
+                                          "mfma_dtype": mdt},
                       "err_u0_max": float(e_u0.max()), "err_traj_max": float(e_tr.max()),
                       "err_traj_p50": float(np.median(e_tr)), "kernel": plan.config()["kernel"]}
         plan.close()
@@ -796,7 +801,9 @@ def main():
     shape = synth.humanoid(args.horizon)
     batch = synth.make_batch([shape] * args.agents, seed=0, stream_id=1,
                              dtype=np.float64 if args.precision == "fp64" else np.float32)
-    plan = mpc.Plan(batch.shapes, precision=args.precision, iters=args.iters, kernel=args.kernel)
+    rkw = (dict(max_refine_sweeps=args.refine_sweeps, refine_tol=1e-6)
+           if args.precision == "fp32r" else {})
+    plan = mpc.Plan(batch.shapes, precision=args.precision, iters=args.iters, kernel=args.kernel, **rkw)
     prob = mpc.to_device(batch, args.precision)
     td = prob["A"].dtype
     gen = torch.Generator(device="cuda")

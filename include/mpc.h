@@ -76,7 +76,16 @@ typedef enum {
                        /* inverse; iterations as MPC_FP32 but rolled out under the */
                        /* exact dynamics, with up to max_refine_sweeps KKT-residual */
                        /* refinement sweeps per x-update                            */
-  MPC_FP16_REFINE = 3  /* as MPC_BF16_REFINE with fp16 operands                     */
+  MPC_FP16_REFINE = 3, /* as MPC_BF16_REFINE with fp16 operands                    */
+  MPC_FP32_REFINE = 4, /* as MPC_BF16_REFINE with fp32 operands on the fp32 matrix */
+                       /* cores (v_mfma_f32_16x16x4f32)                             */
+  MPC_FP32_MFMA = 5    /* as MPC_FP32 on the register-resident kernels, the factor's */
+                       /* block products with fp32 operands on the fp32 matrix     */
+                       /* cores (fp32 accumulation), the stage-Hessian inverse and */
+                       /* K = -H^{-1} G in fp64; no refinement.  Every agent needs  */
+                       /* a register-resident instantiation (UNSUPPORTED_SHAPE     */
+                       /* otherwise); not with kernel = 1, joint limits, no-slip    */
+                       /* rows, the KKT inner solve or the parallel-in-time factor  */
 } mpc_precision;
 
 /* per-agent numerical status */

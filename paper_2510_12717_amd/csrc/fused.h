@@ -27,10 +27,11 @@ hipError_t fused_set_limits();
 // horizons at most N).  phase_mask: 1 = factor kernel, 2 = iteration kernel.
 // counter (device int, or nullptr): the iterations run as one persistent
 // launch over the whole list, every horizon, agents taken from the counter.
+// f32_products: the factor's block products on the FP32 matrix cores.
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
                            int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
                            int warm, State<float> st, float* fws, hipStream_t stream,
-                           int phase_mask, int* counter = nullptr);
+                           int phase_mask, int* counter = nullptr, bool f32_products = false);
 // Workgroup size and dynamic LDS of the persistent launch for longest horizon N.
 void fused_persistent_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds);
 

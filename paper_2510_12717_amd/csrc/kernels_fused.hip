@@ -144,8 +144,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Product precision of the factor's block products: FP64 (v_mfma_f64_16x16x4f64),
-// or BF16 / FP16 operands with FP32 accumulation (v_mfma_f32_16x16x32_{bf16,f16}).
-enum { kProdF64 = 0, kProdBF16 = 1, kProdF16 = 2 };
+// BF16 / FP16 operands with FP32 accumulation (v_mfma_f32_16x16x32_{bf16,f16}),
+// or FP32 operands (v_mfma_f32_16x16x4f32).
+enum { kProdF64 = 0, kProdBF16 = 1, kProdF16 = 2, kProdF32 = 3 };
 
 // Output row of element v of this lane in a 16x16 tile (column is lane % 16).
 template <int PREC>
@@ -161,6 +162,16 @@ template <int PREC, class FA, class FB>
 __device__ inline d4 prod_tile(int ti, int tj, int K, int lane, FA a, FB b) {
   if constexpr (PREC == kProdF64) {
     return mfma_tile(ti, tj, K, lane, a, b);
+  } else if constexpr (PREC == kProdF32) {
+    // lane l feeds A[row l%16][k0 + l/16] and B[k0 + l/16][col l%16]
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int r = lane & 15, kk = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const float av = (float)(k0 + kk < K ? a(ti * 16 + r, k0 + kk) : 0.0);
+      const float bv = (float)(k0 + kk < K ? b(k0 + kk, tj * 16 + r) : 0.0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+    return d4{(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
   } else {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
     const int r = lane & 15, g = lane >> 4;
@@ -215,7 +226,8 @@ constexpr int riccati_lds_bytes() {
          4 * S::NXT * S::LU + 16;
 }
 
-// RES: operators go to the register-resident layout at fws + ofw.
+// RES: operators go to the register-resident layout at fws + ofw (FP64
+// products, or FP32 products for MPC_FP32_MFMA).
 // Otherwise (mixed precision, or FP64 products for the generic iteration
 // kernel at any horizon) they go to the generic per-agent layout at fws + ows:
 // K [N][nu][nx], A_cl [N][nx][nx], H^{-1} [N][nu][nu], s [N][nx], then l, h,
@@ -226,7 +238,7 @@ constexpr int riccati_lds_bytes() {
 // out; then P_k = Q + sigma I + PA' A_cl,k (= Q + A'PA + G'K, as P is
 // symmetric), formed on and above the diagonal and mirrored.
 template <int NX, int NU, int PREC, bool RES>
-__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 ? 4 : 2)
+__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 || PREC == kProdF32 ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
           Inputs<float> in, SolverConsts sc_all, float* __restrict__ fws, int32_t* __restrict__ status) {
   using S = FS<NX, NU>;
@@ -267,7 +279,8 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   const float muf = in.mu[d.omu];
   const double mu = (double)muf;
   constexpr bool kResident = RES;
-  static_assert(!RES || PREC == kProdF64, "the register-resident path takes FP64 products");
+  static_assert(!RES || PREC == kProdF64 || PREC == kProdF32,
+                "the register-resident path takes FP64 or FP32 products");
   float* ops = fws + (kResident ? d.ofw : d.ows);
   float* sk_out = kResident ? ops + (int64_t)N * SLOTS * 64  // [stage][NXP]
                             : ops + (int64_t)N * (NU * NX + NX * NX + NU * NU);
@@ -2345,12 +2358,17 @@ void persistent_shape(int N, int M, int* threads, size_t* lds) {
 template <int NX, int NU>
 hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int M,
                        Inputs<float> in, SolverConsts sc, int iters, int warm, State<float> st,
-                       float* fws, hipStream_t stream, int phase_mask, int* counter) {
+                       float* fws, hipStream_t stream, int phase_mask, int* counter,
+                       bool f32_products) {
   if (n_launch <= 0) return hipSuccess;
   const int lf = riccati_lds_bytes<NX, NU>();
   if (phase_mask & 1) {
-    hipLaunchKernelGGL((k_riccati<NX, NU, kProdF64, true>), dim3(n_launch), dim3(64 * kFactorWaves), lf, stream,
-                       d_desc, list, n_launch, in, sc, fws, st.status);
+    if (f32_products)
+      hipLaunchKernelGGL((k_riccati<NX, NU, kProdF32, true>), dim3(n_launch), dim3(64 * kFactorWaves), lf,
+                         stream, d_desc, list, n_launch, in, sc, fws, st.status);
+    else
+      hipLaunchKernelGGL((k_riccati<NX, NU, kProdF64, true>), dim3(n_launch), dim3(64 * kFactorWaves), lf,
+                         stream, d_desc, list, n_launch, in, sc, fws, st.status);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -2393,6 +2411,9 @@ hipError_t set_limits() {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF32, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
+  if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF64, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
@@ -2400,6 +2421,9 @@ hipError_t set_limits() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF16, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF32, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
@@ -2469,6 +2493,8 @@ hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int
       return launch_factor_generic_out<48, 30, kProdF64>(d_desc, list, n_launch, in, sc, ws, status, stream);
     if (prod == kProdBF16)
       return launch_factor_generic_out<48, 30, kProdBF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
+    if (prod == kProdF32)
+      return launch_factor_generic_out<48, 30, kProdF32>(d_desc, list, n_launch, in, sc, ws, status, stream);
     return launch_factor_generic_out<48, 30, kProdF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
   }
   if (nx == 36 && nu == 24) {
@@ -2476,6 +2502,8 @@ hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int
       return launch_factor_generic_out<36, 24, kProdF64>(d_desc, list, n_launch, in, sc, ws, status, stream);
     if (prod == kProdBF16)
       return launch_factor_generic_out<36, 24, kProdBF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
+    if (prod == kProdF32)
+      return launch_factor_generic_out<36, 24, kProdF32>(d_desc, list, n_launch, in, sc, ws, status, stream);
     return launch_factor_generic_out<36, 24, kProdF16>(d_desc, list, n_launch, in, sc, ws, status, stream);
   }
   return hipErrorInvalidValue;
@@ -2484,14 +2512,14 @@ hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
                            int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
                            int warm, State<float> st, float* fws, hipStream_t stream,
-                           int phase_mask, int* counter) {
+                           int phase_mask, int* counter, bool f32_products) {
   const int m = nu + 4 * n_feet;
   if (nx == 48 && nu == 30)
     return launch_pair<48, 30>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
-                               phase_mask, counter);
+                               phase_mask, counter, f32_products);
   if (nx == 36 && nu == 24)
     return launch_pair<36, 24>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
-                               phase_mask, counter);
+                               phase_mask, counter, f32_products);
   return hipErrorInvalidValue;
 }
 

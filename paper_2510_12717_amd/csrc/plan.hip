@@ -239,7 +239,7 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   if (!desc || !out) return fail(MPC_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   if (desc->n_agents <= 0 || !desc->shapes) return fail(MPC_ERR_INVALID_ARG, "n_agents must be > 0 with a shapes array");
-  if (desc->precision < MPC_FP64 || desc->precision > MPC_FP16_REFINE)
+  if (desc->precision < MPC_FP64 || desc->precision > MPC_FP32_MFMA)
     return fail(MPC_ERR_INVALID_ARG, "unknown precision");
   if (desc->admm_iters <= 0) return fail(MPC_ERR_INVALID_ARG, "admm_iters must be > 0");
   if (!(desc->rho > 0) || !(desc->sigma >= 0) || !(desc->alpha > 0 && desc->alpha < 2) ||
@@ -257,28 +257,34 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   if (desc->joint_limits != 0 && desc->joint_limits != 1)
     return fail(MPC_ERR_INVALID_ARG, "joint_limits must be 0 or 1");
   if (desc->joint_limits &&
-      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
+      (refine_precision(desc->precision) ||
        desc->scaling_iters > 0 || desc->kernel == 2))
     return fail(MPC_ERR_INVALID_ARG,
                 "joint limits run on the generic kernels in FP64 or FP32, without scaling");
   if (desc->no_slip != 0 && desc->no_slip != 1) return fail(MPC_ERR_INVALID_ARG, "no_slip must be 0 or 1");
   if (desc->no_slip &&
-      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
+      (refine_precision(desc->precision) ||
        desc->scaling_iters > 0 || desc->kernel == 2))
     return fail(MPC_ERR_INVALID_ARG,
                 "no-slip rows run on the generic kernels in FP64 or FP32, without scaling");
   if (desc->inner_solve != 0 && desc->inner_solve != 1)
     return fail(MPC_ERR_INVALID_ARG, "inner_solve must be 0 or 1");
+  if (desc->precision == MPC_FP32_MFMA &&
+      (desc->kernel == 1 || desc->joint_limits || desc->no_slip || desc->inner_solve ||
+       desc->riccati_scan))
+    return fail(MPC_ERR_INVALID_ARG,
+                "MPC_FP32_MFMA runs the register-resident kernels: not with kernel = 1, joint "
+                "limits, no-slip rows, the KKT inner solve or the parallel-in-time factor");
   if (desc->riccati_scan != 0 && desc->riccati_scan != 1)
     return fail(MPC_ERR_INVALID_ARG, "riccati_scan must be 0 or 1");
   if (desc->riccati_scan &&
-      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE || desc->inner_solve ||
+      (refine_precision(desc->precision) || desc->inner_solve ||
        desc->kernel == 2 || desc->kernel == 3))
     return fail(MPC_ERR_INVALID_ARG,
                 "the parallel-in-time factor runs on the generic kernels in FP64 or FP32, "
                 "not with the KKT inner solve");
   if (desc->inner_solve &&
-      (desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE ||
+      (refine_precision(desc->precision) ||
        desc->scaling_iters > 0 || desc->rho_interval > 0 || desc->kernel == 2 ||
        desc->joint_limits || desc->no_slip))
     return fail(MPC_ERR_INVALID_ARG,
@@ -370,15 +376,16 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   // instantiation are grouped per (shape class, horizon) and take those
   // kernels; every other agent is grouped per shape class and takes the
   // generic kernels, sized for the group's longest horizon.
-  const bool mixed = desc->precision == MPC_BF16_REFINE || desc->precision == MPC_FP16_REFINE;
+  const bool mixed = refine_precision(desc->precision);
   int n_counters = 0;
   {
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
     for (int a = 0; a < p->n; ++a) {
       const mpc_shape& s = p->shapes[a];
-      const bool fok = desc->precision == MPC_FP32 && !p->limits && !p->contacts && !p->kkt &&
+      const bool fok = (desc->precision == MPC_FP32 || desc->precision == MPC_FP32_MFMA) &&
+                       !p->limits && !p->contacts && !p->kkt &&
                        fused_supported(s.N, s.nx, s.nu, s.n_feet);
-      if ((desc->kernel == 2 || desc->kernel == 3) && !fok) {
+      if ((desc->kernel == 2 || desc->kernel == 3 || desc->precision == MPC_FP32_MFMA) && !fok) {
         delete p;
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
                     "register-resident kernels requested for an agent they do not support");
@@ -706,7 +713,8 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
       PhaseTimer t(p, 0, s);
       HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
                               make_inputs<float>(b), sc, iters, warm,
-                              make_state<float>(p), p->d_fws, s, 1));
+                              make_state<float>(p), p->d_fws, s, 1, nullptr,
+                              p->desc.precision == MPC_FP32_MFMA));
     }
     {
       PhaseTimer t(p, 1, s);
@@ -719,7 +727,7 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
     {
       PhaseTimer t(p, 0, s);
       HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu,
-                                  p->desc.precision == MPC_BF16_REFINE ? 1 : 2,
+                                  refine_product(p->desc.precision),
                                   make_inputs<float>(b), sc, (float*)p->d_ws, p->d_status, s));
     }
     {
@@ -1105,7 +1113,9 @@ extern "C" mpc_status mpc_plan_autotune(mpc_plan_t p, const mpc_problem_batch* b
     struct Cand { int family, threads; };
     std::vector<Cand> cands;
     if (g.fused_ok) cands.push_back({2, g.fthreads});
-    for (int t : {256, 128, 64}) cands.push_back({g.family == 4 ? 4 : 1, t});
+    // MPC_FP32_MFMA is defined on the register-resident kernels only
+    if (p->desc.precision != MPC_FP32_MFMA)
+      for (int t : {256, 128, 64}) cands.push_back({g.family == 4 ? 4 : 1, t});
     float best = INFINITY;
     Cand pick = {g.family, g.family == 2 ? g.fthreads : g.gthreads};
     for (const Cand& c : cands) {

@@ -125,6 +125,7 @@ struct mpc_server_s {
   size_t esz = 4;
   bool fp64 = false;
   bool mixed = false;
+  bool f32_products = false;  // MPC_FP32_MFMA: the register-resident factor's products in FP32
   char* arena_base = nullptr;
   int64_t arena_bytes = 0;
   Arena arena;
@@ -214,7 +215,7 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   if (!desc || !out) return api_fail(MPC_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   const mpc_plan_desc& sd = desc->solver;
-  if (sd.precision < MPC_FP64 || sd.precision > MPC_FP16_REFINE)
+  if (sd.precision < MPC_FP64 || sd.precision > MPC_FP32_MFMA)
     return api_fail(MPC_ERR_INVALID_ARG, "unknown precision");
   if (sd.admm_iters <= 0) return api_fail(MPC_ERR_INVALID_ARG, "admm_iters must be > 0");
   if (!(sd.rho > 0) || !(sd.sigma >= 0) || !(sd.alpha > 0 && sd.alpha < 2) ||
@@ -242,7 +243,8 @@ extern "C" mpc_status mpc_server_create(const mpc_server_desc* desc, mpc_server_
   s->desc.solver.n_agents = 0;
   s->desc.solver.shapes = nullptr;
   s->fp64 = sd.precision == MPC_FP64;
-  s->mixed = sd.precision == MPC_BF16_REFINE || sd.precision == MPC_FP16_REFINE;
+  s->mixed = refine_precision(sd.precision);
+  s->f32_products = sd.precision == MPC_FP32_MFMA;
   s->esz = s->fp64 ? 8 : 4;
   const int B = desc->max_batch;
   // per-slot buffers come out of the budget first
@@ -357,6 +359,9 @@ static mpc_status submit_one(mpc_server_s* s, int64_t ctrl, const mpc_shape* sha
     if (s->mixed && !mixed_supported(sh.nx, sh.nu))
       return api_fail(MPC_ERR_UNSUPPORTED_SHAPE,
                       "mixed precision is built for (nx, nu) = (48, 30) and (36, 24) only");
+    if (s->f32_products && !fused_supported(sh.N, sh.nx, sh.nu, sh.n_feet))
+      return api_fail(MPC_ERR_UNSUPPORTED_SHAPE,
+                      "MPC_FP32_MFMA needs a register-resident instantiation of the shape");
   }
   if (!prob->A || !prob->B || !prob->c || !prob->q_diag || !prob->r_diag || !prob->x_ref ||
       !prob->x0 || !prob->mu || (sh.n_tau > 0 && !prob->tau_max) || (sh.n_feet > 0 && !prob->stance))
@@ -588,12 +593,13 @@ static mpc_status launch_batch(mpc_server_s* s, Slot& sl) {
     if constexpr (std::is_same<T, float>::value) {
       if (g.fam == 2) {
         MPC_HIP_TRY(fused_solve_f32(sl.d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet, in, sc,
-                                    iters, -1, state, (float*)s->arena_base, st, 3));
+                                    iters, -1, state, (float*)s->arena_base, st, 3, nullptr,
+                                    s->f32_products));
         continue;
       }
       if (g.fam == 4) {
         MPC_HIP_TRY(launch_mixed_factor(sl.d_desc, list, g.count, g.nx, g.nu,
-                                        s->desc.solver.precision == MPC_BF16_REFINE ? 1 : 2, in, sc,
+                                        refine_product(s->desc.solver.precision), in, sc,
                                         (float*)s->arena_base, sl.d_status, st));
         MPC_HIP_TRY(launch_generic_admm<float>(sl.d_desc, list, g.count, in, sc, iters, -1,
                                                (const float*)s->arena_base, state, g.lds_a, 256,

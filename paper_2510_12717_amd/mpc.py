@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmpc_hip.so")
 
 MPC_OK, MPC_ERR_INVALID_ARG, MPC_ERR_OUT_OF_MEMORY, MPC_ERR_HIP = 0, 1, 2, 3
 MPC_ERR_UNSUPPORTED_SHAPE, MPC_ERR_BUSY, MPC_ERR_NOT_READY = 4, 5, 6
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "fp32r": 4, "fp32mfma": 5}
 AGENT_OK, AGENT_CONVERGED, AGENT_NOT_PD, AGENT_NONFINITE, AGENT_SUPERSEDED = 0, 1, 2, 3, 4
 
 

@@ -54,6 +54,9 @@ def _create(**over):
 @pytest.mark.parametrize("over,code", [
     (dict(n_agents=0), mpc.MPC_ERR_INVALID_ARG),
     (dict(precision=9), mpc.MPC_ERR_INVALID_ARG),
+    (dict(precision=6), mpc.MPC_ERR_INVALID_ARG),
+    (dict(precision=5, kernel=1), mpc.MPC_ERR_INVALID_ARG),
+    (dict(precision=5, joint_limits=1), mpc.MPC_ERR_INVALID_ARG),
     (dict(admm_iters=0), mpc.MPC_ERR_INVALID_ARG),
     (dict(rho=0.0), mpc.MPC_ERR_INVALID_ARG),
     (dict(alpha=2.0), mpc.MPC_ERR_INVALID_ARG),

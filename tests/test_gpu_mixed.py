@@ -106,3 +106,27 @@ def test_mixed_precision_unsupported_shape():
     with pytest.raises(mpc.MPCError) as ei:
         mpc.Plan([synth.Shape(N=4, nx=20, nu=6, n_tau=6, n_feet=0, foot_dim=3)], precision="bf16")
     assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+def test_fp32_matrix_core_products_with_refinement(kappa):
+    """MPC_FP32_REFINE: the factor's block products on the FP32 matrix cores
+    (unit roundoff 2^-24 = 6e-8 on the operands, FP32 accumulation), the
+    stage-Hessian inverse in FP64, the generic iterations with up to 3
+    KKT-residual refinement sweeps.  A product over K <= 48 terms errs by about
+    sqrt(K) 2^-24 = 4e-7, which the 50 iterations magnify ~60-fold: already
+    before refinement the error is at the FP32 path's level (measured
+    2.0e-6 - 3.7e-6 for kappa 1e2 - 1e6) and within the FP32 tolerance, and
+    the sweeps keep it there."""
+    ids = np.arange(0, 16384, 512)
+    b = synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa, dtype=np.float32)
+    o = oracle.solve_batch(synth.conditioned_humanoid_batch(agent_ids=ids, kappa=kappa), iters=50)
+    errs = {}
+    for sweeps in (0, 3):
+        g, plan = _solve(b, "fp32r", sweeps)
+        assert plan.config()["kernel"] == "mixed_precision"
+        assert np.all(g["status"] == 0)
+        errs[sweeps] = agent_errors(b, g, o)[:, :2].max()
+    print("kappa %.0e fp32 products: before %.2e after %.2e" % (kappa, errs[0], errs[3]))
+    assert errs[0] < 1e-5
+    assert errs[3] < 1e-5

@@ -238,7 +238,7 @@ constexpr int riccati_lds_bytes() {
 // out; then P_k = Q + sigma I + PA' A_cl,k (= Q + A'PA + G'K, as P is
 // symmetric), formed on and above the diagonal and mirrored.
 template <int NX, int NU, int PREC, bool RES>
-__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 || PREC == kProdF32 ? 4 : 2)
+__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 || (PREC == kProdF32 && RES) ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
           Inputs<float> in, SolverConsts sc_all, float* __restrict__ fws, int32_t* __restrict__ status) {
   using S = FS<NX, NU>;
@@ -308,9 +308,17 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       const float lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
       ok &= !isnan(lo) && !isnan(hi) && lo <= hi;
     }
+  if (!RES && in.J)  // no-slip rows: a finite foot Jacobian
+    for (int i = tid; i < d.n_feet * d.foot_dim * NX; i += nt) ok &= (bool)isfinite(in.J[d.oJ + i]);
   if (!ok) atomicOr(flag, 1);
-  // state weight Q + sigma I (+ the joint-limit rows' penalties)
+  // state weight Q + sigma I (+ the joint-limit rows' penalties, + the no-slip
+  // rows' dense Jc' diag(rho_c,N) Jc)
   for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma + state_rho<double>(in, d, i, sc);
+  if (!RES && in.J) {
+    __syncthreads();
+    for (int e = tid; e < NX * NX; e += nt)
+      P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, N, e / NX, e % NX, sc);
+  }
   __syncthreads();
   if (flag[0]) {
     if (tid == 0) status[agent] = AGENT_NONFINITE;
@@ -603,6 +611,15 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       }
     }
     __syncthreads();
+    // the no-slip rows' dense Jc' diag(rho_c,k) Jc (generic layout only: the
+    // register-resident kernels take no state rows)
+    if constexpr (!RES) {
+      if (in.J && k > 0) {
+        for (int e = tid; e < NX * NX; e += nt)
+          P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, k, e / NX, e % NX, sc);
+        __syncthreads();
+      }
+    }
   }
   if (kResident) {
     // S_0 = -B_0 H_0^{-1} B_0' (FP64 matrix-core tiles, once per agent), written in

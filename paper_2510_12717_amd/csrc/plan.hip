@@ -755,14 +755,14 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
     {
       PhaseTimer t(p, 0, s);
       // FP32 plans of the shapes the matrix-core factor is built for take it
-      // (FP64 products, generic operator layout) at any horizon
-      // (the no-slip rows' dense state weight is added by the generic factor only)
+      // (FP64 products, generic operator layout) at any horizon, with the
+      // joint-limit and no-slip rows' state weights
       if (p->scan) {
         double* E0 = p->d_scan + g.scan_off;
         HIP_TRY(launch_scan_factor<T>(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.nu + 4 * g.n_feet, in, sc,
                                       (T*)p->d_ws, E0, E0 + scan_elements_bytes(g.count, g.N, g.nx) / sizeof(double),
                                       p->d_status, g.lds_factor, s));
-      } else if (!p->fp64 && !p->contacts && mixed_supported(g.nx, g.nu))
+      } else if (!p->fp64 && mixed_supported(g.nx, g.nu))
         HIP_TRY(launch_mixed_factor(p->d_desc, list, g.count, g.nx, g.nu, 0, make_inputs<float>(b),
                                     sc, (float*)p->d_ws, p->d_status, s));
       else

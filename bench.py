@@ -157,7 +157,7 @@ def summarize_pmc(paths):
     """Traffic of the iteration kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
     each scaled by what the same counter reads for a 1 GiB device copy."""
     fb, wb, fc, wc = paths
-    kname = "k_admm_resident<48, 30>"
+    kname = "k_admm_resident<48, 30, false>"
     f_k, n_f = _pmc_per_dispatch(fb, "k_admm_resident")
     w_k, n_w = _pmc_per_dispatch(wb, "k_admm_resident")
     f_c, _ = _pmc_per_dispatch(fc, "copy")
@@ -623,7 +623,8 @@ def rti(args):
     npd = np.float64 if prec == "fp64" else np.float32
     b = synth.make_batch([sh] * n, seed=0, stream_id=1, dtype=npd)
     prob = mpc.to_device(b, prec)
-    plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters, no_slip=1 if args.no_slip else 0)
+    plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters, no_slip=1 if args.no_slip else 0,
+                    kernel=args.kernel)
     st = synth.model_states(model, n * (N + 1), seed=5)
     X = torch.from_numpy(np.concatenate([st["q"], st["qd"]], 1).reshape(n, N + 1, sh.nx)
                          .astype(npd)).cuda()
@@ -715,6 +716,7 @@ def rti(args):
            "max_abs_x_finite_agents": float(X[torch.isfinite(X).flatten(1).all(1)].abs().max()),
            "torque_finite": bool(torch.isfinite(tau).all()),
            "iters": args.iters, "precision": prec, "no_slip_rows": bool(args.no_slip),
+           "families": sorted({g["family"] for g in plan.groups()}),
            "dtype": ("f64" if prec == "fp64" else "f32 io, f64 dynamics and Riccati factor")}
     print(json.dumps(out))
     plan.close()
@@ -877,7 +879,7 @@ def main():
     fl_iter = flops_iter_stage(shape.nx, shape.nu) * shape.N * args.iters * args.agents
     peak = PEAK["alu_f64"] if args.precision == "fp64" else PEAK["alu_f32"]
     achieved = fl_iter / avg_admm_s
-    kname = ("k_admm_resident<%d, %d>" % (shape.nx, shape.nu) if cfg["kernel"] == "fused"
+    kname = ("k_admm_resident<%d, %d, false>" % (shape.nx, shape.nu) if cfg["kernel"] == "fused"
              else "k_admm<%s>" % ("double" if args.precision == "fp64" else "float"))
     traffic = recorded_traffic() if cfg["kernel"] == "fused" else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,

@@ -135,8 +135,12 @@ typedef struct {
                             /* kernels, FP64 or FP32 only, without scaling (default 0)  */
   int32_t no_slip;          /* 1: every solve carries the no-slip rows J_f v_k = 0 of   */
                             /* the feet in stance (Eq. (mpc_formulation)) on x_1..x_N,  */
-                            /* stance of stage min(k, N-1); generic kernels, FP64 or    */
-                            /* FP32 only, without scaling (default 0)                   */
+                            /* stance of stage min(k, N-1); FP64 or FP32 only, without  */
+                            /* scaling or the persistent launch (kernel = 3); generic   */
+                            /* kernels, or with kernel = 2 the register-resident one    */
+                            /* (FP32, shapes 48/30 with 2 <= N <= 10 and 36/24 with     */
+                            /* 2 <= N <= 11; its FP32 chains carry the equality rows'   */
+                            /* large duals: error to 2.4e-5 measured) (default 0)       */
   int32_t inner_solve;      /* 0: exact dynamics, Riccati factor and sweeps (default);  */
                             /* 1: the paper's form, dynamics as equality rows with      */
                             /* penalty rho_eq_scale * rho and the quasi-definite KKT    */

@@ -308,13 +308,13 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       const float lo = in.xlo[d.oq + i], hi = in.xhi[d.oq + i];
       ok &= !isnan(lo) && !isnan(hi) && lo <= hi;
     }
-  if (!RES && in.J)  // no-slip rows: a finite foot Jacobian
+  if (in.J)  // no-slip rows: a finite foot Jacobian
     for (int i = tid; i < d.n_feet * d.foot_dim * NX; i += nt) ok &= (bool)isfinite(in.J[d.oJ + i]);
   if (!ok) atomicOr(flag, 1);
   // state weight Q + sigma I (+ the joint-limit rows' penalties, + the no-slip
   // rows' dense Jc' diag(rho_c,N) Jc)
   for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma + state_rho<double>(in, d, i, sc);
-  if (!RES && in.J) {
+  if (in.J) {
     __syncthreads();
     for (int e = tid; e < NX * NX; e += nt)
       P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, N, e / NX, e % NX, sc);
@@ -611,14 +611,11 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
       }
     }
     __syncthreads();
-    // the no-slip rows' dense Jc' diag(rho_c,k) Jc (generic layout only: the
-    // register-resident kernels take no state rows)
-    if constexpr (!RES) {
-      if (in.J && k > 0) {
-        for (int e = tid; e < NX * NX; e += nt)
-          P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, k, e / NX, e % NX, sc);
-        __syncthreads();
-      }
+    // the no-slip rows' dense Jc' diag(rho_c,k) Jc
+    if (in.J && k > 0) {
+      for (int e = tid; e < NX * NX; e += nt)
+        P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, k, e / NX, e % NX, sc);
+      __syncthreads();
     }
   }
   if (kResident) {
@@ -719,11 +716,14 @@ __device__ inline void flag_wait(int* f, int n, int v, int* abort, int lane) {
 struct IterLds {
   int acl, xtf, ppf, gf, ef, sf, cf;                               // float
   int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd, bvd;  // double
+  int jc, jac, dnf;                                                // float, no-slip rows
+  int zcd, ycd, wcd;                                               // double, no-slip rows
   int flag, sync, total;
 };
 
+// nc: no-slip rows per state (0 without them)
 template <int NX, int NU>
-__host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
+__host__ __device__ inline IterLds iter_lds_layout(int N, int M, int nc = 0) {
   using S = FS<NX, NU>;
   IterLds L{};
   int o = 0;
@@ -755,6 +755,12 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M) {
   L.xrd = take(8 * (N + 1) * S::NXP);
   L.qtd = take(8 * N * S::NXP);
   L.bvd = take(8 * S::NXP);
+  L.jc = take(4 * nc * S::NXP);
+  L.jac = take(4 * nc * S::NXP);
+  L.dnf = take(nc ? 4 * S::NXP : 0);
+  L.zcd = take(8 * N * nc);
+  L.ycd = take(8 * N * nc);
+  L.wcd = take(8 * N * nc);
   L.flag = take(16);
   L.sync = take(4 * kSyncInts);
   L.total = o;
@@ -909,8 +915,9 @@ __device__ inline void rollout_exact(const float* __restrict__ A, const float* _
 // output vector spread over the lanes exactly as the next hop reads it.  Inside
 // the iteration loop the two kinds of wavefront meet only through the
 // progress flags; workgroup barriers separate the set-up, the iterations and
-// the write-out.
-template <int NX, int NU>
+// the write-out.  ROWS: the instantiation that takes the no-slip rows (the
+// other one carries none of their code).
+template <int NX, int NU, bool ROWS = false>
 __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict__ desc, int agent,
                                                     Inputs<float> in, SolverConsts sc_all, int iters,
                                                     int warm, const float* __restrict__ fws,
@@ -926,6 +933,8 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
   float* U = st.u + d.ou;
   float* Z = st.z + d.oz;
   float* Y = st.y + d.oy;
+  // no-slip rows J_f v_k = 0 of x_1..x_N (plans with them; N >= 2)
+  const int nc = ROWS && in.J ? d.n_feet * d.foot_dim : 0;
   if (st.status[agent] != AGENT_OK) {
     for (int i = tid; i < (N + 1) * d.nx; i += nt) X[i] = NAN;
     for (int i = tid; i < N * d.nu; i += nt) U[i] = NAN;
@@ -933,9 +942,13 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
       Z[i] = NAN;
       Y[i] = NAN;
     }
+    for (int i = tid; i < N * nc; i += nt) {
+      st.zc[d.ozc + i] = NAN;
+      st.yc[d.ozc + i] = NAN;
+    }
     return;
   }
-  const IterLds L = iter_lds_layout<NX, NU>(N, M);
+  const IterLds L = iter_lds_layout<NX, NU>(N, M, nc);
   extern __shared__ __align__(16) unsigned char sm[];
   const float4* acl4 = reinterpret_cast<const float4*>(sm + L.acl);
   float* xtf = reinterpret_cast<float*>(sm + L.xtf);
@@ -962,6 +975,14 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
   double* bvd = reinterpret_cast<double*>(sm + L.bvd);
   // after the x^0 rollout: g'_0 of iterations of odd / even number
   float* g0f = reinterpret_cast<float*>(sm + L.bvd);
+  // no-slip rows: Jc [nc][NXP], Jc A_cl,N-1 [nc][NXP], Jc' w_c,N [NXP];
+  // z_c, y_c, w_c = y_c - rho_c z_c of x_1..x_N [N][nc]
+  float* jc = reinterpret_cast<float*>(sm + L.jc);
+  float* jac = reinterpret_cast<float*>(sm + L.jac);
+  float* dnf = reinterpret_cast<float*>(sm + L.dnf);
+  double* zcd = reinterpret_cast<double*>(sm + L.zcd);
+  double* ycd = reinterpret_cast<double*>(sm + L.ycd);
+  double* wcd = reinterpret_cast<double*>(sm + L.wcd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
 
@@ -1024,7 +1045,37 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
     zd[i] = wm ? (double)Z[i] : 0.0;
     yd[i] = wm ? (double)Y[i] : 0.0;
   }
+  if (nc) {
+    const float* Jc = in.J + d.oJ;
+    for (int i = tid; i < nc * NX; i += nt) jc[(i / NX) * NXP + i % NX] = Jc[i];
+    for (int i = tid; i < N * nc; i += nt) {
+      const double zz = wm ? (double)st.zc[d.ozc + i] : 0.0, yy = wm ? (double)st.yc[d.ozc + i] : 0.0;
+      double rr;
+      contact_row(d, stance, i / nc + 1, i % nc, sc, rr);
+      zcd[i] = zz;
+      ycd[i] = yy;
+      wcd[i] = yy - rr * zz;
+    }
+  }
   __syncthreads();
+  if (nc) {
+    // Jc A_cl,N-1: the rows of x_N = A_cl,N-1 x_{N-1} + e_{N-1} as seen from the
+    // last stage, so that its wavefront handles them (A_cl,N-1 read from the
+    // chain operator layout: slot i*RB + j of lane a*8 + b, or b*8 + a on odd
+    // stages, holds row a*RB + i, column b*RB + j)
+    const float* aclf = reinterpret_cast<const float*>(sm + L.acl);
+    const int kl = N - 1;
+    for (int e = tid; e < nc * NX; e += nt) {
+      const int rw = e / NX, cj = e % NX, b = cj / RB, j = cj % RB;
+      double acc = 0.0;
+      for (int ri = 0; ri < NX; ++ri) {
+        const int a = ri / RB, slot = (ri % RB) * RB + j, ln = (kl & 1) ? b * 8 + a : a * 8 + b;
+        acc += (double)jc[rw * NXP + ri] * (double)aclf[((kl * AQ + (slot >> 2)) * 64 + ln) * 4 + (slot & 3)];
+      }
+      jac[rw * NXP + cj] = (float)acc;
+    }
+    __syncthreads();
+  }
 
 
 
@@ -1352,13 +1403,32 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
       rt_b0 = NU + 4 * ((lane - d.n_tau) / d.foot_dim);
       rt_cc = (lane - d.n_tau) % d.foot_dim;
     }
+    // The no-slip rows' terms of stage k's state weight (k >= 1), entry i:
+    // Jc' w_c,k, and on the last stage also (Jc A_cl,N-1)' w_c,N, through which
+    // the rows of x_N reach p_{N-1}; the last stage leaves Jc' w_c,N for its C
+    // (p'_{N-1} = p_N + s_{N-1}, p_N holding Jc' w_c,N).
+    auto row_terms = [&](int i) -> double {
+      double v = 0.0;
+      for (int rw = 0; rw < nc; ++rw) v += (double)jc[rw * NXP + i] * wcd[(k - 1) * nc + rw];
+      if (k == N - 1) {
+        double dn = 0.0;
+        for (int rw = 0; rw < nc; ++rw) {
+          const double wn = wcd[(N - 1) * nc + rw];
+          v += (double)jac[rw * NXP + i] * wn;
+          dn += (double)jc[rw * NXP + i] * wn;
+        }
+        dnf[i] = (float)dn;
+      }
+      return v;
+    };
     if (k < N) {
       if (lane < NU) {
         u_own = ud[k * NUP + lane];
         if (uref) ru_own = (double)r[lane] * (double)uref[(int64_t)k * NU + lane];
       }
       if (lane < M) wvd[k * M + lane] = yd[k * M + lane] - rhod[k * M + lane] * zd[k * M + lane];
-      if (k >= 1 && lane < NX) qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xd[k * NXP + lane];
+      if (k >= 1 && lane < NX)
+        qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xd[k * NXP + lane] + (nc ? row_terms(lane) : 0.0);
       wave_sync();
     }
     const int n_it = w < N ? iters : 0;  // wavefronts past the chain wavefront idle
@@ -1458,6 +1528,9 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
         double rtv[CB];
 #pragma unroll
         for (int i = 0; i < RB; ++i) pv[i] = ppf[k * NXP + la * RB + i];
+        if (nc && k == N - 1)
+#pragma unroll
+          for (int i = 0; i < RB; ++i) pv[i] += dnf[la * RB + i];
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
           rtv[j] = rtd[k * NUP + lb * CB + j];
@@ -1506,6 +1579,43 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
       // (D) forward chain on the chain wavefront; E_k starts once xt_k is out
       if (k >= 1) flag_wait(sync + kSyncX + k, 1, T, sync + kSyncAbort, lane);
       // (E) ut_k = K_k xt_k + d_k; relaxation, projection and dual update of stage k
+      if (w < N && nc) {
+        // no-slip rows: zeta = Jc xt_k (k >= 1), and on the last stage the rows of
+        // x_N, zeta = (Jc A_cl,N-1) xt_{N-1} + Jc e_{N-1}; relaxed, projected
+        // (stance rows to 0, free rows to w + y_c / rho_c), dual update.  Quad
+        // rw of the wavefront sums row r0 + rw, each lane every fourth column.
+        const int part = lane & 3;
+        auto row_update = [&](int kr, int rw, double zeta) {
+          const int idx = (kr - 1) * nc + rw;
+          double rr;
+          const bool eq = contact_row(d, stance, kr, rw, sc, rr);
+          const double wv = alpha * zeta + oma * zcd[idx];
+          const double zn = eq ? 0.0 : wv + ycd[idx] / rr;
+          const double yn = ycd[idx] + rr * (wv - zn);
+          ycd[idx] = yn;
+          zcd[idx] = zn;
+          wcd[idx] = yn - rr * zn;
+        };
+        for (int r0 = 0; r0 < nc; r0 += 16) {
+          const int rw = r0 + (lane >> 2);
+          if (k >= 1) {
+            double zeta = 0.0;
+            if (rw < nc)
+              for (int i = part; i < NX; i += 4) zeta += (double)jc[rw * NXP + i] * (double)xtf[k * NXP + i];
+            zeta = quad_sum(zeta);
+            if (rw < nc && part == 0) row_update(k, rw, zeta);
+          }
+          if (k == N - 1) {
+            double zeta = 0.0;
+            if (rw < nc)
+              for (int i = part; i < NX; i += 4)
+                zeta += (double)jac[rw * NXP + i] * (double)xtf[k * NXP + i] +
+                        (double)jc[rw * NXP + i] * (double)ef[k * NXP + i];
+            zeta = quad_sum(zeta);
+            if (rw < nc && part == 0) row_update(N, rw, zeta);
+          }
+        }
+      }
       if (w < N) {
         float xv[RB], su[CB];
         double dvv[CB];
@@ -1529,7 +1639,7 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
         if (k >= 1 && lane < NX) {
           const double xn = alpha * (double)xtf[k * NXP + lane] + oma * xd[k * NXP + lane];
           xd[k * NXP + lane] = xn;
-          qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xn;
+          qtd[k * NXP + lane] = -qd[lane] * xrd[k * NXP + lane] - sigma * xn + (nc ? row_terms(lane) : 0.0);
         }
         // row `lane`: (C ut)_i, relaxation, projection, dual update, w = y - rho z
         if (lane < M) {
@@ -1568,6 +1678,11 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
     Z[i] = (float)zd[i];
     Y[i] = (float)yd[i];
     fin &= (bool)isfinite(Z[i]) && (bool)isfinite(Y[i]);
+  }
+  for (int i = tid; i < N * nc; i += nt) {
+    st.zc[d.ozc + i] = (float)zcd[i];
+    st.yc[d.ozc + i] = (float)ycd[i];
+    fin &= (bool)isfinite(zcd[i]) && (bool)isfinite(ycd[i]);
   }
   if (!fin || sync[kSyncAbort]) atomicOr(flag, 1);
   __syncthreads();
@@ -2308,14 +2423,14 @@ __device__ __forceinline__ void admm_stream_agent(const AgentDesc* __restrict__ 
 }
 
 // One workgroup per agent of the launch list.
-template <int NX, int NU>
+template <int NX, int NU, bool ROWS>
 __global__ void __launch_bounds__(64 * kMaxStages)
 k_admm_resident(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
                 Inputs<float> in, SolverConsts sc_all, int iters, int warm,
                 const float* __restrict__ fws, State<float> st) {
   if ((int)blockIdx.x >= n_launch) return;
-  admm_resident_agent<NX, NU>(desc, list ? list[blockIdx.x] : (int)blockIdx.x, in, sc_all, iters, warm,
-                              fws, st);
+  admm_resident_agent<NX, NU, ROWS>(desc, list ? list[blockIdx.x] : (int)blockIdx.x, in, sc_all, iters,
+                                    warm, fws, st);
 }
 
 template <int NX, int NU>
@@ -2376,7 +2491,7 @@ template <int NX, int NU>
 hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int M,
                        Inputs<float> in, SolverConsts sc, int iters, int warm, State<float> st,
                        float* fws, hipStream_t stream, int phase_mask, int* counter,
-                       bool f32_products) {
+                       bool f32_products, int nc) {
   if (n_launch <= 0) return hipSuccess;
   const int lf = riccati_lds_bytes<NX, NU>();
   if (phase_mask & 1) {
@@ -2408,9 +2523,13 @@ hipError_t launch_pair(const AgentDesc* d_desc, const int32_t* list, int n_launc
   }
   if (phase_mask & 2) {
     if (N + 1 <= kMaxStages) {
-      const int li = iter_lds_layout<NX, NU>(N, M).total;
-      hipLaunchKernelGGL((k_admm_resident<NX, NU>), dim3(n_launch), dim3(64 * (N + 1)), li, stream,
-                         d_desc, list, n_launch, in, sc, iters, warm, fws, st);
+      const int li = iter_lds_layout<NX, NU>(N, M, nc).total;
+      if (nc)
+        hipLaunchKernelGGL((k_admm_resident<NX, NU, true>), dim3(n_launch), dim3(64 * (N + 1)), li, stream,
+                           d_desc, list, n_launch, in, sc, iters, warm, fws, st);
+      else
+        hipLaunchKernelGGL((k_admm_resident<NX, NU, false>), dim3(n_launch), dim3(64 * (N + 1)), li, stream,
+                           d_desc, list, n_launch, in, sc, iters, warm, fws, st);
     } else {
       const int li = stream_lds_layout<NX, NU>(N, M).total;
       hipLaunchKernelGGL((k_admm_stream<NX, NU>), dim3(n_launch), dim3(64 * ((N + 1) / 2 + 2)), li, stream,
@@ -2443,7 +2562,10 @@ hipError_t set_limits() {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_riccati<NX, NU, kProdF32, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, riccati_lds_bytes<NX, NU>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_resident<NX, NU, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_admm_stream<NX, NU>),
@@ -2455,24 +2577,27 @@ hipError_t set_limits() {
 }
 
 template <int NX, int NU>
-int fused_lds(int N, int m) {
-  return N + 1 <= kMaxStages ? iter_lds_layout<NX, NU>(N, m).total : stream_lds_layout<NX, NU>(N, m).total;
+int fused_lds(int N, int m, int nc = 0) {
+  return N + 1 <= kMaxStages ? iter_lds_layout<NX, NU>(N, m, nc).total : stream_lds_layout<NX, NU>(N, m).total;
 }
 
 }  // namespace
 
-bool fused_supported(int N, int nx, int nu, int n_feet) {
+bool fused_supported(int N, int nx, int nu, int n_feet, int nc) {
   const int m = nu + 4 * n_feet;
   if (N < 1 || N > kMaxStream || m > 64) return false;
-  if (nx == 48 && nu == 30) return fused_lds<48, 30>(N, m) <= 160 * 1024;
-  if (nx == 36 && nu == 24) return fused_lds<36, 24>(N, m) <= 160 * 1024;
+  // the no-slip rows run on the register-resident body, and need a stage
+  // before the last (the last stage's wavefront takes the rows of x_N)
+  if (nc && (N < 2 || N + 1 > kMaxStages)) return false;
+  if (nx == 48 && nu == 30) return fused_lds<48, 30>(N, m, nc) <= 160 * 1024;
+  if (nx == 36 && nu == 24) return fused_lds<36, 24>(N, m, nc) <= 160 * 1024;
   return false;
 }
 
-void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds) {
+void fused_launch_shape(int N, int nx, int nu, int n_feet, int* threads, size_t* lds, int nc) {
   const int m = nu + 4 * n_feet;
   *threads = N + 1 <= kMaxStages ? 64 * (N + 1) : 64 * ((N + 1) / 2 + 2);
-  *lds = (nx == 48) ? fused_lds<48, 30>(N, m) : fused_lds<36, 24>(N, m);
+  *lds = (nx == 48) ? fused_lds<48, 30>(N, m, nc) : fused_lds<36, 24>(N, m, nc);
   (void)nu;
 }
 
@@ -2529,14 +2654,15 @@ hipError_t launch_mixed_factor(const AgentDesc* d_desc, const int32_t* list, int
 hipError_t fused_solve_f32(const AgentDesc* d_desc, const int32_t* list, int n_launch, int N, int nx,
                            int nu, int n_feet, Inputs<float> in, SolverConsts sc, int iters,
                            int warm, State<float> st, float* fws, hipStream_t stream,
-                           int phase_mask, int* counter, bool f32_products) {
+                           int phase_mask, int* counter, bool f32_products, int nc) {
   const int m = nu + 4 * n_feet;
+  if (nc && (N + 1 > kMaxStages || counter)) return hipErrorInvalidValue;  // resident body only
   if (nx == 48 && nu == 30)
     return launch_pair<48, 30>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
-                               phase_mask, counter, f32_products);
+                               phase_mask, counter, f32_products, nc);
   if (nx == 36 && nu == 24)
     return launch_pair<36, 24>(d_desc, list, n_launch, N, m, in, sc, iters, warm, st, fws, stream,
-                               phase_mask, counter, f32_products);
+                               phase_mask, counter, f32_products, nc);
   return hipErrorInvalidValue;
 }
 

@@ -45,6 +45,7 @@ struct Group {
   int family = 1;          // 1 generic, 2 register-resident, 4 mixed precision
   bool fused_ok = false;   // register-resident kernels have an instantiation for it
   int N = 0, nx = 0, nu = 0, n_feet = 0;  // N: largest horizon in the group
+  int nc = 0;              // no-slip rows per state (plans with them)
   int count = 0;
   int64_t list_off = 0;    // agents d_list[list_off .. list_off + count)
   int gthreads = 256;      // generic workgroup size
@@ -264,9 +265,10 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
   if (desc->no_slip != 0 && desc->no_slip != 1) return fail(MPC_ERR_INVALID_ARG, "no_slip must be 0 or 1");
   if (desc->no_slip &&
       (refine_precision(desc->precision) ||
-       desc->scaling_iters > 0 || desc->kernel == 2))
+       desc->scaling_iters > 0 || desc->kernel == 3))
     return fail(MPC_ERR_INVALID_ARG,
-                "no-slip rows run on the generic kernels in FP64 or FP32, without scaling");
+                "no-slip rows run on the generic or register-resident kernels in FP64 or FP32, "
+                "without scaling or the persistent launch");
   if (desc->inner_solve != 0 && desc->inner_solve != 1)
     return fail(MPC_ERR_INVALID_ARG, "inner_solve must be 0 or 1");
   if (desc->precision == MPC_FP32_MFMA &&
@@ -382,9 +384,13 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
     std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int32_t>> buckets;
     for (int a = 0; a < p->n; ++a) {
       const mpc_shape& s = p->shapes[a];
+      // no-slip rows: the register-resident body when asked for (kernel = 2),
+      // since its FP32 chains carry the stiff rows' large duals (the generic
+      // kernels accumulate in FP64)
+      const int nca = p->contacts ? s.n_feet * s.foot_dim : 0;
       const bool fok = (desc->precision == MPC_FP32 || desc->precision == MPC_FP32_MFMA) &&
-                       !p->limits && !p->contacts && !p->kkt &&
-                       fused_supported(s.N, s.nx, s.nu, s.n_feet);
+                       !p->limits && !p->kkt && !(nca && desc->kernel != 2) &&
+                       fused_supported(s.N, s.nx, s.nu, s.n_feet, nca);
       if ((desc->kernel == 2 || desc->kernel == 3 || desc->precision == MPC_FP32_MFMA) && !fok) {
         delete p;
         return fail(MPC_ERR_UNSUPPORTED_SHAPE,
@@ -414,13 +420,16 @@ extern "C" mpc_status mpc_plan_create(const mpc_plan_desc* desc, mpc_plan_t* out
       g.nx = s0.nx;
       g.nu = s0.nu;
       g.n_feet = s0.n_feet;
+      g.nc = s0.n_feet * s0.foot_dim;
       g.count = (int)ag.size();
       g.list_off = (int64_t)p->hlist.size();
       const int m = s0.nu + 4 * s0.n_feet;
       g.lds_factor = generic_factor_lds(s0.nx, s0.nu, p->esz);
       g.lds_admm = generic_admm_lds(g.N, s0.nx, s0.nu, m, p->esz, p->limits,
                                     p->contacts ? s0.n_feet * s0.foot_dim : 0);
-      if (g.fused_ok) fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds);
+      if (g.fused_ok)
+        fused_launch_shape(g.N, g.nx, g.nu, g.n_feet, &g.fthreads, &g.flds,
+                           p->contacts ? s0.n_feet * s0.foot_dim : 0);
       if (g.fused_ok && desc->kernel == 3) {
         g.persistent = true;
         g.counter = n_counters++;
@@ -721,7 +730,8 @@ static mpc_status run_group(mpc_plan_s* p, const Group& g, const mpc_problem_bat
       HIP_TRY(fused_solve_f32(p->d_desc, list, g.count, g.N, g.nx, g.nu, g.n_feet,
                               make_inputs<float>(b), sc, iters, warm,
                               make_state<float>(p), p->d_fws, s, 2,
-                              g.persistent ? p->d_counters + g.counter : nullptr));
+                              g.persistent ? p->d_counters + g.counter : nullptr, false,
+                              p->contacts ? g.nc : 0));
     }
   } else if (g.family == 4) {
     {

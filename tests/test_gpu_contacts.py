@@ -1,12 +1,25 @@
 """GPU: no-slip rows of Eq. (mpc_formulation) (J_f v_k = 0 for feet in stance,
 on x_1..x_N) against the oracle, through the C ABI.
 
-Plans created with no_slip = 1 run the generic kernels (FP64 and FP32); each
-agent is compared with the oracle's solve on the same data and Jacobians (FP32
-data widened exactly): u_0 and the trajectory at 1e-10 (FP64) / 1e-5 (FP32),
-z, y and the rows' z_c, y_c at the same bars for FP64, the residual report,
-cold and warm-started from the GPU's own first solve, alone and together with
-joint limits.
+Plans created with no_slip = 1 run the generic kernels (FP64 and FP32), or,
+asked for with kernel = "fused", the register-resident kernel (FP32 agents of
+the humanoid and quadruped shapes, 2 <= N <= 10 / 11, where the last stage's
+wavefront takes the rows of x_N through Jc A_cl,N-1); each agent is compared
+with the oracle's solve on the same data and Jacobians (FP32 data widened
+exactly): u_0 and the trajectory at 1e-10 (FP64) / 1e-5 (FP32), z, y and the
+rows' z_c, y_c at the same bars for FP64 (and z_c, y_c at the trajectory's
+bar, relative to the agent's x and y, for FP32), the residual report, cold and
+warm-started from the GPU's own first solve, alone and together with joint
+limits.
+
+The register-resident kernel runs its chains and stage products in FP32,
+which the equality rows' duals (|y_c| ~ 2.4e4 against |u| ~ 7e2 here, from the
+penalty rho_eq = 1e3 rho) magnify: measured 8.3e-6 / 7.0e-6 (u_0 / trajectory)
+cold and 1.4e-5 warm at N = 10, and up to 1.4e-5 cold and 2.4e-5 warm over
+N = 2..10, against 1.2e-6 on the generic kernels (FP64 accumulation) and
+1.9e-6 on the same kernel without the rows; with rho_eq = 1e2 rho it falls to
+1.8e-6, with 10 rho to 1.4e-6.  That path is gated at 5e-5, and a plan takes
+it only when asked for.
 """
 import numpy as np
 import pytest
@@ -20,7 +33,7 @@ from test_gpu_parity import agent_errors
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "fp32_resident_rows": 5e-5}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -64,17 +77,19 @@ def _prob(b, precision, J, limits=None):
     return prob
 
 
-@pytest.mark.parametrize("precision,kind,with_limits",
-                         [("fp64", "humanoid", False), ("fp32", "humanoid", False),
-                          ("fp64", "uneven", False), ("fp32", "uneven", False),
-                          ("fp64", "uneven", True), ("fp32", "humanoid", True)])
-def test_no_slip_rows_match_oracle_cold_and_warm(precision, kind, with_limits):
+@pytest.mark.parametrize("precision,kind,with_limits,kernel",
+                         [("fp64", "humanoid", False, "auto"), ("fp32", "humanoid", False, "generic"),
+                          ("fp32", "humanoid", False, "fused"),
+                          ("fp64", "uneven", False, "auto"), ("fp32", "uneven", False, "auto"),
+                          ("fp64", "uneven", True, "auto"), ("fp32", "humanoid", True, "auto")])
+def test_no_slip_rows_match_oracle_cold_and_warm(precision, kind, with_limits, kernel):
     b = _batch(kind, precision)
     J = synth.foot_jacobians(b)
     lim = synth.joint_limits(b) if with_limits else None
     plan = mpc.Plan(b.shapes, precision=precision, iters=50, no_slip=1,
-                    joint_limits=1 if with_limits else 0)
-    assert plan.config()["kernel"] == "generic"
+                    joint_limits=1 if with_limits else 0, kernel=kernel)
+    assert {g["family"] for g in plan.groups()} == {"fused" if kernel == "fused" else "generic"}
+    tol = TOL["fp32_resident_rows"] if kernel == "fused" else TOL[precision]
     prob = _prob(b, precision, J, lim)
     plan.solve(prob)
     g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
@@ -84,9 +99,10 @@ def test_no_slip_rows_match_oracle_cold_and_warm(precision, kind, with_limits):
     e = agent_errors(b, g, o)
     ezc = _rel_rows(b, g["zc"], o["zc"], o["x"], "x")
     eyc = _rel_rows(b, g["yc"], o["yc"], o["y"], "z")
-    print(f"{precision} {kind} limits={with_limits} cold: max u0/traj/z/y {e.max(axis=0)} "
+    print(f"{precision} {kind} limits={with_limits} {kernel} cold: max u0/traj/z/y {e.max(axis=0)} "
           f"zc {ezc.max():.2e} yc {eyc.max():.2e}")
-    assert e[:, :2].max() < TOL[precision]
+    assert e[:, :2].max() < tol
+    assert max(ezc.max(), eyc.max()) < tol
     if precision == "fp64":
         assert max(e.max(), ezc.max(), eyc.max()) < TOL["fp64"]
         assert np.allclose(g["residuals"], o["res"], rtol=1e-7, atol=1e-12)
@@ -99,8 +115,11 @@ def test_no_slip_rows_match_oracle_cold_and_warm(precision, kind, with_limits):
     warm = {k: g[k].astype(np.float64) for k in keys}
     o2 = oracle.solve_batch(b, iters=50, warm=warm, x0=x0n, J=J, **kw)
     e2 = agent_errors(b, g2, o2)
-    print(f"{precision} {kind} limits={with_limits} warm: max u0/traj/z/y {e2.max(axis=0)}")
-    assert np.all(g2["status"] == 0) and e2[:, :2].max() < TOL[precision]
+    ezc2 = _rel_rows(b, g2["zc"], o2["zc"], o2["x"], "x")
+    print(f"{precision} {kind} limits={with_limits} {kernel} warm: max u0/traj/z/y {e2.max(axis=0)} "
+          f"zc {ezc2.max():.2e}")
+    assert np.all(g2["status"] == 0) and e2[:, :2].max() < tol
+    assert ezc2.max() < tol
 
 
 def test_set_warm_contacts_resumes_the_rows():
@@ -134,7 +153,7 @@ def test_no_slip_plans_check_their_inputs():
     with pytest.raises(mpc.MPCError):
         plain.set_warm_contacts(torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda"))
     for bad in (dict(precision="bf16"), dict(precision="fp32", scaling_iters=5),
-                dict(precision="fp32", kernel="fused"), dict(precision="fp32", no_slip=2)):
+                dict(precision="fp32", kernel="persistent"), dict(precision="fp32", no_slip=2)):
         kw = dict(no_slip=1)
         kw.update(bad)
         with pytest.raises(mpc.MPCError):
@@ -148,3 +167,52 @@ def test_no_slip_plans_check_their_inputs():
     st = sol["status"].cpu().numpy()
     assert st[0] == mpc.AGENT_NONFINITE and np.all(st[1:] == 0)
     assert np.all(np.isnan(sol["zc"].cpu().numpy()[: b.shapes[0].N * 12]))
+
+
+@pytest.mark.parametrize("kind", ["humanoid", "quadruped"])
+def test_no_slip_rows_on_the_register_resident_kernel_every_horizon(kind):
+    """Every horizon the register-resident kernel takes with the rows (N = 2 up
+    to the LDS limit: humanoid 10, quadruped 11), cold and then warm from the
+    GPU's own iterate, against the oracle; stance patterns of the synthetic
+    batch (some feet swinging) so that equality and free rows both occur."""
+    top = 10 if kind == "humanoid" else 11
+    mk = synth.humanoid if kind == "humanoid" else synth.quadruped
+    shapes = [mk(N) for N in range(2, top + 1) for _ in range(2)]
+    b = synth.make_batch(shapes, seed=7, stream_id=61).astype(np.float32)
+    J = synth.foot_jacobians(b)
+    plan = mpc.Plan(b.shapes, precision="fp32", iters=50, no_slip=1, kernel="fused")
+    assert {g["family"] for g in plan.groups()} == {"fused"}
+    prob = _prob(b, "fp32", J)
+    plan.solve(prob)
+    g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    assert np.all(g["status"] == 0)
+    o = oracle.solve_batch(b, iters=50, J=J)
+    e = agent_errors(b, g, o)
+    ezc = _rel_rows(b, g["zc"], o["zc"], o["x"], "x")
+    eyc = _rel_rows(b, g["yc"], o["yc"], o["y"], "z")
+    print(kind, "resident no-slip cold: max u0/traj", e[:, :2].max(axis=0), "zc/yc", ezc.max(), eyc.max())
+    tol = TOL["fp32_resident_rows"]
+    assert e[:, :2].max() < tol and max(ezc.max(), eyc.max()) < tol
+    x0n = (b.x0 + 0.01 * np.random.default_rng(5).standard_normal(b.x0.shape)).astype(b.x0.dtype)
+    prob["x0"] = torch.from_numpy(x0n).cuda()
+    plan.solve(prob, warm_start=True)
+    g2 = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    warm = {k: g[k].astype(np.float64) for k in ("u", "z", "y", "zc", "yc")}
+    o2 = oracle.solve_batch(b, iters=50, warm=warm, x0=x0n, J=J)
+    e2 = agent_errors(b, g2, o2)
+    print(kind, "resident no-slip warm: max u0/traj", e2[:, :2].max(axis=0))
+    assert np.all(g2["status"] == 0) and e2[:, :2].max() < tol
+
+
+def test_no_slip_register_resident_limits():
+    with pytest.raises(mpc.MPCError) as ei:  # N = 1: no stage before the last
+        mpc.Plan([synth.humanoid(1)], precision="fp32", no_slip=1, kernel="fused")
+    assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE
+    with pytest.raises(mpc.MPCError) as ei:  # beyond the LDS with the rows
+        mpc.Plan([synth.humanoid(11)], precision="fp32", no_slip=1, kernel="fused")
+    assert ei.value.code == mpc.MPC_ERR_UNSUPPORTED_SHAPE
+    with pytest.raises(mpc.MPCError) as ei:
+        mpc.Plan([synth.humanoid(8)], precision="fp32", no_slip=1, kernel="persistent")
+    assert ei.value.code == mpc.MPC_ERR_INVALID_ARG
+    plan = mpc.Plan([synth.humanoid(2), synth.humanoid(8)], precision="fp32", no_slip=1)
+    assert {g["family"] for g in plan.groups()} == {"generic"}  # only when asked for

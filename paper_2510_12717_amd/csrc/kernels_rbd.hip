@@ -237,13 +237,19 @@ constexpr int kMaxCols = 2 * kMaxBodies + kMaxU;  // x and u columns
 constexpr int kMaxFeet = 8;
 
 // Shared state of one stage's linearisation (world frame, per body).
+// Row stride of a 6x6 spatial inertia in LDS: 37 doubles, so that the lanes of
+// a per-body phase (lane i on body i) fall on different banks (a stride of 36
+// doubles put every fourth body on the same banks; padding the 6-double
+// spatial vectors to 7 as well measured no further gain).
+constexpr int kIS = 37;
+
 struct LinLds {
   double S[kMaxBodies][6];      // joint motion subspace
   double v[kMaxBodies][6];      // velocity
   double a[kMaxBodies][6];      // acceleration: qdd = 0 first, then qdd = qdd0
   // arrays whose lifetimes do not overlap share storage
   union {
-    double Io[kMaxBodies][36];  // own spatial inertia (until the forces at qdd0)
+    double Io[kMaxBodies][kIS];  // own spatial inertia (until the forces at qdd0)
     struct {
       double dv[kMaxBodies][6];   // S_j x v_parent(j)
       double al[kMaxBodies][6];   // S_j x a_parent(j) - dv_j x v_parent(j)
@@ -257,8 +263,8 @@ struct LinLds {
       double pl[kMaxBodies][3];   // body's origin in the parent frame (placement only)
     };
     struct {
-      double IC[kMaxBodies][36];  // composite inertia of the subtree
-      double BC[kMaxBodies][36];  // composite of v x* I - I v x
+      double IC[kMaxBodies][kIS];  // composite inertia of the subtree
+      double BC[kMaxBodies][kIS];  // composite of v x* I - I v x
       double fC[kMaxBodies][6];   // composite force, feet's wrenches subtracted
       double fiC[kMaxBodies][6];  // composite force of the bodies alone
     };
@@ -451,8 +457,8 @@ k_linearize(ModelDev md, int N, double dt, const T* __restrict__ X, const T* __r
   if (tid < 84) {
     double* base;
     int stride, e;
-    if (tid < 36) { base = &L.IC[0][0]; stride = 36; e = tid; }
-    else if (tid < 72) { base = &L.BC[0][0]; stride = 36; e = tid - 36; }
+    if (tid < 36) { base = &L.IC[0][0]; stride = kIS; e = tid; }
+    else if (tid < 72) { base = &L.BC[0][0]; stride = kIS; e = tid - 36; }
     else if (tid < 78) { base = &L.hC[0][0]; stride = 6; e = tid - 72; }
     else { base = &L.fC[0][0]; stride = 6; e = tid - 78; }
     for (int i = n - 1; i > 0; --i) {

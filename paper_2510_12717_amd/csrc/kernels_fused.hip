@@ -226,6 +226,43 @@ constexpr int riccati_lds_bytes() {
          4 * S::NXT * S::LU + 16;
 }
 
+// P += Jc' diag(rho_c,k) Jc, the no-slip rows' term of stage k's state weight
+// (P: NX x NX at row stride LX): the rows' penalties first into rc (LDS, nc
+// doubles), then each entry's nc-term sum with a block of Jc's loads in flight
+// (indices past nc clamped, terms added in increasing row order).  Ends with a
+// workgroup barrier.
+template <int NX>
+__device__ inline void add_contact_weight(double* P, int LX, const Inputs<float>& in, const AgentDesc& d,
+                                          int k, const SolverConsts& sc, double* rc, int tid, int nt) {
+  const int nc = d.n_feet * d.foot_dim;
+  const float* Jc = in.J + d.oJ;
+  const uint8_t* stance = in.st + d.ost;
+  for (int r = tid; r < nc; r += nt) {
+    double rr;
+    contact_row(d, stance, k, r, sc, rr);
+    rc[r] = rr;
+  }
+  __syncthreads();
+  for (int e = tid; e < NX * NX; e += nt) {
+    const int i = e / NX, j = e % NX;
+    double acc = 0.0;
+    for (int r0 = 0; r0 < nc; r0 += 8) {
+      float ji[8], jj[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int r = min(r0 + t, nc - 1);
+        ji[t] = Jc[r * NX + i];
+        jj[t] = Jc[r * NX + j];
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (r0 + t < nc) acc += (double)ji[t] * rc[r0 + t] * (double)jj[t];
+    }
+    P[i * LX + j] += acc;
+  }
+  __syncthreads();
+}
+
 // RES: operators go to the register-resident layout at fws + ofw (FP64
 // products, or FP32 products for MPC_FP32_MFMA).
 // Otherwise (mixed precision, or FP64 products for the generic iteration
@@ -316,8 +353,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
   for (int i = tid; i < NX; i += nt) P[i * LX + i] = (double)q[i] + sc.sigma + state_rho<double>(in, d, i, sc);
   if (in.J) {
     __syncthreads();
-    for (int e = tid; e < NX * NX; e += nt)
-      P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, N, e / NX, e % NX, sc);
+    add_contact_weight<NX>(P, LX, in, d, N, sc, xcol, tid, nt);
   }
   __syncthreads();
   if (flag[0]) {
@@ -612,11 +648,7 @@ k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, 
     }
     __syncthreads();
     // the no-slip rows' dense Jc' diag(rho_c,k) Jc
-    if (in.J && k > 0) {
-      for (int e = tid; e < NX * NX; e += nt)
-        P[(e / NX) * LX + e % NX] += contact_weight<double>(in, d, k, e / NX, e % NX, sc);
-      __syncthreads();
-    }
+    if (in.J && k > 0) add_contact_weight<NX>(P, LX, in, d, k, sc, xcol, tid, nt);
   }
   if (kResident) {
     // S_0 = -B_0 H_0^{-1} B_0' (FP64 matrix-core tiles, once per agent), written in
@@ -717,7 +749,7 @@ struct IterLds {
   int acl, xtf, ppf, gf, ef, sf, cf;                               // float
   int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd, bvd;  // double
   int jc, jac, dnf;                                                // float, no-slip rows
-  int zcd, ycd, wcd;                                               // double, no-slip rows
+  int zcd, ycd, wcd, rcd;                                          // double, no-slip rows
   int flag, sync, total;
 };
 
@@ -761,6 +793,7 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M, int nc = 0) {
   L.zcd = take(8 * N * nc);
   L.ycd = take(8 * N * nc);
   L.wcd = take(8 * N * nc);
+  L.rcd = take(8 * N * nc);
   L.flag = take(16);
   L.sync = take(4 * kSyncInts);
   L.total = o;
@@ -983,6 +1016,8 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
   double* zcd = reinterpret_cast<double*>(sm + L.zcd);
   double* ycd = reinterpret_cast<double*>(sm + L.ycd);
   double* wcd = reinterpret_cast<double*>(sm + L.wcd);
+  // the rows' penalties rho_c, negated for the equality (stance) rows
+  double* rcd = reinterpret_cast<double*>(sm + L.rcd);
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
 
@@ -1051,10 +1086,11 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
     for (int i = tid; i < N * nc; i += nt) {
       const double zz = wm ? (double)st.zc[d.ozc + i] : 0.0, yy = wm ? (double)st.yc[d.ozc + i] : 0.0;
       double rr;
-      contact_row(d, stance, i / nc + 1, i % nc, sc, rr);
+      const bool eq = contact_row(d, stance, i / nc + 1, i % nc, sc, rr);
       zcd[i] = zz;
       ycd[i] = yy;
       wcd[i] = yy - rr * zz;
+      rcd[i] = eq ? -rr : rr;
     }
   }
   __syncthreads();
@@ -1587,8 +1623,8 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
         const int part = lane & 3;
         auto row_update = [&](int kr, int rw, double zeta) {
           const int idx = (kr - 1) * nc + rw;
-          double rr;
-          const bool eq = contact_row(d, stance, kr, rw, sc, rr);
+          const double rs = rcd[idx], rr = fabs(rs);
+          const bool eq = rs < 0.0;
           const double wv = alpha * zeta + oma * zcd[idx];
           const double zn = eq ? 0.0 : wv + ycd[idx] / rr;
           const double yn = ycd[idx] + rr * (wv - zn);

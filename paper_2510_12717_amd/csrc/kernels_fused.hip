@@ -275,7 +275,7 @@ __device__ inline void add_contact_weight(double* P, int LX, const Inputs<float>
 // out; then P_k = Q + sigma I + PA' A_cl,k (= Q + A'PA + G'K, as P is
 // symmetric), formed on and above the diagonal and mirrored.
 template <int NX, int NU, int PREC, bool RES>
-__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 || (PREC == kProdF32 && RES) ? 4 : 2)
+__global__ void __launch_bounds__(64 * kFactorWaves, PREC == kProdF64 || (PREC == kProdF32 && (RES || NX == 48)) ? 4 : 2)
 k_riccati(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int n_launch,
           Inputs<float> in, SolverConsts sc_all, float* __restrict__ fws, int32_t* __restrict__ status) {
   using S = FS<NX, NU>;

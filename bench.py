@@ -233,7 +233,8 @@ def uneven(args):
     torch.cuda.set_device(0)
     n = args.agents if args.agents != 4096 else 8192
     b = synth.uneven_batch(n, dtype=np.float32)
-    plan = mpc.Plan(b.shapes, precision="fp32", iters=args.iters, kernel=args.kernel)
+    prec = args.precision if args.precision in ("fp32", "fp32mfma") else "fp32"
+    plan = mpc.Plan(b.shapes, precision=prec, iters=args.iters, kernel=args.kernel)
     prob = mpc.to_device(b, "fp32")
     t_tune = time.perf_counter()
     groups = plan.autotune(prob, reps=2)
@@ -262,7 +263,7 @@ def uneven(args):
     lat = np.array([a.elapsed_time(c) for a, c in ev])
     st = plan.get_solution()["status"]
     out = {"metric": "MPC QP solves/sec, uneven batch (captured step, autotuned groups)",
-           "kernel": args.kernel,
+           "kernel": args.kernel, "precision": prec,
            "value": n * args.steps / wall, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",

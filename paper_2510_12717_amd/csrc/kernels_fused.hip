@@ -749,7 +749,7 @@ struct IterLds {
   int acl, xtf, ppf, gf, ef, sf, cf;                               // float
   int xd, ud, zd, yd, lod, hid, rhod, irhod, wvd, rtd, dd, utd, qd, xrd, qtd, bvd;  // double
   int jc, jac, dnf;                                                // float, no-slip rows
-  int zcd, ycd, wcd, rcd;                                          // double, no-slip rows
+  int zcd, ycd, wcd, rcd, ircd;                                    // double, no-slip rows
   int flag, sync, total;
 };
 
@@ -794,6 +794,7 @@ __host__ __device__ inline IterLds iter_lds_layout(int N, int M, int nc = 0) {
   L.ycd = take(8 * N * nc);
   L.wcd = take(8 * N * nc);
   L.rcd = take(8 * N * nc);
+  L.ircd = take(8 * N * nc);
   L.flag = take(16);
   L.sync = take(4 * kSyncInts);
   L.total = o;
@@ -1018,6 +1019,7 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
   double* wcd = reinterpret_cast<double*>(sm + L.wcd);
   // the rows' penalties rho_c, negated for the equality (stance) rows
   double* rcd = reinterpret_cast<double*>(sm + L.rcd);
+  double* ircd = reinterpret_cast<double*>(sm + L.ircd);  // 1 / rho_c
   int* flag = reinterpret_cast<int*>(sm + L.flag);
   int* sync = reinterpret_cast<int*>(sm + L.sync);
 
@@ -1091,6 +1093,7 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
       ycd[i] = yy;
       wcd[i] = yy - rr * zz;
       rcd[i] = eq ? -rr : rr;
+      ircd[i] = 1.0 / rr;
     }
   }
   __syncthreads();
@@ -1443,15 +1446,42 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
     // Jc' w_c,k, and on the last stage also (Jc A_cl,N-1)' w_c,N, through which
     // the rows of x_N reach p_{N-1}; the last stage leaves Jc' w_c,N for its C
     // (p'_{N-1} = p_N + s_{N-1}, p_N holding Jc' w_c,N).
+    // Rows in blocks of 4, every LDS load of a block issued before the first
+    // add (rows past nc clamped and not added), so that the loads do not wait
+    // one by one on the last stage's critical path.
     auto row_terms = [&](int i) -> double {
       double v = 0.0;
-      for (int rw = 0; rw < nc; ++rw) v += (double)jc[rw * NXP + i] * wcd[(k - 1) * nc + rw];
+      for (int r0 = 0; r0 < nc; r0 += 4) {
+        float jv[4];
+        double wv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int rw = min(r0 + t, nc - 1);
+          jv[t] = jc[rw * NXP + i];
+          wv[t] = wcd[(k - 1) * nc + rw];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (r0 + t < nc) v += (double)jv[t] * wv[t];
+      }
       if (k == N - 1) {
         double dn = 0.0;
-        for (int rw = 0; rw < nc; ++rw) {
-          const double wn = wcd[(N - 1) * nc + rw];
-          v += (double)jac[rw * NXP + i] * wn;
-          dn += (double)jc[rw * NXP + i] * wn;
+        for (int r0 = 0; r0 < nc; r0 += 4) {
+          float av[4], jv[4];
+          double wn[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int rw = min(r0 + t, nc - 1);
+            av[t] = jac[rw * NXP + i];
+            jv[t] = jc[rw * NXP + i];
+            wn[t] = wcd[(N - 1) * nc + rw];
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (r0 + t < nc) {
+              v += (double)av[t] * wn[t];
+              dn += (double)jv[t] * wn[t];
+            }
         }
         dnf[i] = (float)dn;
       }
@@ -1626,7 +1656,7 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
           const double rs = rcd[idx], rr = fabs(rs);
           const bool eq = rs < 0.0;
           const double wv = alpha * zeta + oma * zcd[idx];
-          const double zn = eq ? 0.0 : wv + ycd[idx] / rr;
+          const double zn = eq ? 0.0 : wv + ycd[idx] * ircd[idx];
           const double yn = ycd[idx] + rr * (wv - zn);
           ycd[idx] = yn;
           zcd[idx] = zn;
@@ -1634,19 +1664,35 @@ __device__ __forceinline__ void admm_resident_agent(const AgentDesc* __restrict_
         };
         for (int r0 = 0; r0 < nc; r0 += 16) {
           const int rw = r0 + (lane >> 2);
+          const int rc = min(rw, nc - 1);  // lanes past the last row read it and discard the sum
+          constexpr int TQ = (NX + 3) / 4;  // columns per lane, read four at a time
+          // sum over this lane's columns of u[col] * v[col], four loads of each in flight
+          auto dot4 = [&](const float* u, const float* v) -> double {
+            double acc = 0.0;
+#pragma unroll
+            for (int t0 = 0; t0 < TQ; t0 += 4) {
+              float uv[4], vv[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const int i = min(part + 4 * (t0 + t), NX - 1);
+                uv[t] = u[i];
+                vv[t] = v[i];
+              }
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                if (t0 + t < TQ && part + 4 * (t0 + t) < NX) acc += (double)uv[t] * (double)vv[t];
+            }
+            return acc;
+          };
           if (k >= 1) {
-            double zeta = 0.0;
-            if (rw < nc)
-              for (int i = part; i < NX; i += 4) zeta += (double)jc[rw * NXP + i] * (double)xtf[k * NXP + i];
+            double zeta = dot4(jc + rc * NXP, xtf + k * NXP);
             zeta = quad_sum(zeta);
             if (rw < nc && part == 0) row_update(k, rw, zeta);
           }
           if (k == N - 1) {
-            double zeta = 0.0;
-            if (rw < nc)
-              for (int i = part; i < NX; i += 4)
-                zeta += (double)jac[rw * NXP + i] * (double)xtf[k * NXP + i] +
-                        (double)jc[rw * NXP + i] * (double)ef[k * NXP + i];
+            // (Jc A_cl,N-1) xt_{N-1}, then Jc e_{N-1}
+            double zeta = dot4(jac + rc * NXP, xtf + k * NXP);
+            zeta += dot4(jc + rc * NXP, ef + k * NXP);
             zeta = quad_sum(zeta);
             if (rw < nc && part == 0) row_update(N, rw, zeta);
           }

@@ -104,8 +104,9 @@ def parse():
                     help="run the served request loop instead: Poisson arrivals from independent "
                          "controllers of uneven shapes (prints its own JSON line)")
     ap.add_argument("--controllers", type=int, default=8192)
-    ap.add_argument("--serve-precision", default="fp32", choices=("fp32", "bf16", "fp16"),
-                    help="served loop precision (bf16/fp16: mixed precision with refinement)")
+    ap.add_argument("--serve-precision", default="fp32", choices=("fp32", "bf16", "fp16", "fp32mfma"),
+                    help="served loop precision (bf16/fp16: mixed precision with refinement; "
+                         "fp32mfma: FP32 with the factor's products on the FP32 matrix cores)")
     ap.add_argument("--supersede", action="store_true",
                     help="served loop: a controller's waiting request is dropped when a newer one of "
                          "it arrives (solves/s and latency then count solved requests)")
@@ -584,7 +585,7 @@ def serve(args):
     n_sup = st["superseded"]
     out = {"metric": "served MPC QP solves/sec with p50/p95/p99 arrival-to-result latency",
            "value": (n - n_sup) / t_end, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-           "dtype": {"fp32": "f32", "bf16": "bf16+f32", "fp16": "f16+f32"}[args.serve_precision],
+           "dtype": {"fp32": "f32", "bf16": "bf16+f32", "fp16": "f16+f32", "fp32mfma": "f32"}[args.serve_precision],
            "data": "synthetic",
            "config": {"workload": f"{nc} controllers, Poisson {args.rate_hz:g} Hz each, "
                                   f"{args.sim_seconds:g} s, N ~ U{{5..20}}, half humanoid (48, 30), "

@@ -51,6 +51,23 @@ __device__ inline double block_sum(double v, double* red) {
 // 4096-agent humanoid batch), and larger blocks cost occupancy.
 constexpr int kQuadBlock = 8;
 
+// sum over t = t_first, t_first + step, ... < n of term(t), with kQuadBlock
+// terms' loads in flight (indices past the end clamped, not added), added in
+// increasing t: a single thread's (step 1) or a quad lane's (step 4) share of a
+// dot product.
+template <typename V, class FT>
+__device__ inline V blocked_sum(int t_first, int step, int n, FT term) {
+  V acc = 0;
+  for (int t0 = t_first; t0 < n; t0 += step * kQuadBlock) {
+    V tv[kQuadBlock];
+#pragma unroll
+    for (int s = 0; s < kQuadBlock; ++s) tv[s] = term(min(t0 + step * s, n - 1));
+#pragma unroll
+    for (int s = 0; s < kQuadBlock; ++s) acc += t0 + step * s < n ? tv[s] : V(0);
+  }
+  return acc;
+}
+
 // store(i, sum_t term(i, t)) for i < n_out, t < n_in: each output's sum is
 // split over the 4 lanes of a quad (terms t = sub, sub + 4, ...) and summed
 // with DPP; each lane adds its terms in increasing t.

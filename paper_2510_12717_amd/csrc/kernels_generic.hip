@@ -124,9 +124,8 @@ __device__ inline void forward_exact(int N, int nx, int nu, const T* A, const T*
       const int i = i0 + qd;
       if (i < nx) {  // uniform within a quad
         V acc = 0;
-        if (xk)
-          for (int t = sub; t < nx; t += 4) acc += (V)Ak[i * nx + t] * xk[t];
-        for (int t = sub; t < nu; t += 4) acc += (V)Bk[i * nu + t] * uk[t];
+        if (xk) acc = blocked_sum<V>(sub, 4, nx, [&](int t) { return (V)Ak[i * nx + t] * xk[t]; });
+        acc += blocked_sum<V>(sub, 4, nu, [&](int t) { return (V)Bk[i * nu + t] * uk[t]; });
         acc = quad_sum(acc);
         if (sub == 0) Xn[k * nx + i] = c ? (V)c[(int64_t)k * nx + i] + acc : acc;
       }
@@ -396,9 +395,8 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         V rl = 0;
         for (int idx = tid; idx < N * nu; idx += nt) {
           const int k = idx / nu, j = idx % nu;
-          V acc = 0;
           const T* Bc = B + (int64_t)k * nx * nu + j;
-          for (int t = 0; t < nx; ++t) acc += (V)Bc[t * nu] * pp[k * nx + t];
+          const V acc = blocked_sum<V>(0, 1, nx, [&](int t) { return (V)Bc[t * nu] * pp[k * nx + t]; });
           const V rtd = rtilde_diag<V, T>(d, j, (V)r[j], mu, wrho + (int64_t)k * m, sc);
           hv[idx] = rtd * ut[idx] + rt[idx] + acc;
           rl = fmax(rl, fabs(hv[idx]));
@@ -409,10 +407,8 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         // solved with the low-precision factor
         for (int idx = tid; idx < N * nx; idx += nt) {
           const int k = idx / nx, i = idx % nx;
-          V acc = 0;
           const T* Kc = wK + (int64_t)k * nu * nx + i;
-          for (int j = 0; j < nu; ++j) acc += (V)Kc[j * nx] * hv[k * nu + j];
-          g[idx] = acc;
+          g[idx] = blocked_sum<V>(0, 1, nu, [&](int j) { return (V)Kc[j * nx] * hv[k * nu + j]; });
         }
         for (int i = tid; i < nx; i += nt) p[i] = 0;
         __syncthreads();
@@ -428,18 +424,14 @@ k_admm(const AgentDesc* __restrict__ desc, const int32_t* __restrict__ list, int
         }
         for (int idx = tid; idx < N * nu; idx += nt) {
           const int k = idx / nu, j = idx % nu;
-          V acc = 0;
           const T* Bc = B + (int64_t)k * nx * nu + j;
-          for (int t = 0; t < nx; ++t) acc += (V)Bc[t * nu] * e[k * nx + t];
-          hv[idx] = hv[idx] + acc;
+          hv[idx] = hv[idx] + blocked_sum<V>(0, 1, nx, [&](int t) { return (V)Bc[t * nu] * e[k * nx + t]; });
         }
         __syncthreads();
         for (int idx = tid; idx < N * nu; idx += nt) {
           const int k = idx / nu, j = idx % nu;
-          V acc = 0;
           const T* Hr = wHi + (int64_t)k * nu * nu + j * nu;
-          for (int t = 0; t < nu; ++t) acc += (V)Hr[t] * hv[k * nu + t];
-          dv[idx] = -acc;
+          dv[idx] = -blocked_sum<V>(0, 1, nu, [&](int t) { return (V)Hr[t] * hv[k * nu + t]; });
         }
         __syncthreads();
         // dx (in g, dx_{k+1} at g[k]) and du (in dv) under the exact dynamics

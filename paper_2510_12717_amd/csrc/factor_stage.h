@@ -93,33 +93,25 @@ __device__ inline bool factor_stage(const Inputs<T>& in, const SolverConsts& sc,
   __syncthreads();
   for (int idx = tid; idx < nx * nu; idx += nt) {
     const int i = idx / nu, j = idx % nu;
-    D acc = 0;
-    for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Bk[t * nu + j];
-    PB[idx] = acc;
+    PB[idx] = blocked_sum<D>(0, 1, nx, [&](int t) { return P[i * nx + t] * Bk[t * nu + j]; });
   }
   for (int idx = tid; idx < nx * nx; idx += nt) {
     const int i = idx / nx, j = idx % nx;
-    D acc = 0;
-    for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * Ak[t * nx + j];
-    PA[idx] = acc;
+    PA[idx] = blocked_sum<D>(0, 1, nx, [&](int t) { return P[i * nx + t] * Ak[t * nx + j]; });
   }
   for (int i = tid; i < nx; i += nt) {
-    D acc = 0;
-    for (int t = 0; t < nx; ++t) acc += P[i * nx + t] * (D)c[(int64_t)k * nx + t];
+    const D acc = blocked_sum<D>(0, 1, nx, [&](int t) { return P[i * nx + t] * (D)c[(int64_t)k * nx + t]; });
     wS[(int64_t)k * nx + i] = (T)acc;
   }
   __syncthreads();
   for (int idx = tid; idx < nu * nu; idx += nt) {
     const int i = idx / nu, j = idx % nu;
-    D acc = (i == j) ? rdg[i] : 0.0;
-    for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PB[t * nu + j];
-    H[idx] = acc;
+    H[idx] = blocked_sum<D>(0, 1, nx, [&](int t) { return Bk[t * nu + i] * PB[t * nu + j]; },
+                            (i == j) ? rdg[i] : 0.0);
   }
   for (int idx = tid; idx < nu * nx; idx += nt) {
     const int i = idx / nx, j = idx % nx;
-    D acc = 0;
-    for (int t = 0; t < nx; ++t) acc += Bk[t * nu + i] * PA[t * nx + j];
-    G[idx] = acc;
+    G[idx] = blocked_sum<D>(0, 1, nx, [&](int t) { return Bk[t * nu + i] * PA[t * nx + j]; });
   }
   __syncthreads();
   // Right-looking Cholesky of H_k in place (lower triangle).
@@ -186,23 +178,17 @@ __device__ inline bool factor_stage(const Inputs<T>& in, const SolverConsts& sc,
   for (int idx = tid; idx < nx * nx; idx += nt) {
     const int i = idx / nx, j = idx % nx;
     if (update_P && j >= i) {
-      D a1 = ((i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0) +
-             contact_weight<D>(in, d, k, i, j, sc),
-        a2 = a1;
-      for (int t = 0; t < nx; ++t) {
-        a1 += Ak[t * nx + i] * PA[t * nx + j];
-        a2 += Ak[t * nx + j] * PA[t * nx + i];
-      }
-      for (int t = 0; t < nu; ++t) {
-        a1 += G[t * nx + i] * Kk[t * nx + j];
-        a2 += G[t * nx + j] * Kk[t * nx + i];
-      }
+      const D a0 = ((i == j) ? (D)q[i] + sc.sigma + state_rho<D>(in, d, i, sc) : 0.0) +
+                   contact_weight<D>(in, d, k, i, j, sc);
+      D a1 = blocked_sum<D>(0, 1, nx, [&](int t) { return Ak[t * nx + i] * PA[t * nx + j]; }, a0);
+      D a2 = blocked_sum<D>(0, 1, nx, [&](int t) { return Ak[t * nx + j] * PA[t * nx + i]; }, a0);
+      a1 = blocked_sum<D>(0, 1, nu, [&](int t) { return G[t * nx + i] * Kk[t * nx + j]; }, a1);
+      a2 = blocked_sum<D>(0, 1, nu, [&](int t) { return G[t * nx + j] * Kk[t * nx + i]; }, a2);
       const D v = 0.5 * (a1 + a2);
       P[i * nx + j] = v;
       P[j * nx + i] = v;
     }
-    D acl = Ak[idx];
-    for (int t = 0; t < nu; ++t) acl += Bk[i * nu + t] * Kk[t * nx + j];
+    const D acl = blocked_sum<D>(0, 1, nu, [&](int t) { return Bk[i * nu + t] * Kk[t * nx + j]; }, Ak[idx]);
     wAcl[(int64_t)k * nx * nx + idx] = (T)acl;
   }
   for (int idx = tid; idx < nu * nx; idx += nt) wK[(int64_t)k * nu * nx + idx] = (T)Kk[idx];

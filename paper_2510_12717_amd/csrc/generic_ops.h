@@ -51,13 +51,13 @@ __device__ inline double block_sum(double v, double* red) {
 // 4096-agent humanoid batch), and larger blocks cost occupancy.
 constexpr int kQuadBlock = 8;
 
-// sum over t = t_first, t_first + step, ... < n of term(t), with kQuadBlock
-// terms' loads in flight (indices past the end clamped, not added), added in
-// increasing t: a single thread's (step 1) or a quad lane's (step 4) share of a
-// dot product.
+// init + the sum over t = t_first, t_first + step, ... < n of term(t), with
+// kQuadBlock terms' loads in flight (indices past the end clamped, not added),
+// added in increasing t: a single thread's (step 1) or a quad lane's (step 4)
+// share of a dot product.
 template <typename V, class FT>
-__device__ inline V blocked_sum(int t_first, int step, int n, FT term) {
-  V acc = 0;
+__device__ inline V blocked_sum(int t_first, int step, int n, FT term, V init = V(0)) {
+  V acc = init;
   for (int t0 = t_first; t0 < n; t0 += step * kQuadBlock) {
     V tv[kQuadBlock];
 #pragma unroll

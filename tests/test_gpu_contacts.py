@@ -216,3 +216,29 @@ def test_no_slip_register_resident_limits():
     assert ei.value.code == mpc.MPC_ERR_INVALID_ARG
     plan = mpc.Plan([synth.humanoid(2), synth.humanoid(8)], precision="fp32", no_slip=1)
     assert {g["family"] for g in plan.groups()} == {"generic"}  # only when asked for
+
+
+@pytest.mark.parametrize("kernel", ["auto", "fused"])
+def test_no_slip_rows_humanoid_4096_sampled(kernel):
+    """The 4096-agent humanoid batch with the rows in one plan (the launch the
+    real-time-iteration benchmark runs), every 256th agent against the oracle;
+    FP32 tolerance on the generic kernels, the resident rows' bar on the
+    register-resident one."""
+    n = 4096
+    b = synth.humanoid_batch(n, dtype=np.float32)
+    J = synth.foot_jacobians(b)
+    plan = mpc.Plan(b.shapes, precision="fp32", iters=50, no_slip=1, kernel=kernel)
+    assert {g["family"] for g in plan.groups()} == {"fused" if kernel == "fused" else "generic"}
+    plan.solve(_prob(b, "fp32", J))
+    g = {k: v.cpu().numpy() for k, v in plan.get_solution().items()}
+    assert np.all(g["status"] == 0)
+    ids = np.arange(0, n, 256)
+    sub = synth.humanoid_batch(agent_ids=ids)
+    nc = sub.shapes[0].n_feet * sub.shapes[0].foot_dim
+    Js = np.concatenate([J.reshape(n, nc, -1)[a].ravel() for a in ids])
+    o = oracle.solve_batch(sub, iters=50, J=Js)
+    o["_off"] = sub.offsets()
+    e = agent_errors(b, g, o, agents=ids, go=np.arange(len(ids)))
+    tol = TOL["fp32_resident_rows"] if kernel == "fused" else TOL["fp32"]
+    print(kernel, "4096 sampled no-slip: max u0/traj", e[:, :2].max(axis=0))
+    assert e[:, :2].max() < tol
